@@ -1,0 +1,178 @@
+"""Pins of the oracle's SDF network, sampler and optimiser."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+from oracle import optim as oopt
+from oracle import sampling as osmp
+from synth import MLPSpec, mlp_init, mlp_layout
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SMALL = MLPSpec(n_layers=3, width=16, pe_octaves=2, head_width=8, head_layers=2, beta=100.0,
+                centre=(0.0, 0.0, 0.30), half_size=0.10)
+
+
+def _perturbed(spec, seed, scale=0.3):
+    """Initial weights plus dense noise, so every weight and bias matters."""
+    p = mlp_init(spec, seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    return p + scale * rng.normal(size=p.shape) / np.sqrt(spec.width)
+
+
+def _pts(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform([-0.1, -0.1, 0.2], [0.1, 0.1, 0.4], (n, 3))
+
+
+# ------------------------------------------------------------------ network
+
+def test_positional_encoding_closed_form():
+    x = torch.tensor([[0.25, 0.5, -0.5]], dtype=torch.float64)
+    g = omlp.positional_encoding(x, 2).numpy()[0]
+    s2 = np.sqrt(0.5)
+    expect = [0.25, 0.5, -0.5, s2, 1.0, -1.0, s2, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, -1.0, -1.0]
+    np.testing.assert_allclose(g, expect, atol=1e-15)
+
+
+def test_softplus_closed_forms():
+    z = torch.tensor([0.0, 1.0, -1.0, 0.003], dtype=torch.float64)
+    sp = omlp.softplus(z, 100.0).numpy()
+    assert abs(sp[0] - np.log(2) / 100) < 1e-16
+    assert abs(sp[1] - (1.0 + np.log1p(np.exp(-100.0)) / 100)) < 1e-15
+    assert abs(sp[2] - np.log1p(np.exp(-100.0)) / 100) < 1e-50
+    assert abs(sp[3] - np.log1p(np.exp(0.3)) / 100) < 1e-16
+
+
+def test_geometric_init_is_close_to_a_sphere():
+    """The seeded geometric initialisation makes f close to the SDF of a sphere
+    of radius 0.5 half_size about the cube centre (a property of that
+    initialisation that breaks under transposed weights or a wrong layer order)."""
+    spec = MLPSpec()
+    p = mlp_init(spec, 0)
+    x = _pts(400, 1)
+    f, g, a = omlp.forward(p, spec, x)
+    r = np.linalg.norm(x - np.array(spec.centre), axis=1)
+    target = r - 0.5 * spec.half_size
+    err = np.abs(f - target)
+    assert np.median(err) < 0.1 * spec.half_size, np.median(err)
+    nrm = np.linalg.norm(g, axis=1)
+    assert 0.7 < np.median(nrm) < 1.3
+    radial = (x - np.array(spec.centre)) / r[:, None]
+    assert np.median(np.sum(g / nrm[:, None] * radial, 1)) > 0.9
+    assert np.all((a > 0) & (a < 1))
+
+
+def test_head_with_zero_weights_returns_sigmoid_of_bias():
+    spec = SMALL
+    p = _perturbed(spec, 3)
+    lay = mlp_layout(spec)
+    for k in range(spec.head_layers):
+        o, shp = lay[f"Wh{k}"]
+        p[o:o + int(np.prod(shp))] = 0.0
+    o, shp = lay["wh_out"]
+    p[o:o + int(np.prod(shp))] = 0.0
+    p[lay["bh_out"][0]] = 0.7
+    _, _, a = omlp.forward(p, spec, _pts(5, 2))
+    np.testing.assert_allclose(a, 1.0 / (1.0 + np.exp(-0.7)), rtol=1e-14)
+
+
+def test_gradient_matches_finite_differences():
+    spec = SMALL
+    p = _perturbed(spec, 5)
+    x = _pts(7, 3)
+    _, g, _ = omlp.forward(p, spec, x)
+    h = 1e-7
+    for c in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[:, c] += h
+        xm[:, c] -= h
+        fd = (omlp.forward(p, spec, xp)[0] - omlp.forward(p, spec, xm)[0]) / (2 * h)
+        np.testing.assert_allclose(g[:, c], fd, rtol=2e-6, atol=1e-8)
+
+
+def test_parameter_gradient_with_normals_matches_finite_differences():
+    """The double backward (through grad_x f) against central differences of J."""
+    spec = SMALL
+    p = _perturbed(spec, 7)
+    x = _pts(6, 4)
+    rng = np.random.default_rng(8)
+    gf, gg, ga = rng.normal(size=6), rng.normal(size=(6, 3)), rng.normal(size=6)
+    gp = omlp.backward(p, spec, x, gf, gg, ga)
+    lay = mlp_layout(spec)
+    idx = [lay["W0"][0] + 1, lay["W0"][0] + 20, lay["b0"][0] + 3, lay["W1"][0] + 17,
+           lay["b2"][0] + 5, lay["w_out"][0] + 2, lay["b_out"][0], lay["Wh0"][0] + 9,
+           lay["bh1"][0] + 1, lay["wh_out"][0] + 4, lay["bh_out"][0]]
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (omlp.objective(pp, spec, x, gf, gg, ga) - omlp.objective(pm, spec, x, gf, gg, ga)) / (2 * h)
+        assert abs(fd - gp[i]) <= 1e-5 * max(abs(fd), 1e-2 * np.abs(gp).max()), (i, fd, gp[i])
+    d = rng.normal(size=p.shape)
+    fd = (omlp.objective(p + h * d, spec, x, gf, gg, ga) - omlp.objective(p - h * d, spec, x, gf, gg, ga)) / (2 * h)
+    assert abs(fd - gp @ d) <= 1e-5 * abs(fd)
+
+
+# ------------------------------------------------------------------ sampler
+
+def test_splitmix64_reference_outputs():
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.json")) as fh:
+        g = json.load(fh)
+    got = [int(osmp.splitmix64_output(np.uint64(0), np.uint64(k))) for k in range(len(g["outputs"]))]
+    assert got == [int(h, 16) for h in g["outputs"]]
+
+
+def test_grid_sampling_closed_form_small_workload():
+    """16x16 rays x 16 depths in a 10 cm cube at 0.30 m: depths 0.25 + (k+1/2) 6.25 mm,
+    lateral cell centres, origins on the aperture plane z = 0."""
+    xyz, u, o = osmp.sample_points((0, 0, 0.30), 0.05, (0, 0, 1), 16, 16, 16, "grid")
+    np.testing.assert_allclose(u[0], 0.25 + (np.arange(16) + 0.5) * 0.00625, atol=1e-15)
+    np.testing.assert_allclose(xyz[:, :, 2], u, atol=1e-15)
+    lat = -0.05 + (np.arange(16) + 0.5) * 0.00625
+    np.testing.assert_allclose(o[:16, 0], lat, atol=1e-15)       # x fastest
+    np.testing.assert_allclose(o[::16, 1], lat, atol=1e-15)
+    assert np.all(o[:, 2] == 0)
+
+
+def test_stratified_sampling_strata_and_uniformity():
+    xyz, u, o = osmp.sample_points((0.01, -0.02, 0.30), 0.1, (0, 0, 1), 8, 8, 64, "stratified", seed=3, step=5)
+    lo = 0.20 + np.arange(64) * (0.2 / 64)
+    assert np.all(u >= lo[None] - 1e-15) and np.all(u < lo[None] + 0.2 / 64)
+    frac = (u - lo[None]) / (0.2 / 64)
+    from scipy.stats import kstest
+    assert kstest(frac.ravel(), "uniform").pvalue > 1e-3
+    xyz2, u2, _ = osmp.sample_points((0.01, -0.02, 0.30), 0.1, (0, 0, 1), 8, 8, 64, "stratified", seed=3, step=6)
+    assert not np.allclose(u, u2)
+
+
+def test_slanted_primary_direction():
+    w = np.array([0.2, -0.1, 1.0])
+    w /= np.linalg.norm(w)
+    xyz, u, o = osmp.sample_points((0.0, 0.0, 0.3), 0.05, w, 4, 3, 5, "grid")
+    assert np.allclose(o @ w, 0.0, atol=1e-15)                  # origins on the aperture plane
+    d = xyz - o[:, None, :]
+    np.testing.assert_allclose(d / np.linalg.norm(d, axis=-1, keepdims=True),
+                               np.broadcast_to(w, d.shape), atol=1e-12)
+    assert np.all(np.diff(u, axis=1) > 0)
+
+
+# ------------------------------------------------------------------ optimiser
+
+def test_adamw_first_step_and_decay():
+    rng = np.random.default_rng(0)
+    p0, g = rng.normal(size=10), rng.normal(size=10)
+    p1, m, v = oopt.adamw_step(p0, g, np.zeros(10), np.zeros(10), 1, 1e-3, wd=0.0)
+    np.testing.assert_allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    p2, _, _ = oopt.adamw_step(p0, np.zeros(10), np.zeros(10), np.zeros(10), 1, 1e-3, wd=0.1)
+    np.testing.assert_allclose(p2, p0 * (1 - 1e-4), rtol=1e-14)
+
+
+def test_cosine_schedule_endpoints():
+    assert oopt.cosine_lr(0, 100, 1e-3) == pytest.approx(1e-3)
+    assert oopt.cosine_lr(50, 100, 1e-3) == pytest.approx(5e-4)
+    assert oopt.cosine_lr(100, 100, 1e-3, 1e-5) == pytest.approx(1e-5)
