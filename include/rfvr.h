@@ -1,0 +1,239 @@
+/*
+ * rfvr.h -- C ABI of librfvr, an MI355X (gfx950) implementation of lensless RF
+ * volumetric rendering: GeRaF, "Neural Geometry Reconstruction from Radio
+ * Frequency Signals" (arXiv 2605.29097).
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ * - Array pointers are DEVICE pointers into caller-owned, C-contiguous memory,
+ *   unless marked "host".  Descriptors are host structs read during the call
+ *   and not retained.  Complex arrays are interleaved {re, im} float pairs.
+ * - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *   stream).  Every call only enqueues work on that stream; no call blocks the
+ *   host.  Kernel-time faults surface at the caller's next synchronisation.
+ * - `ws` / `ws_bytes`: device workspace owned by the caller, at least the size
+ *   returned by the matching rfvr_*_ws_bytes() query, 256-byte aligned.  Its
+ *   contents are scratch on entry and on exit.
+ * - Return value: RFVR_OK, or a negative code.  All argument checks happen
+ *   before anything is enqueued, so a failed call has enqueued nothing.
+ *   rfvr_last_error() returns a thread-local message for the last failure.
+ * - Outputs are overwritten, except gradient outputs when `flags` contains
+ *   RFVR_ACCUMULATE, which then add into the existing contents.
+ * - Reductions use a fixed split and a fixed summation order and no floating
+ *   point atomics: results are bitwise reproducible for fixed shapes.
+ * - NaN/Inf inside arrays propagate; only descriptor scalars are checked.
+ *
+ * Notation: i = measurement (antenna, monostatic), n = frequency with
+ * f_n = f0 + n*df, j = sample point laid out [n_ray][n_z] along primary rays
+ * (depth u ascending), c = 299792458 m/s.
+ */
+#ifndef RFVR_H
+#define RFVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RFVR_OK             0
+#define RFVR_E_INVALID     -1   /* bad size, NULL required pointer, non-finite scalar */
+#define RFVR_E_WORKSPACE   -2   /* ws NULL or ws_bytes below the query              */
+#define RFVR_E_UNSUPPORTED -3   /* valid but not implemented (bistatic apertures)   */
+#define RFVR_E_HIP         -4   /* HIP launch / runtime error                       */
+
+/* flags */
+#define RFVR_SPEC_CLAMP     0x0u  /* specular factor max(0, w_o . w_r)   (default)  */
+#define RFVR_SPEC_RAW       0x1u  /* w_o . w_r                                       */
+#define RFVR_SPEC_OFF       0x2u  /* factor 1 (the paper's "without radar physics") */
+#define RFVR_SPEC_MASK      0x3u
+#define RFVR_PHASE_FP64RR   0x0u  /* path length and phase reduction in FP64 (default) */
+#define RFVR_PHASE_NAIVE32  0x4u  /* radians 2 pi f d / c formed in FP32 (precision study) */
+#define RFVR_ACCUMULATE     0x8u  /* gradient outputs add into existing contents   */
+
+/* Measurement geometry and FMCW sweep (Sec. "Radar Basics", Eq. fmcw; App. C). */
+typedef struct rfvr_aperture {
+    int32_t      n_meas;   /* number of (tx, rx) measurements, >= 1             */
+    const float* tx;       /* [n_meas][3] transmitter positions, metres         */
+    const float* rx;       /* NULL = monostatic (rx = tx).  Non-NULL (bistatic) is
+                              reserved: every entry point returns
+                              RFVR_E_UNSUPPORTED for it                          */
+    double       f0_hz;    /* first sweep frequency                              */
+    double       df_hz;    /* frequency step                                     */
+    int32_t      n_freq;   /* >= 1                                               */
+} rfvr_aperture;
+
+/* Lensless sample set (Sec. "Lensless Sampling", Primary Ray). */
+typedef struct rfvr_samples {
+    int32_t      n_ray, n_z;   /* >= 1 each                                          */
+    const float* xyz;          /* [n_ray][n_z][3] points, depth ascending per ray    */
+    const float* ray_weight;   /* [n_ray] Monte-Carlo weight w_r, or NULL (= 1)      */
+} rfvr_samples;
+
+/* Per-point fields of the current scene estimate (Sec. "Opaque density
+ * representation", "Signal representation"). */
+typedef struct rfvr_fields {
+    const float* sdf;      /* [n_ray*n_z] signed distance f, metres                  */
+    const float* grad;     /* [n_ray*n_z][3] grad_x f (normal before normalising)    */
+    const float* refl;     /* [n_ray*n_z] reflectiveness a                           */
+    const float* phi_ray;  /* [n_ray] Phi_s(f) at primary-ray origins, detached; or NULL */
+    const float* phi_tx;   /* [n_meas] Phi_s(f) at transmitters, detached; or NULL   */
+    const float* phi_rx;   /* reserved for bistatic, must be NULL                    */
+    float        s;        /* logistic sharpness (1/m), finite, > 0                  */
+    float        amp_tx;   /* learnt global amplitude A'_tx, finite                  */
+} rfvr_fields;
+
+/* ------------------------------------------------------------------------
+ * Render (signal tracing with lensless alpha blending)
+ *
+ * Computes, for every measurement i and frequency n (Eq. ref_sim with the
+ * amplitude of Eq. signal_amp_tracing and Eq. reflection_angle):
+ *   Phi_k  = 1 / (1 + exp(-s f_k))                         per ray
+ *   alpha_k = clamp((Phi_k - Phi_{k+1}) / (Phi_k + 1e-5), 0, 1), alpha_{n_z-1} = 0
+ *                                            (NeuS discretisation, Sec. Discretization)
+ *   T_k    = prod_{m<k} (1 - alpha_m)
+ *   T'_ik  = clamp(T_k + phi_tx[i] - phi_ray[r], 0, 1)     (Eq. lens-less-transmittance;
+ *            T'_ik = T_k when phi_tx or phi_ray is NULL)
+ *   c_ij   = A' w_r a_j alpha_j T'^2 spec_ij / r_ij^2,  r_ij = |x_j - tx_i|,
+ *            spec = 2 (n_hat . w_i)^2 - 1 (monostatic w_o . w_r), see RFVR_SPEC_*
+ *   s[i,n] = sum_j c_ij exp(-j 2 pi f_n 2 r_ij / c)
+ * signal: [n_meas][n_freq] complex (output).  alpha_out/trans_out: optional
+ * [n_ray*n_z] outputs (NULL to skip).
+ * ------------------------------------------------------------------------ */
+size_t rfvr_render_forward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples* sm);
+int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const rfvr_fields* fl,
+                        uint32_t flags, float* signal, float* alpha_out, float* trans_out,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of rfvr_render_forward (App. A.4 signal-tracing backward), with the
+ * per-term phases and amplitudes recomputed rather than stored:
+ *   G_ij = sum_n Re(g_signal[i,n] exp(+j 2 pi f_n 2 r_ij / c)),
+ * chained through the amplitude, the transmittance product scan, alpha(Phi),
+ * Phi(s f) and n_hat = grad / max(|grad|, 1e-12).  phi_* are detached.
+ * Clamps pass gradient on their closed interval.
+ * g_signal: [n_meas][n_freq] complex (input, PyTorch convention dL/dRe + j dL/dIm).
+ * Outputs (any may be NULL to skip): g_sdf [n_ray*n_z], g_grad [n_ray*n_z][3],
+ * g_refl [n_ray*n_z], g_amp [1] (dL/dA'), g_s [1] (dL/ds). */
+size_t rfvr_render_backward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples* sm);
+int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const rfvr_fields* fl,
+                         uint32_t flags, const float* g_signal, float* g_sdf, float* g_grad,
+                         float* g_refl, float* g_amp, float* g_s,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Matched filter (filter-based rendering, Eq. mf-sm; App. A.4, Alg. 1)
+ *   z_q = sum_{i,n} signal[i,n] exp(+j 2 pi f_n d_iq / c),  power_q = |z_q|
+ * with the monostatic round trip d_iq = 2 |x_q - tx_i|.
+ * xyz_q: [n_q][3] query points.  signal2: optional second signal filtered at
+ * the same points (e.g. the measured one), with outputs z2/power2.
+ * Any of z, power, z2, power2 may be NULL.
+ * ------------------------------------------------------------------------ */
+size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_signals);
+int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q,
+                    const float* signal, float* z, float* power,
+                    const float* signal2, float* z2, float* power2,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of rfvr_mf_forward through power = |z| (App. A.4, Alg. 1 backward):
+ *   g_signal[i,n] = sum_q g_power_q (z_q / power_q) exp(-j 2 pi f_n d_iq / c),
+ * a point with power_q == 0 contributes nothing.  z: [n_q] complex, power: [n_q],
+ * g_power: [n_q] inputs; g_signal: [n_meas][n_freq] complex output. */
+size_t rfvr_mf_backward_ws_bytes(const rfvr_aperture* ap, int64_t n_q);
+int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q,
+                     const float* z, const float* power, const float* g_power,
+                     uint32_t flags, float* g_signal, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * L2 heatmap loss (Sec. Overview, step 5):
+ *   loss = (1/n) sum_q m_q (p_q - p*_q)^2 ,  g_p = 2 m (p - p*) / n
+ * mask may be NULL (m = 1).  loss: [1] float output; g_p: [n] output or NULL.
+ * ------------------------------------------------------------------------ */
+size_t rfvr_loss_ws_bytes(int64_t n);
+int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* mask,
+                 float* loss, float* g_p, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Lensless primary-ray sampling (Sec. "Lensless Sampling", Primary Ray)
+ * Rays run parallel to primary_dir from the aperture plane (through the
+ * origin, normal to primary_dir) through a cube of centre `centre` and half
+ * side `half_extent`; lateral grid of cell centres, ray r = iy*n_ray_x + ix,
+ * lateral axes e1 = unit(y x w_p) (x x w_p if w_p is within ~26 deg of y),
+ * e2 = w_p x e1.  Depth u over [c.w_p - h, c.w_p + h] in n_z strata:
+ *   GRID:       u_k = lo + (k + 1/2) 2h/n_z
+ *   STRATIFIED: u_k = lo + (k + xi) 2h/n_z, xi = (SplitMix64(key, r*n_z+k) >> 40) 2^-24,
+ *               key = SplitMix64(seed, step) (k-th output of SplitMix64 from a
+ *               state = mix(state + (k+1) * 0x9E3779B97F4A7C15))
+ * Outputs: xyz [n_ray][n_z][3], u [n_ray][n_z] (NULL to skip), ray_origin
+ * [n_ray][3] (NULL to skip).
+ * ------------------------------------------------------------------------ */
+#define RFVR_SAMPLE_GRID        0
+#define RFVR_SAMPLE_STRATIFIED  1
+typedef struct rfvr_sample_desc {
+    float    centre[3];
+    float    half_extent;
+    float    primary_dir[3];     /* need not be normalised; non-zero */
+    int32_t  n_ray_x, n_ray_y, n_z;
+    int32_t  mode;               /* RFVR_SAMPLE_* */
+    uint64_t seed, step;
+} rfvr_sample_desc;
+int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* ray_origin,
+                       void* stream);
+
+/* ------------------------------------------------------------------------
+ * SDF network with reflectiveness head (Sec. "Opaque density representation",
+ * "Signal representation"; App. C).  x_hat = (x - centre)/half_size,
+ * gamma = [x_hat, sin(2^k pi x_hat), cos(2^k pi x_hat) for k < pe_octaves]
+ * (3 + 6*pe_octaves values), h_l = softplus_beta(W h_{l-1} + b) for n_layers
+ * layers of `width`, f = half_size (w_out . h + b_out) metres,
+ * head g_k = relu(Wh g_{k-1} + bh) for head_layers layers of head_width on
+ * the last trunk activation, a = sigmoid(wh_out . g + bh_out).
+ * params: flat float32 vector, row-major [out][in] matrices in the order
+ *   W_0,b_0,...,W_{L-1},b_{L-1}, w_out,b_out, Wh_0,bh_0,...,wh_out,bh_out.
+ * ------------------------------------------------------------------------ */
+#define RFVR_PREC_FP32 0
+#define RFVR_PREC_BF16 1         /* BF16 matrix operands, FP32 accumulation */
+typedef struct rfvr_mlp {
+    int32_t      n_layers;       /* 1..16 */
+    int32_t      width;          /* multiple of 64, <= 512 */
+    int32_t      pe_octaves;     /* 0..12 */
+    int32_t      head_width;     /* multiple of 64, <= 256 */
+    int32_t      head_layers;    /* 1..4 */
+    float        softplus_beta;  /* > 0 */
+    float        centre[3];
+    float        half_size;      /* > 0 */
+    int32_t      precision;      /* RFVR_PREC_* */
+    const float* params;         /* device, rfvr_mlp_param_count() floats */
+} rfvr_mlp;
+int64_t rfvr_mlp_param_count(const rfvr_mlp* net);
+
+/* f [n], grad = grad_x f [n][3], refl = a [n]; any output may be NULL. */
+size_t rfvr_mlp_forward_ws_bytes(const rfvr_mlp* net, int64_t n);
+int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sdf, float* grad,
+                     float* refl, void* ws, size_t ws_bytes, void* stream);
+
+/* Parameter gradient of J = sum_q g_sdf f + g_grad . grad_x f + g_refl a,
+ * including the second-order path through grad_x f; activations recomputed.
+ * Inputs g_sdf/g_grad/g_refl may be NULL (= 0).  g_params: rfvr_mlp_param_count()
+ * floats, overwritten unless flags has RFVR_ACCUMULATE. */
+size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp* net, int64_t n);
+int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
+                      const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * AdamW update (App. C: AdamW with cosine annealing), step t >= 1:
+ *   m = b1 m + (1-b1) g ; v = b2 v + (1-b2) g^2
+ *   p -= lr * ( m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps) + wd * p )
+ * ------------------------------------------------------------------------ */
+int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t t, float lr,
+               float b1, float b2, float eps, float wd, void* stream);
+
+/* Library information. */
+const char* rfvr_last_error(void);
+int rfvr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFVR_H */

@@ -1,0 +1,384 @@
+// C ABI of librfvr: argument validation, workspace layout and launches.
+// Every check runs before the first enqueue, so a failing call enqueues nothing.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "rfvr_impl.hpp"
+
+namespace rfvr {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return RFVR_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return RFVR_E_HIP;
+}
+
+static constexpr int kMaxFreq = 8192;
+
+static int check_aperture(const rfvr_aperture* ap, bool allow_rx) {
+    if (!ap) { set_error("aperture descriptor is NULL"); return RFVR_E_INVALID; }
+    if (ap->n_meas < 1) { set_error("n_meas must be >= 1 (got %d)", ap->n_meas); return RFVR_E_INVALID; }
+    if (ap->n_freq < 1 || ap->n_freq > kMaxFreq) {
+        set_error("n_freq must be in [1, %d] (got %d)", kMaxFreq, ap->n_freq);
+        return RFVR_E_INVALID;
+    }
+    if (!ap->tx) { set_error("aperture tx is NULL"); return RFVR_E_INVALID; }
+    if (!std::isfinite(ap->f0_hz) || !std::isfinite(ap->df_hz) || ap->f0_hz <= 0.0 || ap->df_hz < 0.0) {
+        set_error("f0_hz must be finite and > 0, df_hz finite and >= 0");
+        return RFVR_E_INVALID;
+    }
+    if (ap->rx && !allow_rx) {
+        set_error("bistatic apertures (rx != NULL) are not implemented on the GPU");
+        return RFVR_E_UNSUPPORTED;
+    }
+    return RFVR_OK;
+}
+
+static int check_samples(const rfvr_samples* sm) {
+    if (!sm) { set_error("samples descriptor is NULL"); return RFVR_E_INVALID; }
+    if (sm->n_ray < 1 || sm->n_z < 1) {
+        set_error("n_ray and n_z must be >= 1 (got %d, %d)", sm->n_ray, sm->n_z);
+        return RFVR_E_INVALID;
+    }
+    if (!sm->xyz) { set_error("samples xyz is NULL"); return RFVR_E_INVALID; }
+    return RFVR_OK;
+}
+
+static int check_fields(const rfvr_fields* fl) {
+    if (!fl) { set_error("fields descriptor is NULL"); return RFVR_E_INVALID; }
+    if (!fl->sdf || !fl->grad || !fl->refl) { set_error("fields sdf/grad/refl must not be NULL"); return RFVR_E_INVALID; }
+    if (!std::isfinite(fl->s) || fl->s <= 0.0f) { set_error("fields s must be finite and > 0"); return RFVR_E_INVALID; }
+    if (!std::isfinite(fl->amp_tx)) { set_error("fields amp_tx must be finite"); return RFVR_E_INVALID; }
+    if (fl->phi_rx) { set_error("phi_rx is reserved for bistatic apertures and must be NULL"); return RFVR_E_UNSUPPORTED; }
+    return RFVR_OK;
+}
+
+static int check_flags(uint32_t flags) {
+    if ((flags & ~(RFVR_SPEC_MASK | RFVR_PHASE_NAIVE32 | RFVR_ACCUMULATE)) != 0 ||
+        (flags & RFVR_SPEC_MASK) == 3u) {
+        set_error("unknown flag bits 0x%x", flags);
+        return RFVR_E_INVALID;
+    }
+    return RFVR_OK;
+}
+
+static RenderGeom make_geom(const rfvr_aperture* ap, int n_ray, int n_z) {
+    RenderGeom g;
+    g.n_meas = ap->n_meas;
+    g.n_freq = ap->n_freq;
+    g.n_ray = n_ray;
+    g.n_z = n_z;
+    g.n_pts = (long)n_ray * n_z;
+    g.K0 = 2.0 * ap->f0_hz / kSpeedOfLight;
+    g.Kd = 2.0 * ap->df_hz / kSpeedOfLight;
+    return g;
+}
+
+static int padded_freq(int n_freq) { return (n_freq + 31) / 32 * 32; }
+
+static int render_splits(const RenderGeom& g) {
+    const int F = freq_chunk(g.n_freq);
+    const int n_chunks = (g.n_freq + F - 1) / F;
+    return choose_point_splits(g.n_pts, g.n_meas * n_chunks);
+}
+
+static int check_ws(void* ws, size_t have, size_t need) {
+    if (need > 0 && (!ws || have < need)) {
+        set_error("workspace too small: need %zu bytes, got %zu", need, ws ? have : (size_t)0);
+        return RFVR_E_WORKSPACE;
+    }
+    if (ws && (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("workspace must be 256-byte aligned");
+        return RFVR_E_WORKSPACE;
+    }
+    return RFVR_OK;
+}
+
+// ---------------------------------------------------------------- workspace layouts
+static size_t ws_render_forward(const RenderGeom& g) {
+    const int ns = render_splits(g);
+    return align256(sizeof(AntRec) * g.n_meas) + align256(sizeof(PtRec) * g.n_pts) +
+           align256(sizeof(float2) * (size_t)ns * g.n_meas * g.n_freq);
+}
+
+static size_t ws_render_backward(const RenderGeom& g) {
+    const size_t np = padded_freq(g.n_freq);
+    return align256(sizeof(AntRec) * g.n_meas) + align256(sizeof(PtRec) * g.n_pts) +
+           4 * align256(sizeof(float) * g.n_pts) +               // alpha, trans, g_b, g_T
+           align256(sizeof(float) * 3 * g.n_pts) +               // g_n
+           align256(sizeof(float) * g.n_pts) +                   // g_alpha
+           align256(sizeof(float2) * g.n_meas * np) +            // padded g_signal
+           2 * align256(sizeof(float) * g.n_ray);                // per-ray partials
+}
+
+static size_t ws_mf_forward(const rfvr_aperture* ap, int two) {
+    const size_t np = padded_freq(ap->n_freq);
+    return align256(sizeof(AntRec) * ap->n_meas) +
+           (two ? 2 : 1) * align256(sizeof(float2) * ap->n_meas * np);
+}
+
+static int mf_splits(const rfvr_aperture* ap, long n_q) {
+    const int F = freq_chunk(ap->n_freq);
+    return choose_point_splits(n_q, ap->n_meas * ((ap->n_freq + F - 1) / F));
+}
+
+static size_t ws_mf_backward(const rfvr_aperture* ap, long n_q) {
+    const int ns = mf_splits(ap, n_q);
+    return align256(sizeof(AntRec) * ap->n_meas) + align256(sizeof(QRec) * n_q) +
+           align256(sizeof(float2) * (size_t)ns * ap->n_meas * ap->n_freq);
+}
+
+static int loss_blocks(long n) {
+    long b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+}  // namespace rfvr
+
+using namespace rfvr;
+
+extern "C" {
+
+const char* rfvr_last_error(void) { return g_err; }
+int rfvr_version(void) { return 100; }
+
+// ---------------------------------------------------------------- render
+size_t rfvr_render_forward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples* sm) {
+    if (check_aperture(ap, false) || check_samples(sm)) return 0;
+    return ws_render_forward(make_geom(ap, sm->n_ray, sm->n_z));
+}
+
+int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const rfvr_fields* fl,
+                        uint32_t flags, float* signal, float* alpha_out, float* trans_out,
+                        void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_aperture(ap, false)) || (rc = check_samples(sm)) || (rc = check_fields(fl)) ||
+        (rc = check_flags(flags)))
+        return rc;
+    if (!signal) { set_error("signal output is NULL"); return RFVR_E_INVALID; }
+    const RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
+    if ((rc = check_ws(ws, ws_bytes, ws_render_forward(g)))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    AntRec* ant = cur.take<AntRec>(g.n_meas);
+    PtRec* rec = cur.take<PtRec>(g.n_pts);
+    const int ns = render_splits(g);
+    float2* partial = cur.take<float2>((size_t)ns * g.n_meas * g.n_freq);
+    const int use_phi = (fl->phi_ray && fl->phi_tx) ? 1 : 0;
+    if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
+                         "ant records")))
+        return rc;
+    if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, fl->sdf, fl->grad, fl->refl,
+                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, rec, alpha_out,
+                                            trans_out, st),
+                         "render prep")))
+        return rc;
+    if ((rc = hip_status(launch_reduce_points_render(g, ant, rec, flags, ns, partial, st),
+                         "render term kernel")))
+        return rc;
+    return hip_status(launch_split_sum(partial, ns, (long)g.n_meas * g.n_freq, 0,
+                                       reinterpret_cast<float2*>(signal), st),
+                      "render split sum");
+}
+
+size_t rfvr_render_backward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples* sm) {
+    if (check_aperture(ap, false) || check_samples(sm)) return 0;
+    return ws_render_backward(make_geom(ap, sm->n_ray, sm->n_z));
+}
+
+int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const rfvr_fields* fl,
+                         uint32_t flags, const float* g_signal, float* g_sdf, float* g_grad,
+                         float* g_refl, float* g_amp, float* g_s, void* ws, size_t ws_bytes,
+                         void* stream) {
+    int rc;
+    if ((rc = check_aperture(ap, false)) || (rc = check_samples(sm)) || (rc = check_fields(fl)) ||
+        (rc = check_flags(flags)))
+        return rc;
+    if (!g_signal) { set_error("g_signal is NULL"); return RFVR_E_INVALID; }
+    const RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
+    if ((rc = check_ws(ws, ws_bytes, ws_render_backward(g)))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int acc = (flags & RFVR_ACCUMULATE) ? 1 : 0;
+    const int np = padded_freq(g.n_freq);
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    AntRec* ant = cur.take<AntRec>(g.n_meas);
+    PtRec* rec = cur.take<PtRec>(g.n_pts);
+    float* alpha = cur.take<float>(g.n_pts);
+    float* trans = cur.take<float>(g.n_pts);
+    float* gb = cur.take<float>(g.n_pts);
+    float* gT = cur.take<float>(g.n_pts);
+    float* gn = cur.take<float>(3 * (size_t)g.n_pts);
+    float* galpha = cur.take<float>(g.n_pts);
+    float2* gpad = cur.take<float2>((size_t)g.n_meas * np);
+    float* pamp = cur.take<float>(g.n_ray);
+    float* ps = cur.take<float>(g.n_ray);
+    const int use_phi = (fl->phi_ray && fl->phi_tx) ? 1 : 0;
+    if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
+                         "ant records")))
+        return rc;
+    if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, fl->sdf, fl->grad, fl->refl,
+                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, rec, alpha,
+                                            trans, st),
+                         "render prep")))
+        return rc;
+    if ((rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(g_signal), g.n_meas,
+                                           g.n_freq, np, gpad, st),
+                         "pad g_signal")))
+        return rc;
+    if ((rc = hip_status(launch_render_bwd_points(g, ant, rec, gpad, np, flags, gb, gT, gn, st),
+                         "render adjoint term kernel")))
+        return rc;
+    if ((rc = hip_status(launch_scan_adjoint(g, sm->ray_weight, fl->sdf, fl->grad, fl->refl, fl->s,
+                                             fl->amp_tx, alpha, trans, gb, gT, gn, galpha, pamp, ps,
+                                             g_sdf, g_grad, g_refl, acc, st),
+                         "scan adjoint")))
+        return rc;
+    if (g_amp && (rc = hip_status(launch_sum_scalars(pamp, g.n_ray, g_amp, acc, st), "sum g_amp")))
+        return rc;
+    if (g_s && (rc = hip_status(launch_sum_scalars(ps, g.n_ray, g_s, acc, st), "sum g_s")))
+        return rc;
+    return RFVR_OK;
+}
+
+// ---------------------------------------------------------------- matched filter
+size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_signals) {
+    if (check_aperture(ap, false) || n_q < 1) return 0;
+    return ws_mf_forward(ap, two_signals);
+}
+
+int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, const float* signal,
+                    float* z, float* power, const float* signal2, float* z2, float* power2,
+                    void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_aperture(ap, false))) return rc;
+    if (n_q < 1 || !xyz_q || !signal) { set_error("n_q >= 1, xyz_q and signal are required"); return RFVR_E_INVALID; }
+    if (n_q > (int64_t)1 << 40) { set_error("n_q too large"); return RFVR_E_INVALID; }
+    const int two = signal2 ? 1 : 0;
+    if ((rc = check_ws(ws, ws_bytes, ws_mf_forward(ap, two)))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const RenderGeom g = make_geom(ap, 1, 1);
+    const int np = padded_freq(ap->n_freq);
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    AntRec* ant = cur.take<AntRec>(ap->n_meas);
+    float2* sp = cur.take<float2>((size_t)ap->n_meas * np);
+    float2* sp2 = two ? cur.take<float2>((size_t)ap->n_meas * np) : nullptr;
+    if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
+    if ((rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(signal), ap->n_meas,
+                                           ap->n_freq, np, sp, st), "pad signal")))
+        return rc;
+    if (two && (rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(signal2),
+                                                  ap->n_meas, ap->n_freq, np, sp2, st), "pad signal2")))
+        return rc;
+    return hip_status(launch_mf_forward(g, ant, xyz_q, (long)n_q, sp, sp2, np, 0,
+                                        reinterpret_cast<float2*>(z), power,
+                                        reinterpret_cast<float2*>(z2), power2, st),
+                      "mf forward");
+}
+
+size_t rfvr_mf_backward_ws_bytes(const rfvr_aperture* ap, int64_t n_q) {
+    if (check_aperture(ap, false) || n_q < 1) return 0;
+    return ws_mf_backward(ap, (long)n_q);
+}
+
+int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, const float* z,
+                     const float* power, const float* g_power, uint32_t flags, float* g_signal,
+                     void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_aperture(ap, false)) || (rc = check_flags(flags))) return rc;
+    if (n_q < 1 || !xyz_q || !z || !power || !g_power || !g_signal) {
+        set_error("n_q >= 1 and xyz_q, z, power, g_power, g_signal are required");
+        return RFVR_E_INVALID;
+    }
+    if ((rc = check_ws(ws, ws_bytes, ws_mf_backward(ap, (long)n_q)))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    RenderGeom g = make_geom(ap, 1, 1);
+    g.n_pts = (long)n_q;
+    const int ns = mf_splits(ap, (long)n_q);
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    AntRec* ant = cur.take<AntRec>(ap->n_meas);
+    QRec* rec = cur.take<QRec>((size_t)n_q);
+    float2* partial = cur.take<float2>((size_t)ns * ap->n_meas * ap->n_freq);
+    if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
+    if ((rc = hip_status(launch_mf_bwd_records(xyz_q, (long)n_q, reinterpret_cast<const float2*>(z),
+                                               power, g_power, rec, st), "mf adjoint records")))
+        return rc;
+    if ((rc = hip_status(launch_reduce_points_mf(g, ant, rec, flags, ns, partial, st),
+                         "mf adjoint term kernel")))
+        return rc;
+    return hip_status(launch_split_sum(partial, ns, (long)ap->n_meas * ap->n_freq,
+                                       (flags & RFVR_ACCUMULATE) ? 1 : 0,
+                                       reinterpret_cast<float2*>(g_signal), st),
+                      "mf adjoint split sum");
+}
+
+// ---------------------------------------------------------------- loss
+size_t rfvr_loss_ws_bytes(int64_t n) {
+    if (n < 1) return 0;
+    return align256(sizeof(double) * loss_blocks((long)n));
+}
+
+int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* mask, float* loss,
+                 float* g_p, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1 || !p || !p_star || !loss) { set_error("n >= 1, p, p_star and loss are required"); return RFVR_E_INVALID; }
+    int rc;
+    if ((rc = check_ws(ws, ws_bytes, rfvr_loss_ws_bytes(n)))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int nb = loss_blocks((long)n);
+    double* part = reinterpret_cast<double*>(ws);
+    if ((rc = hip_status(launch_loss_partial((long)n, p, p_star, mask, g_p, part, nb, st), "loss partial")))
+        return rc;
+    return hip_status(launch_loss_final(part, nb, (long)n, loss, st), "loss final");
+}
+
+// ---------------------------------------------------------------- sampling
+int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* ray_origin,
+                       void* stream) {
+    if (!d || !xyz) { set_error("descriptor and xyz are required"); return RFVR_E_INVALID; }
+    if (d->n_ray_x < 1 || d->n_ray_y < 1 || d->n_z < 1) { set_error("ray counts must be >= 1"); return RFVR_E_INVALID; }
+    if (!(d->half_extent > 0.0f) || !std::isfinite(d->half_extent)) { set_error("half_extent must be finite and > 0"); return RFVR_E_INVALID; }
+    if (d->mode != RFVR_SAMPLE_GRID && d->mode != RFVR_SAMPLE_STRATIFIED) { set_error("unknown sampling mode %d", d->mode); return RFVR_E_INVALID; }
+    double w[3] = {d->primary_dir[0], d->primary_dir[1], d->primary_dir[2]};
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(w[c]) || !std::isfinite((double)d->centre[c])) { set_error("non-finite direction or centre"); return RFVR_E_INVALID; }
+    double nw = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (!(nw > 0.0)) { set_error("primary_dir must be non-zero"); return RFVR_E_INVALID; }
+    for (int c = 0; c < 3; ++c) w[c] /= nw;
+    double ref[3] = {0.0, 1.0, 0.0};
+    if (std::fabs(w[1]) >= 0.9) { ref[0] = 1.0; ref[1] = 0.0; }
+    double e1[3] = {ref[1] * w[2] - ref[2] * w[1], ref[2] * w[0] - ref[0] * w[2], ref[0] * w[1] - ref[1] * w[0]};
+    double n1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int c = 0; c < 3; ++c) e1[c] /= n1;
+    double e2[3] = {w[1] * e1[2] - w[2] * e1[1], w[2] * e1[0] - w[0] * e1[2], w[0] * e1[1] - w[1] * e1[0]};
+    double basis[9] = {e1[0], e1[1], e1[2], e2[0], e2[1], e2[2], w[0], w[1], w[2]};
+    return hip_status(launch_sample_points(*d, basis, xyz, u, ray_origin,
+                                           reinterpret_cast<hipStream_t>(stream)),
+                      "sample points");
+}
+
+// ---------------------------------------------------------------- AdamW
+int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t t, float lr,
+               float b1, float b2, float eps, float wd, void* stream) {
+    if (n < 1 || !p || !g || !m || !v || t < 1) { set_error("n >= 1, t >= 1 and all arrays are required"); return RFVR_E_INVALID; }
+    if (!std::isfinite(lr) || !std::isfinite(b1) || !std::isfinite(b2) || !std::isfinite(eps) || !std::isfinite(wd) ||
+        b1 < 0.0f || b1 >= 1.0f || b2 < 0.0f || b2 >= 1.0f) {
+        set_error("invalid AdamW hyper-parameters");
+        return RFVR_E_INVALID;
+    }
+    const float bc1 = (float)(1.0 - std::pow((double)b1, (double)t));
+    const float bc2 = (float)(1.0 - std::pow((double)b2, (double)t));
+    return hip_status(launch_adamw((long)n, p, g, m, v, lr, b1, b2, eps, wd, bc1, bc2,
+                                   reinterpret_cast<hipStream_t>(stream)),
+                      "adamw");
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Small bandwidth-bound kernels: L2 heatmap loss, lensless primary-ray
+// sampling and the AdamW update.
+#include "rfvr_impl.hpp"
+
+namespace rfvr {
+
+// ---------------------------------------------------------------------------
+// loss (Sec. Overview step 5): per-block FP64 partial sums, fixed-order final
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loss_partial(long n, const float* __restrict__ p,
+                                                      const float* __restrict__ ps,
+                                                      const float* __restrict__ mask,
+                                                      float* __restrict__ g_p,
+                                                      double* __restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const float inv_n2 = (float)(2.0 / (double)n);
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256) {
+        const float m = mask ? mask[q] : 1.0f;
+        const float d = p[q] - ps[q];
+        acc += (double)(m * d) * (double)d;
+        if (g_p) g_p[q] = inv_n2 * m * d;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int nb,
+                                                    long n, float* __restrict__ loss) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) acc += part[k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = (float)(sh[0] / (double)n);
+}
+
+hipError_t launch_loss_partial(long n, const float* p, const float* ps, const float* mask,
+                               float* g_p, double* part, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss_partial, dim3(n_blocks), dim3(256), 0, st, n, p, ps, mask, g_p, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_final(const double* part, int n_blocks, long n, float* loss,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, n_blocks, n, loss);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// lensless primary-ray sampling (Sec. Lensless Sampling, Primary Ray)
+// counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): k-th output from
+// state x is mix(x + (k+1) * 0x9E3779B97F4A7C15).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t sm64_output(uint64_t state, uint64_t k) {
+    return sm64_mix(state + (k + 1ull) * 0x9E3779B97F4A7C15ull);
+}
+
+struct SampleArgs {
+    double e1[3], e2[3], w[3];
+    double base[3];      // centre projected onto the aperture plane
+    double lo;           // c.w - h
+    double h;
+    int n_rx, n_ry, n_z, mode;
+    uint64_t key;        // per-step stream key
+};
+
+__global__ void k_sample_points(SampleArgs a, float* __restrict__ xyz, float* __restrict__ u_out,
+                                float* __restrict__ origin) {
+    const long n_ray = (long)a.n_rx * a.n_ry;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ray * a.n_z) return;
+    const long r = t / a.n_z;
+    const int k = (int)(t % a.n_z);
+    const int ix = (int)(r % a.n_rx), iy = (int)(r / a.n_rx);
+    const double lx = -a.h + (ix + 0.5) * 2.0 * a.h / a.n_rx;
+    const double ly = -a.h + (iy + 0.5) * 2.0 * a.h / a.n_ry;
+    double o[3];
+    for (int c = 0; c < 3; ++c) o[c] = a.base[c] + lx * a.e1[c] + ly * a.e2[c];
+    double frac = 0.5;
+    if (a.mode == RFVR_SAMPLE_STRATIFIED) {
+        const uint64_t v = sm64_output(a.key, (uint64_t)t);
+        frac = (double)(v >> 40) * (1.0 / 16777216.0);
+    }
+    const double u = a.lo + ((double)k + frac) * (2.0 * a.h / a.n_z);
+    for (int c = 0; c < 3; ++c) xyz[3 * t + c] = (float)(o[c] + u * a.w[c]);
+    if (u_out) u_out[t] = (float)u;
+    if (origin && k == 0)
+        for (int c = 0; c < 3; ++c) origin[3 * r + c] = (float)o[c];
+}
+
+hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
+                                float* u, float* origin, hipStream_t st) {
+    SampleArgs a;
+    for (int c = 0; c < 3; ++c) {
+        a.e1[c] = basis[c];
+        a.e2[c] = basis[3 + c];
+        a.w[c] = basis[6 + c];
+    }
+    const double cx = d.centre[0], cy = d.centre[1], cz = d.centre[2];
+    const double cw = cx * a.w[0] + cy * a.w[1] + cz * a.w[2];
+    a.base[0] = cx - cw * a.w[0];
+    a.base[1] = cy - cw * a.w[1];
+    a.base[2] = cz - cw * a.w[2];
+    a.h = d.half_extent;
+    a.lo = cw - a.h;
+    a.n_rx = d.n_ray_x;
+    a.n_ry = d.n_ray_y;
+    a.n_z = d.n_z;
+    a.mode = d.mode;
+    // host copy of the same generator for the per-step key
+    auto mix = [](uint64_t z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    a.key = mix(d.seed + (d.step + 1ull) * 0x9E3779B97F4A7C15ull);
+    const long n = (long)d.n_ray_x * d.n_ray_y * d.n_z;
+    hipLaunchKernelGGL(k_sample_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
+                       xyz, u, origin);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// AdamW (Loshchilov & Hutter): bc1 = 1 - b1^t, bc2 = 1 - b2^t
+// ---------------------------------------------------------------------------
+__global__ void k_adamw(long n, float* __restrict__ p, const float* __restrict__ g,
+                        float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                        float eps, float wd, float bc1, float bc2) {
+    long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const float upd = (mk / bc1) / (sqrtf(vk / bc2) + eps) + wd * p[k];
+    p[k] = p[k] - lr * upd;
+}
+
+hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                        float b2, float eps, float wd, float bc1, float bc2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adamw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, g, m, v,
+                       lr, b1, b2, eps, wd, bc1, bc2);
+    return hipGetLastError();
+}
+
+}  // namespace rfvr

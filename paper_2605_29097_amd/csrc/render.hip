@@ -1,0 +1,575 @@
+// Render kernels: lensless alpha blending (per-ray scan), signal tracing
+// (reduction over points) and its adjoint (reduction over frequencies and
+// measurements), and the adjoint of the transmittance scan.
+//
+// Signal tracing, Eq. ref_sim / App. A.4 Alg. 2, rebuilt for gfx950:
+//  * forward: a lane owns one (measurement, frequency chunk) pair and keeps the
+//    chunk's complex accumulators in VGPRs; all lanes of a wave walk the same
+//    points, so point records arrive through scalar loads (SGPR operands, no
+//    LDS traffic).  Per (measurement, point) the path length and the phase
+//    origin are set up once (FP64 range reduction + hardware sin/cos in
+//    revolutions); the chunk's frequencies then follow by complex rotation,
+//    since f_n is linear in n.  Points are split across work-groups and the
+//    partial sums reduced in a fixed order (no atomics).
+//  * backward: a lane owns one point; all lanes walk the same measurements, so
+//    measurement records and the incoming signal gradient row are scalar loads.
+//    sum_n g[n] exp(+j 2 pi (theta0 + n delta)) is a polynomial in
+//    w = exp(j 2 pi delta), evaluated by Horner's rule (4 FMA per term).
+#include "rfvr_impl.hpp"
+
+namespace rfvr {
+
+int freq_chunk(int n_freq) { return n_freq <= 16 ? 16 : (n_freq <= 32 ? 32 : 64); }
+
+int choose_point_splits(long n_pts, int lanes_total) {
+    long waves_per_split = (lanes_total + 63) / 64;
+    const long target_waves = 4096;           // 16 waves per SIMD on 256 CUs
+    long ns = (target_waves + waves_per_split - 1) / waves_per_split;
+    long max_by_pts = (n_pts + 127) / 128;    // keep >= 128 points per split
+    if (ns > max_by_pts) ns = max_by_pts;
+    if (ns < 1) ns = 1;
+    if (ns > 65535) ns = 65535;
+    return (int)ns;
+}
+
+// ---------------------------------------------------------------------------
+// pair phase set-up
+// ---------------------------------------------------------------------------
+// Start phase of the chunk (revolutions Kstart * |d|) and per-frequency step
+// (Kd * |d|); returns cos/sin of 2 pi times each, and y ~ 1/|d|.
+template <bool NAIVE>
+__device__ __forceinline__ void pair_phase(double dx, double dy, double dz, double Kstart,
+                                           double Kd, float& y, float& c0, float& s0, float& cw,
+                                           float& sw) {
+    if constexpr (!NAIVE) {
+        double r = range_f64(dx, dy, dz, y);
+        float t0 = frac_rev(r * Kstart);
+        float de = (float)(r * Kd);
+        c0 = cos_rev(t0);
+        s0 = sin_rev(t0);
+        cw = cos_rev(de);
+        sw = sin_rev(de);
+    } else {
+        // FP32 path length and FP32 radians, as a plain FP32 implementation
+        // would form 2 pi f d / c; the library sin/cos then reduce exactly.
+        float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        float r = sqrtf(fx * fx + fy * fy + fz * fz);
+        y = 1.0f / r;
+        const float two_pi = 6.2831853071795864769f;
+        float ph0 = (float)(two_pi * Kstart) * r;
+        float phd = (float)(two_pi * Kd) * r;
+        sincosf(ph0, &s0, &c0);
+        sincosf(phd, &sw, &cw);
+    }
+}
+
+template <int SPEC>
+__device__ __forceinline__ void spec_factor(float nd, float& spec, float& live) {
+    if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+        spec = 1.0f;
+        live = 0.0f;
+    } else {
+        float sr = __builtin_fmaf(2.0f * nd, nd, -1.0f);   // 2 (n.w_i)^2 - 1 = w_o . w_r
+        if constexpr (SPEC == (int)RFVR_SPEC_RAW) {
+            spec = sr;
+            live = 1.0f;
+        } else {
+            spec = fmaxf(sr, 0.0f);
+            live = sr >= 0.0f ? 1.0f : 0.0f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// measurement records
+// ---------------------------------------------------------------------------
+__global__ void k_ant_records(const float* __restrict__ tx, const float* __restrict__ phi_tx,
+                              int n_meas, AntRec* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_meas) return;
+    AntRec a;
+    a.x = (double)tx[3 * i];
+    a.y = (double)tx[3 * i + 1];
+    a.z = (double)tx[3 * i + 2];
+    a.phi = phi_tx ? phi_tx[i] : 0.0f;
+    a.pad = 0.0f;
+    out[i] = a;
+}
+
+hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, AntRec* out,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_ant_records, dim3((n_meas + 255) / 256), dim3(256), 0, st, tx, phi_tx,
+                       n_meas, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-ray prep: opacity, transmittance (product scan across the wave) and the
+// per-point records.  One wave per ray, 64 samples per step.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_render_prep(
+    int n_ray, int n_z, const float* __restrict__ xyz, const float* __restrict__ ray_w,
+    const float* __restrict__ sdf, const float* __restrict__ grad, const float* __restrict__ refl,
+    const float* __restrict__ phi_ray, int use_phi, float s, float amp, PtRec* __restrict__ rec,
+    float* __restrict__ alpha_out, float* __restrict__ trans_out) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= n_ray) return;                       // uniform per wave
+    const int r = wave;
+    const float w = ray_w ? ray_w[r] : 1.0f;
+    const float pr = use_phi ? phi_ray[r] : 0.0f;
+    const size_t base = (size_t)r * n_z;
+    float carry = 1.0f;
+    for (int k0 = 0; k0 < n_z; k0 += 64) {
+        const int k = k0 + lane;
+        const bool valid = k < n_z;
+        float alpha = 0.0f;
+        if (k + 1 < n_z) alpha = alpha_pair(s * sdf[base + k], s * sdf[base + k + 1]);
+        float incl = 1.0f - alpha;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            float t = __shfl_up(incl, d, 64);
+            if (lane >= d) incl *= t;
+        }
+        float excl = __shfl_up(incl, 1, 64);
+        if (lane == 0) excl = 1.0f;
+        const float T = carry * excl;
+        carry *= __shfl(incl, 63, 64);
+        if (valid) {
+            const size_t j = base + k;
+            PtRec p;
+            p.x = (double)xyz[3 * j];
+            p.y = (double)xyz[3 * j + 1];
+            p.z = (double)xyz[3 * j + 2];
+            p.b = amp * w * refl[j] * alpha;
+            p.tp = T - pr;
+            float gx = grad[3 * j], gy = grad[3 * j + 1], gz = grad[3 * j + 2];
+            float inv = 1.0f / fmaxf(sqrtf(gx * gx + gy * gy + gz * gz), 1e-12f);
+            p.nx = gx * inv;
+            p.ny = gy * inv;
+            p.nz = gz * inv;
+            p.pad = 0.0f;
+            rec[j] = p;
+            if (alpha_out) alpha_out[j] = alpha;
+            if (trans_out) trans_out[j] = T;
+        }
+    }
+}
+
+hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w,
+                              const float* sdf, const float* grad, const float* refl,
+                              const float* phi_ray, int use_phi, float s, float amp, PtRec* rec,
+                              float* alpha_out, float* trans_out, hipStream_t st) {
+    const int waves_per_block = 4;
+    dim3 grid((g.n_ray + waves_per_block - 1) / waves_per_block);
+    hipLaunchKernelGGL(k_render_prep, grid, dim3(256), 0, st, g.n_ray, g.n_z, xyz, ray_w, sdf,
+                       grad, refl, phi_ray, use_phi, s, amp, rec, alpha_out, trans_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reduction over points: signal tracing forward (KIND 0) and matched-filter
+// adjoint (KIND 1).  Lane t -> measurement i = t % n_meas, chunk c = t / n_meas;
+// grid.y = point split.
+// ---------------------------------------------------------------------------
+template <int F, int KIND, int SPEC, bool NAIVE>
+__global__ __launch_bounds__(256) void k_reduce_points(
+    int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
+    const void* __restrict__ recs_v, long n_pts, long pts_per_split,
+    float2* __restrict__ partial) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = t % n_meas;
+    int c = t / n_meas;
+    const bool live_lane = c < n_chunks;
+    if (!live_lane) c = n_chunks - 1;
+    const AntRec A = ant[i];
+    const double Kc = K0 + (double)(c * F) * Kd;
+
+    float ar[F], ai[F];
+#pragma unroll
+    for (int n = 0; n < F; ++n) {
+        ar[n] = 0.0f;
+        ai[n] = 0.0f;
+    }
+    const long j0 = (long)blockIdx.y * pts_per_split;
+    long j1 = j0 + pts_per_split;
+    if (j1 > n_pts) j1 = n_pts;
+
+    for (long j = j0; j < j1; ++j) {
+        float pr, pi, y, c0, s0, cw, sw;
+        if constexpr (KIND == 0) {
+            const PtRec P = reinterpret_cast<const PtRec*>(recs_v)[j];
+            const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
+            pair_phase<NAIVE>(dx, dy, dz, Kc, Kd, y, c0, s0, cw, sw);
+            float spec, live;
+            if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                spec = 1.0f;
+            } else {
+                float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * y;
+                spec_factor<SPEC>(nd, spec, live);
+            }
+            float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
+            float cm = P.b * spec * (T * T) * (y * y);
+            pr = cm * c0;
+            pi = -cm * s0;                       // c exp(-j 2 pi theta)
+        } else {
+            const QRec Q = reinterpret_cast<const QRec*>(recs_v)[j];
+            const double dx = Q.x - A.x, dy = Q.y - A.y, dz = Q.z - A.z;
+            pair_phase<NAIVE>(dx, dy, dz, Kc, Kd, y, c0, s0, cw, sw);
+            pr = Q.hr * c0 + Q.hi * s0;          // h exp(-j 2 pi theta)
+            pi = Q.hi * c0 - Q.hr * s0;
+        }
+        const float wr = cw, wi = -sw;           // step exp(-j 2 pi delta)
+#pragma unroll
+        for (int n = 0; n < F; ++n) {
+            ar[n] += pr;
+            ai[n] += pi;
+            const float tr = pr * wr - pi * wi;
+            pi = __builtin_fmaf(pr, wi, pi * wr);
+            pr = tr;
+        }
+    }
+    if (live_lane) {
+        float2* out = partial + ((size_t)blockIdx.y * n_meas + i) * n_freq + (size_t)c * F;
+        const int nv = n_freq - c * F;
+#pragma unroll
+        for (int n = 0; n < F; ++n)
+            if (n < nv) out[n] = make_float2(ar[n], ai[n]);
+    }
+}
+
+template <int F, int KIND, int SPEC, bool NAIVE>
+static hipError_t launch_rp(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
+                            float2* partial, hipStream_t st) {
+    const int n_chunks = (g.n_freq + F - 1) / F;
+    const long lanes = (long)g.n_meas * n_chunks;
+    dim3 grid((unsigned)((lanes + 255) / 256), (unsigned)n_split);
+    const long per = (g.n_pts + n_split - 1) / n_split;
+    hipLaunchKernelGGL((k_reduce_points<F, KIND, SPEC, NAIVE>), grid, dim3(256), 0, st, g.n_meas,
+                       g.n_freq, n_chunks, ant, g.K0, g.Kd, rec, g.n_pts, per, partial);
+    return hipGetLastError();
+}
+
+template <int KIND, int SPEC, bool NAIVE>
+static hipError_t launch_rp_f(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
+                              float2* partial, hipStream_t st) {
+    switch (freq_chunk(g.n_freq)) {
+        case 16: return launch_rp<16, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, st);
+        case 32: return launch_rp<32, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, st);
+        default: return launch_rp<64, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, st);
+    }
+}
+
+hipError_t launch_reduce_points_render(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
+                                       uint32_t flags, int n_split, float2* partial,
+                                       hipStream_t st) {
+    const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
+    switch (flags & RFVR_SPEC_MASK) {
+        case RFVR_SPEC_RAW:
+            return naive ? launch_rp_f<0, RFVR_SPEC_RAW, true>(g, ant, rec, n_split, partial, st)
+                         : launch_rp_f<0, RFVR_SPEC_RAW, false>(g, ant, rec, n_split, partial, st);
+        case RFVR_SPEC_OFF:
+            return naive ? launch_rp_f<0, RFVR_SPEC_OFF, true>(g, ant, rec, n_split, partial, st)
+                         : launch_rp_f<0, RFVR_SPEC_OFF, false>(g, ant, rec, n_split, partial, st);
+        default:
+            return naive ? launch_rp_f<0, RFVR_SPEC_CLAMP, true>(g, ant, rec, n_split, partial, st)
+                         : launch_rp_f<0, RFVR_SPEC_CLAMP, false>(g, ant, rec, n_split, partial, st);
+    }
+}
+
+hipError_t launch_reduce_points_mf(const RenderGeom& g, const AntRec* ant, const QRec* rec,
+                                   uint32_t flags, int n_split, float2* partial, hipStream_t st) {
+    const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
+    return naive ? launch_rp_f<1, RFVR_SPEC_OFF, true>(g, ant, rec, n_split, partial, st)
+                 : launch_rp_f<1, RFVR_SPEC_OFF, false>(g, ant, rec, n_split, partial, st);
+}
+
+// fixed-order sum of split partials: out[o] (+)= sum_s partial[s][o]
+__global__ void k_split_sum(const float2* __restrict__ partial, int n_split, long n_out,
+                            int accumulate, float2* __restrict__ out) {
+    long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n_out) return;
+    float sr = 0.0f, si = 0.0f;
+    for (int s = 0; s < n_split; ++s) {
+        float2 v = partial[(size_t)s * n_out + o];
+        sr += v.x;
+        si += v.y;
+    }
+    if (accumulate) {
+        float2 p = out[o];
+        sr += p.x;
+        si += p.y;
+    }
+    out[o] = make_float2(sr, si);
+}
+
+hipError_t launch_split_sum(const float2* partial, int n_split, long n_out, int accumulate,
+                            float2* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_split_sum, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
+                       partial, n_split, n_out, accumulate, out);
+    return hipGetLastError();
+}
+
+// zero-padded copy of a [n_meas][n_freq] complex array to [n_meas][np]
+__global__ void k_pad_signal(const float2* __restrict__ sig, int n_meas, int n_freq, int np,
+                             float2* __restrict__ out) {
+    long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)n_meas * np) return;
+    int i = (int)(o / np), n = (int)(o % np);
+    out[o] = n < n_freq ? sig[(size_t)i * n_freq + n] : make_float2(0.0f, 0.0f);
+}
+
+hipError_t launch_pad_signal(const float2* sig, int n_meas, int n_freq, int np, float2* out,
+                             hipStream_t st) {
+    long n = (long)n_meas * np;
+    hipLaunchKernelGGL(k_pad_signal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sig,
+                       n_meas, n_freq, np, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// signal tracing adjoint: one lane per point, Horner over the frequencies of
+// each measurement's gradient row (scalar loads), chain rule per pair.
+// ---------------------------------------------------------------------------
+template <int SPEC, bool NAIVE>
+__global__ __launch_bounds__(256) void k_render_bwd_points(
+    long n_pts, const PtRec* __restrict__ rec, int n_meas, const AntRec* __restrict__ ant,
+    const float2* __restrict__ gsig, int np, double K0, double Kd, float* __restrict__ g_b,
+    float* __restrict__ g_T, float* __restrict__ g_n) {
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = j < n_pts;
+    const PtRec P = rec[ok ? j : n_pts - 1];
+    float gb = 0.0f, gt = 0.0f, gn0 = 0.0f, gn1 = 0.0f, gn2 = 0.0f;
+    for (int i = 0; i < n_meas; ++i) {
+        const AntRec A = ant[i];
+        const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
+        float y, c0, s0, cw, sw;
+        pair_phase<NAIVE>(dx, dy, dz, K0, Kd, y, c0, s0, cw, sw);
+        // H = sum_n g[n] w^n with w = exp(+j 2 pi delta), highest n first
+        const float2* g = gsig + (size_t)i * np;
+        float hr = 0.0f, hi = 0.0f;
+        for (int n0 = np - 32; n0 >= 0; n0 -= 32) {
+#pragma unroll
+            for (int u = 31; u >= 0; --u) {
+                const float2 gv = g[n0 + u];
+                const float tr = __builtin_fmaf(-hi, sw, __builtin_fmaf(hr, cw, gv.x));
+                hi = __builtin_fmaf(hi, cw, __builtin_fmaf(hr, sw, gv.y));
+                hr = tr;
+            }
+        }
+        const float G = c0 * hr - s0 * hi;       // Re(exp(+j 2 pi theta0) H)
+        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+        float spec, live = 0.0f;
+        float nd = 0.0f;
+        if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+            spec = 1.0f;
+        } else {
+            nd = (P.nx * fdx + P.ny * fdy + P.nz * fdz) * y;
+            spec_factor<SPEC>(nd, spec, live);
+        }
+        const float Tr = P.tp + A.phi;
+        const float T = fminf(fmaxf(Tr, 0.0f), 1.0f);
+        const float mT = (Tr >= 0.0f && Tr <= 1.0f) ? 1.0f : 0.0f;
+        const float gy = G * (y * y);
+        gb = __builtin_fmaf(gy * spec, T * T, gb);
+        gt = __builtin_fmaf(gy * P.b * spec, 2.0f * T * mT, gt);
+        if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
+            // d spec / d n_hat = 4 (n.w_i) w_i, w_i = d * y
+            const float cn = gy * P.b * (T * T) * (4.0f * nd * y) * live;
+            gn0 = __builtin_fmaf(cn, fdx, gn0);
+            gn1 = __builtin_fmaf(cn, fdy, gn1);
+            gn2 = __builtin_fmaf(cn, fdz, gn2);
+        }
+    }
+    if (ok) {
+        g_b[j] = gb;
+        g_T[j] = gt;
+        g_n[3 * j] = gn0;
+        g_n[3 * j + 1] = gn1;
+        g_n[3 * j + 2] = gn2;
+    }
+}
+
+template <int SPEC>
+static hipError_t launch_rbp(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
+                             const float2* gsig, int np, bool naive, float* g_b, float* g_T,
+                             float* g_n, hipStream_t st) {
+    dim3 grid((unsigned)((g.n_pts + 255) / 256));
+    if (naive)
+        hipLaunchKernelGGL((k_render_bwd_points<SPEC, true>), grid, dim3(256), 0, st, g.n_pts, rec,
+                           g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n);
+    else
+        hipLaunchKernelGGL((k_render_bwd_points<SPEC, false>), grid, dim3(256), 0, st, g.n_pts,
+                           rec, g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
+                                    const float2* gsig_pad, int np, uint32_t flags, float* g_b,
+                                    float* g_T, float* g_n, hipStream_t st) {
+    const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
+    switch (flags & RFVR_SPEC_MASK) {
+        case RFVR_SPEC_RAW:
+            return launch_rbp<RFVR_SPEC_RAW>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n, st);
+        case RFVR_SPEC_OFF:
+            return launch_rbp<RFVR_SPEC_OFF>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n, st);
+        default:
+            return launch_rbp<RFVR_SPEC_CLAMP>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n,
+                                               st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the per-ray scan: one wave per ray.
+//   R_k = g_T[k+1] + (1 - alpha_{k+1}) R_{k+1}, R_{n_z-1} = 0  (suffix scan of
+//   affine maps across the wave, chunks from the far end), g_alpha = direct -
+//   T R; then alpha(Phi_k, Phi_{k+1}), Phi = sigmoid(s f), n_hat = g/|g|.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_adjoint(
+    int n_ray, int n_z, const float* __restrict__ ray_w, const float* __restrict__ sdf,
+    const float* __restrict__ grad, const float* __restrict__ refl, float s, float amp,
+    const float* __restrict__ alpha, const float* __restrict__ trans,
+    const float* __restrict__ g_b, const float* __restrict__ g_T, const float* __restrict__ g_n,
+    float* g_alpha_tmp, float* __restrict__ part_amp, float* __restrict__ part_s,
+    float* __restrict__ g_sdf, float* __restrict__ g_grad, float* __restrict__ g_refl,
+    int accumulate) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= n_ray) return;
+    const int r = wave;
+    const size_t base = (size_t)r * n_z;
+    const float w = ray_w ? ray_w[r] : 1.0f;
+    const int nch = (n_z + 63) / 64;
+    float r_in = 0.0f, pamp = 0.0f, ps = 0.0f;
+    for (int cc = nch - 1; cc >= 0; --cc) {
+        const int k = cc * 64 + lane;
+        float A = 0.0f, B = 0.0f;
+        if (k + 1 < n_z) {
+            A = 1.0f - alpha[base + k + 1];
+            B = g_T[base + k + 1];
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const float A2 = __shfl_down(A, d, 64), B2 = __shfl_down(B, d, 64);
+            if (lane + d < 64) {
+                B = __builtin_fmaf(A, B2, B);
+                A = A * A2;
+            }
+        }
+        const float R = __builtin_fmaf(A, r_in, B);
+        const float R0 = __shfl(R, 0, 64);
+        if (k < n_z) {
+            const size_t j = base + k;
+            const float gb = g_b[j], al = alpha[j], a = refl[j];
+            g_alpha_tmp[j] = gb * amp * w * a - trans[j] * R;
+            pamp = __builtin_fmaf(gb * w * a, al, pamp);
+            if (g_refl) {
+                float v = gb * amp * w * al;
+                g_refl[j] = accumulate ? g_refl[j] + v : v;
+            }
+        }
+        r_in = R0;
+    }
+    __threadfence();
+    for (int cc = 0; cc < nch; ++cc) {
+        const int k = cc * 64 + lane;
+        if (k >= n_z) continue;
+        const size_t j = base + k;
+        const float fk = sdf[j];
+        const float xk = s * fk;
+        const float phik = sigmoidf_(xk);
+        float gphi = 0.0f;
+        if (k + 1 < n_z) {
+            const float fnx = sdf[j + 1];
+            if (xk >= s * fnx) {
+                const float phin = sigmoidf_(s * fnx);
+                const float D = phik + kAlphaEps;
+                gphi += g_alpha_tmp[j] * (phin + kAlphaEps) / (D * D);
+            }
+        }
+        if (k >= 1) {
+            const float fp = sdf[j - 1];
+            if (s * fp >= xk) gphi -= g_alpha_tmp[j - 1] / (sigmoidf_(s * fp) + kAlphaEps);
+        }
+        const float dens = phik * sigmoidf_(-xk);
+        if (g_sdf) {
+            float v = gphi * s * dens;
+            g_sdf[j] = accumulate ? g_sdf[j] + v : v;
+        }
+        ps = __builtin_fmaf(gphi * fk, dens, ps);
+        if (g_grad) {
+            const float gx = grad[3 * j], gy = grad[3 * j + 1], gz = grad[3 * j + 2];
+            const float nrm = sqrtf(gx * gx + gy * gy + gz * gz);
+            const float n0 = g_n[3 * j], n1 = g_n[3 * j + 1], n2 = g_n[3 * j + 2];
+            float o0, o1, o2;
+            if (nrm >= 1e-12f) {
+                const float inv = 1.0f / nrm;
+                const float hx = gx * inv, hy = gy * inv, hz = gz * inv;
+                const float dd = hx * n0 + hy * n1 + hz * n2;
+                o0 = (n0 - hx * dd) * inv;
+                o1 = (n1 - hy * dd) * inv;
+                o2 = (n2 - hz * dd) * inv;
+            } else {
+                o0 = n0 * 1e12f;
+                o1 = n1 * 1e12f;
+                o2 = n2 * 1e12f;
+            }
+            if (accumulate) {
+                o0 += g_grad[3 * j];
+                o1 += g_grad[3 * j + 1];
+                o2 += g_grad[3 * j + 2];
+            }
+            g_grad[3 * j] = o0;
+            g_grad[3 * j + 1] = o1;
+            g_grad[3 * j + 2] = o2;
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        pamp += __shfl_xor(pamp, d, 64);
+        ps += __shfl_xor(ps, d, 64);
+    }
+    if (lane == 0) {
+        part_amp[r] = pamp;
+        part_s[r] = ps;
+    }
+}
+
+hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const float* sdf,
+                               const float* grad, const float* refl, float s, float amp,
+                               const float* alpha, const float* trans, const float* g_b,
+                               const float* g_T, const float* g_n, float* g_alpha_tmp,
+                               float* part_amp, float* part_s, float* g_sdf, float* g_grad,
+                               float* g_refl, int accumulate, hipStream_t st) {
+    dim3 grid((g.n_ray + 3) / 4);
+    hipLaunchKernelGGL(k_scan_adjoint, grid, dim3(256), 0, st, g.n_ray, g.n_z, ray_w, sdf, grad,
+                       refl, s, amp, alpha, trans, g_b, g_T, g_n, g_alpha_tmp, part_amp, part_s,
+                       g_sdf, g_grad, g_refl, accumulate);
+    return hipGetLastError();
+}
+
+// deterministic sum of n floats into out[0] (one work-group, fixed order)
+__global__ __launch_bounds__(256) void k_sum_scalars(const float* __restrict__ part, int n,
+                                                     float* __restrict__ out, int accumulate) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) acc += (double)part[k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float v = (float)sh[0];
+        out[0] = accumulate ? out[0] + v : v;
+    }
+}
+
+hipError_t launch_sum_scalars(const float* part, int n, float* out, int accumulate,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_scalars, dim3(1), dim3(256), 0, st, part, n, out, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace rfvr

@@ -1,0 +1,162 @@
+// Internal declarations of librfvr (not part of the C ABI).
+//
+// Device-side conventions shared by the term kernels:
+//  * complex values are float2 {re, im};
+//  * phases are handled in revolutions: the term for (pair, frequency n) is
+//    exp(-+ j 2 pi (theta0 + n * delta)) with theta0 = f0 * d / c and
+//    delta = df * d / c, d the round-trip path length;
+//  * the default phase mode forms d and the fractional part of theta0 in
+//    FP64 (the only step whose conditioning needs it) and runs everything else
+//    in FP32, with the hardware sin/cos that take revolutions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/rfvr.h"
+
+namespace rfvr {
+
+constexpr double kSpeedOfLight = 299792458.0;
+constexpr float kAlphaEps = 1e-5f;
+
+// Per-point record consumed by the render kernels (48 bytes).
+//   b  = A' * w_r * a * alpha      (amplitude without the per-pair factors)
+//   tp = T - Phi(primary-ray origin)  (lensless transmittance before the per-
+//        antenna shift; equals T when the correction is off)
+struct alignas(16) PtRec {
+    double x, y, z;
+    float b, tp, nx, ny, nz, pad;
+};
+static_assert(sizeof(PtRec) == 48, "PtRec layout");
+
+// Per-query record of the matched-filter adjoint: h = g_P * z / P.
+struct alignas(16) QRec {
+    double x, y, z;
+    float hr, hi;
+};
+static_assert(sizeof(QRec) == 32, "QRec layout");
+
+// Per-measurement record (positions in FP64 so the path length is exact in the
+// inputs; phi = Phi_s at the transmitter, 0 when the correction is off).
+struct alignas(16) AntRec {
+    double x, y, z;
+    float phi, pad;
+};
+static_assert(sizeof(AntRec) == 32, "AntRec layout");
+
+// ----------------------------------------------------------------------------
+// device helpers
+// ----------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RFVR_DEV __device__ __forceinline__
+#else
+#define RFVR_DEV __host__ __device__ inline
+#endif
+
+// |d| in FP64 from an FP32 reciprocal square root and one Newton step
+// (relative error ~1e-14); also returns y ~ 1/|d| in FP32.
+__device__ __forceinline__ double range_f64(double dx, double dy, double dz, float& y) {
+    double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    y = __builtin_amdgcn_rsqf((float)r2);
+    double yd = (double)y;
+    double r0 = r2 * yd;
+    double e = __builtin_fma(-r0, r0, r2);
+    return __builtin_fma(e, 0.5 * yd, r0);
+}
+
+// fractional part in [0, 1) of an FP64 value, returned in FP32
+__device__ __forceinline__ float frac_rev(double t) {
+    return (float)__builtin_amdgcn_fract(t);
+}
+
+// cos / sin of 2*pi*x for x in revolutions (|x| < 256)
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// Opacity between consecutive samples with logits a = s f_k, b = s f_{k+1}:
+// clamp((Phi(a) - Phi(b)) / (Phi(a) + eps), 0, 1).  The difference is formed
+// as Phi(b) (1 - Phi(a)) expm1(a - b), an exact identity of the logistic CDF
+// that avoids cancellation when both samples are far outside the surface.
+__device__ __forceinline__ float alpha_pair(float a, float b) {
+    if (!(a >= b)) return 0.0f;
+    float diff = sigmoidf_(b) * sigmoidf_(-a) * expm1f(a - b);
+    float al = diff / (sigmoidf_(a) + kAlphaEps);
+    return fminf(al, 1.0f);
+}
+
+// ----------------------------------------------------------------------------
+// host-side internals shared between translation units
+// ----------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+int hip_status(hipError_t e, const char* what);
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bump allocator over the caller's workspace.
+struct WsCursor {
+    char* base;
+    size_t used;
+    template <class T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base + used);
+        used += align256(count * sizeof(T));
+        return p;
+    }
+};
+
+// Launchers (render.hip)
+struct RenderGeom {
+    int n_meas, n_freq, n_ray, n_z;
+    long n_pts;
+    double K0, Kd;        // 2 f0 / c and 2 df / c (revolutions per metre of range)
+};
+int choose_point_splits(long n_pts, int lanes_total);
+int freq_chunk(int n_freq);
+
+hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, AntRec* out,
+                              hipStream_t st);
+hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w,
+                              const float* sdf, const float* grad, const float* refl,
+                              const float* phi_ray, int use_phi, float s, float amp, PtRec* rec,
+                              float* alpha_out, float* trans_out, hipStream_t st);
+hipError_t launch_reduce_points_render(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
+                                       uint32_t flags, int n_split, float2* partial, hipStream_t st);
+hipError_t launch_reduce_points_mf(const RenderGeom& g, const AntRec* ant, const QRec* rec,
+                                   uint32_t flags, int n_split, float2* partial, hipStream_t st);
+hipError_t launch_split_sum(const float2* partial, int n_split, long n_out, int accumulate,
+                            float2* out, hipStream_t st);
+hipError_t launch_pad_signal(const float2* sig, int n_meas, int n_freq, int np, float2* out,
+                             hipStream_t st);
+hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
+                                    const float2* gsig_pad, int np, uint32_t flags, float* g_b,
+                                    float* g_T, float* g_n, hipStream_t st);
+hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const float* sdf,
+                               const float* grad, const float* refl, float s, float amp,
+                               const float* alpha, const float* trans, const float* g_b,
+                               const float* g_T, const float* g_n, float* g_alpha_tmp,
+                               float* part_amp, float* part_s, float* g_sdf, float* g_grad,
+                               float* g_refl, int accumulate, hipStream_t st);
+hipError_t launch_sum_scalars(const float* part, int n, float* out, int accumulate,
+                              hipStream_t st);
+
+// Launchers (mf.hip)
+hipError_t launch_mf_forward(const RenderGeom& g, const AntRec* ant, const float* xyz_q, long n_q,
+                             const float2* sig_pad, const float2* sig2_pad, int np, uint32_t flags,
+                             float2* z, float* power, float2* z2, float* power2, hipStream_t st);
+hipError_t launch_mf_bwd_records(const float* xyz_q, long n_q, const float2* z, const float* power,
+                                 const float* g_power, QRec* rec, hipStream_t st);
+
+// Launchers (misc.hip)
+hipError_t launch_loss_partial(long n, const float* p, const float* ps, const float* mask,
+                               float* g_p, double* part, int n_blocks, hipStream_t st);
+hipError_t launch_loss_final(const double* part, int n_blocks, long n, float* loss, hipStream_t st);
+hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
+                                float* u, float* origin, hipStream_t st);
+hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                        float b2, float eps, float wd, float bc1, float bc2, hipStream_t st);
+
+}  // namespace rfvr

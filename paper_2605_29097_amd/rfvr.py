@@ -1,0 +1,361 @@
+"""Thin Python binding of librfvr (include/rfvr.h).
+
+Argument marshalling only: every step runs in the HIP library.  Tensors are
+torch CUDA tensors (device memory on the MI355X); the stream is torch's
+current stream unless one is given.  Workspaces are allocated with torch's
+caching allocator at the size the library's query returns.  If the shared
+library is missing or fails to load, every call raises -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfvr.so")
+
+SPEC_CLAMP, SPEC_RAW, SPEC_OFF = 0x0, 0x1, 0x2
+PHASE_FP64RR, PHASE_NAIVE32 = 0x0, 0x4
+ACCUMULATE = 0x8
+SAMPLE_GRID, SAMPLE_STRATIFIED = 0, 1
+PREC_FP32, PREC_BF16 = 0, 1
+ERRORS = {-1: "RFVR_E_INVALID", -2: "RFVR_E_WORKSPACE", -3: "RFVR_E_UNSUPPORTED", -4: "RFVR_E_HIP"}
+
+_c_i32, _c_i64, _c_u32, _c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+_c_f, _c_d, _vp, _sz = ctypes.c_float, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class CAperture(ctypes.Structure):
+    _fields_ = [("n_meas", _c_i32), ("tx", _vp), ("rx", _vp), ("f0_hz", _c_d), ("df_hz", _c_d),
+                ("n_freq", _c_i32)]
+
+
+class CSamples(ctypes.Structure):
+    _fields_ = [("n_ray", _c_i32), ("n_z", _c_i32), ("xyz", _vp), ("ray_weight", _vp)]
+
+
+class CFields(ctypes.Structure):
+    _fields_ = [("sdf", _vp), ("grad", _vp), ("refl", _vp), ("phi_ray", _vp), ("phi_tx", _vp),
+                ("phi_rx", _vp), ("s", _c_f), ("amp_tx", _c_f)]
+
+
+class CSampleDesc(ctypes.Structure):
+    _fields_ = [("centre", _c_f * 3), ("half_extent", _c_f), ("primary_dir", _c_f * 3),
+                ("n_ray_x", _c_i32), ("n_ray_y", _c_i32), ("n_z", _c_i32), ("mode", _c_i32),
+                ("seed", _c_u64), ("step", _c_u64)]
+
+
+class CMlp(ctypes.Structure):
+    _fields_ = [("n_layers", _c_i32), ("width", _c_i32), ("pe_octaves", _c_i32),
+                ("head_width", _c_i32), ("head_layers", _c_i32), ("softplus_beta", _c_f),
+                ("centre", _c_f * 3), ("half_size", _c_f), ("precision", _c_i32),
+                ("params", _vp)]
+
+
+_P = ctypes.POINTER
+_SIGS = {
+    "rfvr_version": ([], _c_i32),
+    "rfvr_last_error": ([], ctypes.c_char_p),
+    "rfvr_render_forward_ws_bytes": ([_P(CAperture), _P(CSamples)], _sz),
+    "rfvr_render_forward": ([_P(CAperture), _P(CSamples), _P(CFields), _c_u32, _vp, _vp, _vp, _vp,
+                             _sz, _vp], _c_i32),
+    "rfvr_render_backward_ws_bytes": ([_P(CAperture), _P(CSamples)], _sz),
+    "rfvr_render_backward": ([_P(CAperture), _P(CSamples), _P(CFields), _c_u32, _vp, _vp, _vp, _vp,
+                              _vp, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_mf_forward_ws_bytes": ([_P(CAperture), _c_i64, _c_i32], _sz),
+    "rfvr_mf_forward": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                        _c_i32),
+    "rfvr_mf_backward_ws_bytes": ([_P(CAperture), _c_i64], _sz),
+    "rfvr_mf_backward": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
+                         _c_i32),
+    "rfvr_loss_ws_bytes": ([_c_i64], _sz),
+    "rfvr_loss_l2": ([_c_i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_sample_points": ([_P(CSampleDesc), _vp, _vp, _vp, _vp], _c_i32),
+    "rfvr_mlp_param_count": ([_P(CMlp)], _c_i64),
+    "rfvr_mlp_forward_ws_bytes": ([_P(CMlp), _c_i64], _sz),
+    "rfvr_mlp_forward": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_mlp_backward_ws_bytes": ([_P(CMlp), _c_i64], _sz),
+    "rfvr_mlp_backward": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
+                          _c_i32),
+    "rfvr_adamw": ([_c_i64, _vp, _vp, _vp, _vp, _c_i64, _c_f, _c_f, _c_f, _c_f, _c_f, _vp], _c_i32),
+}
+
+_lib = None
+
+
+class RfvrError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded librfvr (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RfvrError(f"librfvr.so not found at {LIB_PATH}; build it with "
+                            "`python -m paper_2605_29097_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().rfvr_last_error().decode()
+        raise RfvrError(f"{what} failed: {ERRORS.get(rc, rc)}: {msg}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to librfvr must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _f32(t, device=None):
+    if t is None:
+        return None
+    t = torch.as_tensor(t)
+    if device is not None:
+        t = t.to(device)
+    return t.to(torch.float32).contiguous()
+
+
+# ----------------------------------------------------------------------------
+# descriptors
+# ----------------------------------------------------------------------------
+@dataclass
+class Aperture:
+    tx: torch.Tensor          # [n_meas, 3] float32 on the device
+    f0: float
+    df: float
+    n_freq: int
+
+    def c(self) -> CAperture:
+        return CAperture(self.tx.shape[0], _ptr(self.tx), None, float(self.f0), float(self.df),
+                         int(self.n_freq))
+
+    @property
+    def n_meas(self) -> int:
+        return int(self.tx.shape[0])
+
+
+@dataclass
+class Samples:
+    xyz: torch.Tensor                      # [n_ray, n_z, 3]
+    ray_weight: Optional[torch.Tensor] = None
+
+    def c(self) -> CSamples:
+        return CSamples(self.xyz.shape[0], self.xyz.shape[1], _ptr(self.xyz), _ptr(self.ray_weight))
+
+
+@dataclass
+class Fields:
+    sdf: torch.Tensor
+    grad: torch.Tensor
+    refl: torch.Tensor
+    s: float = 64.0
+    amp: float = 1.0
+    phi_ray: Optional[torch.Tensor] = None
+    phi_tx: Optional[torch.Tensor] = None
+
+    def c(self) -> CFields:
+        return CFields(_ptr(self.sdf), _ptr(self.grad), _ptr(self.refl), _ptr(self.phi_ray),
+                       _ptr(self.phi_tx), None, float(self.s), float(self.amp))
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI, without the prefix)
+# ----------------------------------------------------------------------------
+def render_forward(ap: Aperture, sm: Samples, fl: Fields, flags: int = 0, want_alpha=False,
+                   stream=None):
+    """signal [n_meas, n_freq, 2] float32 (and alpha, trans [n_ray, n_z] if asked)."""
+    dev = sm.xyz.device
+    cap, csm, cfl = ap.c(), sm.c(), fl.c()
+    sig = torch.empty(ap.n_meas, ap.n_freq, 2, dtype=torch.float32, device=dev)
+    alpha = trans = None
+    if want_alpha:
+        alpha = torch.empty(sm.xyz.shape[:2], dtype=torch.float32, device=dev)
+        trans = torch.empty_like(alpha)
+    nb = lib().rfvr_render_forward_ws_bytes(ctypes.byref(cap), ctypes.byref(csm))
+    ws = _ws(nb, dev)
+    _check(lib().rfvr_render_forward(ctypes.byref(cap), ctypes.byref(csm), ctypes.byref(cfl), flags,
+                                     _ptr(sig), _ptr(alpha), _ptr(trans), _ptr(ws), ws.numel(),
+                                     _stream(stream)), "rfvr_render_forward")
+    return (sig, alpha, trans) if want_alpha else sig
+
+
+def render_backward(ap: Aperture, sm: Samples, fl: Fields, g_signal: torch.Tensor, flags: int = 0,
+                    stream=None):
+    """dict(sdf, grad, refl, amp, s) of gradients."""
+    dev = sm.xyz.device
+    cap, csm, cfl = ap.c(), sm.c(), fl.c()
+    shp = tuple(sm.xyz.shape[:2])
+    out = dict(sdf=torch.empty(shp, dtype=torch.float32, device=dev),
+               grad=torch.empty(shp + (3,), dtype=torch.float32, device=dev),
+               refl=torch.empty(shp, dtype=torch.float32, device=dev),
+               amp=torch.empty(1, dtype=torch.float32, device=dev),
+               s=torch.empty(1, dtype=torch.float32, device=dev))
+    nb = lib().rfvr_render_backward_ws_bytes(ctypes.byref(cap), ctypes.byref(csm))
+    ws = _ws(nb, dev)
+    _check(lib().rfvr_render_backward(ctypes.byref(cap), ctypes.byref(csm), ctypes.byref(cfl), flags,
+                                      _ptr(g_signal.contiguous()), _ptr(out["sdf"]), _ptr(out["grad"]),
+                                      _ptr(out["refl"]), _ptr(out["amp"]), _ptr(out["s"]), _ptr(ws),
+                                      ws.numel(), _stream(stream)), "rfvr_render_backward")
+    return out
+
+
+def mf_forward(ap: Aperture, xyz_q: torch.Tensor, signal: torch.Tensor, signal2=None,
+               flags: int = 0, stream=None):
+    """(z [Q,2], power [Q]) or, with signal2, (z, power, z2, power2)."""
+    dev = xyz_q.device
+    cap = ap.c()
+    nq = xyz_q.numel() // 3
+    z = torch.empty(nq, 2, dtype=torch.float32, device=dev)
+    p = torch.empty(nq, dtype=torch.float32, device=dev)
+    z2 = p2 = None
+    if signal2 is not None:
+        z2 = torch.empty_like(z)
+        p2 = torch.empty_like(p)
+    nb = lib().rfvr_mf_forward_ws_bytes(ctypes.byref(cap), nq, 1 if signal2 is not None else 0)
+    ws = _ws(nb, dev)
+    _check(lib().rfvr_mf_forward(ctypes.byref(cap), _ptr(xyz_q.contiguous()), nq,
+                                 _ptr(signal.contiguous()), _ptr(z), _ptr(p),
+                                 _ptr(signal2.contiguous() if signal2 is not None else None),
+                                 _ptr(z2), _ptr(p2), _ptr(ws), ws.numel(), _stream(stream)),
+           "rfvr_mf_forward")
+    return (z, p) if signal2 is None else (z, p, z2, p2)
+
+
+def mf_backward(ap: Aperture, xyz_q: torch.Tensor, z: torch.Tensor, power: torch.Tensor,
+                g_power: torch.Tensor, flags: int = 0, out=None, stream=None):
+    """dL/dsignal [n_meas, n_freq, 2]."""
+    dev = xyz_q.device
+    cap = ap.c()
+    nq = xyz_q.numel() // 3
+    g = out if out is not None else torch.empty(ap.n_meas, ap.n_freq, 2, dtype=torch.float32,
+                                                device=dev)
+    nb = lib().rfvr_mf_backward_ws_bytes(ctypes.byref(cap), nq)
+    ws = _ws(nb, dev)
+    _check(lib().rfvr_mf_backward(ctypes.byref(cap), _ptr(xyz_q.contiguous()), nq, _ptr(z.contiguous()),
+                                  _ptr(power.contiguous()), _ptr(g_power.contiguous()), flags, _ptr(g),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mf_backward")
+    return g
+
+
+def loss_l2(p: torch.Tensor, p_star: torch.Tensor, mask=None, want_grad=True, stream=None):
+    n = p.numel()
+    dev = p.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g = torch.empty_like(p) if want_grad else None
+    ws = _ws(lib().rfvr_loss_ws_bytes(n), dev)
+    _check(lib().rfvr_loss_l2(n, _ptr(p.contiguous()), _ptr(p_star.contiguous()), _ptr(mask), _ptr(loss),
+                              _ptr(g), _ptr(ws), ws.numel(), _stream(stream)), "rfvr_loss_l2")
+    return loss, g
+
+
+def sample_points(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode=SAMPLE_GRID,
+                  seed=0, step=0, device="cuda", stream=None):
+    """(xyz [n_ray, n_z, 3], u [n_ray, n_z], ray_origin [n_ray, 3])."""
+    d = CSampleDesc((_c_f * 3)(*[float(c) for c in centre]), float(half_extent),
+                    (_c_f * 3)(*[float(c) for c in primary_dir]), int(n_ray_x), int(n_ray_y),
+                    int(n_z), int(mode), int(seed) & (2 ** 64 - 1), int(step) & (2 ** 64 - 1))
+    n_ray = n_ray_x * n_ray_y
+    xyz = torch.empty(n_ray, n_z, 3, dtype=torch.float32, device=device)
+    u = torch.empty(n_ray, n_z, dtype=torch.float32, device=device)
+    o = torch.empty(n_ray, 3, dtype=torch.float32, device=device)
+    _check(lib().rfvr_sample_points(ctypes.byref(d), _ptr(xyz), _ptr(u), _ptr(o), _stream(stream)),
+           "rfvr_sample_points")
+    return xyz, u, o
+
+
+@dataclass
+class MLP:
+    params: torch.Tensor
+    n_layers: int = 8
+    width: int = 256
+    pe_octaves: int = 6
+    head_width: int = 64
+    head_layers: int = 2
+    beta: float = 100.0
+    centre: tuple = (0.0, 0.0, 0.30)
+    half_size: float = 0.10
+    precision: int = PREC_FP32
+
+    def c(self, params: Optional[torch.Tensor] = None) -> CMlp:
+        p = self.params if params is None else params
+        return CMlp(self.n_layers, self.width, self.pe_octaves, self.head_width, self.head_layers,
+                    float(self.beta), (_c_f * 3)(*[float(c) for c in self.centre]),
+                    float(self.half_size), int(self.precision), _ptr(p))
+
+    def param_count(self) -> int:
+        return int(lib().rfvr_mlp_param_count(ctypes.byref(self.c())))
+
+
+def mlp_forward(net: MLP, xyz: torch.Tensor, stream=None):
+    """(f [N], grad [N, 3], a [N])."""
+    dev = xyz.device
+    n = xyz.numel() // 3
+    cn = net.c()
+    f = torch.empty(n, dtype=torch.float32, device=dev)
+    g = torch.empty(n, 3, dtype=torch.float32, device=dev)
+    a = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_mlp_forward_ws_bytes(ctypes.byref(cn), n), dev)
+    _check(lib().rfvr_mlp_forward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(f), _ptr(g), _ptr(a),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mlp_forward")
+    return f, g, a
+
+
+def mlp_backward(net: MLP, xyz: torch.Tensor, g_sdf=None, g_grad=None, g_refl=None, flags=0,
+                 out=None, stream=None):
+    dev = xyz.device
+    n = xyz.numel() // 3
+    cn = net.c()
+    gp = out if out is not None else torch.empty(net.param_count(), dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_mlp_backward_ws_bytes(ctypes.byref(cn), n), dev)
+    _check(lib().rfvr_mlp_backward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(g_sdf), _ptr(g_grad),
+                                   _ptr(g_refl), flags, _ptr(gp), _ptr(ws), ws.numel(),
+                                   _stream(stream)), "rfvr_mlp_backward")
+    return gp
+
+
+def adamw(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, stream=None):
+    _check(lib().rfvr_adamw(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(t), float(lr),
+                            float(b1), float(b2), float(eps), float(wd), _stream(stream)),
+           "rfvr_adamw")
+
+
+# C-ABI names
+rfvr_render_forward = render_forward
+rfvr_render_backward = render_backward
+rfvr_mf_forward = mf_forward
+rfvr_mf_backward = mf_backward
+rfvr_loss_l2 = loss_l2
+rfvr_sample_points = sample_points
+rfvr_mlp_forward = mlp_forward
+rfvr_mlp_backward = mlp_backward
+rfvr_adamw = adamw
