@@ -3,9 +3,11 @@
 // Forward: one lane per query point; all lanes of a wave walk the same
 // measurements, so the measurement record and the signal row are scalar loads.
 // For a measurement, sum_n s[n] exp(+j 2 pi (theta0 + n delta)) =
-// exp(+j 2 pi theta0) * P(w) with P the polynomial of the signal row in
-// w = exp(+j 2 pi delta), evaluated by Horner's rule: 4 FMA per term once the
-// pair's phase origin (FP64 range reduction) and step are set up.  A second
+// exp(+j 2 pi theta_mid) * sum_n s[n] w^(n - mid), a Laurent polynomial of the
+// signal row in w = exp(+j 2 pi delta) around the middle frequency, evaluated
+// by Horner's rule in w (upper half) and conj(w) (lower half): 4 FMA per term
+// once the pair's range (FP64), centre phase (FP64 reduction) and accurately
+// rounded step phasor are set up.  A second
 // signal (e.g. the measured one) can be filtered at the same points sharing the
 // set-up.  The adjoint reduces over points (render.hip, KIND 1).
 #include "rfvr_impl.hpp"
@@ -22,33 +24,23 @@ __global__ __launch_bounds__(256) void k_mf_forward(
     const bool ok = q < n_q;
     const long qq = ok ? q : n_q - 1;
     const double px = (double)xq[3 * qq], py = (double)xq[3 * qq + 1], pz = (double)xq[3 * qq + 2];
+    const int mid = np / 2;                        // multiple of 16
+    const double Km = K0 + (double)mid * Kd;
     float zr = 0.0f, zi = 0.0f, z2r = 0.0f, z2i = 0.0f;
     for (int i = 0; i < n_meas; ++i) {
         const AntRec A = ant[i];
-        const double dx = px - A.x, dy = py - A.y, dz = pz - A.z;
-        float c0, s0, cw, sw;
-        if constexpr (!NAIVE) {
-            float y;
-            const double r = range_f64(dx, dy, dz, y);
-            const float t0 = frac_rev(r * K0);
-            const float de = (float)(r * Kd);
-            c0 = cos_rev(t0);
-            s0 = sin_rev(t0);
-            cw = cos_rev(de);
-            sw = sin_rev(de);
-        } else {
-            const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-            const float r = sqrtf(fx * fx + fy * fy + fz * fz);
-            const float two_pi = 6.2831853071795864769f;
-            sincosf((float)(two_pi * K0) * r, &s0, &c0);
-            sincosf((float)(two_pi * Kd) * r, &sw, &cw);
-        }
+        const PairGeom geo = pair_geom<NAIVE>(px - A.x, py - A.y, pz - A.z);
+        float cw, sw;
+        step_phasor<NAIVE>(geo, Kd, cw, sw);       // w = exp(+j 2 pi delta)
         const float2* row = sig + (size_t)i * np;
         const float2* row2 = TWO ? sig2 + (size_t)i * np : nullptr;
-        float hr = 0.0f, hi = 0.0f, h2r = 0.0f, h2i = 0.0f;
-        for (int n0 = np - 32; n0 >= 0; n0 -= 32) {
+        // H = sum_n s[n] w^(n - mid): upper half by Horner in w from the top,
+        // lower half by Horner in conj(w) from the bottom
+        float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
+        float h2r = 0.0f, h2i = 0.0f, l2r = 0.0f, l2i = 0.0f;
+        for (int n0 = np - 16; n0 >= mid; n0 -= 16) {
 #pragma unroll
-            for (int u = 31; u >= 0; --u) {
+            for (int u = 15; u >= 0; --u) {
                 const float2 sv = row[n0 + u];
                 const float tr = __builtin_fmaf(-hi, sw, __builtin_fmaf(hr, cw, sv.x));
                 hi = __builtin_fmaf(hi, cw, __builtin_fmaf(hr, sw, sv.y));
@@ -61,10 +53,30 @@ __global__ __launch_bounds__(256) void k_mf_forward(
                 }
             }
         }
-        // z += exp(+j 2 pi theta0) * H
+        for (int n0 = 0; n0 < mid; n0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const float2 sv = row[n0 + u];
+                const float tr = __builtin_fmaf(li, sw, __builtin_fmaf(lr, cw, sv.x));
+                li = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, sv.y));
+                lr = tr;
+                if constexpr (TWO) {
+                    const float2 sv2 = row2[n0 + u];
+                    const float t2 = __builtin_fmaf(l2i, sw, __builtin_fmaf(l2r, cw, sv2.x));
+                    l2i = __builtin_fmaf(l2i, cw, __builtin_fmaf(-l2r, sw, sv2.y));
+                    l2r = t2;
+                }
+            }
+        }
+        hr = __builtin_fmaf(lr, cw, __builtin_fmaf(li, sw, hr));
+        hi = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, hi));
+        float c0, s0;
+        seed_phasor<NAIVE>(geo, Km, c0, s0);      // exp(+j 2 pi theta_mid)
         zr = __builtin_fmaf(c0, hr, __builtin_fmaf(-s0, hi, zr));
         zi = __builtin_fmaf(c0, hi, __builtin_fmaf(s0, hr, zi));
         if constexpr (TWO) {
+            h2r = __builtin_fmaf(l2r, cw, __builtin_fmaf(l2i, sw, h2r));
+            h2i = __builtin_fmaf(l2i, cw, __builtin_fmaf(-l2r, sw, h2i));
             z2r = __builtin_fmaf(c0, h2r, __builtin_fmaf(-s0, h2i, z2r));
             z2i = __builtin_fmaf(c0, h2i, __builtin_fmaf(s0, h2r, z2i));
         }

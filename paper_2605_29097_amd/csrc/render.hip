@@ -6,15 +6,17 @@
 //  * forward: a lane owns one (measurement, frequency chunk) pair and keeps the
 //    chunk's complex accumulators in VGPRs; all lanes of a wave walk the same
 //    points, so point records arrive through scalar loads (SGPR operands, no
-//    LDS traffic).  Per (measurement, point) the path length and the phase
-//    origin are set up once (FP64 range reduction + hardware sin/cos in
-//    revolutions); the chunk's frequencies then follow by complex rotation,
-//    since f_n is linear in n.  Points are split across work-groups and the
-//    partial sums reduced in a fixed order (no atomics).
+//    LDS traffic).  Per (measurement, point) the path length (FP64) and the
+//    step phasor (accurately rounded) are set up once; every 16 frequencies a
+//    phasor is re-seeded from an FP64-reduced phase at the sub-chunk centre
+//    and the sub-chunk is walked by complex rotation both ways (f_n is linear
+//    in n).  Points are split across work-groups and the partial sums reduced
+//    in a fixed order (no atomics).
 //  * backward: a lane owns one point; all lanes walk the same measurements, so
 //    measurement records and the incoming signal gradient row are scalar loads.
-//    sum_n g[n] exp(+j 2 pi (theta0 + n delta)) is a polynomial in
-//    w = exp(j 2 pi delta), evaluated by Horner's rule (4 FMA per term).
+//    sum_n g[n] exp(+j 2 pi (theta0 + n delta)) is, around the middle
+//    frequency, a Laurent polynomial in w = exp(j 2 pi delta), evaluated by
+//    Horner's rule in w and conj(w) (4 FMA per term).
 #include "rfvr_impl.hpp"
 
 namespace rfvr {
@@ -30,37 +32,6 @@ int choose_point_splits(long n_pts, int lanes_total) {
     if (ns < 1) ns = 1;
     if (ns > 65535) ns = 65535;
     return (int)ns;
-}
-
-// ---------------------------------------------------------------------------
-// pair phase set-up
-// ---------------------------------------------------------------------------
-// Start phase of the chunk (revolutions Kstart * |d|) and per-frequency step
-// (Kd * |d|); returns cos/sin of 2 pi times each, and y ~ 1/|d|.
-template <bool NAIVE>
-__device__ __forceinline__ void pair_phase(double dx, double dy, double dz, double Kstart,
-                                           double Kd, float& y, float& c0, float& s0, float& cw,
-                                           float& sw) {
-    if constexpr (!NAIVE) {
-        double r = range_f64(dx, dy, dz, y);
-        float t0 = frac_rev(r * Kstart);
-        float de = (float)(r * Kd);
-        c0 = cos_rev(t0);
-        s0 = sin_rev(t0);
-        cw = cos_rev(de);
-        sw = sin_rev(de);
-    } else {
-        // FP32 path length and FP32 radians, as a plain FP32 implementation
-        // would form 2 pi f d / c; the library sin/cos then reduce exactly.
-        float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-        float r = sqrtf(fx * fx + fy * fy + fz * fz);
-        y = 1.0f / r;
-        const float two_pi = 6.2831853071795864769f;
-        float ph0 = (float)(two_pi * Kstart) * r;
-        float phd = (float)(two_pi * Kd) * r;
-        sincosf(ph0, &s0, &c0);
-        sincosf(phd, &sw, &cw);
-    }
 }
 
 template <int SPEC>
@@ -177,13 +148,17 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
     const void* __restrict__ recs_v, long n_pts, long pts_per_split,
     float2* __restrict__ partial) {
+    constexpr int S = F < 16 ? F : 16;           // re-seed interval
+    constexpr int NS = F / S;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int i = t % n_meas;
     int c = t / n_meas;
     const bool live_lane = c < n_chunks;
     if (!live_lane) c = n_chunks - 1;
     const AntRec A = ant[i];
-    const double Kc = K0 + (double)(c * F) * Kd;
+    double Kc[NS];                                // phase rate at each sub-chunk centre
+#pragma unroll
+    for (int m = 0; m < NS; ++m) Kc[m] = K0 + (double)(c * F + m * S + S / 2) * Kd;
 
     float ar[F], ai[F];
 #pragma unroll
@@ -196,37 +171,61 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     if (j1 > n_pts) j1 = n_pts;
 
     for (long j = j0; j < j1; ++j) {
-        float pr, pi, y, c0, s0, cw, sw;
+        float wr, wi, cr, ci;          // step phasor, complex weight of the pair
+        PairGeom g;
         if constexpr (KIND == 0) {
             const PtRec P = reinterpret_cast<const PtRec*>(recs_v)[j];
             const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
-            pair_phase<NAIVE>(dx, dy, dz, Kc, Kd, y, c0, s0, cw, sw);
+            g = pair_geom<NAIVE>(dx, dy, dz);
             float spec, live;
             if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
                 spec = 1.0f;
             } else {
-                float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * y;
+                float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * g.y;
                 spec_factor<SPEC>(nd, spec, live);
             }
-            float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
-            float cm = P.b * spec * (T * T) * (y * y);
-            pr = cm * c0;
-            pi = -cm * s0;                       // c exp(-j 2 pi theta)
+            const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
+            cr = P.b * spec * (T * T) * (g.y * g.y);
+            ci = 0.0f;
         } else {
             const QRec Q = reinterpret_cast<const QRec*>(recs_v)[j];
             const double dx = Q.x - A.x, dy = Q.y - A.y, dz = Q.z - A.z;
-            pair_phase<NAIVE>(dx, dy, dz, Kc, Kd, y, c0, s0, cw, sw);
-            pr = Q.hr * c0 + Q.hi * s0;          // h exp(-j 2 pi theta)
-            pi = Q.hi * c0 - Q.hr * s0;
+            g = pair_geom<NAIVE>(dx, dy, dz);
+            cr = Q.hr;
+            ci = Q.hi;
         }
-        const float wr = cw, wi = -sw;           // step exp(-j 2 pi delta)
+        {
+            float cw, sw;
+            step_phasor<NAIVE>(g, Kd, cw, sw);
+            wr = cw;
+            wi = -sw;                  // exp(-j 2 pi delta)
+        }
 #pragma unroll
-        for (int n = 0; n < F; ++n) {
-            ar[n] += pr;
-            ai[n] += pi;
-            const float tr = pr * wr - pi * wi;
-            pi = __builtin_fmaf(pr, wi, pi * wr);
-            pr = tr;
+        for (int m = 0; m < NS; ++m) {
+            float c0, s0;
+            seed_phasor<NAIVE>(g, Kc[m], c0, s0);
+            // (cr + j ci) * exp(-j 2 pi theta_centre)
+            const float pr0 = __builtin_fmaf(cr, c0, ci * s0);
+            const float pi0 = __builtin_fmaf(ci, c0, -cr * s0);
+            float pr = pr0, pi = pi0;
+#pragma unroll
+            for (int u = S / 2; u < S; ++u) {
+                ar[m * S + u] += pr;
+                ai[m * S + u] += pi;
+                const float tr = __builtin_fmaf(pr, wr, -pi * wi);
+                pi = __builtin_fmaf(pr, wi, pi * wr);
+                pr = tr;
+            }
+            pr = pr0;
+            pi = pi0;
+#pragma unroll
+            for (int u = S / 2 - 1; u >= 0; --u) {
+                const float tr = __builtin_fmaf(pr, wr, pi * wi);     // times conj(w)
+                pi = __builtin_fmaf(pi, wr, -pr * wi);
+                pr = tr;
+                ar[m * S + u] += pr;
+                ai[m * S + u] += pi;
+            }
         }
     }
     if (live_lane) {
@@ -339,25 +338,44 @@ __global__ __launch_bounds__(256) void k_render_bwd_points(
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = j < n_pts;
     const PtRec P = rec[ok ? j : n_pts - 1];
+    const int mid = np / 2;                        // multiple of 16
+    const double Km = K0 + (double)mid * Kd;
     float gb = 0.0f, gt = 0.0f, gn0 = 0.0f, gn1 = 0.0f, gn2 = 0.0f;
     for (int i = 0; i < n_meas; ++i) {
         const AntRec A = ant[i];
         const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
-        float y, c0, s0, cw, sw;
-        pair_phase<NAIVE>(dx, dy, dz, K0, Kd, y, c0, s0, cw, sw);
-        // H = sum_n g[n] w^n with w = exp(+j 2 pi delta), highest n first
+        const PairGeom geo = pair_geom<NAIVE>(dx, dy, dz);
+        float cw, sw;
+        step_phasor<NAIVE>(geo, Kd, cw, sw);       // w = exp(+j 2 pi delta)
         const float2* g = gsig + (size_t)i * np;
-        float hr = 0.0f, hi = 0.0f;
-        for (int n0 = np - 32; n0 >= 0; n0 -= 32) {
+        // H = sum_n g[n] w^(n - mid): upper half by Horner in w from the top,
+        // lower half by Horner in conj(w) from the bottom
+        float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
+        for (int n0 = np - 16; n0 >= mid; n0 -= 16) {
 #pragma unroll
-            for (int u = 31; u >= 0; --u) {
+            for (int u = 15; u >= 0; --u) {
                 const float2 gv = g[n0 + u];
                 const float tr = __builtin_fmaf(-hi, sw, __builtin_fmaf(hr, cw, gv.x));
                 hi = __builtin_fmaf(hi, cw, __builtin_fmaf(hr, sw, gv.y));
                 hr = tr;
             }
         }
-        const float G = c0 * hr - s0 * hi;       // Re(exp(+j 2 pi theta0) H)
+        for (int n0 = 0; n0 < mid; n0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const float2 gv = g[n0 + u];
+                const float tr = __builtin_fmaf(li, sw, __builtin_fmaf(lr, cw, gv.x));
+                li = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, gv.y));
+                lr = tr;
+            }
+        }
+        // H = Hup + conj(w) * Hlow
+        hr = __builtin_fmaf(lr, cw, __builtin_fmaf(li, sw, hr));
+        hi = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, hi));
+        float c0, s0;
+        seed_phasor<NAIVE>(geo, Km, c0, s0);
+        const float G = c0 * hr - s0 * hi;       // Re(exp(+j 2 pi theta_mid) H)
+        const float y = geo.y;
         const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
         float spec, live = 0.0f;
         float nd = 0.0f;

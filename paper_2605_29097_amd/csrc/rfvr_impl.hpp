@@ -88,6 +88,62 @@ __device__ __forceinline__ float alpha_pair(float a, float b) {
     return fminf(al, 1.0f);
 }
 
+// ---------------------------------------------------------------------------
+// pair phase set-up
+// ---------------------------------------------------------------------------
+// A pair's frequencies are visited by complex rotation with the step phasor
+// w = exp(-+ j 2 pi delta).  Rounding of w grows linearly along a walk and the
+// rendered signal is a heavily cancelling sum (Fresnel zones), so:
+//  * w comes from an accurately rounded sin/cos (sincospif);
+//  * walks are short: every S frequencies the phasor is re-seeded from an
+//    FP64-reduced phase at the centre of the sub-chunk and walked S/2 steps
+//    up and S/2 steps down.
+// Re-seed phasors use the hardware sin/cos (errors do not accumulate).
+struct PairGeom {
+    double r;   // |x - tx| (FP64)
+    float y;    // ~1/r
+    float rf;   // r in FP32 (NAIVE mode)
+};
+
+template <bool NAIVE>
+__device__ __forceinline__ PairGeom pair_geom(double dx, double dy, double dz) {
+    PairGeom g;
+    if constexpr (!NAIVE) {
+        g.r = range_f64(dx, dy, dz, g.y);
+        g.rf = 0.0f;
+    } else {
+        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        g.rf = sqrtf(fx * fx + fy * fy + fz * fz);
+        g.y = 1.0f / g.rf;
+        g.r = 0.0;
+    }
+    return g;
+}
+
+// cos/sin of 2 pi * (K * r): FP64 product and reduction, hardware sin/cos;
+// NAIVE: FP32 radians (2 pi K) * r and library sin/cos.
+template <bool NAIVE>
+__device__ __forceinline__ void seed_phasor(const PairGeom& g, double K, float& c, float& s) {
+    if constexpr (!NAIVE) {
+        const float t = frac_rev(g.r * K);
+        c = cos_rev(t);
+        s = sin_rev(t);
+    } else {
+        sincosf((float)(6.283185307179586 * K) * g.rf, &s, &c);
+    }
+}
+
+// accurate step phasor cos/sin of 2 pi * (Kd * r)
+template <bool NAIVE>
+__device__ __forceinline__ void step_phasor(const PairGeom& g, double Kd, float& c, float& s) {
+    if constexpr (!NAIVE) {
+        const float de = (float)(g.r * Kd);
+        sincospif(2.0f * de, &s, &c);
+    } else {
+        sincosf((float)(6.283185307179586 * Kd) * g.rf, &s, &c);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // host-side internals shared between translation units
 // ----------------------------------------------------------------------------

@@ -302,7 +302,10 @@ def test_adamw_matches_oracle(dev):
     t = lambda a: torch.from_numpy(a.copy()).to(dev)
     P, G, M, V = t(p), t(g), t(m), t(v)
     R.adamw(P, G, M, V, 7, 1e-3, wd=0.01)
-    pr, mr, vr = oopt.adamw_step(p, g, m, v, 7, 1e-3, wd=0.01)
-    np.testing.assert_allclose(P.cpu().numpy(), pr, rtol=1e-6, atol=1e-7)
-    np.testing.assert_allclose(M.cpu().numpy(), mr, rtol=1e-6, atol=1e-8)
+    # the kernel receives float32 hyper-parameters; give the oracle the same values
+    f = lambda x: float(np.float32(x))
+    pr, mr, vr = oopt.adamw_step(p, g, m, v, 7, f(1e-3), b1=f(0.9), b2=f(0.999), eps=f(1e-8), wd=f(0.01))
+    # float32 arithmetic on O(0.1..3) operands: a few ulp absolute
+    np.testing.assert_allclose(P.cpu().numpy(), pr, rtol=1e-6, atol=2e-7)
+    np.testing.assert_allclose(M.cpu().numpy(), mr, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(V.cpu().numpy(), vr, rtol=1e-6, atol=1e-9)
