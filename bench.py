@@ -1,0 +1,171 @@
+#!/usr/bin/env python
+"""Benchmark of the lensless RF volumetric rendering hot path on one MI355X.
+
+A step is one full training step of the 2^20-point MLP workload: lensless
+samples, the 8 x 256 FP32 SDF network with its reflectiveness head (and the
+detached origin occupancies), signal tracing with lensless alpha blending,
+the matched filter, the L2 heatmap loss, all adjoints (matched filter,
+signal tracing, transmittance scan, network double backward) and AdamW.
+
+The metric counts render terms: one (point, measurement, frequency) triple
+per pass, four passes per step (signal tracing forward and adjoint, matched
+filter forward and adjoint), 2^20 x 1024 x 128 terms each.
+
+Prints one JSON line (rank 0).  Only --gpus 1 is supported: this build runs on
+one GPU; the multi-GPU sharding is described in the design notes.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_TERM = 8          # one complex multiply-add per term (4 FMA)
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 128 FMA/clk x 2 x 2.4 GHz)
+
+
+def make_inputs(cfg, dev):
+    """Seeded network weights and the measured signal of the box scene."""
+    import numpy as np
+    import torch
+    from synth import MLPSpec, mlp_init
+    spec = MLPSpec(n_layers=cfg.n_layers, width=cfg.width, pe_octaves=cfg.pe_octaves,
+                   head_width=cfg.head_width, head_layers=cfg.head_layers, beta=cfg.beta,
+                   centre=tuple(cfg.cube_centre), half_size=cfg.cube_side / 2)
+    params = torch.from_numpy(mlp_init(spec, cfg.seed)).to(dev)
+    # oracle render of the analytic box + 10 dB noise, written once by
+    # tests/golden/make_box_target.py
+    data = np.load(os.path.join(ROOT, "tests", "golden", "box_target.npz"))
+    noisy = data["noisy"]
+    target = torch.from_numpy(np.stack([noisy.real, noisy.imag], -1).astype(np.float32)).to(dev)
+    return params, target
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle timed on this host on a bounded sample of the workload."""
+    import numpy as np
+    threads = min(16, os.cpu_count() or 1)
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    threads = int(os.environ["OMP_NUM_THREADS"])
+    from oracle import render as orc
+    from synth import Box, freq_grid, line_points, planar_aperture, scene_fields
+    f0, df = freq_grid(cfg.n_freq)
+    tx = planar_aperture(*cfg.ap, cfg.pitch).astype(np.float64)
+    xyz, _ = line_points(cfg.cube_centre, cfg.cube_side, cfg.lines[0], cfg.lines[1], cfg.n_z)
+    sdf, grad, refl = scene_fields(Box(cfg.cube_centre, (0.04, 0.03, 0.02), 0.8), xyz)
+    xyz = xyz.astype(np.float64)
+    F = orc.Fields(sdf=sdf.astype(np.float64), grad=grad.astype(np.float64), refl=refl.astype(np.float64),
+                   s=cfg.s, amp=1.0)
+    n_pts = xyz.shape[0] * xyz.shape[1]
+    rng = np.random.default_rng(0)
+    sel = np.arange(threads)                                   # measurements for point reductions
+    rays = np.arange(0, xyz.shape[0], xyz.shape[0] // 8)[:8]   # rays for frequency reductions
+    q = xyz[rays].reshape(-1, 3)
+    ap_sel = orc.Aperture(tx=tx[sel], f0=f0, df=df, n_freq=cfg.n_freq)
+    ap_all = orc.Aperture(tx=tx, f0=f0, df=df, n_freq=cfg.n_freq)
+    gs = rng.normal(size=(tx.shape[0], cfg.n_freq)) + 1j * rng.normal(size=(tx.shape[0], cfg.n_freq))
+    terms = 0
+    t0 = time.perf_counter()
+    s = orc.render(ap_sel, xyz, F)                                        # forward, all points
+    terms += n_pts * len(sel) * cfg.n_freq
+    z, P = orc.mf(ap_all, q, gs)                                          # MF, 8 rays
+    terms += q.shape[0] * tx.shape[0] * cfg.n_freq
+    zz = rng.normal(size=n_pts) + 1j * rng.normal(size=n_pts)
+    orc.mf_adjoint(ap_sel, xyz.reshape(-1, 3), zz, np.abs(zz), rng.normal(size=n_pts))
+    terms += n_pts * len(sel) * cfg.n_freq                                # MF adjoint, all points
+    Fr = orc.Fields(sdf=F.sdf[rays], grad=F.grad[rays], refl=F.refl[rays], s=cfg.s, amp=1.0)
+    orc.render_adjoint(ap_all, xyz[rays], Fr, gs)                         # adjoint, 8 rays
+    terms += q.shape[0] * tx.shape[0] * cfg.n_freq
+    dt = time.perf_counter() - t0
+    sample = (f"FP64 oracle (C + OpenMP, one sin/cos per term): signal tracing and matched-filter "
+              f"adjoint over all {n_pts} points for {len(sel)} measurements, matched filter and "
+              f"signal-tracing adjoint over 8 whole rays ({q.shape[0]} points) for all "
+              f"{tx.shape[0]} measurements; {terms:.3e} terms in {dt:.1f} s")
+    return dict(value=terms / dt, unit="terms/s", cores=threads, kind="oracle", sample=sample)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
+              "(the multi-GPU sharding by points is a design, not a measured path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from paper_2605_29097_amd.train import StepConfig, Trainer
+    R.lib()
+    dev = torch.device("cuda:0")
+    cfg = StepConfig()
+    params, target = make_inputs(cfg, dev)
+    tr = Trainer(cfg, params, target, device=dev)
+    for _ in range(args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    timers = {}
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        tr.step(timers)
+        print(f"[bench] step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+
+    order = ["start", "sample", "mlp_fwd", "render_fwd", "mf_fwd", "mf_bwd", "render_bwd", "mlp_bwd",
+             "adamw"]
+    phases = {}
+    for a, b in zip(order[:-1], order[1:]):
+        phases[b] = sum(ea.elapsed_time(eb) for ea, eb in zip(timers[a], timers[b])) / args.steps
+    if args.phases:
+        print(json.dumps({"phases_ms": phases}), file=sys.stderr)
+
+    tpp = cfg.terms_per_pass()
+    terms_step = 4 * tpp
+    value = terms_step / (ms_step * 1e-3)
+    # dominant term kernel: the signal-tracing forward, timed by HIP events on
+    # the stream it is launched on (its phase also holds two ~10 us helpers)
+    t_rf = phases["render_fwd"] * 1e-3
+    achieved = tpp * FLOP_PER_TERM / t_rf / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "k_reduce_points<64,0,CLAMP> (signal tracing forward)",
+                "launch_ms": round(phases["render_fwd"], 3)}
+    out = {
+        "metric": "fwd+bwd RF render terms/s",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mlp_box: full-space training step, 2^20 points (64x64 primary rays "
+                               "x 256 depths, 20 cm cube at 0.30 m), 32x32 monostatic aperture at "
+                               "2 mm, 128 frequencies 77-81 GHz, 8x256 softplus(100) SDF MLP on a "
+                               "6-octave encoding + 2x64 head, FP32, box target + 10 dB noise",
+                   "terms_per_step": terms_step, "parallelism": "single GPU"},
+        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

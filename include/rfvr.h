@@ -82,6 +82,8 @@ typedef struct rfvr_fields {
     const float* phi_rx;   /* reserved for bistatic, must be NULL                    */
     float        s;        /* logistic sharpness (1/m), finite, > 0                  */
     float        amp_tx;   /* learnt global amplitude A'_tx, finite                  */
+    const float* amp_ptr;  /* device [1] or NULL; when set, A'_tx is read from device
+                              memory at kernel time (no host round trip per step)   */
 } rfvr_fields;
 
 /* ------------------------------------------------------------------------
@@ -228,6 +230,10 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
  * ------------------------------------------------------------------------ */
 int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t t, float lr,
                float b1, float b2, float eps, float wd, void* stream);
+
+/* Occupancy at the detached ray / antenna origins (Eq. lens-less-transmittance):
+ *   phi[k] = 1 / (1 + exp(-s * sdf[k])),  k < n.  s finite and > 0. */
+int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* stream);
 
 /* Library information. */
 const char* rfvr_last_error(void);

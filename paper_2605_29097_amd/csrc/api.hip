@@ -179,8 +179,8 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
                          "ant records")))
         return rc;
     if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, fl->sdf, fl->grad, fl->refl,
-                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, rec, alpha_out,
-                                            trans_out, st),
+                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, fl->amp_ptr, rec,
+                                            alpha_out, trans_out, st),
                          "render prep")))
         return rc;
     if ((rc = hip_status(launch_reduce_points_render(g, ant, rec, flags, ns, partial, st),
@@ -227,8 +227,8 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                          "ant records")))
         return rc;
     if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, fl->sdf, fl->grad, fl->refl,
-                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, rec, alpha,
-                                            trans, st),
+                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, fl->amp_ptr, rec,
+                                            alpha, trans, st),
                          "render prep")))
         return rc;
     if ((rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(g_signal), g.n_meas,
@@ -239,7 +239,8 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                          "render adjoint term kernel")))
         return rc;
     if ((rc = hip_status(launch_scan_adjoint(g, sm->ray_weight, fl->sdf, fl->grad, fl->refl, fl->s,
-                                             fl->amp_tx, alpha, trans, gb, gT, gn, galpha, pamp, ps,
+                                             fl->amp_tx, fl->amp_ptr, alpha, trans, gb, gT, gn, galpha,
+                                             pamp, ps,
                                              g_sdf, g_grad, g_refl, acc, st),
                          "scan adjoint")))
         return rc;
@@ -363,6 +364,14 @@ int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* r
     return hip_status(launch_sample_points(*d, basis, xyz, u, ray_origin,
                                            reinterpret_cast<hipStream_t>(stream)),
                       "sample points");
+}
+
+// ---------------------------------------------------------------- occupancy
+int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* stream) {
+    if (n < 1 || !sdf || !phi) { set_error("n >= 1, sdf and phi are required"); return RFVR_E_INVALID; }
+    if (!std::isfinite(s) || s <= 0.0f) { set_error("s must be finite and > 0"); return RFVR_E_INVALID; }
+    return hip_status(launch_occupancy((long)n, s, sdf, phi, reinterpret_cast<hipStream_t>(stream)),
+                      "occupancy");
 }
 
 // ---------------------------------------------------------------- AdamW

@@ -159,4 +159,17 @@ hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, fl
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// occupancy Phi = sigmoid(s f)
+// ---------------------------------------------------------------------------
+__global__ void k_occupancy(long n, float s, const float* __restrict__ f, float* __restrict__ phi) {
+    long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) phi[k] = sigmoidf_(s * f[k]);
+}
+
+hipError_t launch_occupancy(long n, float s, const float* f, float* phi, hipStream_t st) {
+    hipLaunchKernelGGL(k_occupancy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, f, phi);
+    return hipGetLastError();
+}
+
 }  // namespace rfvr

@@ -1,33 +1,830 @@
-// SDF network: placeholder entry points until the MFMA kernels land.
+// SDF network with reflectiveness head (Sec. "Opaque density representation",
+// "Signal representation"; App. C) on the MI355X matrix cores.
+//
+// Points are the GEMM's long dimension.  Every dense layer runs as an MFMA
+// (v_mfma_f32_16x16x4_f32) GEMM with the elementwise work of its neighbours
+// fused into the operand loads (softplus, its derivative times a tangent or an
+// adjoint, relu) and the bias / relu-mask / accumulate into its epilogue.
+//
+// Forward call: primal layers, then grad_x f by one reverse sweep
+//   G^(8) = w_out, G^(l) = (softplus'(Z^(l)) . G^(l+1)) W_l, grad = J_PE^T G^(0).
+// Backward call: J = sum g_f f + g_grad . grad_x f + g_a a.  Since
+// g_grad . grad_x f is the directional derivative of f along g_grad, the
+// parameter gradient is reverse mode over a primal + tangent forward pass
+// (Z, Zdot per layer), giving per layer
+//   Zdot_bar = sp'(Z) Hdot_bar,  Z_bar = sp'(Z) H_bar + sp''(Z) Zdot Hdot_bar,
+//   W_bar = Z_bar^T H + Zdot_bar^T Hdot,  H_bar = Z_bar W,  Hdot_bar = Zdot_bar W.
+// Weight gradients reduce over points in fixed splits (no atomics).
 #include "rfvr_impl.hpp"
+
+namespace rfvr {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+enum { PRO_ID = 0, PRO_SP = 1, PRO_DSP_MUL = 2, PRO_RELU = 3 };
+enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2 };
+
+__device__ __forceinline__ float sp_f(float z, float beta) {
+    const float bz = beta * z;
+    return (fmaxf(bz, 0.0f) + log1pf(expf(-fabsf(bz)))) / beta;
+}
+__device__ __forceinline__ float sp_d1(float z, float beta) { return sigmoidf_(beta * z); }
+__device__ __forceinline__ float sp_d2(float z, float beta) {
+    const float s = sigmoidf_(beta * z);
+    return beta * s * (1.0f - s);
+}
+
+template <int PRO>
+__device__ __forceinline__ float4 prologue(float4 v, const float* a2, float beta) {
+    if constexpr (PRO == PRO_SP) {
+        v.x = sp_f(v.x, beta); v.y = sp_f(v.y, beta); v.z = sp_f(v.z, beta); v.w = sp_f(v.w, beta);
+    } else if constexpr (PRO == PRO_DSP_MUL) {
+        const float4 u = *reinterpret_cast<const float4*>(a2);
+        v.x = sp_d1(v.x, beta) * u.x; v.y = sp_d1(v.y, beta) * u.y;
+        v.z = sp_d1(v.z, beta) * u.z; v.w = sp_d1(v.w, beta) * u.w;
+    } else if constexpr (PRO == PRO_RELU) {
+        v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
+    }
+    return v;
+}
+
+// ----------------------------------------------------------------------------
+// Y[P x M] = pro(A)[P x K] * B[M x K]^T  (+ epilogue).  K multiple of 16; A and
+// B rows hold K valid or zero-padded columns; lda/ldb multiples of 4.
+// Block 128 points x BM outputs, 4 waves, 16x16x4 MFMA tiles; the k index of
+// a lane's operand is permuted so each lane reads 4 consecutive k (one float4).
+// ----------------------------------------------------------------------------
+struct GemmArgs {
+    const float* A; const float* A2; long lda;
+    const float* B; long ldb;
+    const float* bias;            // EPI_BIAS: [M] or null
+    const float* C;               // EPI_RELUMASK: mask source [P][ldc]
+    long ldc;
+    float* Y; long ldy;
+    long P; int M; int K;
+    float beta;
+};
+
+template <int PRO, int EPI, int BM>
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+    constexpr int BP = 128, BK = 16, LW = BK + 4;
+    constexpr int WP = (BM == 128) ? 2 : 4;
+    constexpr int WM = 4 / WP;
+    constexpr int TP = BP / WP / 16;
+    constexpr int TM = BM / WM / 16;
+    __shared__ float sA[BP * LW];
+    __shared__ float sB[BM * LW];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int wp = wv % WP, wm = wv / WP;
+    const int li = lane & 15, lg = lane >> 4;
+    const long p0 = (long)blockIdx.x * BP;
+    const int m0 = blockIdx.y * BM;
+    floatx4 acc[TP][TM];
+#pragma unroll
+    for (int a = 0; a < TP; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + h * 256;
+            const int row = e >> 2, c4 = (e & 3) * 4;
+            const long p = p0 + row;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (p < g.P) {
+                const long off = p * g.lda + k0 + c4;
+                v = *reinterpret_cast<const float4*>(g.A + off);
+                v = prologue<PRO>(v, PRO == PRO_DSP_MUL ? g.A2 + off : nullptr, g.beta);
+            }
+            *reinterpret_cast<float4*>(&sA[row * LW + c4]) = v;
+        }
+#pragma unroll
+        for (int e = tid; e < BM * 4; e += 256) {
+            const int row = e >> 2, c4 = (e & 3) * 4;
+            const int m = m0 + row;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (m < g.M) v = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
+            *reinterpret_cast<float4*>(&sB[row * LW + c4]) = v;
+        }
+        __syncthreads();
+        floatx4 af[TP], bf[TM];
+#pragma unroll
+        for (int a = 0; a < TP; ++a)
+            af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * (BP / WP) + a * 16 + li) * LW + lg * 4]);
+#pragma unroll
+        for (int b = 0; b < TM; ++b)
+            bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / WM) + b * 16 + li) * LW + lg * 4]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < TP; ++a)
+#pragma unroll
+                for (int b = 0; b < TM; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < TP; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b) {
+            const int m = m0 + wm * (BM / WM) + b * 16 + li;
+            if (m >= g.M) continue;
+            const float bias = (EPI == EPI_BIAS && g.bias) ? g.bias[m] : 0.0f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
+                if (p >= g.P) continue;
+                float y = acc[a][b][v];
+                if constexpr (EPI == EPI_BIAS) y += bias;
+                if constexpr (EPI == EPI_ACC) y += g.Y[p * g.ldy + m];
+                if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
+                g.Y[p * g.ldy + m] = y;
+            }
+        }
+}
+
+// ----------------------------------------------------------------------------
+// Weight gradient partials: part[split][M][Kout] = sum over the split's points
+// of A[p][m] * pro(B)[p][k].  Block 128 (m) x 128 (k), chunks of 16 points,
+// operands transposed into LDS so MFMA reads float4 along the point index.
+// ----------------------------------------------------------------------------
+struct WgArgs {
+    const float* A; long lda;                  // [P][lda], columns 0..M-1
+    const float* B; const float* B2; long ldb; // [P][ldb], columns 0..Kout-1
+    float* part;                               // [n_split][M][Kout]
+    long P; int M; int Kout; long per_split;
+    float beta;
+};
+
+template <int PRO>
+__global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
+    constexpr int BM = 128, BN = 128, BK = 16, LW = BK + 4;
+    __shared__ float sA[BM * LW];
+    __shared__ float sB[BN * LW];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int wp = wv % 2, wn = wv / 2;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const long split = blockIdx.z;
+    const long pb = split * g.per_split;
+    long pe = pb + g.per_split;
+    if (pe > g.P) pe = g.P;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int row = tid >> 4;          // point within the chunk
+    const int c8 = (tid & 15) * 8;     // 8 consecutive columns
+    for (long q0 = pb; q0 < pe; q0 += BK) {
+        const long p = q0 + row;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = c8 + 4 * h;
+            float4 va = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vb = va;
+            if (p < pe) {
+                if (m0 + c < g.M) va = *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c);
+                if (n0 + c < g.Kout) {
+                    const long off = p * g.ldb + n0 + c;
+                    vb = *reinterpret_cast<const float4*>(g.B + off);
+                    vb = prologue<PRO>(vb, PRO == PRO_DSP_MUL ? g.B2 + off : nullptr, g.beta);
+                }
+            }
+            sA[(c + 0) * LW + row] = va.x; sA[(c + 1) * LW + row] = va.y;
+            sA[(c + 2) * LW + row] = va.z; sA[(c + 3) * LW + row] = va.w;
+            sB[(c + 0) * LW + row] = vb.x; sB[(c + 1) * LW + row] = vb.y;
+            sB[(c + 2) * LW + row] = vb.z; sB[(c + 3) * LW + row] = vb.w;
+        }
+        __syncthreads();
+        floatx4 af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * 64 + a * 16 + li) * LW + lg * 4]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wn * 64 + b * 16 + li) * LW + lg * 4]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+    float* out = g.part + split * (long)g.M * g.Kout;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int k = n0 + wn * 64 + b * 16 + li;
+            if (k >= g.Kout) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wp * 64 + a * 16 + lg * 4 + v;
+                if (m < g.M) out[(long)m * g.Kout + k] = acc[a][b][v];
+            }
+        }
+}
+
+// dst[m][k] (row stride k_real, k < k_real) (+)= sum_s part[s][m][k]
+__global__ void k_wg_reduce(const float* __restrict__ part, int n_split, int M, int Kout, int k_real,
+                            float* __restrict__ dst, int accumulate) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)M * k_real) return;
+    const int m = (int)(o / k_real), k = (int)(o % k_real);
+    float s = 0.0f;
+    for (int t = 0; t < n_split; ++t) s += part[((long)t * M + m) * Kout + k];
+    dst[o] = accumulate ? dst[o] + s : s;
+}
+
+// ----------------------------------------------------------------------------
+// column sums with fused element functions, two fixed-order stages
+//   mode 0: X[p][m]      mode 1: s[p] relu(X[p][m])
+//   mode 2: s[p] sp(X[p][m]) + sp'(X[p][m]) X2[p][m]
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict__ X,
+                                                        const float* __restrict__ X2,
+                                                        const float* __restrict__ s, long ldx,
+                                                        long P, int M, long rows_per, int mode,
+                                                        float beta, float* __restrict__ part) {
+    const int m = threadIdx.x;
+    if (m >= M) return;
+    const long rb = (long)blockIdx.x * rows_per;
+    long re = rb + rows_per;
+    if (re > P) re = P;
+    float acc = 0.0f;
+    for (long p = rb; p < re; ++p) {
+        const float x = X[p * ldx + m];
+        float d;
+        if (mode == 0) d = x;
+        else if (mode == 1) d = s[p] * fmaxf(x, 0.0f);
+        else d = (s ? s[p] * sp_f(x, beta) : 0.0f) + sp_d1(x, beta) * X2[p * ldx + m];
+        acc += d;
+    }
+    part[(long)blockIdx.x * M + m] = acc;
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int nb, int M, float scale,
+                               float* __restrict__ dst, int accumulate) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s += part[(long)b * M + m];
+    s *= scale;
+    dst[m] = accumulate ? dst[m] + s : s;
+}
+
+// ----------------------------------------------------------------------------
+// positional encoding (and its tangent along v / half_size), zero padded to ld
+// ----------------------------------------------------------------------------
+__global__ void k_pe(long n, const float* __restrict__ xyz, float cx, float cy, float cz,
+                     float inv_half, int L, int ld, float* __restrict__ X,
+                     const float* __restrict__ v, float* __restrict__ Xd) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float c[3] = {cx, cy, cz};
+    float* row = X + p * ld;
+    float* drow = Xd ? Xd + p * ld : nullptr;
+    for (int d = 0; d < 3; ++d) {
+        const float xh = (xyz[3 * p + d] - c[d]) * inv_half;
+        const float vd = v ? v[3 * p + d] * inv_half : 0.0f;
+        row[d] = xh;
+        if (drow) drow[d] = vd;
+        float scale = 1.0f;
+        for (int k = 0; k < L; ++k) {
+            float sn, cs;
+            sincospif(scale * xh, &sn, &cs);
+            row[3 + 6 * k + d] = sn;
+            row[3 + 6 * k + 3 + d] = cs;
+            if (drow) {
+                const float w = 3.14159265358979f * scale * vd;
+                drow[3 + 6 * k + d] = cs * w;
+                drow[3 + 6 * k + 3 + d] = -sn * w;
+            }
+            scale *= 2.0f;
+        }
+    }
+    for (int k = 3 + 6 * L; k < ld; ++k) {
+        row[k] = 0.0f;
+        if (drow) drow[k] = 0.0f;
+    }
+}
+
+// grad_x f = J_PE^T G0 (G0 = dF/dgamma, row stride ld)
+__global__ void k_pe_grad(long n, const float* __restrict__ xyz, float cx, float cy, float cz,
+                          float inv_half, int L, const float* __restrict__ G0, int ld,
+                          float* __restrict__ grad) {
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float c[3] = {cx, cy, cz};
+    const float* g = G0 + p * ld;
+    for (int d = 0; d < 3; ++d) {
+        const float xh = (xyz[3 * p + d] - c[d]) * inv_half;
+        float acc = g[d];
+        float scale = 1.0f;
+        for (int k = 0; k < L; ++k) {
+            float sn, cs;
+            sincospif(scale * xh, &sn, &cs);
+            const float w = 3.14159265358979f * scale;
+            acc += w * (cs * g[3 + 6 * k + d] - sn * g[3 + 6 * k + 3 + d]);
+            scale *= 2.0f;
+        }
+        grad[3 * p + d] = acc;   // d/dx = (d/dx_hat) / half, times f's half_size
+    }
+}
+
+// out[p] = post(scale * (sum_m w[m] act(Y[p][m]) + b)); one wave per row
+//   act: 1 softplus, 3 relu ; post: 0 identity, 1 sigmoid
+__global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict__ Y, long ldy,
+                                                int M, int act, int post, const float* __restrict__ w,
+                                                const float* __restrict__ b, float scale, float beta,
+                                                float* __restrict__ out) {
+    const long p = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (p >= n) return;
+    float acc = 0.0f;
+    for (int m = lane; m < M; m += 64) {
+        const float y = Y[p * ldy + m];
+        const float a = act == PRO_SP ? sp_f(y, beta) : fmaxf(y, 0.0f);
+        acc = __builtin_fmaf(w[m], a, acc);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if (lane == 0) {
+        const float v = scale * (acc + b[0]);
+        out[p] = post ? sigmoidf_(v) : v;
+    }
+}
+
+// seed of the normal sweep: S[p][m] = sp'(Z[p][m]) * w[m]
+__global__ void k_seed(long n, int M, const float* __restrict__ Z, long ld, const float* __restrict__ w,
+                       float beta, float* __restrict__ S) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n * M) return;
+    const long p = o / M;
+    const int m = (int)(o % M);
+    S[p * ld + m] = sp_d1(Z[p * ld + m], beta) * w[m];
+}
+
+// head output adjoint: ybar3 = g_a a (1-a) with a recomputed; Ybar2 = ybar3 w relu'(Y2)
+__global__ __launch_bounds__(256) void k_head_out_bwd(long n, const float* __restrict__ Y2, long ld,
+                                                      int M, const float* __restrict__ w,
+                                                      const float* __restrict__ b,
+                                                      const float* __restrict__ g_a,
+                                                      float* __restrict__ ybar3,
+                                                      float* __restrict__ Ybar2) {
+    const long p = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (p >= n) return;
+    float acc = 0.0f;
+    for (int m = lane; m < M; m += 64) acc = __builtin_fmaf(w[m], fmaxf(Y2[p * ld + m], 0.0f), acc);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    const float a = sigmoidf_(acc + b[0]);
+    const float yb = g_a ? g_a[p] * a * (1.0f - a) : 0.0f;
+    if (lane == 0) ybar3[p] = yb;
+    for (int m = lane; m < M; m += 64) Ybar2[p * ld + m] = Y2[p * ld + m] > 0.0f ? yb * w[m] : 0.0f;
+}
+
+// H_bar8[p][m] = half g_f[p] w_out[m] ; Hdot_bar8[p][m] = half w_out[m]
+__global__ void k_top_adjoint(long n, int M, const float* __restrict__ g_f, const float* __restrict__ w,
+                              float half, long ld, float* __restrict__ Hb, float* __restrict__ Hdb) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n * M) return;
+    const long p = o / M;
+    const int m = (int)(o % M);
+    Hb[p * ld + m] = g_f ? half * g_f[p] * w[m] : 0.0f;
+    Hdb[p * ld + m] = half * w[m];
+}
+
+// Z_bar = sp'(Z) H_bar + sp''(Z) Zdot Hdot_bar ; Zdot_bar = sp'(Z) Hdot_bar
+__global__ void k_layer_adjoint(long n, int M, long ld, const float* __restrict__ Z,
+                                const float* __restrict__ Zd, const float* __restrict__ Hb,
+                                const float* __restrict__ Hdb, float beta, float* __restrict__ Zb,
+                                float* __restrict__ Zdb) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n * M) return;
+    const long p = o / M;
+    const long e = p * ld + (o % M);
+    const float z = Z[e];
+    const float s = sigmoidf_(beta * z);
+    const float d2 = beta * s * (1.0f - s);
+    const float hdb = Hdb[e];
+    Zb[e] = s * Hb[e] + d2 * Zd[e] * hdb;
+    Zdb[e] = s * hdb;
+}
+
+__global__ void k_fill(float* __restrict__ p, long n, float v) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n) p[o] = v;
+}
+
+// out[c][r] = in[r][c] for r < R, c < C, zero in the padding; out is [Cpad][Rpad]
+__global__ void k_transpose_pad(const float* __restrict__ in, int R, int C, int Rpad, int Cpad,
+                                float* __restrict__ out) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)Rpad * Cpad) return;
+    const int c = (int)(o / Rpad), r = (int)(o % Rpad);
+    out[o] = (r < R && c < C) ? in[(long)r * C + c] : 0.0f;
+}
+
+// out[r][c] = in[r][c] zero padded to [R][Cpad]
+__global__ void k_pad_cols(const float* __restrict__ in, int R, int C, int Cpad, float* __restrict__ out) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)R * Cpad) return;
+    const int r = (int)(o / Cpad), c = (int)(o % Cpad);
+    out[o] = c < C ? in[(long)r * C + c] : 0.0f;
+}
+
+// ============================================================================
+// host orchestration
+// ============================================================================
+namespace {
+
+constexpr long kChunk = 1 << 18;          // points per pass (bounds the workspace)
+constexpr int kWgSplits = 128;            // weight-gradient point splits per pass
+constexpr int kColBlocks = 256;           // column-sum partial blocks
+
+struct Layout {
+    int L, W, in0, in0p, HL, HW;
+    long oW[16], ob[16], o_wout, o_bout, oWh[4], obh[4], o_whout, o_bhout, total;
+};
+
+int check_net(const rfvr_mlp* n) {
+    if (!n) { set_error("mlp descriptor is NULL"); return RFVR_E_INVALID; }
+    if (n->n_layers < 1 || n->n_layers > 16 || n->width < 64 || n->width > 256 || n->width % 64 ||
+        n->pe_octaves < 0 || n->pe_octaves > 12 || n->head_layers < 1 || n->head_layers > 4 ||
+        n->head_width < 64 || n->head_width > 256 || n->head_width % 64) {
+        set_error("unsupported network shape (layers 1..16, width 64..256 step 64, octaves 0..12, "
+                  "head 1..4 x 64..256 step 64)");
+        return RFVR_E_INVALID;
+    }
+    if ((3 + 6 * n->pe_octaves + 15) / 16 * 16 > n->width) {
+        set_error("encoding width (3 + 6 * pe_octaves, padded to 16) must not exceed the layer width");
+        return RFVR_E_INVALID;
+    }
+    if (!(n->softplus_beta > 0.0f) || !(n->half_size > 0.0f) || n->softplus_beta != n->softplus_beta) {
+        set_error("softplus_beta and half_size must be > 0");
+        return RFVR_E_INVALID;
+    }
+    if (n->precision != RFVR_PREC_FP32 && n->precision != RFVR_PREC_BF16) {
+        set_error("unknown precision %d", n->precision);
+        return RFVR_E_INVALID;
+    }
+    return RFVR_OK;
+}
+
+Layout layout(const rfvr_mlp* n) {
+    Layout l;
+    l.L = n->n_layers; l.W = n->width; l.HL = n->head_layers; l.HW = n->head_width;
+    l.in0 = 3 + 6 * n->pe_octaves;
+    l.in0p = (l.in0 + 15) / 16 * 16;
+    long off = 0;
+    for (int i = 0; i < l.L; ++i) {
+        const int fin = i == 0 ? l.in0 : l.W;
+        l.oW[i] = off; off += (long)l.W * fin;
+        l.ob[i] = off; off += l.W;
+    }
+    l.o_wout = off; off += l.W;
+    l.o_bout = off; off += 1;
+    for (int h = 0; h < l.HL; ++h) {
+        const int fin = h == 0 ? l.W : l.HW;
+        l.oWh[h] = off; off += (long)l.HW * fin;
+        l.obh[h] = off; off += l.HW;
+    }
+    l.o_whout = off; off += l.HW;
+    l.o_bhout = off; off += 1;
+    l.total = off;
+    return l;
+}
+
+inline unsigned blocks(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// device copies of the weights in the layouts the GEMMs read, 256-byte
+// aligned (the flat parameter vector has matrices at odd offsets)
+struct Weights {
+    float* Wp[16];         // W_l [W][fin_pad], zero padded
+    float* WT[16];         // W_l^T [fin_pad][W]
+    float* Whp[4];         // Wh_h [HW][fin]
+    float* WhT[4];         // Wh_h^T [fin][HW]
+};
+
+size_t weights_bytes(const Layout& l) {
+    size_t b = 0;
+    for (int i = 0; i < l.L; ++i) b += 2 * align256(sizeof(float) * (i == 0 ? l.in0p : l.W) * l.W);
+    for (int h = 0; h < l.HL; ++h) b += 2 * align256(sizeof(float) * (h == 0 ? l.W : l.HW) * l.HW);
+    return b;
+}
+
+Weights take_weights(WsCursor& cur, const Layout& l) {
+    Weights w;
+    for (int i = 0; i < l.L; ++i) {
+        w.Wp[i] = cur.take<float>((size_t)(i == 0 ? l.in0p : l.W) * l.W);
+        w.WT[i] = cur.take<float>((size_t)(i == 0 ? l.in0p : l.W) * l.W);
+    }
+    for (int h = 0; h < l.HL; ++h) {
+        w.Whp[h] = cur.take<float>((size_t)(h == 0 ? l.W : l.HW) * l.HW);
+        w.WhT[h] = cur.take<float>((size_t)(h == 0 ? l.W : l.HW) * l.HW);
+    }
+    return w;
+}
+
+hipError_t prep_weights(const Layout& l, const float* P, const Weights& w, hipStream_t st) {
+    for (int i = 0; i < l.L; ++i) {
+        const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
+        hipLaunchKernelGGL(k_pad_cols, dim3(blocks((long)l.W * finp)), dim3(256), 0, st, P + l.oW[i],
+                           l.W, fin, finp, w.Wp[i]);
+        hipLaunchKernelGGL(k_transpose_pad, dim3(blocks((long)l.W * finp)), dim3(256), 0, st,
+                           P + l.oW[i], l.W, fin, l.W, finp, w.WT[i]);
+    }
+    for (int h = 0; h < l.HL; ++h) {
+        const int fin = h == 0 ? l.W : l.HW;
+        hipLaunchKernelGGL(k_pad_cols, dim3(blocks((long)l.HW * fin)), dim3(256), 0, st, P + l.oWh[h],
+                           l.HW, fin, fin, w.Whp[h]);
+        hipLaunchKernelGGL(k_transpose_pad, dim3(blocks((long)l.HW * fin)), dim3(256), 0, st,
+                           P + l.oWh[h], l.HW, fin, l.HW, fin, w.WhT[h]);
+    }
+    return hipGetLastError();
+}
+
+template <int PRO, int EPI>
+void gemm(const GemmArgs& a, hipStream_t st) {
+    const unsigned gx = blocks(a.P, 128);
+    if (a.M <= 64) {
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64>), dim3(gx, 1), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128>), dim3(gx, (unsigned)((a.M + 127) / 128)),
+                           dim3(256), 0, st, a);
+    }
+}
+
+GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
+            float* Y, long ldy, long P, int M, int K, float beta, const float* C = nullptr,
+            long ldc = 0) {
+    GemmArgs g;
+    g.A = A; g.A2 = A2; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.C = C; g.ldc = ldc;
+    g.Y = Y; g.ldy = ldy; g.P = P; g.M = M; g.K = K; g.beta = beta;
+    return g;
+}
+
+template <int PRO>
+void wgrad(const float* A, long lda, int M, const float* B, const float* B2, long ldb, int Kout,
+           long P, float beta, float* part, hipStream_t st) {
+    WgArgs g;
+    g.A = A; g.lda = lda; g.B = B; g.B2 = B2; g.ldb = ldb; g.part = part; g.P = P; g.M = M;
+    g.Kout = Kout; g.per_split = ((P + kWgSplits - 1) / kWgSplits + 15) / 16 * 16; g.beta = beta;
+    hipLaunchKernelGGL((k_gemm_wg<PRO>), dim3((M + 127) / 128, (Kout + 127) / 128, kWgSplits),
+                       dim3(256), 0, st, g);
+}
+
+void wg_reduce(const float* part, int n_split, int M, int Kout, int k_real, float* dst, int acc,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_wg_reduce, dim3(blocks((long)M * k_real)), dim3(256), 0, st, part, n_split, M,
+                       Kout, k_real, dst, acc);
+}
+
+void colsum(const float* X, const float* X2, const float* s, long ldx, long P, int M, int mode,
+            float beta, float scale, float* part, float* dst, int acc, hipStream_t st) {
+    const long per = (P + kColBlocks - 1) / kColBlocks;
+    hipLaunchKernelGGL(k_colsum_partial, dim3(kColBlocks), dim3(256), 0, st, X, X2, s, ldx, P, M, per,
+                       mode, beta, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3(blocks(M)), dim3(256), 0, st, part, kColBlocks, M, scale,
+                       dst, acc);
+}
+
+// --- forward workspace -------------------------------------------------------
+size_t fwd_bytes(const Layout& l, long n) {
+    const long c = n < kChunk ? n : kChunk;
+    return weights_bytes(l) + align256(sizeof(float) * c * l.in0p) +
+           (size_t)l.L * align256(sizeof(float) * c * l.W) + 2 * align256(sizeof(float) * c * l.W) +
+           (size_t)l.HL * align256(sizeof(float) * c * l.HW);
+}
+
+// --- backward workspace ------------------------------------------------------
+size_t bwd_bytes(const Layout& l, long n) {
+    const long c = n < kChunk ? n : kChunk;
+    const long wmax = l.W > l.in0p ? l.W : l.in0p;
+    return weights_bytes(l) + 2 * align256(sizeof(float) * c * l.in0p) +
+           2 * (size_t)l.L * align256(sizeof(float) * c * l.W) +   // Z, Zdot
+           4 * align256(sizeof(float) * c * l.W) +                  // Hbar, Hdotbar, Zbar, Zdotbar
+           2 * (size_t)l.HL * align256(sizeof(float) * c * l.HW) +  // head Y, Ybar
+           align256(sizeof(float) * c * l.HW) +                     // scratch head adjoint
+           align256(sizeof(float) * c) +                            // ybar3
+           align256(sizeof(float) * 2 * kWgSplits * (size_t)l.W * wmax) +
+           align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
+}
+
+}  // namespace
+}  // namespace rfvr
 
 using namespace rfvr;
 
 extern "C" {
 
 int64_t rfvr_mlp_param_count(const rfvr_mlp* net) {
-    if (!net || net->n_layers < 1 || net->width < 1 || net->head_layers < 1 || net->head_width < 1 ||
-        net->pe_octaves < 0)
-        return -1;
-    const int64_t in0 = 3 + 6 * (int64_t)net->pe_octaves;
-    int64_t n = (int64_t)net->width * in0 + net->width;
-    n += (int64_t)(net->n_layers - 1) * ((int64_t)net->width * net->width + net->width);
-    n += net->width + 1;
-    n += (int64_t)net->head_width * net->width + net->head_width;
-    n += (int64_t)(net->head_layers - 1) * ((int64_t)net->head_width * net->head_width + net->head_width);
-    n += net->head_width + 1;
-    return n;
+    if (check_net(net)) return -1;
+    return layout(net).total;
 }
 
-size_t rfvr_mlp_forward_ws_bytes(const rfvr_mlp*, int64_t) { return 0; }
-size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp*, int64_t) { return 0; }
-int rfvr_mlp_forward(const rfvr_mlp*, const float*, int64_t, float*, float*, float*, void*, size_t, void*) {
-    set_error("rfvr_mlp_forward: not built yet");
-    return RFVR_E_UNSUPPORTED;
+size_t rfvr_mlp_forward_ws_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return fwd_bytes(layout(net), (long)n);
 }
-int rfvr_mlp_backward(const rfvr_mlp*, const float*, int64_t, const float*, const float*, const float*,
-                      uint32_t, float*, void*, size_t, void*) {
-    set_error("rfvr_mlp_backward: not built yet");
-    return RFVR_E_UNSUPPORTED;
+
+size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return bwd_bytes(layout(net), (long)n);
 }
+
+int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sdf, float* grad,
+                     float* refl, void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_net(net))) return rc;
+    if (n < 1 || !xyz || !net->params) { set_error("n >= 1, xyz and params are required"); return RFVR_E_INVALID; }
+    if (net->precision != RFVR_PREC_FP32) { set_error("BF16 network path not built"); return RFVR_E_UNSUPPORTED; }
+    const Layout l = layout(net);
+    {
+        const size_t need = fwd_bytes(l, (long)n);
+        if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+            set_error("workspace too small or misaligned: need %zu bytes", need);
+            return RFVR_E_WORKSPACE;
+        }
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float* P = net->params;
+    const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
+    const long chunk = n < kChunk ? (long)n : kChunk;
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    const Weights w = take_weights(cur, l);
+    float* X0 = cur.take<float>((size_t)chunk * l.in0p);
+    float* Z[16];
+    for (int i = 0; i < l.L; ++i) Z[i] = cur.take<float>((size_t)chunk * l.W);
+    float* G[2] = {cur.take<float>((size_t)chunk * l.W), cur.take<float>((size_t)chunk * l.W)};
+    float* Yh[4];
+    for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
+    if ((rc = hip_status(prep_weights(l, P, w, st), "mlp weight prep"))) return rc;
+
+    for (long c0 = 0; c0 < n; c0 += chunk) {
+        const long m = (n - c0) < chunk ? (n - c0) : chunk;
+        const float* x = xyz + 3 * c0;
+        hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
+                           net->centre[2], inv_half, net->pe_octaves, l.in0p, X0, nullptr, nullptr);
+        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), st);
+        for (int i = 1; i < l.L; ++i)
+            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), st);
+        float* Zt = Z[l.L - 1];
+        if (sdf)
+            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Zt, (long)l.W, l.W,
+                               (int)PRO_SP, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
+        if (refl) {
+            gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), st);
+            for (int h = 1; h < l.HL; ++h)
+                gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), st);
+            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
+                               l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
+        }
+        if (grad) {
+            // G^(L) = w_out; G^(i) = (sp'(Z^(i)) . G^(i+1)) W_i
+            hipLaunchKernelGGL(k_seed, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, Zt, (long)l.W,
+                               P + l.o_wout, beta, G[0]);
+            int cur_g = 0;
+            for (int i = l.L - 1; i >= 0; --i) {
+                const int mout = i == 0 ? l.in0p : l.W;
+                float* dst = G[cur_g ^ 1];
+                if (i == l.L - 1)
+                    gemm<PRO_ID, EPI_BIAS>(ga(G[cur_g], nullptr, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), st);
+                else
+                    gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i], G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), st);
+                cur_g ^= 1;
+            }
+            hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
+                               net->centre[1], net->centre[2], inv_half, net->pe_octaves, G[cur_g],
+                               l.in0p, grad + 3 * c0);
+        }
+        if ((rc = hip_status(hipGetLastError(), "mlp forward"))) return rc;
+    }
+    return RFVR_OK;
 }
+
+int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
+                      const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
+                      void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_net(net))) return rc;
+    if (n < 1 || !xyz || !net->params || !g_params) { set_error("n >= 1, xyz, params and g_params are required"); return RFVR_E_INVALID; }
+    if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }
+    if (net->precision != RFVR_PREC_FP32) { set_error("BF16 network path not built"); return RFVR_E_UNSUPPORTED; }
+    const Layout l = layout(net);
+    {
+        const size_t need = bwd_bytes(l, (long)n);
+        if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+            set_error("workspace too small or misaligned: need %zu bytes", need);
+            return RFVR_E_WORKSPACE;
+        }
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float* P = net->params;
+    float* GP = g_params;
+    const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
+    const long chunk = n < kChunk ? (long)n : kChunk;
+    const long wmax = l.W > l.in0p ? l.W : l.in0p;
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    const Weights w = take_weights(cur, l);
+    float* X0 = cur.take<float>((size_t)chunk * l.in0p);
+    float* X0d = cur.take<float>((size_t)chunk * l.in0p);
+    float *Z[16], *Zd[16];
+    for (int i = 0; i < l.L; ++i) Z[i] = cur.take<float>((size_t)chunk * l.W);
+    for (int i = 0; i < l.L; ++i) Zd[i] = cur.take<float>((size_t)chunk * l.W);
+    float* Hb = cur.take<float>((size_t)chunk * l.W);
+    float* Hdb = cur.take<float>((size_t)chunk * l.W);
+    float* Zb = cur.take<float>((size_t)chunk * l.W);
+    float* Zdb = cur.take<float>((size_t)chunk * l.W);
+    float *Yh[4], *Ybh[4];
+    for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
+    for (int h = 0; h < l.HL; ++h) Ybh[h] = cur.take<float>((size_t)chunk * l.HW);
+    float* Rtmp = cur.take<float>((size_t)chunk * l.HW);
+    float* yb3 = cur.take<float>((size_t)chunk);
+    float* part = cur.take<float>((size_t)2 * kWgSplits * l.W * wmax);
+    float* cpart = cur.take<float>((size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
+    if ((rc = hip_status(prep_weights(l, P, w, st), "mlp weight prep"))) return rc;
+
+    for (long c0 = 0; c0 < n; c0 += chunk) {
+        const long m = (n - c0) < chunk ? (n - c0) : chunk;
+        const int acc = (c0 > 0 || (flags & RFVR_ACCUMULATE)) ? 1 : 0;
+        const float* x = xyz + 3 * c0;
+        const float* gf = g_sdf ? g_sdf + c0 : nullptr;
+        const float* ga_ = g_refl ? g_refl + c0 : nullptr;
+        // primal and tangent forward
+        hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
+                           net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
+                           g_grad ? g_grad + 3 * c0 : nullptr, X0d);
+        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), st);
+        gemm<PRO_ID, EPI_BIAS>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Zd[0], l.W, m, l.W, l.in0p, beta), st);
+        for (int i = 1; i < l.L; ++i) {
+            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), st);
+            gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i - 1], Zd[i - 1], l.W, w.Wp[i], l.W, nullptr, Zd[i], l.W, m, l.W, l.W, beta), st);
+        }
+        float* Zt = Z[l.L - 1];
+        float* Zdt = Zd[l.L - 1];
+        // head forward
+        gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), st);
+        for (int h = 1; h < l.HL; ++h)
+            gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), st);
+        // head output: ybar3, Ybar_{HL-1}
+        hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
+                           l.HW, P + l.o_whout, P + l.o_bhout, ga_, yb3, Ybh[l.HL - 1]);
+        colsum(Yh[l.HL - 1], nullptr, yb3, l.HW, m, l.HW, 1, beta, 1.0f, cpart, GP + l.o_whout, acc, st);
+        colsum(yb3, nullptr, nullptr, 1, m, 1, 0, beta, 1.0f, cpart, GP + l.o_bhout, acc, st);
+        // head hidden layers, top down
+        for (int h = l.HL - 1; h >= 0; --h) {
+            float* Yb = Ybh[h];
+            if (h > 0) {
+                wgrad<PRO_RELU>(Yb, l.HW, l.HW, Yh[h - 1], nullptr, l.HW, l.HW, m, beta, part, st);
+                wg_reduce(part, kWgSplits, l.HW, l.HW, l.HW, GP + l.oWh[h], acc, st);
+                colsum(Yb, nullptr, nullptr, l.HW, m, l.HW, 0, beta, 1.0f, cpart, GP + l.obh[h], acc, st);
+                // Ybar_{h-1} = (Ybar_h Wh_h) . relu'(Y_{h-1})
+                gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), st);
+            } else {
+                wgrad<PRO_SP>(Yb, l.HW, l.HW, Zt, nullptr, l.W, l.W, m, beta, part, st);
+                wg_reduce(part, kWgSplits, l.HW, l.W, l.W, GP + l.oWh[0], acc, st);
+                colsum(Yb, nullptr, nullptr, l.HW, m, l.HW, 0, beta, 1.0f, cpart, GP + l.obh[0], acc, st);
+            }
+        }
+        // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0, Hdot_bar = half w_out
+        hipLaunchKernelGGL(k_top_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, gf, P + l.o_wout,
+                           half, (long)l.W, Hb, Hdb);
+        gemm<PRO_ID, EPI_ACC>(ga(Ybh[0], nullptr, l.HW, w.WhT[0], l.HW, nullptr, Hb, l.W, m, l.W, l.HW, beta), st);
+        // sdf output layer: w_out_bar = half sum (g_f H + Hdot), b_out_bar = half sum g_f
+        colsum(Zt, Zdt, gf, l.W, m, l.W, 2, beta, half, cpart, GP + l.o_wout, acc, st);
+        if (gf) colsum(gf, nullptr, nullptr, 1, m, 1, 0, beta, half, cpart, GP + l.o_bout, acc, st);
+        else if (!acc) hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, GP + l.o_bout, 1L, 0.0f);
+        // trunk layers, top down
+        for (int i = l.L - 1; i >= 0; --i) {
+            hipLaunchKernelGGL(k_layer_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, (long)l.W,
+                               Z[i], Zd[i], Hb, Hdb, beta, Zb, Zdb);
+            const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
+            if (i == 0) {
+                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, st);
+                wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
+                              part + (size_t)kWgSplits * l.W * finp, st);
+            } else {
+                wgrad<PRO_SP>(Zb, l.W, l.W, Z[i - 1], nullptr, l.W, finp, m, beta, part, st);
+                wgrad<PRO_DSP_MUL>(Zdb, l.W, l.W, Z[i - 1], Zd[i - 1], l.W, finp, m, beta,
+                                   part + (size_t)kWgSplits * l.W * finp, st);
+            }
+            wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st);
+            colsum(Zb, nullptr, nullptr, l.W, m, l.W, 0, beta, 1.0f, cpart, GP + l.ob[i], acc, st);
+            if (i > 0) {
+                gemm<PRO_ID, EPI_BIAS>(ga(Zb, nullptr, l.W, w.WT[i], l.W, nullptr, Hb, l.W, m, l.W, l.W, beta), st);
+                gemm<PRO_ID, EPI_BIAS>(ga(Zdb, nullptr, l.W, w.WT[i], l.W, nullptr, Hdb, l.W, m, l.W, l.W, beta), st);
+            }
+        }
+        if ((rc = hip_status(hipGetLastError(), "mlp backward"))) return rc;
+    }
+    return RFVR_OK;
+}
+
+}  // extern "C"

@@ -177,8 +177,9 @@ hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, 
                               hipStream_t st);
 hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w,
                               const float* sdf, const float* grad, const float* refl,
-                              const float* phi_ray, int use_phi, float s, float amp, PtRec* rec,
-                              float* alpha_out, float* trans_out, hipStream_t st);
+                              const float* phi_ray, int use_phi, float s, float amp,
+                              const float* amp_ptr, PtRec* rec, float* alpha_out, float* trans_out,
+                              hipStream_t st);
 hipError_t launch_reduce_points_render(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
                                        uint32_t flags, int n_split, float2* partial, hipStream_t st);
 hipError_t launch_reduce_points_mf(const RenderGeom& g, const AntRec* ant, const QRec* rec,
@@ -192,10 +193,10 @@ hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, cons
                                     float* g_T, float* g_n, hipStream_t st);
 hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const float* sdf,
                                const float* grad, const float* refl, float s, float amp,
-                               const float* alpha, const float* trans, const float* g_b,
-                               const float* g_T, const float* g_n, float* g_alpha_tmp,
-                               float* part_amp, float* part_s, float* g_sdf, float* g_grad,
-                               float* g_refl, int accumulate, hipStream_t st);
+                               const float* amp_ptr, const float* alpha, const float* trans,
+                               const float* g_b, const float* g_T, const float* g_n,
+                               float* g_alpha_tmp, float* part_amp, float* part_s, float* g_sdf,
+                               float* g_grad, float* g_refl, int accumulate, hipStream_t st);
 hipError_t launch_sum_scalars(const float* part, int n, float* out, int accumulate,
                               hipStream_t st);
 
@@ -212,6 +213,7 @@ hipError_t launch_loss_partial(long n, const float* p, const float* ps, const fl
 hipError_t launch_loss_final(const double* part, int n_blocks, long n, float* loss, hipStream_t st);
 hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
                                 float* u, float* origin, hipStream_t st);
+hipError_t launch_occupancy(long n, float s, const float* f, float* phi, hipStream_t st);
 hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, float lr, float b1,
                         float b2, float eps, float wd, float bc1, float bc2, hipStream_t st);
 

@@ -41,7 +41,7 @@ class CSamples(ctypes.Structure):
 
 class CFields(ctypes.Structure):
     _fields_ = [("sdf", _vp), ("grad", _vp), ("refl", _vp), ("phi_ray", _vp), ("phi_tx", _vp),
-                ("phi_rx", _vp), ("s", _c_f), ("amp_tx", _c_f)]
+                ("phi_rx", _vp), ("s", _c_f), ("amp_tx", _c_f), ("amp_ptr", _vp)]
 
 
 class CSampleDesc(ctypes.Structure):
@@ -82,6 +82,7 @@ _SIGS = {
     "rfvr_mlp_backward_ws_bytes": ([_P(CMlp), _c_i64], _sz),
     "rfvr_mlp_backward": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
                           _c_i32),
+    "rfvr_occupancy": ([_c_i64, _c_f, _vp, _vp, _vp], _c_i32),
     "rfvr_adamw": ([_c_i64, _vp, _vp, _vp, _vp, _c_i64, _c_f, _c_f, _c_f, _c_f, _c_f, _vp], _c_i32),
 }
 
@@ -182,10 +183,11 @@ class Fields:
     amp: float = 1.0
     phi_ray: Optional[torch.Tensor] = None
     phi_tx: Optional[torch.Tensor] = None
+    amp_dev: Optional[torch.Tensor] = None     # device [1]: overrides amp at kernel time
 
     def c(self) -> CFields:
         return CFields(_ptr(self.sdf), _ptr(self.grad), _ptr(self.refl), _ptr(self.phi_ray),
-                       _ptr(self.phi_tx), None, float(self.s), float(self.amp))
+                       _ptr(self.phi_tx), None, float(self.s), float(self.amp), _ptr(self.amp_dev))
 
 
 # ----------------------------------------------------------------------------
@@ -343,6 +345,14 @@ def mlp_backward(net: MLP, xyz: torch.Tensor, g_sdf=None, g_grad=None, g_refl=No
     return gp
 
 
+def occupancy(s: float, sdf: torch.Tensor, stream=None):
+    """Phi = sigmoid(s * sdf) (detached origin occupancies)."""
+    phi = torch.empty_like(sdf)
+    _check(lib().rfvr_occupancy(sdf.numel(), float(s), _ptr(sdf.contiguous()), _ptr(phi), _stream(stream)),
+           "rfvr_occupancy")
+    return phi
+
+
 def adamw(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, stream=None):
     _check(lib().rfvr_adamw(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(t), float(lr),
                             float(b1), float(b2), float(eps), float(wd), _stream(stream)),
@@ -359,3 +369,4 @@ rfvr_sample_points = sample_points
 rfvr_mlp_forward = mlp_forward
 rfvr_mlp_backward = mlp_backward
 rfvr_adamw = adamw
+rfvr_occupancy = occupancy
