@@ -89,6 +89,34 @@ def cpu_baseline(cfg):
     return dict(value=terms / dt, unit="terms/s", cores=threads, kind="oracle", sample=sample)
 
 
+def probe(tr, which, reps):
+    """Run one term pass `reps` times on the workload's inputs."""
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    c = tr.cfg
+    xyz, u, origin = tr.samples()
+    f, grad, a = R.mlp_forward(tr.net, xyz)
+    sm = R.Samples(xyz=xyz)
+    fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3), refl=a.view(xyz.shape[:2]),
+                  s=c.s, amp=1.0)
+    sig = R.render_forward(tr.ap, sm, fl)
+    z, p = R.mf_forward(tr.ap, xyz, sig)
+    g_p = torch.randn_like(p)
+    g_sig = R.mf_backward(tr.ap, xyz, z, p, g_p)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        if which == "render_fwd":
+            R.render_forward(tr.ap, sm, fl)
+        elif which == "mf_fwd":
+            R.mf_forward(tr.ap, xyz, sig)
+        elif which == "mf_bwd":
+            R.mf_backward(tr.ap, xyz, z, p, g_p)
+        else:
+            R.render_backward(tr.ap, sm, fl, g_sig)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": which, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +124,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
+    ap.add_argument("--kernel-probe", choices=["render_fwd", "mf_fwd", "mf_bwd", "render_bwd"],
+                    help="run only one term pass of the workload (for hardware-counter runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
@@ -107,9 +139,20 @@ def main():
     from paper_2605_29097_amd.train import StepConfig, Trainer
     R.lib()
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
     cfg = StepConfig()
     params, target = make_inputs(cfg, dev)
     tr = Trainer(cfg, params, target, device=dev)
+    if args.kernel_probe:
+        probe(tr, args.kernel_probe, args.steps)
+        return
     for _ in range(args.warmup):
         tr.step()
     torch.cuda.synchronize()

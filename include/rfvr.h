@@ -231,6 +231,61 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
 int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t t, float lr,
                float b1, float b2, float eps, float wd, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal sampler (not in the paper: it concentrates the samples of
+ * Sec. Lensless Sampling where the render's own blend weights are, keeping
+ * stratified uniform samples as the fallback).
+ *
+ * Network: gamma_L(x_hat) -> [Linear(width) -> relu] x layers -> Linear(1),
+ * x_hat = (x - centre)/half_size; flat float32 params
+ *   W_0 [width][3+6L], b_0, ..., W_{layers-1} [width][width], b, w_out [width], b_out [1].
+ * ------------------------------------------------------------------------ */
+typedef struct rfvr_proposal {
+    int32_t      pe_octaves;     /* 0..5 (3 + 6 L <= 64)         */
+    int32_t      width;          /* 64                           */
+    int32_t      layers;         /* 1..4                         */
+    float        centre[3];
+    float        half_size;      /* > 0                          */
+    const float* params;         /* device                       */
+} rfvr_proposal;
+int64_t rfvr_proposal_param_count(const rfvr_proposal* net);
+size_t rfvr_proposal_ws_bytes(const rfvr_proposal* net, int64_t n);
+/* logits [n] at points xyz [n][3]. */
+int rfvr_proposal_forward(const rfvr_proposal* net, const float* xyz, int64_t n, float* logits,
+                          void* ws, size_t ws_bytes, void* stream);
+/* g_params (+)= d/dparams sum_q g_logits[q] z_q (activations recomputed). */
+int rfvr_proposal_backward(const rfvr_proposal* net, const float* xyz, int64_t n,
+                           const float* g_logits, uint32_t flags, float* g_params,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Importance samples along the primary rays of `d` (its n_z and mode are
+ * ignored).  logits: [n_ray][n_bins] at the centres of n_bins equal depth bins
+ * over [c.w_p - h, c.w_p + h].  pdf_b = (sigmoid(z_b) + 1e-3) / sum; slot s of
+ * ray r draws xi = (SplitMix64(key, r*(n_uni+n_imp) + s) >> 40) 2^-24 from the
+ * step's stream key (as RFVR_SAMPLE_STRATIFIED); slots s < n_uni are stratified
+ * uniform over the whole range, u = lo + (s + xi)(hi - lo)/n_uni; the others
+ * invert the CDF at v = (s - n_uni + xi)/n_imp, linearly inside the bin.
+ * Depths are sorted per ray (ties keep slot order).  n_bins <= 64,
+ * n_imp + n_uni <= 64.  Outputs xyz [n_ray][n_uni+n_imp][3], u (or NULL),
+ * ray_origin [n_ray][3] (or NULL). */
+int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32_t n_bins,
+                           int32_t n_imp, int32_t n_uni, float* xyz, float* u, float* ray_origin,
+                           void* stream);
+
+/* Proposal targets: per ray, blend weights w_k = trans_k * alpha_k of the
+ * render at depths u [n_ray][n_k] summed into n_bins equal bins of [lo, hi]
+ * (W_b), t_b = min(1, W_b / max(max_b W_b, 1e-3)).  targets: [n_ray][n_bins].
+ * n_k <= 64, n_bins <= 64. */
+int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
+                          const float* trans, float lo, float hi, int32_t n_bins, float* targets,
+                          void* stream);
+
+/* Mean binary cross-entropy of sigmoid(z) against t and its gradient
+ * g = (sigmoid(z) - t) / n.  loss: [1] output. */
+size_t rfvr_bce_ws_bytes(int64_t n);
+int rfvr_bce(int64_t n, const float* logits, const float* t, float* loss, float* g_logits,
+             void* ws, size_t ws_bytes, void* stream);
+
 /* Occupancy at the detached ray / antenna origins (Eq. lens-less-transmittance):
  *   phi[k] = 1 / (1 + exp(-s * sdf[k])),  k < n.  s finite and > 0. */
 int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* stream);

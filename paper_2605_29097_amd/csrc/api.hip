@@ -342,12 +342,9 @@ int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* ma
 }
 
 // ---------------------------------------------------------------- sampling
-int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* ray_origin,
-                       void* stream) {
-    if (!d || !xyz) { set_error("descriptor and xyz are required"); return RFVR_E_INVALID; }
-    if (d->n_ray_x < 1 || d->n_ray_y < 1 || d->n_z < 1) { set_error("ray counts must be >= 1"); return RFVR_E_INVALID; }
+static int sample_basis(const rfvr_sample_desc* d, double basis[9]) {
+    if (d->n_ray_x < 1 || d->n_ray_y < 1) { set_error("ray counts must be >= 1"); return RFVR_E_INVALID; }
     if (!(d->half_extent > 0.0f) || !std::isfinite(d->half_extent)) { set_error("half_extent must be finite and > 0"); return RFVR_E_INVALID; }
-    if (d->mode != RFVR_SAMPLE_GRID && d->mode != RFVR_SAMPLE_STRATIFIED) { set_error("unknown sampling mode %d", d->mode); return RFVR_E_INVALID; }
     double w[3] = {d->primary_dir[0], d->primary_dir[1], d->primary_dir[2]};
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(w[c]) || !std::isfinite((double)d->centre[c])) { set_error("non-finite direction or centre"); return RFVR_E_INVALID; }
@@ -360,10 +357,64 @@ int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* r
     double n1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
     for (int c = 0; c < 3; ++c) e1[c] /= n1;
     double e2[3] = {w[1] * e1[2] - w[2] * e1[1], w[2] * e1[0] - w[0] * e1[2], w[0] * e1[1] - w[1] * e1[0]};
-    double basis[9] = {e1[0], e1[1], e1[2], e2[0], e2[1], e2[2], w[0], w[1], w[2]};
+    const double b[9] = {e1[0], e1[1], e1[2], e2[0], e2[1], e2[2], w[0], w[1], w[2]};
+    for (int k = 0; k < 9; ++k) basis[k] = b[k];
+    return RFVR_OK;
+}
+
+int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* ray_origin,
+                       void* stream) {
+    if (!d || !xyz) { set_error("descriptor and xyz are required"); return RFVR_E_INVALID; }
+    if (d->n_z < 1) { set_error("n_z must be >= 1"); return RFVR_E_INVALID; }
+    if (d->mode != RFVR_SAMPLE_GRID && d->mode != RFVR_SAMPLE_STRATIFIED) { set_error("unknown sampling mode %d", d->mode); return RFVR_E_INVALID; }
+    double basis[9];
+    int rc;
+    if ((rc = sample_basis(d, basis))) return rc;
     return hip_status(launch_sample_points(*d, basis, xyz, u, ray_origin,
                                            reinterpret_cast<hipStream_t>(stream)),
                       "sample points");
+}
+
+int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32_t n_bins,
+                           int32_t n_imp, int32_t n_uni, float* xyz, float* u, float* ray_origin,
+                           void* stream) {
+    if (!d || !xyz || !logits) { set_error("descriptor, logits and xyz are required"); return RFVR_E_INVALID; }
+    if (n_bins < 1 || n_bins > 64 || n_imp < 0 || n_uni < 0 || n_imp + n_uni < 1 || n_imp + n_uni > 64) {
+        set_error("need 1 <= n_bins <= 64 and 1 <= n_imp + n_uni <= 64");
+        return RFVR_E_INVALID;
+    }
+    double basis[9];
+    int rc;
+    if ((rc = sample_basis(d, basis))) return rc;
+    return hip_status(launch_sample_importance(*d, basis, logits, n_bins, n_imp, n_uni, xyz, u, ray_origin,
+                                               reinterpret_cast<hipStream_t>(stream)),
+                      "importance sampling");
+}
+
+int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
+                          const float* trans, float lo, float hi, int32_t n_bins, float* targets,
+                          void* stream) {
+    if (n_ray < 1 || n_k < 1 || n_k > 64 || n_bins < 1 || n_bins > 64 || !u || !alpha || !trans || !targets) {
+        set_error("need n_ray >= 1, 1 <= n_k <= 64, 1 <= n_bins <= 64 and all arrays");
+        return RFVR_E_INVALID;
+    }
+    if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi)) { set_error("need finite lo < hi"); return RFVR_E_INVALID; }
+    return hip_status(launch_proposal_targets(n_ray, n_k, u, alpha, trans, lo, hi, n_bins, targets,
+                                              reinterpret_cast<hipStream_t>(stream)),
+                      "proposal targets");
+}
+
+size_t rfvr_bce_ws_bytes(int64_t n) { return rfvr_loss_ws_bytes(n); }
+
+int rfvr_bce(int64_t n, const float* logits, const float* t, float* loss, float* g_logits,
+             void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1 || !logits || !t || !loss) { set_error("n >= 1, logits, t and loss are required"); return RFVR_E_INVALID; }
+    int rc;
+    if ((rc = check_ws(ws, ws_bytes, rfvr_bce_ws_bytes(n)))) return rc;
+    const int nb = loss_blocks((long)n);
+    return hip_status(launch_bce((long)n, logits, t, loss, g_logits, reinterpret_cast<double*>(ws), nb,
+                                 reinterpret_cast<hipStream_t>(stream)),
+                      "bce");
 }
 
 // ---------------------------------------------------------------- occupancy

@@ -14,79 +14,112 @@
 
 namespace rfvr {
 
+#ifndef RFVR_HORNER_PPL
+#define RFVR_HORNER_PPL 1
+#endif
+constexpr int kHornerPPL = RFVR_HORNER_PPL;   // query points per lane
+
 template <bool TWO, bool NAIVE>
 __global__ __launch_bounds__(256) void k_mf_forward(
     long n_q, const float* __restrict__ xq, int n_meas, const AntRec* __restrict__ ant,
     const float2* __restrict__ sig, const float2* __restrict__ sig2, int np, double K0,
     double Kd, float2* __restrict__ z, float* __restrict__ power, float2* __restrict__ z2,
     float* __restrict__ power2) {
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = q < n_q;
-    const long qq = ok ? q : n_q - 1;
-    const double px = (double)xq[3 * qq], py = (double)xq[3 * qq + 1], pz = (double)xq[3 * qq + 2];
+    constexpr int PPL = kHornerPPL;
+    const long q0 = (long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+    double px[PPL], py[PPL], pz[PPL];
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        long q = q0 + (long)u * blockDim.x;
+        if (q >= n_q) q = n_q - 1;
+        px[u] = (double)xq[3 * q];
+        py[u] = (double)xq[3 * q + 1];
+        pz[u] = (double)xq[3 * q + 2];
+    }
     const int mid = np / 2;                        // multiple of 16
     const double Km = K0 + (double)mid * Kd;
-    float zr = 0.0f, zi = 0.0f, z2r = 0.0f, z2i = 0.0f;
+    float zr[PPL], zi[PPL], z2r[PPL], z2i[PPL];
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) { zr[u] = zi[u] = z2r[u] = z2i[u] = 0.0f; }
     for (int i = 0; i < n_meas; ++i) {
         const AntRec A = ant[i];
-        const PairGeom geo = pair_geom<NAIVE>(px - A.x, py - A.y, pz - A.z);
-        float cw, sw;
-        step_phasor<NAIVE>(geo, Kd, cw, sw);       // w = exp(+j 2 pi delta)
+        PairGeom geo[PPL];
+        float cw[PPL], sw[PPL];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            geo[u] = pair_geom<NAIVE>(px[u] - A.x, py[u] - A.y, pz[u] - A.z);
+            step_phasor<NAIVE>(geo[u], Kd, cw[u], sw[u]);       // w = exp(+j 2 pi delta)
+        }
         const float2* row = sig + (size_t)i * np;
         const float2* row2 = TWO ? sig2 + (size_t)i * np : nullptr;
         // H = sum_n s[n] w^(n - mid): upper half by Horner in w from the top,
         // lower half by Horner in conj(w) from the bottom
-        float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
-        float h2r = 0.0f, h2i = 0.0f, l2r = 0.0f, l2i = 0.0f;
+        float hr[PPL], hi[PPL], lr[PPL], li[PPL], h2r[PPL], h2i[PPL], l2r[PPL], l2i[PPL];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) hr[u] = hi[u] = lr[u] = li[u] = h2r[u] = h2i[u] = l2r[u] = l2i[u] = 0.0f;
         for (int n0 = np - 16; n0 >= mid; n0 -= 16) {
 #pragma unroll
-            for (int u = 15; u >= 0; --u) {
-                const float2 sv = row[n0 + u];
-                const float tr = __builtin_fmaf(-hi, sw, __builtin_fmaf(hr, cw, sv.x));
-                hi = __builtin_fmaf(hi, cw, __builtin_fmaf(hr, sw, sv.y));
-                hr = tr;
-                if constexpr (TWO) {
-                    const float2 sv2 = row2[n0 + u];
-                    const float t2 = __builtin_fmaf(-h2i, sw, __builtin_fmaf(h2r, cw, sv2.x));
-                    h2i = __builtin_fmaf(h2i, cw, __builtin_fmaf(h2r, sw, sv2.y));
-                    h2r = t2;
+            for (int k = 15; k >= 0; --k) {
+                const float2 sv = row[n0 + k];
+                float2 sv2;
+                if constexpr (TWO) sv2 = row2[n0 + k];
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) {
+                    const float tr = __builtin_fmaf(-hi[u], sw[u], __builtin_fmaf(hr[u], cw[u], sv.x));
+                    hi[u] = __builtin_fmaf(hi[u], cw[u], __builtin_fmaf(hr[u], sw[u], sv.y));
+                    hr[u] = tr;
+                    if constexpr (TWO) {
+                        const float t2 = __builtin_fmaf(-h2i[u], sw[u], __builtin_fmaf(h2r[u], cw[u], sv2.x));
+                        h2i[u] = __builtin_fmaf(h2i[u], cw[u], __builtin_fmaf(h2r[u], sw[u], sv2.y));
+                        h2r[u] = t2;
+                    }
                 }
             }
         }
         for (int n0 = 0; n0 < mid; n0 += 16) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const float2 sv = row[n0 + u];
-                const float tr = __builtin_fmaf(li, sw, __builtin_fmaf(lr, cw, sv.x));
-                li = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, sv.y));
-                lr = tr;
-                if constexpr (TWO) {
-                    const float2 sv2 = row2[n0 + u];
-                    const float t2 = __builtin_fmaf(l2i, sw, __builtin_fmaf(l2r, cw, sv2.x));
-                    l2i = __builtin_fmaf(l2i, cw, __builtin_fmaf(-l2r, sw, sv2.y));
-                    l2r = t2;
+            for (int k = 0; k < 16; ++k) {
+                const float2 sv = row[n0 + k];
+                float2 sv2;
+                if constexpr (TWO) sv2 = row2[n0 + k];
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) {
+                    const float tr = __builtin_fmaf(li[u], sw[u], __builtin_fmaf(lr[u], cw[u], sv.x));
+                    li[u] = __builtin_fmaf(li[u], cw[u], __builtin_fmaf(-lr[u], sw[u], sv.y));
+                    lr[u] = tr;
+                    if constexpr (TWO) {
+                        const float t2 = __builtin_fmaf(l2i[u], sw[u], __builtin_fmaf(l2r[u], cw[u], sv2.x));
+                        l2i[u] = __builtin_fmaf(l2i[u], cw[u], __builtin_fmaf(-l2r[u], sw[u], sv2.y));
+                        l2r[u] = t2;
+                    }
                 }
             }
         }
-        hr = __builtin_fmaf(lr, cw, __builtin_fmaf(li, sw, hr));
-        hi = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, hi));
-        float c0, s0;
-        seed_phasor<NAIVE>(geo, Km, c0, s0);      // exp(+j 2 pi theta_mid)
-        zr = __builtin_fmaf(c0, hr, __builtin_fmaf(-s0, hi, zr));
-        zi = __builtin_fmaf(c0, hi, __builtin_fmaf(s0, hr, zi));
-        if constexpr (TWO) {
-            h2r = __builtin_fmaf(l2r, cw, __builtin_fmaf(l2i, sw, h2r));
-            h2i = __builtin_fmaf(l2i, cw, __builtin_fmaf(-l2r, sw, h2i));
-            z2r = __builtin_fmaf(c0, h2r, __builtin_fmaf(-s0, h2i, z2r));
-            z2i = __builtin_fmaf(c0, h2i, __builtin_fmaf(s0, h2r, z2i));
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            const float Hr = __builtin_fmaf(lr[u], cw[u], __builtin_fmaf(li[u], sw[u], hr[u]));
+            const float Hi = __builtin_fmaf(li[u], cw[u], __builtin_fmaf(-lr[u], sw[u], hi[u]));
+            float c0, s0;
+            seed_phasor<NAIVE>(geo[u], Km, c0, s0);      // exp(+j 2 pi theta_mid)
+            zr[u] = __builtin_fmaf(c0, Hr, __builtin_fmaf(-s0, Hi, zr[u]));
+            zi[u] = __builtin_fmaf(c0, Hi, __builtin_fmaf(s0, Hr, zi[u]));
+            if constexpr (TWO) {
+                const float H2r = __builtin_fmaf(l2r[u], cw[u], __builtin_fmaf(l2i[u], sw[u], h2r[u]));
+                const float H2i = __builtin_fmaf(l2i[u], cw[u], __builtin_fmaf(-l2r[u], sw[u], h2i[u]));
+                z2r[u] = __builtin_fmaf(c0, H2r, __builtin_fmaf(-s0, H2i, z2r[u]));
+                z2i[u] = __builtin_fmaf(c0, H2i, __builtin_fmaf(s0, H2r, z2i[u]));
+            }
         }
     }
-    if (ok) {
-        if (z) z[q] = make_float2(zr, zi);
-        if (power) power[q] = sqrtf(zr * zr + zi * zi);
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        const long q = q0 + (long)u * blockDim.x;
+        if (q >= n_q) continue;
+        if (z) z[q] = make_float2(zr[u], zi[u]);
+        if (power) power[q] = sqrtf(zr[u] * zr[u] + zi[u] * zi[u]);
         if constexpr (TWO) {
-            if (z2) z2[q] = make_float2(z2r, z2i);
-            if (power2) power2[q] = sqrtf(z2r * z2r + z2i * z2i);
+            if (z2) z2[q] = make_float2(z2r[u], z2i[u]);
+            if (power2) power2[q] = sqrtf(z2r[u] * z2r[u] + z2i[u] * z2i[u]);
         }
     }
 }
@@ -94,7 +127,7 @@ __global__ __launch_bounds__(256) void k_mf_forward(
 hipError_t launch_mf_forward(const RenderGeom& g, const AntRec* ant, const float* xyz_q, long n_q,
                              const float2* sig_pad, const float2* sig2_pad, int np, uint32_t flags,
                              float2* z, float* power, float2* z2, float* power2, hipStream_t st) {
-    dim3 grid((unsigned)((n_q + 255) / 256));
+    dim3 grid((unsigned)((n_q + 256L * kHornerPPL - 1) / (256L * kHornerPPL)));
     const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
     if (sig2_pad) {
         if (naive)

@@ -160,6 +160,167 @@ hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, fl
 }
 
 // ---------------------------------------------------------------------------
+// importance sampling from the proposal's bin logits: one wave per ray, lane b
+// holds bin b (CDF by a wave scan), lane s produces slot s, ranks sort in place
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sample_importance(SampleArgs a, const float* __restrict__ logits,
+                                                           int n_bins, int n_imp, int n_uni,
+                                                           float* __restrict__ xyz, float* __restrict__ u_out,
+                                                           float* __restrict__ origin) {
+    const long n_ray = (long)a.n_rx * a.n_ry;
+    const long r = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= n_ray) return;                                    // uniform per wave
+    const int ix = (int)(r % a.n_rx), iy = (int)(r / a.n_rx);
+    const double lx = -a.h + (ix + 0.5) * 2.0 * a.h / a.n_rx;
+    const double ly = -a.h + (iy + 0.5) * 2.0 * a.h / a.n_ry;
+    double o[3];
+    for (int c = 0; c < 3; ++c) o[c] = a.base[c] + lx * a.e1[c] + ly * a.e2[c];
+    const double lo = a.lo, hi = a.lo + 2.0 * a.h;
+    // pdf and inclusive CDF over the bins, in FP64 so that the bin each level
+    // falls in is decided as a double-precision evaluation decides it
+    double p = 0.0;
+    if (lane < n_bins) p = 1.0 / (1.0 + exp(-(double)logits[r * n_bins + lane])) + 1e-3;
+    double cdf = p;
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_up(cdf, d, 64);
+        if (lane >= d) cdf += t;
+    }
+    const double total = __shfl(cdf, n_bins - 1, 64);
+    p /= total;
+    cdf /= total;
+    const int K = n_uni + n_imp;
+    double u = hi + 1.0;                                       // lanes >= K sort last
+    double xi = 0.0;
+    if (lane < K) {
+        const uint64_t v64 = sm64_output(a.key, (uint64_t)(r * K + lane));
+        xi = (double)(v64 >> 40) * (1.0 / 16777216.0);
+        if (lane < n_uni) u = lo + ((double)lane + xi) * (hi - lo) / n_uni;
+    }
+    // inverse CDF for importance slots (every lane joins the shuffles)
+    {
+        const double v = (lane >= n_uni && lane < K) ? ((double)(lane - n_uni) + xi) / n_imp : 0.0;
+        int b = 0;
+        for (int q = 0; q < n_bins; ++q) b += (__shfl(cdf, q, 64) <= v) ? 1 : 0;
+        if (b > n_bins - 1) b = n_bins - 1;
+        const double below = __shfl(cdf, b > 0 ? b - 1 : 0, 64);   // all lanes shuffle
+        const double prev = b > 0 ? below : 0.0;
+        const double pb = __shfl(p, b, 64);
+        const double frac = fmin(fmax((v - prev) / pb, 0.0), 1.0);
+        if (lane >= n_uni && lane < K) u = lo + ((double)b + frac) * ((hi - lo) / n_bins);
+    }
+    // rank = number of slots before this one in (u, slot) order
+    int rank = 0;
+    for (int t = 0; t < K; ++t) {
+        const double ut = __shfl(u, t, 64);
+        rank += (ut < u || (ut == u && t < lane)) ? 1 : 0;
+    }
+    if (lane < K) {
+        const long j = r * K + rank;
+        for (int c = 0; c < 3; ++c) xyz[3 * j + c] = (float)(o[c] + u * a.w[c]);
+        if (u_out) u_out[j] = (float)u;
+    }
+    if (origin && lane < 3) origin[3 * r + lane] = (float)o[lane];
+}
+
+hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basis[9], const float* logits,
+                                    int n_bins, int n_imp, int n_uni, float* xyz, float* u, float* origin,
+                                    hipStream_t st) {
+    SampleArgs a;
+    for (int c = 0; c < 3; ++c) {
+        a.e1[c] = basis[c];
+        a.e2[c] = basis[3 + c];
+        a.w[c] = basis[6 + c];
+    }
+    const double cx = d.centre[0], cy = d.centre[1], cz = d.centre[2];
+    const double cw = cx * a.w[0] + cy * a.w[1] + cz * a.w[2];
+    a.base[0] = cx - cw * a.w[0];
+    a.base[1] = cy - cw * a.w[1];
+    a.base[2] = cz - cw * a.w[2];
+    a.h = d.half_extent;
+    a.lo = cw - a.h;
+    a.n_rx = d.n_ray_x;
+    a.n_ry = d.n_ray_y;
+    a.n_z = n_imp + n_uni;
+    a.mode = 2;
+    auto mix = [](uint64_t z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    a.key = mix(d.seed + (d.step + 1ull) * 0x9E3779B97F4A7C15ull);
+    const long n_ray = (long)d.n_ray_x * d.n_ray_y;
+    hipLaunchKernelGGL(k_sample_importance, dim3((unsigned)((n_ray + 3) / 4)), dim3(256), 0, st, a, logits,
+                       n_bins, n_imp, n_uni, xyz, u, origin);
+    return hipGetLastError();
+}
+
+// proposal targets: bin the blend weights T alpha of each ray, normalise by the max
+__global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, const float* __restrict__ u,
+                                                          const float* __restrict__ alpha,
+                                                          const float* __restrict__ trans, float lo, float hi,
+                                                          int n_bins, float* __restrict__ targets) {
+    const long r = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= n_ray) return;
+    float w = 0.0f;
+    int bk = -1;
+    if (lane < n_k) {
+        const long j = r * n_k + lane;
+        w = trans[j] * alpha[j];
+        // bin decision in FP64, evaluated in the same order as a double-precision reference
+        int b = (int)floor(((double)u[j] - (double)lo) / ((double)hi - (double)lo) * (double)n_bins);
+        bk = b < 0 ? 0 : (b > n_bins - 1 ? n_bins - 1 : b);
+    }
+    float W = 0.0f;
+    for (int k = 0; k < n_k; ++k) {
+        const int bb = __shfl(bk, k, 64);
+        const float ww = __shfl(w, k, 64);
+        if (bb == lane) W += ww;
+    }
+    float mx = lane < n_bins ? W : 0.0f;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, 64));
+    if (lane < n_bins) targets[r * n_bins + lane] = fminf(1.0f, W / fmaxf(mx, 1e-3f));
+}
+
+hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
+                                   float lo, float hi, int n_bins, float* targets, hipStream_t st) {
+    hipLaunchKernelGGL(k_proposal_targets, dim3((unsigned)((n_ray + 3) / 4)), dim3(256), 0, st, n_ray, n_k, u,
+                       alpha, trans, lo, hi, n_bins, targets);
+    return hipGetLastError();
+}
+
+// BCE: per-block FP64 partials, fixed-order final
+__global__ __launch_bounds__(256) void k_bce_partial(long n, const float* __restrict__ z, const float* __restrict__ t,
+                                                     float* __restrict__ g, double* __restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const float inv_n = (float)(1.0 / (double)n);
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256) {
+        const float zq = z[q], tq = t[q];
+        const float spn = fmaxf(-zq, 0.0f) + log1pf(expf(-fabsf(zq)));   // softplus(-z)
+        const float spp = spn + zq;                                       // softplus(z)
+        acc += (double)(tq * spn + (1.0f - tq) * spp);
+        if (g) g[q] = (sigmoidf_(zq) - tq) * inv_n;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+hipError_t launch_bce(long n, const float* z, const float* t, float* loss, float* g, double* part, int nb,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_bce_partial, dim3(nb), dim3(256), 0, st, n, z, t, g, part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nb, n, loss);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // occupancy Phi = sigmoid(s f)
 // ---------------------------------------------------------------------------
 __global__ void k_occupancy(long n, float s, const float* __restrict__ f, float* __restrict__ phi) {

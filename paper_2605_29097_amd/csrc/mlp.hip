@@ -24,13 +24,22 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 enum { PRO_ID = 0, PRO_SP = 1, PRO_DSP_MUL = 2, PRO_RELU = 3 };
 enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2 };
 
+// Activation math of the network on the hardware exp2 / log2 / rcp units
+// (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once or twice per
+// GEMM operand element, where the correctly rounded library forms would
+// dominate the VALU time of the fused operand loads.
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float flog1p_pos(float e) {           // log(1 + e), e in [0, 1]
+    return __builtin_amdgcn_logf(1.0f + e) * 0.6931471805599453f;
+}
+__device__ __forceinline__ float fsig(float x) { return __builtin_amdgcn_rcpf(1.0f + fexp(-x)); }
 __device__ __forceinline__ float sp_f(float z, float beta) {
     const float bz = beta * z;
-    return (fmaxf(bz, 0.0f) + log1pf(expf(-fabsf(bz)))) / beta;
+    return fmaxf(z, 0.0f) + flog1p_pos(fexp(-fabsf(bz))) * __builtin_amdgcn_rcpf(beta);
 }
-__device__ __forceinline__ float sp_d1(float z, float beta) { return sigmoidf_(beta * z); }
+__device__ __forceinline__ float sp_d1(float z, float beta) { return fsig(beta * z); }
 __device__ __forceinline__ float sp_d2(float z, float beta) {
-    const float s = sigmoidf_(beta * z);
+    const float s = fsig(beta * z);
     return beta * s * (1.0f - s);
 }
 
@@ -49,10 +58,12 @@ __device__ __forceinline__ float4 prologue(float4 v, const float* a2, float beta
 }
 
 // ----------------------------------------------------------------------------
-// Y[P x M] = pro(A)[P x K] * B[M x K]^T  (+ epilogue).  K multiple of 16; A and
+// Y[P x M] = pro(A)[P x K] * B[M x K]^T  (+ epilogue).  K multiple of 32; A and
 // B rows hold K valid or zero-padded columns; lda/ldb multiples of 4.
-// Block 128 points x BM outputs, 4 waves, 16x16x4 MFMA tiles; the k index of
-// a lane's operand is permuted so each lane reads 4 consecutive k (one float4).
+// Block 128 points x BM outputs, 4 waves, 16x16x4 MFMA tiles, K chunks of 32
+// staged through LDS with the next chunk's global loads in flight during the
+// current chunk's MFMAs.  The k index of a lane's MFMA operand is permuted so
+// each lane reads 4 consecutive k (one float4) per 16-wide k group.
 // ----------------------------------------------------------------------------
 struct GemmArgs {
     const float* A; const float* A2; long lda;
@@ -67,61 +78,104 @@ struct GemmArgs {
 
 template <int PRO, int EPI, int BM>
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
-    constexpr int BP = 128, BK = 16, LW = BK + 4;
+    constexpr int BP = 128, BK = 32, LW = BK + 4;
     constexpr int WP = (BM == 128) ? 2 : 4;
     constexpr int WM = 4 / WP;
     constexpr int TP = BP / WP / 16;
     constexpr int TM = BM / WM / 16;
+    constexpr int NA = BP * BK / 4 / 256;       // float4 per thread, A
+    constexpr int NB = BM * BK / 4 / 256;       // float4 per thread, B
+    constexpr bool TWO = PRO == PRO_DSP_MUL;
     __shared__ float sA[BP * LW];
     __shared__ float sB[BM * LW];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wp = wv % WP, wm = wv / WP;
     const int li = lane & 15, lg = lane >> 4;
-    const long p0 = (long)blockIdx.x * BP;
-    const int m0 = blockIdx.y * BM;
+    // Work-groups are dispatched round-robin over the 8 XCDs (id % 8).  The
+    // column blocks of one point tile read the same A rows, so they are given
+    // ids b, b+8, ... : same XCD (same L2), consecutive in dispatch order.
+    const int nmb = (g.M + BM - 1) / BM;
+    const long bid = blockIdx.x;
+    const long grp = bid / (8L * nmb);
+    const int within = (int)(bid % (8L * nmb));
+    const int mb = within / 8;
+    const long pt = grp * 8 + (within % 8);
+    const long p0 = pt * BP;
+    const int m0 = mb * BM;
+    if (p0 >= g.P) return;                       // padding work-groups of the last group
     floatx4 acc[TP][TM];
 #pragma unroll
     for (int a = 0; a < TP; ++a)
 #pragma unroll
         for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    float4 ra[NA], ra2[TWO ? NA : 1], rb[NB];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + h * 256;
-            const int row = e >> 2, c4 = (e & 3) * 4;
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + i * 256;
+            const int row = e >> 3, c4 = (e & 7) * 4;
             const long p = p0 + row;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if constexpr (TWO) ra2[i] = ra[i];
             if (p < g.P) {
                 const long off = p * g.lda + k0 + c4;
-                v = *reinterpret_cast<const float4*>(g.A + off);
-                v = prologue<PRO>(v, PRO == PRO_DSP_MUL ? g.A2 + off : nullptr, g.beta);
+                ra[i] = *reinterpret_cast<const float4*>(g.A + off);
+                if constexpr (TWO) ra2[i] = *reinterpret_cast<const float4*>(g.A2 + off);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * 256;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            const int m = m0 + row;
+            rb[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (m < g.M) rb[i] = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + i * 256;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            float4 v = ra[i];
+            if constexpr (PRO == PRO_SP) {
+                v.x = sp_f(v.x, g.beta); v.y = sp_f(v.y, g.beta); v.z = sp_f(v.z, g.beta); v.w = sp_f(v.w, g.beta);
+            } else if constexpr (PRO == PRO_DSP_MUL) {
+                const float4 u = ra2[TWO ? i : 0];
+                v.x = sp_d1(v.x, g.beta) * u.x; v.y = sp_d1(v.y, g.beta) * u.y;
+                v.z = sp_d1(v.z, g.beta) * u.z; v.w = sp_d1(v.w, g.beta) * u.w;
+            } else if constexpr (PRO == PRO_RELU) {
+                v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
             *reinterpret_cast<float4*>(&sA[row * LW + c4]) = v;
         }
 #pragma unroll
-        for (int e = tid; e < BM * 4; e += 256) {
-            const int row = e >> 2, c4 = (e & 3) * 4;
-            const int m = m0 + row;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (m < g.M) v = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
-            *reinterpret_cast<float4*>(&sB[row * LW + c4]) = v;
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * 256;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            *reinterpret_cast<float4*>(&sB[row * LW + c4]) = rb[i];
         }
         __syncthreads();
-        floatx4 af[TP], bf[TM];
+        if (k0 + BK < g.K) load(k0 + BK);
 #pragma unroll
-        for (int a = 0; a < TP; ++a)
-            af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * (BP / WP) + a * 16 + li) * LW + lg * 4]);
-#pragma unroll
-        for (int b = 0; b < TM; ++b)
-            bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / WM) + b * 16 + li) * LW + lg * 4]);
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int kk = 0; kk < BK; kk += 16) {
+            floatx4 af[TP], bf[TM];
 #pragma unroll
             for (int a = 0; a < TP; ++a)
+                af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * (BP / WP) + a * 16 + li) * LW + kk + lg * 4]);
 #pragma unroll
-                for (int b = 0; b < TM; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < TM; ++b)
+                bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / WM) + b * 16 + li) * LW + kk + lg * 4]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < TP; ++a)
+#pragma unroll
+                    for (int b = 0; b < TM; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+        }
         __syncthreads();
     }
 #pragma unroll
@@ -146,27 +200,41 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 
 // ----------------------------------------------------------------------------
 // Weight gradient partials: part[split][M][Kout] = sum over the split's points
-// of A[p][m] * pro(B)[p][k].  Block 128 (m) x 128 (k), chunks of 16 points,
-// operands transposed into LDS so MFMA reads float4 along the point index.
+// of A[p][m] * pro(B)[p][k], and with BIAS also bpart[split][m] = sum_p A[p][m].
+// Block 128 (m) x 128 (k), chunks of 32 points kept point-major in LDS (float4
+// stores, scalar MFMA operand reads along the point index), next chunk's loads
+// in flight during the current chunk's MFMAs.
 // ----------------------------------------------------------------------------
 struct WgArgs {
     const float* A; long lda;                  // [P][lda], columns 0..M-1
     const float* B; const float* B2; long ldb; // [P][ldb], columns 0..Kout-1
     float* part;                               // [n_split][M][Kout]
+    float* bpart;                              // [n_split][M] (BIAS)
     long P; int M; int Kout; long per_split;
+    int n_split;
     float beta;
 };
 
-template <int PRO>
+template <int PRO, bool BIAS>
 __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
-    constexpr int BM = 128, BN = 128, BK = 16, LW = BK + 4;
-    __shared__ float sA[BM * LW];
-    __shared__ float sB[BN * LW];
+    constexpr int BM = 128, BN = 128, BK = 32, LW = 128 + 4;
+    constexpr bool TWO = PRO == PRO_DSP_MUL;
+    __shared__ float sA[BK * LW];
+    __shared__ float sB[BK * LW];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wp = wv % 2, wn = wv / 2;
     const int li = lane & 15, lg = lane >> 4;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const long split = blockIdx.z;
+    // the (m, n) blocks of one point split share operand rows: ids 8 apart,
+    // same XCD, consecutive in dispatch order
+    const int nmb = (g.M + BM - 1) / BM, nnb = (g.Kout + BN - 1) / BN;
+    const long bid = blockIdx.x;
+    const long grp = bid / (8L * nmb * nnb);
+    const int within = (int)(bid % (8L * nmb * nnb));
+    const int tile = within / 8;
+    const long split = grp * 8 + (within % 8);
+    if (split >= g.n_split) return;              // padding work-groups of the last group
+    const int m0 = (tile % nmb) * BM, n0 = (tile / nmb) * BN;
+    const bool first_n = (tile / nmb) == 0;
     const long pb = split * g.per_split;
     long pe = pb + g.per_split;
     if (pe > g.P) pe = g.P;
@@ -175,43 +243,74 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;                         // column sum of A (thread tid < 128 -> column tid)
 
-    const int row = tid >> 4;          // point within the chunk
-    const int c8 = (tid & 15) * 8;     // 8 consecutive columns
-    for (long q0 = pb; q0 < pe; q0 += BK) {
-        const long p = q0 + row;
+    float4 ra[4], rb[4], rb2[TWO ? 4 : 1];
+    auto load = [&](long q0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = c8 + 4 * h;
-            float4 va = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vb = va;
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * 256;
+            const int row = e >> 5, c4 = (e & 31) * 4;
+            const long p = q0 + row;
+            ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rb[i] = ra[i];
+            if constexpr (TWO) rb2[i] = ra[i];
             if (p < pe) {
-                if (m0 + c < g.M) va = *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c);
-                if (n0 + c < g.Kout) {
-                    const long off = p * g.ldb + n0 + c;
-                    vb = *reinterpret_cast<const float4*>(g.B + off);
-                    vb = prologue<PRO>(vb, PRO == PRO_DSP_MUL ? g.B2 + off : nullptr, g.beta);
+                if (m0 + c4 < g.M) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c4);
+                if (n0 + c4 < g.Kout) {
+                    const long off = p * g.ldb + n0 + c4;
+                    rb[i] = *reinterpret_cast<const float4*>(g.B + off);
+                    if constexpr (TWO) rb2[i] = *reinterpret_cast<const float4*>(g.B2 + off);
                 }
             }
-            sA[(c + 0) * LW + row] = va.x; sA[(c + 1) * LW + row] = va.y;
-            sA[(c + 2) * LW + row] = va.z; sA[(c + 3) * LW + row] = va.w;
-            sB[(c + 0) * LW + row] = vb.x; sB[(c + 1) * LW + row] = vb.y;
-            sB[(c + 2) * LW + row] = vb.z; sB[(c + 3) * LW + row] = vb.w;
+        }
+    };
+    if (pb < pe) load(pb);
+    for (long q0 = pb; q0 < pe; q0 += BK) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * 256;
+            const int row = e >> 5, c4 = (e & 31) * 4;
+            const bool live = q0 + row < pe;
+            float4 v = rb[i];
+            if constexpr (PRO == PRO_SP) {
+                v.x = sp_f(v.x, g.beta); v.y = sp_f(v.y, g.beta); v.z = sp_f(v.z, g.beta); v.w = sp_f(v.w, g.beta);
+            } else if constexpr (PRO == PRO_DSP_MUL) {
+                const float4 u = rb2[TWO ? i : 0];
+                v.x = sp_d1(v.x, g.beta) * u.x; v.y = sp_d1(v.y, g.beta) * u.y;
+                v.z = sp_d1(v.z, g.beta) * u.z; v.w = sp_d1(v.w, g.beta) * u.w;
+            } else if constexpr (PRO == PRO_RELU) {
+                v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
+            }
+            if (!live) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            *reinterpret_cast<float4*>(&sA[row * LW + c4]) = ra[i];
+            *reinterpret_cast<float4*>(&sB[row * LW + c4]) = v;
         }
         __syncthreads();
-        floatx4 af[4], bf[4];
+        if (q0 + BK < pe) load(q0 + BK);
+        if constexpr (BIAS) {
+            if (first_n && tid < BM) {
+#pragma unroll 8
+                for (int r = 0; r < BK; ++r) bsum += sA[r * LW + tid];
+            }
+        }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-            af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * 64 + a * 16 + li) * LW + lg * 4]);
+        for (int kk = 0; kk < BK; kk += 16) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wn * 64 + b * 16 + li) * LW + lg * 4]);
+            for (int s = 0; s < 4; ++s) {
+                const int r = kk + lg * 4 + s;
+                float af[4], bf[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+                for (int a = 0; a < 4; ++a) af[a] = sA[r * LW + wp * 64 + a * 16 + li];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) bf[b] = sB[r * LW + wn * 64 + b * 16 + li];
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+            }
+        }
         __syncthreads();
     }
     float* out = g.part + split * (long)g.M * g.Kout;
@@ -227,6 +326,9 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
                 if (m < g.M) out[(long)m * g.Kout + k] = acc[a][b][v];
             }
         }
+    if constexpr (BIAS) {
+        if (first_n && tid < BM && m0 + tid < g.M) g.bpart[split * (long)g.M + m0 + tid] = bsum;
+    }
 }
 
 // dst[m][k] (row stride k_real, k < k_real) (+)= sum_s part[s][m][k]
@@ -256,6 +358,7 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
     long re = rb + rows_per;
     if (re > P) re = P;
     float acc = 0.0f;
+#pragma unroll 8
     for (long p = rb; p < re; ++p) {
         const float x = X[p * ldx + m];
         float d;
@@ -410,7 +513,7 @@ __global__ void k_layer_adjoint(long n, int M, long ld, const float* __restrict_
     const long p = o / M;
     const long e = p * ld + (o % M);
     const float z = Z[e];
-    const float s = sigmoidf_(beta * z);
+    const float s = fsig(beta * z);
     const float d2 = beta * s * (1.0f - s);
     const float hdb = Hdb[e];
     Zb[e] = s * Hb[e] + d2 * Zd[e] * hdb;
@@ -446,7 +549,7 @@ namespace {
 
 constexpr long kChunk = 1 << 18;          // points per pass (bounds the workspace)
 constexpr int kWgSplits = 128;            // weight-gradient point splits per pass
-constexpr int kColBlocks = 256;           // column-sum partial blocks
+constexpr int kColBlocks = 2048;          // column-sum partial blocks
 
 struct Layout {
     int L, W, in0, in0p, HL, HW;
@@ -462,8 +565,8 @@ int check_net(const rfvr_mlp* n) {
                   "head 1..4 x 64..256 step 64)");
         return RFVR_E_INVALID;
     }
-    if ((3 + 6 * n->pe_octaves + 15) / 16 * 16 > n->width) {
-        set_error("encoding width (3 + 6 * pe_octaves, padded to 16) must not exceed the layer width");
+    if ((3 + 6 * n->pe_octaves + 31) / 32 * 32 > n->width) {
+        set_error("encoding width (3 + 6 * pe_octaves, padded to 32) must not exceed the layer width");
         return RFVR_E_INVALID;
     }
     if (!(n->softplus_beta > 0.0f) || !(n->half_size > 0.0f) || n->softplus_beta != n->softplus_beta) {
@@ -481,7 +584,7 @@ Layout layout(const rfvr_mlp* n) {
     Layout l;
     l.L = n->n_layers; l.W = n->width; l.HL = n->head_layers; l.HW = n->head_width;
     l.in0 = 3 + 6 * n->pe_octaves;
-    l.in0p = (l.in0 + 15) / 16 * 16;
+    l.in0p = (l.in0 + 31) / 32 * 32;
     long off = 0;
     for (int i = 0; i < l.L; ++i) {
         const int fin = i == 0 ? l.in0 : l.W;
@@ -552,12 +655,14 @@ hipError_t prep_weights(const Layout& l, const float* P, const Weights& w, hipSt
 
 template <int PRO, int EPI>
 void gemm(const GemmArgs& a, hipStream_t st) {
-    const unsigned gx = blocks(a.P, 128);
+    const long tiles = (a.P + 127) / 128;
+    const long groups = (tiles + 7) / 8;                 // 8 point tiles per XCD group
     if (a.M <= 64) {
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64>), dim3(gx, 1), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128>), dim3(gx, (unsigned)((a.M + 127) / 128)),
-                           dim3(256), 0, st, a);
+        const long nmb = (a.M + 127) / 128;
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
+                           st, a);
     }
 }
 
@@ -572,12 +677,29 @@ GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb,
 
 template <int PRO>
 void wgrad(const float* A, long lda, int M, const float* B, const float* B2, long ldb, int Kout,
-           long P, float beta, float* part, hipStream_t st) {
+           long P, float beta, float* part, hipStream_t st, float* bpart = nullptr) {
     WgArgs g;
-    g.A = A; g.lda = lda; g.B = B; g.B2 = B2; g.ldb = ldb; g.part = part; g.P = P; g.M = M;
-    g.Kout = Kout; g.per_split = ((P + kWgSplits - 1) / kWgSplits + 15) / 16 * 16; g.beta = beta;
-    hipLaunchKernelGGL((k_gemm_wg<PRO>), dim3((M + 127) / 128, (Kout + 127) / 128, kWgSplits),
-                       dim3(256), 0, st, g);
+    g.A = A; g.lda = lda; g.B = B; g.B2 = B2; g.ldb = ldb; g.part = part; g.bpart = bpart; g.P = P;
+    g.M = M; g.Kout = Kout; g.per_split = ((P + kWgSplits - 1) / kWgSplits + 31) / 32 * 32;
+    g.n_split = kWgSplits;
+    g.beta = beta;
+    const long tiles = (long)((M + 127) / 128) * ((Kout + 127) / 128);
+    const long groups = (kWgSplits + 7) / 8;
+    const dim3 grid((unsigned)(groups * 8 * tiles));
+    if (bpart)
+        hipLaunchKernelGGL((k_gemm_wg<PRO, true>), grid, dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((k_gemm_wg<PRO, false>), grid, dim3(256), 0, st, g);
+}
+
+// dst[m] (+)= sum_s bpart[s][m]
+__global__ void k_bias_reduce(const float* __restrict__ bpart, int n_split, int M,
+                              float* __restrict__ dst, int accumulate) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    float s = 0.0f;
+    for (int t = 0; t < n_split; ++t) s += bpart[(long)t * M + m];
+    dst[m] = accumulate ? dst[m] + s : s;
 }
 
 void wg_reduce(const float* part, int n_split, int M, int Kout, int k_real, float* dst, int acc,
@@ -614,6 +736,7 @@ size_t bwd_bytes(const Layout& l, long n) {
            align256(sizeof(float) * c * l.HW) +                     // scratch head adjoint
            align256(sizeof(float) * c) +                            // ybar3
            align256(sizeof(float) * 2 * kWgSplits * (size_t)l.W * wmax) +
+           align256(sizeof(float) * kWgSplits * (size_t)l.W) +
            align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
 }
 
@@ -748,6 +871,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
     float* Rtmp = cur.take<float>((size_t)chunk * l.HW);
     float* yb3 = cur.take<float>((size_t)chunk);
     float* part = cur.take<float>((size_t)2 * kWgSplits * l.W * wmax);
+    float* bpart = cur.take<float>((size_t)kWgSplits * l.W);
     float* cpart = cur.take<float>((size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
     if ((rc = hip_status(prep_weights(l, P, w, st), "mlp weight prep"))) return rc;
 
@@ -782,15 +906,17 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         for (int h = l.HL - 1; h >= 0; --h) {
             float* Yb = Ybh[h];
             if (h > 0) {
-                wgrad<PRO_RELU>(Yb, l.HW, l.HW, Yh[h - 1], nullptr, l.HW, l.HW, m, beta, part, st);
+                wgrad<PRO_RELU>(Yb, l.HW, l.HW, Yh[h - 1], nullptr, l.HW, l.HW, m, beta, part, st, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.HW, l.HW, GP + l.oWh[h], acc, st);
-                colsum(Yb, nullptr, nullptr, l.HW, m, l.HW, 0, beta, 1.0f, cpart, GP + l.obh[h], acc, st);
+                hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
+                                   l.HW, GP + l.obh[h], acc);
                 // Ybar_{h-1} = (Ybar_h Wh_h) . relu'(Y_{h-1})
                 gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), st);
             } else {
-                wgrad<PRO_SP>(Yb, l.HW, l.HW, Zt, nullptr, l.W, l.W, m, beta, part, st);
+                wgrad<PRO_SP>(Yb, l.HW, l.HW, Zt, nullptr, l.W, l.W, m, beta, part, st, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.W, l.W, GP + l.oWh[0], acc, st);
-                colsum(Yb, nullptr, nullptr, l.HW, m, l.HW, 0, beta, 1.0f, cpart, GP + l.obh[0], acc, st);
+                hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
+                                   l.HW, GP + l.obh[0], acc);
             }
         }
         // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0, Hdot_bar = half w_out
@@ -807,16 +933,17 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                                Z[i], Zd[i], Hb, Hdb, beta, Zb, Zdb);
             const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
             if (i == 0) {
-                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, st);
+                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, st, bpart);
                 wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
                               part + (size_t)kWgSplits * l.W * finp, st);
             } else {
-                wgrad<PRO_SP>(Zb, l.W, l.W, Z[i - 1], nullptr, l.W, finp, m, beta, part, st);
+                wgrad<PRO_SP>(Zb, l.W, l.W, Z[i - 1], nullptr, l.W, finp, m, beta, part, st, bpart);
                 wgrad<PRO_DSP_MUL>(Zdb, l.W, l.W, Z[i - 1], Zd[i - 1], l.W, finp, m, beta,
                                    part + (size_t)kWgSplits * l.W * finp, st);
             }
             wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st);
-            colsum(Zb, nullptr, nullptr, l.W, m, l.W, 0, beta, 1.0f, cpart, GP + l.ob[i], acc, st);
+            hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,
+                               GP + l.ob[i], acc);
             if (i > 0) {
                 gemm<PRO_ID, EPI_BIAS>(ga(Zb, nullptr, l.W, w.WT[i], l.W, nullptr, Hb, l.W, m, l.W, l.W, beta), st);
                 gemm<PRO_ID, EPI_BIAS>(ga(Zdb, nullptr, l.W, w.WT[i], l.W, nullptr, Hdb, l.W, m, l.W, l.W, beta), st);
@@ -825,6 +952,182 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         if ((rc = hip_status(hipGetLastError(), "mlp backward"))) return rc;
     }
     return RFVR_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// proposal network: gamma_L -> [Linear(width) -> relu] x layers -> Linear(1)
+// ============================================================================
+namespace rfvr {
+namespace {
+
+struct PLayout {
+    int L, W, in0, in0p, layers;
+    long oW[4], ob[4], o_wout, o_bout, total;
+};
+
+int check_prop(const rfvr_proposal* n) {
+    if (!n) { set_error("proposal descriptor is NULL"); return RFVR_E_INVALID; }
+    if (n->width != 64 || n->layers < 1 || n->layers > 4 || n->pe_octaves < 0 || n->pe_octaves > 5) {
+        set_error("unsupported proposal network (width 64, layers 1..4, pe_octaves 0..5)");
+        return RFVR_E_INVALID;
+    }
+    if (!(n->half_size > 0.0f)) { set_error("half_size must be > 0"); return RFVR_E_INVALID; }
+    return RFVR_OK;
+}
+
+PLayout playout(const rfvr_proposal* n) {
+    PLayout l;
+    l.L = n->pe_octaves; l.W = n->width; l.layers = n->layers;
+    l.in0 = 3 + 6 * l.L;
+    l.in0p = (l.in0 + 31) / 32 * 32;
+    long off = 0;
+    for (int i = 0; i < l.layers; ++i) {
+        const int fin = i == 0 ? l.in0 : l.W;
+        l.oW[i] = off; off += (long)l.W * fin;
+        l.ob[i] = off; off += l.W;
+    }
+    l.o_wout = off; off += l.W;
+    l.o_bout = off; off += 1;
+    l.total = off;
+    return l;
+}
+
+size_t pweights_bytes(const PLayout& l) {
+    size_t b = 0;
+    for (int i = 0; i < l.layers; ++i) b += 2 * align256(sizeof(float) * (i == 0 ? l.in0p : l.W) * l.W);
+    return b;
+}
+
+size_t pbytes(const PLayout& l, long n, bool bwd) {
+    const long c = n < kChunk ? n : kChunk;
+    size_t b = pweights_bytes(l) + align256(sizeof(float) * c * l.in0p) +
+               (size_t)l.layers * align256(sizeof(float) * c * l.W);
+    if (bwd)
+        b += 2 * align256(sizeof(float) * c * l.W) + align256(sizeof(float) * kWgSplits * (size_t)l.W * l.W) +
+             align256(sizeof(float) * kWgSplits * (size_t)l.W) + align256(sizeof(float) * (size_t)kColBlocks * l.W);
+    return b;
+}
+
+// Abar[p][m] = g[p] w[m] relu'(A[p][m])
+__global__ void k_relu_out_bwd(long n, int M, const float* __restrict__ A, long ld, const float* __restrict__ w,
+                               const float* __restrict__ g, float* __restrict__ Ab) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n * M) return;
+    const long p = o / M;
+    const int m = (int)(o % M);
+    Ab[p * ld + m] = A[p * ld + m] > 0.0f ? g[p] * w[m] : 0.0f;
+}
+
+}  // namespace
+}  // namespace rfvr
+
+extern "C" {
+
+int64_t rfvr_proposal_param_count(const rfvr_proposal* net) {
+    if (check_prop(net)) return -1;
+    return playout(net).total;
+}
+
+size_t rfvr_proposal_ws_bytes(const rfvr_proposal* net, int64_t n) {
+    if (check_prop(net) || n < 1) return 0;
+    return pbytes(playout(net), (long)n, true);
+}
+
+static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, float* logits,
+                         const float* g_logits, uint32_t flags, float* g_params, void* ws,
+                         size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_prop(net))) return rc;
+    if (n < 1 || !xyz || !net->params) { set_error("n >= 1, xyz and params are required"); return RFVR_E_INVALID; }
+    const bool bwd = g_params != nullptr;
+    if (bwd && !g_logits) { set_error("g_logits is required"); return RFVR_E_INVALID; }
+    if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }
+    const PLayout l = playout(net);
+    const size_t need = pbytes(l, (long)n, bwd);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("workspace too small or misaligned: need %zu bytes", need);
+        return RFVR_E_WORKSPACE;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float* P = net->params;
+    const long chunk = n < kChunk ? (long)n : kChunk;
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    float *Wp[4], *WT[4];
+    for (int i = 0; i < l.layers; ++i) {
+        Wp[i] = cur.take<float>((size_t)(i == 0 ? l.in0p : l.W) * l.W);
+        WT[i] = cur.take<float>((size_t)(i == 0 ? l.in0p : l.W) * l.W);
+    }
+    float* X0 = cur.take<float>((size_t)chunk * l.in0p);
+    float* A[4];
+    for (int i = 0; i < l.layers; ++i) A[i] = cur.take<float>((size_t)chunk * l.W);
+    float *Ab = nullptr, *Ab2 = nullptr, *part = nullptr, *bpart = nullptr, *cpart = nullptr;
+    if (bwd) {
+        Ab = cur.take<float>((size_t)chunk * l.W);
+        Ab2 = cur.take<float>((size_t)chunk * l.W);
+        part = cur.take<float>((size_t)kWgSplits * l.W * l.W);
+        bpart = cur.take<float>((size_t)kWgSplits * l.W);
+        cpart = cur.take<float>((size_t)kColBlocks * l.W);
+    }
+    for (int i = 0; i < l.layers; ++i) {
+        const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
+        hipLaunchKernelGGL(k_pad_cols, dim3(blocks((long)l.W * finp)), dim3(256), 0, st, P + l.oW[i], l.W,
+                           fin, finp, Wp[i]);
+        hipLaunchKernelGGL(k_transpose_pad, dim3(blocks((long)l.W * finp)), dim3(256), 0, st, P + l.oW[i],
+                           l.W, fin, l.W, finp, WT[i]);
+    }
+    const float beta = 1.0f, inv_half = 1.0f / net->half_size;
+    for (long c0 = 0; c0 < n; c0 += chunk) {
+        const long m = (n - c0) < chunk ? (n - c0) : chunk;
+        const int acc = (c0 > 0 || (flags & RFVR_ACCUMULATE)) ? 1 : 0;
+        hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, xyz + 3 * c0, net->centre[0],
+                           net->centre[1], net->centre[2], inv_half, l.L, l.in0p, X0, nullptr, nullptr);
+        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, Wp[0], l.in0p, P + l.ob[0], A[0], l.W, m, l.W, l.in0p, beta), st);
+        for (int i = 1; i < l.layers; ++i)
+            gemm<PRO_RELU, EPI_BIAS>(ga(A[i - 1], nullptr, l.W, Wp[i], l.W, P + l.ob[i], A[i], l.W, m, l.W, l.W, beta), st);
+        float* At = A[l.layers - 1];
+        if (!bwd) {
+            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, At, (long)l.W, l.W,
+                               (int)PRO_RELU, 0, P + l.o_wout, P + l.o_bout, 1.0f, beta, logits + c0);
+        } else {
+            const float* g = g_logits + c0;
+            colsum(At, nullptr, g, l.W, m, l.W, 1, beta, 1.0f, cpart, g_params + l.o_wout, acc, st);
+            colsum(g, nullptr, nullptr, 1, m, 1, 0, beta, 1.0f, cpart, g_params + l.o_bout, acc, st);
+            hipLaunchKernelGGL(k_relu_out_bwd, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, At, (long)l.W,
+                               P + l.o_wout, g, Ab);
+            for (int i = l.layers - 1; i >= 0; --i) {
+                const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
+                if (i == 0)
+                    wgrad<PRO_ID>(Ab, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, st, bpart);
+                else
+                    wgrad<PRO_RELU>(Ab, l.W, l.W, A[i - 1], nullptr, l.W, finp, m, beta, part, st, bpart);
+                wg_reduce(part, kWgSplits, l.W, finp, fin, g_params + l.oW[i], acc, st);
+                hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,
+                                   g_params + l.ob[i], acc);
+                if (i > 0) {
+                    gemm<PRO_ID, EPI_RELUMASK>(ga(Ab, nullptr, l.W, WT[i], l.W, nullptr, Ab2, l.W, m, l.W, l.W,
+                                                  beta, A[i - 1], l.W), st);
+                    float* t = Ab; Ab = Ab2; Ab2 = t;
+                }
+            }
+        }
+        if ((rc = hip_status(hipGetLastError(), "proposal network"))) return rc;
+    }
+    return RFVR_OK;
+}
+
+int rfvr_proposal_forward(const rfvr_proposal* net, const float* xyz, int64_t n, float* logits,
+                          void* ws, size_t ws_bytes, void* stream) {
+    if (!logits) { set_error("logits output is NULL"); return RFVR_E_INVALID; }
+    return proposal_pass(net, xyz, n, logits, nullptr, 0, nullptr, ws, ws_bytes, stream);
+}
+
+int rfvr_proposal_backward(const rfvr_proposal* net, const float* xyz, int64_t n,
+                           const float* g_logits, uint32_t flags, float* g_params,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (!g_params) { set_error("g_params output is NULL"); return RFVR_E_INVALID; }
+    return proposal_pass(net, xyz, n, nullptr, g_logits, flags, g_params, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -146,6 +146,10 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
 // adjoint (KIND 1).  Lane t -> measurement i = t % n_meas, chunk c = t / n_meas;
 // grid.y = point split.
 // ---------------------------------------------------------------------------
+#ifndef RFVR_RP_ACCURATE_STEP
+#define RFVR_RP_ACCURATE_STEP 1
+#endif
+
 template <int F, int KIND, int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_reduce_points(
     int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
@@ -153,6 +157,13 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     float2* __restrict__ partial) {
     constexpr int S = F < 16 ? F : 16;           // re-seed interval
     constexpr int NS = F / S;
+    // point records of the block's split are staged through LDS in tiles of
+    // TILE, shared by the 4 waves; the next tile is fetched into registers
+    // while the current one is consumed
+    constexpr int TILE = 64;
+    constexpr int RB = KIND == 0 ? (int)sizeof(PtRec) : (int)sizeof(QRec);
+    constexpr int V4 = TILE * RB / 16;           // float4 per tile (192 or 128)
+    __shared__ float4 sRec[2][V4];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int i = t % n_meas;
     int c = t / n_meas;
@@ -172,64 +183,88 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     const long j0 = (long)blockIdx.y * pts_per_split;
     long j1 = j0 + pts_per_split;
     if (j1 > n_pts) j1 = n_pts;
-
-    for (long j = j0; j < j1; ++j) {
-        float wr, wi, cr, ci;          // step phasor, complex weight of the pair
-        PairGeom g;
-        if constexpr (KIND == 0) {
-            const PtRec P = reinterpret_cast<const PtRec*>(recs_v)[j];
-            const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
-            g = pair_geom<NAIVE>(dx, dy, dz);
-            float spec, live;
-            if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
-                spec = 1.0f;
+    const float4* src = reinterpret_cast<const float4*>(recs_v);
+    const int tid = threadIdx.x;
+    // tile loader: element v of tile starting at jt (zero beyond j1)
+    auto fetch = [&](long jt) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const long e = jt * (RB / 16) + tid;
+        if (tid < V4 && e < j1 * (RB / 16)) v = src[e];
+        return v;
+    };
+    float4 pre = fetch(j0);
+    int buf = 0;
+    for (long jt = j0; jt < j1; jt += TILE) {
+        if (tid < V4) sRec[buf][tid] = pre;
+        __syncthreads();
+        if (jt + TILE < j1) pre = fetch(jt + TILE);
+        const int cnt = (j1 - jt) < TILE ? (int)(j1 - jt) : TILE;
+        for (int k = 0; k < cnt; ++k) {
+            float wr, wi, cr, ci;          // step phasor, complex weight of the pair
+            PairGeom g;
+            if constexpr (KIND == 0) {
+                const PtRec P = reinterpret_cast<const PtRec*>(sRec[buf])[k];
+                const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
+                g = pair_geom<NAIVE>(dx, dy, dz);
+                float spec, live;
+                if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                    spec = 1.0f;
+                } else {
+                    float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * g.y;
+                    spec_factor<SPEC>(nd, spec, live);
+                }
+                const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
+                cr = P.b * spec * (T * T) * (g.y * g.y);
+                ci = 0.0f;
             } else {
-                float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * g.y;
-                spec_factor<SPEC>(nd, spec, live);
+                const QRec Q = reinterpret_cast<const QRec*>(sRec[buf])[k];
+                const double dx = Q.x - A.x, dy = Q.y - A.y, dz = Q.z - A.z;
+                g = pair_geom<NAIVE>(dx, dy, dz);
+                cr = Q.hr;
+                ci = Q.hi;
             }
-            const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
-            cr = P.b * spec * (T * T) * (g.y * g.y);
-            ci = 0.0f;
-        } else {
-            const QRec Q = reinterpret_cast<const QRec*>(recs_v)[j];
-            const double dx = Q.x - A.x, dy = Q.y - A.y, dz = Q.z - A.z;
-            g = pair_geom<NAIVE>(dx, dy, dz);
-            cr = Q.hr;
-            ci = Q.hi;
-        }
-        {
-            float cw, sw;
-            step_phasor<NAIVE>(g, Kd, cw, sw);
-            wr = cw;
-            wi = -sw;                  // exp(-j 2 pi delta)
-        }
-#pragma unroll
-        for (int m = 0; m < NS; ++m) {
-            float c0, s0;
-            seed_phasor<NAIVE>(g, Kc[m], c0, s0);
-            // (cr + j ci) * exp(-j 2 pi theta_centre)
-            const float pr0 = __builtin_fmaf(cr, c0, ci * s0);
-            const float pi0 = __builtin_fmaf(ci, c0, -cr * s0);
-            float pr = pr0, pi = pi0;
-#pragma unroll
-            for (int u = S / 2; u < S; ++u) {
-                ar[m * S + u] += pr;
-                ai[m * S + u] += pi;
-                const float tr = __builtin_fmaf(pr, wr, -pi * wi);
-                pi = __builtin_fmaf(pr, wi, pi * wr);
-                pr = tr;
+            {
+                float cw, sw;
+                if constexpr (RFVR_RP_ACCURATE_STEP || NAIVE) {
+                    step_phasor<NAIVE>(g, Kd, cw, sw);
+                } else {
+                    const float de = (float)(g.r * Kd);
+                    cw = cos_rev(de);
+                    sw = sin_rev(de);
+                }
+                wr = cw;
+                wi = -sw;                  // exp(-j 2 pi delta)
             }
-            pr = pr0;
-            pi = pi0;
 #pragma unroll
-            for (int u = S / 2 - 1; u >= 0; --u) {
-                const float tr = __builtin_fmaf(pr, wr, pi * wi);     // times conj(w)
-                pi = __builtin_fmaf(pi, wr, -pr * wi);
-                pr = tr;
-                ar[m * S + u] += pr;
-                ai[m * S + u] += pi;
+            for (int m = 0; m < NS; ++m) {
+                float c0, s0;
+                seed_phasor<NAIVE>(g, Kc[m], c0, s0);
+                // (cr + j ci) * exp(-j 2 pi theta_centre)
+                const float pr0 = __builtin_fmaf(cr, c0, ci * s0);
+                const float pi0 = __builtin_fmaf(ci, c0, -cr * s0);
+                float pr = pr0, pi = pi0;
+#pragma unroll
+                for (int u = S / 2; u < S; ++u) {
+                    ar[m * S + u] += pr;
+                    ai[m * S + u] += pi;
+                    const float tr = __builtin_fmaf(pr, wr, -pi * wi);
+                    pi = __builtin_fmaf(pr, wi, pi * wr);
+                    pr = tr;
+                }
+                pr = pr0;
+                pi = pi0;
+#pragma unroll
+                for (int u = S / 2 - 1; u >= 0; --u) {
+                    const float tr = __builtin_fmaf(pr, wr, pi * wi);     // times conj(w)
+                    pi = __builtin_fmaf(pi, wr, -pr * wi);
+                    pr = tr;
+                    ar[m * S + u] += pr;
+                    ai[m * S + u] += pi;
+                }
             }
         }
+        __syncthreads();
+        buf ^= 1;
     }
     if (live_lane) {
         float2* out = partial + ((size_t)blockIdx.y * n_meas + i) * n_freq + (size_t)c * F;
@@ -333,81 +368,112 @@ hipError_t launch_pad_signal(const float2* sig, int n_meas, int n_freq, int np, 
 // signal tracing adjoint: one lane per point, Horner over the frequencies of
 // each measurement's gradient row (scalar loads), chain rule per pair.
 // ---------------------------------------------------------------------------
+#ifndef RFVR_HORNER_PPL
+#define RFVR_HORNER_PPL 1
+#endif
+constexpr int kBwdPPL = RFVR_HORNER_PPL;      // points per lane
+
 template <int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_render_bwd_points(
     long n_pts, const PtRec* __restrict__ rec, int n_meas, const AntRec* __restrict__ ant,
     const float2* __restrict__ gsig, int np, double K0, double Kd, float* __restrict__ g_b,
     float* __restrict__ g_T, float* __restrict__ g_n) {
-    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = j < n_pts;
-    const PtRec P = rec[ok ? j : n_pts - 1];
+    constexpr int PPL = kBwdPPL;
+    const long j0 = (long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
+    PtRec P[PPL];
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        long j = j0 + (long)u * blockDim.x;
+        P[u] = rec[j < n_pts ? j : n_pts - 1];
+    }
     const int mid = np / 2;                        // multiple of 16
     const double Km = K0 + (double)mid * Kd;
-    float gb = 0.0f, gt = 0.0f, gn0 = 0.0f, gn1 = 0.0f, gn2 = 0.0f;
+    float gb[PPL], gt[PPL], gn0[PPL], gn1[PPL], gn2[PPL];
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) gb[u] = gt[u] = gn0[u] = gn1[u] = gn2[u] = 0.0f;
     for (int i = 0; i < n_meas; ++i) {
         const AntRec A = ant[i];
-        const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
-        const PairGeom geo = pair_geom<NAIVE>(dx, dy, dz);
-        float cw, sw;
-        step_phasor<NAIVE>(geo, Kd, cw, sw);       // w = exp(+j 2 pi delta)
+        PairGeom geo[PPL];
+        float cw[PPL], sw[PPL];
+        double dx[PPL], dy[PPL], dz[PPL];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            dx[u] = P[u].x - A.x; dy[u] = P[u].y - A.y; dz[u] = P[u].z - A.z;
+            geo[u] = pair_geom<NAIVE>(dx[u], dy[u], dz[u]);
+            step_phasor<NAIVE>(geo[u], Kd, cw[u], sw[u]);       // w = exp(+j 2 pi delta)
+        }
         const float2* g = gsig + (size_t)i * np;
         // H = sum_n g[n] w^(n - mid): upper half by Horner in w from the top,
         // lower half by Horner in conj(w) from the bottom
-        float hr = 0.0f, hi = 0.0f, lr = 0.0f, li = 0.0f;
+        float hr[PPL], hi[PPL], lr[PPL], li[PPL];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) hr[u] = hi[u] = lr[u] = li[u] = 0.0f;
         for (int n0 = np - 16; n0 >= mid; n0 -= 16) {
 #pragma unroll
-            for (int u = 15; u >= 0; --u) {
-                const float2 gv = g[n0 + u];
-                const float tr = __builtin_fmaf(-hi, sw, __builtin_fmaf(hr, cw, gv.x));
-                hi = __builtin_fmaf(hi, cw, __builtin_fmaf(hr, sw, gv.y));
-                hr = tr;
+            for (int k = 15; k >= 0; --k) {
+                const float2 gv = g[n0 + k];
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) {
+                    const float tr = __builtin_fmaf(-hi[u], sw[u], __builtin_fmaf(hr[u], cw[u], gv.x));
+                    hi[u] = __builtin_fmaf(hi[u], cw[u], __builtin_fmaf(hr[u], sw[u], gv.y));
+                    hr[u] = tr;
+                }
             }
         }
         for (int n0 = 0; n0 < mid; n0 += 16) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const float2 gv = g[n0 + u];
-                const float tr = __builtin_fmaf(li, sw, __builtin_fmaf(lr, cw, gv.x));
-                li = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, gv.y));
-                lr = tr;
+            for (int k = 0; k < 16; ++k) {
+                const float2 gv = g[n0 + k];
+#pragma unroll
+                for (int u = 0; u < PPL; ++u) {
+                    const float tr = __builtin_fmaf(li[u], sw[u], __builtin_fmaf(lr[u], cw[u], gv.x));
+                    li[u] = __builtin_fmaf(li[u], cw[u], __builtin_fmaf(-lr[u], sw[u], gv.y));
+                    lr[u] = tr;
+                }
             }
         }
-        // H = Hup + conj(w) * Hlow
-        hr = __builtin_fmaf(lr, cw, __builtin_fmaf(li, sw, hr));
-        hi = __builtin_fmaf(li, cw, __builtin_fmaf(-lr, sw, hi));
-        float c0, s0;
-        seed_phasor<NAIVE>(geo, Km, c0, s0);
-        const float G = c0 * hr - s0 * hi;       // Re(exp(+j 2 pi theta_mid) H)
-        const float y = geo.y;
-        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-        float spec, live = 0.0f;
-        float nd = 0.0f;
-        if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
-            spec = 1.0f;
-        } else {
-            nd = (P.nx * fdx + P.ny * fdy + P.nz * fdz) * y;
-            spec_factor<SPEC>(nd, spec, live);
-        }
-        const float Tr = P.tp + A.phi;
-        const float T = fminf(fmaxf(Tr, 0.0f), 1.0f);
-        const float mT = (Tr >= 0.0f && Tr <= 1.0f) ? 1.0f : 0.0f;
-        const float gy = G * (y * y);
-        gb = __builtin_fmaf(gy * spec, T * T, gb);
-        gt = __builtin_fmaf(gy * P.b * spec, 2.0f * T * mT, gt);
-        if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
-            // d spec / d n_hat = 4 (n.w_i) w_i, w_i = d * y
-            const float cn = gy * P.b * (T * T) * (4.0f * nd * y) * live;
-            gn0 = __builtin_fmaf(cn, fdx, gn0);
-            gn1 = __builtin_fmaf(cn, fdy, gn1);
-            gn2 = __builtin_fmaf(cn, fdz, gn2);
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            // H = Hup + conj(w) * Hlow
+            const float Hr = __builtin_fmaf(lr[u], cw[u], __builtin_fmaf(li[u], sw[u], hr[u]));
+            const float Hi = __builtin_fmaf(li[u], cw[u], __builtin_fmaf(-lr[u], sw[u], hi[u]));
+            float c0, s0;
+            seed_phasor<NAIVE>(geo[u], Km, c0, s0);
+            const float G = c0 * Hr - s0 * Hi;       // Re(exp(+j 2 pi theta_mid) H)
+            const float y = geo[u].y;
+            const float fdx = (float)dx[u], fdy = (float)dy[u], fdz = (float)dz[u];
+            float spec, live = 0.0f;
+            float nd = 0.0f;
+            if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                spec = 1.0f;
+            } else {
+                nd = (P[u].nx * fdx + P[u].ny * fdy + P[u].nz * fdz) * y;
+                spec_factor<SPEC>(nd, spec, live);
+            }
+            const float Tr = P[u].tp + A.phi;
+            const float T = fminf(fmaxf(Tr, 0.0f), 1.0f);
+            const float mT = (Tr >= 0.0f && Tr <= 1.0f) ? 1.0f : 0.0f;
+            const float gy = G * (y * y);
+            gb[u] = __builtin_fmaf(gy * spec, T * T, gb[u]);
+            gt[u] = __builtin_fmaf(gy * P[u].b * spec, 2.0f * T * mT, gt[u]);
+            if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
+                // d spec / d n_hat = 4 (n.w_i) w_i, w_i = d * y
+                const float cn = gy * P[u].b * (T * T) * (4.0f * nd * y) * live;
+                gn0[u] = __builtin_fmaf(cn, fdx, gn0[u]);
+                gn1[u] = __builtin_fmaf(cn, fdy, gn1[u]);
+                gn2[u] = __builtin_fmaf(cn, fdz, gn2[u]);
+            }
         }
     }
-    if (ok) {
-        g_b[j] = gb;
-        g_T[j] = gt;
-        g_n[3 * j] = gn0;
-        g_n[3 * j + 1] = gn1;
-        g_n[3 * j + 2] = gn2;
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) {
+        const long j = j0 + (long)u * blockDim.x;
+        if (j >= n_pts) continue;
+        g_b[j] = gb[u];
+        g_T[j] = gt[u];
+        g_n[3 * j] = gn0[u];
+        g_n[3 * j + 1] = gn1[u];
+        g_n[3 * j + 2] = gn2[u];
     }
 }
 
@@ -415,7 +481,7 @@ template <int SPEC>
 static hipError_t launch_rbp(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
                              const float2* gsig, int np, bool naive, float* g_b, float* g_T,
                              float* g_n, hipStream_t st) {
-    dim3 grid((unsigned)((g.n_pts + 255) / 256));
+    dim3 grid((unsigned)((g.n_pts + 256L * kBwdPPL - 1) / (256L * kBwdPPL)));
     if (naive)
         hipLaunchKernelGGL((k_render_bwd_points<SPEC, true>), grid, dim3(256), 0, st, g.n_pts, rec,
                            g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n);

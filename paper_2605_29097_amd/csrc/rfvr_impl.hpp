@@ -214,6 +214,13 @@ hipError_t launch_loss_final(const double* part, int n_blocks, long n, float* lo
 hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
                                 float* u, float* origin, hipStream_t st);
 hipError_t launch_occupancy(long n, float s, const float* f, float* phi, hipStream_t st);
+hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basis[9], const float* logits,
+                                    int n_bins, int n_imp, int n_uni, float* xyz, float* u, float* origin,
+                                    hipStream_t st);
+hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
+                                   float lo, float hi, int n_bins, float* targets, hipStream_t st);
+hipError_t launch_bce(long n, const float* z, const float* t, float* loss, float* g, double* part, int nb,
+                      hipStream_t st);
 hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, float lr, float b1,
                         float b2, float eps, float wd, float bc1, float bc2, hipStream_t st);
 

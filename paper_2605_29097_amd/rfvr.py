@@ -17,7 +17,8 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librfvr.so")
+# RFVR_LIBRARY may point at another build of the same library (kernel tuning)
+LIB_PATH = os.environ.get("RFVR_LIBRARY") or os.path.join(_HERE, "librfvr.so")
 
 SPEC_CLAMP, SPEC_RAW, SPEC_OFF = 0x0, 0x1, 0x2
 PHASE_FP64RR, PHASE_NAIVE32 = 0x0, 0x4
@@ -57,6 +58,11 @@ class CMlp(ctypes.Structure):
                 ("params", _vp)]
 
 
+class CProposal(ctypes.Structure):
+    _fields_ = [("pe_octaves", _c_i32), ("width", _c_i32), ("layers", _c_i32), ("centre", _c_f * 3),
+                ("half_size", _c_f), ("params", _vp)]
+
+
 _P = ctypes.POINTER
 _SIGS = {
     "rfvr_version": ([], _c_i32),
@@ -83,6 +89,15 @@ _SIGS = {
     "rfvr_mlp_backward": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
                           _c_i32),
     "rfvr_occupancy": ([_c_i64, _c_f, _vp, _vp, _vp], _c_i32),
+    "rfvr_proposal_param_count": ([_P(CProposal)], _c_i64),
+    "rfvr_proposal_ws_bytes": ([_P(CProposal), _c_i64], _sz),
+    "rfvr_proposal_forward": ([_P(CProposal), _vp, _c_i64, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_proposal_backward": ([_P(CProposal), _vp, _c_i64, _vp, _c_u32, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_sample_importance": ([_P(CSampleDesc), _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp, _vp],
+                               _c_i32),
+    "rfvr_proposal_targets": ([_c_i32, _c_i32, _vp, _vp, _vp, _c_f, _c_f, _c_i32, _vp, _vp], _c_i32),
+    "rfvr_bce_ws_bytes": ([_c_i64], _sz),
+    "rfvr_bce": ([_c_i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_adamw": ([_c_i64, _vp, _vp, _vp, _vp, _c_i64, _c_f, _c_f, _c_f, _c_f, _c_f, _vp], _c_i32),
 }
 
@@ -280,12 +295,16 @@ def loss_l2(p: torch.Tensor, p_star: torch.Tensor, mask=None, want_grad=True, st
     return loss, g
 
 
+def _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode, seed, step):
+    return CSampleDesc((_c_f * 3)(*[float(c) for c in centre]), float(half_extent),
+                       (_c_f * 3)(*[float(c) for c in primary_dir]), int(n_ray_x), int(n_ray_y),
+                       int(n_z), int(mode), int(seed) & (2 ** 64 - 1), int(step) & (2 ** 64 - 1))
+
+
 def sample_points(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode=SAMPLE_GRID,
                   seed=0, step=0, device="cuda", stream=None):
     """(xyz [n_ray, n_z, 3], u [n_ray, n_z], ray_origin [n_ray, 3])."""
-    d = CSampleDesc((_c_f * 3)(*[float(c) for c in centre]), float(half_extent),
-                    (_c_f * 3)(*[float(c) for c in primary_dir]), int(n_ray_x), int(n_ray_y),
-                    int(n_z), int(mode), int(seed) & (2 ** 64 - 1), int(step) & (2 ** 64 - 1))
+    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode, seed, step)
     n_ray = n_ray_x * n_ray_y
     xyz = torch.empty(n_ray, n_z, 3, dtype=torch.float32, device=device)
     u = torch.empty(n_ray, n_z, dtype=torch.float32, device=device)
@@ -359,6 +378,90 @@ def adamw(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, stream=None):
            "rfvr_adamw")
 
 
+def sample_importance(centre, half_extent, primary_dir, n_ray_x, n_ray_y, logits: torch.Tensor,
+                      n_imp, n_uni, seed=0, step=0, stream=None):
+    """Proposal-guided depths: (xyz [n_ray, K, 3], u [n_ray, K], ray_origin [n_ray, 3]),
+    K = n_uni + n_imp, from bin logits [n_ray, n_bins]."""
+    n_ray = n_ray_x * n_ray_y
+    n_bins = logits.shape[-1]
+    assert logits.numel() == n_ray * n_bins
+    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_imp + n_uni, 0, seed, step)
+    dev = logits.device
+    K = n_imp + n_uni
+    xyz = torch.empty(n_ray, K, 3, dtype=torch.float32, device=dev)
+    u = torch.empty(n_ray, K, dtype=torch.float32, device=dev)
+    o = torch.empty(n_ray, 3, dtype=torch.float32, device=dev)
+    _check(lib().rfvr_sample_importance(ctypes.byref(d), _ptr(logits.contiguous()), int(n_bins), int(n_imp),
+                                        int(n_uni), _ptr(xyz), _ptr(u), _ptr(o), _stream(stream)),
+           "rfvr_sample_importance")
+    return xyz, u, o
+
+
+@dataclass
+class Proposal:
+    params: torch.Tensor
+    pe_octaves: int = 4
+    width: int = 64
+    layers: int = 2
+    centre: tuple = (0.0, 0.0, 0.28)
+    half_size: float = 0.10
+
+    def c(self, params: Optional[torch.Tensor] = None) -> CProposal:
+        p = self.params if params is None else params
+        return CProposal(self.pe_octaves, self.width, self.layers,
+                         (_c_f * 3)(*[float(c) for c in self.centre]), float(self.half_size), _ptr(p))
+
+    def param_count(self) -> int:
+        return int(lib().rfvr_proposal_param_count(ctypes.byref(self.c())))
+
+
+def proposal_forward(net: Proposal, xyz: torch.Tensor, stream=None):
+    """logits [N] at xyz [N, 3]."""
+    dev = xyz.device
+    n = xyz.numel() // 3
+    cn = net.c()
+    z = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_proposal_ws_bytes(ctypes.byref(cn), n), dev)
+    _check(lib().rfvr_proposal_forward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(z), _ptr(ws),
+                                       ws.numel(), _stream(stream)), "rfvr_proposal_forward")
+    return z
+
+
+def proposal_backward(net: Proposal, xyz: torch.Tensor, g_logits: torch.Tensor, flags=0, out=None,
+                      stream=None):
+    dev = xyz.device
+    n = xyz.numel() // 3
+    cn = net.c()
+    gp = out if out is not None else torch.empty(net.param_count(), dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_proposal_ws_bytes(ctypes.byref(cn), n), dev)
+    _check(lib().rfvr_proposal_backward(ctypes.byref(cn), _ptr(xyz.contiguous()), n,
+                                        _ptr(g_logits.contiguous()), flags, _ptr(gp), _ptr(ws), ws.numel(),
+                                        _stream(stream)), "rfvr_proposal_backward")
+    return gp
+
+
+def proposal_targets(u: torch.Tensor, alpha: torch.Tensor, trans: torch.Tensor, lo: float, hi: float,
+                     n_bins: int, stream=None):
+    """Binned, max-normalised blend weights [n_ray, n_bins] of the render at depths u [n_ray, n_k]."""
+    n_ray, n_k = u.shape
+    t = torch.empty(n_ray, n_bins, dtype=torch.float32, device=u.device)
+    _check(lib().rfvr_proposal_targets(n_ray, n_k, _ptr(u.contiguous()), _ptr(alpha.contiguous()),
+                                       _ptr(trans.contiguous()), float(lo), float(hi), int(n_bins), _ptr(t),
+                                       _stream(stream)), "rfvr_proposal_targets")
+    return t
+
+
+def bce(logits: torch.Tensor, t: torch.Tensor, want_grad=True, stream=None):
+    """(loss [1], g_logits) of the mean binary cross-entropy of sigmoid(logits) vs t."""
+    n = logits.numel()
+    loss = torch.empty(1, dtype=torch.float32, device=logits.device)
+    g = torch.empty_like(logits) if want_grad else None
+    ws = _ws(lib().rfvr_bce_ws_bytes(n), logits.device)
+    _check(lib().rfvr_bce(n, _ptr(logits.contiguous()), _ptr(t.contiguous()), _ptr(loss), _ptr(g), _ptr(ws),
+                          ws.numel(), _stream(stream)), "rfvr_bce")
+    return loss, g
+
+
 # C-ABI names
 rfvr_render_forward = render_forward
 rfvr_render_backward = render_backward
@@ -370,3 +473,8 @@ rfvr_mlp_forward = mlp_forward
 rfvr_mlp_backward = mlp_backward
 rfvr_adamw = adamw
 rfvr_occupancy = occupancy
+rfvr_proposal_forward = proposal_forward
+rfvr_proposal_backward = proposal_backward
+rfvr_sample_importance = sample_importance
+rfvr_proposal_targets = proposal_targets
+rfvr_bce = bce

@@ -24,5 +24,5 @@ from .scenes import (  # noqa: F401
     complex_noise,
     random_union_scene,
 )
-from .mlp_init import mlp_layout, mlp_init, MLPSpec  # noqa: F401
+from .mlp_init import mlp_layout, mlp_init, MLPSpec, ProposalSpec, proposal_layout, proposal_init  # noqa: F401
 from .configs import CONFIGS, config  # noqa: F401

@@ -88,3 +88,44 @@ def mlp_init(spec: MLPSpec, seed: int, sphere_radius: float = 0.5) -> np.ndarray
         put(f"Wh{h}", rng.normal(0.0, np.sqrt(2.0 / fan_in), (spec.head_width, fan_in)))
     put("wh_out", rng.normal(0.0, np.sqrt(1.0 / spec.head_width), spec.head_width))
     return p.astype(np.float32)
+
+
+@dataclass(frozen=True)
+class ProposalSpec:
+    pe_octaves: int = 4
+    width: int = 64
+    layers: int = 2
+    centre: Tuple[float, float, float] = (0.0, 0.0, 0.28)
+    half_size: float = 0.10
+
+    @property
+    def in_dim(self) -> int:
+        return 3 + 6 * self.pe_octaves
+
+
+def proposal_layout(spec: ProposalSpec) -> Dict[str, Tuple[int, Tuple[int, ...]]]:
+    """Flat layout of the proposal network: W_l [width, in_l], b_l [width] for
+    l < layers, then w_out [width], b_out [1]."""
+    out = {}
+    off = 0
+    for l in range(spec.layers):
+        fan_in = spec.in_dim if l == 0 else spec.width
+        out[f"W{l}"] = (off, (spec.width, fan_in)); off += spec.width * fan_in
+        out[f"b{l}"] = (off, (spec.width,)); off += spec.width
+    out["w_out"] = (off, (spec.width,)); off += spec.width
+    out["b_out"] = (off, (1,)); off += 1
+    out["__total__"] = (off, ())
+    return out
+
+
+def proposal_init(spec: ProposalSpec, seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, float32 flat vector."""
+    lay = proposal_layout(spec)
+    rng = np.random.default_rng(seed)
+    p = np.zeros(lay["__total__"][0])
+    for l in range(spec.layers):
+        o, shp = lay[f"W{l}"]
+        p[o:o + shp[0] * shp[1]] = rng.normal(0.0, np.sqrt(2.0 / shp[1]), shp).ravel()
+    o, shp = lay["w_out"]
+    p[o:o + shp[0]] = rng.normal(0.0, np.sqrt(1.0 / shp[0]), shp[0])
+    return p.astype(np.float32)
