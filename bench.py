@@ -117,6 +117,59 @@ def probe(tr, which, reps):
     print(json.dumps({"probe": which, "reps": reps}))
 
 
+def proposal_study(args, dev):
+    """Torus-behind-slab scene: full-space training (2^20 grid points) against
+    proposal-sampled training (16 importance + 4 uniform depths per ray, 81,920
+    points) and the untrained control (20 stratified uniform depths), from the
+    same initial network.  Every run is judged by the full-space render of its
+    network against the clean target (signal NRMSE); E* is the full-space run's
+    judge NRMSE after its step budget.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2605_29097_amd.train import (ProposalConfig, ProposalTrainer, StepConfig, Trainer, nrmse)
+    from synth import MLPSpec, mlp_init
+    cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28))
+    spec = MLPSpec(centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
+    data = np.load(os.path.join(ROOT, "tests", "golden", "torus_target.npz"))
+    to_t = lambda a: torch.from_numpy(np.stack([a.real, a.imag], -1).astype(np.float32)).to(dev)
+    noisy, clean = to_t(data["noisy"]), to_t(data["clean"])
+    runs = {
+        "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps),
+        "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(), device=dev),
+                     args.study_prop_steps),
+        "uniform_20": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(train=False), device=dev),
+                       args.study_prop_steps),
+    }
+    every = args.study_eval_every
+    out = {}
+    for name, (make, n_steps) in runs.items():
+        tr = make(torch.from_numpy(mlp_init(spec, cfg.seed)))
+        curve = [(0, nrmse(tr.judge_signal(), clean))]
+        step_ms = []
+        for k in range(1, n_steps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tr.step()
+            e1.record()
+            e1.synchronize()
+            step_ms.append(e0.elapsed_time(e1))
+            if k % every == 0 or k == n_steps:
+                curve.append((k, nrmse(tr.judge_signal(), clean)))
+                print(f"[study] {name} step {k} judge nrmse {curve[-1][1]:.4f} "
+                      f"({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
+        out[name] = {"ms_per_step": float(np.median(step_ms[2:] if len(step_ms) > 4 else step_ms)),
+                     "steps": n_steps, "judge_nrmse": [[k, round(e, 5)] for k, e in curve]}
+    e_star = out["full_space"]["judge_nrmse"][-1][1]
+    for name, r in out.items():
+        hit = next((k for k, e in r["judge_nrmse"] if e <= e_star), None)
+        r["steps_to_e_star"] = hit
+        r["ms_to_e_star"] = None if hit is None else round(hit * r["ms_per_step"], 1)
+    print(json.dumps({"study": "proposal_vs_full_space", "e_star": e_star, "eval_every": every,
+                      "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
+                               "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
+                      "runs": out}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +181,11 @@ def main():
                     help="run only one term pass of the workload (for hardware-counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--proposal-study", action="store_true",
+                    help="train full-space vs proposal-sampled vs uniform-20 on the torus scene")
+    ap.add_argument("--study-full-steps", type=int, default=300)
+    ap.add_argument("--study-prop-steps", type=int, default=1200)
+    ap.add_argument("--study-eval-every", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
@@ -146,6 +204,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
+    if args.proposal_study:
+        proposal_study(args, dev)
         return
     cfg = StepConfig()
     params, target = make_inputs(cfg, dev)

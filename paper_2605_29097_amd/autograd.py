@@ -6,7 +6,7 @@ activations (network) instead of storing them.
 
     f, grad, a = MLPFn.apply(params, xyz, net)
     sig        = RenderFn.apply(sdf, grad, refl, amp, s, ap, xyz, phi_ray, phi_tx, flags)
-    z, p       = MFFn.apply(sig, ap, xyz_q)          (p differentiable)
+    z, p       = MFFn.apply(sig, ap, xyz_q, flags)   (p differentiable)
     loss       = LossFn.apply(p, p_star)
 """
 from __future__ import annotations
@@ -69,18 +69,18 @@ class MFFn(torch.autograd.Function):
     """(z [Q, 2], p [Q]) = matched filter of signal at xyz_q; only p carries gradient."""
 
     @staticmethod
-    def forward(ctx, signal, ap: R.Aperture, xyz_q):
-        z, p = R.mf_forward(ap, xyz_q.contiguous(), signal.contiguous())
+    def forward(ctx, signal, ap: R.Aperture, xyz_q, flags: int = 0):
+        z, p = R.mf_forward(ap, xyz_q.contiguous(), signal.contiguous(), flags=flags)
         ctx.save_for_backward(xyz_q, z, p)
-        ctx.ap = ap
+        ctx.ap, ctx.flags = ap, flags
         ctx.mark_non_differentiable(z)
         return z, p
 
     @staticmethod
     def backward(ctx, g_z, g_p):
         xyz_q, z, p = ctx.saved_tensors
-        g = R.mf_backward(ctx.ap, xyz_q, z, p, g_p.contiguous())
-        return g, None, None
+        g = R.mf_backward(ctx.ap, xyz_q, z, p, g_p.contiguous(), flags=ctx.flags)
+        return g, None, None, None
 
 
 class LossFn(torch.autograd.Function):

@@ -20,6 +20,17 @@
 namespace rfvr {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Eight FP32 operand values (two float4 along k) rounded to BF16 (RNE) for one
+// v_mfma_f32_16x16x32_bf16.  A and B fragments use the same slot <-> k
+// assignment, so the instruction's sum over its 32 slots is the sum over k.
+__device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi) {
+    bf16x8 r;
+    r[0] = (__bf16)lo[0]; r[1] = (__bf16)lo[1]; r[2] = (__bf16)lo[2]; r[3] = (__bf16)lo[3];
+    r[4] = (__bf16)hi[0]; r[5] = (__bf16)hi[1]; r[6] = (__bf16)hi[2]; r[7] = (__bf16)hi[3];
+    return r;
+}
 
 enum { PRO_ID = 0, PRO_SP = 1, PRO_DSP_MUL = 2, PRO_RELU = 3 };
 enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2 };
@@ -76,7 +87,7 @@ struct GemmArgs {
     float beta;
 };
 
-template <int PRO, int EPI, int BM>
+template <int PRO, int EPI, int BM, bool BF>
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     constexpr int BP = 128, BK = 32, LW = BK + 4;
     constexpr int WP = (BM == 128) ? 2 : 4;
@@ -159,22 +170,42 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         }
         __syncthreads();
         if (k0 + BK < g.K) load(k0 + BK);
+        if constexpr (BF) {
+            // the chunk's two 16-wide k groups feed one 16x16x32 BF16 MFMA
+            bf16x8 af[TP], bf[TM];
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-            floatx4 af[TP], bf[TM];
+            for (int a = 0; a < TP; ++a) {
+                const float* r = &sA[(wp * (BP / WP) + a * 16 + li) * LW + lg * 4];
+                af[a] = to_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16));
+            }
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const float* r = &sB[(wm * (BM / WM) + b * 16 + li) * LW + lg * 4];
+                bf[b] = to_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16));
+            }
 #pragma unroll
             for (int a = 0; a < TP; ++a)
-                af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * (BP / WP) + a * 16 + li) * LW + kk + lg * 4]);
 #pragma unroll
-            for (int b = 0; b < TM; ++b)
-                bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / WM) + b * 16 + li) * LW + kk + lg * 4]);
+                for (int b = 0; b < TM; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+        } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int kk = 0; kk < BK; kk += 16) {
+                floatx4 af[TP], bf[TM];
 #pragma unroll
                 for (int a = 0; a < TP; ++a)
+                    af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * (BP / WP) + a * 16 + li) * LW + kk + lg * 4]);
 #pragma unroll
-                    for (int b = 0; b < TM; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < TM; ++b)
+                    bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / WM) + b * 16 + li) * LW + kk + lg * 4]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int a = 0; a < TP; ++a)
+#pragma unroll
+                        for (int b = 0; b < TM; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -215,7 +246,7 @@ struct WgArgs {
     float beta;
 };
 
-template <int PRO, bool BIAS>
+template <int PRO, bool BIAS, bool BF>
 __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
     constexpr int BM = 128, BN = 128, BK = 32, LW = 128 + 4;
     constexpr bool TWO = PRO == PRO_DSP_MUL;
@@ -294,21 +325,50 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
                 for (int r = 0; r < BK; ++r) bsum += sA[r * LW + tid];
             }
         }
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
+        if constexpr (BF) {
+            // points lg*4 + s and 16 + lg*4 + s (s < 4) fill the 8 k slots of a lane
+            floatx4 a0[4], a1[4], b0[4], b1[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const int r = kk + lg * 4 + s;
-                float af[4], bf[4];
+                const int r = lg * 4 + s;
 #pragma unroll
-                for (int a = 0; a < 4; ++a) af[a] = sA[r * LW + wp * 64 + a * 16 + li];
+                for (int a = 0; a < 4; ++a) {
+                    a0[a][s] = sA[r * LW + wp * 64 + a * 16 + li];
+                    a1[a][s] = sA[(r + 16) * LW + wp * 64 + a * 16 + li];
+                }
 #pragma unroll
-                for (int b = 0; b < 4; ++b) bf[b] = sB[r * LW + wn * 64 + b * 16 + li];
+                for (int b = 0; b < 4; ++b) {
+                    b0[b][s] = sB[r * LW + wn * 64 + b * 16 + li];
+                    b1[b][s] = sB[(r + 16) * LW + wn * 64 + b * 16 + li];
+                }
+            }
+            bf16x8 af[4], bf[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a) af[a] = to_bf16x8(a0[a], a1[a]);
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b) bf[b] = to_bf16x8(b0[b], b1[b]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = kk + lg * 4 + s;
+                    float af[4], bf[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) af[a] = sA[r * LW + wp * 64 + a * 16 + li];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) bf[b] = sB[r * LW + wn * 64 + b * 16 + li];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -653,17 +713,36 @@ hipError_t prep_weights(const Layout& l, const float* P, const Weights& w, hipSt
     return hipGetLastError();
 }
 
-template <int PRO, int EPI>
-void gemm(const GemmArgs& a, hipStream_t st) {
+// launch context of the network passes: stream and matrix-operand precision
+// (bf: BF16 operands, FP32 accumulation; layers reading the encoding stay FP32)
+struct Cx {
+    hipStream_t st;
+    bool bf;
+};
+
+template <int PRO, int EPI, bool BF>
+void gemm_launch(const GemmArgs& a, hipStream_t st) {
     const long tiles = (a.P + 127) / 128;
     const long groups = (tiles + 7) / 8;                 // 8 point tiles per XCD group
     if (a.M <= 64) {
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64, BF>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
     } else {
         const long nmb = (a.M + 127) / 128;
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128, BF>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
                            st, a);
     }
+}
+
+template <int PRO, int EPI>
+void gemm(const GemmArgs& a, const Cx& cx) {
+    if (cx.bf) gemm_launch<PRO, EPI, true>(a, cx.st);
+    else gemm_launch<PRO, EPI, false>(a, cx.st);
+}
+
+// FP32 GEMM whatever the context (first layer: its operand is the encoding)
+template <int PRO, int EPI>
+void gemm32(const GemmArgs& a, const Cx& cx) {
+    gemm_launch<PRO, EPI, false>(a, cx.st);
 }
 
 GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
@@ -677,7 +756,8 @@ GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb,
 
 template <int PRO>
 void wgrad(const float* A, long lda, int M, const float* B, const float* B2, long ldb, int Kout,
-           long P, float beta, float* part, hipStream_t st, float* bpart = nullptr) {
+           long P, float beta, float* part, const Cx& cx, float* bpart = nullptr) {
+    hipStream_t st = cx.st;
     WgArgs g;
     g.A = A; g.lda = lda; g.B = B; g.B2 = B2; g.ldb = ldb; g.part = part; g.bpart = bpart; g.P = P;
     g.M = M; g.Kout = Kout; g.per_split = ((P + kWgSplits - 1) / kWgSplits + 31) / 32 * 32;
@@ -686,10 +766,13 @@ void wgrad(const float* A, long lda, int M, const float* B, const float* B2, lon
     const long tiles = (long)((M + 127) / 128) * ((Kout + 127) / 128);
     const long groups = (kWgSplits + 7) / 8;
     const dim3 grid((unsigned)(groups * 8 * tiles));
-    if (bpart)
-        hipLaunchKernelGGL((k_gemm_wg<PRO, true>), grid, dim3(256), 0, st, g);
-    else
-        hipLaunchKernelGGL((k_gemm_wg<PRO, false>), grid, dim3(256), 0, st, g);
+    if (cx.bf) {
+        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, true>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, true>), grid, dim3(256), 0, st, g);
+    } else {
+        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, false>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, false>), grid, dim3(256), 0, st, g);
+    }
 }
 
 // dst[m] (+)= sum_s bpart[s][m]
@@ -767,7 +850,6 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
     int rc;
     if ((rc = check_net(net))) return rc;
     if (n < 1 || !xyz || !net->params) { set_error("n >= 1, xyz and params are required"); return RFVR_E_INVALID; }
-    if (net->precision != RFVR_PREC_FP32) { set_error("BF16 network path not built"); return RFVR_E_UNSUPPORTED; }
     const Layout l = layout(net);
     {
         const size_t need = fwd_bytes(l, (long)n);
@@ -777,6 +859,7 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
         }
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Cx cx{st, net->precision == RFVR_PREC_BF16}, cx32{st, false};
     const float* P = net->params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
     const long chunk = n < kChunk ? (long)n : kChunk;
@@ -795,17 +878,17 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
         const float* x = xyz + 3 * c0;
         hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0, nullptr, nullptr);
-        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), st);
+        gemm32<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), cx);
         for (int i = 1; i < l.L; ++i)
-            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), st);
+            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), cx);
         float* Zt = Z[l.L - 1];
         if (sdf)
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Zt, (long)l.W, l.W,
                                (int)PRO_SP, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
         if (refl) {
-            gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), st);
+            gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
             for (int h = 1; h < l.HL; ++h)
-                gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), st);
+                gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                                l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
@@ -817,10 +900,11 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
             for (int i = l.L - 1; i >= 0; --i) {
                 const int mout = i == 0 ? l.in0p : l.W;
                 float* dst = G[cur_g ^ 1];
+                const Cx& cxi = i == 0 ? cx32 : cx;      // the product with W_0 stays FP32
                 if (i == l.L - 1)
-                    gemm<PRO_ID, EPI_BIAS>(ga(G[cur_g], nullptr, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), st);
+                    gemm<PRO_ID, EPI_BIAS>(ga(G[cur_g], nullptr, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), cxi);
                 else
-                    gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i], G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), st);
+                    gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i], G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), cxi);
                 cur_g ^= 1;
             }
             hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
@@ -839,7 +923,6 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
     if ((rc = check_net(net))) return rc;
     if (n < 1 || !xyz || !net->params || !g_params) { set_error("n >= 1, xyz, params and g_params are required"); return RFVR_E_INVALID; }
     if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }
-    if (net->precision != RFVR_PREC_FP32) { set_error("BF16 network path not built"); return RFVR_E_UNSUPPORTED; }
     const Layout l = layout(net);
     {
         const size_t need = bwd_bytes(l, (long)n);
@@ -849,6 +932,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         }
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Cx cx{st, net->precision == RFVR_PREC_BF16}, cx32{st, false};
     const float* P = net->params;
     float* GP = g_params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
@@ -885,18 +969,18 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
-        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), st);
-        gemm<PRO_ID, EPI_BIAS>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Zd[0], l.W, m, l.W, l.in0p, beta), st);
+        gemm32<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), cx);
+        gemm32<PRO_ID, EPI_BIAS>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Zd[0], l.W, m, l.W, l.in0p, beta), cx);
         for (int i = 1; i < l.L; ++i) {
-            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), st);
-            gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i - 1], Zd[i - 1], l.W, w.Wp[i], l.W, nullptr, Zd[i], l.W, m, l.W, l.W, beta), st);
+            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), cx);
+            gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i - 1], Zd[i - 1], l.W, w.Wp[i], l.W, nullptr, Zd[i], l.W, m, l.W, l.W, beta), cx);
         }
         float* Zt = Z[l.L - 1];
         float* Zdt = Zd[l.L - 1];
         // head forward
-        gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), st);
+        gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
         for (int h = 1; h < l.HL; ++h)
-            gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), st);
+            gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
         // head output: ybar3, Ybar_{HL-1}
         hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                            l.HW, P + l.o_whout, P + l.o_bhout, ga_, yb3, Ybh[l.HL - 1]);
@@ -906,14 +990,14 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         for (int h = l.HL - 1; h >= 0; --h) {
             float* Yb = Ybh[h];
             if (h > 0) {
-                wgrad<PRO_RELU>(Yb, l.HW, l.HW, Yh[h - 1], nullptr, l.HW, l.HW, m, beta, part, st, bpart);
+                wgrad<PRO_RELU>(Yb, l.HW, l.HW, Yh[h - 1], nullptr, l.HW, l.HW, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.HW, l.HW, GP + l.oWh[h], acc, st);
                 hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
                                    l.HW, GP + l.obh[h], acc);
                 // Ybar_{h-1} = (Ybar_h Wh_h) . relu'(Y_{h-1})
-                gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), st);
+                gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), cx);
             } else {
-                wgrad<PRO_SP>(Yb, l.HW, l.HW, Zt, nullptr, l.W, l.W, m, beta, part, st, bpart);
+                wgrad<PRO_SP>(Yb, l.HW, l.HW, Zt, nullptr, l.W, l.W, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.W, l.W, GP + l.oWh[0], acc, st);
                 hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
                                    l.HW, GP + l.obh[0], acc);
@@ -922,7 +1006,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0, Hdot_bar = half w_out
         hipLaunchKernelGGL(k_top_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, gf, P + l.o_wout,
                            half, (long)l.W, Hb, Hdb);
-        gemm<PRO_ID, EPI_ACC>(ga(Ybh[0], nullptr, l.HW, w.WhT[0], l.HW, nullptr, Hb, l.W, m, l.W, l.HW, beta), st);
+        gemm<PRO_ID, EPI_ACC>(ga(Ybh[0], nullptr, l.HW, w.WhT[0], l.HW, nullptr, Hb, l.W, m, l.W, l.HW, beta), cx);
         // sdf output layer: w_out_bar = half sum (g_f H + Hdot), b_out_bar = half sum g_f
         colsum(Zt, Zdt, gf, l.W, m, l.W, 2, beta, half, cpart, GP + l.o_wout, acc, st);
         if (gf) colsum(gf, nullptr, nullptr, 1, m, 1, 0, beta, half, cpart, GP + l.o_bout, acc, st);
@@ -933,20 +1017,20 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                                Z[i], Zd[i], Hb, Hdb, beta, Zb, Zdb);
             const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
             if (i == 0) {
-                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, st, bpart);
+                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32, bpart);
                 wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
-                              part + (size_t)kWgSplits * l.W * finp, st);
+                              part + (size_t)kWgSplits * l.W * finp, cx32);
             } else {
-                wgrad<PRO_SP>(Zb, l.W, l.W, Z[i - 1], nullptr, l.W, finp, m, beta, part, st, bpart);
+                wgrad<PRO_SP>(Zb, l.W, l.W, Z[i - 1], nullptr, l.W, finp, m, beta, part, cx, bpart);
                 wgrad<PRO_DSP_MUL>(Zdb, l.W, l.W, Z[i - 1], Zd[i - 1], l.W, finp, m, beta,
-                                   part + (size_t)kWgSplits * l.W * finp, st);
+                                   part + (size_t)kWgSplits * l.W * finp, cx);
             }
             wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st);
             hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,
                                GP + l.ob[i], acc);
             if (i > 0) {
-                gemm<PRO_ID, EPI_BIAS>(ga(Zb, nullptr, l.W, w.WT[i], l.W, nullptr, Hb, l.W, m, l.W, l.W, beta), st);
-                gemm<PRO_ID, EPI_BIAS>(ga(Zdb, nullptr, l.W, w.WT[i], l.W, nullptr, Hdb, l.W, m, l.W, l.W, beta), st);
+                gemm<PRO_ID, EPI_BIAS>(ga(Zb, nullptr, l.W, w.WT[i], l.W, nullptr, Hb, l.W, m, l.W, l.W, beta), cx);
+                gemm<PRO_ID, EPI_BIAS>(ga(Zdb, nullptr, l.W, w.WT[i], l.W, nullptr, Hdb, l.W, m, l.W, l.W, beta), cx);
             }
         }
         if ((rc = hip_status(hipGetLastError(), "mlp backward"))) return rc;
@@ -1051,6 +1135,7 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
         return RFVR_E_WORKSPACE;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Cx cx{st, false};
     const float* P = net->params;
     const long chunk = n < kChunk ? (long)n : kChunk;
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
@@ -1083,9 +1168,9 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
         const int acc = (c0 > 0 || (flags & RFVR_ACCUMULATE)) ? 1 : 0;
         hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, xyz + 3 * c0, net->centre[0],
                            net->centre[1], net->centre[2], inv_half, l.L, l.in0p, X0, nullptr, nullptr);
-        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, Wp[0], l.in0p, P + l.ob[0], A[0], l.W, m, l.W, l.in0p, beta), st);
+        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, Wp[0], l.in0p, P + l.ob[0], A[0], l.W, m, l.W, l.in0p, beta), cx);
         for (int i = 1; i < l.layers; ++i)
-            gemm<PRO_RELU, EPI_BIAS>(ga(A[i - 1], nullptr, l.W, Wp[i], l.W, P + l.ob[i], A[i], l.W, m, l.W, l.W, beta), st);
+            gemm<PRO_RELU, EPI_BIAS>(ga(A[i - 1], nullptr, l.W, Wp[i], l.W, P + l.ob[i], A[i], l.W, m, l.W, l.W, beta), cx);
         float* At = A[l.layers - 1];
         if (!bwd) {
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, At, (long)l.W, l.W,
@@ -1099,15 +1184,15 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
             for (int i = l.layers - 1; i >= 0; --i) {
                 const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
                 if (i == 0)
-                    wgrad<PRO_ID>(Ab, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, st, bpart);
+                    wgrad<PRO_ID>(Ab, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx, bpart);
                 else
-                    wgrad<PRO_RELU>(Ab, l.W, l.W, A[i - 1], nullptr, l.W, finp, m, beta, part, st, bpart);
+                    wgrad<PRO_RELU>(Ab, l.W, l.W, A[i - 1], nullptr, l.W, finp, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.W, finp, fin, g_params + l.oW[i], acc, st);
                 hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,
                                    g_params + l.ob[i], acc);
                 if (i > 0) {
                     gemm<PRO_ID, EPI_RELUMASK>(ga(Ab, nullptr, l.W, WT[i], l.W, nullptr, Ab2, l.W, m, l.W, l.W,
-                                                  beta, A[i - 1], l.W), st);
+                                                  beta, A[i - 1], l.W), cx);
                     float* t = Ab; Ab = Ab2; Ab2 = t;
                 }
             }

@@ -4,9 +4,10 @@
 //
 // Signal tracing, Eq. ref_sim / App. A.4 Alg. 2, rebuilt for gfx950:
 //  * forward: a lane owns one (measurement, frequency chunk) pair and keeps the
-//    chunk's complex accumulators in VGPRs; all lanes of a wave walk the same
-//    points, so point records arrive through scalar loads (SGPR operands, no
-//    LDS traffic).  Per (measurement, point) the path length (FP64) and the
+//    chunk's complex accumulators in VGPRs; all lanes of a work-group walk the
+//    same points, whose records are staged through LDS in double-buffered
+//    tiles of 64 (one wide load per record, broadcast reads, the next tile's
+//    global loads in flight).  Per (measurement, point) the path length (FP64) and the
 //    step phasor (accurately rounded) are set up once; every 16 frequencies a
 //    phasor is re-seeded from an FP64-reduced phase at the sub-chunk centre
 //    and the sub-chunk is walked by complex rotation both ways (f_n is linear

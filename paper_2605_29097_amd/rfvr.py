@@ -209,11 +209,16 @@ class Fields:
 # entry points (same names as the C ABI, without the prefix)
 # ----------------------------------------------------------------------------
 def render_forward(ap: Aperture, sm: Samples, fl: Fields, flags: int = 0, want_alpha=False,
-                   stream=None):
-    """signal [n_meas, n_freq, 2] float32 (and alpha, trans [n_ray, n_z] if asked)."""
+                   out=None, stream=None):
+    """signal [n_meas, n_freq, 2] float32 (and alpha, trans [n_ray, n_z] if asked).
+    out: optional contiguous [n_meas, n_freq, 2] destination (e.g. rows of a bank)."""
     dev = sm.xyz.device
     cap, csm, cfl = ap.c(), sm.c(), fl.c()
-    sig = torch.empty(ap.n_meas, ap.n_freq, 2, dtype=torch.float32, device=dev)
+    if out is not None:
+        assert out.is_contiguous() and out.shape == (ap.n_meas, ap.n_freq, 2) and out.dtype == torch.float32
+        sig = out
+    else:
+        sig = torch.empty(ap.n_meas, ap.n_freq, 2, dtype=torch.float32, device=dev)
     alpha = trans = None
     if want_alpha:
         alpha = torch.empty(sm.xyz.shape[:2], dtype=torch.float32, device=dev)

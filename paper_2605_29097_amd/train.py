@@ -49,6 +49,7 @@ class StepConfig:
     total_steps: int = 50000
     seed: int = 0
     spec_flags: int = R.SPEC_CLAMP
+    bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
 
     @property
     def n_pts(self) -> int:
@@ -70,6 +71,21 @@ def aperture_positions(cfg: StepConfig) -> np.ndarray:
     return np.stack([gx.ravel(), gy.ravel(), np.zeros(nx * ny)], 1).astype(np.float32)
 
 
+def patch_order(cfg: StepConfig) -> np.ndarray:
+    """Measurement ids (i = iy * nx + ix) in patch-major order: the aperture is
+    cut into px x py tiles (Sec. Signal Tracing Bank), tiles in row-major order,
+    antennas row-major inside a tile.  With this order every patch is one
+    contiguous block of rows of the signal."""
+    nx, ny = cfg.ap
+    px, py = cfg.bank_patch
+    if nx % px or ny % py:
+        raise ValueError(f"patch {px}x{py} does not tile the {nx}x{ny} aperture")
+    ids = [iy * nx + ix
+           for by in range(ny // py) for bx in range(nx // px)
+           for iy in range(by * py, (by + 1) * py) for ix in range(bx * px, (bx + 1) * px)]
+    return np.asarray(ids, np.int64)
+
+
 class Trainer:
     """State of one reconstruction: network, amplitude, optimiser moments, target."""
 
@@ -79,7 +95,17 @@ class Trainer:
         self.dev = torch.device(device)
         f0 = cfg.f_lo
         df = 0.0 if cfg.n_freq == 1 else (cfg.f_hi - cfg.f_lo) / (cfg.n_freq - 1)
-        self.tx = torch.from_numpy(aperture_positions(cfg)).to(self.dev)
+        tx = aperture_positions(cfg)
+        self.perm = None
+        if cfg.bank_patch is not None:
+            # measurements are held in patch-major order (the target's rows too)
+            self.perm = patch_order(cfg)
+            tx = tx[self.perm]
+            self.patch_len = cfg.bank_patch[0] * cfg.bank_patch[1]
+            self.n_patch = cfg.n_meas // self.patch_len
+            self.bank = None
+        self.tx = torch.from_numpy(np.ascontiguousarray(tx)).to(self.dev)
+        self.f0, self.df = f0, df
         self.ap = R.Aperture(tx=self.tx, f0=f0, df=df, n_freq=cfg.n_freq)
         self.net = R.MLP(params=params.to(self.dev).contiguous(), n_layers=cfg.n_layers,
                          width=cfg.width, pe_octaves=cfg.pe_octaves, head_width=cfg.head_width,
@@ -96,7 +122,10 @@ class Trainer:
         self.amp = torch.tensor([cfg.amp0], device=self.dev)
         self.amp_m = torch.zeros(1, device=self.dev)
         self.amp_v = torch.zeros(1, device=self.dev)
-        self.target = target_signal.to(self.dev).contiguous()
+        target = target_signal.to(self.dev)
+        if self.perm is not None:
+            target = target[torch.from_numpy(self.perm).to(self.dev)]
+        self.target = target.contiguous()
         self.t = 0
         self.p_star = None
         self._xyz_key = None
@@ -138,7 +167,22 @@ class Trainer:
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
                       refl=a.view(xyz.shape[:2]), s=c.s, amp=1.0, amp_dev=self.amp,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
-        sig = R.render_forward(self.ap, sm, fl, flags=c.spec_flags)
+        ap_r, fl_r = self.ap, fl
+        if c.bank_patch is None:
+            sig = R.render_forward(self.ap, sm, fl, flags=c.spec_flags)
+        else:
+            # Signal Tracing Bank: trace only the current patch's antennas into
+            # its rows of the bank; the other rows keep earlier results
+            if self.bank is None:
+                self.bank = R.render_forward(self.ap, sm, fl, flags=c.spec_flags)
+            k = self.t % self.n_patch
+            i0, i1 = k * self.patch_len, (k + 1) * self.patch_len
+            ap_r = R.Aperture(tx=self.tx[i0:i1], f0=self.f0, df=self.df, n_freq=c.n_freq)
+            n_ray = origin.shape[0]
+            fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=c.s, amp=1.0, amp_dev=self.amp,
+                            phi_ray=fl.phi_ray, phi_tx=phi[n_ray + i0:n_ray + i1].contiguous())
+            R.render_forward(ap_r, sm, fl_r, flags=c.spec_flags, out=self.bank[i0:i1])
+            sig = self.bank
         mark("render_fwd")
         key = (c.sampling, None if c.sampling == R.SAMPLE_GRID else self.t)
         if self.p_star is None or key != self._xyz_key:
@@ -148,9 +192,10 @@ class Trainer:
             z, p = R.mf_forward(self.ap, xyz, sig)
         mark("mf_fwd")
         loss, g_p = R.loss_l2(p, self.p_star)
-        g_sig = R.mf_backward(self.ap, xyz, z, p, g_p)
+        # the filter has no parameters: only the traced rows carry gradient
+        g_sig = R.mf_backward(ap_r, xyz, z, p, g_p)
         mark("mf_bwd")
-        gr = R.render_backward(self.ap, sm, fl, g_sig, flags=c.spec_flags)
+        gr = R.render_backward(ap_r, sm, fl_r, g_sig, flags=c.spec_flags)
         mark("render_bwd")
         R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
                        out=self.g)
@@ -163,5 +208,140 @@ class Trainer:
         R.adamw(self.amp, gr["amp"], self.amp_m, self.amp_v, self.t, self.lr(c.lr_other))
         mark("adamw")
         self.last = dict(signal=sig, loss=loss)
+        return loss
+
+    # ------------------------------------------------------------------ judge
+    def judge_signal(self):
+        """Full-space render of the current network on the uniform grid of the
+        configured sample cube (lensless primary rays, c.lines x c.n_z)."""
+        c = self.cfg
+        xyz, _, origin = R.sample_points(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0],
+                                         c.lines[1], c.n_z, mode=R.SAMPLE_GRID, device=self.dev)
+        f, grad, a = R.mlp_forward(self.net, xyz)
+        f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
+        phi = R.occupancy(c.s, f_org)
+        fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
+                      refl=a.view(xyz.shape[:2]), s=c.s, amp=1.0, amp_dev=self.amp,
+                      phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
+        return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.spec_flags)
+
+
+def nrmse(sig: torch.Tensor, ref: torch.Tensor) -> float:
+    """||sig - ref|| / ||ref|| over all measurements and frequencies."""
+    return float(torch.linalg.vector_norm(sig - ref) / torch.linalg.vector_norm(ref))
+
+
+@dataclass
+class ProposalConfig:
+    n_bins: int = 64
+    n_imp: int = 16
+    n_uni: int = 4
+    pe_octaves: int = 4
+    width: int = 64
+    layers: int = 2
+    lr: float = 1e-3
+    train: bool = True          # False: the untrained control, a uniform pdf (stratified samples only)
+    seed: int = 0
+
+
+class ProposalTrainer(Trainer):
+    """Training step with proposal-guided samples: the proposal network scores
+    n_bins depth bins per primary ray, n_imp depths are drawn from its pdf and
+    n_uni stratified uniform depths keep the whole range covered.  The SDF
+    network is trained exactly as in full-space training (matched-filter loss,
+    the measured signal's filter output recomputed at the new points); the
+    proposal is trained on the render's own blend weights T alpha at the drawn
+    depths (binned, normalised, BCE)."""
+
+    def __init__(self, cfg: StepConfig, params: torch.Tensor, target_signal: torch.Tensor,
+                 pcfg: ProposalConfig, prop_params: Optional[torch.Tensor] = None, device="cuda"):
+        super().__init__(cfg, params, target_signal, device)
+        self.pc = pcfg
+        n_ray = cfg.lines[0] * cfg.lines[1]
+        h = cfg.cube_side / 2
+        self.bin_xyz, _, _ = R.sample_points(cfg.cube_centre, h, (0.0, 0.0, 1.0), cfg.lines[0], cfg.lines[1],
+                                             pcfg.n_bins, mode=R.SAMPLE_GRID, device=self.dev)
+        self.lo = float(np.float32(cfg.cube_centre[2]) - np.float32(h))
+        self.hi = float(np.float32(cfg.cube_centre[2]) + np.float32(h))
+        self.zero_logits = torch.zeros(n_ray, pcfg.n_bins, device=self.dev)
+        self.prop = None
+        if pcfg.train:
+            if prop_params is None:
+                from synth.mlp_init import ProposalSpec, proposal_init
+                spec = ProposalSpec(pcfg.pe_octaves, pcfg.width, pcfg.layers, tuple(cfg.cube_centre), h)
+                prop_params = torch.from_numpy(proposal_init(spec, pcfg.seed))
+            self.prop = R.Proposal(params=prop_params.to(self.dev).contiguous(), pe_octaves=pcfg.pe_octaves,
+                                   width=pcfg.width, layers=pcfg.layers, centre=tuple(cfg.cube_centre),
+                                   half_size=h)
+            npp = self.prop.param_count()
+            assert self.prop.params.numel() == npp
+            self.pg = torch.zeros(npp, device=self.dev)
+            self.pm = torch.zeros(npp, device=self.dev)
+            self.pv = torch.zeros(npp, device=self.dev)
+        self.train_sdf = True
+
+    def logits(self):
+        n_ray = self.cfg.lines[0] * self.cfg.lines[1]
+        if self.prop is None:
+            return self.zero_logits
+        return R.proposal_forward(self.prop, self.bin_xyz).view(n_ray, self.pc.n_bins)
+
+    def proposal_samples(self, logits):
+        c, pc = self.cfg, self.pc
+        return R.sample_importance(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0], c.lines[1],
+                                   logits, pc.n_imp, pc.n_uni, seed=c.seed, step=self.t)
+
+    def step(self, timers: Optional[dict] = None):
+        c, pc = self.cfg, self.pc
+        ev = timers
+
+        def mark(name):
+            if ev is not None:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                ev.setdefault(name, []).append(e)
+
+        mark("start")
+        logits = self.logits()
+        xyz, u, origin = self.proposal_samples(logits)
+        n_ray, K = u.shape
+        mark("propose")
+        f, grad, a = R.mlp_forward(self.net, xyz)
+        f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
+        phi = R.occupancy(c.s, f_org)
+        mark("mlp_fwd")
+        sm = R.Samples(xyz=xyz)
+        fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=c.s,
+                      amp=1.0, amp_dev=self.amp, phi_ray=phi[:n_ray].contiguous(),
+                      phi_tx=phi[n_ray:].contiguous())
+        sig, alpha, trans = R.render_forward(self.ap, sm, fl, flags=c.spec_flags, want_alpha=True)
+        mark("render_fwd")
+        self.t += 1
+        loss = None
+        if self.train_sdf:
+            z, p, _, p_star = R.mf_forward(self.ap, xyz, sig, self.target)
+            mark("mf_fwd")
+            loss, g_p = R.loss_l2(p, p_star)
+            g_sig = R.mf_backward(self.ap, xyz, z, p, g_p)
+            mark("mf_bwd")
+            gr = R.render_backward(self.ap, sm, fl, g_sig, flags=c.spec_flags)
+            mark("render_bwd")
+            R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
+                           out=self.g)
+            mark("mlp_bwd")
+            P, G, M, V = self.net.params, self.g, self.m, self.v
+            ns = self.n_sdf
+            R.adamw(P[:ns], G[:ns], M[:ns], V[:ns], self.t, self.lr(c.lr_sdf))
+            R.adamw(P[ns:], G[ns:], M[ns:], V[ns:], self.t, self.lr(c.lr_other))
+            R.adamw(self.amp, gr["amp"], self.amp_m, self.amp_v, self.t, self.lr(c.lr_other))
+            mark("adamw")
+        if self.prop is not None:
+            t = R.proposal_targets(u, alpha.view(n_ray, K), trans.view(n_ray, K), self.lo, self.hi, pc.n_bins)
+            ploss, g_z = R.bce(logits, t)
+            R.proposal_backward(self.prop, self.bin_xyz, g_z, out=self.pg)
+            R.adamw(self.prop.params, self.pg, self.pm, self.pv, self.t, pc.lr)
+            self.last_proposal_loss = ploss
+            mark("proposal")
+        self.last = dict(signal=sig, loss=loss, xyz=xyz, u=u, alpha=alpha, trans=trans)
         return loss
 
