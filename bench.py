@@ -29,6 +29,38 @@ FLOP_PER_TERM = 8          # one complex multiply-add per term (4 FMA)
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 128 FMA/clk x 2 x 2.4 GHz)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "render_fwd_mlp_box_hbm_counters.md")
+TERM_KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_29097_amd", "csrc", f) for f in ("render.hip", "rfvr_impl.hpp")]
+
+
+def term_kernel_digest() -> str:
+    """sha256 over the sources of the signal-tracing term kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TERM_KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the term kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy), or None when the
+    kernel's sources changed after the counters were taken."""
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "source_sha256")):
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != term_kernel_digest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def make_inputs(cfg, dev):
     """Seeded network weights and the measured signal of the box scene."""
     import numpy as np
@@ -242,7 +274,7 @@ def main():
     t_rf = phases["render_fwd"] * 1e-3
     achieved = tpp * FLOP_PER_TERM / t_rf / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
                 "kernel": "k_reduce_points<64,0,CLAMP> (signal tracing forward)",
                 "launch_ms": round(phases["render_fwd"], 3)}
     out = {

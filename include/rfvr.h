@@ -129,10 +129,10 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
  * with the monostatic round trip d_iq = 2 |x_q - tx_i|.
  * xyz_q: [n_q][3] query points.  signal2: optional second signal filtered at
  * the same points (e.g. the measured one), with outputs z2/power2.
- * Any of z, power, z2, power2 may be NULL.
+ * Any of z, power, z2, power2 may be NULL.  flags: 0 or RFVR_PHASE_NAIVE32.
  * ------------------------------------------------------------------------ */
 size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_signals);
-int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q,
+int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, uint32_t flags,
                     const float* signal, float* z, float* power,
                     const float* signal2, float* z2, float* power2,
                     void* ws, size_t ws_bytes, void* stream);

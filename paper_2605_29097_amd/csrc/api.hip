@@ -257,11 +257,12 @@ size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_si
     return ws_mf_forward(ap, two_signals);
 }
 
-int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, const float* signal,
-                    float* z, float* power, const float* signal2, float* z2, float* power2,
-                    void* ws, size_t ws_bytes, void* stream) {
+int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, uint32_t flags,
+                    const float* signal, float* z, float* power, const float* signal2, float* z2,
+                    float* power2, void* ws, size_t ws_bytes, void* stream) {
     int rc;
     if ((rc = check_aperture(ap, false))) return rc;
+    if (flags & ~(uint32_t)RFVR_PHASE_NAIVE32) { set_error("only RFVR_PHASE_NAIVE32 is meaningful here"); return RFVR_E_INVALID; }
     if (n_q < 1 || !xyz_q || !signal) { set_error("n_q >= 1, xyz_q and signal are required"); return RFVR_E_INVALID; }
     if (n_q > (int64_t)1 << 40) { set_error("n_q too large"); return RFVR_E_INVALID; }
     const int two = signal2 ? 1 : 0;
@@ -280,7 +281,7 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, co
     if (two && (rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(signal2),
                                                   ap->n_meas, ap->n_freq, np, sp2, st), "pad signal2")))
         return rc;
-    return hip_status(launch_mf_forward(g, ant, xyz_q, (long)n_q, sp, sp2, np, 0,
+    return hip_status(launch_mf_forward(g, ant, xyz_q, (long)n_q, sp, sp2, np, flags,
                                         reinterpret_cast<float2*>(z), power,
                                         reinterpret_cast<float2*>(z2), power2, st),
                       "mf forward");

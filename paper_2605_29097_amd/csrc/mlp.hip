@@ -33,7 +33,13 @@ __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi) {
 }
 
 enum { PRO_ID = 0, PRO_SP = 1, PRO_DSP_MUL = 2, PRO_RELU = 3 };
-enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2 };
+// epilogues: BIAS  Y = acc + bias
+//            ACC   Y += acc
+//            RELUMASK  Y = acc where C > 0, else 0
+//            BIAS_SP   Y = acc + bias and Y2 = softplus(Y)            (layer output and activation)
+//            DSPMUL    Y = acc * softplus'(C)                          (normal sweep, adjoint to Z)
+//            DSP2      Y = acc and Y2 = acc * softplus'(C)              (tangent and its activation)
+enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_DSP2 = 5 };
 
 // Activation math of the network on the hardware exp2 / log2 / rcp units
 // (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once or twice per
@@ -80,9 +86,10 @@ struct GemmArgs {
     const float* A; const float* A2; long lda;
     const float* B; long ldb;
     const float* bias;            // EPI_BIAS: [M] or null
-    const float* C;               // EPI_RELUMASK: mask source [P][ldc]
+    const float* C;               // EPI_RELUMASK / DSPMUL / DSP2: [P][ldc]
     long ldc;
     float* Y; long ldy;
+    float* Y2;                    // EPI_BIAS_SP / DSP2: second output, row stride ldy
     long P; int M; int K;
     float beta;
 };
@@ -215,16 +222,19 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         for (int b = 0; b < TM; ++b) {
             const int m = m0 + wm * (BM / WM) + b * 16 + li;
             if (m >= g.M) continue;
-            const float bias = (EPI == EPI_BIAS && g.bias) ? g.bias[m] : 0.0f;
+            const float bias = ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP) && g.bias) ? g.bias[m] : 0.0f;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
                 if (p >= g.P) continue;
                 float y = acc[a][b][v];
-                if constexpr (EPI == EPI_BIAS) y += bias;
+                if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
                 if constexpr (EPI == EPI_ACC) y += g.Y[p * g.ldy + m];
                 if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
+                if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
                 g.Y[p * g.ldy + m] = y;
+                if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
+                if constexpr (EPI == EPI_DSP2) g.Y2[p * g.ldy + m] = y * sp_d1(g.C[p * g.ldc + m], g.beta);
             }
         }
 }
@@ -424,7 +434,8 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
         float d;
         if (mode == 0) d = x;
         else if (mode == 1) d = s[p] * fmaxf(x, 0.0f);
-        else d = (s ? s[p] * sp_f(x, beta) : 0.0f) + sp_d1(x, beta) * X2[p * ldx + m];
+        else if (mode == 2) d = (s ? s[p] * sp_f(x, beta) : 0.0f) + sp_d1(x, beta) * X2[p * ldx + m];
+        else d = (s ? s[p] * x : 0.0f) + X2[p * ldx + m];
         acc += d;
     }
     part[(long)blockIdx.x * M + m] = acc;
@@ -500,7 +511,7 @@ __global__ void k_pe_grad(long n, const float* __restrict__ xyz, float cx, float
 }
 
 // out[p] = post(scale * (sum_m w[m] act(Y[p][m]) + b)); one wave per row
-//   act: 1 softplus, 3 relu ; post: 0 identity, 1 sigmoid
+//   act: 0 identity, 1 softplus, 3 relu ; post: 0 identity, 1 sigmoid
 __global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict__ Y, long ldy,
                                                 int M, int act, int post, const float* __restrict__ w,
                                                 const float* __restrict__ b, float scale, float beta,
@@ -511,7 +522,7 @@ __global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict_
     float acc = 0.0f;
     for (int m = lane; m < M; m += 64) {
         const float y = Y[p * ldy + m];
-        const float a = act == PRO_SP ? sp_f(y, beta) : fmaxf(y, 0.0f);
+        const float a = act == PRO_ID ? y : (act == PRO_SP ? sp_f(y, beta) : fmaxf(y, 0.0f));
         acc = __builtin_fmaf(w[m], a, acc);
     }
 #pragma unroll
@@ -747,10 +758,10 @@ void gemm32(const GemmArgs& a, const Cx& cx) {
 
 GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
             float* Y, long ldy, long P, int M, int K, float beta, const float* C = nullptr,
-            long ldc = 0) {
+            long ldc = 0, float* Y2 = nullptr) {
     GemmArgs g;
     g.A = A; g.A2 = A2; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.C = C; g.ldc = ldc;
-    g.Y = Y; g.ldy = ldy; g.P = P; g.M = M; g.K = K; g.beta = beta;
+    g.Y = Y; g.ldy = ldy; g.Y2 = Y2; g.P = P; g.M = M; g.K = K; g.beta = beta;
     return g;
 }
 
@@ -813,7 +824,7 @@ size_t bwd_bytes(const Layout& l, long n) {
     const long c = n < kChunk ? n : kChunk;
     const long wmax = l.W > l.in0p ? l.W : l.in0p;
     return weights_bytes(l) + 2 * align256(sizeof(float) * c * l.in0p) +
-           2 * (size_t)l.L * align256(sizeof(float) * c * l.W) +   // Z, Zdot
+           4 * (size_t)l.L * align256(sizeof(float) * c * l.W) +   // Z, Zdot, H, Hdot
            4 * align256(sizeof(float) * c * l.W) +                  // Hbar, Hdotbar, Zbar, Zdotbar
            2 * (size_t)l.HL * align256(sizeof(float) * c * l.HW) +  // head Y, Ybar
            align256(sizeof(float) * c * l.HW) +                     // scratch head adjoint
@@ -878,33 +889,41 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
         const float* x = xyz + 3 * c0;
         hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0, nullptr, nullptr);
-        gemm32<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), cx);
+        // Z_i = H_{i-1} W_i^T + b_i and H_i = sp(Z_i) from the epilogue; the
+        // activations live in the two sweep buffers until the sweep starts
+        float* H[2] = {G[0], G[1]};
+        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
+                                       nullptr, 0, H[0]), cx);
         for (int i = 1; i < l.L; ++i)
-            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), cx);
+            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[(i - 1) & 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W,
+                                         beta, nullptr, 0, H[i & 1]), cx);
+        float* Ht = H[(l.L - 1) & 1];
         float* Zt = Z[l.L - 1];
         if (sdf)
-            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Zt, (long)l.W, l.W,
-                               (int)PRO_SP, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
+            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
+                               (int)PRO_ID, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
         if (refl) {
-            gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
+            gemm<PRO_ID, EPI_BIAS>(ga(Ht, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
             for (int h = 1; h < l.HL; ++h)
                 gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                                l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
         if (grad) {
-            // G^(L) = w_out; G^(i) = (sp'(Z^(i)) . G^(i+1)) W_i
+            // adjoint of f w.r.t. Z_{L-1}: sp'(Z_{L-1}) w_out; then
+            // dZ_{i-1} = (dZ_i W_i) . sp'(Z_{i-1}) (epilogue) and dgamma = dZ_0 W_0
             hipLaunchKernelGGL(k_seed, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, Zt, (long)l.W,
                                P + l.o_wout, beta, G[0]);
             int cur_g = 0;
             for (int i = l.L - 1; i >= 0; --i) {
                 const int mout = i == 0 ? l.in0p : l.W;
                 float* dst = G[cur_g ^ 1];
-                const Cx& cxi = i == 0 ? cx32 : cx;      // the product with W_0 stays FP32
-                if (i == l.L - 1)
-                    gemm<PRO_ID, EPI_BIAS>(ga(G[cur_g], nullptr, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), cxi);
-                else
-                    gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i], G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta), cxi);
+                if (i > 0)
+                    gemm<PRO_ID, EPI_DSPMUL>(ga(G[cur_g], nullptr, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W,
+                                                beta, Z[i - 1], l.W), cx);
+                else    // the product with W_0 stays FP32
+                    gemm32<PRO_ID, EPI_BIAS>(ga(G[cur_g], nullptr, l.W, w.WT[0], l.W, nullptr, dst, mout, m, mout, l.W,
+                                                beta), cx);
                 cur_g ^= 1;
             }
             hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
@@ -942,9 +961,11 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
     const Weights w = take_weights(cur, l);
     float* X0 = cur.take<float>((size_t)chunk * l.in0p);
     float* X0d = cur.take<float>((size_t)chunk * l.in0p);
-    float *Z[16], *Zd[16];
+    float *Z[16], *Zd[16], *H[16], *Hd[16];
     for (int i = 0; i < l.L; ++i) Z[i] = cur.take<float>((size_t)chunk * l.W);
     for (int i = 0; i < l.L; ++i) Zd[i] = cur.take<float>((size_t)chunk * l.W);
+    for (int i = 0; i < l.L; ++i) H[i] = cur.take<float>((size_t)chunk * l.W);
+    for (int i = 0; i < l.L; ++i) Hd[i] = cur.take<float>((size_t)chunk * l.W);
     float* Hb = cur.take<float>((size_t)chunk * l.W);
     float* Hdb = cur.take<float>((size_t)chunk * l.W);
     float* Zb = cur.take<float>((size_t)chunk * l.W);
@@ -969,16 +990,21 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
-        gemm32<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta), cx);
-        gemm32<PRO_ID, EPI_BIAS>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Zd[0], l.W, m, l.W, l.in0p, beta), cx);
+        // (Z_i, H_i = sp(Z_i)) and (Zdot_i, Hdot_i = sp'(Z_i) Zdot_i), activations from the epilogues
+        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
+                                       nullptr, 0, H[0]), cx);
+        gemm32<PRO_ID, EPI_DSP2>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Zd[0], l.W, m, l.W, l.in0p, beta,
+                                    Z[0], l.W, Hd[0]), cx);
         for (int i = 1; i < l.L; ++i) {
-            gemm<PRO_SP, EPI_BIAS>(ga(Z[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta), cx);
-            gemm<PRO_DSP_MUL, EPI_BIAS>(ga(Z[i - 1], Zd[i - 1], l.W, w.Wp[i], l.W, nullptr, Zd[i], l.W, m, l.W, l.W, beta), cx);
+            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta,
+                                         nullptr, 0, H[i]), cx);
+            gemm<PRO_ID, EPI_DSP2>(ga(Hd[i - 1], nullptr, l.W, w.Wp[i], l.W, nullptr, Zd[i], l.W, m, l.W, l.W, beta,
+                                      Z[i], l.W, Hd[i]), cx);
         }
-        float* Zt = Z[l.L - 1];
-        float* Zdt = Zd[l.L - 1];
+        float* Ht = H[l.L - 1];
+        float* Hdt = Hd[l.L - 1];
         // head forward
-        gemm<PRO_SP, EPI_BIAS>(ga(Zt, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
+        gemm<PRO_ID, EPI_BIAS>(ga(Ht, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
         for (int h = 1; h < l.HL; ++h)
             gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
         // head output: ybar3, Ybar_{HL-1}
@@ -997,7 +1023,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                 // Ybar_{h-1} = (Ybar_h Wh_h) . relu'(Y_{h-1})
                 gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), cx);
             } else {
-                wgrad<PRO_SP>(Yb, l.HW, l.HW, Zt, nullptr, l.W, l.W, m, beta, part, cx, bpart);
+                wgrad<PRO_ID>(Yb, l.HW, l.HW, Ht, nullptr, l.W, l.W, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.W, l.W, GP + l.oWh[0], acc, st);
                 hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
                                    l.HW, GP + l.obh[0], acc);
@@ -1008,7 +1034,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                            half, (long)l.W, Hb, Hdb);
         gemm<PRO_ID, EPI_ACC>(ga(Ybh[0], nullptr, l.HW, w.WhT[0], l.HW, nullptr, Hb, l.W, m, l.W, l.HW, beta), cx);
         // sdf output layer: w_out_bar = half sum (g_f H + Hdot), b_out_bar = half sum g_f
-        colsum(Zt, Zdt, gf, l.W, m, l.W, 2, beta, half, cpart, GP + l.o_wout, acc, st);
+        colsum(Ht, Hdt, gf, l.W, m, l.W, 3, beta, half, cpart, GP + l.o_wout, acc, st);
         if (gf) colsum(gf, nullptr, nullptr, 1, m, 1, 0, beta, half, cpart, GP + l.o_bout, acc, st);
         else if (!acc) hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, GP + l.o_bout, 1L, 0.0f);
         // trunk layers, top down
@@ -1021,9 +1047,9 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                 wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
                               part + (size_t)kWgSplits * l.W * finp, cx32);
             } else {
-                wgrad<PRO_SP>(Zb, l.W, l.W, Z[i - 1], nullptr, l.W, finp, m, beta, part, cx, bpart);
-                wgrad<PRO_DSP_MUL>(Zdb, l.W, l.W, Z[i - 1], Zd[i - 1], l.W, finp, m, beta,
-                                   part + (size_t)kWgSplits * l.W * finp, cx);
+                wgrad<PRO_ID>(Zb, l.W, l.W, H[i - 1], nullptr, l.W, finp, m, beta, part, cx, bpart);
+                wgrad<PRO_ID>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta,
+                              part + (size_t)kWgSplits * l.W * finp, cx);
             }
             wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st);
             hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,

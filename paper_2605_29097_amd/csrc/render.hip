@@ -150,6 +150,9 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
 #ifndef RFVR_RP_ACCURATE_STEP
 #define RFVR_RP_ACCURATE_STEP 1
 #endif
+#ifndef RFVR_RP_CHEB
+#define RFVR_RP_CHEB 0
+#endif
 
 template <int F, int KIND, int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_reduce_points(
@@ -243,6 +246,35 @@ __global__ __launch_bounds__(256) void k_reduce_points(
                 // (cr + j ci) * exp(-j 2 pi theta_centre)
                 const float pr0 = __builtin_fmaf(cr, c0, ci * s0);
                 const float pi0 = __builtin_fmaf(ci, c0, -cr * s0);
+#if RFVR_RP_CHEB
+                // three-term recurrence p_{n+1} = 2 cos(2 pi delta) p_n - p_{n-1}
+                // (both parts), seeded with p_0 and p_{+-1} = p_0 w^{+-1}
+                const float k2 = 2.0f * wr;
+                {
+                    float ar0 = pr0, ai0 = pi0;
+                    float ar1 = __builtin_fmaf(pr0, wr, -pi0 * wi), ai1 = __builtin_fmaf(pr0, wi, pi0 * wr);
+                    ar[m * S + S / 2] += ar0;
+                    ai[m * S + S / 2] += ai0;
+#pragma unroll
+                    for (int u = S / 2 + 1; u < S; ++u) {
+                        ar[m * S + u] += ar1;
+                        ai[m * S + u] += ai1;
+                        const float tr = __builtin_fmaf(k2, ar1, -ar0), ti = __builtin_fmaf(k2, ai1, -ai0);
+                        ar0 = ar1; ai0 = ai1; ar1 = tr; ai1 = ti;
+                    }
+                    ar0 = pr0; ai0 = pi0;
+                    ar1 = __builtin_fmaf(pr0, wr, pi0 * wi);
+                    ai1 = __builtin_fmaf(pi0, wr, -pr0 * wi);
+#pragma unroll
+                    for (int u = S / 2 - 1; u >= 0; --u) {
+                        ar[m * S + u] += ar1;
+                        ai[m * S + u] += ai1;
+                        const float tr = __builtin_fmaf(k2, ar1, -ar0), ti = __builtin_fmaf(k2, ai1, -ai0);
+                        ar0 = ar1; ai0 = ai1; ar1 = tr; ai1 = ti;
+                    }
+                }
+                continue;
+#endif
                 float pr = pr0, pi = pi0;
 #pragma unroll
                 for (int u = S / 2; u < S; ++u) {

@@ -74,7 +74,7 @@ _SIGS = {
     "rfvr_render_backward": ([_P(CAperture), _P(CSamples), _P(CFields), _c_u32, _vp, _vp, _vp, _vp,
                               _vp, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_mf_forward_ws_bytes": ([_P(CAperture), _c_i64, _c_i32], _sz),
-    "rfvr_mf_forward": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+    "rfvr_mf_forward": ([_P(CAperture), _vp, _c_i64, _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
                         _c_i32),
     "rfvr_mf_backward_ws_bytes": ([_P(CAperture), _c_i64], _sz),
     "rfvr_mf_backward": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
@@ -265,7 +265,7 @@ def mf_forward(ap: Aperture, xyz_q: torch.Tensor, signal: torch.Tensor, signal2=
         p2 = torch.empty_like(p)
     nb = lib().rfvr_mf_forward_ws_bytes(ctypes.byref(cap), nq, 1 if signal2 is not None else 0)
     ws = _ws(nb, dev)
-    _check(lib().rfvr_mf_forward(ctypes.byref(cap), _ptr(xyz_q.contiguous()), nq,
+    _check(lib().rfvr_mf_forward(ctypes.byref(cap), _ptr(xyz_q.contiguous()), nq, int(flags),
                                  _ptr(signal.contiguous()), _ptr(z), _ptr(p),
                                  _ptr(signal2.contiguous() if signal2 is not None else None),
                                  _ptr(z2), _ptr(p2), _ptr(ws), ws.numel(), _stream(stream)),

@@ -120,8 +120,9 @@ def test_mf_and_loss_reject_bad_arguments(R):
     L = R.lib()
     ap = _ap(R)
     v = ctypes.c_void_p(0x1000)
-    assert L.rfvr_mf_forward(ctypes.byref(ap), v, 0, v, v, v, None, None, None, v, 1 << 20, None) == -1
-    assert L.rfvr_mf_forward(ctypes.byref(ap), None, 10, v, v, v, None, None, None, v, 1 << 20, None) == -1
+    assert L.rfvr_mf_forward(ctypes.byref(ap), v, 0, 0, v, v, v, None, None, None, v, 1 << 20, None) == -1
+    assert L.rfvr_mf_forward(ctypes.byref(ap), None, 10, 0, v, v, v, None, None, None, v, 1 << 20, None) == -1
+    assert L.rfvr_mf_forward(ctypes.byref(ap), v, 10, 0x8, v, v, v, None, None, None, v, 1 << 20, None) == -1
     assert L.rfvr_mf_backward(ctypes.byref(ap), v, 10, v, v, None, 0, v, v, 1 << 20, None) == -1
     assert L.rfvr_loss_l2(0, v, v, None, v, None, v, 256, None) == -1
     assert L.rfvr_loss_l2(10, v, v, None, v, None, None, 0, None) == -2
