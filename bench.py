@@ -154,15 +154,18 @@ def proposal_study(args, dev):
     proposal-sampled training (16 importance + 4 uniform depths per ray, 81,920
     points) and the untrained control (20 stratified uniform depths), from the
     same initial network.  Every run is judged by the full-space render of its
-    network against the clean target (signal NRMSE); E* is the full-space run's
-    judge NRMSE after its step budget.  Prints one JSON line."""
+    network against the clean target: signal NRMSE and heatmap (filter output)
+    NRMSE on the full-space grid.  E* is the full-space run's judge error after
+    its step budget; steps_to_e_star is the first evaluation at or below it.
+    Prints one JSON line."""
     import numpy as np
     import torch
-    from paper_2605_29097_amd.train import (ProposalConfig, ProposalTrainer, StepConfig, Trainer, nrmse)
+    from paper_2605_29097_amd.train import ProposalConfig, ProposalTrainer, StepConfig, Trainer
     from synth import MLPSpec, mlp_init
-    cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28))
+    cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28), learn_s=args.study_learn_s, s=args.study_s)
     spec = MLPSpec(centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
-    data = np.load(os.path.join(ROOT, "tests", "golden", "torus_target.npz"))
+    name = "torus_target.npz" if cfg.s == 64.0 else f"torus_target_s{int(cfg.s)}.npz"
+    data = np.load(os.path.join(ROOT, "tests", "golden", name))      # rendered by the oracle at this s
     to_t = lambda a: torch.from_numpy(np.stack([a.real, a.imag], -1).astype(np.float32)).to(dev)
     noisy, clean = to_t(data["noisy"]), to_t(data["clean"])
     runs = {
@@ -176,7 +179,8 @@ def proposal_study(args, dev):
     out = {}
     for name, (make, n_steps) in runs.items():
         tr = make(torch.from_numpy(mlp_init(spec, cfg.seed)))
-        curve = [(0, nrmse(tr.judge_signal(), clean))]
+        j = tr.judge(clean)
+        curve = [(0, j["signal"], j["heatmap"])]
         step_ms = []
         for k in range(1, n_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -186,17 +190,21 @@ def proposal_study(args, dev):
             e1.synchronize()
             step_ms.append(e0.elapsed_time(e1))
             if k % every == 0 or k == n_steps:
-                curve.append((k, nrmse(tr.judge_signal(), clean)))
-                print(f"[study] {name} step {k} judge nrmse {curve[-1][1]:.4f} "
-                      f"({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
+                j = tr.judge(clean)
+                curve.append((k, j["signal"], j["heatmap"]))
+                print(f"[study] {name} step {k} judge signal {j['signal']:.4f} heatmap {j['heatmap']:.4f} "
+                      f"s {tr.s:.1f} ({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
         out[name] = {"ms_per_step": float(np.median(step_ms[2:] if len(step_ms) > 4 else step_ms)),
-                     "steps": n_steps, "judge_nrmse": [[k, round(e, 5)] for k, e in curve]}
-    e_star = out["full_space"]["judge_nrmse"][-1][1]
+                     "steps": n_steps, "final_s": tr.s,
+                     "judge": [[k, round(a, 5), round(b, 5)] for k, a, b in curve]}
+    e_star = {"signal": out["full_space"]["judge"][-1][1], "heatmap": out["full_space"]["judge"][-1][2]}
     for name, r in out.items():
-        hit = next((k for k, e in r["judge_nrmse"] if e <= e_star), None)
-        r["steps_to_e_star"] = hit
-        r["ms_to_e_star"] = None if hit is None else round(hit * r["ms_per_step"], 1)
+        for col, key in ((1, "signal"), (2, "heatmap")):
+            hit = next((row[0] for row in r["judge"] if row[col] <= e_star[key]), None)
+            r[f"steps_to_e_star_{key}"] = hit
+            r[f"ms_to_e_star_{key}"] = None if hit is None else round(hit * r["ms_per_step"], 1)
     print(json.dumps({"study": "proposal_vs_full_space", "e_star": e_star, "eval_every": every,
+                      "learn_s": cfg.learn_s, "s0": cfg.s,
                       "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
                                "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
                       "runs": out}))
@@ -218,6 +226,9 @@ def main():
     ap.add_argument("--study-full-steps", type=int, default=300)
     ap.add_argument("--study-prop-steps", type=int, default=1200)
     ap.add_argument("--study-eval-every", type=int, default=50)
+    ap.add_argument("--study-learn-s", action="store_true", help="train log s in every run")
+    ap.add_argument("--study-s", type=float, default=64.0,
+                    help="initial s (1/m); the target is the oracle render of the scene at this s")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "

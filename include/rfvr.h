@@ -195,6 +195,9 @@ int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* r
  * ------------------------------------------------------------------------ */
 #define RFVR_PREC_FP32 0
 #define RFVR_PREC_BF16 1         /* BF16 matrix operands, FP32 accumulation */
+#define RFVR_PREC_BF16X3 2       /* BF16 MFMA on split operands, x = big + small with
+                                    big = bf16(x), small = bf16(x - big); products
+                                    big*big + big*small + small*big, FP32 accumulation */
 typedef struct rfvr_mlp {
     int32_t      n_layers;       /* 1..16 */
     int32_t      width;          /* multiple of 64, <= 512 */

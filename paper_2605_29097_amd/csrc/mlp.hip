@@ -32,6 +32,20 @@ __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi) {
     return r;
 }
 
+// x = big + small with big = bf16(x), small = bf16(x - big): 16 significant bits
+__device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big, bf16x8& small) {
+    big = to_bf16x8(lo, hi);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        small[e] = (__bf16)(lo[e] - (float)big[e]);
+        small[4 + e] = (__bf16)(hi[e] - (float)big[4 + e]);
+    }
+}
+
+// operand precision of a network GEMM: FP32 MFMA, BF16 MFMA, or BF16 MFMA on
+// split operands (a b ~ a_big b_big + a_big b_small + a_small b_big)
+enum { MM_FP32 = 0, MM_BF16 = 1, MM_BF16X3 = 3 };
+
 enum { PRO_ID = 0, PRO_SP = 1, PRO_DSP_MUL = 2, PRO_RELU = 3 };
 // epilogues: BIAS  Y = acc + bias
 //            ACC   Y += acc
@@ -94,7 +108,7 @@ struct GemmArgs {
     float beta;
 };
 
-template <int PRO, int EPI, int BM, bool BF>
+template <int PRO, int EPI, int BM, int MM>
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     constexpr int BP = 128, BK = 32, LW = BK + 4;
     constexpr int WP = (BM == 128) ? 2 : 4;
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         }
         __syncthreads();
         if (k0 + BK < g.K) load(k0 + BK);
-        if constexpr (BF) {
+        if constexpr (MM == MM_BF16) {
             // the chunk's two 16-wide k groups feed one 16x16x32 BF16 MFMA
             bf16x8 af[TP], bf[TM];
 #pragma unroll
@@ -195,6 +209,26 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
                 for (int b = 0; b < TM; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+        } else if constexpr (MM == MM_BF16X3) {
+            bf16x8 ab[TP], as[TP], bb[TM], bs[TM];
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                const float* r = &sA[(wp * (BP / WP) + a * 16 + li) * LW + lg * 4];
+                split_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16), ab[a], as[a]);
+            }
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const float* r = &sB[(wm * (BM / WM) + b * 16 + li) * LW + lg * 4];
+                split_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16), bb[b], bs[b]);
+            }
+#pragma unroll
+            for (int a = 0; a < TP; ++a)
+#pragma unroll
+                for (int b = 0; b < TM; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[a], bb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[a], bs[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[a], bb[b], acc[a][b], 0, 0, 0);
+                }
         } else {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
@@ -256,7 +290,7 @@ struct WgArgs {
     float beta;
 };
 
-template <int PRO, bool BIAS, bool BF>
+template <int PRO, bool BIAS, int MM>
 __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
     constexpr int BM = 128, BN = 128, BK = 32, LW = 128 + 4;
     constexpr bool TWO = PRO == PRO_DSP_MUL;
@@ -335,7 +369,7 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
                 for (int r = 0; r < BK; ++r) bsum += sA[r * LW + tid];
             }
         }
-        if constexpr (BF) {
+        if constexpr (MM != MM_FP32) {
             // points lg*4 + s and 16 + lg*4 + s (s < 4) fill the 8 k slots of a lane
             floatx4 a0[4], a1[4], b0[4], b1[4];
 #pragma unroll
@@ -352,16 +386,32 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
                     b1[b][s] = sB[(r + 16) * LW + wn * 64 + b * 16 + li];
                 }
             }
-            bf16x8 af[4], bf[4];
+            if constexpr (MM == MM_BF16) {
+                bf16x8 af[4], bf[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) af[a] = to_bf16x8(a0[a], a1[a]);
+                for (int a = 0; a < 4; ++a) af[a] = to_bf16x8(a0[a], a1[a]);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bf[b] = to_bf16x8(b0[b], b1[b]);
+                for (int b = 0; b < 4; ++b) bf[b] = to_bf16x8(b0[b], b1[b]);
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+            } else {
+                bf16x8 ab[4], as[4], bb[4], bs[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) split_bf16x8(a0[a], a1[a], ab[a], as[a]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) split_bf16x8(b0[b], b1[b], bb[b], bs[b]);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[a], bb[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[a], bs[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[a], bb[b], acc[a][b], 0, 0, 0);
+                    }
+            }
         } else {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 16) {
@@ -407,8 +457,18 @@ __global__ void k_wg_reduce(const float* __restrict__ part, int n_split, int M, 
     const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= (long)M * k_real) return;
     const int m = (int)(o / k_real), k = (int)(o % k_real);
-    float s = 0.0f;
-    for (int t = 0; t < n_split; ++t) s += part[((long)t * M + m) * Kout + k];
+    // eight interleaved chains (t mod 8) keep eight loads in flight; the
+    // chains are combined in a fixed order, so the result is reproducible
+    const long stride = (long)M * Kout;
+    const float* q = part + (long)m * Kout + k;
+    float c[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    int t = 0;
+    for (; t + 8 <= n_split; t += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) c[u] += q[(long)(t + u) * stride];
+    }
+    for (; t < n_split; ++t) c[t & 7] += q[(long)t * stride];
+    const float s = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
     dst[o] = accumulate ? dst[o] + s : s;
 }
 
@@ -441,50 +501,60 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
     part[(long)blockIdx.x * M + m] = acc;
 }
 
-__global__ void k_colsum_final(const float* __restrict__ part, int nb, int M, float scale,
-                               float* __restrict__ dst, int accumulate) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
+// dst[m] (+)= scale * sum_b part[b][m]: one work-group per column, thread t
+// sums rows t, t + 256, ..., then a fixed-order tree over the 256 threads
+__global__ __launch_bounds__(256) void k_colsum_final(const float* __restrict__ part, int nb, int M,
+                                                      float scale, float* __restrict__ dst, int accumulate) {
+    __shared__ float sh[256];
+    const int m = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nb; ++b) s += part[(long)b * M + m];
-    s *= scale;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(long)b * M + m];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    s = sh[0] * scale;
     dst[m] = accumulate ? dst[m] + s : s;
 }
 
 // ----------------------------------------------------------------------------
 // positional encoding (and its tangent along v / half_size), zero padded to ld
 // ----------------------------------------------------------------------------
+// one thread per (point, column): consecutive threads write consecutive
+// columns of a row (coalesced); column e < 3: x_hat_e; e = 3 + 6k + j: sin
+// (j < 3) or cos (j >= 3) of 2^k pi x_hat_{j mod 3}; zero padding up to ld
 __global__ void k_pe(long n, const float* __restrict__ xyz, float cx, float cy, float cz,
                      float inv_half, int L, int ld, float* __restrict__ X,
                      const float* __restrict__ v, float* __restrict__ Xd) {
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const float c[3] = {cx, cy, cz};
-    float* row = X + p * ld;
-    float* drow = Xd ? Xd + p * ld : nullptr;
-    for (int d = 0; d < 3; ++d) {
-        const float xh = (xyz[3 * p + d] - c[d]) * inv_half;
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n * ld) return;
+    const long p = o / ld;
+    const int e = (int)(o % ld);
+    float val = 0.0f, dval = 0.0f;
+    if (e < 3 + 6 * L) {
+        const int d = e < 3 ? e : (e - 3) % 3;
+        const float c = d == 0 ? cx : (d == 1 ? cy : cz);
+        const float xh = (xyz[3 * p + d] - c) * inv_half;
         const float vd = v ? v[3 * p + d] * inv_half : 0.0f;
-        row[d] = xh;
-        if (drow) drow[d] = vd;
-        float scale = 1.0f;
-        for (int k = 0; k < L; ++k) {
+        if (e < 3) {
+            val = xh;
+            dval = vd;
+        } else {
+            const int k = (e - 3) / 6;
+            const bool is_cos = ((e - 3) % 6) >= 3;
+            const float scale = (float)(1 << k);
             float sn, cs;
             sincospif(scale * xh, &sn, &cs);
-            row[3 + 6 * k + d] = sn;
-            row[3 + 6 * k + 3 + d] = cs;
-            if (drow) {
-                const float w = 3.14159265358979f * scale * vd;
-                drow[3 + 6 * k + d] = cs * w;
-                drow[3 + 6 * k + 3 + d] = -sn * w;
-            }
-            scale *= 2.0f;
+            const float w = 3.14159265358979f * scale * vd;
+            val = is_cos ? cs : sn;
+            dval = is_cos ? -sn * w : cs * w;
         }
     }
-    for (int k = 3 + 6 * L; k < ld; ++k) {
-        row[k] = 0.0f;
-        if (drow) drow[k] = 0.0f;
-    }
+    X[o] = val;
+    if (Xd) Xd[o] = dval;
 }
 
 // grad_x f = J_PE^T G0 (G0 = dF/dgamma, row stride ld)
@@ -644,7 +714,7 @@ int check_net(const rfvr_mlp* n) {
         set_error("softplus_beta and half_size must be > 0");
         return RFVR_E_INVALID;
     }
-    if (n->precision != RFVR_PREC_FP32 && n->precision != RFVR_PREC_BF16) {
+    if (n->precision != RFVR_PREC_FP32 && n->precision != RFVR_PREC_BF16 && n->precision != RFVR_PREC_BF16X3) {
         set_error("unknown precision %d", n->precision);
         return RFVR_E_INVALID;
     }
@@ -724,36 +794,41 @@ hipError_t prep_weights(const Layout& l, const float* P, const Weights& w, hipSt
     return hipGetLastError();
 }
 
+int mm_of(int precision) {
+    return precision == RFVR_PREC_BF16 ? MM_BF16 : (precision == RFVR_PREC_BF16X3 ? MM_BF16X3 : MM_FP32);
+}
+
 // launch context of the network passes: stream and matrix-operand precision
 // (bf: BF16 operands, FP32 accumulation; layers reading the encoding stay FP32)
 struct Cx {
     hipStream_t st;
-    bool bf;
+    int mm;        // MM_*
 };
 
-template <int PRO, int EPI, bool BF>
+template <int PRO, int EPI, int MM>
 void gemm_launch(const GemmArgs& a, hipStream_t st) {
     const long tiles = (a.P + 127) / 128;
     const long groups = (tiles + 7) / 8;                 // 8 point tiles per XCD group
     if (a.M <= 64) {
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64, BF>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64, MM>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
     } else {
         const long nmb = (a.M + 127) / 128;
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128, BF>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128, MM>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
                            st, a);
     }
 }
 
 template <int PRO, int EPI>
 void gemm(const GemmArgs& a, const Cx& cx) {
-    if (cx.bf) gemm_launch<PRO, EPI, true>(a, cx.st);
-    else gemm_launch<PRO, EPI, false>(a, cx.st);
+    if (cx.mm == MM_BF16) gemm_launch<PRO, EPI, MM_BF16>(a, cx.st);
+    else if (cx.mm == MM_BF16X3) gemm_launch<PRO, EPI, MM_BF16X3>(a, cx.st);
+    else gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
 }
 
 // FP32 GEMM whatever the context (first layer: its operand is the encoding)
 template <int PRO, int EPI>
 void gemm32(const GemmArgs& a, const Cx& cx) {
-    gemm_launch<PRO, EPI, false>(a, cx.st);
+    gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
 }
 
 GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
@@ -777,23 +852,16 @@ void wgrad(const float* A, long lda, int M, const float* B, const float* B2, lon
     const long tiles = (long)((M + 127) / 128) * ((Kout + 127) / 128);
     const long groups = (kWgSplits + 7) / 8;
     const dim3 grid((unsigned)(groups * 8 * tiles));
-    if (cx.bf) {
-        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, true>), grid, dim3(256), 0, st, g);
-        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, true>), grid, dim3(256), 0, st, g);
+    if (cx.mm == MM_BF16) {
+        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, MM_BF16>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, MM_BF16>), grid, dim3(256), 0, st, g);
+    } else if (cx.mm == MM_BF16X3) {
+        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, MM_BF16X3>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, MM_BF16X3>), grid, dim3(256), 0, st, g);
     } else {
-        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, false>), grid, dim3(256), 0, st, g);
-        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, false>), grid, dim3(256), 0, st, g);
+        if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, MM_FP32>), grid, dim3(256), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_wg<PRO, false, MM_FP32>), grid, dim3(256), 0, st, g);
     }
-}
-
-// dst[m] (+)= sum_s bpart[s][m]
-__global__ void k_bias_reduce(const float* __restrict__ bpart, int n_split, int M,
-                              float* __restrict__ dst, int accumulate) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    float s = 0.0f;
-    for (int t = 0; t < n_split; ++t) s += bpart[(long)t * M + m];
-    dst[m] = accumulate ? dst[m] + s : s;
 }
 
 void wg_reduce(const float* part, int n_split, int M, int Kout, int k_real, float* dst, int acc,
@@ -807,7 +875,7 @@ void colsum(const float* X, const float* X2, const float* s, long ldx, long P, i
     const long per = (P + kColBlocks - 1) / kColBlocks;
     hipLaunchKernelGGL(k_colsum_partial, dim3(kColBlocks), dim3(256), 0, st, X, X2, s, ldx, P, M, per,
                        mode, beta, part);
-    hipLaunchKernelGGL(k_colsum_final, dim3(blocks(M)), dim3(256), 0, st, part, kColBlocks, M, scale,
+    hipLaunchKernelGGL(k_colsum_final, dim3(M), dim3(256), 0, st, part, kColBlocks, M, scale,
                        dst, acc);
 }
 
@@ -870,7 +938,7 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
         }
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const Cx cx{st, net->precision == RFVR_PREC_BF16}, cx32{st, false};
+    const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
     const float* P = net->params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
     const long chunk = n < kChunk ? (long)n : kChunk;
@@ -887,7 +955,7 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
     for (long c0 = 0; c0 < n; c0 += chunk) {
         const long m = (n - c0) < chunk ? (n - c0) : chunk;
         const float* x = xyz + 3 * c0;
-        hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
+        hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0, nullptr, nullptr);
         // Z_i = H_{i-1} W_i^T + b_i and H_i = sp(Z_i) from the epilogue; the
         // activations live in the two sweep buffers until the sweep starts
@@ -951,7 +1019,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         }
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const Cx cx{st, net->precision == RFVR_PREC_BF16}, cx32{st, false};
+    const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
     const float* P = net->params;
     float* GP = g_params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
@@ -987,7 +1055,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         const float* gf = g_sdf ? g_sdf + c0 : nullptr;
         const float* ga_ = g_refl ? g_refl + c0 : nullptr;
         // primal and tangent forward
-        hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
+        hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
         // (Z_i, H_i = sp(Z_i)) and (Zdot_i, Hdot_i = sp'(Z_i) Zdot_i), activations from the epilogues
@@ -1018,15 +1086,15 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
             if (h > 0) {
                 wgrad<PRO_RELU>(Yb, l.HW, l.HW, Yh[h - 1], nullptr, l.HW, l.HW, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.HW, l.HW, GP + l.oWh[h], acc, st);
-                hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
-                                   l.HW, GP + l.obh[h], acc);
+                hipLaunchKernelGGL(k_colsum_final, dim3(l.HW), dim3(256), 0, st, bpart, kWgSplits, l.HW, 1.0f,
+                               GP + l.obh[h], acc);
                 // Ybar_{h-1} = (Ybar_h Wh_h) . relu'(Y_{h-1})
                 gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), cx);
             } else {
                 wgrad<PRO_ID>(Yb, l.HW, l.HW, Ht, nullptr, l.W, l.W, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.W, l.W, GP + l.oWh[0], acc, st);
-                hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.HW)), dim3(256), 0, st, bpart, kWgSplits,
-                                   l.HW, GP + l.obh[0], acc);
+                hipLaunchKernelGGL(k_colsum_final, dim3(l.HW), dim3(256), 0, st, bpart, kWgSplits, l.HW, 1.0f,
+                               GP + l.obh[0], acc);
             }
         }
         // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0, Hdot_bar = half w_out
@@ -1052,7 +1120,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                               part + (size_t)kWgSplits * l.W * finp, cx);
             }
             wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st);
-            hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,
+            hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
                                GP + l.ob[i], acc);
             if (i > 0) {
                 gemm<PRO_ID, EPI_BIAS>(ga(Zb, nullptr, l.W, w.WT[i], l.W, nullptr, Hb, l.W, m, l.W, l.W, beta), cx);
@@ -1161,7 +1229,7 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
         return RFVR_E_WORKSPACE;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const Cx cx{st, false};
+    const Cx cx{st, MM_FP32};
     const float* P = net->params;
     const long chunk = n < kChunk ? (long)n : kChunk;
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
@@ -1192,7 +1260,7 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
     for (long c0 = 0; c0 < n; c0 += chunk) {
         const long m = (n - c0) < chunk ? (n - c0) : chunk;
         const int acc = (c0 > 0 || (flags & RFVR_ACCUMULATE)) ? 1 : 0;
-        hipLaunchKernelGGL(k_pe, dim3(blocks(m)), dim3(256), 0, st, m, xyz + 3 * c0, net->centre[0],
+        hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, xyz + 3 * c0, net->centre[0],
                            net->centre[1], net->centre[2], inv_half, l.L, l.in0p, X0, nullptr, nullptr);
         gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, Wp[0], l.in0p, P + l.ob[0], A[0], l.W, m, l.W, l.in0p, beta), cx);
         for (int i = 1; i < l.layers; ++i)
@@ -1214,8 +1282,8 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
                 else
                     wgrad<PRO_RELU>(Ab, l.W, l.W, A[i - 1], nullptr, l.W, finp, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.W, finp, fin, g_params + l.oW[i], acc, st);
-                hipLaunchKernelGGL(k_bias_reduce, dim3(blocks(l.W)), dim3(256), 0, st, bpart, kWgSplits, l.W,
-                                   g_params + l.ob[i], acc);
+                hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
+                               g_params + l.ob[i], acc);
                 if (i > 0) {
                     gemm<PRO_ID, EPI_RELUMASK>(ga(Ab, nullptr, l.W, WT[i], l.W, nullptr, Ab2, l.W, m, l.W, l.W,
                                                   beta, A[i - 1], l.W), cx);

@@ -10,8 +10,10 @@
 //    global loads in flight).  Per (measurement, point) the path length (FP64) and the
 //    step phasor (accurately rounded) are set up once; every 16 frequencies a
 //    phasor is re-seeded from an FP64-reduced phase at the sub-chunk centre
-//    and the sub-chunk is walked by complex rotation both ways (f_n is linear
-//    in n).  Points are split across work-groups and the partial sums reduced
+//    and the sub-chunk is walked both ways (f_n is linear in n) by the
+//    three-term recurrence p_{n+1} = 2 cos(2 pi delta) p_n - p_{n-1} (2 FMA per
+//    term and part, RFVR_RP_CHEB; the complex-rotation walk is the
+//    alternative).  Points are split across work-groups and the partial sums reduced
 //    in a fixed order (no atomics).
 //  * backward: a lane owns one point; all lanes walk the same measurements, so
 //    measurement records and the incoming signal gradient row are scalar loads.
@@ -151,13 +153,13 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
 #define RFVR_RP_ACCURATE_STEP 1
 #endif
 #ifndef RFVR_RP_CHEB
-#define RFVR_RP_CHEB 0
+#define RFVR_RP_CHEB 1
 #endif
 
 template <int F, int KIND, int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_reduce_points(
     int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
-    const void* __restrict__ recs_v, long n_pts, long pts_per_split,
+    const void* __restrict__ recs_v, long n_pts, long pts_per_split, int n_split, int gx,
     float2* __restrict__ partial) {
     constexpr int S = F < 16 ? F : 16;           // re-seed interval
     constexpr int NS = F / S;
@@ -168,7 +170,14 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     constexpr int RB = KIND == 0 ? (int)sizeof(PtRec) : (int)sizeof(QRec);
     constexpr int V4 = TILE * RB / 16;           // float4 per tile (192 or 128)
     __shared__ float4 sRec[2][V4];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // 1-D grid, XCD-aware: work-groups are dealt round-robin over the 8 XCDs
+    // (id % 8), so the gx lane blocks of one point split get ids of one residue
+    // mod 8 and read the split's records through one L2
+    const long bid = blockIdx.x;
+    const int lb = (int)((bid / 8) % gx);
+    const long split = (bid / (8L * gx)) * 8 + (bid % 8);
+    if (split >= n_split) return;                 // padding work-groups (whole block)
+    const int t = lb * blockDim.x + threadIdx.x;
     int i = t % n_meas;
     int c = t / n_meas;
     const bool live_lane = c < n_chunks;
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(256) void k_reduce_points(
         ar[n] = 0.0f;
         ai[n] = 0.0f;
     }
-    const long j0 = (long)blockIdx.y * pts_per_split;
+    const long j0 = split * pts_per_split;
     long j1 = j0 + pts_per_split;
     if (j1 > n_pts) j1 = n_pts;
     const float4* src = reinterpret_cast<const float4*>(recs_v);
@@ -300,7 +309,7 @@ __global__ __launch_bounds__(256) void k_reduce_points(
         buf ^= 1;
     }
     if (live_lane) {
-        float2* out = partial + ((size_t)blockIdx.y * n_meas + i) * n_freq + (size_t)c * F;
+        float2* out = partial + ((size_t)split * n_meas + i) * n_freq + (size_t)c * F;
         const int nv = n_freq - c * F;
 #pragma unroll
         for (int n = 0; n < F; ++n)
@@ -313,10 +322,12 @@ static hipError_t launch_rp(const RenderGeom& g, const AntRec* ant, const void* 
                             float2* partial, hipStream_t st) {
     const int n_chunks = (g.n_freq + F - 1) / F;
     const long lanes = (long)g.n_meas * n_chunks;
-    dim3 grid((unsigned)((lanes + 255) / 256), (unsigned)n_split);
+    const int gx = (int)((lanes + 255) / 256);
+    const long groups = (n_split + 7) / 8;                // 8 splits per group, one per XCD
+    dim3 grid((unsigned)(groups * 8 * gx));
     const long per = (g.n_pts + n_split - 1) / n_split;
     hipLaunchKernelGGL((k_reduce_points<F, KIND, SPEC, NAIVE>), grid, dim3(256), 0, st, g.n_meas,
-                       g.n_freq, n_chunks, ant, g.K0, g.Kd, rec, g.n_pts, per, partial);
+                       g.n_freq, n_chunks, ant, g.K0, g.Kd, rec, g.n_pts, per, n_split, gx, partial);
     return hipGetLastError();
 }
 

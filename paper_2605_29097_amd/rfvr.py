@@ -24,7 +24,7 @@ SPEC_CLAMP, SPEC_RAW, SPEC_OFF = 0x0, 0x1, 0x2
 PHASE_FP64RR, PHASE_NAIVE32 = 0x0, 0x4
 ACCUMULATE = 0x8
 SAMPLE_GRID, SAMPLE_STRATIFIED = 0, 1
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
 ERRORS = {-1: "RFVR_E_INVALID", -2: "RFVR_E_WORKSPACE", -3: "RFVR_E_UNSUPPORTED", -4: "RFVR_E_HIP"}
 
 _c_i32, _c_i64, _c_u32, _c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64

@@ -50,6 +50,7 @@ class StepConfig:
     seed: int = 0
     spec_flags: int = R.SPEC_CLAMP
     bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
+    learn_s: bool = False                  # train log s with the head's learning rate
 
     @property
     def n_pts(self) -> int:
@@ -126,6 +127,8 @@ class Trainer:
         if self.perm is not None:
             target = target[torch.from_numpy(self.perm).to(self.dev)]
         self.target = target.contiguous()
+        self.s = float(cfg.s)
+        self._s_m = self._s_v = 0.0
         self.t = 0
         self.p_star = None
         self._xyz_key = None
@@ -161,11 +164,11 @@ class Trainer:
         # detached occupancies at the primary-ray origins and the antennas
         org = torch.cat([origin, self.tx], 0)
         f_org, _, _ = R.mlp_forward(self.net, org)
-        phi = R.occupancy(c.s, f_org)
+        phi = R.occupancy(self.s, f_org)
         mark("mlp_fwd")
         sm = R.Samples(xyz=xyz)
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
-                      refl=a.view(xyz.shape[:2]), s=c.s, amp=1.0, amp_dev=self.amp,
+                      refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
         ap_r, fl_r = self.ap, fl
         if c.bank_patch is None:
@@ -179,7 +182,7 @@ class Trainer:
             i0, i1 = k * self.patch_len, (k + 1) * self.patch_len
             ap_r = R.Aperture(tx=self.tx[i0:i1], f0=self.f0, df=self.df, n_freq=c.n_freq)
             n_ray = origin.shape[0]
-            fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=c.s, amp=1.0, amp_dev=self.amp,
+            fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=self.s, amp=1.0, amp_dev=self.amp,
                             phi_ray=fl.phi_ray, phi_tx=phi[n_ray + i0:n_ray + i1].contiguous())
             R.render_forward(ap_r, sm, fl_r, flags=c.spec_flags, out=self.bank[i0:i1])
             sig = self.bank
@@ -207,8 +210,22 @@ class Trainer:
         R.adamw(P[ns:], G[ns:], M[ns:], V[ns:], self.t, self.lr(c.lr_other))
         R.adamw(self.amp, gr["amp"], self.amp_m, self.amp_v, self.t, self.lr(c.lr_other))
         mark("adamw")
+        if c.learn_s:
+            self.update_s(gr["s"])
         self.last = dict(signal=sig, loss=loss)
         return loss
+
+    def update_s(self, g_s: torch.Tensor):
+        """Adam step on log s (host scalar: the kernels take s by value; this
+        reads one float back, so it synchronises the stream once per step)."""
+        c = self.cfg
+        g = float(g_s.item()) * self.s                       # d/dlog s
+        b1, b2, eps = 0.9, 0.999, 1e-8
+        self._s_m = b1 * self._s_m + (1 - b1) * g
+        self._s_v = b2 * self._s_v + (1 - b2) * g * g
+        mh = self._s_m / (1 - b1 ** self.t)
+        vh = self._s_v / (1 - b2 ** self.t)
+        self.s = float(math.exp(math.log(self.s) - self.lr(c.lr_other) * mh / (math.sqrt(vh) + eps)))
 
     # ------------------------------------------------------------------ judge
     def judge_signal(self):
@@ -219,11 +236,20 @@ class Trainer:
                                          c.lines[1], c.n_z, mode=R.SAMPLE_GRID, device=self.dev)
         f, grad, a = R.mlp_forward(self.net, xyz)
         f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
-        phi = R.occupancy(c.s, f_org)
+        phi = R.occupancy(self.s, f_org)
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
-                      refl=a.view(xyz.shape[:2]), s=c.s, amp=1.0, amp_dev=self.amp,
+                      refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
+        self._judge_xyz = xyz
         return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.spec_flags)
+
+    def judge(self, clean: torch.Tensor) -> dict:
+        """Judge errors of the full-space render against a clean target signal:
+        signal NRMSE, and NRMSE of the filter output (heatmap) on the full-space
+        grid."""
+        sig = self.judge_signal()
+        _, p, _, p_ref = R.mf_forward(self.ap, self._judge_xyz, sig, clean)
+        return {"signal": nrmse(sig, clean), "heatmap": nrmse(p, p_ref)}
 
 
 def nrmse(sig: torch.Tensor, ref: torch.Tensor) -> float:
@@ -308,10 +334,10 @@ class ProposalTrainer(Trainer):
         mark("propose")
         f, grad, a = R.mlp_forward(self.net, xyz)
         f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
-        phi = R.occupancy(c.s, f_org)
+        phi = R.occupancy(self.s, f_org)
         mark("mlp_fwd")
         sm = R.Samples(xyz=xyz)
-        fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=c.s,
+        fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=self.s,
                       amp=1.0, amp_dev=self.amp, phi_ray=phi[:n_ray].contiguous(),
                       phi_tx=phi[n_ray:].contiguous())
         sig, alpha, trans = R.render_forward(self.ap, sm, fl, flags=c.spec_flags, want_alpha=True)
@@ -335,6 +361,8 @@ class ProposalTrainer(Trainer):
             R.adamw(P[ns:], G[ns:], M[ns:], V[ns:], self.t, self.lr(c.lr_other))
             R.adamw(self.amp, gr["amp"], self.amp_m, self.amp_v, self.t, self.lr(c.lr_other))
             mark("adamw")
+            if c.learn_s:
+                self.update_s(gr["s"])
         if self.prop is not None:
             t = R.proposal_targets(u, alpha.view(n_ray, K), trans.view(n_ray, K), self.lo, self.hi, pc.n_bins)
             ploss, g_z = R.bce(logits, t)

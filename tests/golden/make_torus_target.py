@@ -4,8 +4,9 @@ Scene: torus R = 4 cm, r = 1 cm (axis z, a = 0.8) centred at (0, 0, 0.30) m behi
 a 1 cm slab z in [0.195, 0.205] m (a = 0.1), seen by a 32 x 32 monostatic
 aperture at 2 mm pitch, 128 frequencies 77-81 GHz, rendered at the full-space
 grid of that workload (64 x 64 lines x 256 depths in a 20 cm cube centred at
-(0, 0, 0.28) m), s = 64 / m, A' = 1, clamped specular factor; then circular
-complex Gaussian noise at 10 dB SNR (seed 0).  Output: torus_target.npz with
+(0, 0, 0.28) m), s = 64 / m (or the s given as the first argument), A' = 1,
+clamped specular factor; then circular complex Gaussian noise at 10 dB SNR
+(seed 0).  Output: torus_target.npz (torus_target_s<S>.npz for another s) with
 `clean` and `noisy` complex128 [1024, 128].  Only the oracle and the seeded
 generators are used.
 """
@@ -23,7 +24,9 @@ from synth import (Slab, Torus, Union, complex_noise, freq_grid, line_points,  #
                    planar_aperture, scene_fields)
 
 
-def main(out=os.path.join(HERE, "torus_target.npz")):
+def main(s=64.0, out=None):
+    if out is None:
+        out = os.path.join(HERE, "torus_target.npz" if s == 64.0 else f"torus_target_s{int(s)}.npz")
     f0, df = freq_grid(128)
     tx = planar_aperture(32, 32, 2e-3)
     xyz, _ = line_points((0.0, 0.0, 0.28), 0.20, 64, 64, 256)
@@ -31,7 +34,7 @@ def main(out=os.path.join(HERE, "torus_target.npz")):
     sdf, grad, refl = scene_fields(scene, xyz)
     ap = orc.Aperture(tx=tx.astype(np.float64), f0=f0, df=df, n_freq=128)
     F = orc.Fields(sdf=sdf.astype(np.float64), grad=grad.astype(np.float64), refl=refl.astype(np.float64),
-                   s=64.0, amp=1.0)
+                   s=s, amp=1.0)
     t0 = time.time()
     clean = orc.render(ap, xyz.astype(np.float64), F, spec="clamp")
     noisy = clean + complex_noise(clean, 10.0, seed=0)
@@ -40,4 +43,4 @@ def main(out=os.path.join(HERE, "torus_target.npz")):
 
 
 if __name__ == "__main__":
-    main()
+    main(float(sys.argv[1]) if len(sys.argv) > 1 else 64.0)

@@ -44,7 +44,21 @@ def _loss(R, A, net, ap, xyz, params, amp, s, p_star):
     return A.LossFn.apply(p, p_star)
 
 
+def _field_loss(R, A, ap, xyz, sdf, grad, refl, amp, s, p_star):
+    sig = A.RenderFn.apply(sdf, grad, refl, amp, s, ap, xyz)
+    z, p = A.MFFn.apply(sig, ap, xyz.view(-1, 3))
+    return A.LossFn.apply(p, p_star)
+
+
+def _fd_ok(fd, an, L, eps, rtol):
+    # FP32 forward: allow a rounding floor of ~1e-6 |L| in the loss difference
+    return abs(fd - an) <= rtol * abs(an) + 1e-6 * abs(L) / (2 * eps)
+
+
 def test_pipeline_gradient_finite_differences(dev):
+    """Central differences with eps = 1e-3 along random unit directions, in the
+    network parameters and in each per-point field entering the render (sdf,
+    grad, refl); relative eps = 1e-3 for A' and s."""
     _say("autograd pipeline vs finite differences (eps=1e-3)")
     from paper_2605_29097_amd import autograd as A
     R, spec, p_np, net, ap, xyz, *_ = _setup(dev)
@@ -54,33 +68,58 @@ def test_pipeline_gradient_finite_differences(dev):
     p_star = torch.rand(xyz.shape[0] * xyz.shape[1], device=dev, generator=torch.Generator(dev).manual_seed(1)) * 50
     L = _loss(R, A, net, ap, xyz, params, amp, s, p_star)
     L.backward()
+    Lv = L.item()
     gp, ga, gs = params.grad.clone(), amp.grad.clone(), s.grad.clone()
     gen = torch.Generator(dev).manual_seed(2)
-    checks = []
+    eps = 1e-3
     for k in range(3):
         d = torch.randn(params.shape, device=dev, generator=gen)
-        d = d / d.norm() * params.detach().norm()       # eps relative to the parameter scale
-        eps = 1e-3
+        d = d / d.norm()
         with torch.no_grad():
             Lp = _loss(R, A, net, ap, xyz, params + eps * d, amp, s, p_star)
             Lm = _loss(R, A, net, ap, xyz, params - eps * d, amp, s, p_star)
         fd = (Lp - Lm).item() / (2 * eps)
         an = (gp * d).sum().item()
-        checks.append((fd, an))
         print(f"params dir {k}: fd {fd:.6e} analytic {an:.6e}")
-        assert abs(fd - an) <= 2e-2 * abs(an) + 1e-6 * abs(L.item())
+        assert _fd_ok(fd, an, Lv, eps, 2e-2)
     with torch.no_grad():
-        eps = 1e-3 * amp.item()
-        fd = (_loss(R, A, net, ap, xyz, params, amp + eps, s, p_star) -
-              _loss(R, A, net, ap, xyz, params, amp - eps, s, p_star)).item() / (2 * eps)
+        e = 1e-3 * amp.item()
+        fd = (_loss(R, A, net, ap, xyz, params, amp + e, s, p_star) -
+              _loss(R, A, net, ap, xyz, params, amp - e, s, p_star)).item() / (2 * e)
     print(f"amp: fd {fd:.6e} analytic {ga.item():.6e}")
-    assert abs(fd - ga.item()) <= 1e-2 * abs(ga.item())
+    assert _fd_ok(fd, ga.item(), Lv, e, 1e-2)
     with torch.no_grad():
-        eps = 1e-3 * s.item()
-        fd = (_loss(R, A, net, ap, xyz, params, amp, s + eps, p_star) -
-              _loss(R, A, net, ap, xyz, params, amp, s - eps, p_star)).item() / (2 * eps)
+        e = 1e-3 * s.item()
+        fd = (_loss(R, A, net, ap, xyz, params, amp, s + e, p_star) -
+              _loss(R, A, net, ap, xyz, params, amp, s - e, p_star)).item() / (2 * e)
     print(f"s: fd {fd:.6e} analytic {gs.item():.6e}")
-    assert abs(fd - gs.item()) <= 2e-2 * abs(gs.item())
+    assert _fd_ok(fd, gs.item(), Lv, e, 2e-2)
+    # per-point fields
+    with torch.no_grad():
+        f, g, a = R.mlp_forward(net, xyz.view(-1, 3))
+    shp = xyz.shape[:2]
+    fields = [f.view(shp).clone().requires_grad_(), g.view(*shp, 3).clone().requires_grad_(),
+              a.view(shp).clone().requires_grad_()]
+    Lf = _field_loss(R, A, ap, xyz, *fields, amp.detach(), s.detach(), p_star)
+    Lf.backward()
+    # the sdf direction is a smooth random field (a plane wave of 10 cm
+    # wavelength over the points): neighbouring samples of a ray move together,
+    # as under any change of the network, instead of straddling the kink of the
+    # opacity clamp at alpha = 0 independently
+    kvec = torch.randn(3, device=dev, generator=gen)
+    kvec = 2 * np.pi / 0.10 * kvec / kvec.norm()
+    smooth = torch.cos(xyz.view(-1, 3) @ kvec + 0.3).view(shp)
+    for name, t in zip(("sdf", "grad", "refl"), fields):
+        d = smooth.clone() if name == "sdf" else torch.randn(t.shape, device=dev, generator=gen)
+        d = d / d.norm()
+        with torch.no_grad():
+            args_p = [x.detach() + (eps * d if x is t else 0) for x in fields]
+            args_m = [x.detach() - (eps * d if x is t else 0) for x in fields]
+            fd = (_field_loss(R, A, ap, xyz, *args_p, amp, s, p_star) -
+                  _field_loss(R, A, ap, xyz, *args_m, amp, s, p_star)).item() / (2 * eps)
+        an = (t.grad * d).sum().item()
+        print(f"{name}: fd {fd:.6e} analytic {an:.6e}")
+        assert _fd_ok(fd, an, Lf.item(), eps, 2e-2), name
 
 
 def test_pipeline_gradient_matches_oracle(dev):
