@@ -274,6 +274,191 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 }
 
 // ----------------------------------------------------------------------------
+// Two products with one B operand, Y = A B^T and Yd = A2 B^T (a layer's primal
+// and tangent, or the two adjoints of its input), the layer's elementwise work
+// in the epilogue:
+//   EPI2_FWD: Z = acc + bias, H = sp(Z), Zdot = acc2, Hdot = sp'(Z) Zdot
+//             -> Y, Y2, Y3, Y4
+//   EPI2_ADJ: Hbar = acc, Hdotbar = acc2 with C = Z, C2 = Zdot of the layer below:
+//             Zbar = sp'(Z) Hbar + sp''(Z) Zdot Hdotbar, Zdotbar = sp'(Z) Hdotbar
+//             -> Y, Y2
+// Tiling as k_gemm_nt with BM = 128; the B tile is staged once for both.
+// ----------------------------------------------------------------------------
+enum { EPI2_FWD = 0, EPI2_ADJ = 1 };
+
+struct DualArgs {
+    const float* A; const float* A2; long lda;
+    const float* B; long ldb;
+    const float* bias;
+    const float* C; const float* C2;        // EPI2_ADJ: [P][ldy]
+    float* Y; float* Y2; float* Y3; float* Y4; long ldy;
+    long P; int M; int K;
+    float beta;
+};
+
+template <int EPI2, int MM>
+__global__ __launch_bounds__(512) void k_gemm_dual(DualArgs g) {
+    // 8 waves: 4 along points x 2 along outputs, 2 x 4 tiles of 16 x 16 each,
+    // two accumulator sets (64 registers) per wave
+    constexpr int NT = 512;
+    constexpr int BP = 128, BM = 128, BK = 32, LW = BK + 4;
+    constexpr int WP = 4, TP = 2, TM = 4;
+    constexpr int NA = BP * BK / 4 / NT, NB = BM * BK / 4 / NT;
+    __shared__ float sA[BP * LW];
+    __shared__ float sA2[BP * LW];
+    __shared__ float sB[BM * LW];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int wp = wv % WP, wm = wv / WP;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nmb = (g.M + BM - 1) / BM;
+    const long bid = blockIdx.x;
+    const long grp = bid / (8L * nmb);
+    const int within = (int)(bid % (8L * nmb));
+    const int mb = within / 8;
+    const long pt = grp * 8 + (within % 8);
+    const long p0 = pt * BP;
+    const int m0 = mb * BM;
+    if (p0 >= g.P) return;                       // padding work-groups of the last group
+    floatx4 acc[TP][TM], acd[TP][TM];
+#pragma unroll
+    for (int a = 0; a < TP; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b) {
+            acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            acd[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    float4 ra[NA], ra2[NA], rb[NB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + i * NT;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            const long p = p0 + row;
+            ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            ra2[i] = ra[i];
+            if (p < g.P) {
+                const long off = p * g.lda + k0 + c4;
+                ra[i] = *reinterpret_cast<const float4*>(g.A + off);
+                ra2[i] = *reinterpret_cast<const float4*>(g.A2 + off);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * NT;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            const int m = m0 + row;
+            rb[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (m < g.M) rb[i] = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + i * NT;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            *reinterpret_cast<float4*>(&sA[row * LW + c4]) = ra[i];
+            *reinterpret_cast<float4*>(&sA2[row * LW + c4]) = ra2[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + i * NT;
+            const int row = e >> 3, c4 = (e & 7) * 4;
+            *reinterpret_cast<float4*>(&sB[row * LW + c4]) = rb[i];
+        }
+        __syncthreads();
+        if (k0 + BK < g.K) load(k0 + BK);
+        if constexpr (MM == MM_FP32) {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                floatx4 af[TP], af2[TP], bf[TM];
+#pragma unroll
+                for (int a = 0; a < TP; ++a) {
+                    const int r = (wp * (BP / WP) + a * 16 + li) * LW + kk + lg * 4;
+                    af[a] = *reinterpret_cast<const floatx4*>(&sA[r]);
+                    af2[a] = *reinterpret_cast<const floatx4*>(&sA2[r]);
+                }
+#pragma unroll
+                for (int b = 0; b < TM; ++b)
+                    bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / 2) + b * 16 + li) * LW + kk + lg * 4]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int a = 0; a < TP; ++a)
+#pragma unroll
+                        for (int b = 0; b < TM; ++b) {
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+                            acd[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af2[a][s], bf[b][s], acd[a][b], 0, 0, 0);
+                        }
+            }
+        } else {
+            bf16x8 bb[TM], bs[TM];
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const float* r = &sB[(wm * (BM / 2) + b * 16 + li) * LW + lg * 4];
+                if constexpr (MM == MM_BF16)
+                    bb[b] = to_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16));
+                else
+                    split_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16), bb[b], bs[b]);
+            }
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                const int off = (wp * (BP / WP) + a * 16 + li) * LW + lg * 4;
+#pragma unroll
+                for (int which = 0; which < 2; ++which) {
+                    const float* r = which ? &sA2[off] : &sA[off];
+                    floatx4* dst = which ? acd[a] : acc[a];
+                    if constexpr (MM == MM_BF16) {
+                        const bf16x8 ab = to_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16));
+#pragma unroll
+                        for (int b = 0; b < TM; ++b)
+                            dst[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb[b], dst[b], 0, 0, 0);
+                    } else {
+                        bf16x8 ab, as;
+                        split_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16), ab, as);
+#pragma unroll
+                        for (int b = 0; b < TM; ++b) {
+                            dst[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as, bb[b], dst[b], 0, 0, 0);
+                            dst[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bs[b], dst[b], 0, 0, 0);
+                            dst[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb[b], dst[b], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < TP; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b) {
+            const int m = m0 + wm * (BM / 2) + b * 16 + li;
+            if (m >= g.M) continue;
+            const float bias = (EPI2 == EPI2_FWD && g.bias) ? g.bias[m] : 0.0f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
+                if (p >= g.P) continue;
+                const long o = p * g.ldy + m;
+                if constexpr (EPI2 == EPI2_FWD) {
+                    const float z = acc[a][b][v] + bias, zd = acd[a][b][v];
+                    g.Y[o] = z;
+                    g.Y2[o] = sp_f(z, g.beta);
+                    g.Y3[o] = zd;
+                    g.Y4[o] = sp_d1(z, g.beta) * zd;
+                } else {
+                    const float z = g.C[o], zd = g.C2[o];
+                    const float sg = fsig(g.beta * z);
+                    const float d2 = g.beta * sg * (1.0f - sg);
+                    const float hb = acc[a][b][v], hdb = acd[a][b][v];
+                    g.Y[o] = sg * hb + d2 * zd * hdb;
+                    g.Y2[o] = sg * hdb;
+                }
+            }
+        }
+}
+
+// ----------------------------------------------------------------------------
 // Weight gradient partials: part[split][M][Kout] = sum over the split's points
 // of A[p][m] * pro(B)[p][k], and with BIAS also bpart[split][m] = sum_p A[p][m].
 // Block 128 (m) x 128 (k), chunks of 32 points kept point-major in LDS (float4
@@ -831,6 +1016,26 @@ void gemm32(const GemmArgs& a, const Cx& cx) {
     gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
 }
 
+template <int EPI2>
+void gemm_dual(const DualArgs& a, int mm, hipStream_t st) {
+    const long tiles = (a.P + 127) / 128;
+    const long groups = (tiles + 7) / 8;
+    const long nmb = (a.M + 127) / 128;
+    const dim3 grid((unsigned)(groups * 8 * nmb));
+    if (mm == MM_BF16) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16>), grid, dim3(512), 0, st, a);
+    else if (mm == MM_BF16X3) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16X3>), grid, dim3(512), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_FP32>), grid, dim3(512), 0, st, a);
+}
+
+DualArgs da(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
+            const float* C, const float* C2, float* Y, float* Y2, float* Y3, float* Y4, long ldy,
+            long P, int M, int K, float beta) {
+    DualArgs g;
+    g.A = A; g.A2 = A2; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.C = C; g.C2 = C2;
+    g.Y = Y; g.Y2 = Y2; g.Y3 = Y3; g.Y4 = Y4; g.ldy = ldy; g.P = P; g.M = M; g.K = K; g.beta = beta;
+    return g;
+}
+
 GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
             float* Y, long ldy, long P, int M, int K, float beta, const float* C = nullptr,
             long ldc = 0, float* Y2 = nullptr) {
@@ -1059,16 +1264,12 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
         // (Z_i, H_i = sp(Z_i)) and (Zdot_i, Hdot_i = sp'(Z_i) Zdot_i), activations from the epilogues
-        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
-                                       nullptr, 0, H[0]), cx);
-        gemm32<PRO_ID, EPI_DSP2>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Zd[0], l.W, m, l.W, l.in0p, beta,
-                                    Z[0], l.W, Hd[0]), cx);
-        for (int i = 1; i < l.L; ++i) {
-            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta,
-                                         nullptr, 0, H[i]), cx);
-            gemm<PRO_ID, EPI_DSP2>(ga(Hd[i - 1], nullptr, l.W, w.Wp[i], l.W, nullptr, Zd[i], l.W, m, l.W, l.W, beta,
-                                      Z[i], l.W, Hd[i]), cx);
-        }
+        // one dual GEMM per layer: (Z_i, H_i) and (Zdot_i, Hdot_i) share W_i
+        gemm_dual<EPI2_FWD>(da(X0, X0d, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], nullptr, nullptr, Z[0], H[0], Zd[0],
+                               Hd[0], l.W, m, l.W, l.in0p, beta), MM_FP32, st);
+        for (int i = 1; i < l.L; ++i)
+            gemm_dual<EPI2_FWD>(da(H[i - 1], Hd[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], nullptr, nullptr, Z[i], H[i],
+                                   Zd[i], Hd[i], l.W, m, l.W, l.W, beta), cx.mm, st);
         float* Ht = H[l.L - 1];
         float* Hdt = Hd[l.L - 1];
         // head forward
@@ -1105,10 +1306,14 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         colsum(Ht, Hdt, gf, l.W, m, l.W, 3, beta, half, cpart, GP + l.o_wout, acc, st);
         if (gf) colsum(gf, nullptr, nullptr, 1, m, 1, 0, beta, half, cpart, GP + l.o_bout, acc, st);
         else if (!acc) hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, GP + l.o_bout, 1L, 0.0f);
-        // trunk layers, top down
+        // trunk layers, top down: the top layer's (Zbar, Zdotbar) elementwise,
+        // the others from the dual adjoint GEMM of the layer above
+        hipLaunchKernelGGL(k_layer_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, (long)l.W,
+                           Z[l.L - 1], Zd[l.L - 1], Hb, Hdb, beta, Zb, Zdb);
+        float *Zb_c = Zb, *Zdb_c = Zdb, *Zb_n = Hb, *Zdb_n = Hdb;
         for (int i = l.L - 1; i >= 0; --i) {
-            hipLaunchKernelGGL(k_layer_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, (long)l.W,
-                               Z[i], Zd[i], Hb, Hdb, beta, Zb, Zdb);
+            float* Zb = Zb_c;
+            float* Zdb = Zdb_c;
             const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
             if (i == 0) {
                 wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32, bpart);
@@ -1123,8 +1328,10 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
             hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
                                GP + l.ob[i], acc);
             if (i > 0) {
-                gemm<PRO_ID, EPI_BIAS>(ga(Zb, nullptr, l.W, w.WT[i], l.W, nullptr, Hb, l.W, m, l.W, l.W, beta), cx);
-                gemm<PRO_ID, EPI_BIAS>(ga(Zdb, nullptr, l.W, w.WT[i], l.W, nullptr, Hdb, l.W, m, l.W, l.W, beta), cx);
+                gemm_dual<EPI2_ADJ>(da(Zb, Zdb, l.W, w.WT[i], l.W, nullptr, Z[i - 1], Zd[i - 1], Zb_n, Zdb_n, nullptr,
+                                       nullptr, l.W, m, l.W, l.W, beta), cx.mm, st);
+                float* t = Zb_c; Zb_c = Zb_n; Zb_n = t;
+                t = Zdb_c; Zdb_c = Zdb_n; Zdb_n = t;
             }
         }
         if ((rc = hip_status(hipGetLastError(), "mlp backward"))) return rc;
