@@ -149,11 +149,14 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
 // adjoint (KIND 1).  Lane t -> measurement i = t % n_meas, chunk c = t / n_meas;
 // grid.y = point split.
 // ---------------------------------------------------------------------------
-#ifndef RFVR_RP_ACCURATE_STEP
-#define RFVR_RP_ACCURATE_STEP 1
-#endif
 #ifndef RFVR_RP_CHEB
 #define RFVR_RP_CHEB 1
+#endif
+#ifndef RFVR_RP_SEED
+#define RFVR_RP_SEED 32
+#endif
+#ifndef RFVR_RP_ACC_SEED
+#define RFVR_RP_ACC_SEED 0
 #endif
 
 template <int F, int KIND, int SPEC, bool NAIVE>
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
     const void* __restrict__ recs_v, long n_pts, long pts_per_split, int n_split, int gx,
     float2* __restrict__ partial) {
-    constexpr int S = F < 16 ? F : 16;           // re-seed interval
+    constexpr int S = F < RFVR_RP_SEED ? F : RFVR_RP_SEED;   // re-seed interval
     constexpr int NS = F / S;
     // point records of the block's split are staged through LDS in tiles of
     // TILE, shared by the 4 waves; the next tile is fetched into registers
@@ -238,20 +241,15 @@ __global__ __launch_bounds__(256) void k_reduce_points(
             }
             {
                 float cw, sw;
-                if constexpr (RFVR_RP_ACCURATE_STEP || NAIVE) {
-                    step_phasor<NAIVE>(g, Kd, cw, sw);
-                } else {
-                    const float de = (float)(g.r * Kd);
-                    cw = cos_rev(de);
-                    sw = sin_rev(de);
-                }
+                step_phasor_cr<NAIVE>(g, Kd, cw, sw);
                 wr = cw;
                 wi = -sw;                  // exp(-j 2 pi delta)
             }
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 float c0, s0;
-                seed_phasor<NAIVE>(g, Kc[m], c0, s0);
+                if constexpr (RFVR_RP_ACC_SEED) seed_phasor_cr<NAIVE>(g, Kc[m], c0, s0);
+                else seed_phasor<NAIVE>(g, Kc[m], c0, s0);
                 // (cr + j ci) * exp(-j 2 pi theta_centre)
                 const float pr0 = __builtin_fmaf(cr, c0, ci * s0);
                 const float pi0 = __builtin_fmaf(ci, c0, -cr * s0);

@@ -91,10 +91,10 @@ __device__ __forceinline__ float alpha_pair(float a, float b) {
 // ---------------------------------------------------------------------------
 // pair phase set-up
 // ---------------------------------------------------------------------------
-// A pair's frequencies are visited by complex rotation with the step phasor
+// A pair's frequencies are visited by a recurrence in the step phasor
 // w = exp(-+ j 2 pi delta).  Rounding of w grows linearly along a walk and the
 // rendered signal is a heavily cancelling sum (Fresnel zones), so:
-//  * w comes from an accurately rounded sin/cos (sincospif);
+//  * w comes from an accurately rounded sin/cos (cos_sin_rev_accurate);
 //  * walks are short: every S frequencies the phasor is re-seeded from an
 //    FP64-reduced phase at the centre of the sub-chunk and walked S/2 steps
 //    up and S/2 steps down.
@@ -133,7 +133,61 @@ __device__ __forceinline__ void seed_phasor(const PairGeom& g, double K, float& 
     }
 }
 
-// accurate step phasor cos/sin of 2 pi * (Kd * r)
+// ---------------------------------------------------------------------------
+// correctly rounded cos / sin of 2 pi d for an FP64 phase d (revolutions):
+// d mod 1 = k / 1024 + e with |e| <= 1/2048; cos/sin(2 pi k / 1024) from a
+// table and cos/sin(2 pi e) from their Taylor series (|2 pi e| <= pi / 1024:
+// three terms leave < 1e-19), combined by the angle-sum identities, all in
+// FP64 and rounded once to FP32.  The table is built at compile time from the
+// Taylor series of cos and sin on the first octant and the 45-degree rotation.
+// ---------------------------------------------------------------------------
+namespace phase_table {
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double taylor_sin(double x) {
+    double t = x, s = x;
+    for (int n = 1; n < 14; ++n) { t *= -x * x / ((2 * n) * (2 * n + 1)); s += t; }
+    return s;
+}
+constexpr double taylor_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int n = 1; n < 14; ++n) { t *= -x * x / ((2 * n - 1) * (2 * n)); s += t; }
+    return s;
+}
+struct Table {
+    double v[2 * 1024];
+    constexpr Table() : v() {
+        const double h = 0.70710678118654752440084436210484903928;   // cos 45 deg
+        for (int k = 0; k < 1024; ++k) {
+            const int q = (k * 8) / 1024;                                // octant
+            const double a = 2.0 * kPi * ((double)k / 1024.0 - q / 8.0);  // [0, pi/4)
+            double c = taylor_cos(a), s = taylor_sin(a);
+            for (int i = 0; i < q; ++i) {
+                const double nc = h * (c - s), ns = h * (c + s);
+                c = nc;
+                s = ns;
+            }
+            v[2 * k] = c;
+            v[2 * k + 1] = s;
+        }
+    }
+};
+}  // namespace phase_table
+__device__ constexpr phase_table::Table kPhaseTable{};
+
+__device__ __forceinline__ void cos_sin_rev_accurate(double d, float& c, float& s) {
+    const double dr = __builtin_amdgcn_fract(d) * 1024.0;     // exact scaling
+    const double kf = __builtin_rint(dr);
+    const int k = (int)kf & 1023;
+    const double x = (dr - kf) * (6.283185307179586476925 / 1024.0);
+    const double x2 = x * x;
+    const double cl = __builtin_fma(x2, __builtin_fma(x2, 1.0 / 24.0, -0.5), 1.0);
+    const double sl = __builtin_fma(x * x2, __builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+    const double tc = kPhaseTable.v[2 * k], ts = kPhaseTable.v[2 * k + 1];
+    c = (float)__builtin_fma(tc, cl, -ts * sl);
+    s = (float)__builtin_fma(ts, cl, tc * sl);
+}
+
+// accurate step phasor cos/sin of 2 pi * (Kd * r) (frequency reductions)
 template <bool NAIVE>
 __device__ __forceinline__ void step_phasor(const PairGeom& g, double Kd, float& c, float& s) {
     if constexpr (!NAIVE) {
@@ -142,6 +196,19 @@ __device__ __forceinline__ void step_phasor(const PairGeom& g, double Kd, float&
     } else {
         sincosf((float)(6.283185307179586 * Kd) * g.rf, &s, &c);
     }
+}
+
+// correctly rounded step / seed phasors (point reductions, where the
+// three-term recurrence amplifies the rounding of cos by 1 / sin(2 pi delta))
+template <bool NAIVE>
+__device__ __forceinline__ void step_phasor_cr(const PairGeom& g, double Kd, float& c, float& s) {
+    if constexpr (!NAIVE) cos_sin_rev_accurate(g.r * Kd, c, s);
+    else sincosf((float)(6.283185307179586 * Kd) * g.rf, &s, &c);
+}
+template <bool NAIVE>
+__device__ __forceinline__ void seed_phasor_cr(const PairGeom& g, double K, float& c, float& s) {
+    if constexpr (!NAIVE) cos_sin_rev_accurate(g.r * K, c, s);
+    else sincosf((float)(6.283185307179586 * K) * g.rf, &s, &c);
 }
 
 // ----------------------------------------------------------------------------
