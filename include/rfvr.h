@@ -157,9 +157,10 @@ int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* ma
 
 /* ------------------------------------------------------------------------
  * Lensless primary-ray sampling (Sec. "Lensless Sampling", Primary Ray)
- * Rays run parallel to primary_dir from the aperture plane (through the
- * origin, normal to primary_dir) through a cube of centre `centre` and half
- * side `half_extent`; lateral grid of cell centres, ray r = iy*n_ray_x + ix,
+ * Rays run parallel to primary_dir from the aperture plane (normal to
+ * primary_dir at signed distance plane_offset from the world origin along the
+ * unit primary direction w_p) through a cube of centre `centre` and half side
+ * `half_extent`; lateral grid of cell centres, ray r = iy*n_ray_x + ix,
  * lateral axes e1 = unit(y x w_p) (x x w_p if w_p is within ~26 deg of y),
  * e2 = w_p x e1.  Depth u over [c.w_p - h, c.w_p + h] in n_z strata:
  *   GRID:       u_k = lo + (k + 1/2) 2h/n_z
@@ -167,7 +168,9 @@ int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* ma
  *               key = SplitMix64(seed, step) (k-th output of SplitMix64 from a
  *               state = mix(state + (k+1) * 0x9E3779B97F4A7C15))
  * Outputs: xyz [n_ray][n_z][3], u [n_ray][n_z] (NULL to skip), ray_origin
- * [n_ray][3] (NULL to skip).
+ * [n_ray][3] (NULL to skip): the ray's foot on the aperture plane, where the
+ * occupancy of Eq. lens-less-transmittance is evaluated.  u is measured along
+ * w_p from the parallel plane through the world origin.
  * ------------------------------------------------------------------------ */
 #define RFVR_SAMPLE_GRID        0
 #define RFVR_SAMPLE_STRATIFIED  1
@@ -178,6 +181,7 @@ typedef struct rfvr_sample_desc {
     int32_t  n_ray_x, n_ray_y, n_z;
     int32_t  mode;               /* RFVR_SAMPLE_* */
     uint64_t seed, step;
+    float    plane_offset;       /* aperture plane: {x : x . w_p = plane_offset} */
 } rfvr_sample_desc;
 int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* ray_origin,
                        void* stream);

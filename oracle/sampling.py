@@ -61,8 +61,10 @@ def lateral_basis(w_p):
     return e1, e2, w
 
 
-def sample_points(centre, half_extent, w_p, n_rx, n_ry, n_z, mode="grid", seed=0, step=0):
-    """Returns (xyz [n_ray, n_z, 3], u [n_ray, n_z], ray_origin [n_ray, 3]) in float64."""
+def sample_points(centre, half_extent, w_p, n_rx, n_ry, n_z, mode="grid", seed=0, step=0, plane_offset=0.0):
+    """Returns (xyz [n_ray, n_z, 3], u [n_ray, n_z], ray_origin [n_ray, 3]) in float64.
+    The ray origins are the rays' feet on the aperture plane x . w = plane_offset;
+    u is measured along w from the parallel plane through the world origin."""
     c = np.asarray(centre, np.float64)
     h = float(half_extent)
     e1, e2, w = lateral_basis(w_p)
@@ -81,4 +83,4 @@ def sample_points(centre, half_extent, w_p, n_rx, n_ry, n_z, mode="grid", seed=0
         raise ValueError(mode)
     u = (np.dot(c, w) - h) + (np.arange(n_z)[None, :] + frac) * (2.0 * h / n_z)
     xyz = origin[:, None, :] + u[:, :, None] * w[None, None, :]
-    return xyz, u, origin
+    return xyz, u, origin + float(plane_offset) * w[None, :]

@@ -346,6 +346,7 @@ int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* ma
 static int sample_basis(const rfvr_sample_desc* d, double basis[9]) {
     if (d->n_ray_x < 1 || d->n_ray_y < 1) { set_error("ray counts must be >= 1"); return RFVR_E_INVALID; }
     if (!(d->half_extent > 0.0f) || !std::isfinite(d->half_extent)) { set_error("half_extent must be finite and > 0"); return RFVR_E_INVALID; }
+    if (!std::isfinite(d->plane_offset)) { set_error("plane_offset must be finite"); return RFVR_E_INVALID; }
     double w[3] = {d->primary_dir[0], d->primary_dir[1], d->primary_dir[2]};
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(w[c]) || !std::isfinite((double)d->centre[c])) { set_error("non-finite direction or centre"); return RFVR_E_INVALID; }

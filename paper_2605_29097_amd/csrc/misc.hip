@@ -75,6 +75,7 @@ struct SampleArgs {
     double base[3];      // centre projected onto the aperture plane
     double lo;           // c.w - h
     double h;
+    double off;          // aperture plane offset along w (ray origins)
     int n_rx, n_ry, n_z, mode;
     uint64_t key;        // per-step stream key
 };
@@ -100,7 +101,7 @@ __global__ void k_sample_points(SampleArgs a, float* __restrict__ xyz, float* __
     for (int c = 0; c < 3; ++c) xyz[3 * t + c] = (float)(o[c] + u * a.w[c]);
     if (u_out) u_out[t] = (float)u;
     if (origin && k == 0)
-        for (int c = 0; c < 3; ++c) origin[3 * r + c] = (float)o[c];
+        for (int c = 0; c < 3; ++c) origin[3 * r + c] = (float)(o[c] + a.off * a.w[c]);
 }
 
 hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
@@ -117,6 +118,7 @@ hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9]
     a.base[1] = cy - cw * a.w[1];
     a.base[2] = cz - cw * a.w[2];
     a.h = d.half_extent;
+    a.off = d.plane_offset;
     a.lo = cw - a.h;
     a.n_rx = d.n_ray_x;
     a.n_ry = d.n_ray_y;
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void k_sample_importance(SampleArgs a, const f
         for (int c = 0; c < 3; ++c) xyz[3 * j + c] = (float)(o[c] + u * a.w[c]);
         if (u_out) u_out[j] = (float)u;
     }
-    if (origin && lane < 3) origin[3 * r + lane] = (float)o[lane];
+    if (origin && lane < 3) origin[3 * r + lane] = (float)(o[lane] + a.off * a.w[lane]);
 }
 
 hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basis[9], const float* logits,
@@ -238,6 +240,7 @@ hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basi
     a.base[1] = cy - cw * a.w[1];
     a.base[2] = cz - cw * a.w[2];
     a.h = d.half_extent;
+    a.off = d.plane_offset;
     a.lo = cw - a.h;
     a.n_rx = d.n_ray_x;
     a.n_ry = d.n_ray_y;

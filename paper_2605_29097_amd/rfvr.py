@@ -48,7 +48,7 @@ class CFields(ctypes.Structure):
 class CSampleDesc(ctypes.Structure):
     _fields_ = [("centre", _c_f * 3), ("half_extent", _c_f), ("primary_dir", _c_f * 3),
                 ("n_ray_x", _c_i32), ("n_ray_y", _c_i32), ("n_z", _c_i32), ("mode", _c_i32),
-                ("seed", _c_u64), ("step", _c_u64)]
+                ("seed", _c_u64), ("step", _c_u64), ("plane_offset", _c_f)]
 
 
 class CMlp(ctypes.Structure):
@@ -300,16 +300,17 @@ def loss_l2(p: torch.Tensor, p_star: torch.Tensor, mask=None, want_grad=True, st
     return loss, g
 
 
-def _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode, seed, step):
+def _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode, seed, step, plane_offset=0.0):
     return CSampleDesc((_c_f * 3)(*[float(c) for c in centre]), float(half_extent),
                        (_c_f * 3)(*[float(c) for c in primary_dir]), int(n_ray_x), int(n_ray_y),
-                       int(n_z), int(mode), int(seed) & (2 ** 64 - 1), int(step) & (2 ** 64 - 1))
+                       int(n_z), int(mode), int(seed) & (2 ** 64 - 1), int(step) & (2 ** 64 - 1),
+                       float(plane_offset))
 
 
 def sample_points(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode=SAMPLE_GRID,
-                  seed=0, step=0, device="cuda", stream=None):
+                  seed=0, step=0, device="cuda", plane_offset=0.0, stream=None):
     """(xyz [n_ray, n_z, 3], u [n_ray, n_z], ray_origin [n_ray, 3])."""
-    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode, seed, step)
+    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, mode, seed, step, plane_offset)
     n_ray = n_ray_x * n_ray_y
     xyz = torch.empty(n_ray, n_z, 3, dtype=torch.float32, device=device)
     u = torch.empty(n_ray, n_z, dtype=torch.float32, device=device)
@@ -384,13 +385,14 @@ def adamw(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, stream=None):
 
 
 def sample_importance(centre, half_extent, primary_dir, n_ray_x, n_ray_y, logits: torch.Tensor,
-                      n_imp, n_uni, seed=0, step=0, stream=None):
+                      n_imp, n_uni, seed=0, step=0, plane_offset=0.0, stream=None):
     """Proposal-guided depths: (xyz [n_ray, K, 3], u [n_ray, K], ray_origin [n_ray, 3]),
     K = n_uni + n_imp, from bin logits [n_ray, n_bins]."""
     n_ray = n_ray_x * n_ray_y
     n_bins = logits.shape[-1]
     assert logits.numel() == n_ray * n_bins
-    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_imp + n_uni, 0, seed, step)
+    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_imp + n_uni, 0, seed, step,
+                     plane_offset)
     dev = logits.device
     K = n_imp + n_uni
     xyz = torch.empty(n_ray, K, 3, dtype=torch.float32, device=dev)

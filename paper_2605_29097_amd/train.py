@@ -252,6 +252,85 @@ class Trainer:
         return {"signal": nrmse(sig, clean), "heatmap": nrmse(p, p_ref)}
 
 
+class MultiPlaneTrainer(Trainer):
+    """Training on several scanning planes with one shared network (the paper's
+    multi-plane scans, Sec. Number of Radar Scanning Planes).  Each plane has its
+    own aperture, primary direction (the plane normal), lensless primary rays
+    through the sample cube with their own alpha/T scans, and its own measured
+    signal.  A step visits ``planes_per_step`` planes in cyclic order; their
+    heatmap losses add, the network and amplitude gradients accumulate
+    (RFVR_ACCUMULATE), and one AdamW update follows.
+
+    planes: list of dict(tx [n_meas, 3] float32, w [3] unit primary direction,
+    offset: plane {x : x . w = offset}); targets: per-plane signals
+    [n_meas, n_freq, 2]."""
+
+    def __init__(self, cfg: StepConfig, params: torch.Tensor, planes, targets, device="cuda",
+                 planes_per_step: Optional[int] = None):
+        if cfg.bank_patch is not None:
+            raise ValueError("the Signal Tracing Bank is per plane; not combined with multi-plane steps")
+        super().__init__(cfg, params, targets[0], device)
+        self.planes = []
+        for pl, tg in zip(planes, targets):
+            tx = torch.from_numpy(np.ascontiguousarray(pl["tx"], np.float32)).to(self.dev)
+            self.planes.append({
+                "tx": tx, "ap": R.Aperture(tx=tx, f0=self.f0, df=self.df, n_freq=cfg.n_freq),
+                "w": tuple(float(v) for v in pl["w"]), "offset": float(pl["offset"]),
+                "target": tg.to(self.dev).contiguous(), "p_star": None})
+        self.pps = planes_per_step or len(self.planes)
+        self.g_amp = torch.zeros(1, device=self.dev)
+        self.loss_sum = torch.zeros(1, device=self.dev)
+
+    def plane_samples(self, k: int):
+        c, pl = self.cfg, self.planes[k]
+        return R.sample_points(c.cube_centre, c.cube_side / 2, pl["w"], c.lines[0], c.lines[1], c.n_z,
+                               mode=c.sampling, seed=c.seed, step=self.t * len(self.planes) + k,
+                               device=self.dev, plane_offset=pl["offset"])
+
+    def step(self, timers: Optional[dict] = None):
+        c = self.cfg
+        n_pl = len(self.planes)
+        for j in range(self.pps):
+            k = (self.t * self.pps + j) % n_pl
+            pl = self.planes[k]
+            xyz, u, origin = self.plane_samples(k)
+            n_ray = origin.shape[0]
+            f, grad, a = R.mlp_forward(self.net, xyz)
+            f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, pl["tx"]], 0))
+            phi = R.occupancy(self.s, f_org)
+            sm = R.Samples(xyz=xyz)
+            fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
+                          refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
+                          phi_ray=phi[:n_ray].contiguous(), phi_tx=phi[n_ray:].contiguous())
+            sig = R.render_forward(pl["ap"], sm, fl, flags=c.spec_flags)
+            if pl["p_star"] is None or c.sampling != R.SAMPLE_GRID:
+                z, p, _, p_star = R.mf_forward(pl["ap"], xyz, sig, pl["target"])
+                if c.sampling == R.SAMPLE_GRID:
+                    pl["p_star"] = p_star
+            else:
+                z, p = R.mf_forward(pl["ap"], xyz, sig)
+                p_star = pl["p_star"]
+            loss, g_p = R.loss_l2(p, p_star)
+            g_sig = R.mf_backward(pl["ap"], xyz, z, p, g_p)
+            gr = R.render_backward(pl["ap"], sm, fl, g_sig, flags=c.spec_flags)
+            R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
+                           flags=R.ACCUMULATE if j > 0 else 0, out=self.g)
+            if j == 0:
+                self.g_amp.copy_(gr["amp"])
+                self.loss_sum.copy_(loss)
+            else:
+                self.g_amp.add_(gr["amp"])
+                self.loss_sum.add_(loss)
+        self.t += 1
+        P, G, M, V = self.net.params, self.g, self.m, self.v
+        ns = self.n_sdf
+        R.adamw(P[:ns], G[:ns], M[:ns], V[:ns], self.t, self.lr(c.lr_sdf))
+        R.adamw(P[ns:], G[ns:], M[ns:], V[ns:], self.t, self.lr(c.lr_other))
+        R.adamw(self.amp, self.g_amp, self.amp_m, self.amp_v, self.t, self.lr(c.lr_other))
+        self.last = dict(loss=self.loss_sum)
+        return self.loss_sum
+
+
 def nrmse(sig: torch.Tensor, ref: torch.Tensor) -> float:
     """||sig - ref|| / ||ref|| over all measurements and frequencies."""
     return float(torch.linalg.vector_norm(sig - ref) / torch.linalg.vector_norm(ref))

@@ -13,6 +13,7 @@ analytic SDF evaluators work in float64 and the caller rounds.
 """
 from .scenes import (  # noqa: F401
     planar_aperture,
+    ring_apertures,
     freq_grid,
     line_points,
     Sphere,

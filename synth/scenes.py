@@ -28,6 +28,34 @@ def planar_aperture(nx: int, ny: int, pitch: float, z: float = 0.0,
     return np.ascontiguousarray(pos, dtype=np.float32)
 
 
+def ring_apertures(n_planes: int, distance: float, nx: int, ny: int, pitch: float,
+                   centre: Sequence[float] = (0.0, 0.0, 0.30), first: float = 0.0,
+                   span: float = 2.0 * np.pi):
+    """Scanning planes on a ring around a vertical (y) axis through ``centre``.
+
+    Plane k sits at azimuth phi_k = first + span * k / n_planes, its centre at
+    centre + distance * (sin phi, 0, -cos phi), facing the centre: unit primary
+    direction w = (-sin phi, 0, cos phi).  Its antennas form an nx x ny grid of
+    pitch ``pitch`` along e_x = (cos phi, 0, sin phi) and e_y = (0, 1, 0), index
+    i = iy * nx + ix.  Plane 0 with centre (0, 0, d) is the standard aperture in
+    z = 0.  Returns a list of dicts: tx float32 [nx*ny, 3], w float64 [3],
+    offset = plane centre . w (the plane is {x : x . w = offset})."""
+    c = np.asarray(centre, np.float64)
+    out = []
+    for k in range(n_planes):
+        phi = first + span * k / n_planes
+        w = np.array([-np.sin(phi), 0.0, np.cos(phi)])
+        ex = np.array([np.cos(phi), 0.0, np.sin(phi)])
+        ey = np.array([0.0, 1.0, 0.0])
+        pc = c - distance * w
+        ix = (np.arange(nx) - (nx - 1) / 2.0) * pitch
+        iy = (np.arange(ny) - (ny - 1) / 2.0) * pitch
+        gx, gy = np.meshgrid(ix, iy, indexing="xy")
+        tx = pc[None] + gx.ravel()[:, None] * ex[None] + gy.ravel()[:, None] * ey[None]
+        out.append({"tx": np.ascontiguousarray(tx, np.float32), "w": w, "offset": float(pc @ w)})
+    return out
+
+
 def freq_grid(n_freq: int, f_lo: float = 77e9, f_hi: float = 81e9) -> Tuple[float, float]:
     """(f0, df) of an inclusive linear grid of ``n_freq`` frequencies."""
     if n_freq < 1:

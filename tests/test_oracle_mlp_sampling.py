@@ -176,3 +176,34 @@ def test_cosine_schedule_endpoints():
     assert oopt.cosine_lr(0, 100, 1e-3) == pytest.approx(1e-3)
     assert oopt.cosine_lr(50, 100, 1e-3) == pytest.approx(5e-4)
     assert oopt.cosine_lr(100, 100, 1e-3, 1e-5) == pytest.approx(1e-5)
+
+
+def test_ring_apertures_geometry():
+    """Each scanning plane faces the ring centre at the given distance, its
+    antennas lie in the plane x . w = offset, and plane 0 is the standard
+    aperture in z = 0."""
+    from synth import planar_aperture, ring_apertures
+    c = np.array([0.0, 0.0, 0.30])
+    planes = ring_apertures(6, 0.30, 5, 4, 2e-3, centre=c)
+    np.testing.assert_allclose(planes[0]["tx"], planar_aperture(5, 4, 2e-3), atol=1e-7)
+    for k, pl in enumerate(planes):
+        w, tx = pl["w"], pl["tx"].astype(np.float64)
+        assert abs(np.linalg.norm(w) - 1.0) < 1e-12
+        np.testing.assert_allclose(tx @ w, pl["offset"], atol=1e-7)
+        np.testing.assert_allclose(tx.mean(0), c - 0.30 * w, atol=1e-7)
+        phi = 2 * np.pi * k / 6
+        np.testing.assert_allclose(w, [-np.sin(phi), 0.0, np.cos(phi)], atol=1e-12)
+
+
+def test_sampling_origins_on_the_aperture_plane():
+    """With a plane offset the ray origins lie on x . w = offset and every
+    sample lies on its ray; the samples themselves do not depend on it."""
+    from oracle.sampling import sample_points
+    w = np.array([-1.0, 0.0, 1.0]) / np.sqrt(2.0)
+    a = sample_points((0.0, 0.0, 0.3), 0.05, w, 5, 3, 7)
+    b = sample_points((0.0, 0.0, 0.3), 0.05, w, 5, 3, 7, plane_offset=-0.1)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_allclose(b[2] @ w, -0.1, atol=1e-14)
+    d = b[0] - b[2][:, None, :]
+    cross = np.cross(d, w[None, None, :])
+    assert np.abs(cross).max() < 1e-14
