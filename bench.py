@@ -210,6 +210,48 @@ def proposal_study(args, dev):
                       "runs": out}))
 
 
+def naive_compare(args, dev):
+    """Forward cost of the per-antenna method vs lensless sampling at one size:
+    the 8x256 network, an n x n aperture, 32 x 32 rays x 64 depths, 128
+    frequencies.  Prints one JSON line."""
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from paper_2605_29097_amd.naive import naive_forward
+    from synth import MLPSpec, mlp_init
+    from paper_2605_29097_amd.train import StepConfig, aperture_positions
+    out = {"study": "naive_vs_lensless_forward", "runs": []}
+    spec = MLPSpec()
+    net = R.MLP(params=torch.from_numpy(mlp_init(spec, 0)).to(dev))
+    for n_ap in args.naive_apertures:
+        cfg = StepConfig(ap=(n_ap, n_ap))
+        tx = torch.from_numpy(aperture_positions(cfg)).to(dev)
+        ap = R.Aperture(tx=tx, f0=77e9, df=4e9 / 127, n_freq=128)
+
+        def lensless():
+            xyz, _, _ = R.sample_points(cfg.cube_centre, 0.1, (0, 0, 1), 32, 32, 64, device=dev)
+            f, g, a = R.mlp_forward(net, xyz)
+            fl = R.Fields(sdf=f.view(1024, 64), grad=g.view(1024, 64, 3), refl=a.view(1024, 64), s=64.0)
+            return R.render_forward(ap, R.Samples(xyz=xyz), fl)
+
+        def naive():
+            return naive_forward(net, ap, cfg.cube_centre, 0.1, (0, 0, 1), 32, 32, 64, s=64.0)
+
+        row = {"n_ant": n_ap * n_ap, "points_lensless": 32 * 32 * 64, "points_naive": n_ap * n_ap * 32 * 32 * 64}
+        for name, fn in (("lensless", lensless), ("naive", naive)):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                fn()
+            e1.record()
+            e1.synchronize()
+            row[f"{name}_ms"] = round(e0.elapsed_time(e1) / 3, 3)
+            print(f"[naive] n_ant {n_ap * n_ap} {name} {row[name + '_ms']} ms", file=sys.stderr, flush=True)
+        out["runs"].append(row)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +271,9 @@ def main():
     ap.add_argument("--study-learn-s", action="store_true", help="train log s in every run")
     ap.add_argument("--study-s", type=float, default=64.0,
                     help="initial s (1/m); the target is the oracle render of the scene at this s")
+    ap.add_argument("--naive-compare", action="store_true",
+                    help="forward time of per-antenna sampling vs lensless sampling")
+    ap.add_argument("--naive-apertures", type=int, nargs="+", default=[4, 8, 16])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
@@ -250,6 +295,9 @@ def main():
         return
     if args.proposal_study:
         proposal_study(args, dev)
+        return
+    if args.naive_compare:
+        naive_compare(args, dev)
         return
     cfg = StepConfig()
     params, target = make_inputs(cfg, dev)

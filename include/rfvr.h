@@ -69,6 +69,9 @@ typedef struct rfvr_samples {
     int32_t      n_ray, n_z;   /* >= 1 each                                          */
     const float* xyz;          /* [n_ray][n_z][3] points, depth ascending per ray    */
     const float* ray_weight;   /* [n_ray] Monte-Carlo weight w_r, or NULL (= 1)      */
+    const float* point_weight; /* [n_ray*n_z] volume weight per sample multiplying its
+                                  amplitude, or NULL (= 1); rfvr_render_forward only
+                                  (the per-antenna renderer's Jacobian)            */
 } rfvr_samples;
 
 /* Per-point fields of the current scene estimate (Sec. "Opaque density
@@ -292,6 +295,34 @@ int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const floa
 size_t rfvr_bce_ws_bytes(int64_t n);
 int rfvr_bce(int64_t n, const float* logits, const float* t, float* loss, float* g_logits,
              void* ws, size_t ws_bytes, void* stream);
+
+/* Per-antenna ("naive") sampling, the brute-force Monte Carlo of Sec.
+ * Integration that the lensless sampling replaces: for antenna i, ray r runs
+ * from tx_i through the r-th point of the lateral grid of cell centres on the
+ * plane through the cube centre normal to w_p (grid as rfvr_sample_points);
+ * its n_z samples sit at the cell centres of the ray's segment between the
+ * planes x . w_p = c . w_p -+ h (the antenna must lie before the first plane).
+ * jac = (|x - tx_i| / |g_r - tx_i|)^2 is the sample's volume relative to a
+ * lensless cell (spherical volume element of a ray through a grid cell), to be
+ * passed as point_weight.  Outputs xyz [n_ant][n_ray][n_z][3], jac
+ * [n_ant][n_ray][n_z] (NULL to skip).  d's n_z is used; mode, seed, step and
+ * plane_offset are ignored. */
+int rfvr_sample_naive(const rfvr_sample_desc* d, const float* tx, int32_t n_ant, float* xyz,
+                      float* jac, void* stream);
+
+/* Dynamic loss masking (Sec. Optimization): a point whose rendered filter
+ * output was high in an earlier iteration but is low now is left out of the
+ * loss.  With S = max_q power_ref[q] (the measured heatmap's peak):
+ *   mask[q] = 0 if history[q] >= tau_hi * S and power[q] < tau_lo * history[q],
+ *             else 1;
+ *   then history[q] = max(history[q], power[q]).
+ * All comparisons in FP32 (products rounded to FP32 first).  history [n] is
+ * caller-owned state, zero before the first iteration; mask [n] output, usable
+ * as the mask of rfvr_loss_l2.  tau_hi, tau_lo finite and >= 0. */
+size_t rfvr_mask_ws_bytes(int64_t n);
+int rfvr_mask_update(int64_t n, const float* power, const float* power_ref, float* history,
+                     float tau_hi, float tau_lo, float* mask, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* Occupancy at the detached ray / antenna origins (Eq. lens-less-transmittance):
  *   phi[k] = 1 / (1 + exp(-s * sdf[k])),  k < n.  s finite and > 0. */

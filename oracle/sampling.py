@@ -84,3 +84,31 @@ def sample_points(centre, half_extent, w_p, n_rx, n_ry, n_z, mode="grid", seed=0
     u = (np.dot(c, w) - h) + (np.arange(n_z)[None, :] + frac) * (2.0 * h / n_z)
     xyz = origin[:, None, :] + u[:, :, None] * w[None, None, :]
     return xyz, u, origin + float(plane_offset) * w[None, :]
+
+
+def sample_naive(tx, centre, half_extent, w_p, n_rx, n_ry, n_z):
+    """Per-antenna Monte Carlo samples of Sec. Integration (the brute force the
+    lensless sampling replaces).  Ray r of antenna i runs from tx_i through the
+    r-th cell centre g_r of the lateral grid on the plane through the cube
+    centre normal to w; its n_z samples are the cell centres of the ray's
+    segment between the planes x . w = c . w -+ h.  jac = (|x - tx_i| / |g_r -
+    tx_i|)^2 is the sample's volume relative to a lensless grid cell.
+    Returns xyz [n_ant, n_ray, n_z, 3], jac [n_ant, n_ray, n_z] (float64)."""
+    c = np.asarray(centre, np.float64)
+    h = float(half_extent)
+    e1, e2, w = lateral_basis(w_p)
+    ax = -h + (np.arange(n_rx) + 0.5) * 2.0 * h / n_rx
+    ay = -h + (np.arange(n_ry) + 0.5) * 2.0 * h / n_ry
+    gx, gy = np.meshgrid(ax, ay, indexing="xy")
+    g = c[None] + gx.ravel()[:, None] * e1[None] + gy.ravel()[:, None] * e2[None]      # [n_ray, 3]
+    t = np.asarray(tx, np.float64).reshape(-1, 3)
+    d = g[None, :, :] - t[:, None, :]                                                 # [n_ant, n_ray, 3]
+    rc = np.linalg.norm(d, axis=-1)
+    u = d / rc[..., None]
+    cos_w = u @ w
+    tw = t @ w
+    s_in = (np.dot(c, w) - h - tw)[:, None] / cos_w
+    s_out = (np.dot(c, w) + h - tw)[:, None] / cos_w
+    dist = s_in[..., None] + (np.arange(n_z) + 0.5)[None, None, :] * ((s_out - s_in) / n_z)[..., None]
+    xyz = t[:, None, None, :] + dist[..., None] * u[:, :, None, :]
+    return xyz, (dist / rc[..., None]) ** 2

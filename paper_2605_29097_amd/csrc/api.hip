@@ -178,7 +178,7 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
     if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
                          "ant records")))
         return rc;
-    if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, fl->sdf, fl->grad, fl->refl,
+    if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, sm->point_weight, fl->sdf, fl->grad, fl->refl,
                                             fl->phi_ray, use_phi, fl->s, fl->amp_tx, fl->amp_ptr, rec,
                                             alpha_out, trans_out, st),
                          "render prep")))
@@ -205,6 +205,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
         (rc = check_flags(flags)))
         return rc;
     if (!g_signal) { set_error("g_signal is NULL"); return RFVR_E_INVALID; }
+    if (sm->point_weight) { set_error("point weights are supported by rfvr_render_forward only"); return RFVR_E_UNSUPPORTED; }
     const RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
     if ((rc = check_ws(ws, ws_bytes, ws_render_backward(g)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -226,7 +227,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
     if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
                          "ant records")))
         return rc;
-    if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, fl->sdf, fl->grad, fl->refl,
+    if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, nullptr, fl->sdf, fl->grad, fl->refl,
                                             fl->phi_ray, use_phi, fl->s, fl->amp_tx, fl->amp_ptr, rec,
                                             alpha, trans, st),
                          "render prep")))
@@ -377,6 +378,17 @@ int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* r
                       "sample points");
 }
 
+int rfvr_sample_naive(const rfvr_sample_desc* d, const float* tx, int32_t n_ant, float* xyz, float* jac,
+                      void* stream) {
+    if (!d || !tx || !xyz || n_ant < 1) { set_error("descriptor, tx, xyz and n_ant >= 1 are required"); return RFVR_E_INVALID; }
+    if (d->n_z < 1) { set_error("n_z must be >= 1"); return RFVR_E_INVALID; }
+    double basis[9];
+    int rc;
+    if ((rc = sample_basis(d, basis))) return rc;
+    return hip_status(launch_sample_naive(*d, basis, tx, n_ant, xyz, jac, reinterpret_cast<hipStream_t>(stream)),
+                      "naive sampling");
+}
+
 int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32_t n_bins,
                            int32_t n_imp, int32_t n_uni, float* xyz, float* u, float* ray_origin,
                            void* stream) {
@@ -407,6 +419,29 @@ int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const floa
 }
 
 size_t rfvr_bce_ws_bytes(int64_t n) { return rfvr_loss_ws_bytes(n); }
+
+size_t rfvr_mask_ws_bytes(int64_t n) {
+    if (n < 1) return 0;
+    return align256(sizeof(float) * (loss_blocks((long)n) + 1));
+}
+
+int rfvr_mask_update(int64_t n, const float* power, const float* power_ref, float* history, float tau_hi,
+                     float tau_lo, float* mask, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1 || !power || !power_ref || !history || !mask) {
+        set_error("n >= 1, power, power_ref, history and mask are required");
+        return RFVR_E_INVALID;
+    }
+    if (!std::isfinite(tau_hi) || !std::isfinite(tau_lo) || tau_hi < 0.0f || tau_lo < 0.0f) {
+        set_error("tau_hi and tau_lo must be finite and >= 0");
+        return RFVR_E_INVALID;
+    }
+    int rc;
+    if ((rc = check_ws(ws, ws_bytes, rfvr_mask_ws_bytes(n)))) return rc;
+    const int nb = loss_blocks((long)n);
+    return hip_status(launch_mask_update((long)n, power, power_ref, history, tau_hi, tau_lo, mask,
+                                         reinterpret_cast<float*>(ws), nb, reinterpret_cast<hipStream_t>(stream)),
+                      "mask update");
+}
 
 int rfvr_bce(int64_t n, const float* logits, const float* t, float* loss, float* g_logits,
              void* ws, size_t ws_bytes, void* stream) {

@@ -258,6 +258,64 @@ hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basi
     return hipGetLastError();
 }
 
+// per-antenna sampling: rays from each antenna through the lateral grid on the
+// plane through the cube centre, samples at the cell centres of the ray's
+// segment between the cube's two planes normal to w; volume Jacobian
+// (dist / dist to the grid point)^2 relative to a lensless cell
+__global__ void k_sample_naive(SampleArgs a, const float* __restrict__ tx, int n_ant,
+                               float* __restrict__ xyz, float* __restrict__ jac) {
+    const long n_ray = (long)a.n_rx * a.n_ry;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n_ant * n_ray * a.n_z) return;
+    const int k = (int)(t % a.n_z);
+    const long r = (t / a.n_z) % n_ray;
+    const int i = (int)(t / ((long)a.n_z * n_ray));
+    const int ix = (int)(r % a.n_rx), iy = (int)(r / a.n_rx);
+    const double lx = -a.h + (ix + 0.5) * 2.0 * a.h / a.n_rx;
+    const double ly = -a.h + (iy + 0.5) * 2.0 * a.h / a.n_ry;
+    double p[3], d[3];
+    for (int q = 0; q < 3; ++q) {
+        p[q] = (double)tx[3 * i + q];
+        d[q] = a.base[q] + lx * a.e1[q] + ly * a.e2[q] - p[q];      // base: the cube centre
+    }
+    const double rc = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int q = 0; q < 3; ++q) d[q] /= rc;
+    const double cw = d[0] * a.w[0] + d[1] * a.w[1] + d[2] * a.w[2];        // cos of the ray to w
+    const double pw = p[0] * a.w[0] + p[1] * a.w[1] + p[2] * a.w[2];
+    const double s_in = (a.lo - pw) / cw, s_out = (a.lo + 2.0 * a.h - pw) / cw;
+    const double dist = s_in + ((double)k + 0.5) * (s_out - s_in) / a.n_z;
+    for (int q = 0; q < 3; ++q) xyz[3 * t + q] = (float)(p[q] + dist * d[q]);
+    if (jac) jac[t] = (float)((dist / rc) * (dist / rc));
+}
+
+hipError_t launch_sample_naive(const rfvr_sample_desc& d, const double basis[9], const float* tx, int n_ant,
+                               float* xyz, float* jac, hipStream_t st) {
+    SampleArgs a;
+    for (int c = 0; c < 3; ++c) {
+        a.e1[c] = basis[c];
+        a.e2[c] = basis[3 + c];
+        a.w[c] = basis[6 + c];
+    }
+    const double cx = d.centre[0], cy = d.centre[1], cz = d.centre[2];
+    const double cw = cx * a.w[0] + cy * a.w[1] + cz * a.w[2];
+    a.h = d.half_extent;
+    a.lo = cw - a.h;
+    a.n_rx = d.n_ray_x;
+    a.n_ry = d.n_ray_y;
+    a.n_z = d.n_z;
+    a.mode = 0;
+    a.off = 0.0;
+    a.key = 0;
+    // the lateral grid is centred on the cube centre (held in base)
+    a.base[0] = cx;
+    a.base[1] = cy;
+    a.base[2] = cz;
+    const long n = (long)n_ant * d.n_ray_x * d.n_ray_y * d.n_z;
+    hipLaunchKernelGGL(k_sample_naive, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, tx, n_ant,
+                       xyz, jac);
+    return hipGetLastError();
+}
+
 // proposal targets: bin the blend weights T alpha of each ray, normalise by the max
 __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, const float* __restrict__ u,
                                                           const float* __restrict__ alpha,
@@ -320,6 +378,58 @@ hipError_t launch_bce(long n, const float* z, const float* t, float* loss, float
                       hipStream_t st) {
     hipLaunchKernelGGL(k_bce_partial, dim3(nb), dim3(256), 0, st, n, z, t, g, part);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nb, n, loss);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dynamic loss masking: peak of the reference heatmap, then mask and history
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_max_partial(long n, const float* __restrict__ x,
+                                                     float* __restrict__ part) {
+    __shared__ float sh[256];
+    float m = 0.0f;
+    for (long q = (long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long)gridDim.x * 256) m = fmaxf(m, x[q]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + d]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_max_final(const float* __restrict__ part, int nb,
+                                                   float* __restrict__ out) {
+    __shared__ float sh[256];
+    float m = 0.0f;
+    for (int k = threadIdx.x; k < nb; k += 256) m = fmaxf(m, part[k]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + d]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_mask_update(long n, const float* __restrict__ p,
+                                                     float* __restrict__ hist, const float* __restrict__ peak,
+                                                     float tau_hi, float tau_lo, float* __restrict__ mask) {
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const float hi = __fmul_rn(tau_hi, peak[0]);
+    const float h = hist[q], pq = p[q];
+    const bool drop = (h >= hi) && (pq < __fmul_rn(tau_lo, h));
+    mask[q] = drop ? 0.0f : 1.0f;
+    hist[q] = fmaxf(h, pq);
+}
+
+hipError_t launch_mask_update(long n, const float* p, const float* p_ref, float* hist, float tau_hi,
+                              float tau_lo, float* mask, float* part, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(256), 0, st, n, p_ref, part);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, part, nb, part + nb);
+    hipLaunchKernelGGL(k_mask_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, hist,
+                       part + nb, tau_hi, tau_lo, mask);
     return hipGetLastError();
 }
 

@@ -83,7 +83,7 @@ hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_render_prep(
     int n_ray, int n_z, const float* __restrict__ xyz, const float* __restrict__ ray_w,
-    const float* __restrict__ sdf, const float* __restrict__ grad, const float* __restrict__ refl,
+    const float* __restrict__ pt_w, const float* __restrict__ sdf, const float* __restrict__ grad, const float* __restrict__ refl,
     const float* __restrict__ phi_ray, int use_phi, float s, float amp_h,
     const float* __restrict__ amp_ptr, PtRec* __restrict__ rec, float* __restrict__ alpha_out,
     float* __restrict__ trans_out) {
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_render_prep(
             p.x = (double)xyz[3 * j];
             p.y = (double)xyz[3 * j + 1];
             p.z = (double)xyz[3 * j + 2];
-            p.b = amp * w * refl[j] * alpha;
+            p.b = amp * w * refl[j] * alpha * (pt_w ? pt_w[j] : 1.0f);
             p.tp = T - pr;
             float gx = grad[3 * j], gy = grad[3 * j + 1], gz = grad[3 * j + 2];
             float inv = 1.0f / fmaxf(sqrtf(gx * gx + gy * gy + gz * gz), 1e-12f);
@@ -133,13 +133,13 @@ __global__ __launch_bounds__(256) void k_render_prep(
 }
 
 hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w,
-                              const float* sdf, const float* grad, const float* refl,
+                              const float* pt_w, const float* sdf, const float* grad, const float* refl,
                               const float* phi_ray, int use_phi, float s, float amp,
                               const float* amp_ptr, PtRec* rec, float* alpha_out, float* trans_out,
                               hipStream_t st) {
     const int waves_per_block = 4;
     dim3 grid((g.n_ray + waves_per_block - 1) / waves_per_block);
-    hipLaunchKernelGGL(k_render_prep, grid, dim3(256), 0, st, g.n_ray, g.n_z, xyz, ray_w, sdf,
+    hipLaunchKernelGGL(k_render_prep, grid, dim3(256), 0, st, g.n_ray, g.n_z, xyz, ray_w, pt_w, sdf,
                        grad, refl, phi_ray, use_phi, s, amp, amp_ptr, rec, alpha_out, trans_out);
     return hipGetLastError();
 }

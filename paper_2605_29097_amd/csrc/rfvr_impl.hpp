@@ -242,7 +242,7 @@ int freq_chunk(int n_freq);
 
 hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, AntRec* out,
                               hipStream_t st);
-hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w,
+hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w, const float* pt_w,
                               const float* sdf, const float* grad, const float* refl,
                               const float* phi_ray, int use_phi, float s, float amp,
                               const float* amp_ptr, PtRec* rec, float* alpha_out, float* trans_out,
@@ -281,9 +281,13 @@ hipError_t launch_loss_final(const double* part, int n_blocks, long n, float* lo
 hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
                                 float* u, float* origin, hipStream_t st);
 hipError_t launch_occupancy(long n, float s, const float* f, float* phi, hipStream_t st);
+hipError_t launch_mask_update(long n, const float* p, const float* p_ref, float* hist, float tau_hi,
+                              float tau_lo, float* mask, float* part, int nb, hipStream_t st);
 hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basis[9], const float* logits,
                                     int n_bins, int n_imp, int n_uni, float* xyz, float* u, float* origin,
                                     hipStream_t st);
+hipError_t launch_sample_naive(const rfvr_sample_desc& d, const double basis[9], const float* tx, int n_ant,
+                               float* xyz, float* jac, hipStream_t st);
 hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
                                    float lo, float hi, int n_bins, float* targets, hipStream_t st);
 hipError_t launch_bce(long n, const float* z, const float* t, float* loss, float* g, double* part, int nb,

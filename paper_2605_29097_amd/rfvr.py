@@ -37,7 +37,7 @@ class CAperture(ctypes.Structure):
 
 
 class CSamples(ctypes.Structure):
-    _fields_ = [("n_ray", _c_i32), ("n_z", _c_i32), ("xyz", _vp), ("ray_weight", _vp)]
+    _fields_ = [("n_ray", _c_i32), ("n_z", _c_i32), ("xyz", _vp), ("ray_weight", _vp), ("point_weight", _vp)]
 
 
 class CFields(ctypes.Structure):
@@ -93,10 +93,13 @@ _SIGS = {
     "rfvr_proposal_ws_bytes": ([_P(CProposal), _c_i64], _sz),
     "rfvr_proposal_forward": ([_P(CProposal), _vp, _c_i64, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_proposal_backward": ([_P(CProposal), _vp, _c_i64, _vp, _c_u32, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_sample_naive": ([_P(CSampleDesc), _vp, _c_i32, _vp, _vp, _vp], _c_i32),
     "rfvr_sample_importance": ([_P(CSampleDesc), _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp, _vp],
                                _c_i32),
     "rfvr_proposal_targets": ([_c_i32, _c_i32, _vp, _vp, _vp, _c_f, _c_f, _c_i32, _vp, _vp], _c_i32),
     "rfvr_bce_ws_bytes": ([_c_i64], _sz),
+    "rfvr_mask_ws_bytes": ([_c_i64], _sz),
+    "rfvr_mask_update": ([_c_i64, _vp, _vp, _vp, _c_f, _c_f, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_bce": ([_c_i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_adamw": ([_c_i64, _vp, _vp, _vp, _vp, _c_i64, _c_f, _c_f, _c_f, _c_f, _c_f, _vp], _c_i32),
 }
@@ -184,9 +187,11 @@ class Aperture:
 class Samples:
     xyz: torch.Tensor                      # [n_ray, n_z, 3]
     ray_weight: Optional[torch.Tensor] = None
+    point_weight: Optional[torch.Tensor] = None   # [n_ray, n_z], forward render only
 
     def c(self) -> CSamples:
-        return CSamples(self.xyz.shape[0], self.xyz.shape[1], _ptr(self.xyz), _ptr(self.ray_weight))
+        return CSamples(self.xyz.shape[0], self.xyz.shape[1], _ptr(self.xyz), _ptr(self.ray_weight),
+                        _ptr(self.point_weight))
 
 
 @dataclass
@@ -384,6 +389,18 @@ def adamw(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0, stream=None):
            "rfvr_adamw")
 
 
+def sample_naive(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, tx: torch.Tensor, stream=None):
+    """Per-antenna samples: (xyz [n_ant, n_ray, n_z, 3], jac [n_ant, n_ray, n_z])."""
+    n_ant = tx.shape[0]
+    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, 0, 0, 0)
+    n_ray = n_ray_x * n_ray_y
+    xyz = torch.empty(n_ant, n_ray, n_z, 3, dtype=torch.float32, device=tx.device)
+    jac = torch.empty(n_ant, n_ray, n_z, dtype=torch.float32, device=tx.device)
+    _check(lib().rfvr_sample_naive(ctypes.byref(d), _ptr(tx.contiguous()), int(n_ant), _ptr(xyz), _ptr(jac),
+                                   _stream(stream)), "rfvr_sample_naive")
+    return xyz, jac
+
+
 def sample_importance(centre, half_extent, primary_dir, n_ray_x, n_ray_y, logits: torch.Tensor,
                       n_imp, n_uni, seed=0, step=0, plane_offset=0.0, stream=None):
     """Proposal-guided depths: (xyz [n_ray, K, 3], u [n_ray, K], ray_origin [n_ray, 3]),
@@ -469,6 +486,18 @@ def bce(logits: torch.Tensor, t: torch.Tensor, want_grad=True, stream=None):
     return loss, g
 
 
+def mask_update(power: torch.Tensor, power_ref: torch.Tensor, history: torch.Tensor, tau_hi: float = 0.25,
+                tau_lo: float = 0.25, out=None, stream=None):
+    """Dynamic loss mask [n] (1 keep, 0 drop); updates history in place."""
+    n = power.numel()
+    mask = out if out is not None else torch.empty_like(power)
+    ws = _ws(lib().rfvr_mask_ws_bytes(n), power.device)
+    _check(lib().rfvr_mask_update(n, _ptr(power.contiguous()), _ptr(power_ref.contiguous()), _ptr(history),
+                                  float(tau_hi), float(tau_lo), _ptr(mask), _ptr(ws), ws.numel(),
+                                  _stream(stream)), "rfvr_mask_update")
+    return mask
+
+
 # C-ABI names
 rfvr_render_forward = render_forward
 rfvr_render_backward = render_backward
@@ -483,5 +512,7 @@ rfvr_occupancy = occupancy
 rfvr_proposal_forward = proposal_forward
 rfvr_proposal_backward = proposal_backward
 rfvr_sample_importance = sample_importance
+rfvr_sample_naive = sample_naive
 rfvr_proposal_targets = proposal_targets
 rfvr_bce = bce
+rfvr_mask_update = mask_update

@@ -51,6 +51,7 @@ class StepConfig:
     spec_flags: int = R.SPEC_CLAMP
     bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
     learn_s: bool = False                  # train log s with the head's learning rate
+    mask_tau: Optional[tuple] = None       # (tau_hi, tau_lo): dynamic loss masking on
 
     @property
     def n_pts(self) -> int:
@@ -129,6 +130,7 @@ class Trainer:
         self.target = target.contiguous()
         self.s = float(cfg.s)
         self._s_m = self._s_v = 0.0
+        self.history = None                    # per-point filter-output history (masking)
         self.t = 0
         self.p_star = None
         self._xyz_key = None
@@ -194,7 +196,15 @@ class Trainer:
         else:
             z, p = R.mf_forward(self.ap, xyz, sig)
         mark("mf_fwd")
-        loss, g_p = R.loss_l2(p, self.p_star)
+        mask = None
+        if c.mask_tau is not None:
+            # dynamic loss masking (Sec. Optimization): per sample point, so the
+            # sample set must be the same every step (grid or stratified cells)
+            if self.history is None:
+                self.history = torch.zeros_like(p)
+            mask = R.mask_update(p, self.p_star, self.history, *c.mask_tau)
+        loss, g_p = R.loss_l2(p, self.p_star, mask=mask)
+        self.last_mask = mask
         # the filter has no parameters: only the traced rows carry gradient
         g_sig = R.mf_backward(ap_r, xyz, z, p, g_p)
         mark("mf_bwd")

@@ -207,3 +207,31 @@ def test_sampling_origins_on_the_aperture_plane():
     d = b[0] - b[2][:, None, :]
     cross = np.cross(d, w[None, None, :])
     assert np.abs(cross).max() < 1e-14
+
+
+def test_naive_samples_on_antenna_rays_and_volume_jacobian():
+    """Per-antenna samples lie on the ray from the antenna through their grid
+    point, inside the cube's slab; for an on-axis antenna the Jacobian-weighted
+    cell volumes add up to the volume of the pyramid frustum the rays fill
+    (closed form), within the midpoint rule's error."""
+    from oracle.sampling import sample_naive
+    c, h = (0.0, 0.0, 0.30), 0.05
+    tx = np.array([[0.0, 0.0, 0.0], [0.004, -0.002, 0.0]])
+    n = (8, 6, 40)
+    xyz, jac = sample_naive(tx, c, h, (0, 0, 1), *n)
+    assert xyz.shape == (2, 48, 40, 3) and jac.shape == (2, 48, 40)
+    assert xyz[..., 2].min() > 0.25 and xyz[..., 2].max() < 0.35
+    d = xyz - tx[:, None, None, :]
+    cross = np.cross(d[:, :, :1, :], d)                      # all samples of a ray are collinear
+    assert np.abs(cross).max() < 1e-15
+    # on-axis antenna: frustum of the pyramid through the 10 cm square at z = 0.30
+    dV = (2 * h / n[0]) * (2 * h / n[1]) * (2 * h / n[2])
+    D, V_exact = 0.30, 4 * h * h / 0.30 ** 2 * ((0.30 + h) ** 3 - (0.30 - h) ** 3) / 3.0
+    V = jac[0].sum() * dV
+    assert abs(V - V_exact) / V_exact < 1e-3
+    # a distant antenna gives parallel rays: the lensless grid, unit Jacobian
+    far = np.array([[0.0, 0.0, -1e5]])
+    xf, jf = sample_naive(far, c, h, (0, 0, 1), 4, 4, 5)
+    from oracle.sampling import sample_points
+    xs, _, _ = sample_points(c, h, (0, 0, 1), 4, 4, 5)
+    assert np.abs(xf[0] - xs).max() < 1e-6 and np.abs(jf - 1).max() < 1e-5
