@@ -296,13 +296,14 @@ struct DualArgs {
     float beta;
 };
 
-template <int EPI2, int MM>
-__global__ __launch_bounds__(512) void k_gemm_dual(DualArgs g) {
-    // 8 waves: 4 along points x 2 along outputs, 2 x 4 tiles of 16 x 16 each,
-    // two accumulator sets (64 registers) per wave
-    constexpr int NT = 512;
-    constexpr int BP = 128, BM = 128, BK = 32, LW = BK + 4;
-    constexpr int WP = 4, TP = 2, TM = 4;
+template <int EPI2, int MM, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_dual(DualArgs g) {
+    // NW = 8: 4 waves along points x 2 along outputs, 128 x 128 block, 2 x 4
+    // tiles of 16 x 16 per wave; NW = 4: 2 x 2 waves, 128 x 64 block, 4 x 2
+    // tiles.  Two accumulator sets (64 registers) per wave either way.
+    constexpr int NT = NW * 64;
+    constexpr int BP = 128, BM = NW == 8 ? 128 : 64, BK = 32, LW = BK + 4;
+    constexpr int WP = NW == 8 ? 4 : 2, TP = BP / WP / 16, TM = BM / 2 / 16;
     constexpr int NA = BP * BK / 4 / NT, NB = BM * BK / 4 / NT;
     __shared__ float sA[BP * LW];
     __shared__ float sA2[BP * LW];
@@ -1016,15 +1017,19 @@ void gemm32(const GemmArgs& a, const Cx& cx) {
     gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
 }
 
+#ifndef RFVR_DUAL_NW
+#define RFVR_DUAL_NW 8
+#endif
 template <int EPI2>
 void gemm_dual(const DualArgs& a, int mm, hipStream_t st) {
+    constexpr int NW = RFVR_DUAL_NW, BM = NW == 8 ? 128 : 64;
     const long tiles = (a.P + 127) / 128;
     const long groups = (tiles + 7) / 8;
-    const long nmb = (a.M + 127) / 128;
+    const long nmb = (a.M + BM - 1) / BM;
     const dim3 grid((unsigned)(groups * 8 * nmb));
-    if (mm == MM_BF16) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16>), grid, dim3(512), 0, st, a);
-    else if (mm == MM_BF16X3) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16X3>), grid, dim3(512), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_FP32>), grid, dim3(512), 0, st, a);
+    if (mm == MM_BF16) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16, NW>), grid, dim3(NW * 64), 0, st, a);
+    else if (mm == MM_BF16X3) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16X3, NW>), grid, dim3(NW * 64), 0, st, a);
+    else hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_FP32, NW>), grid, dim3(NW * 64), 0, st, a);
 }
 
 DualArgs da(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
