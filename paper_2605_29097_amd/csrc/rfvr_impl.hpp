@@ -225,8 +225,7 @@ __device__ __forceinline__ void cos_sin_rev_accurate(double d, float& c, float& 
 template <bool NAIVE>
 __device__ __forceinline__ void step_phasor(const PairGeom& g, double Kd, float& c, float& s) {
     if constexpr (!NAIVE) {
-        const float de = (float)(g.r * Kd);
-        sincospif(2.0f * de, &s, &c);
+        cos_sin_rev_cr32(g.r * Kd, c, s);
     } else {
         sincosf((float)(6.283185307179586 * Kd) * g.rf, &s, &c);
     }
