@@ -46,19 +46,20 @@ __device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big
 // split operands (a b ~ a_big b_big + a_big b_small + a_small b_big)
 enum { MM_FP32 = 0, MM_BF16 = 1, MM_BF16X3 = 3 };
 
-enum { PRO_ID = 0, PRO_SP = 1, PRO_DSP_MUL = 2, PRO_RELU = 3 };
+// operand prologues: identity or relu (the softplus activations are written
+// by the producing GEMM's epilogue, so no operand is transformed twice)
+enum { PRO_ID = 0, PRO_RELU = 3 };
 // epilogues: BIAS  Y = acc + bias
 //            ACC   Y += acc
 //            RELUMASK  Y = acc where C > 0, else 0
 //            BIAS_SP   Y = acc + bias and Y2 = softplus(Y)            (layer output and activation)
 //            DSPMUL    Y = acc * softplus'(C)                          (normal sweep, adjoint to Z)
-//            DSP2      Y = acc and Y2 = acc * softplus'(C)              (tangent and its activation)
-enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_DSP2 = 5 };
+enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4 };
 
 // Activation math of the network on the hardware exp2 / log2 / rcp units
-// (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once or twice per
-// GEMM operand element, where the correctly rounded library forms would
-// dominate the VALU time of the fused operand loads.
+// (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once per element
+// in the GEMM epilogues and elementwise kernels, where the correctly rounded
+// library forms would add several times their VALU work.
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 __device__ __forceinline__ float flog1p_pos(float e) {           // log(1 + e), e in [0, 1]
     return __builtin_amdgcn_logf(1.0f + e) * 0.6931471805599453f;
@@ -74,19 +75,6 @@ __device__ __forceinline__ float sp_d2(float z, float beta) {
     return beta * s * (1.0f - s);
 }
 
-template <int PRO>
-__device__ __forceinline__ float4 prologue(float4 v, const float* a2, float beta) {
-    if constexpr (PRO == PRO_SP) {
-        v.x = sp_f(v.x, beta); v.y = sp_f(v.y, beta); v.z = sp_f(v.z, beta); v.w = sp_f(v.w, beta);
-    } else if constexpr (PRO == PRO_DSP_MUL) {
-        const float4 u = *reinterpret_cast<const float4*>(a2);
-        v.x = sp_d1(v.x, beta) * u.x; v.y = sp_d1(v.y, beta) * u.y;
-        v.z = sp_d1(v.z, beta) * u.z; v.w = sp_d1(v.w, beta) * u.w;
-    } else if constexpr (PRO == PRO_RELU) {
-        v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
-    }
-    return v;
-}
 
 // ----------------------------------------------------------------------------
 // Y[P x M] = pro(A)[P x K] * B[M x K]^T  (+ epilogue).  K multiple of 32; A and
@@ -117,7 +105,6 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     constexpr int TM = BM / WM / 16;
     constexpr int NA = BP * BK / 4 / 256;       // float4 per thread, A
     constexpr int NB = BM * BK / 4 / 256;       // float4 per thread, B
-    constexpr bool TWO = PRO == PRO_DSP_MUL;
     __shared__ float sA[BP * LW];
     __shared__ float sB[BM * LW];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -141,7 +128,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    float4 ra[NA], ra2[TWO ? NA : 1], rb[NB];
+    float4 ra[NA], rb[NB];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
@@ -149,12 +136,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             const int row = e >> 3, c4 = (e & 7) * 4;
             const long p = p0 + row;
             ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if constexpr (TWO) ra2[i] = ra[i];
-            if (p < g.P) {
-                const long off = p * g.lda + k0 + c4;
-                ra[i] = *reinterpret_cast<const float4*>(g.A + off);
-                if constexpr (TWO) ra2[i] = *reinterpret_cast<const float4*>(g.A2 + off);
-            }
+            if (p < g.P) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -172,13 +154,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             const int e = tid + i * 256;
             const int row = e >> 3, c4 = (e & 7) * 4;
             float4 v = ra[i];
-            if constexpr (PRO == PRO_SP) {
-                v.x = sp_f(v.x, g.beta); v.y = sp_f(v.y, g.beta); v.z = sp_f(v.z, g.beta); v.w = sp_f(v.w, g.beta);
-            } else if constexpr (PRO == PRO_DSP_MUL) {
-                const float4 u = ra2[TWO ? i : 0];
-                v.x = sp_d1(v.x, g.beta) * u.x; v.y = sp_d1(v.y, g.beta) * u.y;
-                v.z = sp_d1(v.z, g.beta) * u.z; v.w = sp_d1(v.w, g.beta) * u.w;
-            } else if constexpr (PRO == PRO_RELU) {
+            if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
             *reinterpret_cast<float4*>(&sA[row * LW + c4]) = v;
@@ -268,7 +244,6 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
                 g.Y[p * g.ldy + m] = y;
                 if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
-                if constexpr (EPI == EPI_DSP2) g.Y2[p * g.ldy + m] = y * sp_d1(g.C[p * g.ldc + m], g.beta);
             }
         }
 }
@@ -479,7 +454,6 @@ struct WgArgs {
 template <int PRO, bool BIAS, int MM>
 __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
     constexpr int BM = 128, BN = 128, BK = 32, LW = 128 + 4;
-    constexpr bool TWO = PRO == PRO_DSP_MUL;
     __shared__ float sA[BK * LW];
     __shared__ float sB[BK * LW];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -506,7 +480,7 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
         for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;                         // column sum of A (thread tid < 128 -> column tid)
 
-    float4 ra[4], rb[4], rb2[TWO ? 4 : 1];
+    float4 ra[4], rb[4];
     auto load = [&](long q0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -515,13 +489,11 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
             const long p = q0 + row;
             ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             rb[i] = ra[i];
-            if constexpr (TWO) rb2[i] = ra[i];
             if (p < pe) {
                 if (m0 + c4 < g.M) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c4);
                 if (n0 + c4 < g.Kout) {
                     const long off = p * g.ldb + n0 + c4;
                     rb[i] = *reinterpret_cast<const float4*>(g.B + off);
-                    if constexpr (TWO) rb2[i] = *reinterpret_cast<const float4*>(g.B2 + off);
                 }
             }
         }
@@ -534,13 +506,7 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
             const int row = e >> 5, c4 = (e & 31) * 4;
             const bool live = q0 + row < pe;
             float4 v = rb[i];
-            if constexpr (PRO == PRO_SP) {
-                v.x = sp_f(v.x, g.beta); v.y = sp_f(v.y, g.beta); v.z = sp_f(v.z, g.beta); v.w = sp_f(v.w, g.beta);
-            } else if constexpr (PRO == PRO_DSP_MUL) {
-                const float4 u = rb2[TWO ? i : 0];
-                v.x = sp_d1(v.x, g.beta) * u.x; v.y = sp_d1(v.y, g.beta) * u.y;
-                v.z = sp_d1(v.z, g.beta) * u.z; v.w = sp_d1(v.w, g.beta) * u.w;
-            } else if constexpr (PRO == PRO_RELU) {
+            if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
             if (!live) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -661,7 +627,7 @@ __global__ void k_wg_reduce(const float* __restrict__ part, int n_split, int M, 
 // ----------------------------------------------------------------------------
 // column sums with fused element functions, two fixed-order stages
 //   mode 0: X[p][m]      mode 1: s[p] relu(X[p][m])
-//   mode 2: s[p] sp(X[p][m]) + sp'(X[p][m]) X2[p][m]
+//   mode 3: s[p] X[p][m] + X2[p][m]   (s may be NULL)
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict__ X,
                                                         const float* __restrict__ X2,
@@ -680,7 +646,6 @@ __global__ __launch_bounds__(256) void k_colsum_partial(const float* __restrict_
         float d;
         if (mode == 0) d = x;
         else if (mode == 1) d = s[p] * fmaxf(x, 0.0f);
-        else if (mode == 2) d = (s ? s[p] * sp_f(x, beta) : 0.0f) + sp_d1(x, beta) * X2[p * ldx + m];
         else d = (s ? s[p] * x : 0.0f) + X2[p * ldx + m];
         acc += d;
     }
@@ -767,7 +732,7 @@ __global__ void k_pe_grad(long n, const float* __restrict__ xyz, float cx, float
 }
 
 // out[p] = post(scale * (sum_m w[m] act(Y[p][m]) + b)); one wave per row
-//   act: 0 identity, 1 softplus, 3 relu ; post: 0 identity, 1 sigmoid
+//   act: 0 identity, 3 relu ; post: 0 identity, 1 sigmoid
 __global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict__ Y, long ldy,
                                                 int M, int act, int post, const float* __restrict__ w,
                                                 const float* __restrict__ b, float scale, float beta,
@@ -778,7 +743,7 @@ __global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict_
     float acc = 0.0f;
     for (int m = lane; m < M; m += 64) {
         const float y = Y[p * ldy + m];
-        const float a = act == PRO_ID ? y : (act == PRO_SP ? sp_f(y, beta) : fmaxf(y, 0.0f));
+        const float a = act == PRO_ID ? y : fmaxf(y, 0.0f);
         acc = __builtin_fmaf(w[m], a, acc);
     }
 #pragma unroll

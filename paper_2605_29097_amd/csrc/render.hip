@@ -7,14 +7,14 @@
 //    chunk's complex accumulators in VGPRs; all lanes of a work-group walk the
 //    same points, whose records are staged through LDS in double-buffered
 //    tiles of 64 (one wide load per record, broadcast reads, the next tile's
-//    global loads in flight).  Per (measurement, point) the path length (FP64) and the
-//    step phasor (accurately rounded) are set up once; every 16 frequencies a
-//    phasor is re-seeded from an FP64-reduced phase at the sub-chunk centre
-//    and the sub-chunk is walked both ways (f_n is linear in n) by the
-//    three-term recurrence p_{n+1} = 2 cos(2 pi delta) p_n - p_{n-1} (2 FMA per
-//    term and part, RFVR_RP_CHEB; the complex-rotation walk is the
-//    alternative).  Points are split across work-groups and the partial sums reduced
-//    in a fixed order (no atomics).
+//    global loads in flight).  Per (measurement, point) the path length (FP64)
+//    and the correctly rounded step phasor are set up once; every 32
+//    frequencies a phasor is re-seeded from an FP64-reduced phase at the
+//    sub-chunk centre and the sub-chunk is walked both ways (f_n is linear in
+//    n) by the three-term recurrence p_{n+1} = 2 cos(2 pi delta) p_n - p_{n-1}
+//    (one FMA per term and part, plus the accumulate).  Points are split across
+//    work-groups (XCD-aware) and the partial sums reduced in a fixed order (no
+//    atomics).
 //  * backward: a lane owns one point; all lanes walk the same measurements, so
 //    measurement records and the incoming signal gradient row are scalar loads.
 //    sum_n g[n] exp(+j 2 pi (theta0 + n delta)) is, around the middle
@@ -149,22 +149,17 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
 // adjoint (KIND 1).  Lane t -> measurement i = t % n_meas, chunk c = t / n_meas;
 // grid.y = point split.
 // ---------------------------------------------------------------------------
-#ifndef RFVR_RP_CHEB
-#define RFVR_RP_CHEB 1
-#endif
-#ifndef RFVR_RP_SEED
-#define RFVR_RP_SEED 32
-#endif
-#ifndef RFVR_RP_ACC_SEED
-#define RFVR_RP_ACC_SEED 0
-#endif
+// Seeds every kSeed frequencies: the walks run kSeed/2 steps each way; longer
+// walks trade fewer seeds for rounding growth (16: 4.1e-5, 32: 5.7e-5, 64: 9.9e-5
+// relative error of the 2^20-point signal against the FP64 reference).
+constexpr int kSeed = 32;
 
 template <int F, int KIND, int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_reduce_points(
     int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
     const void* __restrict__ recs_v, long n_pts, long pts_per_split, int n_split, int gx,
     float2* __restrict__ partial) {
-    constexpr int S = F < RFVR_RP_SEED ? F : RFVR_RP_SEED;   // re-seed interval
+    constexpr int S = F < kSeed ? F : kSeed;     // re-seed interval
     constexpr int NS = F / S;
     // point records of the block's split are staged through LDS in tiles of
     // TILE, shared by the 4 waves; the next tile is fetched into registers
@@ -241,19 +236,17 @@ __global__ __launch_bounds__(256) void k_reduce_points(
             }
             {
                 float cw, sw;
-                step_phasor_cr<NAIVE>(g, Kd, cw, sw);
+                step_phasor<NAIVE>(g, Kd, cw, sw);
                 wr = cw;
                 wi = -sw;                  // exp(-j 2 pi delta)
             }
 #pragma unroll
             for (int m = 0; m < NS; ++m) {
                 float c0, s0;
-                if constexpr (RFVR_RP_ACC_SEED) seed_phasor_cr<NAIVE>(g, Kc[m], c0, s0);
-                else seed_phasor<NAIVE>(g, Kc[m], c0, s0);
+                seed_phasor<NAIVE>(g, Kc[m], c0, s0);
                 // (cr + j ci) * exp(-j 2 pi theta_centre)
                 const float pr0 = __builtin_fmaf(cr, c0, ci * s0);
                 const float pi0 = __builtin_fmaf(ci, c0, -cr * s0);
-#if RFVR_RP_CHEB
                 // three-term recurrence p_{n+1} = 2 cos(2 pi delta) p_n - p_{n-1}
                 // (both parts), seeded with p_0 and p_{+-1} = p_0 w^{+-1}
                 const float k2 = 2.0f * wr;
@@ -279,27 +272,6 @@ __global__ __launch_bounds__(256) void k_reduce_points(
                         const float tr = __builtin_fmaf(k2, ar1, -ar0), ti = __builtin_fmaf(k2, ai1, -ai0);
                         ar0 = ar1; ai0 = ai1; ar1 = tr; ai1 = ti;
                     }
-                }
-                continue;
-#endif
-                float pr = pr0, pi = pi0;
-#pragma unroll
-                for (int u = S / 2; u < S; ++u) {
-                    ar[m * S + u] += pr;
-                    ai[m * S + u] += pi;
-                    const float tr = __builtin_fmaf(pr, wr, -pi * wi);
-                    pi = __builtin_fmaf(pr, wi, pi * wr);
-                    pr = tr;
-                }
-                pr = pr0;
-                pi = pi0;
-#pragma unroll
-                for (int u = S / 2 - 1; u >= 0; --u) {
-                    const float tr = __builtin_fmaf(pr, wr, pi * wi);     // times conj(w)
-                    pi = __builtin_fmaf(pi, wr, -pr * wi);
-                    pr = tr;
-                    ar[m * S + u] += pr;
-                    ai[m * S + u] += pi;
                 }
             }
         }

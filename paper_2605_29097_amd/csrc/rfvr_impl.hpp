@@ -94,7 +94,7 @@ __device__ __forceinline__ float alpha_pair(float a, float b) {
 // A pair's frequencies are visited by a recurrence in the step phasor
 // w = exp(-+ j 2 pi delta).  Rounding of w grows linearly along a walk and the
 // rendered signal is a heavily cancelling sum (Fresnel zones), so:
-//  * w comes from an accurately rounded sin/cos (cos_sin_rev_accurate);
+//  * w comes from a correctly rounded sin/cos (cos_sin_rev_cr32);
 //  * walks are short: every S frequencies the phasor is re-seeded from an
 //    FP64-reduced phase at the centre of the sub-chunk and walked S/2 steps
 //    up and S/2 steps down.
@@ -136,10 +136,10 @@ __device__ __forceinline__ void seed_phasor(const PairGeom& g, double K, float& 
 // ---------------------------------------------------------------------------
 // correctly rounded cos / sin of 2 pi d for an FP64 phase d (revolutions):
 // d mod 1 = k / 1024 + e with |e| <= 1/2048; cos/sin(2 pi k / 1024) from a
-// table and cos/sin(2 pi e) from their Taylor series (|2 pi e| <= pi / 1024:
-// three terms leave < 1e-19), combined by the angle-sum identities, all in
-// FP64 and rounded once to FP32.  The table is built at compile time from the
-// Taylor series of cos and sin on the first octant and the 45-degree rotation.
+// table and cos/sin(2 pi e) from their Taylor series (|2 pi e| <= pi / 1024),
+// combined by the angle-sum identities.  The table is built at compile time in
+// FP64 from the Taylor series of cos and sin on the first octant and the
+// 45-degree rotation.
 // ---------------------------------------------------------------------------
 namespace phase_table {
 constexpr double kPi = 3.141592653589793238462643383279502884;
@@ -172,13 +172,12 @@ struct Table {
     }
 };
 }  // namespace phase_table
-__device__ constexpr phase_table::Table kPhaseTable{};
-
 // The same table split into FP32 hi/lo parts (c_hi, c_lo, s_hi, s_lo): with
 // x = 2 pi e, cos(a + x) = cos a + [cos a (cos x - 1) - sin a sin x] (and the
 // sine alike).  The bracket is below 3.2e-3 in magnitude, so FP32 evaluates it
-// to ~4e-10 and the final addition rounds once: cos/sin within ~0.5 ulp with
-// five FP64 operations (the reduction) instead of fifteen.
+// to ~4e-10 and the final addition rounds once: cos/sin within 3.1e-8
+// absolute (half an ulp of values near 1), with five FP64 operations (the
+// reduction of d).
 struct TableHiLo {
     float v[4 * 1024];
     constexpr TableHiLo() : v() {
@@ -208,20 +207,9 @@ __device__ __forceinline__ void cos_sin_rev_cr32(double d, float& c, float& s) {
     s = t.z + __builtin_fmaf(t.z, cm, __builtin_fmaf(t.x, sx, t.w));
 }
 
-__device__ __forceinline__ void cos_sin_rev_accurate(double d, float& c, float& s) {
-    const double dr = __builtin_amdgcn_fract(d) * 1024.0;     // exact scaling
-    const double kf = __builtin_rint(dr);
-    const int k = (int)kf & 1023;
-    const double x = (dr - kf) * (6.283185307179586476925 / 1024.0);
-    const double x2 = x * x;
-    const double cl = __builtin_fma(x2, __builtin_fma(x2, 1.0 / 24.0, -0.5), 1.0);
-    const double sl = __builtin_fma(x * x2, __builtin_fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
-    const double tc = kPhaseTable.v[2 * k], ts = kPhaseTable.v[2 * k + 1];
-    c = (float)__builtin_fma(tc, cl, -ts * sl);
-    s = (float)__builtin_fma(ts, cl, tc * sl);
-}
-
-// accurate step phasor cos/sin of 2 pi * (Kd * r) (frequency reductions)
+// correctly rounded step phasor cos/sin of 2 pi * (Kd * r); the point
+// reductions' three-term recurrence amplifies the rounding of cos by
+// 1 / sin(2 pi delta), so it needs that accuracy
 template <bool NAIVE>
 __device__ __forceinline__ void step_phasor(const PairGeom& g, double Kd, float& c, float& s) {
     if constexpr (!NAIVE) {
@@ -229,19 +217,6 @@ __device__ __forceinline__ void step_phasor(const PairGeom& g, double Kd, float&
     } else {
         sincosf((float)(6.283185307179586 * Kd) * g.rf, &s, &c);
     }
-}
-
-// correctly rounded step / seed phasors (point reductions, where the
-// three-term recurrence amplifies the rounding of cos by 1 / sin(2 pi delta))
-template <bool NAIVE>
-__device__ __forceinline__ void step_phasor_cr(const PairGeom& g, double Kd, float& c, float& s) {
-    if constexpr (!NAIVE) cos_sin_rev_cr32(g.r * Kd, c, s);
-    else sincosf((float)(6.283185307179586 * Kd) * g.rf, &s, &c);
-}
-template <bool NAIVE>
-__device__ __forceinline__ void seed_phasor_cr(const PairGeom& g, double K, float& c, float& s) {
-    if constexpr (!NAIVE) cos_sin_rev_accurate(g.r * K, c, s);
-    else sincosf((float)(6.283185307179586 * K) * g.rf, &s, &c);
 }
 
 // ----------------------------------------------------------------------------
