@@ -233,6 +233,28 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                       const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* Training pair: the same two operations, sharing a caller-owned reserve
+ * (device, 256-byte aligned, rfvr_mlp_reserve_bytes() bytes: every trunk
+ * layer's pre-activation and activation, float32 [n][width] each).
+ * rfvr_mlp_forward_train computes what rfvr_mlp_forward does and fills the
+ * reserve; rfvr_mlp_backward_train reads it instead of recomputing the primal
+ * layers, so it runs one matrix product per layer fewer.  The caller keeps
+ * net (params unchanged), xyz and n the same between the two calls and does
+ * not write the reserve in between; nothing checks this, and a mismatch gives
+ * wrong gradients without an error.  Outputs agree with the plain calls to
+ * float32 rounding.  A NULL or zero-sized reserve is RFVR_E_INVALID, a short
+ * or misaligned one RFVR_E_WORKSPACE. */
+size_t rfvr_mlp_reserve_bytes(const rfvr_mlp* net, int64_t n);
+size_t rfvr_mlp_forward_train_ws_bytes(const rfvr_mlp* net, int64_t n);
+int rfvr_mlp_forward_train(const rfvr_mlp* net, const float* xyz, int64_t n, float* sdf, float* grad,
+                           float* refl, void* reserve, size_t reserve_bytes, void* ws, size_t ws_bytes,
+                           void* stream);
+size_t rfvr_mlp_backward_train_ws_bytes(const rfvr_mlp* net, int64_t n);
+int rfvr_mlp_backward_train(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
+                            const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
+                            const void* reserve, size_t reserve_bytes, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* ------------------------------------------------------------------------
  * AdamW update (App. C: AdamW with cosine annealing), step t >= 1:
  *   m = b1 m + (1-b1) g ; v = b2 v + (1-b2) g^2

@@ -11,9 +11,12 @@
 // Backward call: J = sum g_f f + g_grad . grad_x f + g_a a.  Since
 // g_grad . grad_x f is the directional derivative of f along g_grad, the
 // parameter gradient is reverse mode over a primal + tangent forward pass
-// (Z, Zdot per layer), giving per layer
+// (Z, H, Hdot = sp'(Z) Zdot per layer), giving per layer
 //   Zdot_bar = sp'(Z) Hdot_bar,  Z_bar = sp'(Z) H_bar + sp''(Z) Zdot Hdot_bar,
-//   W_bar = Z_bar^T H + Zdot_bar^T Hdot,  H_bar = Z_bar W,  Hdot_bar = Zdot_bar W.
+//   W_bar = Z_bar^T H + Zdot_bar^T Hdot,  H_bar = Z_bar W,  Hdot_bar = Zdot_bar W,
+// where sp''(Z) Zdot = beta sigma(-beta Z) Hdot, so Zdot itself is never stored.
+// The training pair of calls keeps the forward's (Z, H) of every layer in a
+// caller-owned reserve; the backward then runs only the tangent GEMM per layer.
 // Weight gradients reduce over points in fixed splits (no atomics).
 #include "rfvr_impl.hpp"
 
@@ -88,10 +91,10 @@ struct GemmArgs {
     const float* A; const float* A2; long lda;
     const float* B; long ldb;
     const float* bias;            // EPI_BIAS: [M] or null
-    const float* C;               // EPI_RELUMASK / DSPMUL / DSP2: [P][ldc]
+    const float* C;               // EPI_RELUMASK / DSPMUL: [P][ldc]
     long ldc;
     float* Y; long ldy;
-    float* Y2;                    // EPI_BIAS_SP / DSP2: second output, row stride ldy
+    float* Y2;                    // EPI_BIAS_SP: second output, row stride ldy
     long P; int M; int K;
     float beta;
 };
@@ -252,11 +255,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 // Two products with one B operand, Y = A B^T and Yd = A2 B^T (a layer's primal
 // and tangent, or the two adjoints of its input), the layer's elementwise work
 // in the epilogue:
-//   EPI2_FWD: Z = acc + bias, H = sp(Z), Zdot = acc2, Hdot = sp'(Z) Zdot
-//             -> Y, Y2, Y3, Y4
-//   EPI2_ADJ: Hbar = acc, Hdotbar = acc2 with C = Z, C2 = Zdot of the layer below:
-//             Zbar = sp'(Z) Hbar + sp''(Z) Zdot Hdotbar, Zdotbar = sp'(Z) Hdotbar
-//             -> Y, Y2
+//   EPI2_FWD: Z = acc + bias, H = sp(Z), Hdot = sp'(Z) acc2     -> Y, Y2, Y3
+//   EPI2_ADJ: Hbar = acc, Hdotbar = acc2 with C = Z, C2 = Hdot of the layer below:
+//             Zbar = sp'(Z) Hbar + beta sigma(-beta Z) Hdot Hdotbar,
+//             Zdotbar = sp'(Z) Hdotbar                         -> Y, Y2
 // Tiling as k_gemm_nt with BM = 128; the B tile is staged once for both.
 // ----------------------------------------------------------------------------
 enum { EPI2_FWD = 0, EPI2_ADJ = 1 };
@@ -266,7 +268,7 @@ struct DualArgs {
     const float* B; long ldb;
     const float* bias;
     const float* C; const float* C2;        // EPI2_ADJ: [P][ldy]
-    float* Y; float* Y2; float* Y3; float* Y4; long ldy;
+    float* Y; float* Y2; float* Y3; long ldy;
     long P; int M; int K;
     float beta;
 };
@@ -417,17 +419,15 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_dual(DualArgs g) {
                 if (p >= g.P) continue;
                 const long o = p * g.ldy + m;
                 if constexpr (EPI2 == EPI2_FWD) {
-                    const float z = acc[a][b][v] + bias, zd = acd[a][b][v];
+                    const float z = acc[a][b][v] + bias;
                     g.Y[o] = z;
                     g.Y2[o] = sp_f(z, g.beta);
-                    g.Y3[o] = zd;
-                    g.Y4[o] = sp_d1(z, g.beta) * zd;
+                    g.Y3[o] = sp_d1(z, g.beta) * acd[a][b][v];
                 } else {
-                    const float z = g.C[o], zd = g.C2[o];
+                    const float z = g.C[o], hd = g.C2[o];
                     const float sg = fsig(g.beta * z);
-                    const float d2 = g.beta * sg * (1.0f - sg);
                     const float hb = acc[a][b][v], hdb = acd[a][b][v];
-                    g.Y[o] = sg * hb + d2 * zd * hdb;
+                    g.Y[o] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
                     g.Y2[o] = sg * hdb;
                 }
             }
@@ -795,9 +795,9 @@ __global__ void k_top_adjoint(long n, int M, const float* __restrict__ g_f, cons
     Hdb[p * ld + m] = half * w[m];
 }
 
-// Z_bar = sp'(Z) H_bar + sp''(Z) Zdot Hdot_bar ; Zdot_bar = sp'(Z) Hdot_bar
+// Z_bar = sp'(Z) H_bar + beta sigma(-beta Z) Hdot Hdot_bar ; Zdot_bar = sp'(Z) Hdot_bar
 __global__ void k_layer_adjoint(long n, int M, long ld, const float* __restrict__ Z,
-                                const float* __restrict__ Zd, const float* __restrict__ Hb,
+                                const float* __restrict__ Hd, const float* __restrict__ Hb,
                                 const float* __restrict__ Hdb, float beta, float* __restrict__ Zb,
                                 float* __restrict__ Zdb) {
     const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -806,9 +806,8 @@ __global__ void k_layer_adjoint(long n, int M, long ld, const float* __restrict_
     const long e = p * ld + (o % M);
     const float z = Z[e];
     const float s = fsig(beta * z);
-    const float d2 = beta * s * (1.0f - s);
     const float hdb = Hdb[e];
-    Zb[e] = s * Hb[e] + d2 * Zd[e] * hdb;
+    Zb[e] = s * Hb[e] + beta * (1.0f - s) * Hd[e] * hdb;
     Zdb[e] = s * hdb;
 }
 
@@ -998,11 +997,11 @@ void gemm_dual(const DualArgs& a, int mm, hipStream_t st) {
 }
 
 DualArgs da(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
-            const float* C, const float* C2, float* Y, float* Y2, float* Y3, float* Y4, long ldy,
+            const float* C, const float* C2, float* Y, float* Y2, float* Y3, long ldy,
             long P, int M, int K, float beta) {
     DualArgs g;
     g.A = A; g.A2 = A2; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.C = C; g.C2 = C2;
-    g.Y = Y; g.Y2 = Y2; g.Y3 = Y3; g.Y4 = Y4; g.ldy = ldy; g.P = P; g.M = M; g.K = K; g.beta = beta;
+    g.Y = Y; g.Y2 = Y2; g.Y3 = Y3; g.ldy = ldy; g.P = P; g.M = M; g.K = K; g.beta = beta;
     return g;
 }
 
@@ -1055,73 +1054,67 @@ void colsum(const float* X, const float* X2, const float* s, long ldx, long P, i
 }
 
 // --- forward workspace -------------------------------------------------------
-size_t fwd_bytes(const Layout& l, long n) {
+// keep: the layers' (Z, H) go to the caller's reserve instead of the workspace
+size_t fwd_bytes(const Layout& l, long n, bool keep) {
     const long c = n < kChunk ? n : kChunk;
     return weights_bytes(l) + align256(sizeof(float) * c * l.in0p) +
-           (size_t)l.L * align256(sizeof(float) * c * l.W) + 2 * align256(sizeof(float) * c * l.W) +
+           (keep ? 0 : (size_t)l.L * align256(sizeof(float) * c * l.W)) + 2 * align256(sizeof(float) * c * l.W) +
            (size_t)l.HL * align256(sizeof(float) * c * l.HW);
 }
 
 // --- backward workspace ------------------------------------------------------
-size_t bwd_bytes(const Layout& l, long n) {
+size_t bwd_bytes(const Layout& l, long n, bool keep) {
     const long c = n < kChunk ? n : kChunk;
     const long wmax = l.W > l.in0p ? l.W : l.in0p;
     return weights_bytes(l) + 2 * align256(sizeof(float) * c * l.in0p) +
-           4 * (size_t)l.L * align256(sizeof(float) * c * l.W) +   // Z, Zdot, H, Hdot
+           (keep ? 1 : 3) * (size_t)l.L * align256(sizeof(float) * c * l.W) +  // Hdot (and Z, H)
            4 * align256(sizeof(float) * c * l.W) +                  // Hbar, Hdotbar, Zbar, Zdotbar
            2 * (size_t)l.HL * align256(sizeof(float) * c * l.HW) +  // head Y, Ybar
-           align256(sizeof(float) * c * l.HW) +                     // scratch head adjoint
            align256(sizeof(float) * c) +                            // ybar3
            align256(sizeof(float) * 2 * kWgSplits * (size_t)l.W * wmax) +
            align256(sizeof(float) * kWgSplits * (size_t)l.W) +
            align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
 }
 
-}  // namespace
-}  // namespace rfvr
+// --- reserve of the training pair: Z_i [n][W] for every layer, then H_i -------
+size_t reserve_layer_bytes(const Layout& l, long n) { return align256(sizeof(float) * (size_t)n * l.W); }
+size_t reserve_bytes(const Layout& l, long n) { return 2 * (size_t)l.L * reserve_layer_bytes(l, n); }
+float* reserve_z(void* r, const Layout& l, long n, int i) {
+    return reinterpret_cast<float*>(static_cast<char*>(r) + (size_t)i * reserve_layer_bytes(l, n));
+}
+float* reserve_h(void* r, const Layout& l, long n, int i) { return reserve_z(r, l, n, l.L + i); }
 
-using namespace rfvr;
-
-extern "C" {
-
-int64_t rfvr_mlp_param_count(const rfvr_mlp* net) {
-    if (check_net(net)) return -1;
-    return layout(net).total;
+int check_buffers(void* ws, size_t ws_bytes, size_t need, void* reserve, size_t reserve_bytes_, size_t rneed) {
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
+        set_error("workspace too small or misaligned: need %zu bytes", need);
+        return RFVR_E_WORKSPACE;
+    }
+    if (rneed && (!reserve || reserve_bytes_ < rneed || (reinterpret_cast<uintptr_t>(reserve) & 255u))) {
+        set_error("reserve too small or misaligned: need %zu bytes", rneed);
+        return RFVR_E_WORKSPACE;
+    }
+    return RFVR_OK;
 }
 
-size_t rfvr_mlp_forward_ws_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
-    return fwd_bytes(layout(net), (long)n);
-}
-
-size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
-    return bwd_bytes(layout(net), (long)n);
-}
-
-int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sdf, float* grad,
-                     float* refl, void* ws, size_t ws_bytes, void* stream) {
+int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float* grad, float* refl,
+                void* reserve, size_t reserve_bytes_, void* ws, size_t ws_bytes, hipStream_t st) {
     int rc;
     if ((rc = check_net(net))) return rc;
     if (n < 1 || !xyz || !net->params) { set_error("n >= 1, xyz and params are required"); return RFVR_E_INVALID; }
     const Layout l = layout(net);
-    {
-        const size_t need = fwd_bytes(l, (long)n);
-        if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
-            set_error("workspace too small or misaligned: need %zu bytes", need);
-            return RFVR_E_WORKSPACE;
-        }
-    }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
+    const bool keep = reserve_bytes_ != 0 || reserve != nullptr;
+    if ((rc = check_buffers(ws, ws_bytes, fwd_bytes(l, n, keep), reserve, reserve_bytes_,
+                            keep ? reserve_bytes(l, n) : 0)))
+        return rc;
+    const Cx cx{st, mm_of(net->precision)};
     const float* P = net->params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
-    const long chunk = n < kChunk ? (long)n : kChunk;
+    const long chunk = n < kChunk ? n : kChunk;
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     const Weights w = take_weights(cur, l);
     float* X0 = cur.take<float>((size_t)chunk * l.in0p);
-    float* Z[16];
-    for (int i = 0; i < l.L; ++i) Z[i] = cur.take<float>((size_t)chunk * l.W);
+    float* Zw[16];
+    for (int i = 0; i < l.L && !keep; ++i) Zw[i] = cur.take<float>((size_t)chunk * l.W);
     float* G[2] = {cur.take<float>((size_t)chunk * l.W), cur.take<float>((size_t)chunk * l.W)};
     float* Yh[4];
     for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
@@ -1132,15 +1125,20 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
         const float* x = xyz + 3 * c0;
         hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0, nullptr, nullptr);
-        // Z_i = H_{i-1} W_i^T + b_i and H_i = sp(Z_i) from the epilogue; the
-        // activations live in the two sweep buffers until the sweep starts
-        float* H[2] = {G[0], G[1]};
+        // Z_i = H_{i-1} W_i^T + b_i and H_i = sp(Z_i) from the epilogue; without
+        // a reserve the activations live in the two sweep buffers until the
+        // sweep starts
+        float *Z[16], *H[16];
+        for (int i = 0; i < l.L; ++i) {
+            Z[i] = keep ? reserve_z(reserve, l, n, i) + c0 * l.W : Zw[i];
+            H[i] = keep ? reserve_h(reserve, l, n, i) + c0 * l.W : G[i & 1];
+        }
         gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
                                        nullptr, 0, H[0]), cx);
         for (int i = 1; i < l.L; ++i)
-            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[(i - 1) & 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W,
-                                         beta, nullptr, 0, H[i & 1]), cx);
-        float* Ht = H[(l.L - 1) & 1];
+            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W,
+                                         beta, nullptr, 0, H[i]), cx);
+        float* Ht = H[l.L - 1];
         float* Zt = Z[l.L - 1];
         if (sdf)
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
@@ -1178,36 +1176,31 @@ int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sd
     return RFVR_OK;
 }
 
-int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
-                      const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
-                      void* ws, size_t ws_bytes, void* stream) {
+int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_sdf, const float* g_grad,
+                 const float* g_refl, uint32_t flags, float* g_params, void* reserve, size_t reserve_bytes_,
+                 void* ws, size_t ws_bytes, hipStream_t st) {
     int rc;
     if ((rc = check_net(net))) return rc;
     if (n < 1 || !xyz || !net->params || !g_params) { set_error("n >= 1, xyz, params and g_params are required"); return RFVR_E_INVALID; }
     if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }
     const Layout l = layout(net);
-    {
-        const size_t need = bwd_bytes(l, (long)n);
-        if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
-            set_error("workspace too small or misaligned: need %zu bytes", need);
-            return RFVR_E_WORKSPACE;
-        }
-    }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool keep = reserve_bytes_ != 0 || reserve != nullptr;
+    if ((rc = check_buffers(ws, ws_bytes, bwd_bytes(l, n, keep), reserve, reserve_bytes_,
+                            keep ? reserve_bytes(l, n) : 0)))
+        return rc;
     const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
     const float* P = net->params;
     float* GP = g_params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
-    const long chunk = n < kChunk ? (long)n : kChunk;
+    const long chunk = n < kChunk ? n : kChunk;
     const long wmax = l.W > l.in0p ? l.W : l.in0p;
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     const Weights w = take_weights(cur, l);
     float* X0 = cur.take<float>((size_t)chunk * l.in0p);
     float* X0d = cur.take<float>((size_t)chunk * l.in0p);
-    float *Z[16], *Zd[16], *H[16], *Hd[16];
-    for (int i = 0; i < l.L; ++i) Z[i] = cur.take<float>((size_t)chunk * l.W);
-    for (int i = 0; i < l.L; ++i) Zd[i] = cur.take<float>((size_t)chunk * l.W);
-    for (int i = 0; i < l.L; ++i) H[i] = cur.take<float>((size_t)chunk * l.W);
+    float *Zw[16], *Hw[16], *Hd[16];
+    for (int i = 0; i < l.L && !keep; ++i) Zw[i] = cur.take<float>((size_t)chunk * l.W);
+    for (int i = 0; i < l.L && !keep; ++i) Hw[i] = cur.take<float>((size_t)chunk * l.W);
     for (int i = 0; i < l.L; ++i) Hd[i] = cur.take<float>((size_t)chunk * l.W);
     float* Hb = cur.take<float>((size_t)chunk * l.W);
     float* Hdb = cur.take<float>((size_t)chunk * l.W);
@@ -1216,7 +1209,6 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
     float *Yh[4], *Ybh[4];
     for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
     for (int h = 0; h < l.HL; ++h) Ybh[h] = cur.take<float>((size_t)chunk * l.HW);
-    float* Rtmp = cur.take<float>((size_t)chunk * l.HW);
     float* yb3 = cur.take<float>((size_t)chunk);
     float* part = cur.take<float>((size_t)2 * kWgSplits * l.W * wmax);
     float* bpart = cur.take<float>((size_t)kWgSplits * l.W);
@@ -1229,17 +1221,30 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         const float* x = xyz + 3 * c0;
         const float* gf = g_sdf ? g_sdf + c0 : nullptr;
         const float* ga_ = g_refl ? g_refl + c0 : nullptr;
-        // primal and tangent forward
+        float *Z[16], *H[16];
+        for (int i = 0; i < l.L; ++i) {
+            Z[i] = keep ? reserve_z(reserve, l, n, i) + c0 * l.W : Zw[i];
+            H[i] = keep ? reserve_h(reserve, l, n, i) + c0 * l.W : Hw[i];
+        }
+        // encoding and its tangent along g_grad
         hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
-        // (Z_i, H_i = sp(Z_i)) and (Zdot_i, Hdot_i = sp'(Z_i) Zdot_i), activations from the epilogues
-        // one dual GEMM per layer: (Z_i, H_i) and (Zdot_i, Hdot_i) share W_i
-        gemm_dual<EPI2_FWD>(da(X0, X0d, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], nullptr, nullptr, Z[0], H[0], Zd[0],
-                               Hd[0], l.W, m, l.W, l.in0p, beta), MM_FP32, st);
-        for (int i = 1; i < l.L; ++i)
-            gemm_dual<EPI2_FWD>(da(H[i - 1], Hd[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], nullptr, nullptr, Z[i], H[i],
-                                   Zd[i], Hd[i], l.W, m, l.W, l.W, beta), cx.mm, st);
+        if (keep) {
+            // tangent only: Hdot_i = sp'(Z_i) (Hdot_{i-1} W_i^T) with Z_i from the reserve
+            gemm32<PRO_ID, EPI_DSPMUL>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Hd[0], l.W, m, l.W, l.in0p,
+                                          beta, Z[0], l.W), cx);
+            for (int i = 1; i < l.L; ++i)
+                gemm<PRO_ID, EPI_DSPMUL>(ga(Hd[i - 1], nullptr, l.W, w.Wp[i], l.W, nullptr, Hd[i], l.W, m, l.W, l.W,
+                                            beta, Z[i], l.W), cx);
+        } else {
+            // one dual GEMM per layer: (Z_i, H_i) and Hdot_i share W_i
+            gemm_dual<EPI2_FWD>(da(X0, X0d, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], nullptr, nullptr, Z[0], H[0], Hd[0],
+                                   l.W, m, l.W, l.in0p, beta), MM_FP32, st);
+            for (int i = 1; i < l.L; ++i)
+                gemm_dual<EPI2_FWD>(da(H[i - 1], Hd[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], nullptr, nullptr, Z[i],
+                                       H[i], Hd[i], l.W, m, l.W, l.W, beta), cx.mm, st);
+        }
         float* Ht = H[l.L - 1];
         float* Hdt = Hd[l.L - 1];
         // head forward
@@ -1279,7 +1284,7 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         // trunk layers, top down: the top layer's (Zbar, Zdotbar) elementwise,
         // the others from the dual adjoint GEMM of the layer above
         hipLaunchKernelGGL(k_layer_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, (long)l.W,
-                           Z[l.L - 1], Zd[l.L - 1], Hb, Hdb, beta, Zb, Zdb);
+                           Z[l.L - 1], Hd[l.L - 1], Hb, Hdb, beta, Zb, Zdb);
         float *Zb_c = Zb, *Zdb_c = Zdb, *Zb_n = Hb, *Zdb_n = Hdb;
         for (int i = l.L - 1; i >= 0; --i) {
             float* Zb = Zb_c;
@@ -1298,8 +1303,8 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
             hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
                                GP + l.ob[i], acc);
             if (i > 0) {
-                gemm_dual<EPI2_ADJ>(da(Zb, Zdb, l.W, w.WT[i], l.W, nullptr, Z[i - 1], Zd[i - 1], Zb_n, Zdb_n, nullptr,
-                                       nullptr, l.W, m, l.W, l.W, beta), cx.mm, st);
+                gemm_dual<EPI2_ADJ>(da(Zb, Zdb, l.W, w.WT[i], l.W, nullptr, Z[i - 1], Hd[i - 1], Zb_n, Zdb_n, nullptr,
+                                       l.W, m, l.W, l.W, beta), cx.mm, st);
                 float* t = Zb_c; Zb_c = Zb_n; Zb_n = t;
                 t = Zdb_c; Zdb_c = Zdb_n; Zdb_n = t;
             }
@@ -1307,6 +1312,73 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
         if ((rc = hip_status(hipGetLastError(), "mlp backward"))) return rc;
     }
     return RFVR_OK;
+}
+
+}  // namespace
+}  // namespace rfvr
+
+using namespace rfvr;
+
+extern "C" {
+
+int64_t rfvr_mlp_param_count(const rfvr_mlp* net) {
+    if (check_net(net)) return -1;
+    return layout(net).total;
+}
+
+size_t rfvr_mlp_forward_ws_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return fwd_bytes(layout(net), (long)n, false);
+}
+
+size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return bwd_bytes(layout(net), (long)n, false);
+}
+
+int rfvr_mlp_forward(const rfvr_mlp* net, const float* xyz, int64_t n, float* sdf, float* grad,
+                     float* refl, void* ws, size_t ws_bytes, void* stream) {
+    return mlp_forward(net, xyz, (long)n, sdf, grad, refl, nullptr, 0, ws, ws_bytes,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
+                      const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
+                      void* ws, size_t ws_bytes, void* stream) {
+    return mlp_backward(net, xyz, (long)n, g_sdf, g_grad, g_refl, flags, g_params, nullptr, 0, ws, ws_bytes,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t rfvr_mlp_reserve_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return reserve_bytes(layout(net), (long)n);
+}
+
+size_t rfvr_mlp_forward_train_ws_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return fwd_bytes(layout(net), (long)n, true);
+}
+
+size_t rfvr_mlp_backward_train_ws_bytes(const rfvr_mlp* net, int64_t n) {
+    if (check_net(net) || n < 1) return 0;
+    return bwd_bytes(layout(net), (long)n, true);
+}
+
+int rfvr_mlp_forward_train(const rfvr_mlp* net, const float* xyz, int64_t n, float* sdf, float* grad,
+                           float* refl, void* reserve, size_t reserve_bytes_, void* ws, size_t ws_bytes,
+                           void* stream) {
+    if (!reserve || !reserve_bytes_) { set_error("the training forward needs a reserve"); return RFVR_E_INVALID; }
+    return mlp_forward(net, xyz, (long)n, sdf, grad, refl, reserve, reserve_bytes_, ws, ws_bytes,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+int rfvr_mlp_backward_train(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
+                            const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
+                            const void* reserve, size_t reserve_bytes_, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!reserve || !reserve_bytes_) { set_error("the training backward needs a reserve"); return RFVR_E_INVALID; }
+    return mlp_backward(net, xyz, (long)n, g_sdf, g_grad, g_refl, flags, g_params, const_cast<void*>(reserve),
+                        reserve_bytes_, ws, ws_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

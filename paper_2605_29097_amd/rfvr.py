@@ -88,6 +88,12 @@ _SIGS = {
     "rfvr_mlp_backward_ws_bytes": ([_P(CMlp), _c_i64], _sz),
     "rfvr_mlp_backward": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
                           _c_i32),
+    "rfvr_mlp_reserve_bytes": ([_P(CMlp), _c_i64], _sz),
+    "rfvr_mlp_forward_train_ws_bytes": ([_P(CMlp), _c_i64], _sz),
+    "rfvr_mlp_forward_train": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _vp, _sz, _vp, _sz, _vp], _c_i32),
+    "rfvr_mlp_backward_train_ws_bytes": ([_P(CMlp), _c_i64], _sz),
+    "rfvr_mlp_backward_train": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp, _sz,
+                                 _vp], _c_i32),
     "rfvr_occupancy": ([_c_i64, _c_f, _vp, _vp, _vp], _c_i32),
     "rfvr_proposal_param_count": ([_P(CProposal)], _c_i64),
     "rfvr_proposal_ws_bytes": ([_P(CProposal), _c_i64], _sz),
@@ -348,30 +354,51 @@ class MLP:
         return int(lib().rfvr_mlp_param_count(ctypes.byref(self.c())))
 
 
-def mlp_forward(net: MLP, xyz: torch.Tensor, stream=None):
-    """(f [N], grad [N, 3], a [N])."""
+def mlp_reserve(net: MLP, n: int, device) -> torch.Tensor:
+    """Reserve of the training pair for n points (every trunk layer's Z and H)."""
+    return _ws(lib().rfvr_mlp_reserve_bytes(ctypes.byref(net.c()), int(n)), device)
+
+
+def mlp_forward(net: MLP, xyz: torch.Tensor, stream=None, reserve: Optional[torch.Tensor] = None):
+    """(f [N], grad [N, 3], a [N]); with ``reserve`` (from mlp_reserve) the
+    training forward, which also fills the reserve for mlp_backward."""
     dev = xyz.device
     n = xyz.numel() // 3
     cn = net.c()
     f = torch.empty(n, dtype=torch.float32, device=dev)
     g = torch.empty(n, 3, dtype=torch.float32, device=dev)
     a = torch.empty(n, dtype=torch.float32, device=dev)
-    ws = _ws(lib().rfvr_mlp_forward_ws_bytes(ctypes.byref(cn), n), dev)
-    _check(lib().rfvr_mlp_forward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(f), _ptr(g), _ptr(a),
-                                  _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mlp_forward")
+    if reserve is None:
+        ws = _ws(lib().rfvr_mlp_forward_ws_bytes(ctypes.byref(cn), n), dev)
+        _check(lib().rfvr_mlp_forward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(f), _ptr(g), _ptr(a),
+                                      _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mlp_forward")
+    else:
+        ws = _ws(lib().rfvr_mlp_forward_train_ws_bytes(ctypes.byref(cn), n), dev)
+        _check(lib().rfvr_mlp_forward_train(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(f), _ptr(g),
+                                            _ptr(a), _ptr(reserve), reserve.numel(), _ptr(ws), ws.numel(),
+                                            _stream(stream)), "rfvr_mlp_forward_train")
     return f, g, a
 
 
 def mlp_backward(net: MLP, xyz: torch.Tensor, g_sdf=None, g_grad=None, g_refl=None, flags=0,
-                 out=None, stream=None):
+                 out=None, stream=None, reserve: Optional[torch.Tensor] = None):
+    """Parameter gradient; with ``reserve`` the training backward, which reads
+    the activations the training forward left there (same net, xyz)."""
     dev = xyz.device
     n = xyz.numel() // 3
     cn = net.c()
     gp = out if out is not None else torch.empty(net.param_count(), dtype=torch.float32, device=dev)
-    ws = _ws(lib().rfvr_mlp_backward_ws_bytes(ctypes.byref(cn), n), dev)
-    _check(lib().rfvr_mlp_backward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(g_sdf), _ptr(g_grad),
-                                   _ptr(g_refl), flags, _ptr(gp), _ptr(ws), ws.numel(),
-                                   _stream(stream)), "rfvr_mlp_backward")
+    if reserve is None:
+        ws = _ws(lib().rfvr_mlp_backward_ws_bytes(ctypes.byref(cn), n), dev)
+        _check(lib().rfvr_mlp_backward(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(g_sdf), _ptr(g_grad),
+                                       _ptr(g_refl), flags, _ptr(gp), _ptr(ws), ws.numel(),
+                                       _stream(stream)), "rfvr_mlp_backward")
+    else:
+        ws = _ws(lib().rfvr_mlp_backward_train_ws_bytes(ctypes.byref(cn), n), dev)
+        _check(lib().rfvr_mlp_backward_train(ctypes.byref(cn), _ptr(xyz.contiguous()), n, _ptr(g_sdf),
+                                             _ptr(g_grad), _ptr(g_refl), flags, _ptr(gp), _ptr(reserve),
+                                             reserve.numel(), _ptr(ws), ws.numel(), _stream(stream)),
+               "rfvr_mlp_backward_train")
     return gp
 
 
@@ -507,6 +534,18 @@ rfvr_loss_l2 = loss_l2
 rfvr_sample_points = sample_points
 rfvr_mlp_forward = mlp_forward
 rfvr_mlp_backward = mlp_backward
+rfvr_mlp_reserve_bytes = mlp_reserve
+
+
+def rfvr_mlp_forward_train(net: MLP, xyz: torch.Tensor, reserve: torch.Tensor, stream=None):
+    return mlp_forward(net, xyz, stream=stream, reserve=reserve)
+
+
+def rfvr_mlp_backward_train(net: MLP, xyz: torch.Tensor, g_sdf, g_grad, g_refl, reserve: torch.Tensor,
+                            flags=0, out=None, stream=None):
+    return mlp_backward(net, xyz, g_sdf, g_grad, g_refl, flags=flags, out=out, stream=stream, reserve=reserve)
+
+
 rfvr_adamw = adamw
 rfvr_occupancy = occupancy
 rfvr_proposal_forward = proposal_forward

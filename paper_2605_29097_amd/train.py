@@ -3,13 +3,13 @@ driven through the C ABI with explicit forward / adjoint calls.
 
 step():
   1. lensless primary-ray samples (Sec. Lensless Sampling)          rfvr_sample_points
-  2. SDF network at the samples: f, grad_x f, a                      rfvr_mlp_forward
+  2. SDF network at the samples: f, grad_x f, a                      rfvr_mlp_forward_train
      and at the ray / antenna origins: detached Phi (Eq. lens-less-transmittance)
   3. signal tracing with lensless alpha blending (Eq. ref_sim)       rfvr_render_forward
   4. matched filter at the samples (Eq. mf-sm)                      rfvr_mf_forward
   5. L2 loss against the measured signal's filter output             rfvr_loss_l2
   then the adjoints in reverse (rfvr_mf_backward, rfvr_render_backward,
-  rfvr_mlp_backward) and AdamW with cosine annealing (App. C)        rfvr_adamw
+  rfvr_mlp_backward_train) and AdamW with cosine annealing (App. C)        rfvr_adamw
 No host synchronisation happens inside a step.
 """
 from __future__ import annotations
@@ -51,6 +51,8 @@ class StepConfig:
     spec_flags: int = R.SPEC_CLAMP
     bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
     learn_s: bool = False                  # train log s with the head's learning rate
+    keep_activations: bool = True          # network training pair: the backward reads the
+                                           # forward's layer activations from a reserve
     mask_tau: Optional[tuple] = None       # (tau_hi, tau_lo): dynamic loss masking on
 
     @property
@@ -118,6 +120,7 @@ class Trainer:
         self.m = torch.zeros(n_par, device=self.dev)
         self.v = torch.zeros(n_par, device=self.dev)
         self.g = torch.zeros(n_par, device=self.dev)
+        self._res = None
         # the SDF branch (trunk + sdf output) comes first in the flat layout
         w, L, in0 = cfg.width, cfg.n_layers, 3 + 6 * cfg.pe_octaves
         self.n_sdf = w * in0 + w + (L - 1) * (w * w + w) + w + 1
@@ -162,7 +165,8 @@ class Trainer:
         xyz, u, origin = self.samples()
         n = xyz.shape[0] * xyz.shape[1]
         mark("sample")
-        f, grad, a = R.mlp_forward(self.net, xyz)
+        res = self.reserve(n)
+        f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
         # detached occupancies at the primary-ray origins and the antennas
         org = torch.cat([origin, self.tx], 0)
         f_org, _, _ = R.mlp_forward(self.net, org)
@@ -211,7 +215,7 @@ class Trainer:
         gr = R.render_backward(ap_r, sm, fl_r, g_sig, flags=c.spec_flags)
         mark("render_bwd")
         R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
-                       out=self.g)
+                       out=self.g, reserve=res)
         mark("mlp_bwd")
         self.t += 1
         P, G, M, V = self.net.params, self.g, self.m, self.v
@@ -224,6 +228,14 @@ class Trainer:
             self.update_s(gr["s"])
         self.last = dict(signal=sig, loss=loss)
         return loss
+
+    def reserve(self, n: int):
+        """Reserve of the network's training pair for n points (None when off)."""
+        if not self.cfg.keep_activations:
+            return None
+        if self._res is None or self._res_n != n:
+            self._res, self._res_n = R.mlp_reserve(self.net, n, self.dev), n
+        return self._res
 
     def update_s(self, g_s: torch.Tensor):
         """Adam step on log s (host scalar: the kernels take s by value; this
@@ -305,7 +317,8 @@ class MultiPlaneTrainer(Trainer):
             pl = self.planes[k]
             xyz, u, origin = self.plane_samples(k)
             n_ray = origin.shape[0]
-            f, grad, a = R.mlp_forward(self.net, xyz)
+            res = self.reserve(xyz.shape[0] * xyz.shape[1])
+            f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
             f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, pl["tx"]], 0))
             phi = R.occupancy(self.s, f_org)
             sm = R.Samples(xyz=xyz)
@@ -324,7 +337,7 @@ class MultiPlaneTrainer(Trainer):
             g_sig = R.mf_backward(pl["ap"], xyz, z, p, g_p)
             gr = R.render_backward(pl["ap"], sm, fl, g_sig, flags=c.spec_flags)
             R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
-                           flags=R.ACCUMULATE if j > 0 else 0, out=self.g)
+                           flags=R.ACCUMULATE if j > 0 else 0, out=self.g, reserve=res)
             if j == 0:
                 self.g_amp.copy_(gr["amp"])
                 self.loss_sum.copy_(loss)
@@ -421,7 +434,8 @@ class ProposalTrainer(Trainer):
         xyz, u, origin = self.proposal_samples(logits)
         n_ray, K = u.shape
         mark("propose")
-        f, grad, a = R.mlp_forward(self.net, xyz)
+        res = self.reserve(n_ray * K) if self.train_sdf else None
+        f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
         f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
         phi = R.occupancy(self.s, f_org)
         mark("mlp_fwd")
@@ -442,7 +456,7 @@ class ProposalTrainer(Trainer):
             gr = R.render_backward(self.ap, sm, fl, g_sig, flags=c.spec_flags)
             mark("render_bwd")
             R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
-                           out=self.g)
+                           out=self.g, reserve=res)
             mark("mlp_bwd")
             P, G, M, V = self.net.params, self.g, self.m, self.v
             ns = self.n_sdf

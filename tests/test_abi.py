@@ -152,3 +152,28 @@ def test_mlp_param_count_matches_layout(R):
     spec2 = MLPSpec(n_layers=3, width=64, pe_octaves=4, head_width=64, head_layers=1)
     net2 = R.MLP(params=None, n_layers=3, width=64, pe_octaves=4, head_width=64, head_layers=1)
     assert net2.param_count() == mlp_layout(spec2)["__total__"][0]
+
+
+def test_mlp_training_pair_checks_reserve_before_launch(R):
+    L = R.lib()
+    spec = dict(n_layers=8, width=256, pe_octaves=6, head_width=64, head_layers=2)
+    net = R.MLP(params=None, **spec).c()
+    net.params = ctypes.c_void_p(0x1000)
+    n = 1000
+    rb = L.rfvr_mlp_reserve_bytes(ctypes.byref(net), n)
+    assert rb >= 2 * 8 * n * 256 * 4
+    assert 0 < L.rfvr_mlp_forward_train_ws_bytes(ctypes.byref(net), n) < L.rfvr_mlp_forward_ws_bytes(ctypes.byref(net), n)
+    assert 0 < L.rfvr_mlp_backward_train_ws_bytes(ctypes.byref(net), n) < L.rfvr_mlp_backward_ws_bytes(ctypes.byref(net), n)
+    v, ws, big = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000), 1 << 40
+
+    def fwd(res, nb):
+        return L.rfvr_mlp_forward_train(ctypes.byref(net), v, n, v, v, v, res, nb, ws, big, None)
+
+    def bwd(res, nb):
+        return L.rfvr_mlp_backward_train(ctypes.byref(net), v, n, v, v, v, 0, v, res, nb, ws, big, None)
+
+    for call in (fwd, bwd):
+        assert call(None, 0) == -1
+        assert call(ctypes.c_void_p(0x200000), rb - 1) == -2
+        assert call(ctypes.c_void_p(0x200001), rb) == -2            # misaligned
+        assert b"reserve" in L.rfvr_last_error()

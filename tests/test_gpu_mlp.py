@@ -124,3 +124,64 @@ def test_mlp_chunked_large_batch_sampled(dev):
     assert rel_rms(f.cpu().numpy()[idx], fr) <= 1e-4
     assert rel_rms(g.cpu().numpy()[idx], gr) <= 1e-4
     assert rel_rms(a.cpu().numpy()[idx], ar) <= 1e-4
+
+
+@pytest.mark.parametrize("name,spec,n", CASES, ids=[c[0] for c in CASES])
+def test_mlp_training_pair(dev, name, spec, n):
+    """Training forward = plain forward bit for bit; training backward (layer
+    activations read from the reserve) against the oracle and the plain call."""
+    _say(f"mlp training pair {name} n={n}")
+    R = _R()
+    p = _params(spec, 5)
+    x = _pts(n, spec, 6)
+    rng = np.random.default_rng(7)
+    gf = rng.normal(size=n).astype(np.float32)
+    gg = rng.normal(size=(n, 3)).astype(np.float32)
+    gaa = rng.normal(size=n).astype(np.float32)
+    net = _net(R, spec, p, dev)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    res = R.mlp_reserve(net, n, dev)
+    assert res.numel() >= 2 * spec.n_layers * n * spec.width * 4
+    f, g, a = R.mlp_forward(net, t(x), reserve=res)
+    f0, g0, a0 = R.mlp_forward(net, t(x))
+    assert torch.equal(f, f0) and torch.equal(g, g0) and torch.equal(a, a0)
+    gp = R.mlp_backward(net, t(x), t(gf), t(gg), t(gaa), reserve=res).cpu().numpy()
+    gp0 = R.mlp_backward(net, t(x), t(gf), t(gg), t(gaa)).cpu().numpy()
+    ref = omlp.backward(p.astype(np.float64), spec, x.astype(np.float64), gf, gg, gaa)
+    e, e0 = rel_rms(gp, ref), rel_rms(gp, gp0)
+    print(f"training backward vs oracle {e:.2e}, vs plain backward {e0:.2e}")
+    assert e <= 1e-4
+    assert e0 <= 1e-5
+
+
+def test_mlp_backward_chunked_sparse_upstream(dev):
+    """More points than one internal pass (2^18) with upstream gradients on a
+    few rows only (around the pass boundary and at the tail): the parameter
+    gradient then equals the oracle's over those rows alone.  Both the plain
+    and the training backward (reserve offsets per pass)."""
+    _say("mlp_backward chunked, sparse upstream")
+    R = _R()
+    spec = MLPSpec()
+    p = _params(spec, 13)
+    n = (1 << 18) + 777
+    x = _pts(n, spec, 14)
+    idx = np.r_[0:3, (1 << 18) - 3:(1 << 18) + 3, n - 3:n]
+    rng = np.random.default_rng(15)
+    gf = np.zeros(n, np.float32)
+    gg = np.zeros((n, 3), np.float32)
+    gaa = np.zeros(n, np.float32)
+    gf[idx] = rng.normal(size=idx.size)
+    gg[idx] = rng.normal(size=(idx.size, 3))
+    gaa[idx] = rng.normal(size=idx.size)
+    net = _net(R, spec, p, dev)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    ref = omlp.backward(p.astype(np.float64), spec, x[idx].astype(np.float64), gf[idx].astype(np.float64),
+                        gg[idx].astype(np.float64), gaa[idx].astype(np.float64))
+    gp0 = R.mlp_backward(net, t(x), t(gf), t(gg), t(gaa)).cpu().numpy()
+    res = R.mlp_reserve(net, n, dev)
+    R.mlp_forward(net, t(x), reserve=res)
+    gp = R.mlp_backward(net, t(x), t(gf), t(gg), t(gaa), reserve=res).cpu().numpy()
+    del res
+    e0, e = rel_rms(gp0, ref), rel_rms(gp, ref)
+    print(f"plain {e0:.2e}, training pair {e:.2e}")
+    assert e0 <= 1e-4 and e <= 1e-4
