@@ -838,7 +838,7 @@ __global__ void k_pad_cols(const float* __restrict__ in, int R, int C, int Cpad,
 // ============================================================================
 namespace {
 
-constexpr long kChunk = 1 << 18;          // points per pass (bounds the workspace)
+constexpr long kChunk = 1 << 20;          // points per pass (bounds the workspace)
 constexpr int kWgSplits = 128;            // weight-gradient point splits per pass
 constexpr int kColBlocks = 2048;          // column-sum partial blocks
 

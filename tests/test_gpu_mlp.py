@@ -12,6 +12,8 @@ from gpu_common import rel_rms
 
 pytestmark = pytest.mark.gpu
 
+PASS = 1 << 20          # points per internal pass of the network calls
+
 
 def _R():
     from paper_2605_29097_amd import rfvr as R
@@ -110,16 +112,16 @@ def test_mlp_backward_partial_inputs_and_accumulate(dev):
 
 
 def test_mlp_chunked_large_batch_sampled(dev):
-    """More points than one internal pass (2^18): spot-check rows against the oracle."""
+    """More points than one internal pass (2^20): spot-check rows against the oracle."""
     _say("mlp_forward chunked")
     R = _R()
     spec = MLPSpec()
     p = _params(spec, 11)
-    n = (1 << 18) + 777
+    n = PASS + 777
     x = _pts(n, spec, 12)
     net = _net(R, spec, p, dev)
     f, g, a = R.mlp_forward(net, torch.from_numpy(x).to(dev))
-    idx = np.r_[0:5, (1 << 18) - 3:(1 << 18) + 3, n - 5:n]
+    idx = np.r_[0:5, PASS - 3:PASS + 3, n - 5:n]
     fr, gr, ar = omlp.forward(p.astype(np.float64), spec, x[idx].astype(np.float64))
     assert rel_rms(f.cpu().numpy()[idx], fr) <= 1e-4
     assert rel_rms(g.cpu().numpy()[idx], gr) <= 1e-4
@@ -155,7 +157,7 @@ def test_mlp_training_pair(dev, name, spec, n):
 
 
 def test_mlp_backward_chunked_sparse_upstream(dev):
-    """More points than one internal pass (2^18) with upstream gradients on a
+    """More points than one internal pass (2^20) with upstream gradients on a
     few rows only (around the pass boundary and at the tail): the parameter
     gradient then equals the oracle's over those rows alone.  Both the plain
     and the training backward (reserve offsets per pass)."""
@@ -163,9 +165,9 @@ def test_mlp_backward_chunked_sparse_upstream(dev):
     R = _R()
     spec = MLPSpec()
     p = _params(spec, 13)
-    n = (1 << 18) + 777
+    n = PASS + 777
     x = _pts(n, spec, 14)
-    idx = np.r_[0:3, (1 << 18) - 3:(1 << 18) + 3, n - 3:n]
+    idx = np.r_[0:3, PASS - 3:PASS + 3, n - 3:n]
     rng = np.random.default_rng(15)
     gf = np.zeros(n, np.float32)
     gg = np.zeros((n, 3), np.float32)
