@@ -51,6 +51,22 @@ extern "C" {
 #define RFVR_PHASE_FP64RR   0x0u  /* path length and phase reduction in FP64 (default) */
 #define RFVR_PHASE_NAIVE32  0x4u  /* radians 2 pi f d / c formed in FP32 (precision study) */
 #define RFVR_ACCUMULATE     0x8u  /* gradient outputs add into existing contents   */
+#define RFVR_TERMS_DIRECT   0x10u /* per-frequency evaluation of the term sums (see below) */
+
+/* Evaluation of the term sums (Eq. ref_sim, Eq. mf-sm and their adjoints).
+ * By default the four term entry points (render forward / backward, matched
+ * filter forward / backward) evaluate the sums through Chebyshev moments of
+ * each measurement's range interval over the launch's bounding box: the
+ * phasor exp(-+j 2 pi (f0 + n df) 2r/c) is expanded in Chebyshev polynomials
+ * of the normalised range (Jacobi-Anger expansion), cut at the smallest order
+ * K in {24, 32, 40, 48, 64} whose truncation bound 2 (z/2)^K / K! (z = 2 pi
+ * (n_freq - 1) df 2h/c, h the half-width of the widest interval) is below
+ * 1e-7 of the sum of the term magnitudes.  The choice is made on the device
+ * for every call; when no K qualifies (a range spread too wide for the band)
+ * or K is not below n_freq, the per-frequency kernels run, which
+ * RFVR_TERMS_DIRECT (and RFVR_PHASE_NAIVE32) also select.  Both evaluate the
+ * same sums; they differ by rounding. */
+
 
 /* Measurement geometry and FMCW sweep (Sec. "Radar Basics", Eq. fmcw; App. C). */
 typedef struct rfvr_aperture {
@@ -148,6 +164,14 @@ size_t rfvr_mf_backward_ws_bytes(const rfvr_aperture* ap, int64_t n_q);
 int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q,
                      const float* z, const float* power, const float* g_power,
                      uint32_t flags, float* g_signal, void* ws, size_t ws_bytes, void* stream);
+
+/* The order K that the term entry points choose for measurements ap and
+ * points xyz [n_pts][3] (device), written to *order (device int32; 0 = the
+ * per-frequency kernels), as described with RFVR_TERMS_DIRECT.  Asynchronous
+ * on stream like every other call; RFVR_E_WORKSPACE below the query. */
+size_t rfvr_term_order_ws_bytes(const rfvr_aperture* ap, int64_t n_pts);
+int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, int32_t* order,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * L2 heatmap loss (Sec. Overview, step 5):

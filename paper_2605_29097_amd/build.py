@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librfvr.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RFVR_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["api.hip", "render.hip", "mf.hip", "misc.hip", "mlp.hip"]
+SOURCES = ["api.hip", "render.hip", "mf.hip", "misc.hip", "mlp.hip", "cheb.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-variable",
          "-Wno-unused-but-set-variable"]

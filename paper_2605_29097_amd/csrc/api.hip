@@ -64,7 +64,7 @@ static int check_fields(const rfvr_fields* fl) {
 }
 
 static int check_flags(uint32_t flags) {
-    if ((flags & ~(RFVR_SPEC_MASK | RFVR_PHASE_NAIVE32 | RFVR_ACCUMULATE)) != 0 ||
+    if ((flags & ~(RFVR_SPEC_MASK | RFVR_PHASE_NAIVE32 | RFVR_ACCUMULATE | RFVR_TERMS_DIRECT)) != 0 ||
         (flags & RFVR_SPEC_MASK) == 3u) {
         set_error("unknown flag bits 0x%x", flags);
         return RFVR_E_INVALID;
@@ -104,11 +104,44 @@ static int check_ws(void* ws, size_t have, size_t need) {
     return RFVR_OK;
 }
 
+// The term sums go through the Chebyshev-moment kernels unless the caller asks
+// for the per-frequency kernels or the FP32-radian phase study; the plan
+// (decided on the device per launch) can still fall back to the latter.
+static bool use_cheb(uint32_t flags) { return (flags & (RFVR_PHASE_NAIVE32 | RFVR_TERMS_DIRECT)) == 0; }
+
+static size_t ws_cheb(long n_pts, int n_meas) {
+    return align256(sizeof(float) * 6 * cheb_bbox_blocks(n_pts)) + align256(sizeof(ChebPlan)) +
+           align256(sizeof(MeasCheb) * n_meas);
+}
+
+struct ChebWs {
+    float* bbox;
+    ChebPlan* plan;
+    MeasCheb* meas;
+};
+
+static ChebWs take_cheb(WsCursor& cur, long n_pts, int n_meas) {
+    ChebWs c;
+    c.bbox = cur.take<float>((size_t)6 * cheb_bbox_blocks(n_pts));
+    c.plan = cur.take<ChebPlan>(1);
+    c.meas = cur.take<MeasCheb>(n_meas);
+    return c;
+}
+
+// split partials of a reduction over points: per-frequency [ns][meas][freq]
+// or moments [ns][meas][kChebMaxOrder] (only one of the two runs)
+static size_t partial_count(long n_pts, int n_meas, int n_freq, int ns_direct) {
+    const size_t d = (size_t)ns_direct * n_meas * n_freq;
+    const size_t c = (size_t)cheb_point_splits(n_pts, n_meas) * n_meas * kChebMaxOrder;
+    return d > c ? d : c;
+}
+
 // ---------------------------------------------------------------- workspace layouts
 static size_t ws_render_forward(const RenderGeom& g) {
     const int ns = render_splits(g);
     return align256(sizeof(AntRec) * g.n_meas) + align256(sizeof(PtRec) * g.n_pts) +
-           align256(sizeof(float2) * (size_t)ns * g.n_meas * g.n_freq);
+           align256(sizeof(float2) * partial_count(g.n_pts, g.n_meas, g.n_freq, ns)) +
+           align256(sizeof(float2) * (size_t)g.n_meas * kChebMaxOrder) + ws_cheb(g.n_pts, g.n_meas);
 }
 
 static size_t ws_render_backward(const RenderGeom& g) {
@@ -118,13 +151,16 @@ static size_t ws_render_backward(const RenderGeom& g) {
            align256(sizeof(float) * 3 * g.n_pts) +               // g_n
            align256(sizeof(float) * g.n_pts) +                   // g_alpha
            align256(sizeof(float2) * g.n_meas * np) +            // padded g_signal
-           2 * align256(sizeof(float) * g.n_ray);                // per-ray partials
+           2 * align256(sizeof(float) * g.n_ray) +               // per-ray partials
+           align256(sizeof(float2) * (size_t)g.n_meas * kChebMaxOrder) + ws_cheb(g.n_pts, g.n_meas);
 }
 
-static size_t ws_mf_forward(const rfvr_aperture* ap, int two) {
+static size_t ws_mf_forward(const rfvr_aperture* ap, long n_q, int two) {
     const size_t np = padded_freq(ap->n_freq);
     return align256(sizeof(AntRec) * ap->n_meas) +
-           (two ? 2 : 1) * align256(sizeof(float2) * ap->n_meas * np);
+           (two ? 2 : 1) * (align256(sizeof(float2) * ap->n_meas * np) +
+                            align256(sizeof(float2) * (size_t)ap->n_meas * kChebMaxOrder)) +
+           ws_cheb(n_q, ap->n_meas);
 }
 
 static int mf_splits(const rfvr_aperture* ap, long n_q) {
@@ -135,7 +171,8 @@ static int mf_splits(const rfvr_aperture* ap, long n_q) {
 static size_t ws_mf_backward(const rfvr_aperture* ap, long n_q) {
     const int ns = mf_splits(ap, n_q);
     return align256(sizeof(AntRec) * ap->n_meas) + align256(sizeof(QRec) * n_q) +
-           align256(sizeof(float2) * (size_t)ns * ap->n_meas * ap->n_freq);
+           align256(sizeof(float2) * partial_count(n_q, ap->n_meas, ap->n_freq, ns)) +
+           align256(sizeof(float2) * (size_t)ap->n_meas * kChebMaxOrder) + ws_cheb(n_q, ap->n_meas);
 }
 
 static int loss_blocks(long n) {
@@ -173,7 +210,9 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
     AntRec* ant = cur.take<AntRec>(g.n_meas);
     PtRec* rec = cur.take<PtRec>(g.n_pts);
     const int ns = render_splits(g);
-    float2* partial = cur.take<float2>((size_t)ns * g.n_meas * g.n_freq);
+    float2* partial = cur.take<float2>(partial_count(g.n_pts, g.n_meas, g.n_freq, ns));
+    float2* M = cur.take<float2>((size_t)g.n_meas * kChebMaxOrder);
+    const ChebWs cw = take_cheb(cur, g.n_pts, g.n_meas);
     const int use_phi = (fl->phi_ray && fl->phi_tx) ? 1 : 0;
     if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
                          "ant records")))
@@ -183,11 +222,23 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
                                             alpha_out, trans_out, st),
                          "render prep")))
         return rc;
-    if ((rc = hip_status(launch_reduce_points_render(g, ant, rec, flags, ns, partial, st),
+    const ChebPlan* sel = nullptr;
+    if (use_cheb(flags)) {
+        if ((rc = hip_status(launch_cheb_plan(sm->xyz, g.n_pts, ant, g.n_meas, g.Kd, g.n_freq, cw.bbox, cw.meas,
+                                              cw.plan, st), "term plan")))
+            return rc;
+        sel = cw.plan;
+        if ((rc = hip_status(launch_cheb_points(g, 0, flags, ant, cw.meas, cw.plan, rec,
+                                                cheb_point_splits(g.n_pts, g.n_meas), partial, M,
+                                                reinterpret_cast<float2*>(signal), 0, st),
+                             "render moment kernels")))
+            return rc;
+    }
+    if ((rc = hip_status(launch_reduce_points_render(g, ant, rec, flags, ns, partial, sel, st),
                          "render term kernel")))
         return rc;
     return hip_status(launch_split_sum(partial, ns, (long)g.n_meas * g.n_freq, 0,
-                                       reinterpret_cast<float2*>(signal), st),
+                                       reinterpret_cast<float2*>(signal), sel, st),
                       "render split sum");
 }
 
@@ -223,6 +274,8 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
     float2* gpad = cur.take<float2>((size_t)g.n_meas * np);
     float* pamp = cur.take<float>(g.n_ray);
     float* ps = cur.take<float>(g.n_ray);
+    float2* B = cur.take<float2>((size_t)g.n_meas * kChebMaxOrder);
+    const ChebWs cw = take_cheb(cur, g.n_pts, g.n_meas);
     const int use_phi = (fl->phi_ray && fl->phi_tx) ? 1 : 0;
     if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
                          "ant records")))
@@ -236,7 +289,20 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                                            g.n_freq, np, gpad, st),
                          "pad g_signal")))
         return rc;
-    if ((rc = hip_status(launch_render_bwd_points(g, ant, rec, gpad, np, flags, gb, gT, gn, st),
+    const ChebPlan* sel = nullptr;
+    if (use_cheb(flags)) {
+        if ((rc = hip_status(launch_cheb_plan(sm->xyz, g.n_pts, ant, g.n_meas, g.Kd, g.n_freq, cw.bbox, cw.meas,
+                                              cw.plan, st), "term plan")))
+            return rc;
+        sel = cw.plan;
+        if ((rc = hip_status(launch_cheb_coef(g, cw.plan, cw.meas, reinterpret_cast<const float2*>(g_signal), B,
+                                              st), "render adjoint coefficients")))
+            return rc;
+        if ((rc = hip_status(launch_cheb_render_bwd(g, flags, cw.plan, ant, cw.meas, rec, B, gb, gT, gn, st),
+                             "render adjoint series kernels")))
+            return rc;
+    }
+    if ((rc = hip_status(launch_render_bwd_points(g, ant, rec, gpad, np, flags, gb, gT, gn, sel, st),
                          "render adjoint term kernel")))
         return rc;
     if ((rc = hip_status(launch_scan_adjoint(g, sm->ray_weight, fl->sdf, fl->grad, fl->refl, fl->s,
@@ -255,7 +321,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
 // ---------------------------------------------------------------- matched filter
 size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_signals) {
     if (check_aperture(ap, false) || n_q < 1) return 0;
-    return ws_mf_forward(ap, two_signals);
+    return ws_mf_forward(ap, (long)n_q, two_signals);
 }
 
 int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, uint32_t flags,
@@ -263,11 +329,14 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
                     float* power2, void* ws, size_t ws_bytes, void* stream) {
     int rc;
     if ((rc = check_aperture(ap, false))) return rc;
-    if (flags & ~(uint32_t)RFVR_PHASE_NAIVE32) { set_error("only RFVR_PHASE_NAIVE32 is meaningful here"); return RFVR_E_INVALID; }
+    if (flags & ~(uint32_t)(RFVR_PHASE_NAIVE32 | RFVR_TERMS_DIRECT)) {
+        set_error("only RFVR_PHASE_NAIVE32 and RFVR_TERMS_DIRECT are meaningful here");
+        return RFVR_E_INVALID;
+    }
     if (n_q < 1 || !xyz_q || !signal) { set_error("n_q >= 1, xyz_q and signal are required"); return RFVR_E_INVALID; }
     if (n_q > (int64_t)1 << 40) { set_error("n_q too large"); return RFVR_E_INVALID; }
     const int two = signal2 ? 1 : 0;
-    if ((rc = check_ws(ws, ws_bytes, ws_mf_forward(ap, two)))) return rc;
+    if ((rc = check_ws(ws, ws_bytes, ws_mf_forward(ap, (long)n_q, two)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const RenderGeom g = make_geom(ap, 1, 1);
     const int np = padded_freq(ap->n_freq);
@@ -275,6 +344,9 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
     AntRec* ant = cur.take<AntRec>(ap->n_meas);
     float2* sp = cur.take<float2>((size_t)ap->n_meas * np);
     float2* sp2 = two ? cur.take<float2>((size_t)ap->n_meas * np) : nullptr;
+    float2* B = cur.take<float2>((size_t)ap->n_meas * kChebMaxOrder);
+    float2* B2 = two ? cur.take<float2>((size_t)ap->n_meas * kChebMaxOrder) : nullptr;
+    const ChebWs cw = take_cheb(cur, (long)n_q, ap->n_meas);
     if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
     if ((rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(signal), ap->n_meas,
                                            ap->n_freq, np, sp, st), "pad signal")))
@@ -282,9 +354,26 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
     if (two && (rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(signal2),
                                                   ap->n_meas, ap->n_freq, np, sp2, st), "pad signal2")))
         return rc;
+    const ChebPlan* sel = nullptr;
+    if (use_cheb(flags)) {
+        if ((rc = hip_status(launch_cheb_plan(xyz_q, (long)n_q, ant, ap->n_meas, g.Kd, ap->n_freq, cw.bbox,
+                                              cw.meas, cw.plan, st), "term plan")))
+            return rc;
+        sel = cw.plan;
+        if ((rc = hip_status(launch_cheb_coef(g, cw.plan, cw.meas, reinterpret_cast<const float2*>(signal), B, st),
+                             "mf coefficients")))
+            return rc;
+        if (two && (rc = hip_status(launch_cheb_coef(g, cw.plan, cw.meas, reinterpret_cast<const float2*>(signal2),
+                                                     B2, st), "mf coefficients")))
+            return rc;
+        if ((rc = hip_status(launch_cheb_mf(g, cw.plan, (long)n_q, xyz_q, ant, cw.meas, B, B2,
+                                            reinterpret_cast<float2*>(z), power, reinterpret_cast<float2*>(z2),
+                                            power2, st), "mf series kernels")))
+            return rc;
+    }
     return hip_status(launch_mf_forward(g, ant, xyz_q, (long)n_q, sp, sp2, np, flags,
                                         reinterpret_cast<float2*>(z), power,
-                                        reinterpret_cast<float2*>(z2), power2, st),
+                                        reinterpret_cast<float2*>(z2), power2, sel, st),
                       "mf forward");
 }
 
@@ -310,18 +399,56 @@ int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, c
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     AntRec* ant = cur.take<AntRec>(ap->n_meas);
     QRec* rec = cur.take<QRec>((size_t)n_q);
-    float2* partial = cur.take<float2>((size_t)ns * ap->n_meas * ap->n_freq);
+    float2* partial = cur.take<float2>(partial_count((long)n_q, ap->n_meas, ap->n_freq, ns));
+    float2* M = cur.take<float2>((size_t)ap->n_meas * kChebMaxOrder);
+    const ChebWs cw = take_cheb(cur, (long)n_q, ap->n_meas);
+    const int acc = (flags & RFVR_ACCUMULATE) ? 1 : 0;
     if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
     if ((rc = hip_status(launch_mf_bwd_records(xyz_q, (long)n_q, reinterpret_cast<const float2*>(z),
                                                power, g_power, rec, st), "mf adjoint records")))
         return rc;
-    if ((rc = hip_status(launch_reduce_points_mf(g, ant, rec, flags, ns, partial, st),
+    const ChebPlan* sel = nullptr;
+    if (use_cheb(flags)) {
+        if ((rc = hip_status(launch_cheb_plan(xyz_q, (long)n_q, ant, ap->n_meas, g.Kd, ap->n_freq, cw.bbox,
+                                              cw.meas, cw.plan, st), "term plan")))
+            return rc;
+        sel = cw.plan;
+        if ((rc = hip_status(launch_cheb_points(g, 1, flags, ant, cw.meas, cw.plan, rec,
+                                                cheb_point_splits((long)n_q, ap->n_meas), partial, M,
+                                                reinterpret_cast<float2*>(g_signal), acc, st),
+                             "mf adjoint moment kernels")))
+            return rc;
+    }
+    if ((rc = hip_status(launch_reduce_points_mf(g, ant, rec, flags, ns, partial, sel, st),
                          "mf adjoint term kernel")))
         return rc;
-    return hip_status(launch_split_sum(partial, ns, (long)ap->n_meas * ap->n_freq,
-                                       (flags & RFVR_ACCUMULATE) ? 1 : 0,
-                                       reinterpret_cast<float2*>(g_signal), st),
+    return hip_status(launch_split_sum(partial, ns, (long)ap->n_meas * ap->n_freq, acc,
+                                       reinterpret_cast<float2*>(g_signal), sel, st),
                       "mf adjoint split sum");
+}
+
+// ---------------------------------------------------------------- term evaluation order
+size_t rfvr_term_order_ws_bytes(const rfvr_aperture* ap, int64_t n_pts) {
+    if (check_aperture(ap, false) || n_pts < 1) return 0;
+    return align256(sizeof(AntRec) * ap->n_meas) + ws_cheb((long)n_pts, ap->n_meas);
+}
+
+int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, int32_t* order, void* ws,
+                    size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_aperture(ap, false))) return rc;
+    if (n_pts < 1 || !xyz || !order) { set_error("n_pts >= 1, xyz and order are required"); return RFVR_E_INVALID; }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_term_order_ws_bytes(ap, n_pts)))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const RenderGeom g = make_geom(ap, 1, 1);
+    WsCursor cur{reinterpret_cast<char*>(ws), 0};
+    AntRec* ant = cur.take<AntRec>(ap->n_meas);
+    const ChebWs cw = take_cheb(cur, (long)n_pts, ap->n_meas);
+    if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
+    if ((rc = hip_status(launch_cheb_plan(xyz, (long)n_pts, ant, ap->n_meas, g.Kd, ap->n_freq, cw.bbox, cw.meas,
+                                          cw.plan, st), "term plan")))
+        return rc;
+    return hip_status(launch_cheb_order(cw.plan, order, st), "term order");
 }
 
 // ---------------------------------------------------------------- loss

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_mf_forward(
     long n_q, const float* __restrict__ xq, int n_meas, const AntRec* __restrict__ ant,
     const float2* __restrict__ sig, const float2* __restrict__ sig2, int np, double K0,
     double Kd, float2* __restrict__ z, float* __restrict__ power, float2* __restrict__ z2,
-    float* __restrict__ power2) {
+    float* __restrict__ power2, const ChebPlan* __restrict__ sel) {
+    if (sel && sel->K != 0) return;              // the Chebyshev path took this launch
     constexpr int PPL = kHornerPPL;
     const long q0 = (long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
     double px[PPL], py[PPL], pz[PPL];
@@ -126,27 +127,28 @@ __global__ __launch_bounds__(256) void k_mf_forward(
 
 hipError_t launch_mf_forward(const RenderGeom& g, const AntRec* ant, const float* xyz_q, long n_q,
                              const float2* sig_pad, const float2* sig2_pad, int np, uint32_t flags,
-                             float2* z, float* power, float2* z2, float* power2, hipStream_t st) {
+                             float2* z, float* power, float2* z2, float* power2, const ChebPlan* sel,
+                             hipStream_t st) {
     dim3 grid((unsigned)((n_q + 256L * kHornerPPL - 1) / (256L * kHornerPPL)));
     const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
     if (sig2_pad) {
         if (naive)
             hipLaunchKernelGGL((k_mf_forward<true, true>), grid, dim3(256), 0, st, n_q, xyz_q,
                                g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2);
+                               power2, sel);
         else
             hipLaunchKernelGGL((k_mf_forward<true, false>), grid, dim3(256), 0, st, n_q, xyz_q,
                                g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2);
+                               power2, sel);
     } else {
         if (naive)
             hipLaunchKernelGGL((k_mf_forward<false, true>), grid, dim3(256), 0, st, n_q, xyz_q,
                                g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2);
+                               power2, sel);
         else
             hipLaunchKernelGGL((k_mf_forward<false, false>), grid, dim3(256), 0, st, n_q, xyz_q,
                                g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2);
+                               power2, sel);
     }
     return hipGetLastError();
 }

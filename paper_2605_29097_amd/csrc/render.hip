@@ -37,23 +37,6 @@ int choose_point_splits(long n_pts, int lanes_total) {
     return (int)ns;
 }
 
-template <int SPEC>
-__device__ __forceinline__ void spec_factor(float nd, float& spec, float& live) {
-    if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
-        spec = 1.0f;
-        live = 0.0f;
-    } else {
-        float sr = __builtin_fmaf(2.0f * nd, nd, -1.0f);   // 2 (n.w_i)^2 - 1 = w_o . w_r
-        if constexpr (SPEC == (int)RFVR_SPEC_RAW) {
-            spec = sr;
-            live = 1.0f;
-        } else {
-            spec = fmaxf(sr, 0.0f);
-            live = sr >= 0.0f ? 1.0f : 0.0f;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // measurement records
 // ---------------------------------------------------------------------------
@@ -158,7 +141,8 @@ template <int F, int KIND, int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_reduce_points(
     int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
     const void* __restrict__ recs_v, long n_pts, long pts_per_split, int n_split, int gx,
-    float2* __restrict__ partial) {
+    float2* __restrict__ partial, const ChebPlan* __restrict__ sel) {
+    if (sel && sel->K != 0) return;              // the Chebyshev path took this launch
     constexpr int S = F < kSeed ? F : kSeed;     // re-seed interval
     constexpr int NS = F / S;
     // point records of the block's split are staged through LDS in tiles of
@@ -289,7 +273,7 @@ __global__ __launch_bounds__(256) void k_reduce_points(
 
 template <int F, int KIND, int SPEC, bool NAIVE>
 static hipError_t launch_rp(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
-                            float2* partial, hipStream_t st) {
+                            float2* partial, const ChebPlan* sel, hipStream_t st) {
     const int n_chunks = (g.n_freq + F - 1) / F;
     const long lanes = (long)g.n_meas * n_chunks;
     const int gx = (int)((lanes + 255) / 256);
@@ -297,47 +281,49 @@ static hipError_t launch_rp(const RenderGeom& g, const AntRec* ant, const void* 
     dim3 grid((unsigned)(groups * 8 * gx));
     const long per = (g.n_pts + n_split - 1) / n_split;
     hipLaunchKernelGGL((k_reduce_points<F, KIND, SPEC, NAIVE>), grid, dim3(256), 0, st, g.n_meas,
-                       g.n_freq, n_chunks, ant, g.K0, g.Kd, rec, g.n_pts, per, n_split, gx, partial);
+                       g.n_freq, n_chunks, ant, g.K0, g.Kd, rec, g.n_pts, per, n_split, gx, partial, sel);
     return hipGetLastError();
 }
 
 template <int KIND, int SPEC, bool NAIVE>
 static hipError_t launch_rp_f(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
-                              float2* partial, hipStream_t st) {
+                              float2* partial, const ChebPlan* sel, hipStream_t st) {
     switch (freq_chunk(g.n_freq)) {
-        case 16: return launch_rp<16, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, st);
-        case 32: return launch_rp<32, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, st);
-        default: return launch_rp<64, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, st);
+        case 16: return launch_rp<16, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, sel, st);
+        case 32: return launch_rp<32, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, sel, st);
+        default: return launch_rp<64, KIND, SPEC, NAIVE>(g, ant, rec, n_split, partial, sel, st);
     }
 }
 
 hipError_t launch_reduce_points_render(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
-                                       uint32_t flags, int n_split, float2* partial,
+                                       uint32_t flags, int n_split, float2* partial, const ChebPlan* sel,
                                        hipStream_t st) {
     const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
     switch (flags & RFVR_SPEC_MASK) {
         case RFVR_SPEC_RAW:
-            return naive ? launch_rp_f<0, RFVR_SPEC_RAW, true>(g, ant, rec, n_split, partial, st)
-                         : launch_rp_f<0, RFVR_SPEC_RAW, false>(g, ant, rec, n_split, partial, st);
+            return naive ? launch_rp_f<0, RFVR_SPEC_RAW, true>(g, ant, rec, n_split, partial, sel, st)
+                         : launch_rp_f<0, RFVR_SPEC_RAW, false>(g, ant, rec, n_split, partial, sel, st);
         case RFVR_SPEC_OFF:
-            return naive ? launch_rp_f<0, RFVR_SPEC_OFF, true>(g, ant, rec, n_split, partial, st)
-                         : launch_rp_f<0, RFVR_SPEC_OFF, false>(g, ant, rec, n_split, partial, st);
+            return naive ? launch_rp_f<0, RFVR_SPEC_OFF, true>(g, ant, rec, n_split, partial, sel, st)
+                         : launch_rp_f<0, RFVR_SPEC_OFF, false>(g, ant, rec, n_split, partial, sel, st);
         default:
-            return naive ? launch_rp_f<0, RFVR_SPEC_CLAMP, true>(g, ant, rec, n_split, partial, st)
-                         : launch_rp_f<0, RFVR_SPEC_CLAMP, false>(g, ant, rec, n_split, partial, st);
+            return naive ? launch_rp_f<0, RFVR_SPEC_CLAMP, true>(g, ant, rec, n_split, partial, sel, st)
+                         : launch_rp_f<0, RFVR_SPEC_CLAMP, false>(g, ant, rec, n_split, partial, sel, st);
     }
 }
 
 hipError_t launch_reduce_points_mf(const RenderGeom& g, const AntRec* ant, const QRec* rec,
-                                   uint32_t flags, int n_split, float2* partial, hipStream_t st) {
+                                   uint32_t flags, int n_split, float2* partial, const ChebPlan* sel,
+                                   hipStream_t st) {
     const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
-    return naive ? launch_rp_f<1, RFVR_SPEC_OFF, true>(g, ant, rec, n_split, partial, st)
-                 : launch_rp_f<1, RFVR_SPEC_OFF, false>(g, ant, rec, n_split, partial, st);
+    return naive ? launch_rp_f<1, RFVR_SPEC_OFF, true>(g, ant, rec, n_split, partial, sel, st)
+                 : launch_rp_f<1, RFVR_SPEC_OFF, false>(g, ant, rec, n_split, partial, sel, st);
 }
 
 // fixed-order sum of split partials: out[o] (+)= sum_s partial[s][o]
 __global__ void k_split_sum(const float2* __restrict__ partial, int n_split, long n_out,
-                            int accumulate, float2* __restrict__ out) {
+                            int accumulate, float2* __restrict__ out, const ChebPlan* __restrict__ sel) {
+    if (sel && sel->K != 0) return;
     long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n_out) return;
     float sr = 0.0f, si = 0.0f;
@@ -355,9 +341,9 @@ __global__ void k_split_sum(const float2* __restrict__ partial, int n_split, lon
 }
 
 hipError_t launch_split_sum(const float2* partial, int n_split, long n_out, int accumulate,
-                            float2* out, hipStream_t st) {
+                            float2* out, const ChebPlan* sel, hipStream_t st) {
     hipLaunchKernelGGL(k_split_sum, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                       partial, n_split, n_out, accumulate, out);
+                       partial, n_split, n_out, accumulate, out, sel);
     return hipGetLastError();
 }
 
@@ -391,7 +377,8 @@ template <int SPEC, bool NAIVE>
 __global__ __launch_bounds__(256) void k_render_bwd_points(
     long n_pts, const PtRec* __restrict__ rec, int n_meas, const AntRec* __restrict__ ant,
     const float2* __restrict__ gsig, int np, double K0, double Kd, float* __restrict__ g_b,
-    float* __restrict__ g_T, float* __restrict__ g_n) {
+    float* __restrict__ g_T, float* __restrict__ g_n, const ChebPlan* __restrict__ sel) {
+    if (sel && sel->K != 0) return;              // the Chebyshev path took this launch
     constexpr int PPL = kBwdPPL;
     const long j0 = (long)blockIdx.x * blockDim.x * PPL + threadIdx.x;
     PtRec P[PPL];
@@ -494,29 +481,29 @@ __global__ __launch_bounds__(256) void k_render_bwd_points(
 template <int SPEC>
 static hipError_t launch_rbp(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
                              const float2* gsig, int np, bool naive, float* g_b, float* g_T,
-                             float* g_n, hipStream_t st) {
+                             float* g_n, const ChebPlan* sel, hipStream_t st) {
     dim3 grid((unsigned)((g.n_pts + 256L * kBwdPPL - 1) / (256L * kBwdPPL)));
     if (naive)
         hipLaunchKernelGGL((k_render_bwd_points<SPEC, true>), grid, dim3(256), 0, st, g.n_pts, rec,
-                           g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n);
+                           g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n, sel);
     else
         hipLaunchKernelGGL((k_render_bwd_points<SPEC, false>), grid, dim3(256), 0, st, g.n_pts,
-                           rec, g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n);
+                           rec, g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n, sel);
     return hipGetLastError();
 }
 
 hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
                                     const float2* gsig_pad, int np, uint32_t flags, float* g_b,
-                                    float* g_T, float* g_n, hipStream_t st) {
+                                    float* g_T, float* g_n, const ChebPlan* sel, hipStream_t st) {
     const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
     switch (flags & RFVR_SPEC_MASK) {
         case RFVR_SPEC_RAW:
-            return launch_rbp<RFVR_SPEC_RAW>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n, st);
+            return launch_rbp<RFVR_SPEC_RAW>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n, sel, st);
         case RFVR_SPEC_OFF:
-            return launch_rbp<RFVR_SPEC_OFF>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n, st);
+            return launch_rbp<RFVR_SPEC_OFF>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n, sel, st);
         default:
             return launch_rbp<RFVR_SPEC_CLAMP>(g, ant, rec, gsig_pad, np, naive, g_b, g_T, g_n,
-                                               st);
+                                               sel, st);
     }
 }
 

@@ -88,6 +88,25 @@ __device__ __forceinline__ float alpha_pair(float a, float b) {
     return fminf(al, 1.0f);
 }
 
+// specular factor of a pair from nd = n_hat . w_i: 2 nd^2 - 1 = w_o . w_r,
+// clamped at 0 (CLAMP), raw (RAW) or 1 (OFF); live = 1 where it is not clamped
+template <int SPEC>
+__device__ __forceinline__ void spec_factor(float nd, float& spec, float& live) {
+    if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+        spec = 1.0f;
+        live = 0.0f;
+    } else {
+        float sr = __builtin_fmaf(2.0f * nd, nd, -1.0f);   // 2 (n.w_i)^2 - 1 = w_o . w_r
+        if constexpr (SPEC == (int)RFVR_SPEC_RAW) {
+            spec = sr;
+            live = 1.0f;
+        } else {
+            spec = fmaxf(sr, 0.0f);
+            live = sr >= 0.0f ? 1.0f : 0.0f;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pair phase set-up
 // ---------------------------------------------------------------------------
@@ -239,6 +258,17 @@ struct WsCursor {
     }
 };
 
+// Chebyshev-moment evaluation of the term sums (cheb.hip): per-measurement
+// range interval [rc - h, rc + h] of a launch and the chosen order K (0: the
+// per-frequency kernels run instead).
+struct alignas(16) MeasCheb {
+    double rc, h, inv_h, pad;
+};
+struct alignas(16) ChebPlan {
+    int K, pad;
+    double zmax;
+};
+
 // Launchers (render.hip)
 struct RenderGeom {
     int n_meas, n_freq, n_ray, n_z;
@@ -255,17 +285,21 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
                               const float* phi_ray, int use_phi, float s, float amp,
                               const float* amp_ptr, PtRec* rec, float* alpha_out, float* trans_out,
                               hipStream_t st);
+// sel: NULL, or the plan of the Chebyshev path (these kernels then return at
+// once unless it chose the per-frequency kernels, K == 0)
 hipError_t launch_reduce_points_render(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
-                                       uint32_t flags, int n_split, float2* partial, hipStream_t st);
+                                       uint32_t flags, int n_split, float2* partial, const ChebPlan* sel,
+                                       hipStream_t st);
 hipError_t launch_reduce_points_mf(const RenderGeom& g, const AntRec* ant, const QRec* rec,
-                                   uint32_t flags, int n_split, float2* partial, hipStream_t st);
+                                   uint32_t flags, int n_split, float2* partial, const ChebPlan* sel,
+                                   hipStream_t st);
 hipError_t launch_split_sum(const float2* partial, int n_split, long n_out, int accumulate,
-                            float2* out, hipStream_t st);
+                            float2* out, const ChebPlan* sel, hipStream_t st);
 hipError_t launch_pad_signal(const float2* sig, int n_meas, int n_freq, int np, float2* out,
                              hipStream_t st);
 hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, const PtRec* rec,
                                     const float2* gsig_pad, int np, uint32_t flags, float* g_b,
-                                    float* g_T, float* g_n, hipStream_t st);
+                                    float* g_T, float* g_n, const ChebPlan* sel, hipStream_t st);
 hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const float* sdf,
                                const float* grad, const float* refl, float s, float amp,
                                const float* amp_ptr, const float* alpha, const float* trans,
@@ -278,7 +312,8 @@ hipError_t launch_sum_scalars(const float* part, int n, float* out, int accumula
 // Launchers (mf.hip)
 hipError_t launch_mf_forward(const RenderGeom& g, const AntRec* ant, const float* xyz_q, long n_q,
                              const float2* sig_pad, const float2* sig2_pad, int np, uint32_t flags,
-                             float2* z, float* power, float2* z2, float* power2, hipStream_t st);
+                             float2* z, float* power, float2* z2, float* power2, const ChebPlan* sel,
+                             hipStream_t st);
 hipError_t launch_mf_bwd_records(const float* xyz_q, long n_q, const float2* z, const float* power,
                                  const float* g_power, QRec* rec, hipStream_t st);
 
@@ -302,5 +337,24 @@ hipError_t launch_bce(long n, const float* z, const float* t, float* loss, float
                       hipStream_t st);
 hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, float lr, float b1,
                         float b2, float eps, float wd, float bc1, float bc2, hipStream_t st);
+
+// Launchers (cheb.hip)
+constexpr int kChebMaxOrder = 64;
+int cheb_bbox_blocks(long n);
+int cheb_point_splits(long n_pts, int n_meas);
+hipError_t launch_cheb_order(const ChebPlan* plan, int32_t* order, hipStream_t st);
+hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, int n_meas, double Kd, int n_freq,
+                            float* bbox_part, MeasCheb* meas, ChebPlan* plan, hipStream_t st);
+hipError_t launch_cheb_points(const RenderGeom& g, int kind, uint32_t flags, const AntRec* ant,
+                              const MeasCheb* meas, const ChebPlan* plan, const void* rec, int n_split,
+                              float2* partial, float2* M, float2* out, int accumulate, hipStream_t st);
+hipError_t launch_cheb_coef(const RenderGeom& g, const ChebPlan* plan, const MeasCheb* meas, const float2* sig,
+                            float2* B, hipStream_t st);
+hipError_t launch_cheb_mf(const RenderGeom& g, const ChebPlan* plan, long n_q, const float* xq,
+                          const AntRec* ant, const MeasCheb* meas, const float2* B, const float2* B2,
+                          float2* z, float* power, float2* z2, float* power2, hipStream_t st);
+hipError_t launch_cheb_render_bwd(const RenderGeom& g, uint32_t flags, const ChebPlan* plan, const AntRec* ant,
+                                  const MeasCheb* meas, const PtRec* rec, const float2* B, float* g_b,
+                                  float* g_T, float* g_n, hipStream_t st);
 
 }  // namespace rfvr

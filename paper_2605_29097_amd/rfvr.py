@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("RFVR_LIBRARY") or os.path.join(_HERE, "librfvr.so")
 SPEC_CLAMP, SPEC_RAW, SPEC_OFF = 0x0, 0x1, 0x2
 PHASE_FP64RR, PHASE_NAIVE32 = 0x0, 0x4
 ACCUMULATE = 0x8
+TERMS_DIRECT = 0x10      # per-frequency evaluation of the term sums
 SAMPLE_GRID, SAMPLE_STRATIFIED = 0, 1
 PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
 ERRORS = {-1: "RFVR_E_INVALID", -2: "RFVR_E_WORKSPACE", -3: "RFVR_E_UNSUPPORTED", -4: "RFVR_E_HIP"}
@@ -108,6 +109,8 @@ _SIGS = {
     "rfvr_mask_update": ([_c_i64, _vp, _vp, _vp, _c_f, _c_f, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_bce": ([_c_i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_adamw": ([_c_i64, _vp, _vp, _vp, _vp, _c_i64, _c_f, _c_f, _c_f, _c_f, _c_f, _vp], _c_i32),
+    "rfvr_term_order_ws_bytes": ([_P(CAperture), _c_i64], _sz),
+    "rfvr_term_order": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _sz, _vp], _c_i32),
 }
 
 _lib = None
@@ -402,6 +405,19 @@ def mlp_backward(net: MLP, xyz: torch.Tensor, g_sdf=None, g_grad=None, g_refl=No
     return gp
 
 
+def term_order(ap: Aperture, xyz: torch.Tensor, stream=None) -> int:
+    """Order K of the Chebyshev-moment evaluation the term calls choose for
+    these measurements and points (0: per-frequency kernels).  Synchronises."""
+    dev = xyz.device
+    n = xyz.numel() // 3
+    cap = ap.c()
+    ws = _ws(lib().rfvr_term_order_ws_bytes(ctypes.byref(cap), n), dev)
+    out = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(lib().rfvr_term_order(ctypes.byref(cap), _ptr(xyz.contiguous()), n, _ptr(out), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "rfvr_term_order")
+    return int(out.item())
+
+
 def occupancy(s: float, sdf: torch.Tensor, stream=None):
     """Phi = sigmoid(s * sdf) (detached origin occupancies)."""
     phi = torch.empty_like(sdf)
@@ -555,3 +571,4 @@ rfvr_sample_naive = sample_naive
 rfvr_proposal_targets = proposal_targets
 rfvr_bce = bce
 rfvr_mask_update = mask_update
+rfvr_term_order = term_order
