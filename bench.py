@@ -25,28 +25,51 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_TERM = 8          # one complex multiply-add per term (4 FMA)
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CU x 128 FMA/clk x 2 x 2.4 GHz)
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 matrix (and vector) peak: 256 CU x 256 FLOP/clk x 2.4 GHz
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "render_fwd_mlp_box_hbm_counters.md")
-TERM_KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_29097_amd", "csrc", f) for f in ("render.hip", "rfvr_impl.hpp")]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mlp_backward_train_mlp_box_hbm_counters.md")
+NETWORK_SOURCES = [os.path.join(ROOT, "paper_2605_29097_amd", "csrc", f) for f in ("mlp.hip", "rfvr_impl.hpp")]
 
 
-def term_kernel_digest() -> str:
-    """sha256 over the sources of the signal-tracing term kernel."""
+def network_digest() -> str:
+    """sha256 over the sources of the network kernels."""
     import hashlib
     h = hashlib.sha256()
-    for f in TERM_KERNEL_SOURCES:
+    for f in NETWORK_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
+def mlp_backward_flop(cfg) -> int:
+    """Algorithmic FLOP per point of the training backward of the network
+    (2 per multiply-add, unpadded shapes): per trunk layer the tangent product
+    and two weight-gradient products, per layer above the first the two
+    adjoint products; the head's forward recompute, adjoint and weight
+    gradients; the scalar output layers are not counted."""
+    W, L, HW, HL = cfg.width, cfg.n_layers, cfg.head_width, cfg.head_layers
+    fin = [3 + 6 * cfg.pe_octaves] + [W] * (L - 1)
+    trunk = sum(2 * f * W for f in fin)                 # tangent
+    trunk += sum(2 * 2 * f * W for f in fin)            # W_bar = Z_bar^T H + Zdot_bar^T Hdot
+    trunk += sum(2 * 2 * W * W for _ in fin[1:])        # H_bar, Hdot_bar of the layer below
+    hin = [W] + [HW] * (HL - 1)
+    head = sum(2 * f * HW for f in hin)                 # forward recompute
+    head += sum(2 * f * HW for f in hin)                # weight gradients
+    head += sum(2 * f * HW for f in hin)                # adjoints of the head inputs (into the trunk)
+    return trunk + head
+
+
+def moment_flop_per_pair(K: int) -> int:
+    """FLOP per (measurement, point) pair of the moment kernel: per order one
+    recurrence FMA and one complex-by-real multiply-add (2 FMA)."""
+    return 6 * K
+
+
 def measured_traffic():
-    """HBM bytes per launch of the term kernel from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy), or None when the
-    kernel's sources changed after the counters were taken."""
+    """HBM bytes per call of the network training backward from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy),
+    or None when the network's sources changed after the counters were taken."""
     try:
         txt = open(TRAFFIC_PROFILE).read()
     except OSError:
@@ -56,7 +79,7 @@ def measured_traffic():
         if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "source_sha256")):
             k, v = line.strip().split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != term_kernel_digest() or "traffic_bytes_per_launch" not in vals:
+    if vals.get("source_sha256") != network_digest() or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -122,22 +145,28 @@ def cpu_baseline(cfg):
 
 
 def probe(tr, which, reps):
-    """Run one term pass `reps` times on the workload's inputs."""
+    """Run one pass (a term pass or the network training backward) `reps`
+    times on the workload's inputs."""
     import torch
     from paper_2605_29097_amd import rfvr as R
     c = tr.cfg
     xyz, u, origin = tr.samples()
-    f, grad, a = R.mlp_forward(tr.net, xyz)
-    sm = R.Samples(xyz=xyz)
-    fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3), refl=a.view(xyz.shape[:2]),
-                  s=c.s, amp=1.0)
-    sig = R.render_forward(tr.ap, sm, fl)
-    z, p = R.mf_forward(tr.ap, xyz, sig)
-    g_p = torch.randn_like(p)
-    g_sig = R.mf_backward(tr.ap, xyz, z, p, g_p)
+    res = tr.reserve(xyz.shape[0] * xyz.shape[1])
+    f, grad, a = R.mlp_forward(tr.net, xyz, reserve=res)
+    g_f, g_g, g_a = torch.randn_like(f), torch.randn_like(grad), torch.randn_like(a)
+    if which != "mlp_bwd":
+        sm = R.Samples(xyz=xyz)
+        fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3), refl=a.view(xyz.shape[:2]),
+                      s=c.s, amp=1.0)
+        sig = R.render_forward(tr.ap, sm, fl)
+        z, p = R.mf_forward(tr.ap, xyz, sig)
+        g_p = torch.randn_like(p)
+        g_sig = R.mf_backward(tr.ap, xyz, z, p, g_p)
     torch.cuda.synchronize()
     for _ in range(reps):
-        if which == "render_fwd":
+        if which == "mlp_bwd":
+            R.mlp_backward(tr.net, xyz, g_f, g_g, g_a, out=tr.g, reserve=res)
+        elif which == "render_fwd":
             R.render_forward(tr.ap, sm, fl)
         elif which == "mf_fwd":
             R.mf_forward(tr.ap, xyz, sig)
@@ -259,8 +288,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
-    ap.add_argument("--kernel-probe", choices=["render_fwd", "mf_fwd", "mf_bwd", "render_bwd"],
-                    help="run only one term pass of the workload (for hardware-counter runs)")
+    ap.add_argument("--kernel-probe", choices=["mlp_bwd", "render_fwd", "mf_fwd", "mf_bwd", "render_bwd"],
+                    help="run only one pass of the workload (for hardware-counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--proposal-study", action="store_true",
@@ -328,14 +357,26 @@ def main():
     tpp = cfg.terms_per_pass()
     terms_step = 4 * tpp
     value = terms_step / (ms_step * 1e-3)
-    # dominant term kernel: the signal-tracing forward, timed by HIP events on
-    # the stream it is launched on (its phase also holds two ~10 us helpers)
-    t_rf = phases["render_fwd"] * 1e-3
-    achieved = tpp * FLOP_PER_TERM / t_rf / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+    # dominant part of the step: the network training backward, one C-ABI
+    # call whose GEMMs (FP32 MFMA) take most of its time; timed by HIP events
+    # on the stream the call launches on
+    t_nb = phases["mlp_bwd"] * 1e-3
+    achieved = cfg.n_pts * mlp_backward_flop(cfg) / t_nb / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
-                "kernel": "k_reduce_points<64,0,CLAMP> (signal tracing forward)",
-                "launch_ms": round(phases["render_fwd"], 3)}
+                "kernel": "rfvr_mlp_backward_train (per layer: tangent, dual adjoint and two weight-gradient "
+                          "FP32 MFMA GEMMs, with the elementwise adjoints)",
+                "launch_ms": round(phases["mlp_bwd"], 3)}
+    # the term kernels: signal tracing forward through its moments, priced at
+    # the moment kernel's own work per (measurement, point) pair
+    K = R.term_order(tr.ap, tr.samples()[0])
+    t_rf = phases["render_fwd"] * 1e-3
+    a_t = cfg.n_pts * cfg.n_meas * moment_flop_per_pair(K) / t_rf / 1e12
+    roofline_terms = {"bound": "alu", "kernel": f"k_cheb_points<{K},0,CLAMP> (signal tracing forward, "
+                                                f"order {K})", "order": K,
+                      "achieved": round(a_t, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(a_t / PEAK_FP32_TFLOPS, 4), "launch_ms": round(phases["render_fwd"], 3),
+                      "terms_per_s": round(tpp / t_rf, 1)}
     out = {
         "metric": "fwd+bwd RF render terms/s",
         "value": value,
@@ -356,6 +397,7 @@ def main():
                    "terms_per_step": terms_step, "parallelism": "single GPU"},
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
         "roofline": roofline,
+        "roofline_terms": roofline_terms,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)

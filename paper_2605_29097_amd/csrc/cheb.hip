@@ -32,7 +32,7 @@
 // Per pair the moments cost 3 FP32 operations per order (recurrence of T_k and
 // a complex accumulate) and Clenshaw 4, against 4 per frequency in the
 // per-frequency kernels; the FP64 range and the one phasor exp(-+j 2 pi K0 r)
-// are set up once per pair.  Bessel values come from Miller's backward
+// (hardware sin / cos of the FP64-reduced phase) are set up once per pair.  Bessel values come from Miller's backward
 // recurrence in FP64 (first pass: normalisation J_0 + 2 sum J_2m = 1 and the
 // number of rescalings; second pass: the values, consumed as produced).
 #include <cmath>

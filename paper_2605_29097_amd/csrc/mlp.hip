@@ -99,13 +99,8 @@ struct GemmArgs {
     float beta;
 };
 
-#ifdef RFVR_NT_PREC
-#define RFVR_NT_LB __launch_bounds__(256, 2)
-#else
-#define RFVR_NT_LB __launch_bounds__(256)
-#endif
 template <int PRO, int EPI, int BM, int MM>
-__global__ RFVR_NT_LB void k_gemm_nt(GemmArgs g) {
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     constexpr int BP = 128, BK = 32, LW = BK + 4;
     constexpr int WP = (BM == 128) ? 2 : 4;
     constexpr int WM = 4 / WP;
@@ -136,22 +131,6 @@ __global__ RFVR_NT_LB void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-#ifdef RFVR_NT_PREC
-    float cpre[TP][TM][4];
-    if constexpr (EPI == EPI_DSPMUL || EPI == EPI_RELUMASK) {
-#pragma unroll
-        for (int a = 0; a < TP; ++a)
-#pragma unroll
-            for (int b = 0; b < TM; ++b) {
-                const int m = m0 + wm * (BM / WM) + b * 16 + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
-                    cpre[a][b][v] = (m < g.M && p < g.P) ? g.C[p * g.ldc + m] : 0.0f;
-                }
-            }
-    }
-#endif
     float4 ra[NA], rb[NB];
     auto load = [&](int k0) {
 #pragma unroll
@@ -264,13 +243,8 @@ __global__ RFVR_NT_LB void k_gemm_nt(GemmArgs g) {
                 float y = acc[a][b][v];
                 if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
                 if constexpr (EPI == EPI_ACC) y += g.Y[p * g.ldy + m];
-#ifdef RFVR_NT_PREC
-                if constexpr (EPI == EPI_RELUMASK) y = cpre[a][b][v] > 0.0f ? y : 0.0f;
-                if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(cpre[a][b][v], g.beta);
-#else
                 if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
                 if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
-#endif
                 g.Y[p * g.ldy + m] = y;
                 if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
             }
@@ -331,7 +305,6 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_dual(DualArgs g) {
             acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             acd[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         }
-#ifdef RFVR_DUAL_PREC
     // the adjoint epilogue's operands (Z and Hdot of the layer below) do not
     // depend on the products: fetch them before the main loop
     float cz[TP][TM][4], chd[TP][TM][4];
@@ -350,7 +323,6 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_dual(DualArgs g) {
                 }
             }
     }
-#endif
     float4 ra[NA], ra2[NA], rb[NB];
     auto load = [&](int k0) {
 #pragma unroll
@@ -470,11 +442,7 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_dual(DualArgs g) {
                     g.Y2[o] = sp_f(z, g.beta);
                     g.Y3[o] = sp_d1(z, g.beta) * acd[a][b][v];
                 } else {
-#ifdef RFVR_DUAL_PREC
                     const float z = cz[a][b][v], hd = chd[a][b][v];
-#else
-                    const float z = g.C[o], hd = g.C2[o];
-#endif
                     const float sg = fsig(g.beta * z);
                     const float hb = acc[a][b][v], hdb = acd[a][b][v];
                     g.Y[o] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
