@@ -53,11 +53,15 @@ enum { MM_FP32 = 0, MM_BF16 = 1, MM_BF16X3 = 3 };
 // by the producing GEMM's epilogue, so no operand is transformed twice)
 enum { PRO_ID = 0, PRO_RELU = 3 };
 // epilogues: BIAS  Y = acc + bias
-//            ACC   Y += acc
 //            RELUMASK  Y = acc where C > 0, else 0
 //            BIAS_SP   Y = acc + bias and Y2 = softplus(Y)            (layer output and activation)
 //            DSPMUL    Y = acc * softplus'(C)                          (normal sweep, adjoint to Z)
-enum { EPI_BIAS = 0, EPI_ACC = 1, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4 };
+//            BIAS_SP_SEED  as BIAS_SP and Y3 = softplus'(Y) colv      (top layer: seed of the sweep)
+//            TOPADJ    Hbar = acc + scale rowv[p] colv[m], Hdotbar = scale colv[m] with
+//                      C = Z, C2 = Hdot of the top layer: Y = Zbar, Y2 = Zdotbar
+//                      (the top trunk layer's adjoints, as the dual adjoint's epilogue)
+enum { EPI_BIAS = 0, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_BIAS_SP_SEED = 5,
+       EPI_TOPADJ = 6 };
 
 // Activation math of the network on the hardware exp2 / log2 / rcp units
 // (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once per element
@@ -88,13 +92,18 @@ __device__ __forceinline__ float sp_d2(float z, float beta) {
 // each lane reads 4 consecutive k (one float4) per 16-wide k group.
 // ----------------------------------------------------------------------------
 struct GemmArgs {
-    const float* A; const float* A2; long lda;
+    const float* A; long lda;
     const float* B; long ldb;
-    const float* bias;            // EPI_BIAS: [M] or null
-    const float* C;               // EPI_RELUMASK / DSPMUL: [P][ldc]
+    const float* bias;            // EPI_BIAS*: [M] or null
+    const float* C;               // EPI_RELUMASK / DSPMUL / TOPADJ: [P][ldc]
+    const float* C2;              // EPI_TOPADJ: [P][ldc]
     long ldc;
     float* Y; long ldy;
-    float* Y2;                    // EPI_BIAS_SP: second output, row stride ldy
+    float* Y2;                    // EPI_BIAS_SP*, TOPADJ: second output, row stride ldy
+    float* Y3;                    // EPI_BIAS_SP_SEED: third output, row stride ldy
+    const float* rowv;            // EPI_TOPADJ: [P] or null
+    const float* colv;            // EPI_BIAS_SP_SEED, TOPADJ: [M]
+    float scale;                  // EPI_TOPADJ
     long P; int M; int K;
     float beta;
 };
@@ -235,18 +244,30 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         for (int b = 0; b < TM; ++b) {
             const int m = m0 + wm * (BM / WM) + b * 16 + li;
             if (m >= g.M) continue;
-            const float bias = ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP) && g.bias) ? g.bias[m] : 0.0f;
+            const float bias =
+                ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP || EPI == EPI_BIAS_SP_SEED) && g.bias) ? g.bias[m] : 0.0f;
+            float cv = 0.0f;
+            if constexpr (EPI == EPI_BIAS_SP_SEED || EPI == EPI_TOPADJ) cv = g.colv[m];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
                 if (p >= g.P) continue;
                 float y = acc[a][b][v];
-                if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
-                if constexpr (EPI == EPI_ACC) y += g.Y[p * g.ldy + m];
+                if constexpr (EPI == EPI_TOPADJ) {
+                    const float hb = g.rowv ? __builtin_fmaf(g.scale * g.rowv[p], cv, y) : y;
+                    const float hdb = g.scale * cv;
+                    const float z = g.C[p * g.ldc + m], hd = g.C2[p * g.ldc + m];
+                    const float sg = fsig(g.beta * z);
+                    g.Y[p * g.ldy + m] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
+                    g.Y2[p * g.ldy + m] = sg * hdb;
+                    continue;
+                }
+                if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP || EPI == EPI_BIAS_SP_SEED) y += bias;
                 if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
                 if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
                 g.Y[p * g.ldy + m] = y;
-                if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
+                if constexpr (EPI == EPI_BIAS_SP || EPI == EPI_BIAS_SP_SEED) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
+                if constexpr (EPI == EPI_BIAS_SP_SEED) g.Y3[p * g.ldy + m] = sp_d1(y, g.beta) * cv;
             }
         }
 }
@@ -802,33 +823,6 @@ __global__ __launch_bounds__(256) void k_head_out_bwd(long n, const float* __res
     for (int m = lane; m < M; m += 64) Ybar2[p * ld + m] = Y2[p * ld + m] > 0.0f ? yb * w[m] : 0.0f;
 }
 
-// H_bar8[p][m] = half g_f[p] w_out[m] ; Hdot_bar8[p][m] = half w_out[m]
-__global__ void k_top_adjoint(long n, int M, const float* __restrict__ g_f, const float* __restrict__ w,
-                              float half, long ld, float* __restrict__ Hb, float* __restrict__ Hdb) {
-    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n * M) return;
-    const long p = o / M;
-    const int m = (int)(o % M);
-    Hb[p * ld + m] = g_f ? half * g_f[p] * w[m] : 0.0f;
-    Hdb[p * ld + m] = half * w[m];
-}
-
-// Z_bar = sp'(Z) H_bar + beta sigma(-beta Z) Hdot Hdot_bar ; Zdot_bar = sp'(Z) Hdot_bar
-__global__ void k_layer_adjoint(long n, int M, long ld, const float* __restrict__ Z,
-                                const float* __restrict__ Hd, const float* __restrict__ Hb,
-                                const float* __restrict__ Hdb, float beta, float* __restrict__ Zb,
-                                float* __restrict__ Zdb) {
-    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n * M) return;
-    const long p = o / M;
-    const long e = p * ld + (o % M);
-    const float z = Z[e];
-    const float s = fsig(beta * z);
-    const float hdb = Hdb[e];
-    Zb[e] = s * Hb[e] + beta * (1.0f - s) * Hd[e] * hdb;
-    Zdb[e] = s * hdb;
-}
-
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
     const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (o < n) p[o] = v;
@@ -1023,11 +1017,11 @@ DualArgs da(const float* A, const float* A2, long lda, const float* B, long ldb,
     return g;
 }
 
-GemmArgs ga(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
+GemmArgs ga(const float* A, long lda, const float* B, long ldb, const float* bias,
             float* Y, long ldy, long P, int M, int K, float beta, const float* C = nullptr,
             long ldc = 0, float* Y2 = nullptr) {
-    GemmArgs g;
-    g.A = A; g.A2 = A2; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.C = C; g.ldc = ldc;
+    GemmArgs g = {};
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.C = C; g.ldc = ldc;
     g.Y = Y; g.ldy = ldy; g.Y2 = Y2; g.P = P; g.M = M; g.K = K; g.beta = beta;
     return g;
 }
@@ -1151,37 +1145,48 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
             Z[i] = keep ? reserve_z(reserve, l, n, i) + c0 * l.W : Zw[i];
             H[i] = keep ? reserve_h(reserve, l, n, i) + c0 * l.W : G[i & 1];
         }
-        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, nullptr, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
+        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
                                        nullptr, 0, H[0]), cx);
-        for (int i = 1; i < l.L; ++i)
-            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], nullptr, l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W,
-                                         beta, nullptr, 0, H[i]), cx);
+        // with a reserve the sweep buffers are free, so the top layer's epilogue
+        // also writes the sweep's seed sp'(Z_{L-1}) w_out
+        const bool seed_fused = keep && grad && l.L > 1;
+        for (int i = 1; i < l.L; ++i) {
+            GemmArgs a = ga(H[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta, nullptr, 0, H[i]);
+            if (seed_fused && i == l.L - 1) {
+                a.Y3 = G[0];
+                a.colv = P + l.o_wout;
+                gemm<PRO_ID, EPI_BIAS_SP_SEED>(a, cx);
+            } else {
+                gemm<PRO_ID, EPI_BIAS_SP>(a, cx);
+            }
+        }
         float* Ht = H[l.L - 1];
         float* Zt = Z[l.L - 1];
         if (sdf)
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
                                (int)PRO_ID, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
         if (refl) {
-            gemm<PRO_ID, EPI_BIAS>(ga(Ht, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
+            gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
             for (int h = 1; h < l.HL; ++h)
-                gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
+                gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                                l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
         if (grad) {
             // adjoint of f w.r.t. Z_{L-1}: sp'(Z_{L-1}) w_out; then
             // dZ_{i-1} = (dZ_i W_i) . sp'(Z_{i-1}) (epilogue) and dgamma = dZ_0 W_0
-            hipLaunchKernelGGL(k_seed, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, Zt, (long)l.W,
-                               P + l.o_wout, beta, G[0]);
+            if (!seed_fused)
+                hipLaunchKernelGGL(k_seed, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, Zt, (long)l.W,
+                                   P + l.o_wout, beta, G[0]);
             int cur_g = 0;
             for (int i = l.L - 1; i >= 0; --i) {
                 const int mout = i == 0 ? l.in0p : l.W;
                 float* dst = G[cur_g ^ 1];
                 if (i > 0)
-                    gemm<PRO_ID, EPI_DSPMUL>(ga(G[cur_g], nullptr, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W,
+                    gemm<PRO_ID, EPI_DSPMUL>(ga(G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W,
                                                 beta, Z[i - 1], l.W), cx);
                 else    // the product with W_0 stays FP32
-                    gemm32<PRO_ID, EPI_BIAS>(ga(G[cur_g], nullptr, l.W, w.WT[0], l.W, nullptr, dst, mout, m, mout, l.W,
+                    gemm32<PRO_ID, EPI_BIAS>(ga(G[cur_g], l.W, w.WT[0], l.W, nullptr, dst, mout, m, mout, l.W,
                                                 beta), cx);
                 cur_g ^= 1;
             }
@@ -1250,10 +1255,10 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
         if (keep) {
             // tangent only: Hdot_i = sp'(Z_i) (Hdot_{i-1} W_i^T) with Z_i from the reserve
-            gemm32<PRO_ID, EPI_DSPMUL>(ga(X0d, nullptr, l.in0p, w.Wp[0], l.in0p, nullptr, Hd[0], l.W, m, l.W, l.in0p,
+            gemm32<PRO_ID, EPI_DSPMUL>(ga(X0d, l.in0p, w.Wp[0], l.in0p, nullptr, Hd[0], l.W, m, l.W, l.in0p,
                                           beta, Z[0], l.W), cx);
             for (int i = 1; i < l.L; ++i)
-                gemm<PRO_ID, EPI_DSPMUL>(ga(Hd[i - 1], nullptr, l.W, w.Wp[i], l.W, nullptr, Hd[i], l.W, m, l.W, l.W,
+                gemm<PRO_ID, EPI_DSPMUL>(ga(Hd[i - 1], l.W, w.Wp[i], l.W, nullptr, Hd[i], l.W, m, l.W, l.W,
                                             beta, Z[i], l.W), cx);
         } else {
             // one dual GEMM per layer: (Z_i, H_i) and Hdot_i share W_i
@@ -1266,9 +1271,9 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
         float* Ht = H[l.L - 1];
         float* Hdt = Hd[l.L - 1];
         // head forward
-        gemm<PRO_ID, EPI_BIAS>(ga(Ht, nullptr, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
+        gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
         for (int h = 1; h < l.HL; ++h)
-            gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], nullptr, l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
+            gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
         // head output: ybar3, Ybar_{HL-1}
         hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                            l.HW, P + l.o_whout, P + l.o_bhout, ga_, yb3, Ybh[l.HL - 1]);
@@ -1283,7 +1288,7 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                 hipLaunchKernelGGL(k_colsum_final, dim3(l.HW), dim3(256), 0, st, bpart, kWgSplits, l.HW, 1.0f,
                                GP + l.obh[h], acc);
                 // Ybar_{h-1} = (Ybar_h Wh_h) . relu'(Y_{h-1})
-                gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, nullptr, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), cx);
+                gemm<PRO_ID, EPI_RELUMASK>(ga(Yb, l.HW, w.WhT[h], l.HW, nullptr, Ybh[h - 1], l.HW, m, l.HW, l.HW, beta, Yh[h - 1], l.HW), cx);
             } else {
                 wgrad<PRO_ID>(Yb, l.HW, l.HW, Ht, nullptr, l.W, l.W, m, beta, part, cx, bpart);
                 wg_reduce(part, kWgSplits, l.HW, l.W, l.W, GP + l.oWh[0], acc, st);
@@ -1291,18 +1296,22 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                                GP + l.obh[0], acc);
             }
         }
-        // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0, Hdot_bar = half w_out
-        hipLaunchKernelGGL(k_top_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, gf, P + l.o_wout,
-                           half, (long)l.W, Hb, Hdb);
-        gemm<PRO_ID, EPI_ACC>(ga(Ybh[0], nullptr, l.HW, w.WhT[0], l.HW, nullptr, Hb, l.W, m, l.W, l.HW, beta), cx);
+        // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0 and Hdot_bar =
+        // half w_out, turned into the top layer's (Zbar, Zdotbar) in the epilogue
+        {
+            GemmArgs a = ga(Ybh[0], l.HW, w.WhT[0], l.HW, nullptr, Zb, l.W, m, l.W, l.HW, beta, Z[l.L - 1], l.W, Zdb);
+            a.C2 = Hd[l.L - 1];
+            a.rowv = gf;
+            a.colv = P + l.o_wout;
+            a.scale = half;
+            gemm<PRO_ID, EPI_TOPADJ>(a, cx);
+        }
         // sdf output layer: w_out_bar = half sum (g_f H + Hdot), b_out_bar = half sum g_f
         colsum(Ht, Hdt, gf, l.W, m, l.W, 3, beta, half, cpart, GP + l.o_wout, acc, st);
         if (gf) colsum(gf, nullptr, nullptr, 1, m, 1, 0, beta, half, cpart, GP + l.o_bout, acc, st);
         else if (!acc) hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, GP + l.o_bout, 1L, 0.0f);
-        // trunk layers, top down: the top layer's (Zbar, Zdotbar) elementwise,
-        // the others from the dual adjoint GEMM of the layer above
-        hipLaunchKernelGGL(k_layer_adjoint, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, (long)l.W,
-                           Z[l.L - 1], Hd[l.L - 1], Hb, Hdb, beta, Zb, Zdb);
+        // trunk layers, top down: the others' (Zbar, Zdotbar) from the dual
+        // adjoint GEMM of the layer above
         float *Zb_c = Zb, *Zdb_c = Zdb, *Zb_n = Hb, *Zdb_n = Hdb;
         for (int i = l.L - 1; i >= 0; --i) {
             float* Zb = Zb_c;
@@ -1529,9 +1538,9 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
         const int acc = (c0 > 0 || (flags & RFVR_ACCUMULATE)) ? 1 : 0;
         hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, xyz + 3 * c0, net->centre[0],
                            net->centre[1], net->centre[2], inv_half, l.L, l.in0p, X0, nullptr, nullptr);
-        gemm<PRO_ID, EPI_BIAS>(ga(X0, nullptr, l.in0p, Wp[0], l.in0p, P + l.ob[0], A[0], l.W, m, l.W, l.in0p, beta), cx);
+        gemm<PRO_ID, EPI_BIAS>(ga(X0, l.in0p, Wp[0], l.in0p, P + l.ob[0], A[0], l.W, m, l.W, l.in0p, beta), cx);
         for (int i = 1; i < l.layers; ++i)
-            gemm<PRO_RELU, EPI_BIAS>(ga(A[i - 1], nullptr, l.W, Wp[i], l.W, P + l.ob[i], A[i], l.W, m, l.W, l.W, beta), cx);
+            gemm<PRO_RELU, EPI_BIAS>(ga(A[i - 1], l.W, Wp[i], l.W, P + l.ob[i], A[i], l.W, m, l.W, l.W, beta), cx);
         float* At = A[l.layers - 1];
         if (!bwd) {
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, At, (long)l.W, l.W,
@@ -1552,7 +1561,7 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
                 hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
                                g_params + l.ob[i], acc);
                 if (i > 0) {
-                    gemm<PRO_ID, EPI_RELUMASK>(ga(Ab, nullptr, l.W, WT[i], l.W, nullptr, Ab2, l.W, m, l.W, l.W,
+                    gemm<PRO_ID, EPI_RELUMASK>(ga(Ab, l.W, WT[i], l.W, nullptr, Ab2, l.W, m, l.W, l.W,
                                                   beta, A[i - 1], l.W), cx);
                     float* t = Ab; Ab = Ab2; Ab2 = t;
                 }
