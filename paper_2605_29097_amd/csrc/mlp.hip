@@ -108,17 +108,48 @@ struct GemmArgs {
     float beta;
 };
 
+#ifndef RFVR_NT_BK
+#define RFVR_NT_BK 32
+#endif
+#ifndef RFVR_NT_DB
+#define RFVR_NT_DB 0
+#endif
+#ifndef RFVR_NT_SWZ
+#define RFVR_NT_SWZ 0
+#endif
+// LDS tile of BK-deep rows: padded rows (stride BK + 4 floats) or unpadded
+// rows with the float4 index XOR-swizzled by the row, both free of bank
+// conflicts for the MFMA fragment reads (16 rows, one float4 column)
+template <int BK, bool SWZ>
+struct LdsTile {
+    static constexpr int LW = SWZ ? BK : BK + 4;
+    __device__ static __forceinline__ int off(int row, int q) {
+        if constexpr (SWZ) {
+            const int sw = BK == 32 ? ((row >> 1) & 7) : (row & 15);
+            return row * LW + 4 * (q ^ sw);
+        } else {
+            return row * LW + 4 * q;
+        }
+    }
+};
+
+#ifndef RFVR_NT_WAVES
+#define RFVR_NT_WAVES 1
+#endif
 template <int PRO, int EPI, int BM, int MM>
-__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
-    constexpr int BP = 128, BK = 32, LW = BK + 4;
+__global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
+    constexpr int BP = 128, BK = MM == MM_FP32 ? RFVR_NT_BK : 32;
+    constexpr bool DB = RFVR_NT_DB != 0;
+    using L = LdsTile<BK, RFVR_NT_SWZ != 0>;
+    constexpr int LW = L::LW, RPF = BK / 4, NBUF = DB ? 2 : 1;
     constexpr int WP = (BM == 128) ? 2 : 4;
     constexpr int WM = 4 / WP;
     constexpr int TP = BP / WP / 16;
     constexpr int TM = BM / WM / 16;
     constexpr int NA = BP * BK / 4 / 256;       // float4 per thread, A
     constexpr int NB = BM * BK / 4 / 256;       // float4 per thread, B
-    __shared__ float sA[BP * LW];
-    __shared__ float sB[BM * LW];
+    __shared__ float sA[NBUF][BP * LW];
+    __shared__ float sB[NBUF][BM * LW];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wp = wv % WP, wm = wv / WP;
     const int li = lane & 15, lg = lane >> 4;
@@ -140,57 +171,79 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
+    // the top-adjoint epilogue reads two operands that do not depend on the
+    // product: fetch them before the (short, K = head width) main loop
+    float cz[EPI == EPI_TOPADJ ? TP : 1][EPI == EPI_TOPADJ ? TM : 1][4];
+    float chd[EPI == EPI_TOPADJ ? TP : 1][EPI == EPI_TOPADJ ? TM : 1][4];
+    if constexpr (EPI == EPI_TOPADJ) {
+#pragma unroll
+        for (int a = 0; a < TP; ++a)
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const int m = m0 + wm * (BM / WM) + b * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
+                    const bool in = m < g.M && p < g.P;
+                    cz[a][b][v] = in ? g.C[p * g.ldc + m] : 0.0f;
+                    chd[a][b][v] = in ? g.C2[p * g.ldc + m] : 0.0f;
+                }
+            }
+    }
     float4 ra[NA], rb[NB];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * 256;
-            const int row = e >> 3, c4 = (e & 7) * 4;
+            const int row = e / RPF, c4 = (e % RPF) * 4;
             const long p = p0 + row;
             ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (p < g.P) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
+            if (p < g.P && (BK == 32 || k0 + c4 < g.K))     // K is a multiple of 32
+                ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int e = tid + i * 256;
-            const int row = e >> 3, c4 = (e & 7) * 4;
+            const int row = e / RPF, c4 = (e % RPF) * 4;
             const int m = m0 + row;
             rb[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (m < g.M) rb[i] = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
+            if (m < g.M && (BK == 32 || k0 + c4 < g.K))
+                rb[i] = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
         }
     };
-    load(0);
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    auto store = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * 256;
-            const int row = e >> 3, c4 = (e & 7) * 4;
             float4 v = ra[i];
             if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
-            *reinterpret_cast<float4*>(&sA[row * LW + c4]) = v;
+            *reinterpret_cast<float4*>(&sA[buf][L::off(e / RPF, e % RPF)]) = v;
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int e = tid + i * 256;
-            const int row = e >> 3, c4 = (e & 7) * 4;
-            *reinterpret_cast<float4*>(&sB[row * LW + c4]) = rb[i];
+            *reinterpret_cast<float4*>(&sB[buf][L::off(e / RPF, e % RPF)]) = rb[i];
         }
-        __syncthreads();
-        if (k0 + BK < g.K) load(k0 + BK);
+    };
+    auto compute = [&](int buf) {
+        const float* A_ = sA[buf];
+        const float* B_ = sB[buf];
         if constexpr (MM == MM_BF16) {
             // the chunk's two 16-wide k groups feed one 16x16x32 BF16 MFMA
             bf16x8 af[TP], bf[TM];
 #pragma unroll
             for (int a = 0; a < TP; ++a) {
-                const float* r = &sA[(wp * (BP / WP) + a * 16 + li) * LW + lg * 4];
-                af[a] = to_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16));
+                const int row = wp * (BP / WP) + a * 16 + li;
+                af[a] = to_bf16x8(*reinterpret_cast<const floatx4*>(&A_[L::off(row, lg)]),
+                                  *reinterpret_cast<const floatx4*>(&A_[L::off(row, lg + 4)]));
             }
 #pragma unroll
             for (int b = 0; b < TM; ++b) {
-                const float* r = &sB[(wm * (BM / WM) + b * 16 + li) * LW + lg * 4];
-                bf[b] = to_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16));
+                const int row = wm * (BM / WM) + b * 16 + li;
+                bf[b] = to_bf16x8(*reinterpret_cast<const floatx4*>(&B_[L::off(row, lg)]),
+                                  *reinterpret_cast<const floatx4*>(&B_[L::off(row, lg + 4)]));
             }
 #pragma unroll
             for (int a = 0; a < TP; ++a)
@@ -201,13 +254,15 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             bf16x8 ab[TP], as[TP], bb[TM], bs[TM];
 #pragma unroll
             for (int a = 0; a < TP; ++a) {
-                const float* r = &sA[(wp * (BP / WP) + a * 16 + li) * LW + lg * 4];
-                split_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16), ab[a], as[a]);
+                const int row = wp * (BP / WP) + a * 16 + li;
+                split_bf16x8(*reinterpret_cast<const floatx4*>(&A_[L::off(row, lg)]),
+                             *reinterpret_cast<const floatx4*>(&A_[L::off(row, lg + 4)]), ab[a], as[a]);
             }
 #pragma unroll
             for (int b = 0; b < TM; ++b) {
-                const float* r = &sB[(wm * (BM / WM) + b * 16 + li) * LW + lg * 4];
-                split_bf16x8(*reinterpret_cast<const floatx4*>(r), *reinterpret_cast<const floatx4*>(r + 16), bb[b], bs[b]);
+                const int row = wm * (BM / WM) + b * 16 + li;
+                split_bf16x8(*reinterpret_cast<const floatx4*>(&B_[L::off(row, lg)]),
+                             *reinterpret_cast<const floatx4*>(&B_[L::off(row, lg + 4)]), bb[b], bs[b]);
             }
 #pragma unroll
             for (int a = 0; a < TP; ++a)
@@ -223,10 +278,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 floatx4 af[TP], bf[TM];
 #pragma unroll
                 for (int a = 0; a < TP; ++a)
-                    af[a] = *reinterpret_cast<const floatx4*>(&sA[(wp * (BP / WP) + a * 16 + li) * LW + kk + lg * 4]);
+                    af[a] = *reinterpret_cast<const floatx4*>(&A_[L::off(wp * (BP / WP) + a * 16 + li, kk / 4 + lg)]);
 #pragma unroll
                 for (int b = 0; b < TM; ++b)
-                    bf[b] = *reinterpret_cast<const floatx4*>(&sB[(wm * (BM / WM) + b * 16 + li) * LW + kk + lg * 4]);
+                    bf[b] = *reinterpret_cast<const floatx4*>(&B_[L::off(wm * (BM / WM) + b * 16 + li, kk / 4 + lg)]);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -236,7 +291,33 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
             }
         }
+    };
+    if constexpr (!DB) {
+        // one LDS buffer: store, barrier, next chunk's global loads in flight
+        // during this chunk's MFMAs, barrier
+        load(0);
+        for (int k0 = 0; k0 < g.K; k0 += BK) {
+            store(0);
+            __syncthreads();
+            if (k0 + BK < g.K) load(k0 + BK);
+            compute(0);
+            __syncthreads();
+        }
+    } else {
+        // two LDS buffers: one barrier per chunk; the next chunk is stored
+        // into the other buffer after this chunk's MFMAs
+        load(0);
+        store(0);
         __syncthreads();
+        int cur = 0;
+        for (int k0 = 0; k0 < g.K; k0 += BK) {
+            const bool more = k0 + BK < g.K;
+            if (more) load(k0 + BK);
+            compute(cur);
+            if (more) store(cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
+        }
     }
 #pragma unroll
     for (int a = 0; a < TP; ++a)
@@ -256,7 +337,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 if constexpr (EPI == EPI_TOPADJ) {
                     const float hb = g.rowv ? __builtin_fmaf(g.scale * g.rowv[p], cv, y) : y;
                     const float hdb = g.scale * cv;
-                    const float z = g.C[p * g.ldc + m], hd = g.C2[p * g.ldc + m];
+                    const float z = cz[a][b][v], hd = chd[a][b][v];
                     const float sg = fsig(g.beta * z);
                     g.Y[p * g.ldy + m] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
                     g.Y2[p * g.ldy + m] = sg * hdb;
@@ -295,13 +376,13 @@ struct DualArgs {
 };
 
 template <int EPI2, int MM, int NW>
-__global__ __launch_bounds__(NW * 64) void k_gemm_dual(DualArgs g) {
-    // NW = 8: 4 waves along points x 2 along outputs, 128 x 128 block, 2 x 4
-    // tiles of 16 x 16 per wave; NW = 4: 2 x 2 waves, 128 x 64 block, 4 x 2
-    // tiles.  Two accumulator sets (64 registers) per wave either way.
+__global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_gemm_dual(DualArgs g) {
+    // NW = 8: 4 waves along points x 2 along outputs, 128 x 128 block; NW = 4:
+    // 2 x 2 waves, 64 x 128 block.  2 x 4 tiles of 16 x 16 per wave and two
+    // accumulator sets (64 registers) either way.
     constexpr int NT = NW * 64;
-    constexpr int BP = 128, BM = NW == 8 ? 128 : 64, BK = 32, LW = BK + 4;
-    constexpr int WP = NW == 8 ? 4 : 2, TP = BP / WP / 16, TM = BM / 2 / 16;
+    constexpr int BP = NW == 8 ? 128 : 64, BM = 128, BK = 32, LW = BK + 4;
+    constexpr int WP = NW / 2, TP = BP / WP / 16, TM = BM / 2 / 16;
     constexpr int NA = BP * BK / 4 / NT, NB = BM * BK / 4 / NT;
     __shared__ float sA[BP * LW];
     __shared__ float sA2[BP * LW];
@@ -994,12 +1075,12 @@ void gemm32(const GemmArgs& a, const Cx& cx) {
 }
 
 #ifndef RFVR_DUAL_NW
-#define RFVR_DUAL_NW 8
+#define RFVR_DUAL_NW 4
 #endif
 template <int EPI2>
 void gemm_dual(const DualArgs& a, int mm, hipStream_t st) {
-    constexpr int NW = RFVR_DUAL_NW, BM = NW == 8 ? 128 : 64;
-    const long tiles = (a.P + 127) / 128;
+    constexpr int NW = RFVR_DUAL_NW, BP = NW == 8 ? 128 : 64, BM = 128;
+    const long tiles = (a.P + BP - 1) / BP;
     const long groups = (tiles + 7) / 8;
     const long nmb = (a.M + BM - 1) / BM;
     const dim3 grid((unsigned)(groups * 8 * nmb));
