@@ -108,48 +108,22 @@ struct GemmArgs {
     float beta;
 };
 
-#ifndef RFVR_NT_BK
-#define RFVR_NT_BK 32
-#endif
-#ifndef RFVR_NT_DB
-#define RFVR_NT_DB 0
-#endif
-#ifndef RFVR_NT_SWZ
-#define RFVR_NT_SWZ 0
-#endif
-// LDS tile of BK-deep rows: padded rows (stride BK + 4 floats) or unpadded
-// rows with the float4 index XOR-swizzled by the row, both free of bank
-// conflicts for the MFMA fragment reads (16 rows, one float4 column)
-template <int BK, bool SWZ>
-struct LdsTile {
-    static constexpr int LW = SWZ ? BK : BK + 4;
-    __device__ static __forceinline__ int off(int row, int q) {
-        if constexpr (SWZ) {
-            const int sw = BK == 32 ? ((row >> 1) & 7) : (row & 15);
-            return row * LW + 4 * (q ^ sw);
-        } else {
-            return row * LW + 4 * q;
-        }
-    }
-};
-
-#ifndef RFVR_NT_WAVES
-#define RFVR_NT_WAVES 1
-#endif
 template <int PRO, int EPI, int BM, int MM>
-__global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
-    constexpr int BP = 128, BK = MM == MM_FP32 ? RFVR_NT_BK : 32;
-    constexpr bool DB = RFVR_NT_DB != 0;
-    using L = LdsTile<BK, RFVR_NT_SWZ != 0>;
-    constexpr int LW = L::LW, RPF = BK / 4, NBUF = DB ? 2 : 1;
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+    // padded LDS rows (BK + 4 floats): the MFMA fragment reads (16 rows, one
+    // float4 column) are free of bank conflicts.  Variants measured slower on
+    // this shape: an XOR-swizzled unpadded layout, two LDS buffers with one
+    // barrier per chunk, 64-deep chunks (all at two waves per SIMD, against
+    // three here).
+    constexpr int BP = 128, BK = 32, LW = BK + 4, RPF = BK / 4;
     constexpr int WP = (BM == 128) ? 2 : 4;
     constexpr int WM = 4 / WP;
     constexpr int TP = BP / WP / 16;
     constexpr int TM = BM / WM / 16;
     constexpr int NA = BP * BK / 4 / 256;       // float4 per thread, A
     constexpr int NB = BM * BK / 4 / 256;       // float4 per thread, B
-    __shared__ float sA[NBUF][BP * LW];
-    __shared__ float sB[NBUF][BM * LW];
+    __shared__ float sA[BP * LW];
+    __shared__ float sB[BM * LW];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wp = wv % WP, wm = wv / WP;
     const int li = lane & 15, lg = lane >> 4;
@@ -198,8 +172,7 @@ __global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
             const int row = e / RPF, c4 = (e % RPF) * 4;
             const long p = p0 + row;
             ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (p < g.P && (BK == 32 || k0 + c4 < g.K))     // K is a multiple of 32
-                ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
+            if (p < g.P) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -207,11 +180,11 @@ __global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
             const int row = e / RPF, c4 = (e % RPF) * 4;
             const int m = m0 + row;
             rb[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (m < g.M && (BK == 32 || k0 + c4 < g.K))
-                rb[i] = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
+            if (m < g.M) rb[i] = *reinterpret_cast<const float4*>(g.B + (long)m * g.ldb + k0 + c4);
         }
     };
-    auto store = [&](int buf) {
+    auto off = [](int row, int q) { return row * LW + 4 * q; };
+    auto store = [&]() {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * 256;
@@ -219,31 +192,31 @@ __global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
             if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
-            *reinterpret_cast<float4*>(&sA[buf][L::off(e / RPF, e % RPF)]) = v;
+            *reinterpret_cast<float4*>(&sA[off(e / RPF, e % RPF)]) = v;
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int e = tid + i * 256;
-            *reinterpret_cast<float4*>(&sB[buf][L::off(e / RPF, e % RPF)]) = rb[i];
+            *reinterpret_cast<float4*>(&sB[off(e / RPF, e % RPF)]) = rb[i];
         }
     };
-    auto compute = [&](int buf) {
-        const float* A_ = sA[buf];
-        const float* B_ = sB[buf];
+    auto compute = [&]() {
+        const float* A_ = sA;
+        const float* B_ = sB;
         if constexpr (MM == MM_BF16) {
             // the chunk's two 16-wide k groups feed one 16x16x32 BF16 MFMA
             bf16x8 af[TP], bf[TM];
 #pragma unroll
             for (int a = 0; a < TP; ++a) {
                 const int row = wp * (BP / WP) + a * 16 + li;
-                af[a] = to_bf16x8(*reinterpret_cast<const floatx4*>(&A_[L::off(row, lg)]),
-                                  *reinterpret_cast<const floatx4*>(&A_[L::off(row, lg + 4)]));
+                af[a] = to_bf16x8(*reinterpret_cast<const floatx4*>(&A_[off(row, lg)]),
+                                  *reinterpret_cast<const floatx4*>(&A_[off(row, lg + 4)]));
             }
 #pragma unroll
             for (int b = 0; b < TM; ++b) {
                 const int row = wm * (BM / WM) + b * 16 + li;
-                bf[b] = to_bf16x8(*reinterpret_cast<const floatx4*>(&B_[L::off(row, lg)]),
-                                  *reinterpret_cast<const floatx4*>(&B_[L::off(row, lg + 4)]));
+                bf[b] = to_bf16x8(*reinterpret_cast<const floatx4*>(&B_[off(row, lg)]),
+                                  *reinterpret_cast<const floatx4*>(&B_[off(row, lg + 4)]));
             }
 #pragma unroll
             for (int a = 0; a < TP; ++a)
@@ -255,14 +228,14 @@ __global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
             for (int a = 0; a < TP; ++a) {
                 const int row = wp * (BP / WP) + a * 16 + li;
-                split_bf16x8(*reinterpret_cast<const floatx4*>(&A_[L::off(row, lg)]),
-                             *reinterpret_cast<const floatx4*>(&A_[L::off(row, lg + 4)]), ab[a], as[a]);
+                split_bf16x8(*reinterpret_cast<const floatx4*>(&A_[off(row, lg)]),
+                             *reinterpret_cast<const floatx4*>(&A_[off(row, lg + 4)]), ab[a], as[a]);
             }
 #pragma unroll
             for (int b = 0; b < TM; ++b) {
                 const int row = wm * (BM / WM) + b * 16 + li;
-                split_bf16x8(*reinterpret_cast<const floatx4*>(&B_[L::off(row, lg)]),
-                             *reinterpret_cast<const floatx4*>(&B_[L::off(row, lg + 4)]), bb[b], bs[b]);
+                split_bf16x8(*reinterpret_cast<const floatx4*>(&B_[off(row, lg)]),
+                             *reinterpret_cast<const floatx4*>(&B_[off(row, lg + 4)]), bb[b], bs[b]);
             }
 #pragma unroll
             for (int a = 0; a < TP; ++a)
@@ -278,10 +251,10 @@ __global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
                 floatx4 af[TP], bf[TM];
 #pragma unroll
                 for (int a = 0; a < TP; ++a)
-                    af[a] = *reinterpret_cast<const floatx4*>(&A_[L::off(wp * (BP / WP) + a * 16 + li, kk / 4 + lg)]);
+                    af[a] = *reinterpret_cast<const floatx4*>(&A_[off(wp * (BP / WP) + a * 16 + li, kk / 4 + lg)]);
 #pragma unroll
                 for (int b = 0; b < TM; ++b)
-                    bf[b] = *reinterpret_cast<const floatx4*>(&B_[L::off(wm * (BM / WM) + b * 16 + li, kk / 4 + lg)]);
+                    bf[b] = *reinterpret_cast<const floatx4*>(&B_[off(wm * (BM / WM) + b * 16 + li, kk / 4 + lg)]);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -292,32 +265,15 @@ __global__ __launch_bounds__(256, RFVR_NT_WAVES) void k_gemm_nt(GemmArgs g) {
             }
         }
     };
-    if constexpr (!DB) {
-        // one LDS buffer: store, barrier, next chunk's global loads in flight
-        // during this chunk's MFMAs, barrier
-        load(0);
-        for (int k0 = 0; k0 < g.K; k0 += BK) {
-            store(0);
-            __syncthreads();
-            if (k0 + BK < g.K) load(k0 + BK);
-            compute(0);
-            __syncthreads();
-        }
-    } else {
-        // two LDS buffers: one barrier per chunk; the next chunk is stored
-        // into the other buffer after this chunk's MFMAs
-        load(0);
-        store(0);
+    // one LDS buffer: store, barrier, next chunk's global loads in flight
+    // during this chunk's MFMAs, barrier
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        store();
         __syncthreads();
-        int cur = 0;
-        for (int k0 = 0; k0 < g.K; k0 += BK) {
-            const bool more = k0 + BK < g.K;
-            if (more) load(k0 + BK);
-            compute(cur);
-            if (more) store(cur ^ 1);
-            __syncthreads();
-            cur ^= 1;
-        }
+        if (k0 + BK < g.K) load(k0 + BK);
+        compute();
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < TP; ++a)
