@@ -19,7 +19,7 @@
 //   * a reduction over frequencies into a Chebyshev series per measurement,
 //       B_ik = eps_k j^k sum_n g[i][n] exp(+j 2 pi n Kd rc_i) J_k(z_in),
 //       sum_n g[i][n] exp(+j 2 pi (K0 + n Kd) r) = exp(+j 2 pi K0 r) sum_k B_ik T_k(x),
-//     evaluated per pair by Clenshaw's recurrence.
+//     evaluated per pair with T_k from their three-term recurrence.
 // Since |T_k| <= 1 on [-1, 1] and |J_k(z)| <= (z/2)^k / k!, cutting the series
 // at K changes each output by at most 2 (z/2)^K / K! / (1 - z / (2K + 2)) times
 // the sum of the magnitudes of its terms' weights.  A one-block plan kernel
@@ -29,8 +29,8 @@
 // stays on the device: every candidate kernel is launched and all but the
 // chosen one return at once, so no host synchronisation is needed.
 //
-// Per pair the moments cost 3 FP32 operations per order (recurrence of T_k and
-// a complex accumulate) and Clenshaw 4, against 4 per frequency in the
+// Per pair both cost 3 FP32 operations per order (recurrence of T_k and a
+// complex multiply-add by a real), against 4 per frequency in the
 // per-frequency kernels; the FP64 range and the one phasor exp(-+j 2 pi K0 r)
 // (hardware sin / cos of the FP64-reduced phase) are set up once per pair.  Bessel values come from Miller's backward
 // recurrence in FP64 (first pass: normalisation J_0 + 2 sum J_2m = 1 and the
@@ -429,24 +429,59 @@ __global__ __launch_bounds__(64) void k_cheb_coef(const ChebPlan* __restrict__ p
     }
 }
 
-// sum_k B_k T_k(x) by Clenshaw's recurrence (complex coefficients, real x)
+// sum_k B_k T_k(x) (complex coefficients, real x) with T_k from their
+// three-term recurrence: 3 operations per order (Clenshaw's backward form
+// takes 4), the coefficients being wave-uniform scalar operands
 template <int K>
-__device__ __forceinline__ void clenshaw(const float2* __restrict__ Bi, float x, float& sr, float& si) {
+__device__ __forceinline__ void cheb_series(const float2* __restrict__ Bi, float x, float& sr, float& si) {
     const float x2 = x + x;
-    float b1r = 0.0f, b1i = 0.0f, b2r = 0.0f, b2i = 0.0f;
+    float2 c = Bi[0];
+    sr = c.x;
+    si = c.y;
+    c = Bi[1];
+    sr = __builtin_fmaf(c.x, x, sr);
+    si = __builtin_fmaf(c.y, x, si);
+    float tm = 1.0f, tk = x;
 #pragma unroll
-    for (int k = K - 1; k >= 1; --k) {
-        const float2 c = Bi[k];
-        const float tr = __builtin_fmaf(x2, b1r, c.x - b2r);
-        const float ti = __builtin_fmaf(x2, b1i, c.y - b2i);
-        b2r = b1r;
-        b2i = b1i;
-        b1r = tr;
-        b1i = ti;
+    for (int k = 2; k < K; ++k) {
+        const float tn = __builtin_fmaf(x2, tk, -tm);
+        tm = tk;
+        tk = tn;
+        c = Bi[k];
+        sr = __builtin_fmaf(c.x, tn, sr);
+        si = __builtin_fmaf(c.y, tn, si);
     }
-    const float2 c0 = Bi[0];
-    sr = __builtin_fmaf(x, b1r, c0.x - b2r);
-    si = __builtin_fmaf(x, b1i, c0.y - b2i);
+}
+
+// two series with the same argument, sharing the recurrence
+template <int K>
+__device__ __forceinline__ void cheb_series2(const float2* __restrict__ Bi, const float2* __restrict__ Ci, float x,
+                                             float& sr, float& si, float& s2r, float& s2i) {
+    const float x2 = x + x;
+    float2 c = Bi[0], d = Ci[0];
+    sr = c.x;
+    si = c.y;
+    s2r = d.x;
+    s2i = d.y;
+    c = Bi[1];
+    d = Ci[1];
+    sr = __builtin_fmaf(c.x, x, sr);
+    si = __builtin_fmaf(c.y, x, si);
+    s2r = __builtin_fmaf(d.x, x, s2r);
+    s2i = __builtin_fmaf(d.y, x, s2i);
+    float tm = 1.0f, tk = x;
+#pragma unroll
+    for (int k = 2; k < K; ++k) {
+        const float tn = __builtin_fmaf(x2, tk, -tm);
+        tm = tk;
+        tk = tn;
+        c = Bi[k];
+        d = Ci[k];
+        sr = __builtin_fmaf(c.x, tn, sr);
+        si = __builtin_fmaf(c.y, tn, si);
+        s2r = __builtin_fmaf(d.x, tn, s2r);
+        s2i = __builtin_fmaf(d.y, tn, s2i);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -475,14 +510,16 @@ __global__ __launch_bounds__(256) void k_cheb_mf(const ChebPlan* __restrict__ pl
         const float t0 = frac_rev(r * K0);
         const float c0 = cos_rev(t0), s0 = sin_rev(t0);       // exp(+j 2 pi K0 r)
         float sr, si;
-        clenshaw<K>(B + (size_t)i * kChebKMax, x, sr, si);
+        if constexpr (TWO) {
+            float s2r, s2i;
+            cheb_series2<K>(B + (size_t)i * kChebKMax, B2 + (size_t)i * kChebKMax, x, sr, si, s2r, s2i);
+            z2r = __builtin_fmaf(c0, s2r, __builtin_fmaf(-s0, s2i, z2r));
+            z2i = __builtin_fmaf(c0, s2i, __builtin_fmaf(s0, s2r, z2i));
+        } else {
+            cheb_series<K>(B + (size_t)i * kChebKMax, x, sr, si);
+        }
         zr = __builtin_fmaf(c0, sr, __builtin_fmaf(-s0, si, zr));
         zi = __builtin_fmaf(c0, si, __builtin_fmaf(s0, sr, zi));
-        if constexpr (TWO) {
-            clenshaw<K>(B2 + (size_t)i * kChebKMax, x, sr, si);
-            z2r = __builtin_fmaf(c0, sr, __builtin_fmaf(-s0, si, z2r));
-            z2i = __builtin_fmaf(c0, si, __builtin_fmaf(s0, sr, z2i));
-        }
     }
     if (q >= n_q) return;
     if (z) z[q] = make_float2(zr, zi);
@@ -518,7 +555,7 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
         const double r = range_f64(dx, dy, dz, y);
         const float x = (float)((r - mc.rc) * mc.inv_h);
         float sr, si;
-        clenshaw<K>(B + (size_t)i * kChebKMax, x, sr, si);
+        cheb_series<K>(B + (size_t)i * kChebKMax, x, sr, si);
         const float t0 = frac_rev(r * K0);
         const float c0 = cos_rev(t0), s0 = sin_rev(t0);
         const float G = c0 * sr - s0 * si;                     // Re(exp(+j 2 pi K0 r) S)
