@@ -888,7 +888,10 @@ __global__ void k_pad_cols(const float* __restrict__ in, int R, int C, int Cpad,
 namespace {
 
 constexpr long kChunk = 1 << 20;          // points per pass (bounds the workspace)
-constexpr int kWgSplits = 128;            // weight-gradient point splits per pass
+#ifndef RFVR_WG_SPLITS
+#define RFVR_WG_SPLITS 384
+#endif
+constexpr int kWgSplits = RFVR_WG_SPLITS; // weight-gradient point splits per pass
 constexpr int kColBlocks = 2048;          // column-sum partial blocks
 
 struct Layout {
