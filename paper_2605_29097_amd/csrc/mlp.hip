@@ -49,19 +49,19 @@ __device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big
 // split operands (a b ~ a_big b_big + a_big b_small + a_small b_big)
 enum { MM_FP32 = 0, MM_BF16 = 1, MM_BF16X3 = 3 };
 
-// operand prologues: identity or relu (the softplus activations are written
-// by the producing GEMM's epilogue, so no operand is transformed twice)
-enum { PRO_ID = 0, PRO_RELU = 3 };
+// operand prologues: identity, relu, or SEED: A[p][k] -> softplus'(A[p][k])
+// colv[k] (the normal sweep's seed from the top layer's Z, formed while the
+// tile is staged); the softplus activations themselves are written by the
+// producing GEMM's epilogue, so no operand is transformed twice
+enum { PRO_ID = 0, PRO_SEED = 1, PRO_RELU = 3 };
 // epilogues: BIAS  Y = acc + bias
 //            RELUMASK  Y = acc where C > 0, else 0
 //            BIAS_SP   Y = acc + bias and Y2 = softplus(Y)            (layer output and activation)
 //            DSPMUL    Y = acc * softplus'(C)                          (normal sweep, adjoint to Z)
-//            BIAS_SP_SEED  as BIAS_SP and Y3 = softplus'(Y) colv      (top layer: seed of the sweep)
 //            TOPADJ    Hbar = acc + scale rowv[p] colv[m], Hdotbar = scale colv[m] with
 //                      C = Z, C2 = Hdot of the top layer: Y = Zbar, Y2 = Zdotbar
 //                      (the top trunk layer's adjoints, as the dual adjoint's epilogue)
-enum { EPI_BIAS = 0, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_BIAS_SP_SEED = 5,
-       EPI_TOPADJ = 6 };
+enum { EPI_BIAS = 0, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_TOPADJ = 6 };
 
 // Activation math of the network on the hardware exp2 / log2 / rcp units
 // (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once per element
@@ -99,10 +99,9 @@ struct GemmArgs {
     const float* C2;              // EPI_TOPADJ: [P][ldc]
     long ldc;
     float* Y; long ldy;
-    float* Y2;                    // EPI_BIAS_SP*, TOPADJ: second output, row stride ldy
-    float* Y3;                    // EPI_BIAS_SP_SEED: third output, row stride ldy
+    float* Y2;                    // EPI_BIAS_SP, TOPADJ: second output, row stride ldy
     const float* rowv;            // EPI_TOPADJ: [P] or null
-    const float* colv;            // EPI_BIAS_SP_SEED, TOPADJ: [M]
+    const float* colv;            // EPI_TOPADJ: [M]; PRO_SEED: [K]
     float scale;                  // EPI_TOPADJ
     long P; int M; int K;
     float beta;
@@ -184,13 +183,18 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         }
     };
     auto off = [](int row, int q) { return row * LW + 4 * q; };
-    auto store = [&]() {
+    auto store = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * 256;
             float4 v = ra[i];
             if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
+            }
+            if constexpr (PRO == PRO_SEED) {
+                const float* w = g.colv + k0 + (e % RPF) * 4;
+                v.x = sp_d1(v.x, g.beta) * w[0]; v.y = sp_d1(v.y, g.beta) * w[1];
+                v.z = sp_d1(v.z, g.beta) * w[2]; v.w = sp_d1(v.w, g.beta) * w[3];
             }
             *reinterpret_cast<float4*>(&sA[off(e / RPF, e % RPF)]) = v;
         }
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     // during this chunk's MFMAs, barrier
     load(0);
     for (int k0 = 0; k0 < g.K; k0 += BK) {
-        store();
+        store(k0);
         __syncthreads();
         if (k0 + BK < g.K) load(k0 + BK);
         compute();
@@ -281,10 +285,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         for (int b = 0; b < TM; ++b) {
             const int m = m0 + wm * (BM / WM) + b * 16 + li;
             if (m >= g.M) continue;
-            const float bias =
-                ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP || EPI == EPI_BIAS_SP_SEED) && g.bias) ? g.bias[m] : 0.0f;
+            const float bias = ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP) && g.bias) ? g.bias[m] : 0.0f;
             float cv = 0.0f;
-            if constexpr (EPI == EPI_BIAS_SP_SEED || EPI == EPI_TOPADJ) cv = g.colv[m];
+            if constexpr (EPI == EPI_TOPADJ) cv = g.colv[m];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
@@ -299,12 +302,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                     g.Y2[p * g.ldy + m] = sg * hdb;
                     continue;
                 }
-                if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP || EPI == EPI_BIAS_SP_SEED) y += bias;
+                if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
                 if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
                 if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
                 g.Y[p * g.ldy + m] = y;
-                if constexpr (EPI == EPI_BIAS_SP || EPI == EPI_BIAS_SP_SEED) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
-                if constexpr (EPI == EPI_BIAS_SP_SEED) g.Y3[p * g.ldy + m] = sp_d1(y, g.beta) * cv;
+                if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
             }
         }
 }
@@ -830,16 +832,6 @@ __global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict_
     }
 }
 
-// seed of the normal sweep: S[p][m] = sp'(Z[p][m]) * w[m]
-__global__ void k_seed(long n, int M, const float* __restrict__ Z, long ld, const float* __restrict__ w,
-                       float beta, float* __restrict__ S) {
-    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n * M) return;
-    const long p = o / M;
-    const int m = (int)(o % M);
-    S[p * ld + m] = sp_d1(Z[p * ld + m], beta) * w[m];
-}
-
 // head output adjoint: ybar3 = g_a a (1-a) with a recomputed; Ybar2 = ybar3 w relu'(Y2)
 __global__ __launch_bounds__(256) void k_head_out_bwd(long n, const float* __restrict__ Y2, long ld,
                                                       int M, const float* __restrict__ w,
@@ -1187,19 +1179,9 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
         }
         gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
                                        nullptr, 0, H[0]), cx);
-        // with a reserve the sweep buffers are free, so the top layer's epilogue
-        // also writes the sweep's seed sp'(Z_{L-1}) w_out
-        const bool seed_fused = keep && grad && l.L > 1;
-        for (int i = 1; i < l.L; ++i) {
-            GemmArgs a = ga(H[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W, beta, nullptr, 0, H[i]);
-            if (seed_fused && i == l.L - 1) {
-                a.Y3 = G[0];
-                a.colv = P + l.o_wout;
-                gemm<PRO_ID, EPI_BIAS_SP_SEED>(a, cx);
-            } else {
-                gemm<PRO_ID, EPI_BIAS_SP>(a, cx);
-            }
-        }
+        for (int i = 1; i < l.L; ++i)
+            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W,
+                                         beta, nullptr, 0, H[i]), cx);
         float* Ht = H[l.L - 1];
         float* Zt = Z[l.L - 1];
         if (sdf)
@@ -1213,21 +1195,24 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
                                l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
         if (grad) {
-            // adjoint of f w.r.t. Z_{L-1}: sp'(Z_{L-1}) w_out; then
-            // dZ_{i-1} = (dZ_i W_i) . sp'(Z_{i-1}) (epilogue) and dgamma = dZ_0 W_0
-            if (!seed_fused)
-                hipLaunchKernelGGL(k_seed, dim3(blocks(m * l.W)), dim3(256), 0, st, m, l.W, Zt, (long)l.W,
-                                   P + l.o_wout, beta, G[0]);
+            // adjoint of f w.r.t. Z_{L-1}: sp'(Z_{L-1}) w_out, formed as the first
+            // product's operand (PRO_SEED); then dZ_{i-1} = (dZ_i W_i) . sp'(Z_{i-1})
+            // (epilogue) and dgamma = dZ_0 W_0
             int cur_g = 0;
             for (int i = l.L - 1; i >= 0; --i) {
                 const int mout = i == 0 ? l.in0p : l.W;
+                const bool top = i == l.L - 1;
                 float* dst = G[cur_g ^ 1];
-                if (i > 0)
-                    gemm<PRO_ID, EPI_DSPMUL>(ga(G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W,
-                                                beta, Z[i - 1], l.W), cx);
-                else    // the product with W_0 stays FP32
-                    gemm32<PRO_ID, EPI_BIAS>(ga(G[cur_g], l.W, w.WT[0], l.W, nullptr, dst, mout, m, mout, l.W,
-                                                beta), cx);
+                GemmArgs a = ga(top ? Zt : G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta,
+                                i > 0 ? Z[i - 1] : nullptr, l.W);
+                a.colv = P + l.o_wout;
+                if (i > 0) {
+                    if (top) gemm<PRO_SEED, EPI_DSPMUL>(a, cx);
+                    else gemm<PRO_ID, EPI_DSPMUL>(a, cx);
+                } else {    // the product with W_0 stays FP32
+                    if (top) gemm32<PRO_SEED, EPI_BIAS>(a, cx);
+                    else gemm32<PRO_ID, EPI_BIAS>(a, cx);
+                }
                 cur_g ^= 1;
             }
             hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
