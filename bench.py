@@ -118,8 +118,8 @@ def cpu_baseline(cfg):
                    s=cfg.s, amp=1.0)
     n_pts = xyz.shape[0] * xyz.shape[1]
     rng = np.random.default_rng(0)
-    sel = np.arange(threads)                                   # measurements for point reductions
-    rays = np.arange(0, xyz.shape[0], xyz.shape[0] // 8)[:8]   # rays for frequency reductions
+    sel = np.arange(2 * threads)                               # measurements for point reductions
+    rays = np.arange(0, xyz.shape[0], xyz.shape[0] // 16)[:16]  # rays for frequency reductions
     q = xyz[rays].reshape(-1, 3)
     ap_sel = orc.Aperture(tx=tx[sel], f0=f0, df=df, n_freq=cfg.n_freq)
     ap_all = orc.Aperture(tx=tx, f0=f0, df=df, n_freq=cfg.n_freq)
@@ -128,18 +128,18 @@ def cpu_baseline(cfg):
     t0 = time.perf_counter()
     s = orc.render(ap_sel, xyz, F)                                        # forward, all points
     terms += n_pts * len(sel) * cfg.n_freq
-    z, P = orc.mf(ap_all, q, gs)                                          # MF, 8 rays
+    z, P = orc.mf(ap_all, q, gs)                                          # MF, sampled rays
     terms += q.shape[0] * tx.shape[0] * cfg.n_freq
     zz = rng.normal(size=n_pts) + 1j * rng.normal(size=n_pts)
     orc.mf_adjoint(ap_sel, xyz.reshape(-1, 3), zz, np.abs(zz), rng.normal(size=n_pts))
     terms += n_pts * len(sel) * cfg.n_freq                                # MF adjoint, all points
     Fr = orc.Fields(sdf=F.sdf[rays], grad=F.grad[rays], refl=F.refl[rays], s=cfg.s, amp=1.0)
-    orc.render_adjoint(ap_all, xyz[rays], Fr, gs)                         # adjoint, 8 rays
+    orc.render_adjoint(ap_all, xyz[rays], Fr, gs)                         # adjoint, sampled rays
     terms += q.shape[0] * tx.shape[0] * cfg.n_freq
     dt = time.perf_counter() - t0
     sample = (f"FP64 oracle (C + OpenMP, one sin/cos per term): signal tracing and matched-filter "
               f"adjoint over all {n_pts} points for {len(sel)} measurements, matched filter and "
-              f"signal-tracing adjoint over 8 whole rays ({q.shape[0]} points) for all "
+              f"signal-tracing adjoint over {len(rays)} whole rays ({q.shape[0]} points) for all "
               f"{tx.shape[0]} measurements; {terms:.3e} terms in {dt:.1f} s")
     return dict(value=terms / dt, unit="terms/s", cores=threads, kind="oracle", sample=sample)
 
