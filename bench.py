@@ -45,14 +45,15 @@ def network_digest() -> str:
 def mlp_backward_flop(cfg) -> int:
     """Algorithmic FLOP per point of the training backward of the network
     (2 per multiply-add, unpadded shapes): per trunk layer the tangent product
-    and two weight-gradient products, per layer above the first the two
-    adjoint products; the head's forward recompute, adjoint and weight
+    and two weight-gradient products, per layer above the first the adjoint
+    product H_bar = Z_bar W (the tangent's adjoint comes from the forward's
+    gradient sweep); the head's forward recompute, adjoint and weight
     gradients; the scalar output layers are not counted."""
     W, L, HW, HL = cfg.width, cfg.n_layers, cfg.head_width, cfg.head_layers
     fin = [3 + 6 * cfg.pe_octaves] + [W] * (L - 1)
     trunk = sum(2 * f * W for f in fin)                 # tangent
     trunk += sum(2 * 2 * f * W for f in fin)            # W_bar = Z_bar^T H + Zdot_bar^T Hdot
-    trunk += sum(2 * 2 * W * W for _ in fin[1:])        # H_bar, Hdot_bar of the layer below
+    trunk += sum(2 * W * W for _ in fin[1:])            # H_bar of the layer below
     hin = [W] + [HW] * (HL - 1)
     head = sum(2 * f * HW for f in hin)                 # forward recompute
     head += sum(2 * f * HW for f in hin)                # weight gradients
@@ -364,8 +365,8 @@ def main():
     achieved = cfg.n_pts * mlp_backward_flop(cfg) / t_nb / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
-                "kernel": "rfvr_mlp_backward_train (per layer: tangent, dual adjoint and two weight-gradient "
-                          "FP32 MFMA GEMMs, with the elementwise adjoints)",
+                "kernel": "rfvr_mlp_backward_train (per layer: tangent, adjoint and two weight-gradient "
+                          "FP32 MFMA GEMMs, elementwise work in their epilogues)",
                 "launch_ms": round(phases["mlp_bwd"], 3)}
     # the term kernels: signal tracing forward through its moments, priced at
     # the moment kernel's own work per (measurement, point) pair

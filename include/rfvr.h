@@ -258,11 +258,14 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
                       void* ws, size_t ws_bytes, void* stream);
 
 /* Training pair: the same two operations, sharing a caller-owned reserve
- * (device, 256-byte aligned, rfvr_mlp_reserve_bytes() bytes: every trunk
- * layer's pre-activation and activation, float32 [n][width] each).
- * rfvr_mlp_forward_train computes what rfvr_mlp_forward does and fills the
- * reserve; rfvr_mlp_backward_train reads it instead of recomputing the primal
- * layers, so it runs one matrix product per layer fewer.  The caller keeps
+ * (device, 256-byte aligned, rfvr_mlp_reserve_bytes() bytes: for every trunk
+ * layer its pre-activation, its activation and the gradient sweep's adjoint
+ * of f to the pre-activation, float32 [n][width] each).  rfvr_mlp_forward_train computes
+ * what rfvr_mlp_forward does (running the gradient sweep even when grad is
+ * NULL) and fills the reserve; rfvr_mlp_backward_train reads it instead of
+ * recomputing the primal layers and the adjoint of the tangent pass (the
+ * sweep's adjoint scaled by half_size), so per layer it runs two matrix
+ * products fewer than rfvr_mlp_backward.  The caller keeps
  * net (params unchanged), xyz and n the same between the two calls and does
  * not write the reserve in between; nothing checks this, and a mismatch gives
  * wrong gradients without an error.  Outputs agree with the plain calls to

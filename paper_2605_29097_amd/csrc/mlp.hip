@@ -61,7 +61,12 @@ enum { PRO_ID = 0, PRO_SEED = 1, PRO_RELU = 3 };
 //            TOPADJ    Hbar = acc + scale rowv[p] colv[m], Hdotbar = scale colv[m] with
 //                      C = Z, C2 = Hdot of the top layer: Y = Zbar, Y2 = Zdotbar
 //                      (the top trunk layer's adjoints, as the dual adjoint's epilogue)
-enum { EPI_BIAS = 0, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_TOPADJ = 6 };
+//            ADJ1      Hbar = acc, Hdotbar = scale C3 / sp'(C) with C = Z, C2 = Hdot and
+//                      C3 = the normal sweep's adjoint to Z of the layer below:
+//                      Y = Zbar = sp'(Z) Hbar + beta sigma(-beta Z) Hdot Hdotbar
+//                        = sp'(Z) Hbar + beta exp(-beta Z) Hdot scale C3
+//                      (exp(-beta Z) capped at 1e30, where Hdot C3 is below 1e-60)
+enum { EPI_BIAS = 0, EPI_RELUMASK = 2, EPI_BIAS_SP = 3, EPI_DSPMUL = 4, EPI_TOPADJ = 6, EPI_ADJ1 = 8 };
 
 // Activation math of the network on the hardware exp2 / log2 / rcp units
 // (v_exp_f32, v_log_f32, v_rcp_f32; ~1 ulp each): these run once per element
@@ -96,13 +101,14 @@ struct GemmArgs {
     const float* B; long ldb;
     const float* bias;            // EPI_BIAS*: [M] or null
     const float* C;               // EPI_RELUMASK / DSPMUL / TOPADJ: [P][ldc]
-    const float* C2;              // EPI_TOPADJ: [P][ldc]
+    const float* C2;              // EPI_TOPADJ, ADJ1: [P][ldc]
+    const float* C3;              // EPI_ADJ1: [P][ldc]
     long ldc;
     float* Y; long ldy;
     float* Y2;                    // EPI_BIAS_SP, TOPADJ: second output, row stride ldy
     const float* rowv;            // EPI_TOPADJ: [P] or null
     const float* colv;            // EPI_TOPADJ: [M]; PRO_SEED: [K]
-    float scale;                  // EPI_TOPADJ
+    float scale;                  // EPI_TOPADJ, ADJ1
     long P; int M; int K;
     float beta;
 };
@@ -304,6 +310,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 }
                 if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
                 if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
+                if constexpr (EPI == EPI_ADJ1) {
+                    // the sweep kept S = sp'(Z) G, so sigma(-beta Z) G = exp(-beta Z) S
+                    const long e = p * g.ldc + m;
+                    const float ex = fexp(-g.beta * g.C[e]);
+                    const float sg = __builtin_amdgcn_rcpf(1.0f + ex);
+                    g.Y[p * g.ldy + m] = sg * y + g.beta * fminf(ex, 1e30f) * g.C2[e] * (g.scale * g.C3[e]);
+                    continue;
+                }
                 if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
                 g.Y[p * g.ldy + m] = y;
                 if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
@@ -682,23 +696,29 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
 }
 
 // dst[m][k] (row stride k_real, k < k_real) (+)= sum_s part[s][m][k]
-__global__ void k_wg_reduce(const float* __restrict__ part, int n_split, int M, int Kout, int k_real,
-                            float* __restrict__ dst, int accumulate) {
-    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (long)M * k_real) return;
-    const int m = (int)(o / k_real), k = (int)(o % k_real);
-    // eight interleaved chains (t mod 8) keep eight loads in flight; the
-    // chains are combined in a fixed order, so the result is reproducible
-    const long stride = (long)M * Kout;
-    const float* q = part + (long)m * Kout + k;
+// fixed-order sum of partials t0 <= t < t1 with eight interleaved chains
+// (t mod 8), which keep eight loads in flight
+__device__ __forceinline__ float wg_chain_sum(const float* __restrict__ q, long stride, int t0, int t1) {
     float c[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    int t = 0;
-    for (; t + 8 <= n_split; t += 8) {
+    int t = t0;
+    for (; t + 8 <= t1; t += 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) c[u] += q[(long)(t + u) * stride];
     }
-    for (; t < n_split; ++t) c[t & 7] += q[(long)t * stride];
-    const float s = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+    for (; t < t1; ++t) c[(t - t0) & 7] += q[(long)t * stride];
+    return ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+}
+
+// dst (+)= sum_{t < n1} part[t] + scale2 sum_{n1 <= t < n_split} part[t]
+__global__ void k_wg_reduce(const float* __restrict__ part, int n_split, int n1, float scale2, int M, int Kout,
+                            int k_real, float* __restrict__ dst, int accumulate) {
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (long)M * k_real) return;
+    const int m = (int)(o / k_real), k = (int)(o % k_real);
+    const long stride = (long)M * Kout;
+    const float* q = part + (long)m * Kout + k;
+    float s = wg_chain_sum(q, stride, 0, n1);
+    if (n1 < n_split) s = __builtin_fmaf(scale2, wg_chain_sum(q, stride, n1, n_split), s);
     dst[o] = accumulate ? dst[o] + s : s;
 }
 
@@ -1083,9 +1103,9 @@ void wgrad(const float* A, long lda, int M, const float* B, const float* B2, lon
 }
 
 void wg_reduce(const float* part, int n_split, int M, int Kout, int k_real, float* dst, int acc,
-               hipStream_t st) {
-    hipLaunchKernelGGL(k_wg_reduce, dim3(blocks((long)M * k_real)), dim3(256), 0, st, part, n_split, M,
-                       Kout, k_real, dst, acc);
+               hipStream_t st, int n1 = -1, float scale2 = 1.0f) {
+    hipLaunchKernelGGL(k_wg_reduce, dim3(blocks((long)M * k_real)), dim3(256), 0, st, part, n_split,
+                       n1 < 0 ? n_split : n1, scale2, M, Kout, k_real, dst, acc);
 }
 
 void colsum(const float* X, const float* X2, const float* s, long ldx, long P, int M, int mode,
@@ -1120,13 +1140,15 @@ size_t bwd_bytes(const Layout& l, long n, bool keep) {
            align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
 }
 
-// --- reserve of the training pair: Z_i [n][W] for every layer, then H_i -------
+// --- reserve of the training pair, [n][W] per layer: Z_i, H_i, and the normal
+// sweep's adjoint S_i = df/dZ_i --------------------------------------------------
 size_t reserve_layer_bytes(const Layout& l, long n) { return align256(sizeof(float) * (size_t)n * l.W); }
-size_t reserve_bytes(const Layout& l, long n) { return 2 * (size_t)l.L * reserve_layer_bytes(l, n); }
+size_t reserve_bytes(const Layout& l, long n) { return 3 * (size_t)l.L * reserve_layer_bytes(l, n); }
 float* reserve_z(void* r, const Layout& l, long n, int i) {
     return reinterpret_cast<float*>(static_cast<char*>(r) + (size_t)i * reserve_layer_bytes(l, n));
 }
 float* reserve_h(void* r, const Layout& l, long n, int i) { return reserve_z(r, l, n, l.L + i); }
+float* reserve_s(void* r, const Layout& l, long n, int i) { return reserve_z(r, l, n, 2 * l.L + i); }
 
 int check_buffers(void* ws, size_t ws_bytes, size_t need, void* reserve, size_t reserve_bytes_, size_t rneed) {
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
@@ -1194,16 +1216,20 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                                l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
-        if (grad) {
-            // adjoint of f w.r.t. Z_{L-1}: sp'(Z_{L-1}) w_out, formed as the first
-            // product's operand (PRO_SEED); then dZ_{i-1} = (dZ_i W_i) . sp'(Z_{i-1})
-            // (epilogue) and dgamma = dZ_0 W_0
+        if (grad || keep) {
+            // adjoint of f w.r.t. Z_{L-1}: S_{L-1} = sp'(Z_{L-1}) w_out, formed as the
+            // first product's operand (PRO_SEED); then S_{i-1} = (S_i W_i) . sp'(Z_{i-1})
+            // (epilogue), and dgamma = S_0 W_0.  The training forward keeps S_i
+            // (i < L-1) in the reserve: scaled by half_size, S_i and S_i / sp'(Z_i)
+            // are the backward's adjoints of the tangent pass to Zdot_i and Hdot_i,
+            // so the backward does not recompute them.
             int cur_g = 0;
             for (int i = l.L - 1; i >= 0; --i) {
                 const int mout = i == 0 ? l.in0p : l.W;
                 const bool top = i == l.L - 1;
-                float* dst = G[cur_g ^ 1];
-                GemmArgs a = ga(top ? Zt : G[cur_g], l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta,
+                const float* src = top ? Zt : (keep ? reserve_s(reserve, l, n, i) + c0 * l.W : G[cur_g]);
+                float* dst = (keep && i > 0) ? reserve_s(reserve, l, n, i - 1) + c0 * l.W : G[cur_g ^ 1];
+                GemmArgs a = ga(src, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta,
                                 i > 0 ? Z[i - 1] : nullptr, l.W);
                 a.colv = P + l.o_wout;
                 if (i > 0) {
@@ -1215,9 +1241,10 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
                 }
                 cur_g ^= 1;
             }
-            hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
-                               net->centre[1], net->centre[2], inv_half, net->pe_octaves, G[cur_g],
-                               l.in0p, grad + 3 * c0);
+            if (grad)
+                hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
+                                   net->centre[1], net->centre[2], inv_half, net->pe_octaves, G[cur_g],
+                                   l.in0p, grad + 3 * c0);
         }
         if ((rc = hip_status(hipGetLastError(), "mlp forward"))) return rc;
     }
@@ -1340,7 +1367,10 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
         float *Zb_c = Zb, *Zdb_c = Zdb, *Zb_n = Hb, *Zdb_n = Hdb;
         for (int i = l.L - 1; i >= 0; --i) {
             float* Zb = Zb_c;
-            float* Zdb = Zdb_c;
+            // Zdot_bar_i: from the dual adjoint (plain), or half S_i kept by the
+            // training forward (the top layer's from the top-adjoint epilogue)
+            const bool kept = keep && i < l.L - 1;
+            const float* Zdb = kept ? reserve_s(reserve, l, n, i) + c0 * l.W : Zdb_c;
             const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
             if (i == 0) {
                 wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32, bpart);
@@ -1351,10 +1381,18 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                 wgrad<PRO_ID>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta,
                               part + (size_t)kWgSplits * l.W * finp, cx);
             }
-            wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st);
+            wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st, kWgSplits, kept ? half : 1.0f);
             hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
                                GP + l.ob[i], acc);
-            if (i > 0) {
+            if (i > 0 && keep) {
+                // Zbar_{i-1} from Hbar_{i-1} = Zbar_i W_i and Hdotbar_{i-1} = half S_{i-1} / sp'(Z_{i-1})
+                GemmArgs a = ga(Zb, l.W, w.WT[i], l.W, nullptr, Zb_n, l.W, m, l.W, l.W, beta, Z[i - 1], l.W);
+                a.C2 = Hd[i - 1];
+                a.C3 = reserve_s(reserve, l, n, i - 1) + c0 * l.W;
+                a.scale = half;
+                gemm<PRO_ID, EPI_ADJ1>(a, cx);
+                float* t = Zb_c; Zb_c = Zb_n; Zb_n = t;
+            } else if (i > 0) {
                 gemm_dual<EPI2_ADJ>(da(Zb, Zdb, l.W, w.WT[i], l.W, nullptr, Z[i - 1], Hd[i - 1], Zb_n, Zdb_n, nullptr,
                                        l.W, m, l.W, l.W, beta), cx.mm, st);
                 float* t = Zb_c; Zb_c = Zb_n; Zb_n = t;
