@@ -15,8 +15,11 @@
 //   Zdot_bar = sp'(Z) Hdot_bar,  Z_bar = sp'(Z) H_bar + sp''(Z) Zdot Hdot_bar,
 //   W_bar = Z_bar^T H + Zdot_bar^T Hdot,  H_bar = Z_bar W,  Hdot_bar = Zdot_bar W,
 // where sp''(Z) Zdot = beta sigma(-beta Z) Hdot, so Zdot itself is never stored.
-// The training pair of calls keeps the forward's (Z, H) of every layer in a
-// caller-owned reserve; the backward then runs only the tangent GEMM per layer.
+// The training pair of calls keeps the forward's (Z, H) of every layer and the
+// sweep's adjoint S = sp'(Z) G^(l+1) to every pre-activation in a caller-owned
+// reserve; the backward then runs only the tangent GEMM per layer, and takes
+// the tangent pass's adjoints from S (Zdot_bar = half_size S), so one adjoint
+// GEMM per layer remains.
 // Weight gradients reduce over points in fixed splits (no atomics).
 #include "rfvr_impl.hpp"
 
@@ -150,25 +153,6 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // the top-adjoint epilogue reads two operands that do not depend on the
-    // product: fetch them before the (short, K = head width) main loop
-    float cz[EPI == EPI_TOPADJ ? TP : 1][EPI == EPI_TOPADJ ? TM : 1][4];
-    float chd[EPI == EPI_TOPADJ ? TP : 1][EPI == EPI_TOPADJ ? TM : 1][4];
-    if constexpr (EPI == EPI_TOPADJ) {
-#pragma unroll
-        for (int a = 0; a < TP; ++a)
-#pragma unroll
-            for (int b = 0; b < TM; ++b) {
-                const int m = m0 + wm * (BM / WM) + b * 16 + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
-                    const bool in = m < g.M && p < g.P;
-                    cz[a][b][v] = in ? g.C[p * g.ldc + m] : 0.0f;
-                    chd[a][b][v] = in ? g.C2[p * g.ldc + m] : 0.0f;
-                }
-            }
-    }
     float4 ra[NA], rb[NB];
     auto load = [&](int k0) {
 #pragma unroll
@@ -285,44 +269,77 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         compute();
         __syncthreads();
     }
+    // Epilogue, one 16-row group at a time.  The group's operand loads use
+    // indices clamped into the arrays, so they carry no per-element branch and
+    // are all in flight before the first is used; only the stores are guarded,
+    // and tiles that lie wholly inside the output take a path without guards.
+    constexpr int NC = (EPI == EPI_ADJ1) ? 3 : (EPI == EPI_TOPADJ) ? 2 : (EPI == EPI_DSPMUL || EPI == EPI_RELUMASK) ? 1 : 0;
+    auto epilogue = [&](auto guarded) {
+        constexpr bool GUARD = decltype(guarded)::value;
 #pragma unroll
-    for (int a = 0; a < TP; ++a)
-#pragma unroll
-        for (int b = 0; b < TM; ++b) {
-            const int m = m0 + wm * (BM / WM) + b * 16 + li;
-            if (m >= g.M) continue;
-            const float bias = ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP) && g.bias) ? g.bias[m] : 0.0f;
-            float cv = 0.0f;
-            if constexpr (EPI == EPI_TOPADJ) cv = g.colv[m];
+        for (int a = 0; a < TP; ++a) {
+            long pr[4];
+            bool pin[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
-                if (p >= g.P) continue;
-                float y = acc[a][b][v];
-                if constexpr (EPI == EPI_TOPADJ) {
-                    const float hb = g.rowv ? __builtin_fmaf(g.scale * g.rowv[p], cv, y) : y;
-                    const float hdb = g.scale * cv;
-                    const float z = cz[a][b][v], hd = chd[a][b][v];
-                    const float sg = fsig(g.beta * z);
-                    g.Y[p * g.ldy + m] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
-                    g.Y2[p * g.ldy + m] = sg * hdb;
-                    continue;
+                pin[v] = !GUARD || p < g.P;
+                pr[v] = pin[v] ? p : g.P - 1;
+            }
+            float cl[NC ? NC : 1][TM][4];
+            if constexpr (NC > 0) {
+#pragma unroll
+                for (int b = 0; b < TM; ++b) {
+                    const int m = m0 + wm * (BM / WM) + b * 16 + li;
+                    const int mc = GUARD ? min(m, g.M - 1) : m;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const long e = pr[v] * g.ldc + mc;
+                        cl[0][b][v] = g.C[e];
+                        if constexpr (NC >= 2) cl[1][b][v] = g.C2[e];
+                        if constexpr (NC >= 3) cl[2][b][v] = g.C3[e];
+                    }
                 }
-                if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
-                if constexpr (EPI == EPI_RELUMASK) y = g.C[p * g.ldc + m] > 0.0f ? y : 0.0f;
-                if constexpr (EPI == EPI_ADJ1) {
-                    // the sweep kept S = sp'(Z) G, so sigma(-beta Z) G = exp(-beta Z) S
-                    const long e = p * g.ldc + m;
-                    const float ex = fexp(-g.beta * g.C[e]);
-                    const float sg = __builtin_amdgcn_rcpf(1.0f + ex);
-                    g.Y[p * g.ldy + m] = sg * y + g.beta * fminf(ex, 1e30f) * g.C2[e] * (g.scale * g.C3[e]);
-                    continue;
+            }
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const int m = m0 + wm * (BM / WM) + b * 16 + li;
+                if (GUARD && m >= g.M) continue;
+                const float bias = ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP) && g.bias) ? g.bias[m] : 0.0f;
+                float cv = 0.0f;
+                if constexpr (EPI == EPI_TOPADJ) cv = g.colv[m];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (GUARD && !pin[v]) continue;
+                    const long p = pr[v];
+                    float y = acc[a][b][v];
+                    if constexpr (EPI == EPI_TOPADJ) {
+                        const float hb = g.rowv ? __builtin_fmaf(g.scale * g.rowv[p], cv, y) : y;
+                        const float hdb = g.scale * cv;
+                        const float z = cl[0][b][v], hd = cl[1][b][v];
+                        const float sg = fsig(g.beta * z);
+                        g.Y[p * g.ldy + m] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
+                        g.Y2[p * g.ldy + m] = sg * hdb;
+                        continue;
+                    }
+                    if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
+                    if constexpr (EPI == EPI_RELUMASK) y = cl[0][b][v] > 0.0f ? y : 0.0f;
+                    if constexpr (EPI == EPI_ADJ1) {
+                        // the sweep kept S = sp'(Z) G, so sigma(-beta Z) G = exp(-beta Z) S
+                        const float ex = fexp(-g.beta * cl[0][b][v]);
+                        const float sg = __builtin_amdgcn_rcpf(1.0f + ex);
+                        g.Y[p * g.ldy + m] = sg * y + g.beta * fminf(ex, 1e30f) * cl[1][b][v] * (g.scale * cl[2][b][v]);
+                        continue;
+                    }
+                    if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(cl[0][b][v], g.beta);
+                    g.Y[p * g.ldy + m] = y;
+                    if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
                 }
-                if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(g.C[p * g.ldc + m], g.beta);
-                g.Y[p * g.ldy + m] = y;
-                if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
             }
         }
+    };
+    if (p0 + BP <= g.P && m0 + BM <= g.M) epilogue(std::false_type{});
+    else epilogue(std::true_type{});
 }
 
 // ----------------------------------------------------------------------------
