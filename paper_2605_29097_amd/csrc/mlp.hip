@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             for (int a = 0; a < TP; ++a)
 #pragma unroll
                 for (int b = 0; b < TM; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[b], af[a], acc[a][b], 0, 0, 0);
         } else if constexpr (MM == MM_BF16X3) {
             bf16x8 ab[TP], as[TP], bb[TM], bs[TM];
 #pragma unroll
@@ -235,9 +235,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             for (int a = 0; a < TP; ++a)
 #pragma unroll
                 for (int b = 0; b < TM; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[a], bb[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[a], bs[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[a], bb[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb[b], as[a], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bs[b], ab[a], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb[b], ab[a], acc[a][b], 0, 0, 0);
                 }
         } else {
 #pragma unroll
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                     for (int a = 0; a < TP; ++a)
 #pragma unroll
                         for (int b = 0; b < TM; ++b)
-                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[b][s], af[a][s], acc[a][b], 0, 0, 0);
             }
         }
     };
@@ -269,76 +269,100 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         compute();
         __syncthreads();
     }
-    // Epilogue, one 16-row group at a time.  The group's operand loads use
-    // indices clamped into the arrays, so they carry no per-element branch and
-    // are all in flight before the first is used; only the stores are guarded,
-    // and tiles that lie wholly inside the output take a path without guards.
+    // Epilogue.  The weights are the MFMA's first operand, so a lane's four
+    // accumulator values acc[a][b][0..3] are four consecutive outputs
+    // m = m0 + wm (BM/WM) + 16 b + 4 lg + v of one point p = p0 + wp (BP/WP)
+    // + 16 a + li: one float4 of a row-major [P][ld] array.  Tiles wholly inside
+    // the output (with 16-byte aligned rows) load and store float4s without
+    // guards; the others clamp their loads into the arrays and guard each
+    // store.  A 16-point group's loads are all issued before the first is used.
     constexpr int NC = (EPI == EPI_ADJ1) ? 3 : (EPI == EPI_TOPADJ) ? 2 : (EPI == EPI_DSPMUL || EPI == EPI_RELUMASK) ? 1 : 0;
     auto epilogue = [&](auto guarded) {
         constexpr bool GUARD = decltype(guarded)::value;
-#pragma unroll
-        for (int a = 0; a < TP; ++a) {
-            long pr[4];
-            bool pin[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const long p = p0 + wp * (BP / WP) + a * 16 + lg * 4 + v;
-                pin[v] = !GUARD || p < g.P;
-                pr[v] = pin[v] ? p : g.P - 1;
-            }
-            float cl[NC ? NC : 1][TM][4];
-            if constexpr (NC > 0) {
-#pragma unroll
-                for (int b = 0; b < TM; ++b) {
-                    const int m = m0 + wm * (BM / WM) + b * 16 + li;
-                    const int mc = GUARD ? min(m, g.M - 1) : m;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const long e = pr[v] * g.ldc + mc;
-                        cl[0][b][v] = g.C[e];
-                        if constexpr (NC >= 2) cl[1][b][v] = g.C2[e];
-                        if constexpr (NC >= 3) cl[2][b][v] = g.C3[e];
-                    }
-                }
-            }
+        // per-output vector (bias, or the top adjoint's column vector): the same
+        // 16 values for every point group of the lane, loaded once
+        constexpr bool VEC = (EPI == EPI_BIAS || EPI == EPI_BIAS_SP || EPI == EPI_TOPADJ);
+        const float* vsrc = (EPI == EPI_TOPADJ) ? g.colv : g.bias;
+        floatx4 vv[VEC ? TM : 1];
+        if constexpr (VEC) {
 #pragma unroll
             for (int b = 0; b < TM; ++b) {
-                const int m = m0 + wm * (BM / WM) + b * 16 + li;
-                if (GUARD && m >= g.M) continue;
-                const float bias = ((EPI == EPI_BIAS || EPI == EPI_BIAS_SP) && g.bias) ? g.bias[m] : 0.0f;
-                float cv = 0.0f;
-                if constexpr (EPI == EPI_TOPADJ) cv = g.colv[m];
+                const int mb = m0 + wm * (BM / WM) + b * 16 + lg * 4;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    vv[b][v] = vsrc ? vsrc[GUARD ? min(mb + v, g.M - 1) : mb + v] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < TP; ++a) {
+            const long p = p0 + wp * (BP / WP) + a * 16 + li;
+            const bool pin = !GUARD || p < g.P;
+            const long pr = pin ? p : g.P - 1;
+            floatx4 cl[NC ? NC : 1][TM];
+            const float* src[3] = {g.C, g.C2, g.C3};
+            if constexpr (NC > 0 && !GUARD) {
+#pragma unroll
+                for (int b = 0; b < TM; ++b) {
+                    const int mb = m0 + wm * (BM / WM) + b * 16 + lg * 4;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        cl[c][b] = *reinterpret_cast<const floatx4*>(src[c] + pr * g.ldc + mb);
+                }
+            }
+            float rv = 0.0f;
+            if constexpr (EPI == EPI_TOPADJ) rv = g.rowv ? g.scale * g.rowv[pr] : 0.0f;
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const int mb = m0 + wm * (BM / WM) + b * 16 + lg * 4;
+                if constexpr (NC > 0 && GUARD) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) cl[c][b][v] = src[c][pr * g.ldc + min(mb + v, g.M - 1)];
+                }
+                floatx4 y = acc[a][b], y2 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    if (GUARD && !pin[v]) continue;
-                    const long p = pr[v];
-                    float y = acc[a][b][v];
+                    if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y[v] += vv[b][v];
+                    if constexpr (EPI == EPI_BIAS_SP) y2[v] = sp_f(y[v], g.beta);
+                    if constexpr (EPI == EPI_RELUMASK) y[v] = cl[0][b][v] > 0.0f ? y[v] : 0.0f;
+                    if constexpr (EPI == EPI_DSPMUL) y[v] *= sp_d1(cl[0][b][v], g.beta);
                     if constexpr (EPI == EPI_TOPADJ) {
-                        const float hb = g.rowv ? __builtin_fmaf(g.scale * g.rowv[p], cv, y) : y;
+                        const float cv = vv[b][v];
+                        const float hb = __builtin_fmaf(rv, cv, y[v]);
                         const float hdb = g.scale * cv;
-                        const float z = cl[0][b][v], hd = cl[1][b][v];
-                        const float sg = fsig(g.beta * z);
-                        g.Y[p * g.ldy + m] = sg * hb + g.beta * (1.0f - sg) * hd * hdb;
-                        g.Y2[p * g.ldy + m] = sg * hdb;
-                        continue;
+                        const float sg = fsig(g.beta * cl[0][b][v]);
+                        y[v] = sg * hb + g.beta * (1.0f - sg) * cl[1][b][v] * hdb;
+                        y2[v] = sg * hdb;
                     }
-                    if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y += bias;
-                    if constexpr (EPI == EPI_RELUMASK) y = cl[0][b][v] > 0.0f ? y : 0.0f;
                     if constexpr (EPI == EPI_ADJ1) {
                         // the sweep kept S = sp'(Z) G, so sigma(-beta Z) G = exp(-beta Z) S
                         const float ex = fexp(-g.beta * cl[0][b][v]);
                         const float sg = __builtin_amdgcn_rcpf(1.0f + ex);
-                        g.Y[p * g.ldy + m] = sg * y + g.beta * fminf(ex, 1e30f) * cl[1][b][v] * (g.scale * cl[2][b][v]);
-                        continue;
+                        y[v] = sg * y[v] + g.beta * fminf(ex, 1e30f) * cl[1][b][v] * (g.scale * cl[2][b][v]);
                     }
-                    if constexpr (EPI == EPI_DSPMUL) y *= sp_d1(cl[0][b][v], g.beta);
-                    g.Y[p * g.ldy + m] = y;
-                    if constexpr (EPI == EPI_BIAS_SP) g.Y2[p * g.ldy + m] = sp_f(y, g.beta);
                 }
+                constexpr bool TWO = (EPI == EPI_BIAS_SP || EPI == EPI_TOPADJ);
+                if constexpr (!GUARD) {
+                    *reinterpret_cast<floatx4*>(g.Y + p * g.ldy + mb) = y;
+                    if constexpr (TWO) *reinterpret_cast<floatx4*>(g.Y2 + p * g.ldy + mb) = y2;
+                } else if (pin) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (mb + v >= g.M) continue;
+                        g.Y[p * g.ldy + mb + v] = y[v];
+                        if constexpr (TWO) g.Y2[p * g.ldy + mb + v] = y2[v];
+                    }
+                }
+                if constexpr (GUARD && NC >= 2) __builtin_amdgcn_sched_barrier(0);
             }
+            // the next group's loads stay behind this group's stores
+            if constexpr (NC >= 2) __builtin_amdgcn_sched_barrier(0);
         }
     };
-    if (p0 + BP <= g.P && m0 + BM <= g.M) epilogue(std::false_type{});
+    const bool aligned = (((g.ldy | g.ldc) & 3) == 0) &&
+                         (((uintptr_t)g.Y | (uintptr_t)g.Y2 | (uintptr_t)g.C | (uintptr_t)g.C2 | (uintptr_t)g.C3) & 15) == 0;
+    if (aligned && p0 + BP <= g.P && m0 + BM <= g.M) epilogue(std::false_type{});
     else epilogue(std::true_type{});
 }
 
