@@ -57,10 +57,12 @@ extern "C" {
  * By default the four term entry points (render forward / backward, matched
  * filter forward / backward) evaluate the sums through Chebyshev moments of
  * each measurement's range interval over the launch's bounding box: the
- * phasor exp(-+j 2 pi (f0 + n df) 2r/c) is expanded in Chebyshev polynomials
- * of the normalised range (Jacobi-Anger expansion), cut at the smallest order
- * K in {24, 32, 40, 48, 64} whose truncation bound 2 (z/2)^K / K! (z = 2 pi
- * (n_freq - 1) df 2h/c, h the half-width of the widest interval) is below
+ * phasor exp(-+j 2 pi (f0 + n df) 2r/c) is split at the centre of the band
+ * and its offset from there, exp(-+j 2 pi (n - (n_freq-1)/2) df 2r/c), is
+ * expanded in Chebyshev polynomials of the normalised range (Jacobi-Anger
+ * expansion), cut at the smallest order K in {24, 28, 32, 40, 48, 64} whose
+ * truncation bound 2 (z/2)^K / K! / (1 - z/(2K+2)) (z = 2 pi
+ * ((n_freq - 1)/2) df 2h/c, h the half-width of the widest interval) is below
  * 1e-7 of the sum of the term magnitudes.  The choice is made on the device
  * for every call; when no K qualifies (a range spread too wide for the band)
  * or K is not below n_freq, the per-frequency kernels run, which

@@ -5,25 +5,30 @@
 //
 // A pair's phasor at frequency n is exp(s j 2 pi (K0 + n Kd) r), s = -1 for
 // the reductions over points (render forward, filter adjoint) and +1 for the
-// reductions over frequencies (filter forward, render adjoint).  Every point
-// of a launch lies in an axis-aligned box, so for measurement i its range r
-// lies in [rc_i - h_i, rc_i + h_i] (distances from the transmitter to the
-// box).  With x = (r - rc) / h in [-1, 1] and z_n = 2 pi n Kd h,
-//   exp(s j 2 pi n Kd r) = exp(s j 2 pi n Kd rc) exp(s j z_n x)
+// reductions over frequencies (filter forward, render adjoint).  It is split at
+// the centre of the band, Kc = K0 + nc Kd with nc = (n_freq - 1) / 2, and
+// dn = n - nc in [-nc, nc].  Every point of a launch lies in an axis-aligned
+// box, so for measurement i its range r lies in [rc_i - h_i, rc_i + h_i]
+// (distances from the transmitter to the box).  With x = (r - rc) / h in
+// [-1, 1] and z_n = 2 pi dn Kd h (of either sign),
+//   exp(s j 2 pi dn Kd r) = exp(s j 2 pi dn Kd rc) exp(s j z_n x)
 // and the Jacobi-Anger expansion
 //   exp(s j z x) = sum_k eps_k (s j)^k J_k(z) T_k(x),  eps_0 = 1, eps_k = 2,
-// (T_k Chebyshev polynomials, J_k Bessel functions of the first kind) turns
+// (T_k Chebyshev polynomials, J_k Bessel functions of the first kind, with
+// J_k(-z) = (-1)^k J_k(z)) turns
 //   * a reduction over points into K moments per measurement,
-//       M_ik = sum_j a_ij exp(-j 2 pi K0 r_ij) T_k(x_ij),
-//       out[i][n] = exp(-j 2 pi n Kd rc_i) sum_k eps_k (-j)^k J_k(z_in) M_ik;
+//       M_ik = sum_j a_ij exp(-j 2 pi Kc r_ij) T_k(x_ij),
+//       out[i][n] = exp(-j 2 pi dn Kd rc_i) sum_k eps_k (-j)^k J_k(z_in) M_ik;
 //   * a reduction over frequencies into a Chebyshev series per measurement,
-//       B_ik = eps_k j^k sum_n g[i][n] exp(+j 2 pi n Kd rc_i) J_k(z_in),
-//       sum_n g[i][n] exp(+j 2 pi (K0 + n Kd) r) = exp(+j 2 pi K0 r) sum_k B_ik T_k(x),
+//       B_ik = eps_k j^k sum_n g[i][n] exp(+j 2 pi dn Kd rc_i) J_k(z_in),
+//       sum_n g[i][n] exp(+j 2 pi (K0 + n Kd) r) = exp(+j 2 pi Kc r) sum_k B_ik T_k(x),
 //     evaluated per pair with T_k from their three-term recurrence.
-// Since |T_k| <= 1 on [-1, 1] and |J_k(z)| <= (z/2)^k / k!, cutting the series
-// at K changes each output by at most 2 (z/2)^K / K! / (1 - z / (2K + 2)) times
-// the sum of the magnitudes of its terms' weights.  A one-block plan kernel
-// takes the largest z of the launch and picks the smallest K of kChebKs whose
+// Centring the band halves the largest |z| (against splitting at f0), and with
+// it the number of orders the series needs.  Since |T_k| <= 1 on [-1, 1] and
+// |J_k(z)| <= (|z|/2)^k / k!, cutting the series at K changes each output by at
+// most 2 (z/2)^K / K! / (1 - z / (2K + 2)) (z = max |z_n|) times the sum of the
+// magnitudes of its terms' weights.  A one-block plan kernel takes the largest
+// z of the launch and picks the smallest K of kChebKs whose
 // bound is below kChebTol, or 0 (the per-frequency kernels) when none is (a
 // wide range spread) or K is not below the number of frequencies.  The choice
 // stays on the device: every candidate kernel is launched and all but the
@@ -31,8 +36,8 @@
 //
 // Per pair both cost 3 FP32 operations per order (recurrence of T_k and a
 // complex multiply-add by a real), against 4 per frequency in the
-// per-frequency kernels; the FP64 range and the one phasor exp(-+j 2 pi K0 r)
-// (hardware sin / cos of the FP64-reduced phase) are set up once per pair.  Bessel values come from Miller's backward
+// per-frequency kernels; the FP64 range and the one phasor exp(-+j 2 pi Kc r)
+// (hardware sin / cos of the FP64-reduced phase, at Kc) are set up once per pair.  Bessel values come from Miller's backward
 // recurrence in FP64 (first pass: normalisation J_0 + 2 sum J_2m = 1 and the
 // number of rescalings; second pass: the values, consumed as produced).
 #include <cmath>
@@ -41,7 +46,7 @@
 
 namespace rfvr {
 
-constexpr int kChebKs[] = {24, 32, 40, 48, 64};
+constexpr int kChebKs[] = {24, 28, 32, 40, 48, 64};
 constexpr int kChebKMax = kChebMaxOrder;
 constexpr double kChebTol = 1e-7;
 
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(256) void k_cheb_plan(const float* __restrict__ par
         m.inv_h = 1.0 / m.h;
         m.pad = 0.0;
         meas[i] = m;
-        zl = fmax(zl, 6.283185307179586 * (double)(n_freq - 1) * Kd * m.h);
+        zl = fmax(zl, 6.283185307179586 * (0.5 * (double)(n_freq - 1)) * Kd * m.h);
     }
     sz[t] = zl;
     __syncthreads();
@@ -184,7 +189,7 @@ __device__ __forceinline__ int miller_start(int nk, double z) {
 }
 
 template <class Visit>
-__device__ __forceinline__ void bessel_j_desc(double z, int nk, Visit visit) {
+__device__ __forceinline__ void bessel_j_desc_pos(double z, int nk, Visit visit) {
     if (!(z > 1e-300)) {
         for (int k = nk - 1; k >= 1; --k) visit(k, 0.0);
         visit(0, 1.0);
@@ -220,6 +225,16 @@ __device__ __forceinline__ void bessel_j_desc(double z, int nk, Visit visit) {
     }
 }
 
+// J_k(z) for z of either sign: J_k(-z) = (-1)^k J_k(z)
+template <class Visit>
+__device__ __forceinline__ void bessel_j_desc(double z, int nk, Visit visit) {
+    if (z >= 0.0) {
+        bessel_j_desc_pos(z, nk, visit);
+    } else {
+        bessel_j_desc_pos(-z, nk, [&](int k, double J) { visit(k, (k & 1) ? -J : J); });
+    }
+}
+
 // ---------------------------------------------------------------------------
 // moments over points: signal tracing forward (KIND 0) and filter adjoint
 // (KIND 1).  Lane = measurement; the lanes of a work-group walk the same point
@@ -230,7 +245,7 @@ __device__ __forceinline__ void bessel_j_desc(double z, int nk, Visit visit) {
 template <int K, int KIND, int SPEC>
 __global__ __launch_bounds__(256) void k_cheb_points(
     int n_meas, const AntRec* __restrict__ ant, const MeasCheb* __restrict__ meas,
-    const ChebPlan* __restrict__ plan, double K0, const void* __restrict__ recs_v, long n_pts,
+    const ChebPlan* __restrict__ plan, double Kc, const void* __restrict__ recs_v, long n_pts,
     long pts_per_split, int n_split, int gx, float2* __restrict__ partial) {
     if (plan->K != K) return;
     constexpr int TILE = 64;
@@ -292,8 +307,8 @@ __global__ __launch_bounds__(256) void k_cheb_points(
                 cr = Q.hr;
                 ci = Q.hi;
             }
-            // weight times exp(-j 2 pi K0 r)
-            const float t0 = frac_rev(r * K0);
+            // weight times exp(-j 2 pi Kc r)
+            const float t0 = frac_rev(r * Kc);
             const float c0 = cos_rev(t0), s0 = sin_rev(t0);
             const float br = __builtin_fmaf(cr, c0, ci * s0);
             const float bi = __builtin_fmaf(ci, c0, -cr * s0);
@@ -340,7 +355,7 @@ __global__ void k_cheb_moment_sum(const float2* __restrict__ partial, int n_spli
     M[o] = make_float2((float)sr, (float)si);
 }
 
-// out[i][n] (+)= exp(-j 2 pi n Kd rc_i) sum_k eps_k (-j)^k J_k(z_in) M_ik
+// out[i][n] (+)= exp(-j 2 pi dn Kd rc_i) sum_k eps_k (-j)^k J_k(z_in) M_ik
 __global__ __launch_bounds__(256) void k_cheb_out(const ChebPlan* __restrict__ plan,
                                                   const MeasCheb* __restrict__ meas,
                                                   const float2* __restrict__ M, int n_meas, int n_freq,
@@ -351,7 +366,8 @@ __global__ __launch_bounds__(256) void k_cheb_out(const ChebPlan* __restrict__ p
     if (o >= (long)n_meas * n_freq) return;
     const int i = (int)(o / n_freq), n = (int)(o % n_freq);
     const MeasCheb mc = meas[i];
-    const double z = 6.283185307179586 * (double)n * Kd * mc.h;
+    const double dn = (double)n - 0.5 * (double)(n_freq - 1);
+    const double z = 6.283185307179586 * dn * Kd * mc.h;
     const float2* Mi = M + (size_t)i * kChebKMax;
     double ar = 0.0, ai = 0.0;
     bessel_j_desc(z, K, [&](int k, double J) {
@@ -369,7 +385,8 @@ __global__ __launch_bounds__(256) void k_cheb_out(const ChebPlan* __restrict__ p
         ai += e * vi;
     });
     double s, c;
-    sincos(6.283185307179586 * (((double)n * Kd * mc.rc) - floor((double)n * Kd * mc.rc)), &s, &c);
+    const double ph = dn * Kd * mc.rc;
+    sincos(6.283185307179586 * (ph - floor(ph)), &s, &c);
     // times exp(-j phase)
     const float re = (float)(ar * c + ai * s), im = (float)(ai * c - ar * s);
     if (accumulate) {
@@ -382,7 +399,7 @@ __global__ __launch_bounds__(256) void k_cheb_out(const ChebPlan* __restrict__ p
     }
 }
 
-// B[i][k] = eps_k j^k sum_n g[i][n] exp(+j 2 pi n Kd rc_i) J_k(z_in), k < K;
+// B[i][k] = eps_k j^k sum_n g[i][n] exp(+j 2 pi dn Kd rc_i) J_k(z_in), k < K;
 // one wave per measurement, lane-private sums in LDS, then a fixed-order sum
 // over lanes per k
 __global__ __launch_bounds__(64) void k_cheb_coef(const ChebPlan* __restrict__ plan,
@@ -397,11 +414,12 @@ __global__ __launch_bounds__(64) void k_cheb_coef(const ChebPlan* __restrict__ p
     for (int k = 0; k < K; ++k) acc[k][lane] = make_double2(0.0, 0.0);
     for (int n = lane; n < n_freq; n += 64) {
         const float2 gv = g[(size_t)i * n_freq + n];
-        const double ph = (double)n * Kd * mc.rc;
+        const double dn = (double)n - 0.5 * (double)(n_freq - 1);
+        const double ph = dn * Kd * mc.rc;
         double s, c;
         sincos(6.283185307179586 * (ph - floor(ph)), &s, &c);
         const double wr = gv.x * c - gv.y * s, wi = gv.x * s + gv.y * c;   // g exp(+j phase)
-        const double z = 6.283185307179586 * (double)n * Kd * mc.h;
+        const double z = 6.283185307179586 * dn * Kd * mc.h;
         bessel_j_desc(z, K, [&](int k, double J) {
             double2 a = acc[k][lane];
             a.x += wr * J;
@@ -494,7 +512,7 @@ __global__ __launch_bounds__(256) void k_cheb_mf(const ChebPlan* __restrict__ pl
                                                  const AntRec* __restrict__ ant,
                                                  const MeasCheb* __restrict__ meas,
                                                  const float2* __restrict__ B, const float2* __restrict__ B2,
-                                                 double K0, float2* __restrict__ z, float* __restrict__ power,
+                                                 double Kc, float2* __restrict__ z, float* __restrict__ power,
                                                  float2* __restrict__ z2, float* __restrict__ power2) {
     if (plan->K != K) return;
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -507,8 +525,8 @@ __global__ __launch_bounds__(256) void k_cheb_mf(const ChebPlan* __restrict__ pl
         float y;
         const double r = range_f64(px - A.x, py - A.y, pz - A.z, y);
         const float x = (float)((r - mc.rc) * mc.inv_h);
-        const float t0 = frac_rev(r * K0);
-        const float c0 = cos_rev(t0), s0 = sin_rev(t0);       // exp(+j 2 pi K0 r)
+        const float t0 = frac_rev(r * Kc);
+        const float c0 = cos_rev(t0), s0 = sin_rev(t0);       // exp(+j 2 pi Kc r)
         float sr, si;
         if constexpr (TWO) {
             float s2r, s2i;
@@ -540,7 +558,7 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
                                                          const PtRec* __restrict__ rec, int n_meas,
                                                          const AntRec* __restrict__ ant,
                                                          const MeasCheb* __restrict__ meas,
-                                                         const float2* __restrict__ B, double K0,
+                                                         const float2* __restrict__ B, double Kc,
                                                          float* __restrict__ g_b, float* __restrict__ g_T,
                                                          float* __restrict__ g_n) {
     if (plan->K != K) return;
@@ -556,9 +574,9 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
         const float x = (float)((r - mc.rc) * mc.inv_h);
         float sr, si;
         cheb_series<K>(B + (size_t)i * kChebKMax, x, sr, si);
-        const float t0 = frac_rev(r * K0);
+        const float t0 = frac_rev(r * Kc);
         const float c0 = cos_rev(t0), s0 = sin_rev(t0);
-        const float G = c0 * sr - s0 * si;                     // Re(exp(+j 2 pi K0 r) S)
+        const float G = c0 * sr - s0 * si;                     // Re(exp(+j 2 pi Kc r) S)
         const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
         float spec, live = 0.0f, nd = 0.0f;
         if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
@@ -615,6 +633,9 @@ hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, int n_m
     return hipGetLastError();
 }
 
+// wavenumber at the centre of the band (revolutions per metre of range)
+static double band_centre(const RenderGeom& g) { return g.K0 + 0.5 * (double)(g.n_freq - 1) * g.Kd; }
+
 template <int KIND, int SPEC>
 static void launch_cp_all(const RenderGeom& g, const AntRec* ant, const MeasCheb* meas, const ChebPlan* plan,
                           const void* rec, int n_split, float2* partial, hipStream_t st) {
@@ -622,16 +643,17 @@ static void launch_cp_all(const RenderGeom& g, const AntRec* ant, const MeasCheb
     const long groups = (n_split + 7) / 8;
     dim3 grid((unsigned)(groups * 8 * gx));
     const long per = (g.n_pts + n_split - 1) / n_split;
-    hipLaunchKernelGGL((k_cheb_points<24, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, g.K0,
-                       rec, g.n_pts, per, n_split, gx, partial);
-    hipLaunchKernelGGL((k_cheb_points<32, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, g.K0,
-                       rec, g.n_pts, per, n_split, gx, partial);
-    hipLaunchKernelGGL((k_cheb_points<40, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, g.K0,
-                       rec, g.n_pts, per, n_split, gx, partial);
-    hipLaunchKernelGGL((k_cheb_points<48, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, g.K0,
-                       rec, g.n_pts, per, n_split, gx, partial);
-    hipLaunchKernelGGL((k_cheb_points<64, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, g.K0,
-                       rec, g.n_pts, per, n_split, gx, partial);
+    const double Kc = band_centre(g);
+#define RFVR_CP(KK)                                                                                           \
+    hipLaunchKernelGGL((k_cheb_points<KK, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, Kc, \
+                       rec, g.n_pts, per, n_split, gx, partial)
+    RFVR_CP(24);
+    RFVR_CP(28);
+    RFVR_CP(32);
+    RFVR_CP(40);
+    RFVR_CP(48);
+    RFVR_CP(64);
+#undef RFVR_CP
 }
 
 int cheb_point_splits(long n_pts, int n_meas) { return choose_point_splits(n_pts, n_meas); }
@@ -669,10 +691,12 @@ static void launch_cmf_all(const RenderGeom& g, const ChebPlan* plan, long n_q, 
                            const AntRec* ant, const MeasCheb* meas, const float2* B, const float2* B2,
                            float2* z, float* power, float2* z2, float* power2, hipStream_t st) {
     dim3 grid((unsigned)((n_q + 255) / 256));
+    const double Kc = band_centre(g);
 #define RFVR_CMF(KK)                                                                                     \
     hipLaunchKernelGGL((k_cheb_mf<KK, TWO>), grid, dim3(256), 0, st, plan, n_q, xq, g.n_meas, ant, meas, B, \
-                       B2, g.K0, z, power, z2, power2)
+                       B2, Kc, z, power, z2, power2)
     RFVR_CMF(24);
+    RFVR_CMF(28);
     RFVR_CMF(32);
     RFVR_CMF(40);
     RFVR_CMF(48);
@@ -693,10 +717,12 @@ static void launch_crb_all(const RenderGeom& g, const ChebPlan* plan, const AntR
                            const PtRec* rec, const float2* B, float* g_b, float* g_T, float* g_n,
                            hipStream_t st) {
     dim3 grid((unsigned)((g.n_pts + 255) / 256));
+    const double Kc = band_centre(g);
 #define RFVR_CRB(KK)                                                                                        \
     hipLaunchKernelGGL((k_cheb_render_bwd<KK, SPEC>), grid, dim3(256), 0, st, plan, g.n_pts, rec, g.n_meas, ant, \
-                       meas, B, g.K0, g_b, g_T, g_n)
+                       meas, B, Kc, g_b, g_T, g_n)
     RFVR_CRB(24);
+    RFVR_CRB(28);
     RFVR_CRB(32);
     RFVR_CRB(40);
     RFVR_CRB(48);
