@@ -41,6 +41,7 @@
 // recurrence in FP64 (first pass: normalisation J_0 + 2 sum J_2m = 1 and the
 // number of rescalings; second pass: the values, consumed as produced).
 #include <cmath>
+#include <type_traits>
 
 #include "rfvr_impl.hpp"
 
@@ -238,8 +239,8 @@ __device__ __forceinline__ void bessel_j_desc(double z, int nk, Visit visit) {
 // ---------------------------------------------------------------------------
 // moments over points: signal tracing forward (KIND 0) and filter adjoint
 // (KIND 1).  Lane = measurement; the lanes of a work-group walk the same point
-// records, staged through LDS in double-buffered tiles; grid as the
-// per-frequency kernel (point splits dealt over the XCDs).
+// records in step, read as wave-uniform scalar loads; point splits dealt over
+// the XCDs as in the per-frequency kernel.
 // partial[split][meas][kChebKMax] (k < K written).
 // ---------------------------------------------------------------------------
 template <int K, int KIND, int SPEC>
@@ -248,10 +249,7 @@ __global__ __launch_bounds__(256) void k_cheb_points(
     const ChebPlan* __restrict__ plan, double Kc, const void* __restrict__ recs_v, long n_pts,
     long pts_per_split, int n_split, int gx, float2* __restrict__ partial) {
     if (plan->K != K) return;
-    constexpr int TILE = 64;
-    constexpr int RB = KIND == 0 ? (int)sizeof(PtRec) : (int)sizeof(QRec);
-    constexpr int V4 = TILE * RB / 16;
-    __shared__ float4 sRec[2][V4];
+    using Rec = typename std::conditional<KIND == 0, PtRec, QRec>::type;
     const long bid = blockIdx.x;
     const int lb = (int)((bid / 8) % gx);
     const long split = (bid / (8L * gx)) * 8 + (bid % 8);
@@ -267,69 +265,60 @@ __global__ __launch_bounds__(256) void k_cheb_points(
     const long j0 = split * pts_per_split;
     long j1 = j0 + pts_per_split;
     if (j1 > n_pts) j1 = n_pts;
-    const float4* src = reinterpret_cast<const float4*>(recs_v);
-    const int tid = threadIdx.x;
-    auto fetch = [&](long jt) {
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const long e = jt * (RB / 16) + tid;
-        if (tid < V4 && e < j1 * (RB / 16)) v = src[e];
-        return v;
-    };
-    float4 pre = fetch(j0);
-    int buf = 0;
-    for (long jt = j0; jt < j1; jt += TILE) {
-        if (tid < V4) sRec[buf][tid] = pre;
-        __syncthreads();
-        if (jt + TILE < j1) pre = fetch(jt + TILE);
-        const int cnt = (j1 - jt) < TILE ? (int)(j1 - jt) : TILE;
-        for (int q = 0; q < cnt; ++q) {
-            double r;
-            float cr, ci;
-            if constexpr (KIND == 0) {
-                const PtRec P = reinterpret_cast<const PtRec*>(sRec[buf])[q];
-                const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
-                float y;
-                r = range_f64(dx, dy, dz, y);
-                float spec, live;
-                if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
-                    spec = 1.0f;
-                } else {
-                    const float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * y;
-                    spec_factor<SPEC>(nd, spec, live);
-                }
-                const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
-                cr = P.b * spec * (T * T) * (y * y);
-                ci = 0.0f;
+    // every lane of the work-group takes the same point at the same time: its
+    // record is a wave-uniform (scalar) load.  The next record is requested
+    // once the current one has been read (scalar loads complete out of order,
+    // so any wait is for all of them) and lands during the moment updates.
+    const Rec* recs = reinterpret_cast<const Rec*>(recs_v);
+    Rec cur = recs[j0 < j1 ? j0 : 0];
+    for (long j = j0; j < j1; ++j) {
+        double r;
+        float cr, ci;
+        if constexpr (KIND == 0) {
+            const PtRec& P = cur;
+            const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
+            float y;
+            r = range_f64(dx, dy, dz, y);
+            float spec, live;
+            if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                spec = 1.0f;
             } else {
-                const QRec Q = reinterpret_cast<const QRec*>(sRec[buf])[q];
-                float y;
-                r = range_f64(Q.x - A.x, Q.y - A.y, Q.z - A.z, y);
-                cr = Q.hr;
-                ci = Q.hi;
+                const float nd = (P.nx * (float)dx + P.ny * (float)dy + P.nz * (float)dz) * y;
+                spec_factor<SPEC>(nd, spec, live);
             }
-            // weight times exp(-j 2 pi Kc r)
-            const float t0 = frac_rev(r * Kc);
-            const float c0 = cos_rev(t0), s0 = sin_rev(t0);
-            const float br = __builtin_fmaf(cr, c0, ci * s0);
-            const float bi = __builtin_fmaf(ci, c0, -cr * s0);
-            const float x = (float)((r - mc.rc) * mc.inv_h);
-            const float x2 = x + x;
-            mr[0] += br;
-            mi[0] += bi;
-            float tm = 1.0f, tk = x;
-            mr[1] = __builtin_fmaf(br, x, mr[1]);
-            mi[1] = __builtin_fmaf(bi, x, mi[1]);
-#pragma unroll
-            for (int k = 2; k < K; ++k) {
-                const float tn = __builtin_fmaf(x2, tk, -tm);
-                tm = tk;
-                tk = tn;
-                mr[k] = __builtin_fmaf(br, tn, mr[k]);
-                mi[k] = __builtin_fmaf(bi, tn, mi[k]);
-            }
+            const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
+            cr = P.b * spec * (T * T) * (y * y);
+            ci = 0.0f;
+        } else {
+            const QRec& Q = cur;
+            float y;
+            r = range_f64(Q.x - A.x, Q.y - A.y, Q.z - A.z, y);
+            cr = Q.hr;
+            ci = Q.hi;
         }
-        __syncthreads();
-        buf ^= 1;
+        // weight times exp(-j 2 pi Kc r)
+        const float t0 = frac_rev(r * Kc);
+        const float c0 = cos_rev(t0), s0 = sin_rev(t0);
+        const float br = __builtin_fmaf(cr, c0, ci * s0);
+        const float bi = __builtin_fmaf(ci, c0, -cr * s0);
+        const float x = (float)((r - mc.rc) * mc.inv_h);
+        const Rec nxt = recs[j + 1 < j1 ? j + 1 : j];
+        __builtin_amdgcn_sched_barrier(0);
+        const float x2 = x + x;
+        mr[0] += br;
+        mi[0] += bi;
+        float tm = 1.0f, tk = x;
+        mr[1] = __builtin_fmaf(br, x, mr[1]);
+        mi[1] = __builtin_fmaf(bi, x, mi[1]);
+#pragma unroll
+        for (int k = 2; k < K; ++k) {
+            const float tn = __builtin_fmaf(x2, tk, -tm);
+            tm = tk;
+            tk = tn;
+            mr[k] = __builtin_fmaf(br, tn, mr[k]);
+            mi[k] = __builtin_fmaf(bi, tn, mi[k]);
+        }
+        cur = nxt;
     }
     if (live_lane) {
         float2* out = partial + ((size_t)split * n_meas + i) * kChebKMax;
@@ -656,7 +645,19 @@ static void launch_cp_all(const RenderGeom& g, const AntRec* ant, const MeasCheb
 #undef RFVR_CP
 }
 
-int cheb_point_splits(long n_pts, int n_meas) { return choose_point_splits(n_pts, n_meas); }
+// Point splits of the moment kernels: twice the waves of the per-frequency
+// kernels' rule (8192, eight per SIMD).  A lane's work per point is short at
+// the lower orders, where five waves per SIMD fit, and more resident waves
+// hide the per-tile barriers and LDS reads; >= 128 points per split.
+int cheb_point_splits(long n_pts, int n_meas) {
+    const long waves_per_split = (n_meas + 63) / 64;
+    long ns = (8192 + waves_per_split - 1) / waves_per_split;
+    const long max_by_pts = (n_pts + 127) / 128;
+    if (ns > max_by_pts) ns = max_by_pts;
+    if (ns < 1) ns = 1;
+    if (ns > 65535) ns = 65535;
+    return (int)ns;
+}
 
 hipError_t launch_cheb_points(const RenderGeom& g, int kind, uint32_t flags, const AntRec* ant,
                               const MeasCheb* meas, const ChebPlan* plan, const void* rec, int n_split,
