@@ -261,8 +261,9 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
 
 /* Training pair: the same two operations, sharing a caller-owned reserve
  * (device, 256-byte aligned, rfvr_mlp_reserve_bytes() bytes: for every trunk
- * layer its pre-activation, its activation and the gradient sweep's adjoint
- * of f to the pre-activation, float32 [n][width] each).  rfvr_mlp_forward_train computes
+ * layer its activation H = softplus(Z) and the gradient sweep's adjoint of f
+ * to the pre-activation Z, float32 [n][width] each; softplus'(Z) and
+ * exp(-beta Z) are recovered from H).  rfvr_mlp_forward_train computes
  * what rfvr_mlp_forward does (running the gradient sweep even when grad is
  * NULL) and fills the reserve; rfvr_mlp_backward_train reads it instead of
  * recomputing the primal layers and the adjoint of the tangent pass (the

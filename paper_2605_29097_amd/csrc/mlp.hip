@@ -52,19 +52,21 @@ __device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big
 // split operands (a b ~ a_big b_big + a_big b_small + a_small b_big)
 enum { MM_FP32 = 0, MM_BF16 = 1, MM_BF16X3 = 3 };
 
-// operand prologues: identity, relu, or SEED: A[p][k] -> softplus'(A[p][k])
-// colv[k] (the normal sweep's seed from the top layer's Z, formed while the
-// tile is staged); the softplus activations themselves are written by the
-// producing GEMM's epilogue, so no operand is transformed twice
+// operand prologues: identity, relu, or SEED: A[p][k] = H -> sp'(Z) colv[k] (the
+// normal sweep's seed from the top layer's activation, formed while the tile is
+// staged); the softplus activations themselves are written by the producing
+// GEMM's epilogue, so no operand is transformed twice
 enum { PRO_ID = 0, PRO_SEED = 1, PRO_RELU = 3 };
-// epilogues: BIAS  Y = acc + bias
+// epilogues (C = H = sp(Z) of a layer: sp'(Z) = 1 - e^(-beta H), e^(-beta Z) =
+// 1 / (e^(beta H) - 1), so Z itself is never stored):
+//            BIAS      Y = acc + bias
 //            RELUMASK  Y = acc where C > 0, else 0
-//            BIAS_SP   Y = acc + bias and Y2 = softplus(Y)            (layer output and activation)
-//            DSPMUL    Y = acc * softplus'(C)                          (normal sweep, adjoint to Z)
+//            BIAS_SP   Y = softplus(acc + bias)                        (layer activation)
+//            DSPMUL    Y = acc * sp'(Z)                                (normal sweep, tangent)
 //            TOPADJ    Hbar = acc + scale rowv[p] colv[m], Hdotbar = scale colv[m] with
-//                      C = Z, C2 = Hdot of the top layer: Y = Zbar, Y2 = Zdotbar
-//                      (the top trunk layer's adjoints, as the dual adjoint's epilogue)
-//            ADJ1      Hbar = acc, Hdotbar = scale C3 / sp'(C) with C = Z, C2 = Hdot and
+//                      C = H, C2 = Hdot of the top layer: Y = Zbar, Y2 = Zdotbar
+//                      (the top trunk layer's adjoints)
+//            ADJ1      Hbar = acc, Hdotbar = scale C3 / sp'(Z) with C = H, C2 = Hdot and
 //                      C3 = the normal sweep's adjoint to Z of the layer below:
 //                      Y = Zbar = sp'(Z) Hbar + beta sigma(-beta Z) Hdot Hdotbar
 //                        = sp'(Z) Hbar + beta exp(-beta Z) Hdot scale C3
@@ -85,6 +87,9 @@ __device__ __forceinline__ float sp_f(float z, float beta) {
     return fmaxf(z, 0.0f) + flog1p_pos(fexp(-fabsf(bz))) * __builtin_amdgcn_rcpf(beta);
 }
 __device__ __forceinline__ float sp_d1(float z, float beta) { return fsig(beta * z); }
+// sp'(Z) from H = sp(Z): e^(beta H) = 1 + e^(beta Z), so sp'(Z) = 1 - e^(-beta H)
+// (absolute error ~1e-7, the rounding of the exponential near 1)
+__device__ __forceinline__ float sp_d1_h(float h, float beta) { return 1.0f - fexp(-beta * h); }
 __device__ __forceinline__ float sp_d2(float z, float beta) {
     const float s = fsig(beta * z);
     return beta * s * (1.0f - s);
@@ -108,7 +113,7 @@ struct GemmArgs {
     const float* C3;              // EPI_ADJ1: [P][ldc]
     long ldc;
     float* Y; long ldy;
-    float* Y2;                    // EPI_BIAS_SP, TOPADJ: second output, row stride ldy
+    float* Y2;                    // EPI_TOPADJ: second output, row stride ldy
     const float* rowv;            // EPI_TOPADJ: [P] or null
     const float* colv;            // EPI_TOPADJ: [M]; PRO_SEED: [K]
     float scale;                  // EPI_TOPADJ, ADJ1
@@ -183,8 +188,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
             }
             if constexpr (PRO == PRO_SEED) {
                 const float* w = g.colv + k0 + (e % RPF) * 4;
-                v.x = sp_d1(v.x, g.beta) * w[0]; v.y = sp_d1(v.y, g.beta) * w[1];
-                v.z = sp_d1(v.z, g.beta) * w[2]; v.w = sp_d1(v.w, g.beta) * w[3];
+                v.x = sp_d1_h(v.x, g.beta) * w[0]; v.y = sp_d1_h(v.y, g.beta) * w[1];
+                v.z = sp_d1_h(v.z, g.beta) * w[2]; v.w = sp_d1_h(v.w, g.beta) * w[3];
             }
             *reinterpret_cast<float4*>(&sA[off(e / RPF, e % RPF)]) = v;
         }
@@ -324,25 +329,28 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_SP) y[v] += vv[b][v];
-                    if constexpr (EPI == EPI_BIAS_SP) y2[v] = sp_f(y[v], g.beta);
+                    if constexpr (EPI == EPI_BIAS_SP) y[v] = sp_f(y[v], g.beta);
                     if constexpr (EPI == EPI_RELUMASK) y[v] = cl[0][b][v] > 0.0f ? y[v] : 0.0f;
-                    if constexpr (EPI == EPI_DSPMUL) y[v] *= sp_d1(cl[0][b][v], g.beta);
+                    if constexpr (EPI == EPI_DSPMUL) y[v] *= sp_d1_h(cl[0][b][v], g.beta);
                     if constexpr (EPI == EPI_TOPADJ) {
                         const float cv = vv[b][v];
                         const float hb = __builtin_fmaf(rv, cv, y[v]);
                         const float hdb = g.scale * cv;
-                        const float sg = fsig(g.beta * cl[0][b][v]);
-                        y[v] = sg * hb + g.beta * (1.0f - sg) * cl[1][b][v] * hdb;
+                        const float em = fexp(-g.beta * cl[0][b][v]);   // 1 - sp'(Z)
+                        const float sg = 1.0f - em;
+                        y[v] = sg * hb + g.beta * em * cl[1][b][v] * hdb;
                         y2[v] = sg * hdb;
                     }
                     if constexpr (EPI == EPI_ADJ1) {
-                        // the sweep kept S = sp'(Z) G, so sigma(-beta Z) G = exp(-beta Z) S
-                        const float ex = fexp(-g.beta * cl[0][b][v]);
-                        const float sg = __builtin_amdgcn_rcpf(1.0f + ex);
+                        // the sweep kept S = sp'(Z) G, so sigma(-beta Z) G = exp(-beta Z) S,
+                        // with exp(-beta Z) = 1 / (e^(beta H) - 1)
+                        const float bh = g.beta * cl[0][b][v];
+                        const float ex = __builtin_amdgcn_rcpf(fexp(bh) - 1.0f);
+                        const float sg = 1.0f - fexp(-bh);
                         y[v] = sg * y[v] + g.beta * fminf(ex, 1e30f) * cl[1][b][v] * (g.scale * cl[2][b][v]);
                     }
                 }
-                constexpr bool TWO = (EPI == EPI_BIAS_SP || EPI == EPI_TOPADJ);
+                constexpr bool TWO = (EPI == EPI_TOPADJ);
                 if constexpr (!GUARD) {
                     *reinterpret_cast<floatx4*>(g.Y + p * g.ldy + mb) = y;
                     if constexpr (TWO) *reinterpret_cast<floatx4*>(g.Y2 + p * g.ldy + mb) = y2;
@@ -1181,15 +1189,14 @@ size_t bwd_bytes(const Layout& l, long n, bool keep) {
            align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
 }
 
-// --- reserve of the training pair, [n][W] per layer: Z_i, H_i, and the normal
-// sweep's adjoint S_i = df/dZ_i --------------------------------------------------
+// --- reserve of the training pair, [n][W] per layer: H_i = sp(Z_i) and the
+// normal sweep's adjoint S_i = df/dZ_i ------------------------------------------
 size_t reserve_layer_bytes(const Layout& l, long n) { return align256(sizeof(float) * (size_t)n * l.W); }
-size_t reserve_bytes(const Layout& l, long n) { return 3 * (size_t)l.L * reserve_layer_bytes(l, n); }
-float* reserve_z(void* r, const Layout& l, long n, int i) {
+size_t reserve_bytes(const Layout& l, long n) { return 2 * (size_t)l.L * reserve_layer_bytes(l, n); }
+float* reserve_h(void* r, const Layout& l, long n, int i) {
     return reinterpret_cast<float*>(static_cast<char*>(r) + (size_t)i * reserve_layer_bytes(l, n));
 }
-float* reserve_h(void* r, const Layout& l, long n, int i) { return reserve_z(r, l, n, l.L + i); }
-float* reserve_s(void* r, const Layout& l, long n, int i) { return reserve_z(r, l, n, 2 * l.L + i); }
+float* reserve_s(void* r, const Layout& l, long n, int i) { return reserve_h(r, l, n, l.L + i); }
 
 int check_buffers(void* ws, size_t ws_bytes, size_t need, void* reserve, size_t reserve_bytes_, size_t rneed) {
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
@@ -1220,8 +1227,8 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     const Weights w = take_weights(cur, l);
     float* X0 = cur.take<float>((size_t)chunk * l.in0p);
-    float* Zw[16];
-    for (int i = 0; i < l.L && !keep; ++i) Zw[i] = cur.take<float>((size_t)chunk * l.W);
+    float* Hw[16];
+    for (int i = 0; i < l.L && !keep; ++i) Hw[i] = cur.take<float>((size_t)chunk * l.W);
     float* G[2] = {cur.take<float>((size_t)chunk * l.W), cur.take<float>((size_t)chunk * l.W)};
     float* Yh[4];
     for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
@@ -1232,21 +1239,16 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
         const float* x = xyz + 3 * c0;
         hipLaunchKernelGGL(k_pe, dim3(blocks(m * l.in0p)), dim3(256), 0, st, m, x, net->centre[0], net->centre[1],
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0, nullptr, nullptr);
-        // Z_i = H_{i-1} W_i^T + b_i and H_i = sp(Z_i) from the epilogue; without
-        // a reserve the activations live in the two sweep buffers until the
-        // sweep starts
-        float *Z[16], *H[16];
-        for (int i = 0; i < l.L; ++i) {
-            Z[i] = keep ? reserve_z(reserve, l, n, i) + c0 * l.W : Zw[i];
-            H[i] = keep ? reserve_h(reserve, l, n, i) + c0 * l.W : G[i & 1];
-        }
-        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], Z[0], l.W, m, l.W, l.in0p, beta,
-                                       nullptr, 0, H[0]), cx);
+        // H_i = sp(H_{i-1} W_i^T + b_i) from the epilogue (the reserve's, or
+        // the workspace's until the sweep has used them)
+        float* H[16];
+        for (int i = 0; i < l.L; ++i) H[i] = keep ? reserve_h(reserve, l, n, i) + c0 * l.W : Hw[i];
+        gemm32<PRO_ID, EPI_BIAS_SP>(ga(X0, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], H[0], l.W, m, l.W, l.in0p, beta),
+                                    cx);
         for (int i = 1; i < l.L; ++i)
-            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], Z[i], l.W, m, l.W, l.W,
-                                         beta, nullptr, 0, H[i]), cx);
+            gemm<PRO_ID, EPI_BIAS_SP>(ga(H[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], H[i], l.W, m, l.W, l.W, beta),
+                                      cx);
         float* Ht = H[l.L - 1];
-        float* Zt = Z[l.L - 1];
         if (sdf)
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
                                (int)PRO_ID, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
@@ -1258,8 +1260,9 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
                                l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
         if (grad || keep) {
-            // adjoint of f w.r.t. Z_{L-1}: S_{L-1} = sp'(Z_{L-1}) w_out, formed as the
-            // first product's operand (PRO_SEED); then S_{i-1} = (S_i W_i) . sp'(Z_{i-1})
+            // adjoint of f w.r.t. Z_{L-1}: S_{L-1} = sp'(Z_{L-1}) w_out, formed from
+            // H_{L-1} as the first product's operand (PRO_SEED); then
+            // S_{i-1} = (S_i W_i) . sp'(Z_{i-1})
             // (epilogue), and dgamma = S_0 W_0.  The training forward keeps S_i
             // (i < L-1) in the reserve: scaled by half_size, S_i and S_i / sp'(Z_i)
             // are the backward's adjoints of the tangent pass to Zdot_i and Hdot_i,
@@ -1268,10 +1271,10 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
             for (int i = l.L - 1; i >= 0; --i) {
                 const int mout = i == 0 ? l.in0p : l.W;
                 const bool top = i == l.L - 1;
-                const float* src = top ? Zt : (keep ? reserve_s(reserve, l, n, i) + c0 * l.W : G[cur_g]);
+                const float* src = top ? Ht : (keep ? reserve_s(reserve, l, n, i) + c0 * l.W : G[cur_g]);
                 float* dst = (keep && i > 0) ? reserve_s(reserve, l, n, i - 1) + c0 * l.W : G[cur_g ^ 1];
                 GemmArgs a = ga(src, l.W, w.WT[i], l.W, nullptr, dst, mout, m, mout, l.W, beta,
-                                i > 0 ? Z[i - 1] : nullptr, l.W);
+                                i > 0 ? H[i - 1] : nullptr, l.W);
                 a.colv = P + l.o_wout;
                 if (i > 0) {
                     if (top) gemm<PRO_SEED, EPI_DSPMUL>(a, cx);
@@ -1337,9 +1340,9 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
         const float* x = xyz + 3 * c0;
         const float* gf = g_sdf ? g_sdf + c0 : nullptr;
         const float* ga_ = g_refl ? g_refl + c0 : nullptr;
-        float *Z[16], *H[16];
+        float *Z[16], *H[16];   // Z: the plain backward's recomputed pre-activations only
         for (int i = 0; i < l.L; ++i) {
-            Z[i] = keep ? reserve_z(reserve, l, n, i) + c0 * l.W : Zw[i];
+            Z[i] = keep ? nullptr : Zw[i];
             H[i] = keep ? reserve_h(reserve, l, n, i) + c0 * l.W : Hw[i];
         }
         // encoding and its tangent along g_grad
@@ -1347,12 +1350,13 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                            net->centre[2], inv_half, net->pe_octaves, l.in0p, X0,
                            g_grad ? g_grad + 3 * c0 : nullptr, X0d);
         if (keep) {
-            // tangent only: Hdot_i = sp'(Z_i) (Hdot_{i-1} W_i^T) with Z_i from the reserve
+            // tangent only: Hdot_i = sp'(Z_i) (Hdot_{i-1} W_i^T), sp'(Z_i) from the
+            // reserve's H_i
             gemm32<PRO_ID, EPI_DSPMUL>(ga(X0d, l.in0p, w.Wp[0], l.in0p, nullptr, Hd[0], l.W, m, l.W, l.in0p,
-                                          beta, Z[0], l.W), cx);
+                                          beta, H[0], l.W), cx);
             for (int i = 1; i < l.L; ++i)
                 gemm<PRO_ID, EPI_DSPMUL>(ga(Hd[i - 1], l.W, w.Wp[i], l.W, nullptr, Hd[i], l.W, m, l.W, l.W,
-                                            beta, Z[i], l.W), cx);
+                                            beta, H[i], l.W), cx);
         } else {
             // one dual GEMM per layer: (Z_i, H_i) and Hdot_i share W_i
             gemm_dual<EPI2_FWD>(da(X0, X0d, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], nullptr, nullptr, Z[0], H[0], Hd[0],
@@ -1392,7 +1396,7 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
         // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0 and Hdot_bar =
         // half w_out, turned into the top layer's (Zbar, Zdotbar) in the epilogue
         {
-            GemmArgs a = ga(Ybh[0], l.HW, w.WhT[0], l.HW, nullptr, Zb, l.W, m, l.W, l.HW, beta, Z[l.L - 1], l.W, Zdb);
+            GemmArgs a = ga(Ybh[0], l.HW, w.WhT[0], l.HW, nullptr, Zb, l.W, m, l.W, l.HW, beta, H[l.L - 1], l.W, Zdb);
             a.C2 = Hd[l.L - 1];
             a.rowv = gf;
             a.colv = P + l.o_wout;
@@ -1427,7 +1431,7 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                                GP + l.ob[i], acc);
             if (i > 0 && keep) {
                 // Zbar_{i-1} from Hbar_{i-1} = Zbar_i W_i and Hdotbar_{i-1} = half S_{i-1} / sp'(Z_{i-1})
-                GemmArgs a = ga(Zb, l.W, w.WT[i], l.W, nullptr, Zb_n, l.W, m, l.W, l.W, beta, Z[i - 1], l.W);
+                GemmArgs a = ga(Zb, l.W, w.WT[i], l.W, nullptr, Zb_n, l.W, m, l.W, l.W, beta, H[i - 1], l.W);
                 a.C2 = Hd[i - 1];
                 a.C3 = reserve_s(reserve, l, n, i - 1) + c0 * l.W;
                 a.scale = half;
