@@ -117,6 +117,8 @@ struct GemmArgs {
     const float* rowv;            // EPI_TOPADJ: [P] or null
     const float* colv;            // EPI_TOPADJ: [M]; PRO_SEED: [K]
     float scale;                  // EPI_TOPADJ, ADJ1
+    float* cpart;                 // EPI_TOPADJ: [point tiles][M] column partials of
+                                  // rowv[p] scale C + scale C2 (one row per tile), or null
     long P; int M; int K;
     float beta;
 };
@@ -364,6 +366,24 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 }
                 if constexpr (GUARD && NC >= 2) __builtin_amdgcn_sched_barrier(0);
             }
+            if constexpr (EPI == EPI_TOPADJ) {
+                if (g.cpart) {
+                    // the group's share of the output layer's weight gradient,
+                    // sum_p (rowv[p] scale H + scale Hdot) per column: a fixed-order
+                    // sum over the 16 lanes of the same columns (lane bits 0-3:
+                    // the points), one row per (group, wave) into LDS
+#pragma unroll
+                    for (int b = 0; b < TM; ++b) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            float c = pin ? __builtin_fmaf(rv, cl[0][b][v], g.scale * cl[1][b][v]) : 0.0f;
+#pragma unroll
+                            for (int o = 1; o < 16; o <<= 1) c += __shfl_xor(c, o);
+                            if (li == 0) sA[(a * 4 + wv) * (BM / WM) + b * 16 + lg * 4 + v] = c;
+                        }
+                    }
+                }
+            }
             // the next group's loads stay behind this group's stores
             if constexpr (NC >= 2) __builtin_amdgcn_sched_barrier(0);
         }
@@ -372,6 +392,22 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                          (((uintptr_t)g.Y | (uintptr_t)g.Y2 | (uintptr_t)g.C | (uintptr_t)g.C2 | (uintptr_t)g.C3) & 15) == 0;
     if (aligned && p0 + BP <= g.P && m0 + BM <= g.M) epilogue(std::false_type{});
     else epilogue(std::true_type{});
+    if constexpr (EPI == EPI_TOPADJ) {
+        if (g.cpart) {
+            // the tile's column sums: one thread per column adds the rows of
+            // its waves along points and their groups in a fixed order (the LDS
+            // tiles were last read before the main loop's final barrier; the
+            // rows above were written after it); one partial row per tile
+            __syncthreads();
+            if (tid < BM) {
+                const int wmc = tid / (BM / WM), col = tid % (BM / WM);
+                float t = 0.0f;
+                for (int q = 0; q < WP; ++q)
+                    for (int a = 0; a < TP; ++a) t += sA[(a * 4 + (wmc * WP + q)) * (BM / WM) + col];
+                if (m0 + tid < g.M) g.cpart[(p0 / BP) * (long)g.M + m0 + tid] = t;
+            }
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1176,6 +1212,9 @@ size_t fwd_bytes(const Layout& l, long n, bool keep) {
 }
 
 // --- backward workspace ------------------------------------------------------
+// rows of the top-adjoint GEMM's column partials: one per 128-point tile
+long top_rows(long n) { return (n + 127) / 128; }
+
 size_t bwd_bytes(const Layout& l, long n, bool keep) {
     const long c = n < kChunk ? n : kChunk;
     const long wmax = l.W > l.in0p ? l.W : l.in0p;
@@ -1186,7 +1225,8 @@ size_t bwd_bytes(const Layout& l, long n, bool keep) {
            align256(sizeof(float) * c) +                            // ybar3
            align256(sizeof(float) * 2 * kWgSplits * (size_t)l.W * wmax) +
            align256(sizeof(float) * kWgSplits * (size_t)l.W) +
-           align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
+           align256(sizeof(float) * (size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW)) +
+           align256(sizeof(float) * (size_t)top_rows(c) * l.W);   // output layer column partials
 }
 
 // --- reserve of the training pair, [n][W] per layer: H_i = sp(Z_i) and the
@@ -1332,6 +1372,7 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
     float* part = cur.take<float>((size_t)2 * kWgSplits * l.W * wmax);
     float* bpart = cur.take<float>((size_t)kWgSplits * l.W);
     float* cpart = cur.take<float>((size_t)kColBlocks * (l.W > l.HW ? l.W : l.HW));
+    float* tpart = cur.take<float>((size_t)top_rows(chunk) * l.W);
     if ((rc = hip_status(prep_weights(l, P, w, st), "mlp weight prep"))) return rc;
 
     for (long c0 = 0; c0 < n; c0 += chunk) {
@@ -1366,7 +1407,6 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                                        H[i], Hd[i], l.W, m, l.W, l.W, beta), cx.mm, st);
         }
         float* Ht = H[l.L - 1];
-        float* Hdt = Hd[l.L - 1];
         // head forward
         gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
         for (int h = 1; h < l.HL; ++h)
@@ -1394,17 +1434,22 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
             }
         }
         // top of the trunk: H_bar = half g_f w_out + Ybar_0 Wh_0 and Hdot_bar =
-        // half w_out, turned into the top layer's (Zbar, Zdotbar) in the epilogue
+        // half w_out, turned into the top layer's (Zbar, Zdotbar) in the
+        // epilogue, which also forms the column partials of the output layer's
+        // weight gradient w_out_bar = half sum_p (g_f H + Hdot) from the same
+        // operands
         {
             GemmArgs a = ga(Ybh[0], l.HW, w.WhT[0], l.HW, nullptr, Zb, l.W, m, l.W, l.HW, beta, H[l.L - 1], l.W, Zdb);
             a.C2 = Hd[l.L - 1];
             a.rowv = gf;
             a.colv = P + l.o_wout;
             a.scale = half;
+            a.cpart = tpart;
             gemm<PRO_ID, EPI_TOPADJ>(a, cx);
         }
-        // sdf output layer: w_out_bar = half sum (g_f H + Hdot), b_out_bar = half sum g_f
-        colsum(Ht, Hdt, gf, l.W, m, l.W, 3, beta, half, cpart, GP + l.o_wout, acc, st);
+        // sdf output layer: w_out_bar from the partials, b_out_bar = half sum g_f
+        hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, tpart, (int)top_rows(m), l.W, 1.0f,
+                           GP + l.o_wout, acc);
         if (gf) colsum(gf, nullptr, nullptr, 1, m, 1, 0, beta, half, cpart, GP + l.o_bout, acc, st);
         else if (!acc) hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, GP + l.o_bout, 1L, 0.0f);
         // trunk layers, top down: the others' (Zbar, Zdotbar) from the dual
