@@ -327,21 +327,37 @@ __global__ __launch_bounds__(256) void k_cheb_points(
     }
 }
 
-// fixed-order sum over the splits of the moments: M[i][k] for k < K
-__global__ void k_cheb_moment_sum(const float2* __restrict__ partial, int n_split, int n_meas,
-                                  const ChebPlan* __restrict__ plan, float2* __restrict__ M) {
+// fixed-order sum over the splits of the moments: M[i][k] for k < K.  A
+// work-group takes 32 outputs; its 8 thread groups sum every 8th split in FP64,
+// then the 8 group sums are added in order.
+constexpr int kMsOut = 32, kMsGroups = 8;
+__global__ __launch_bounds__(256) void k_cheb_moment_sum(const float2* __restrict__ partial, int n_split,
+                                                         int n_meas, const ChebPlan* __restrict__ plan,
+                                                         float2* __restrict__ M) {
+    __shared__ double sr[kMsGroups][kMsOut], si[kMsGroups][kMsOut];
     const int K = plan->K;
     if (K == 0) return;
-    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (long)n_meas * kChebKMax) return;
-    if ((int)(o % kChebKMax) >= K) return;
-    double sr = 0.0, si = 0.0;
-    for (int s = 0; s < n_split; ++s) {
-        const float2 v = partial[(size_t)s * n_meas * kChebKMax + o];
-        sr += v.x;
-        si += v.y;
+    const int ol = threadIdx.x % kMsOut, gi = threadIdx.x / kMsOut;
+    const long o = (long)blockIdx.x * kMsOut + ol;
+    const bool live = o < (long)n_meas * kChebKMax && (int)(o % kChebKMax) < K;
+    double ar = 0.0, ai = 0.0;
+    if (live) {
+        for (int s = gi; s < n_split; s += kMsGroups) {
+            const float2 v = partial[(size_t)s * n_meas * kChebKMax + o];
+            ar += v.x;
+            ai += v.y;
+        }
     }
-    M[o] = make_float2((float)sr, (float)si);
+    sr[gi][ol] = ar;
+    si[gi][ol] = ai;
+    __syncthreads();
+    if (gi != 0 || !live) return;
+    double tr = 0.0, ti = 0.0;
+    for (int g = 0; g < kMsGroups; ++g) {
+        tr += sr[g][ol];
+        ti += si[g][ol];
+    }
+    M[o] = make_float2((float)tr, (float)ti);
 }
 
 // out[i][n] (+)= exp(-j 2 pi dn Kd rc_i) sum_k eps_k (-j)^k J_k(z_in) M_ik
@@ -672,8 +688,8 @@ hipError_t launch_cheb_points(const RenderGeom& g, int kind, uint32_t flags, con
         }
     }
     const long nm = (long)g.n_meas * kChebKMax;
-    hipLaunchKernelGGL(k_cheb_moment_sum, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, st, partial, n_split,
-                       g.n_meas, plan, M);
+    hipLaunchKernelGGL(k_cheb_moment_sum, dim3((unsigned)((nm + kMsOut - 1) / kMsOut)), dim3(kMsOut * kMsGroups), 0,
+                       st, partial, n_split, g.n_meas, plan, M);
     const long no = (long)g.n_meas * g.n_freq;
     hipLaunchKernelGGL(k_cheb_out, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, st, plan, meas, M, g.n_meas,
                        g.n_freq, g.Kd, accumulate, out);

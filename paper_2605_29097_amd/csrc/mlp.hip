@@ -979,6 +979,34 @@ __global__ void k_pad_cols(const float* __restrict__ in, int R, int C, int Cpad,
     out[o] = c < C ? in[(long)r * C + c] : 0.0f;
 }
 
+// All of a call's weight copies in one launch: job k writes elements
+// [begin[k], begin[k+1]) of the concatenated outputs, either in[R][C] zero
+// padded to [R][Cpad] or its transpose zero padded to [Cpad][Rpad].
+constexpr int kPrepJobs = 40;
+struct PrepJob {
+    const float* in;
+    float* out;
+    int R, C, Rpad, Cpad, transpose, pad;
+};
+struct PrepTable {
+    PrepJob job[kPrepJobs];
+    long begin[kPrepJobs + 1];
+    int n;
+};
+__global__ void k_prep_weights(PrepTable t) {
+    for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < t.begin[t.n];
+         o += (long)gridDim.x * blockDim.x) {
+        int k = 0;
+        while (k + 1 < t.n && o >= t.begin[k + 1]) ++k;
+        const PrepJob& j = t.job[k];
+        const long q = o - t.begin[k];
+        int r, c;
+        if (j.transpose) { c = (int)(q / j.Rpad); r = (int)(q % j.Rpad); }
+        else { r = (int)(q / j.Cpad); c = (int)(q % j.Cpad); }
+        j.out[q] = (r < j.R && c < j.C) ? j.in[(long)r * j.C + c] : 0.0f;
+    }
+}
+
 // ============================================================================
 // host orchestration
 // ============================================================================
@@ -1076,20 +1104,29 @@ Weights take_weights(WsCursor& cur, const Layout& l) {
 }
 
 hipError_t prep_weights(const Layout& l, const float* P, const Weights& w, hipStream_t st) {
-    for (int i = 0; i < l.L; ++i) {
+    PrepTable t = {};
+    long total = 0;
+    auto add = [&](const float* in, float* out, int R, int C, int Rpad, int Cpad, int transpose) {
+        PrepJob& j = t.job[t.n];
+        j.in = in; j.out = out; j.R = R; j.C = C; j.Rpad = Rpad; j.Cpad = Cpad; j.transpose = transpose;
+        t.begin[t.n] = total;
+        total += (long)Rpad * Cpad;
+        ++t.n;
+    };
+    for (int i = 0; i < l.L; ++i) {          // at most 16 layers and 4 head layers: <= 40 jobs
         const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
-        hipLaunchKernelGGL(k_pad_cols, dim3(blocks((long)l.W * finp)), dim3(256), 0, st, P + l.oW[i],
-                           l.W, fin, finp, w.Wp[i]);
-        hipLaunchKernelGGL(k_transpose_pad, dim3(blocks((long)l.W * finp)), dim3(256), 0, st,
-                           P + l.oW[i], l.W, fin, l.W, finp, w.WT[i]);
+        add(P + l.oW[i], w.Wp[i], l.W, fin, l.W, finp, 0);
+        add(P + l.oW[i], w.WT[i], l.W, fin, l.W, finp, 1);
     }
     for (int h = 0; h < l.HL; ++h) {
         const int fin = h == 0 ? l.W : l.HW;
-        hipLaunchKernelGGL(k_pad_cols, dim3(blocks((long)l.HW * fin)), dim3(256), 0, st, P + l.oWh[h],
-                           l.HW, fin, fin, w.Whp[h]);
-        hipLaunchKernelGGL(k_transpose_pad, dim3(blocks((long)l.HW * fin)), dim3(256), 0, st,
-                           P + l.oWh[h], l.HW, fin, l.HW, fin, w.WhT[h]);
+        add(P + l.oWh[h], w.Whp[h], l.HW, fin, l.HW, fin, 0);
+        add(P + l.oWh[h], w.WhT[h], l.HW, fin, l.HW, fin, 1);
     }
+    t.begin[t.n] = total;
+    long nb = (total + 255) / 256;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_prep_weights, dim3((unsigned)nb), dim3(256), 0, st, t);
     return hipGetLastError();
 }
 
