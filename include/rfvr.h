@@ -263,12 +263,13 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
  * (device, 256-byte aligned, rfvr_mlp_reserve_bytes() bytes: for every trunk
  * layer its activation H = softplus(Z) and the gradient sweep's adjoint of f
  * to the pre-activation Z, float32 [n][width] each; softplus'(Z) and
- * exp(-beta Z) are recovered from H).  rfvr_mlp_forward_train computes
- * what rfvr_mlp_forward does (running the gradient sweep even when grad is
- * NULL) and fills the reserve; rfvr_mlp_backward_train reads it instead of
- * recomputing the primal layers and the adjoint of the tangent pass (the
- * sweep's adjoint scaled by half_size), so per layer it runs two matrix
- * products fewer than rfvr_mlp_backward.  The caller keeps
+ * exp(-beta Z) are recovered from H; then for every head layer its output
+ * before the relu, float32 [n][head_width]).  rfvr_mlp_forward_train computes
+ * what rfvr_mlp_forward does (running the gradient sweep and the head even
+ * when grad or refl is NULL) and fills the reserve; rfvr_mlp_backward_train
+ * reads it instead of recomputing the primal and head layers and the adjoint
+ * of the tangent pass (the sweep's adjoint scaled by half_size), so per trunk
+ * layer it runs two matrix products fewer than rfvr_mlp_backward.  The caller keeps
  * net (params unchanged), xyz and n the same between the two calls and does
  * not write the reserve in between; nothing checks this, and a mismatch gives
  * wrong gradients without an error.  Outputs agree with the plain calls to

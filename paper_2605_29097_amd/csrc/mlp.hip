@@ -1245,7 +1245,7 @@ size_t fwd_bytes(const Layout& l, long n, bool keep) {
     const long c = n < kChunk ? n : kChunk;
     return weights_bytes(l) + align256(sizeof(float) * c * l.in0p) +
            (keep ? 0 : (size_t)l.L * align256(sizeof(float) * c * l.W)) + 2 * align256(sizeof(float) * c * l.W) +
-           (size_t)l.HL * align256(sizeof(float) * c * l.HW);
+           (keep ? 0 : (size_t)l.HL * align256(sizeof(float) * c * l.HW));   // head Y (else in the reserve)
 }
 
 // --- backward workspace ------------------------------------------------------
@@ -1258,7 +1258,7 @@ size_t bwd_bytes(const Layout& l, long n, bool keep) {
     return weights_bytes(l) + 2 * align256(sizeof(float) * c * l.in0p) +
            (keep ? 1 : 3) * (size_t)l.L * align256(sizeof(float) * c * l.W) +  // Hdot (and Z, H)
            4 * align256(sizeof(float) * c * l.W) +                  // Hbar, Hdotbar, Zbar, Zdotbar
-           2 * (size_t)l.HL * align256(sizeof(float) * c * l.HW) +  // head Y, Ybar
+           (keep ? 1 : 2) * (size_t)l.HL * align256(sizeof(float) * c * l.HW) +  // head Ybar (and Y)
            align256(sizeof(float) * c) +                            // ybar3
            align256(sizeof(float) * 2 * kWgSplits * (size_t)l.W * wmax) +
            align256(sizeof(float) * kWgSplits * (size_t)l.W) +
@@ -1266,14 +1266,22 @@ size_t bwd_bytes(const Layout& l, long n, bool keep) {
            align256(sizeof(float) * (size_t)top_rows(c) * l.W);   // output layer column partials
 }
 
-// --- reserve of the training pair, [n][W] per layer: H_i = sp(Z_i) and the
-// normal sweep's adjoint S_i = df/dZ_i ------------------------------------------
+// --- reserve of the training pair, [n][W] per trunk layer: H_i = sp(Z_i) and
+// the normal sweep's adjoint S_i = df/dZ_i; then [n][HW] per head layer: its
+// output before the relu ----------------------------------------------------------
 size_t reserve_layer_bytes(const Layout& l, long n) { return align256(sizeof(float) * (size_t)n * l.W); }
-size_t reserve_bytes(const Layout& l, long n) { return 2 * (size_t)l.L * reserve_layer_bytes(l, n); }
+size_t reserve_head_bytes(const Layout& l, long n) { return align256(sizeof(float) * (size_t)n * l.HW); }
+size_t reserve_bytes(const Layout& l, long n) {
+    return 2 * (size_t)l.L * reserve_layer_bytes(l, n) + (size_t)l.HL * reserve_head_bytes(l, n);
+}
 float* reserve_h(void* r, const Layout& l, long n, int i) {
     return reinterpret_cast<float*>(static_cast<char*>(r) + (size_t)i * reserve_layer_bytes(l, n));
 }
 float* reserve_s(void* r, const Layout& l, long n, int i) { return reserve_h(r, l, n, l.L + i); }
+float* reserve_y(void* r, const Layout& l, long n, int h) {
+    return reinterpret_cast<float*>(static_cast<char*>(r) + 2 * (size_t)l.L * reserve_layer_bytes(l, n) +
+                                    (size_t)h * reserve_head_bytes(l, n));
+}
 
 int check_buffers(void* ws, size_t ws_bytes, size_t need, void* reserve, size_t reserve_bytes_, size_t rneed) {
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) {
@@ -1307,8 +1315,8 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
     float* Hw[16];
     for (int i = 0; i < l.L && !keep; ++i) Hw[i] = cur.take<float>((size_t)chunk * l.W);
     float* G[2] = {cur.take<float>((size_t)chunk * l.W), cur.take<float>((size_t)chunk * l.W)};
-    float* Yh[4];
-    for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
+    float* Yw[4];
+    for (int h = 0; h < l.HL && !keep; ++h) Yw[h] = cur.take<float>((size_t)chunk * l.HW);
     if ((rc = hip_status(prep_weights(l, P, w, st), "mlp weight prep"))) return rc;
 
     for (long c0 = 0; c0 < n; c0 += chunk) {
@@ -1329,12 +1337,16 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
         if (sdf)
             hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
                                (int)PRO_ID, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
-        if (refl) {
+        if (refl || keep) {
+            // head layers (the training forward keeps their outputs in the reserve)
+            float* Yh[4];
+            for (int h = 0; h < l.HL; ++h) Yh[h] = keep ? reserve_y(reserve, l, n, h) + c0 * l.HW : Yw[h];
             gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
             for (int h = 1; h < l.HL; ++h)
                 gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
-            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
-                               l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
+            if (refl)
+                hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
+                                   l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
         if (grad || keep) {
             // adjoint of f w.r.t. Z_{L-1}: S_{L-1} = sp'(Z_{L-1}) w_out, formed from
@@ -1402,8 +1414,8 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
     float* Hdb = cur.take<float>((size_t)chunk * l.W);
     float* Zb = cur.take<float>((size_t)chunk * l.W);
     float* Zdb = cur.take<float>((size_t)chunk * l.W);
-    float *Yh[4], *Ybh[4];
-    for (int h = 0; h < l.HL; ++h) Yh[h] = cur.take<float>((size_t)chunk * l.HW);
+    float *Yw[4], *Ybh[4];
+    for (int h = 0; h < l.HL && !keep; ++h) Yw[h] = cur.take<float>((size_t)chunk * l.HW);
     for (int h = 0; h < l.HL; ++h) Ybh[h] = cur.take<float>((size_t)chunk * l.HW);
     float* yb3 = cur.take<float>((size_t)chunk);
     float* part = cur.take<float>((size_t)2 * kWgSplits * l.W * wmax);
@@ -1444,10 +1456,15 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                                        H[i], Hd[i], l.W, m, l.W, l.W, beta), cx.mm, st);
         }
         float* Ht = H[l.L - 1];
-        // head forward
-        gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
-        for (int h = 1; h < l.HL; ++h)
-            gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
+        // head forward (the training backward reads it from the reserve)
+        float* Yh[4];
+        for (int h = 0; h < l.HL; ++h) Yh[h] = keep ? reserve_y(reserve, l, n, h) + c0 * l.HW : Yw[h];
+        if (!keep) {
+            gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
+            for (int h = 1; h < l.HL; ++h)
+                gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW,
+                                           l.HW, beta), cx);
+        }
         // head output: ybar3, Ybar_{HL-1}
         hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                            l.HW, P + l.o_whout, P + l.o_bhout, ga_, yb3, Ybh[l.HL - 1]);

@@ -161,7 +161,7 @@ def test_mlp_training_pair_checks_reserve_before_launch(R):
     net.params = ctypes.c_void_p(0x1000)
     n = 1000
     rb = L.rfvr_mlp_reserve_bytes(ctypes.byref(net), n)
-    assert rb == 2 * 8 * n * 256 * 4          # H and the sweep adjoint S per trunk layer
+    assert rb == (2 * 8 * 256 + 2 * 64) * n * 4   # H and the sweep adjoint S per trunk layer, the head outputs
     assert 0 < L.rfvr_mlp_forward_train_ws_bytes(ctypes.byref(net), n) < L.rfvr_mlp_forward_ws_bytes(ctypes.byref(net), n)
     assert 0 < L.rfvr_mlp_backward_train_ws_bytes(ctypes.byref(net), n) < L.rfvr_mlp_backward_ws_bytes(ctypes.byref(net), n)
     v, ws, big = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000), 1 << 40
