@@ -914,24 +914,37 @@ __global__ void k_pe_grad(long n, const float* __restrict__ xyz, float cx, float
     }
 }
 
-// out[p] = post(scale * (sum_m w[m] act(Y[p][m]) + b)); one wave per row
+// Row kernels: 16 lanes per row (four rows per wave), each lane taking every
+// 16th float4 of the row (widths are multiples of 64, rows 16-byte aligned),
+// then a fixed-order sum over the 16 lanes.
+constexpr int kRowLanes = 16;
+__device__ __forceinline__ float row_sum16(float acc) {
+#pragma unroll
+    for (int d = kRowLanes / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, kRowLanes);
+    return acc;
+}
+
+// out[p] = post(scale * (sum_m w[m] act(Y[p][m]) + b))
 //   act: 0 identity, 3 relu ; post: 0 identity, 1 sigmoid
 __global__ __launch_bounds__(256) void k_rowdot(long n, const float* __restrict__ Y, long ldy,
                                                 int M, int act, int post, const float* __restrict__ w,
                                                 const float* __restrict__ b, float scale, float beta,
                                                 float* __restrict__ out) {
-    const long p = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long p = gid / kRowLanes;          // the 16 lanes of a row exit together
+    const int l = (int)(gid % kRowLanes);
     if (p >= n) return;
     float acc = 0.0f;
-    for (int m = lane; m < M; m += 64) {
-        const float y = Y[p * ldy + m];
-        const float a = act == PRO_ID ? y : fmaxf(y, 0.0f);
-        acc = __builtin_fmaf(w[m], a, acc);
+    for (int m = 4 * l; m < M; m += 4 * kRowLanes) {
+        const float4 y = *reinterpret_cast<const float4*>(Y + p * ldy + m);
+        const bool r = act != PRO_ID;
+        acc = __builtin_fmaf(w[m], r ? fmaxf(y.x, 0.0f) : y.x, acc);
+        acc = __builtin_fmaf(w[m + 1], r ? fmaxf(y.y, 0.0f) : y.y, acc);
+        acc = __builtin_fmaf(w[m + 2], r ? fmaxf(y.z, 0.0f) : y.z, acc);
+        acc = __builtin_fmaf(w[m + 3], r ? fmaxf(y.w, 0.0f) : y.w, acc);
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-    if (lane == 0) {
+    acc = row_sum16(acc);
+    if (l == 0) {
         const float v = scale * (acc + b[0]);
         out[p] = post ? sigmoidf_(v) : v;
     }
@@ -944,17 +957,31 @@ __global__ __launch_bounds__(256) void k_head_out_bwd(long n, const float* __res
                                                       const float* __restrict__ g_a,
                                                       float* __restrict__ ybar3,
                                                       float* __restrict__ Ybar2) {
-    const long p = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long p = gid / kRowLanes;          // the 16 lanes of a row exit together
+    const int l = (int)(gid % kRowLanes);
     if (p >= n) return;
     float acc = 0.0f;
-    for (int m = lane; m < M; m += 64) acc = __builtin_fmaf(w[m], fmaxf(Y2[p * ld + m], 0.0f), acc);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    for (int m = 4 * l; m < M; m += 4 * kRowLanes) {
+        const float4 y = *reinterpret_cast<const float4*>(Y2 + p * ld + m);
+        acc = __builtin_fmaf(w[m], fmaxf(y.x, 0.0f), acc);
+        acc = __builtin_fmaf(w[m + 1], fmaxf(y.y, 0.0f), acc);
+        acc = __builtin_fmaf(w[m + 2], fmaxf(y.z, 0.0f), acc);
+        acc = __builtin_fmaf(w[m + 3], fmaxf(y.w, 0.0f), acc);
+    }
+    acc = row_sum16(acc);
     const float a = sigmoidf_(acc + b[0]);
     const float yb = g_a ? g_a[p] * a * (1.0f - a) : 0.0f;
-    if (lane == 0) ybar3[p] = yb;
-    for (int m = lane; m < M; m += 64) Ybar2[p * ld + m] = Y2[p * ld + m] > 0.0f ? yb * w[m] : 0.0f;
+    if (l == 0) ybar3[p] = yb;
+    for (int m = 4 * l; m < M; m += 4 * kRowLanes) {
+        const float4 y = *reinterpret_cast<const float4*>(Y2 + p * ld + m);
+        float4 o;
+        o.x = y.x > 0.0f ? yb * w[m] : 0.0f;
+        o.y = y.y > 0.0f ? yb * w[m + 1] : 0.0f;
+        o.z = y.z > 0.0f ? yb * w[m + 2] : 0.0f;
+        o.w = y.w > 0.0f ? yb * w[m + 3] : 0.0f;
+        *reinterpret_cast<float4*>(Ybar2 + p * ld + m) = o;
+    }
 }
 
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
@@ -1335,7 +1362,7 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
                                       cx);
         float* Ht = H[l.L - 1];
         if (sdf)
-            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
+            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * kRowLanes)), dim3(256), 0, st, m, Ht, (long)l.W, l.W,
                                (int)PRO_ID, 0, P + l.o_wout, P + l.o_bout, half, beta, sdf + c0);
         if (refl || keep) {
             // head layers (the training forward keeps their outputs in the reserve)
@@ -1345,7 +1372,7 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
             for (int h = 1; h < l.HL; ++h)
                 gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW, l.HW, beta), cx);
             if (refl)
-                hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
+                hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * kRowLanes)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                                    l.HW, (int)PRO_RELU, 1, P + l.o_whout, P + l.o_bhout, 1.0f, beta, refl + c0);
         }
         if (grad || keep) {
@@ -1466,7 +1493,7 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                                            l.HW, beta), cx);
         }
         // head output: ybar3, Ybar_{HL-1}
-        hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * 64)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
+        hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * kRowLanes)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,
                            l.HW, P + l.o_whout, P + l.o_bhout, ga_, yb3, Ybh[l.HL - 1]);
         colsum(Yh[l.HL - 1], nullptr, yb3, l.HW, m, l.HW, 1, beta, 1.0f, cpart, GP + l.o_whout, acc, st);
         colsum(yb3, nullptr, nullptr, 1, m, 1, 0, beta, 1.0f, cpart, GP + l.o_bhout, acc, st);
@@ -1750,7 +1777,7 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
             gemm<PRO_RELU, EPI_BIAS>(ga(A[i - 1], l.W, Wp[i], l.W, P + l.ob[i], A[i], l.W, m, l.W, l.W, beta), cx);
         float* At = A[l.layers - 1];
         if (!bwd) {
-            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * 64)), dim3(256), 0, st, m, At, (long)l.W, l.W,
+            hipLaunchKernelGGL(k_rowdot, dim3(blocks(m * kRowLanes)), dim3(256), 0, st, m, At, (long)l.W, l.W,
                                (int)PRO_RELU, 0, P + l.o_wout, P + l.o_bout, 1.0f, beta, logits + c0);
         } else {
             const float* g = g_logits + c0;
