@@ -891,26 +891,47 @@ __global__ void k_pe(long n, const float* __restrict__ xyz, float cx, float cy, 
     if (Xd) Xd[o] = dval;
 }
 
-// grad_x f = J_PE^T G0 (G0 = dF/dgamma, row stride ld)
+// grad_x f = J_PE^T G0 (G0 = dF/dgamma, row stride ld, a multiple of 4): 16
+// lanes per point, each taking every 16th float4 of the row (column e < 3:
+// x_hat_e, e = 3 + 6k + j: sin (j < 3) or cos (j >= 3) of 2^k pi x_hat_{j mod 3},
+// whose derivative is pi 2^k cos or -pi 2^k sin), then a fixed-order sum over
+// the 16 lanes per dimension
 __global__ void k_pe_grad(long n, const float* __restrict__ xyz, float cx, float cy, float cz,
                           float inv_half, int L, const float* __restrict__ G0, int ld,
                           float* __restrict__ grad) {
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long p = gid / 16;                  // the 16 lanes of a point exit together
+    const int l = (int)(gid % 16);
     if (p >= n) return;
-    const float c[3] = {cx, cy, cz};
-    const float* g = G0 + p * ld;
-    for (int d = 0; d < 3; ++d) {
-        const float xh = (xyz[3 * p + d] - c[d]) * inv_half;
-        float acc = g[d];
-        float scale = 1.0f;
-        for (int k = 0; k < L; ++k) {
-            float sn, cs;
-            sincospif(scale * xh, &sn, &cs);
-            const float w = 3.14159265358979f * scale;
-            acc += w * (cs * g[3 + 6 * k + d] - sn * g[3 + 6 * k + 3 + d]);
-            scale *= 2.0f;
+    const float xh[3] = {(xyz[3 * p] - cx) * inv_half, (xyz[3 * p + 1] - cy) * inv_half,
+                         (xyz[3 * p + 2] - cz) * inv_half};
+    const int ne = 3 + 6 * L;
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int m = 4 * l; m < ld && m < ne; m += 64) {
+        const float4 g4 = *reinterpret_cast<const float4*>(G0 + p * ld + m);
+        const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = m + q;
+            if (e >= ne) break;
+            if (e < 3) {
+                acc[e] += gv[q];
+            } else {
+                const int k = (e - 3) / 6, j = (e - 3) % 6, d = j % 3;
+                const float scale = (float)(1 << k);
+                const float t = scale * xh[d], w = 3.14159265358979f * scale;
+                acc[d] += j < 3 ? w * cospif(t) * gv[q] : -w * sinpif(t) * gv[q];
+            }
         }
-        grad[3 * p + d] = acc;   // d/dx = (d/dx_hat) / half, times f's half_size
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) acc[d] += __shfl_xor(acc[d], o, 16);
+    if (l == 0) {
+        grad[3 * p] = acc[0];   // d/dx = (d/dx_hat) / half, times f's half_size
+        grad[3 * p + 1] = acc[1];
+        grad[3 * p + 2] = acc[2];
     }
 }
 
@@ -1402,7 +1423,7 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
                 cur_g ^= 1;
             }
             if (grad)
-                hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m)), dim3(256), 0, st, m, x, net->centre[0],
+                hipLaunchKernelGGL(k_pe_grad, dim3(blocks(m * 16)), dim3(256), 0, st, m, x, net->centre[0],
                                    net->centre[1], net->centre[2], inv_half, net->pe_octaves, G[cur_g],
                                    l.in0p, grad + 3 * c0);
         }
