@@ -592,12 +592,13 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
         }
         const float Tr = P.tp + A.phi;
         const float T = fminf(fmaxf(Tr, 0.0f), 1.0f);
-        const float mT = (Tr >= 0.0f && Tr <= 1.0f) ? 1.0f : 0.0f;
+        const float Tm = T == Tr ? T : 0.0f;                   // T where the clamp is inactive
         const float gy = G * (y * y);
-        gb = __builtin_fmaf(gy * spec, T * T, gb);
-        gt = __builtin_fmaf(gy * P.b * spec, 2.0f * T * mT, gt);
+        const float gs = gy * spec, T2 = T * T;
+        gb = __builtin_fmaf(gs, T2, gb);
+        gt = __builtin_fmaf(gs, Tm, gt);                       // times 2 b after the loop
         if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
-            const float cn = gy * P.b * (T * T) * (4.0f * nd * y) * live;
+            const float cn = gy * T2 * (nd * y) * live;        // times 4 b after the loop
             gn0 = __builtin_fmaf(cn, fdx, gn0);
             gn1 = __builtin_fmaf(cn, fdy, gn1);
             gn2 = __builtin_fmaf(cn, fdz, gn2);
@@ -605,10 +606,11 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
     }
     if (j >= n_pts) return;
     g_b[j] = gb;
-    g_T[j] = gt;
-    g_n[3 * j] = gn0;
-    g_n[3 * j + 1] = gn1;
-    g_n[3 * j + 2] = gn2;
+    g_T[j] = 2.0f * P.b * gt;
+    const float b4 = 4.0f * P.b;
+    g_n[3 * j] = b4 * gn0;
+    g_n[3 * j + 1] = b4 * gn1;
+    g_n[3 * j + 2] = b4 * gn2;
 }
 
 __global__ void k_cheb_order(const ChebPlan* __restrict__ plan, int32_t* __restrict__ order) {
