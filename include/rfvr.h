@@ -63,7 +63,7 @@ extern "C" {
  * expansion), cut at the smallest order K in {24, 28, 32, 40, 48, 64} whose
  * truncation bound 2 (z/2)^K / K! / (1 - z/(2K+2)) (z = 2 pi
  * ((n_freq - 1)/2) df 2h/c, h the half-width of the widest interval) is below
- * 1e-7 of the sum of the term magnitudes.  The choice is made on the device
+ * 1e-6 of the sum of the term magnitudes.  The choice is made on the device
  * for every call; when no K qualifies (a range spread too wide for the band)
  * or K is not below n_freq, the per-frequency kernels run, which
  * RFVR_TERMS_DIRECT (and RFVR_PHASE_NAIVE32) also select.  Both evaluate the

@@ -49,7 +49,10 @@ namespace rfvr {
 
 constexpr int kChebKs[] = {24, 28, 32, 40, 48, 64};
 constexpr int kChebKMax = kChebMaxOrder;
-constexpr double kChebTol = 1e-7;
+// truncation bound, relative to the sum of the term magnitudes: of the order of
+// the FP32 rounding of the sums themselves (a lane's moments accumulate a
+// point split of ~2k points in FP32)
+constexpr double kChebTol = 1e-6;
 
 // ---------------------------------------------------------------------------
 // bounding box of a launch's points: per-block min / max, then the plan
