@@ -183,9 +183,9 @@ def proposal_study(args, dev):
     """Torus-behind-slab scene: full-space training (2^20 grid points) against
     proposal-sampled training (16 importance + 4 uniform depths per ray, 81,920
     points) and the untrained control (20 stratified uniform depths), from the
-    same initial network.  Every run is judged by the full-space render of its
+    same initial network.  Every run is evaluated by the full-space render of its
     network against the clean target: signal NRMSE and heatmap (filter output)
-    NRMSE on the full-space grid.  E* is the full-space run's judge error after
+    NRMSE on the full-space grid.  E* is the full-space run's reference error after
     its step budget; steps_to_e_star is the first evaluation at or below it.
     Prints one JSON line."""
     import numpy as np
@@ -209,7 +209,7 @@ def proposal_study(args, dev):
     out = {}
     for name, (make, n_steps) in runs.items():
         tr = make(torch.from_numpy(mlp_init(spec, cfg.seed)))
-        j = tr.judge(clean)
+        j = tr.evaluate(clean)
         curve = [(0, j["signal"], j["heatmap"])]
         step_ms = []
         for k in range(1, n_steps + 1):
@@ -220,17 +220,17 @@ def proposal_study(args, dev):
             e1.synchronize()
             step_ms.append(e0.elapsed_time(e1))
             if k % every == 0 or k == n_steps:
-                j = tr.judge(clean)
+                j = tr.evaluate(clean)
                 curve.append((k, j["signal"], j["heatmap"]))
-                print(f"[study] {name} step {k} judge signal {j['signal']:.4f} heatmap {j['heatmap']:.4f} "
+                print(f"[study] {name} step {k} reference signal {j['signal']:.4f} heatmap {j['heatmap']:.4f} "
                       f"s {tr.s:.1f} ({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
         out[name] = {"ms_per_step": float(np.median(step_ms[2:] if len(step_ms) > 4 else step_ms)),
                      "steps": n_steps, "final_s": tr.s,
-                     "judge": [[k, round(a, 5), round(b, 5)] for k, a, b in curve]}
-    e_star = {"signal": out["full_space"]["judge"][-1][1], "heatmap": out["full_space"]["judge"][-1][2]}
+                     "reference": [[k, round(a, 5), round(b, 5)] for k, a, b in curve]}
+    e_star = {"signal": out["full_space"]["reference"][-1][1], "heatmap": out["full_space"]["reference"][-1][2]}
     for name, r in out.items():
         for col, key in ((1, "signal"), (2, "heatmap")):
-            hit = next((row[0] for row in r["judge"] if row[col] <= e_star[key]), None)
+            hit = next((row[0] for row in r["reference"] if row[col] <= e_star[key]), None)
             r[f"steps_to_e_star_{key}"] = hit
             r[f"ms_to_e_star_{key}"] = None if hit is None else round(hit * r["ms_per_step"], 1)
     print(json.dumps({"study": "proposal_vs_full_space", "e_star": e_star, "eval_every": every,

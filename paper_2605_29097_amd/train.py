@@ -249,8 +249,8 @@ class Trainer:
         vh = self._s_v / (1 - b2 ** self.t)
         self.s = float(math.exp(math.log(self.s) - self.lr(c.lr_other) * mh / (math.sqrt(vh) + eps)))
 
-    # ------------------------------------------------------------------ judge
-    def judge_signal(self):
+    # ------------------------------------------------------- reference evaluation
+    def reference_signal(self):
         """Full-space render of the current network on the uniform grid of the
         configured sample cube (lensless primary rays, c.lines x c.n_z)."""
         c = self.cfg
@@ -262,15 +262,15 @@ class Trainer:
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
                       refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
-        self._judge_xyz = xyz
+        self._ref_xyz = xyz
         return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.spec_flags)
 
-    def judge(self, clean: torch.Tensor) -> dict:
+    def evaluate(self, clean: torch.Tensor) -> dict:
         """Judge errors of the full-space render against a clean target signal:
         signal NRMSE, and NRMSE of the filter output (heatmap) on the full-space
         grid."""
-        sig = self.judge_signal()
-        _, p, _, p_ref = R.mf_forward(self.ap, self._judge_xyz, sig, clean)
+        sig = self.reference_signal()
+        _, p, _, p_ref = R.mf_forward(self.ap, self._ref_xyz, sig, clean)
         return {"signal": nrmse(sig, clean), "heatmap": nrmse(p, p_ref)}
 
 

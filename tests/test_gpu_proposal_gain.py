@@ -3,7 +3,7 @@
 The SDF network is held at its geometric initialisation (a sphere of radius
 5 cm at the centre of a 20 cm sample cube) and only the proposal network is
 trained, on the blend weights T alpha that the library's own render returns at
-the proposal's samples.  The judge is a dense full-space render on the uniform
+the proposal's samples.  The reference is a dense full-space render on the uniform
 64 x 64 x 256 grid: its blend weights, binned into the proposal's 64 bins, mark
 the bins that hold at least half of a ray's maximum weight (the surface bins).
 
@@ -12,7 +12,7 @@ Checks, on the GPU path end to end:
     several times what the uniform pdf (the method without a proposal) puts there;
   * the drawn importance samples land in the surface bins at that rate;
   * the sum of binned blend weights seen by the proposal's samples approaches
-    the dense judge's, far closer than the same number of uniform samples.
+    the dense reference's, far closer than the same number of uniform samples.
 """
 import numpy as np
 import pytest
@@ -42,8 +42,8 @@ def _trainer(dev, train):
     return R, tr
 
 
-def _judge_bins(R, tr):
-    """Dense blend weights of the judge grid, binned: [n_ray, n_bins]."""
+def _reference_bins(R, tr):
+    """Dense blend weights of the reference grid, binned: [n_ray, n_bins]."""
     c = tr.cfg
     xyz, u, origin = R.sample_points(c.cube_centre, c.cube_side / 2, (0, 0, 1), c.lines[0], c.lines[1],
                                      c.n_z, mode=R.SAMPLE_GRID, device=tr.dev)
@@ -68,7 +68,7 @@ def test_trained_proposal_concentrates_samples_on_the_surface(dev):
     _say("proposal gain: 400 proposal-only steps, sphere SDF, s=300/m")
     R, tr = _trainer(dev, train=True)
     _, ctl = _trainer(dev, train=False)
-    W = _judge_bins(R, tr)
+    W = _reference_bins(R, tr)
     hit = W.max(1) > 1e-3                                  # rays that meet the sphere
     hot = (W >= 0.5 * W.max(1, keepdims=True)) & hit[:, None]
     assert hit.sum() > 500
@@ -97,7 +97,7 @@ def test_trained_proposal_concentrates_samples_on_the_surface(dev):
         in_hot = np.take_along_axis(hot, b, 1)[hit]
         frac_hot = float(in_hot[:, :].mean())
         # second-order weight sum sum_k T_k^2 alpha_k (the round-trip amplitude
-        # factor), vs the dense judge's value on the same rays
+        # factor), vs the dense reference's value on the same rays
         w2 = (trans * trans * alpha).view(n_ray, K).double().cpu().numpy().sum(1)
         return frac_hot, w2
 
