@@ -176,6 +176,42 @@ int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, in
                     void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Several scenes or scan planes in one call (Sec. 3 problem statement: an
+ * object is scanned from several radar planes, each with its own aperture
+ * and primary rays; Sec. "Number of Radar Scanning Planes").  scenes: host
+ * array of n_scenes >= 1 descriptors, each holding what the single-scene
+ * call takes (fields: render calls only; the matched filter runs at each
+ * scene's sample points, n_q = n_ray * n_z).  Arrays are packed in scene
+ * order: signals [sum_s n_meas_s * n_freq_s] complex, per-point arrays
+ * [sum_s n_ray_s * n_z_s] (times 3 for positions and gradients, times 2 for
+ * complex z), per-scene scalars (g_amp, g_s) [n_scenes].  Every scene is
+ * checked before anything is enqueued (an error names the scene); the scenes
+ * then run one after another on stream, reusing the workspace, whose size is
+ * the largest single-scene requirement.  Same errors as the single calls.
+ * ------------------------------------------------------------------------ */
+typedef struct rfvr_scene {
+    rfvr_aperture ap;
+    rfvr_samples  sm;
+    rfvr_fields   fl;
+} rfvr_scene;
+size_t rfvr_render_forward_batched_ws_bytes(int32_t n_scenes, const rfvr_scene* scenes);
+int rfvr_render_forward_batched(int32_t n_scenes, const rfvr_scene* scenes, uint32_t flags, float* signal,
+                                float* alpha_out, float* trans_out, void* ws, size_t ws_bytes,
+                                void* stream);
+size_t rfvr_render_backward_batched_ws_bytes(int32_t n_scenes, const rfvr_scene* scenes);
+int rfvr_render_backward_batched(int32_t n_scenes, const rfvr_scene* scenes, uint32_t flags,
+                                 const float* g_signal, float* g_sdf, float* g_grad, float* g_refl,
+                                 float* g_amp, float* g_s, void* ws, size_t ws_bytes, void* stream);
+size_t rfvr_mf_forward_batched_ws_bytes(int32_t n_scenes, const rfvr_scene* scenes, int two_signals);
+int rfvr_mf_forward_batched(int32_t n_scenes, const rfvr_scene* scenes, uint32_t flags, const float* signal,
+                            float* z, float* power, const float* signal2, float* z2, float* power2,
+                            void* ws, size_t ws_bytes, void* stream);
+size_t rfvr_mf_backward_batched_ws_bytes(int32_t n_scenes, const rfvr_scene* scenes);
+int rfvr_mf_backward_batched(int32_t n_scenes, const rfvr_scene* scenes, const float* z, const float* power,
+                             const float* g_power, uint32_t flags, float* g_signal, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * L2 heatmap loss (Sec. Overview, step 5):
  *   loss = (1/n) sum_q m_q (p_q - p*_q)^2 ,  g_p = 2 m (p - p*) / n
  * mask may be NULL (m = 1).  loss: [1] float output; g_p: [n] output or NULL.
@@ -258,6 +294,21 @@ size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp* net, int64_t n);
 int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const float* g_sdf,
                       const float* g_grad, const float* g_refl, uint32_t flags, float* g_params,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* Several networks in one call (one per scene, e.g. scenes trained side by
+ * side): nets host [n_nets], n host [n_nets] point counts (>= 1 each), points
+ * xyz packed [sum n][3]; outputs and upstream gradients packed per point as
+ * for the single calls; g_params packed by rfvr_mlp_param_count of each net.
+ * Every net is checked before anything is enqueued; the nets then run one
+ * after another on stream, reusing the workspace (the largest single-net
+ * requirement).  flags: as rfvr_mlp_backward, applied to every net. */
+size_t rfvr_mlp_forward_grouped_ws_bytes(int32_t n_nets, const rfvr_mlp* nets, const int64_t* n);
+int rfvr_mlp_forward_grouped(int32_t n_nets, const rfvr_mlp* nets, const float* xyz, const int64_t* n,
+                             float* sdf, float* grad, float* refl, void* ws, size_t ws_bytes, void* stream);
+size_t rfvr_mlp_backward_grouped_ws_bytes(int32_t n_nets, const rfvr_mlp* nets, const int64_t* n);
+int rfvr_mlp_backward_grouped(int32_t n_nets, const rfvr_mlp* nets, const float* xyz, const int64_t* n,
+                              const float* g_sdf, const float* g_grad, const float* g_refl, uint32_t flags,
+                              float* g_params, void* ws, size_t ws_bytes, void* stream);
 
 /* Training pair: the same two operations, sharing a caller-owned reserve
  * (device, 256-byte aligned, rfvr_mlp_reserve_bytes() bytes: for every trunk

@@ -1,5 +1,6 @@
 // C ABI of librfvr: argument validation, workspace layout and launches.
 // Every check runs before the first enqueue, so a failing call enqueues nothing.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -603,6 +604,196 @@ int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t 
     return hip_status(launch_adamw((long)n, p, g, m, v, lr, b1, b2, eps, wd, bc1, bc2,
                                    reinterpret_cast<hipStream_t>(stream)),
                       "adamw");
+}
+
+// ---------------------------------------------------------------- several scenes per call
+// Each scene runs through the single-scene entry point, in scene order on the
+// stream, with the packed arrays offset per scene; every scene is checked
+// first, so a failed call enqueues nothing.
+static int scene_error(int s, int rc) {
+    char msg[480];
+    snprintf(msg, sizeof msg, "%s", rfvr_last_error());
+    set_error("scene %d: %s", s, msg);
+    return rc;
+}
+
+static int check_scenes(int32_t n, const rfvr_scene* sc, bool fields) {
+    if (n < 1 || !sc) { set_error("n_scenes must be >= 1 and scenes non-NULL"); return RFVR_E_INVALID; }
+    for (int s = 0; s < n; ++s) {
+        int rc;
+        if ((rc = check_aperture(&sc[s].ap, false)) || (rc = check_samples(&sc[s].sm)) ||
+            (fields && (rc = check_fields(&sc[s].fl))))
+            return scene_error(s, rc);
+    }
+    return RFVR_OK;
+}
+
+static size_t scene_signal(const rfvr_scene& s) { return 2 * (size_t)s.ap.n_meas * s.ap.n_freq; }
+static size_t scene_points(const rfvr_scene& s) { return (size_t)s.sm.n_ray * s.sm.n_z; }
+extern "C++" {
+template <class T> static T* at(T* p, size_t off) { return p ? p + off : nullptr; }
+}
+
+size_t rfvr_render_forward_batched_ws_bytes(int32_t n, const rfvr_scene* sc) {
+    size_t m = 0;
+    for (int s = 0; sc && s < n; ++s) m = std::max(m, rfvr_render_forward_ws_bytes(&sc[s].ap, &sc[s].sm));
+    return m;
+}
+
+int rfvr_render_forward_batched(int32_t n, const rfvr_scene* sc, uint32_t flags, float* signal,
+                                float* alpha_out, float* trans_out, void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_scenes(n, sc, true)) || (rc = check_flags(flags))) return rc;
+    if (!signal) { set_error("signal output is NULL"); return RFVR_E_INVALID; }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_render_forward_batched_ws_bytes(n, sc)))) return rc;
+    size_t so = 0, po = 0;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = rfvr_render_forward(&sc[s].ap, &sc[s].sm, &sc[s].fl, flags, signal + so, at(alpha_out, po),
+                                      at(trans_out, po), ws, ws_bytes, stream)))
+            return scene_error(s, rc);
+        so += scene_signal(sc[s]);
+        po += scene_points(sc[s]);
+    }
+    return RFVR_OK;
+}
+
+size_t rfvr_render_backward_batched_ws_bytes(int32_t n, const rfvr_scene* sc) {
+    size_t m = 0;
+    for (int s = 0; sc && s < n; ++s) m = std::max(m, rfvr_render_backward_ws_bytes(&sc[s].ap, &sc[s].sm));
+    return m;
+}
+
+int rfvr_render_backward_batched(int32_t n, const rfvr_scene* sc, uint32_t flags, const float* g_signal,
+                                 float* g_sdf, float* g_grad, float* g_refl, float* g_amp, float* g_s,
+                                 void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_scenes(n, sc, true)) || (rc = check_flags(flags))) return rc;
+    if (!g_signal) { set_error("g_signal is NULL"); return RFVR_E_INVALID; }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_render_backward_batched_ws_bytes(n, sc)))) return rc;
+    size_t so = 0, po = 0;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = rfvr_render_backward(&sc[s].ap, &sc[s].sm, &sc[s].fl, flags, g_signal + so, at(g_sdf, po),
+                                       at(g_grad, 3 * po), at(g_refl, po), at(g_amp, (size_t)s), at(g_s, (size_t)s),
+                                       ws, ws_bytes, stream)))
+            return scene_error(s, rc);
+        so += scene_signal(sc[s]);
+        po += scene_points(sc[s]);
+    }
+    return RFVR_OK;
+}
+
+size_t rfvr_mf_forward_batched_ws_bytes(int32_t n, const rfvr_scene* sc, int two_signals) {
+    size_t m = 0;
+    for (int s = 0; sc && s < n; ++s)
+        m = std::max(m, rfvr_mf_forward_ws_bytes(&sc[s].ap, (int64_t)scene_points(sc[s]), two_signals));
+    return m;
+}
+
+int rfvr_mf_forward_batched(int32_t n, const rfvr_scene* sc, uint32_t flags, const float* signal, float* z,
+                            float* power, const float* signal2, float* z2, float* power2, void* ws,
+                            size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_scenes(n, sc, false))) return rc;
+    if (!signal) { set_error("signal is NULL"); return RFVR_E_INVALID; }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_mf_forward_batched_ws_bytes(n, sc, signal2 ? 1 : 0)))) return rc;
+    size_t so = 0, po = 0;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = rfvr_mf_forward(&sc[s].ap, sc[s].sm.xyz, (int64_t)scene_points(sc[s]), flags, signal + so,
+                                  at(z, 2 * po), at(power, po), at(signal2, so), at(z2, 2 * po), at(power2, po),
+                                  ws, ws_bytes, stream)))
+            return scene_error(s, rc);
+        so += scene_signal(sc[s]);
+        po += scene_points(sc[s]);
+    }
+    return RFVR_OK;
+}
+
+size_t rfvr_mf_backward_batched_ws_bytes(int32_t n, const rfvr_scene* sc) {
+    size_t m = 0;
+    for (int s = 0; sc && s < n; ++s)
+        m = std::max(m, rfvr_mf_backward_ws_bytes(&sc[s].ap, (int64_t)scene_points(sc[s])));
+    return m;
+}
+
+int rfvr_mf_backward_batched(int32_t n, const rfvr_scene* sc, const float* z, const float* power,
+                             const float* g_power, uint32_t flags, float* g_signal, void* ws, size_t ws_bytes,
+                             void* stream) {
+    int rc;
+    if ((rc = check_scenes(n, sc, false))) return rc;
+    if (!z || !power || !g_power || !g_signal) {
+        set_error("z, power, g_power and g_signal are required");
+        return RFVR_E_INVALID;
+    }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_mf_backward_batched_ws_bytes(n, sc)))) return rc;
+    size_t so = 0, po = 0;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = rfvr_mf_backward(&sc[s].ap, sc[s].sm.xyz, (int64_t)scene_points(sc[s]), z + 2 * po, power + po,
+                                   g_power + po, flags, g_signal + so, ws, ws_bytes, stream)))
+            return scene_error(s, rc);
+        so += scene_signal(sc[s]);
+        po += scene_points(sc[s]);
+    }
+    return RFVR_OK;
+}
+
+// ---------------------------------------------------------------- several networks per call
+static int check_nets(int32_t n, const rfvr_mlp* nets, const int64_t* cnt) {
+    if (n < 1 || !nets || !cnt) { set_error("n_nets must be >= 1, nets and n non-NULL"); return RFVR_E_INVALID; }
+    for (int s = 0; s < n; ++s) {
+        if (rfvr_mlp_param_count(&nets[s]) < 0) return scene_error(s, RFVR_E_INVALID);
+        if (cnt[s] < 1 || !nets[s].params) {
+            set_error("net %d: n >= 1 and params are required", s);
+            return RFVR_E_INVALID;
+        }
+    }
+    return RFVR_OK;
+}
+
+size_t rfvr_mlp_forward_grouped_ws_bytes(int32_t n, const rfvr_mlp* nets, const int64_t* cnt) {
+    size_t m = 0;
+    for (int s = 0; nets && cnt && s < n; ++s) m = std::max(m, rfvr_mlp_forward_ws_bytes(&nets[s], cnt[s]));
+    return m;
+}
+
+int rfvr_mlp_forward_grouped(int32_t n, const rfvr_mlp* nets, const float* xyz, const int64_t* cnt, float* sdf,
+                             float* grad, float* refl, void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_nets(n, nets, cnt))) return rc;
+    if (!xyz) { set_error("xyz is NULL"); return RFVR_E_INVALID; }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_mlp_forward_grouped_ws_bytes(n, nets, cnt)))) return rc;
+    size_t po = 0;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = rfvr_mlp_forward(&nets[s], xyz + 3 * po, cnt[s], at(sdf, po), at(grad, 3 * po), at(refl, po), ws,
+                                   ws_bytes, stream)))
+            return scene_error(s, rc);
+        po += (size_t)cnt[s];
+    }
+    return RFVR_OK;
+}
+
+size_t rfvr_mlp_backward_grouped_ws_bytes(int32_t n, const rfvr_mlp* nets, const int64_t* cnt) {
+    size_t m = 0;
+    for (int s = 0; nets && cnt && s < n; ++s) m = std::max(m, rfvr_mlp_backward_ws_bytes(&nets[s], cnt[s]));
+    return m;
+}
+
+int rfvr_mlp_backward_grouped(int32_t n, const rfvr_mlp* nets, const float* xyz, const int64_t* cnt,
+                              const float* g_sdf, const float* g_grad, const float* g_refl, uint32_t flags,
+                              float* g_params, void* ws, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_nets(n, nets, cnt))) return rc;
+    if (!xyz || !g_params) { set_error("xyz and g_params are required"); return RFVR_E_INVALID; }
+    if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }
+    if ((rc = check_ws(ws, ws_bytes, rfvr_mlp_backward_grouped_ws_bytes(n, nets, cnt)))) return rc;
+    size_t po = 0, go = 0;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = rfvr_mlp_backward(&nets[s], xyz + 3 * po, cnt[s], at(g_sdf, po), at(g_grad, 3 * po),
+                                    at(g_refl, po), flags, g_params + go, ws, ws_bytes, stream)))
+            return scene_error(s, rc);
+        po += (size_t)cnt[s];
+        go += (size_t)rfvr_mlp_param_count(&nets[s]);
+    }
+    return RFVR_OK;
 }
 
 }  // extern "C"

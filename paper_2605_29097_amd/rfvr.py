@@ -59,6 +59,10 @@ class CMlp(ctypes.Structure):
                 ("params", _vp)]
 
 
+class CScene(ctypes.Structure):
+    _fields_ = [("ap", CAperture), ("sm", CSamples), ("fl", CFields)]
+
+
 class CProposal(ctypes.Structure):
     _fields_ = [("pe_octaves", _c_i32), ("width", _c_i32), ("layers", _c_i32), ("centre", _c_f * 3),
                 ("half_size", _c_f), ("params", _vp)]
@@ -110,6 +114,21 @@ _SIGS = {
     "rfvr_bce": ([_c_i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
     "rfvr_adamw": ([_c_i64, _vp, _vp, _vp, _vp, _c_i64, _c_f, _c_f, _c_f, _c_f, _c_f, _vp], _c_i32),
     "rfvr_term_order_ws_bytes": ([_P(CAperture), _c_i64], _sz),
+    "rfvr_render_forward_batched_ws_bytes": ([_c_i32, _P(CScene)], _sz),
+    "rfvr_render_forward_batched": ([_c_i32, _P(CScene), _c_u32, _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_render_backward_batched_ws_bytes": ([_c_i32, _P(CScene)], _sz),
+    "rfvr_render_backward_batched": ([_c_i32, _P(CScene), _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                                     _c_i32),
+    "rfvr_mf_forward_batched_ws_bytes": ([_c_i32, _P(CScene), _c_i32], _sz),
+    "rfvr_mf_forward_batched": ([_c_i32, _P(CScene), _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                                _c_i32),
+    "rfvr_mf_backward_batched_ws_bytes": ([_c_i32, _P(CScene)], _sz),
+    "rfvr_mf_backward_batched": ([_c_i32, _P(CScene), _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_mlp_forward_grouped_ws_bytes": ([_c_i32, _P(CMlp), _P(_c_i64)], _sz),
+    "rfvr_mlp_forward_grouped": ([_c_i32, _P(CMlp), _vp, _P(_c_i64), _vp, _vp, _vp, _vp, _sz, _vp], _c_i32),
+    "rfvr_mlp_backward_grouped_ws_bytes": ([_c_i32, _P(CMlp), _P(_c_i64)], _sz),
+    "rfvr_mlp_backward_grouped": ([_c_i32, _P(CMlp), _vp, _P(_c_i64), _vp, _vp, _vp, _c_u32, _vp, _vp, _sz,
+                                   _vp], _c_i32),
     "rfvr_term_order": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _sz, _vp], _c_i32),
 }
 
@@ -358,7 +377,8 @@ class MLP:
 
 
 def mlp_reserve(net: MLP, n: int, device) -> torch.Tensor:
-    """Reserve of the training pair for n points (every trunk layer's Z and H)."""
+    """Reserve of the training pair for n points (every trunk layer's H and
+    sweep adjoint S, every head layer's output)."""
     return _ws(lib().rfvr_mlp_reserve_bytes(ctypes.byref(net.c()), int(n)), device)
 
 
@@ -403,6 +423,132 @@ def mlp_backward(net: MLP, xyz: torch.Tensor, g_sdf=None, g_grad=None, g_refl=No
                                              reserve.numel(), _ptr(ws), ws.numel(), _stream(stream)),
                "rfvr_mlp_backward_train")
     return gp
+
+
+# ----------------------------------------------------------------------------
+# several scenes (scan planes) or networks per call: lists in, packed for the
+# C ABI, per-scene views out
+# ----------------------------------------------------------------------------
+def _scenes(scenes):
+    """(ctypes array of CScene, keep-alive list) from [(Aperture, Samples, Fields or None)]."""
+    arr = (CScene * len(scenes))()
+    for k, (ap, sm, fl) in enumerate(scenes):
+        arr[k].ap = ap.c()
+        arr[k].sm = sm.c()
+        if fl is not None:
+            arr[k].fl = fl.c()
+    return arr
+
+
+def _split(t: torch.Tensor, sizes, tail=()):
+    out, o = [], 0
+    for n in sizes:
+        out.append(t[o:o + n].view((n,) + tuple(tail)) if tail else t[o:o + n])
+        o += n
+    return out
+
+
+def render_forward_batched(scenes, flags: int = 0, stream=None):
+    """Signals of several scenes [(Aperture, Samples, Fields)]: list of [n_meas, n_freq, 2]."""
+    dev = scenes[0][1].xyz.device
+    arr = _scenes(scenes)
+    sizes = [ap.n_meas * ap.n_freq for ap, _, _ in scenes]
+    sig = torch.empty(sum(sizes), 2, dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_render_forward_batched_ws_bytes(len(scenes), arr), dev)
+    _check(lib().rfvr_render_forward_batched(len(scenes), arr, flags, _ptr(sig), None, None, _ptr(ws), ws.numel(),
+                                             _stream(stream)), "rfvr_render_forward_batched")
+    return [v.view(ap.n_meas, ap.n_freq, 2) for v, (ap, _, _) in zip(_split(sig, sizes), scenes)]
+
+
+def render_backward_batched(scenes, g_signals, flags: int = 0, stream=None):
+    """Per-scene dicts (sdf, grad, refl, amp, s) of gradients, as render_backward."""
+    dev = scenes[0][1].xyz.device
+    arr = _scenes(scenes)
+    npts = [sm.xyz.shape[0] * sm.xyz.shape[1] for _, sm, _ in scenes]
+    n = sum(npts)
+    g_sig = torch.cat([g.reshape(-1, 2) for g in g_signals]).contiguous()
+    sdf = torch.empty(n, dtype=torch.float32, device=dev)
+    grad = torch.empty(n, 3, dtype=torch.float32, device=dev)
+    refl = torch.empty(n, dtype=torch.float32, device=dev)
+    amp = torch.empty(len(scenes), dtype=torch.float32, device=dev)
+    gs = torch.empty(len(scenes), dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_render_backward_batched_ws_bytes(len(scenes), arr), dev)
+    _check(lib().rfvr_render_backward_batched(len(scenes), arr, flags, _ptr(g_sig), _ptr(sdf), _ptr(grad), _ptr(refl),
+                                              _ptr(amp), _ptr(gs), _ptr(ws), ws.numel(), _stream(stream)),
+           "rfvr_render_backward_batched")
+    out = []
+    for k, (a, b, c) in enumerate(zip(_split(sdf, npts), _split(grad, npts), _split(refl, npts))):
+        shp = tuple(scenes[k][1].xyz.shape[:2])
+        out.append(dict(sdf=a.view(shp), grad=b.view(shp + (3,)), refl=c.view(shp), amp=amp[k:k + 1], s=gs[k:k + 1]))
+    return out
+
+
+def mf_forward_batched(scenes, signals, flags: int = 0, stream=None):
+    """Matched filter of each scene's signal at its sample points: list of (z [Q, 2], power [Q])."""
+    dev = scenes[0][1].xyz.device
+    arr = _scenes([(ap, sm, None) for ap, sm, *_ in scenes])
+    npts = [sm.xyz.shape[0] * sm.xyz.shape[1] for _, sm, *_ in scenes]
+    sig = torch.cat([s.reshape(-1, 2) for s in signals]).contiguous()
+    z = torch.empty(sum(npts), 2, dtype=torch.float32, device=dev)
+    p = torch.empty(sum(npts), dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_mf_forward_batched_ws_bytes(len(scenes), arr, 0), dev)
+    _check(lib().rfvr_mf_forward_batched(len(scenes), arr, flags, _ptr(sig), _ptr(z), _ptr(p), None, None, None,
+                                         _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mf_forward_batched")
+    return list(zip(_split(z, npts), _split(p, npts)))
+
+
+def mf_backward_batched(scenes, zs, powers, g_powers, flags: int = 0, stream=None):
+    """dL/dsignal of each scene: list of [n_meas, n_freq, 2]."""
+    dev = scenes[0][1].xyz.device
+    arr = _scenes([(ap, sm, None) for ap, sm, *_ in scenes])
+    sizes = [ap.n_meas * ap.n_freq for ap, *_ in scenes]
+    z = torch.cat([t.reshape(-1, 2) for t in zs]).contiguous()
+    p = torch.cat([t.reshape(-1) for t in powers]).contiguous()
+    gp = torch.cat([t.reshape(-1) for t in g_powers]).contiguous()
+    g = torch.empty(sum(sizes), 2, dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_mf_backward_batched_ws_bytes(len(scenes), arr), dev)
+    _check(lib().rfvr_mf_backward_batched(len(scenes), arr, _ptr(z), _ptr(p), _ptr(gp), flags, _ptr(g), _ptr(ws),
+                                          ws.numel(), _stream(stream)), "rfvr_mf_backward_batched")
+    return [v.view(ap.n_meas, ap.n_freq, 2) for v, (ap, *_) in zip(_split(g, sizes), scenes)]
+
+
+def _nets(nets, xyzs):
+    arr = (CMlp * len(nets))()
+    for k, net in enumerate(nets):
+        arr[k] = net.c()
+    cnt = (_c_i64 * len(nets))(*[x.numel() // 3 for x in xyzs])
+    return arr, cnt
+
+
+def mlp_forward_grouped(nets, xyzs, stream=None):
+    """(f, grad, a) of several networks, each at its own points: list of triples."""
+    dev = xyzs[0].device
+    arr, cnt = _nets(nets, xyzs)
+    n = [int(c) for c in cnt]
+    x = torch.cat([t.reshape(-1, 3) for t in xyzs]).contiguous()
+    f = torch.empty(sum(n), dtype=torch.float32, device=dev)
+    g = torch.empty(sum(n), 3, dtype=torch.float32, device=dev)
+    a = torch.empty(sum(n), dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_mlp_forward_grouped_ws_bytes(len(nets), arr, cnt), dev)
+    _check(lib().rfvr_mlp_forward_grouped(len(nets), arr, _ptr(x), cnt, _ptr(f), _ptr(g), _ptr(a), _ptr(ws),
+                                          ws.numel(), _stream(stream)), "rfvr_mlp_forward_grouped")
+    return list(zip(_split(f, n), _split(g, n), _split(a, n)))
+
+
+def mlp_backward_grouped(nets, xyzs, g_sdfs, g_grads, g_refls, flags: int = 0, stream=None):
+    """Parameter gradients of several networks: list of flat tensors."""
+    dev = xyzs[0].device
+    arr, cnt = _nets(nets, xyzs)
+    x = torch.cat([t.reshape(-1, 3) for t in xyzs]).contiguous()
+    cat = lambda ts, w: torch.cat([t.reshape(-1, w) for t in ts]).contiguous()
+    gf, gg, ga = cat(g_sdfs, 1), cat(g_grads, 3), cat(g_refls, 1)
+    counts = [net.param_count() for net in nets]
+    gp = torch.empty(sum(counts), dtype=torch.float32, device=dev)
+    ws = _ws(lib().rfvr_mlp_backward_grouped_ws_bytes(len(nets), arr, cnt), dev)
+    _check(lib().rfvr_mlp_backward_grouped(len(nets), arr, _ptr(x), cnt, _ptr(gf), _ptr(gg), _ptr(ga), flags,
+                                           _ptr(gp), _ptr(ws), ws.numel(), _stream(stream)),
+           "rfvr_mlp_backward_grouped")
+    return _split(gp, counts)
 
 
 def term_order(ap: Aperture, xyz: torch.Tensor, stream=None) -> int:

@@ -177,3 +177,27 @@ def test_mlp_training_pair_checks_reserve_before_launch(R):
         assert call(ctypes.c_void_p(0x200000), rb - 1) == -2
         assert call(ctypes.c_void_p(0x200001), rb) == -2            # misaligned
         assert b"reserve" in L.rfvr_last_error()
+
+
+def test_batched_calls_check_every_scene_before_launch(R):
+    """A bad scene anywhere in the array is reported, with its index, before
+    anything is enqueued (nothing here touches a GPU)."""
+    L = R.lib()
+    tx = ctypes.c_void_p(0x1000)
+    good_ap = R.CAperture(4, tx, None, 77e9, 1e8, 16)
+    bad_ap = R.CAperture(0, tx, None, 77e9, 1e8, 16)
+    sm = R.CSamples(2, 3, ctypes.c_void_p(0x2000), None, None)
+    fl = R.CFields(ctypes.c_void_p(0x3000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x3000), None, None, None,
+                   64.0, 1.0, None)
+    arr = (R.CScene * 3)()
+    for k in range(3):
+        arr[k].ap, arr[k].sm, arr[k].fl = (bad_ap if k == 2 else good_ap), sm, fl
+    v, ws = ctypes.c_void_p(0x4000), ctypes.c_void_p(0x100000)
+    assert L.rfvr_render_forward_batched(3, arr, 0, v, None, None, ws, 1 << 40, None) == -1
+    assert b"scene 2" in L.rfvr_last_error()
+    assert L.rfvr_mf_backward_batched(3, arr, v, v, v, 0, v, ws, 1 << 40, None) == -1
+    assert b"scene 2" in L.rfvr_last_error()
+    assert L.rfvr_render_forward_batched(0, arr, 0, v, None, None, ws, 1 << 40, None) == -1
+    assert L.rfvr_render_forward_batched_ws_bytes(2, arr) == max(
+        L.rfvr_render_forward_ws_bytes(ctypes.byref(arr[0].ap), ctypes.byref(arr[0].sm)),
+        L.rfvr_render_forward_ws_bytes(ctypes.byref(arr[1].ap), ctypes.byref(arr[1].sm)))
