@@ -372,6 +372,9 @@ int rfvr_proposal_backward(const rfvr_proposal* net, const float* xyz, int64_t n
                            const float* g_logits, uint32_t flags, float* g_params,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* Largest number of samples per ray of the proposal calls below. */
+#define RFVR_MAX_RAY_SAMPLES 1024
+
 /* Importance samples along the primary rays of `d` (its n_z and mode are
  * ignored).  logits: [n_ray][n_bins] at the centres of n_bins equal depth bins
  * over [c.w_p - h, c.w_p + h].  pdf_b = (sigmoid(z_b) + 1e-3) / sum; slot s of
@@ -380,7 +383,7 @@ int rfvr_proposal_backward(const rfvr_proposal* net, const float* xyz, int64_t n
  * uniform over the whole range, u = lo + (s + xi)(hi - lo)/n_uni; the others
  * invert the CDF at v = (s - n_uni + xi)/n_imp, linearly inside the bin.
  * Depths are sorted per ray (ties keep slot order).  n_bins <= 64,
- * n_imp + n_uni <= 64.  Outputs xyz [n_ray][n_uni+n_imp][3], u (or NULL),
+ * n_imp + n_uni <= RFVR_MAX_RAY_SAMPLES.  Outputs xyz [n_ray][n_uni+n_imp][3], u (or NULL),
  * ray_origin [n_ray][3] (or NULL). */
 int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32_t n_bins,
                            int32_t n_imp, int32_t n_uni, float* xyz, float* u, float* ray_origin,
@@ -389,7 +392,7 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
 /* Proposal targets: per ray, blend weights w_k = trans_k * alpha_k of the
  * render at depths u [n_ray][n_k] summed into n_bins equal bins of [lo, hi]
  * (W_b), t_b = min(1, W_b / max(max_b W_b, 1e-3)).  targets: [n_ray][n_bins].
- * n_k <= 64, n_bins <= 64. */
+ * n_k <= RFVR_MAX_RAY_SAMPLES, n_bins <= 64. */
 int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
                           const float* trans, float lo, float hi, int32_t n_bins, float* targets,
                           void* stream);

@@ -521,8 +521,9 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
                            int32_t n_imp, int32_t n_uni, float* xyz, float* u, float* ray_origin,
                            void* stream) {
     if (!d || !xyz || !logits) { set_error("descriptor, logits and xyz are required"); return RFVR_E_INVALID; }
-    if (n_bins < 1 || n_bins > 64 || n_imp < 0 || n_uni < 0 || n_imp + n_uni < 1 || n_imp + n_uni > 64) {
-        set_error("need 1 <= n_bins <= 64 and 1 <= n_imp + n_uni <= 64");
+    if (n_bins < 1 || n_bins > 64 || n_imp < 0 || n_uni < 0 || n_imp > RFVR_MAX_RAY_SAMPLES ||
+        n_uni > RFVR_MAX_RAY_SAMPLES || n_imp + n_uni < 1 || n_imp + n_uni > RFVR_MAX_RAY_SAMPLES) {
+        set_error("need 1 <= n_bins <= 64 and 1 <= n_imp + n_uni <= RFVR_MAX_RAY_SAMPLES (1024)");
         return RFVR_E_INVALID;
     }
     double basis[9];
@@ -536,8 +537,9 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
 int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
                           const float* trans, float lo, float hi, int32_t n_bins, float* targets,
                           void* stream) {
-    if (n_ray < 1 || n_k < 1 || n_k > 64 || n_bins < 1 || n_bins > 64 || !u || !alpha || !trans || !targets) {
-        set_error("need n_ray >= 1, 1 <= n_k <= 64, 1 <= n_bins <= 64 and all arrays");
+    if (n_ray < 1 || n_k < 1 || n_k > RFVR_MAX_RAY_SAMPLES || n_bins < 1 || n_bins > 64 || !u || !alpha ||
+        !trans || !targets) {
+        set_error("need n_ray >= 1, 1 <= n_k <= RFVR_MAX_RAY_SAMPLES (1024), 1 <= n_bins <= 64 and all arrays");
         return RFVR_E_INVALID;
     }
     if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi)) { set_error("need finite lo < hi"); return RFVR_E_INVALID; }

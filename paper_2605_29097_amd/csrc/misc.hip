@@ -163,8 +163,10 @@ hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, fl
 
 // ---------------------------------------------------------------------------
 // importance sampling from the proposal's bin logits: one wave per ray, lane b
-// holds bin b (CDF by a wave scan), lane s produces slot s, ranks sort in place
+// holds bin b (CDF by a wave scan); slot j = s*64 + lane sits in register s of
+// its lane (S registers cover up to 64*S slots), and ranks sort in place
 // ---------------------------------------------------------------------------
+template <int S>
 __global__ __launch_bounds__(256) void k_sample_importance(SampleArgs a, const float* __restrict__ logits,
                                                            int n_bins, int n_imp, int n_uni,
                                                            float* __restrict__ xyz, float* __restrict__ u_out,
@@ -192,35 +194,61 @@ __global__ __launch_bounds__(256) void k_sample_importance(SampleArgs a, const f
     p /= total;
     cdf /= total;
     const int K = n_uni + n_imp;
-    double u = hi + 1.0;                                       // lanes >= K sort last
-    double xi = 0.0;
-    if (lane < K) {
-        const uint64_t v64 = sm64_output(a.key, (uint64_t)(r * K + lane));
-        xi = (double)(v64 >> 40) * (1.0 / 16777216.0);
-        if (lane < n_uni) u = lo + ((double)lane + xi) * (hi - lo) / n_uni;
+    double u[S], v[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = s * 64 + lane;
+        u[s] = hi + 1.0;                                       // slots >= K sort last
+        v[s] = 0.0;
+        if (j < K) {
+            const uint64_t v64 = sm64_output(a.key, (uint64_t)(r * K + j));
+            const double xi = (double)(v64 >> 40) * (1.0 / 16777216.0);
+            if (j < n_uni) u[s] = lo + ((double)j + xi) * (hi - lo) / n_uni;
+            else v[s] = ((double)(j - n_uni) + xi) / n_imp;
+        }
     }
-    // inverse CDF for importance slots (every lane joins the shuffles)
-    {
-        const double v = (lane >= n_uni && lane < K) ? ((double)(lane - n_uni) + xi) / n_imp : 0.0;
-        int b = 0;
-        for (int q = 0; q < n_bins; ++q) b += (__shfl(cdf, q, 64) <= v) ? 1 : 0;
-        if (b > n_bins - 1) b = n_bins - 1;
-        const double below = __shfl(cdf, b > 0 ? b - 1 : 0, 64);   // all lanes shuffle
-        const double prev = b > 0 ? below : 0.0;
-        const double pb = __shfl(p, b, 64);
-        const double frac = fmin(fmax((v - prev) / pb, 0.0), 1.0);
-        if (lane >= n_uni && lane < K) u = lo + ((double)b + frac) * ((hi - lo) / n_bins);
+    // inverse CDF for importance slots: bin = number of CDF values <= v
+    int b[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) b[s] = 0;
+    for (int q = 0; q < n_bins; ++q) {
+        const double c = __shfl(cdf, q, 64);
+#pragma unroll
+        for (int s = 0; s < S; ++s) b[s] += (c <= v[s]) ? 1 : 0;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = s * 64 + lane;
+        const int bs = b[s] > n_bins - 1 ? n_bins - 1 : b[s];
+        const double below = __shfl(cdf, bs > 0 ? bs - 1 : 0, 64);   // all lanes shuffle
+        const double prev = bs > 0 ? below : 0.0;
+        const double pb = __shfl(p, bs, 64);
+        const double frac = fmin(fmax((v[s] - prev) / pb, 0.0), 1.0);
+        if (j >= n_uni && j < K) u[s] = lo + ((double)bs + frac) * ((hi - lo) / n_bins);
     }
     // rank = number of slots before this one in (u, slot) order
-    int rank = 0;
-    for (int t = 0; t < K; ++t) {
-        const double ut = __shfl(u, t, 64);
-        rank += (ut < u || (ut == u && t < lane)) ? 1 : 0;
+    int rank[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) rank[s] = 0;
+#pragma unroll
+    for (int s2 = 0; s2 < S; ++s2) {
+        for (int l = 0; l < 64; ++l) {
+            const int t = s2 * 64 + l;
+            if (t >= K) break;                                 // uniform
+            const double ut = __shfl(u[s2], l, 64);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                rank[s] += (ut < u[s] || (ut == u[s] && t < s * 64 + lane)) ? 1 : 0;
+        }
     }
-    if (lane < K) {
-        const long j = r * K + rank;
-        for (int c = 0; c < 3; ++c) xyz[3 * j + c] = (float)(o[c] + u * a.w[c]);
-        if (u_out) u_out[j] = (float)u;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = s * 64 + lane;
+        if (j < K) {
+            const long o_j = r * K + rank[s];
+            for (int c = 0; c < 3; ++c) xyz[3 * o_j + c] = (float)(o[c] + u[s] * a.w[c]);
+            if (u_out) u_out[o_j] = (float)u[s];
+        }
     }
     if (origin && lane < 3) origin[3 * r + lane] = (float)(o[lane] + a.off * a.w[lane]);
 }
@@ -253,8 +281,18 @@ hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basi
     };
     a.key = mix(d.seed + (d.step + 1ull) * 0x9E3779B97F4A7C15ull);
     const long n_ray = (long)d.n_ray_x * d.n_ray_y;
-    hipLaunchKernelGGL(k_sample_importance, dim3((unsigned)((n_ray + 3) / 4)), dim3(256), 0, st, a, logits,
-                       n_bins, n_imp, n_uni, xyz, u, origin);
+    const dim3 grid((unsigned)((n_ray + 3) / 4));
+    const int K = n_imp + n_uni;
+    if (K <= 64)
+        hipLaunchKernelGGL(k_sample_importance<1>, grid, dim3(256), 0, st, a, logits, n_bins, n_imp, n_uni, xyz, u, origin);
+    else if (K <= 128)
+        hipLaunchKernelGGL(k_sample_importance<2>, grid, dim3(256), 0, st, a, logits, n_bins, n_imp, n_uni, xyz, u, origin);
+    else if (K <= 256)
+        hipLaunchKernelGGL(k_sample_importance<4>, grid, dim3(256), 0, st, a, logits, n_bins, n_imp, n_uni, xyz, u, origin);
+    else if (K <= 512)
+        hipLaunchKernelGGL(k_sample_importance<8>, grid, dim3(256), 0, st, a, logits, n_bins, n_imp, n_uni, xyz, u, origin);
+    else                                                       // K <= RFVR_MAX_RAY_SAMPLES = 1024
+        hipLaunchKernelGGL(k_sample_importance<16>, grid, dim3(256), 0, st, a, logits, n_bins, n_imp, n_uni, xyz, u, origin);
     return hipGetLastError();
 }
 
@@ -317,6 +355,8 @@ hipError_t launch_sample_naive(const rfvr_sample_desc& d, const double basis[9],
 }
 
 // proposal targets: bin the blend weights T alpha of each ray, normalise by the max
+// per ray, one wave: sample k = s*64 + lane in register s (S >= n_k / 64)
+template <int S>
 __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, const float* __restrict__ u,
                                                           const float* __restrict__ alpha,
                                                           const float* __restrict__ trans, float lo, float hi,
@@ -324,20 +364,32 @@ __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, co
     const long r = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (r >= n_ray) return;
-    float w = 0.0f;
-    int bk = -1;
-    if (lane < n_k) {
-        const long j = r * n_k + lane;
-        w = trans[j] * alpha[j];
-        // bin decision in FP64, evaluated in the same order as a double-precision reference
-        int b = (int)floor(((double)u[j] - (double)lo) / ((double)hi - (double)lo) * (double)n_bins);
-        bk = b < 0 ? 0 : (b > n_bins - 1 ? n_bins - 1 : b);
+    // sample k = s*64 + lane sits in register s of its lane
+    float w[S];
+    int bk[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k = s * 64 + lane;
+        w[s] = 0.0f;
+        bk[s] = -1;
+        if (k < n_k) {
+            const long j = r * n_k + k;
+            w[s] = trans[j] * alpha[j];
+            // bin decision in FP64, evaluated in the same order as a double-precision reference
+            const int b = (int)floor(((double)u[j] - (double)lo) / ((double)hi - (double)lo) * (double)n_bins);
+            bk[s] = b < 0 ? 0 : (b > n_bins - 1 ? n_bins - 1 : b);
+        }
     }
+    // lane b sums the weights of its bin in sample order
     float W = 0.0f;
-    for (int k = 0; k < n_k; ++k) {
-        const int bb = __shfl(bk, k, 64);
-        const float ww = __shfl(w, k, 64);
-        if (bb == lane) W += ww;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        for (int l = 0; l < 64; ++l) {
+            if (s * 64 + l >= n_k) break;                      // uniform
+            const int bb = __shfl(bk[s], l, 64);
+            const float ww = __shfl(w[s], l, 64);
+            if (bb == lane) W += ww;
+        }
     }
     float mx = lane < n_bins ? W : 0.0f;
 #pragma unroll
@@ -347,8 +399,15 @@ __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, co
 
 hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
                                    float lo, float hi, int n_bins, float* targets, hipStream_t st) {
-    hipLaunchKernelGGL(k_proposal_targets, dim3((unsigned)((n_ray + 3) / 4)), dim3(256), 0, st, n_ray, n_k, u,
-                       alpha, trans, lo, hi, n_bins, targets);
+    const dim3 grid((unsigned)((n_ray + 3) / 4));
+#define RFVR_PT(S_) hipLaunchKernelGGL(k_proposal_targets<S_>, grid, dim3(256), 0, st, n_ray, n_k, u, alpha, \
+                                       trans, lo, hi, n_bins, targets)
+    if (n_k <= 64) RFVR_PT(1);
+    else if (n_k <= 128) RFVR_PT(2);
+    else if (n_k <= 256) RFVR_PT(4);
+    else if (n_k <= 512) RFVR_PT(8);
+    else RFVR_PT(16);                                          // n_k <= RFVR_MAX_RAY_SAMPLES = 1024
+#undef RFVR_PT
     return hipGetLastError();
 }
 

@@ -62,3 +62,15 @@ def small_sphere_centre(seed: int) -> np.ndarray:
     """Sphere centre of the small parity workload: (0,0,0.30) + U(-5,5) mm per axis."""
     rng = np.random.default_rng(seed)
     return np.array([0.0, 0.0, 0.30]) + rng.uniform(-5e-3, 5e-3, 3)
+
+
+def batched8_scene(k: int) -> dict:
+    """Scene ``k`` (0..7) of the eight-scene workload: aperture side (antennas
+    per axis at 2 mm), cube centre on the axis at a seeded range in
+    [0.25, 0.40] m, the SNR of its measured signal, and the seed of its union
+    of primitives (``synth.scenes.random_union_scene``)."""
+    c = CONFIGS["batched8"]
+    rng = np.random.default_rng(8000 + k)
+    rc = float(rng.uniform(c["range_lo"], c["range_hi"]))
+    snr = float(rng.uniform(c["snr_lo"], c["snr_hi"]))
+    return dict(side=c["ap_sides"][k], centre=(0.0, 0.0, rc), half=0.5 * c["cube_side"], snr_db=snr, seed=k)

@@ -190,16 +190,26 @@ class Union:
         return refls[sdfs.argmin(axis=0)]
 
 
-def scene_fields(scene, xyz: np.ndarray):
-    """(sdf, grad, refl) of an analytic scene at points ``xyz`` as float32."""
-    sdf, grad = scene.eval(np.asarray(xyz, np.float64))
-    if isinstance(scene, Union):
-        refl = scene.refl_at(xyz)
-    else:
-        refl = np.full(sdf.shape, scene.refl)
-    return (np.ascontiguousarray(sdf, np.float32),
-            np.ascontiguousarray(grad, np.float32),
-            np.ascontiguousarray(refl, np.float32))
+def scene_fields(scene, xyz: np.ndarray, chunk: int = 1 << 16):
+    """(sdf, grad, refl) of an analytic scene at points ``xyz`` as float32.
+
+    Evaluated in chunks of ``chunk`` points (every operation is per point, so
+    the values do not depend on the chunking; small chunks keep the float64
+    temporaries in cache, which matters at millions of points)."""
+    xyz = np.asarray(xyz)
+    shp = xyz.shape[:-1]
+    flat = xyz.reshape(-1, 3)
+    n = flat.shape[0]
+    sdf = np.empty(n, np.float32)
+    grad = np.empty((n, 3), np.float32)
+    refl = np.empty(n, np.float32)
+    for a in range(0, n, chunk):
+        x = np.asarray(flat[a:a + chunk], np.float64)
+        f, g = scene.eval(x)
+        sdf[a:a + chunk] = f
+        grad[a:a + chunk] = g
+        refl[a:a + chunk] = scene.refl_at(x) if isinstance(scene, Union) else scene.refl
+    return sdf.reshape(shp), grad.reshape(shp + (3,)), refl.reshape(shp)
 
 
 def complex_noise(clean: np.ndarray, snr_db: float, seed: int) -> np.ndarray:

@@ -84,6 +84,10 @@ SAMPLE_CASES = [
     (3, 11, 37, 27, 0, (0.1, -0.2, 1.0)),
     (4, 4, 1, 0, 9, (0.0, 0.0, 1.0)),
     (9, 2, 64, 60, 4, (0.0, 1.0, 0.05)),
+    # more slots than lanes: several slots per lane, ragged last register
+    (5, 3, 64, 192, 64, (0.0, 0.0, 1.0)),
+    (3, 2, 17, 700, 1, (0.2, 0.1, 1.0)),
+    (2, 2, 64, 1000, 24, (0.0, 0.0, 1.0)),        # RFVR_MAX_RAY_SAMPLES exactly
 ]
 
 
@@ -131,7 +135,8 @@ def test_sample_importance_full_size(dev):
     assert err <= 4e-8
 
 
-@pytest.mark.parametrize("n_ray,n_k,n_bins", [(5, 64, 64), (300, 20, 64), (33, 7, 13)])
+@pytest.mark.parametrize("n_ray,n_k,n_bins", [(5, 64, 64), (300, 20, 64), (33, 7, 13), (40, 256, 64),
+                                               (6, 1000, 37), (3, 1024, 64)])
 def test_proposal_targets(dev, n_ray, n_k, n_bins):
     _say(f"proposal_targets n_ray={n_ray} n_k={n_k} n_bins={n_bins}")
     R = _R()
@@ -142,7 +147,9 @@ def test_proposal_targets(dev, n_ray, n_k, n_bins):
     edges = (lo.astype(np.float64) + np.arange(n_bins + 1) * (hi - lo) / n_bins).astype(np.float32)
     u[0, : min(n_k, n_bins + 1)] = edges[: min(n_k, n_bins + 1)]
     u[0] = np.sort(u[0])
-    alpha = rng.uniform(0, 1, (n_ray, n_k)).astype(np.float32)
+    # past 64 samples, small alphas keep the transmittance (and with it the
+    # weight of every register of samples) away from zero
+    alpha = rng.uniform(0, 1.0 if n_k <= 64 else 4.0 / n_k, (n_ray, n_k)).astype(np.float32)
     trans = np.cumprod(1 - alpha, 1).astype(np.float32)
     alpha[min(2, n_ray - 1)] = 1e-6                # floor case
     t = R.proposal_targets(_t(u, dev), _t(alpha, dev), _t(trans, dev), float(lo), float(hi), n_bins)
@@ -175,7 +182,10 @@ def test_proposal_entry_points_reject_bad_arguments(dev):
         R.sample_importance((0, 0, 0.3), 0.1, (0, 0, 1), 2, 2, z, 8, 2)       # 65 bins
     z = torch.zeros(4, 8, device=dev)
     with pytest.raises(R.RfvrError):
-        R.sample_importance((0, 0, 0.3), 0.1, (0, 0, 1), 2, 2, z, 60, 5)      # 65 samples
+        R.sample_importance((0, 0, 0.3), 0.1, (0, 0, 1), 2, 2, z, 1000, 25)   # 1025 samples
+    u = torch.zeros(2, 1025, device=dev)
+    with pytest.raises(R.RfvrError):
+        R.proposal_targets(u, u, u, 0.2, 0.4, 64)                             # 1025 samples
     bad = _net(R, ProposalSpec(layers=5), np.zeros(10, np.float32), dev)
     assert bad.param_count() == -1
     with pytest.raises(R.RfvrError):

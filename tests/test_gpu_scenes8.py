@@ -1,0 +1,292 @@
+"""The eight-scene workload at its full size, through the batched and grouped
+entry points, checked on sampled outputs against the FP64 oracle.
+
+Workload: 8 scenes, planar monostatic apertures of 32^2 .. 64^2 antennas at
+2 mm (19,292 in all), 256 frequencies 77-81 GHz, 128 x 128 primary rays x
+(192 importance + 64 uniform) depths = 2^22 points per scene in a 25 cm cube
+at a seeded range of 0.25-0.40 m, each scene a seeded union of 1-3 spheres,
+boxes and tori; one network per scene (8 x 256 softplus trunk, 2 x 64 head)
+with split-BF16 matrix operands.  The proposal's bin logits stand in for a
+trained proposal: high within about 1 cm of a surface, plus seeded noise.
+
+Both sides take the same float32 inputs: the points are the oracle sampler's
+depths rounded to float32 (the GPU sampler is held to those depths on every
+ray), the fields are the analytic scene's at those points.  Sampled outputs:
+  * importance depths of every ray of every scene (float32 rounding);
+  * the rendered signal at 3 measurements x 4 frequencies per scene;
+  * the filter output at 32 query points per scene;
+  * the filter adjoint at 2 measurements x 4 frequencies per scene;
+  * the render adjoint along one surface-crossing ray per scene (per-ray
+    quantities depend on that ray alone);
+  * network outputs at 32 points per network, and the parameter gradient with
+    upstream gradients on 16 points per network (zero elsewhere: the gradient
+    is then the oracle's over those points).
+Bars: 1e-4 RMS relative (FP32 path) for the render and filter; 1e-2 for the
+networks (BF16 path)."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Case, as_complex, rel_rms
+from oracle import mlp as omlp
+from oracle import proposal as op
+from oracle import render as orc
+from oracle.sampling import sample_points as o_sample_points
+from synth import MLPSpec, freq_grid, mlp_init, planar_aperture, random_union_scene, scene_fields
+from synth.configs import PITCH, batched8_scene, config
+
+pytestmark = pytest.mark.gpu
+
+CFG = config("batched8")
+N_SCENES = len(CFG["ap_sides"])
+N_FREQ = CFG["n_freq"]
+NX, NY = CFG["lines"]
+N_IMP, N_UNI = CFG["n_imp"], CFG["n_uni"]
+N_BINS = 64
+STEP = 3
+FREQ_SEL = np.array([0, 85, 170, 255])          # strided: f0 + 85 n df, n = 0..3
+W = np.array([0.0, 0.0, 1.0])
+
+
+def _R():
+    from paper_2605_29097_amd import rfvr as R
+    R.lib()
+    return R
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _bin_logits(union, origin, lo, hi, rng):
+    """[n_ray, 64] logits at the bin centres: -4 + 10 exp(-(f / 1 cm)^2) + N(0, 1)."""
+    ub = lo + (np.arange(N_BINS) + 0.5) * (hi - lo) / N_BINS
+    xb = origin[:, None, :] + ub[None, :, None] * W
+    f, _, _ = scene_fields(union, xb)
+    z = -4.0 + 10.0 * np.exp(-(f.astype(np.float64) / 0.01) ** 2) + rng.normal(0.0, 1.0, f.shape)
+    return z.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def scenes(dev):
+    f0, df = freq_grid(N_FREQ)
+    out = []
+    for k in range(N_SCENES):
+        g = batched8_scene(k)
+        _say(f"scene {k}: aperture {g['side']}^2, range {g['centre'][2]:.3f} m (host preparation)")
+        union = random_union_scene(g["seed"], g["centre"])
+        h = g["half"]
+        lo, hi = g["centre"][2] - h, g["centre"][2] + h
+        _, _, origin = o_sample_points(g["centre"], h, W, NX, NY, 1)
+        logits = _bin_logits(union, origin, lo, hi, np.random.default_rng(100 + k))
+        u_ref, _ = op.importance_depths(logits.astype(np.float64), lo, hi, N_IMP, N_UNI, k, STEP)
+        x32 = (origin[:, None, :] + u_ref[..., None] * W).astype(np.float32)
+        sdf, grad, refl = scene_fields(union, x32)
+        tx = planar_aperture(g["side"], g["side"], PITCH)
+        case = Case(tx, f0, df, N_FREQ, x32, sdf, grad, refl, s=CFG["s"], amp=CFG["amp"])
+        out.append(dict(k=k, geo=g, lo=lo, hi=hi, logits=logits, u_ref=u_ref, origin=origin, case=case,
+                        gpu=case.g(dev)))
+    return out
+
+
+def _o_ap(c, sel=None, freqs=None):
+    """Oracle aperture over measurements `sel` and the strided frequencies."""
+    tx = (c.tx if sel is None else c.tx[sel]).astype(np.float64)
+    if freqs is None:
+        return orc.Aperture(tx=tx, f0=c.f0, df=c.df, n_freq=c.n_freq)
+    stride = int(freqs[1] - freqs[0])
+    assert np.array_equal(freqs, freqs[0] + stride * np.arange(len(freqs)))
+    return orc.Aperture(tx=tx, f0=c.f0 + freqs[0] * c.df, df=stride * c.df, n_freq=len(freqs))
+
+
+def _chunked_sum(fn, n, parts=16):
+    """sum of fn(idx) over `parts` disjoint index chunks of range(n), evaluated
+    in threads (the oracle's C core releases the interpreter lock)."""
+    chunks = np.array_split(np.arange(n), parts)
+    with ThreadPoolExecutor(parts) as ex:
+        return sum(ex.map(fn, chunks))
+
+
+def _render_oracle(c, sel, freqs):
+    """Oracle signal at measurements `sel` and the strided frequencies.  The
+    signal is a sum over primary rays whose transmittance depends on the ray
+    alone, so it is the sum of the oracle's renders of disjoint ray chunks."""
+    ap = _o_ap(c, sel, freqs)
+    return _chunked_sum(lambda r: orc.render(ap, c.xyz[r], c.o_fields(rays=r)), c.xyz.shape[0])
+
+
+def _mf_adjoint_oracle(c, sel, freqs, z, p, gp):
+    """Oracle filter adjoint at measurements `sel` and the strided frequencies:
+    a sum over query points, so the sum over disjoint chunks of them."""
+    ap = _o_ap(c, sel, freqs)
+    xq = c.xyz.reshape(-1, 3)
+    return _chunked_sum(lambda q: orc.mf_adjoint(ap, xq[q], z[q], p[q], gp[q]), xq.shape[0])
+
+
+def _meas_sel(side):
+    n = side * side
+    return np.array([0, (side // 2) * side + side // 2, n - 1])      # two corners and the centre
+
+
+def test_importance_sampling_every_ray(dev, scenes):
+    R = _R()
+    worst = 0.0
+    for S in scenes:
+        g = S["geo"]
+        _say(f"sample_importance scene {S['k']}: 128x128 rays, 64 bins, {N_IMP} + {N_UNI} samples")
+        xyz, u, o = R.sample_importance(g["centre"], g["half"], tuple(W), NX, NY, _t(S["logits"], dev), N_IMP,
+                                        N_UNI, seed=S["k"], step=STEP)
+        ug = u.cpu().numpy()
+        du = float(np.abs(ug.astype(np.float64) - S["u_ref"]).max())
+        x_ref = S["origin"][:, None, :] + S["u_ref"][..., None] * W
+        dx = float(np.abs(xyz.cpu().numpy().astype(np.float64) - x_ref).max())
+        worst = max(worst, du, dx)
+        assert np.all(np.diff(ug, axis=1) >= 0)
+        # float32 rounding of depths below 0.53 m is at most 3e-8
+        assert du <= 6e-8 and dx <= 6e-8, (S["k"], du, dx)
+        del xyz, u, o, x_ref
+    print(f"max |du|, |dx| over 8 x 2^22 samples: {worst:.2e} m")
+
+
+def test_render_forward_batched_sampled(dev, scenes):
+    R = _R()
+    _say("render_forward_batched, 8 scenes x 2^22 points")
+    for S in scenes:
+        ap, sm, _ = S["gpu"]
+        K = R.term_order(ap, sm.xyz)
+        print(f"scene {S['k']}: moment order {K}")
+        assert K > 0                                  # the Chebyshev-moment kernels run
+    sig = R.render_forward_batched([S["gpu"] for S in scenes])
+    for S, s in zip(scenes, sig):
+        c = S["case"]
+        sel = _meas_sel(S["geo"]["side"])
+        ref = _render_oracle(c, sel, FREQ_SEL)
+        got = as_complex(s)[sel][:, FREQ_SEL]
+        e = rel_rms(got, ref)
+        print(f"scene {S['k']}: signal rms rel {e:.2e}")
+        assert e <= 1e-4, S["k"]
+
+
+def test_mf_forward_batched_sampled(dev, scenes):
+    R = _R()
+    _say("mf_forward_batched, 8 scenes x 2^22 query points")
+    rng = np.random.default_rng(21)
+    sigs = []
+    for S in scenes:
+        n_meas = S["case"].tx.shape[0]
+        sigs.append((rng.normal(size=(n_meas, N_FREQ)) + 1j * rng.normal(size=(n_meas, N_FREQ))).astype(np.complex64))
+    zp = R.mf_forward_batched([S["gpu"] for S in scenes],
+                              [_t(np.stack([s.real, s.imag], -1), dev) for s in sigs])
+    for S, s, (z, p) in zip(scenes, sigs, zp):
+        c = S["case"]
+        q = rng.choice(NX * NY * (N_IMP + N_UNI), 32, replace=False)
+        zr, pr = orc.mf(_o_ap(c), c.xyz.reshape(-1, 3)[q], s.astype(np.complex128))
+        e = rel_rms(as_complex(z)[q], zr)
+        ep = rel_rms(p.cpu().numpy()[q], pr)
+        print(f"scene {S['k']}: z rms rel {e:.2e}, P rms rel {ep:.2e}")
+        assert e <= 1e-4 and ep <= 1e-4, S["k"]
+
+
+def test_mf_backward_batched_sampled(dev, scenes):
+    R = _R()
+    _say("mf_backward_batched, 8 scenes x 2^22 query points")
+    rng = np.random.default_rng(22)
+    nq = NX * NY * (N_IMP + N_UNI)
+    zs, ps, gps = [], [], []
+    for _ in scenes:
+        z = (rng.normal(size=nq) + 1j * rng.normal(size=nq)).astype(np.complex64)
+        zs.append(z)
+        ps.append(np.abs(z).astype(np.float32))
+        gps.append(rng.normal(size=nq).astype(np.float32))
+    g = R.mf_backward_batched([S["gpu"] for S in scenes], [_t(np.stack([z.real, z.imag], -1), dev) for z in zs],
+                              [_t(p, dev) for p in ps], [_t(gp, dev) for gp in gps])
+    for S, z, p, gp, gk in zip(scenes, zs, ps, gps, g):
+        c = S["case"]
+        sel = _meas_sel(S["geo"]["side"])[[0, 2]]
+        gr = _mf_adjoint_oracle(c, sel, FREQ_SEL, z.astype(np.complex128), p.astype(np.float64),
+                                gp.astype(np.float64))
+        e = rel_rms(as_complex(gk)[sel][:, FREQ_SEL], gr)
+        print(f"scene {S['k']}: g_signal rms rel {e:.2e}")
+        assert e <= 1e-4, S["k"]
+
+
+def test_render_backward_batched_sampled_rays(dev, scenes):
+    R = _R()
+    _say("render_backward_batched, 8 scenes x 2^22 points")
+    rng = np.random.default_rng(23)
+    gss = []
+    for S in scenes:
+        n_meas = S["case"].tx.shape[0]
+        gss.append((rng.normal(size=(n_meas, N_FREQ)) + 1j * rng.normal(size=(n_meas, N_FREQ))).astype(np.complex64))
+    out = R.render_backward_batched([S["gpu"] for S in scenes],
+                                    [_t(np.stack([g.real, g.imag], -1), dev) for g in gss])
+    for S, gs, o in zip(scenes, gss, out):
+        c = S["case"]
+        ray = int(np.abs(c.sdf).min(axis=1).argmin())          # a ray that crosses a surface
+        rays = np.array([ray])
+        ref = orc.render_adjoint(_o_ap(c), c.xyz[rays], c.o_fields(rays=rays), gs.astype(np.complex128))
+        for key in ("sdf", "grad", "refl"):
+            e = rel_rms(o[key].cpu().numpy()[rays], ref[key])
+            print(f"scene {S['k']} ray {ray}: {key} rms rel {e:.2e}")
+            assert e <= 1e-4, (S["k"], key)
+
+
+def test_networks_grouped_sampled(dev, scenes):
+    R = _R()
+    _say("mlp_forward_grouped / mlp_backward_grouped, 8 networks x 2^22 points, split BF16")
+    m = CFG["mlp"]
+    nets, specs, params, xs = [], [], [], []
+    for S in scenes:
+        g = S["geo"]
+        spec = MLPSpec(n_layers=m["n_layers"], width=m["width"], pe_octaves=m["pe_octaves"],
+                       head_width=m["head_width"], head_layers=m["head_layers"], beta=m["beta"],
+                       centre=g["centre"], half_size=g["half"])
+        p = mlp_init(spec, S["k"]).astype(np.float64)
+        p = (p + 0.3 * np.random.default_rng(S["k"] + 1000).normal(size=p.shape) / np.sqrt(spec.width)).astype(np.float32)
+        specs.append(spec)
+        params.append(p)
+        nets.append(R.MLP(params=_t(p, dev), n_layers=spec.n_layers, width=spec.width, pe_octaves=spec.pe_octaves,
+                          head_width=spec.head_width, head_layers=spec.head_layers, beta=spec.beta,
+                          centre=spec.centre, half_size=spec.half_size, precision=R.PREC_BF16X3))
+        xs.append(S["gpu"][1].xyz.reshape(-1, 3))
+    outs = R.mlp_forward_grouped(nets, xs)
+    rng = np.random.default_rng(24)
+    n = NX * NY * (N_IMP + N_UNI)
+    for S, spec, p, (f, gr, a) in zip(scenes, specs, params, outs):
+        idx = rng.choice(n, 32, replace=False)
+        x = S["case"].xyz.reshape(-1, 3)[idx].astype(np.float64)
+        fr, grr, ar = omlp.forward(p.astype(np.float64), spec, x)
+        ef, eg, ea = (rel_rms(f.cpu().numpy()[idx], fr), rel_rms(gr.cpu().numpy()[idx], grr),
+                      rel_rms(a.cpu().numpy()[idx], ar))
+        print(f"net {S['k']}: f {ef:.2e}, grad {eg:.2e}, a {ea:.2e}")
+        assert ef <= 1e-2 and eg <= 1e-2 and ea <= 1e-2, S["k"]
+    del outs
+    # upstream gradients on 16 points per network, zero elsewhere
+    idxs, gfs, ggs, gas = [], [], [], []
+    for _ in scenes:
+        idx = rng.choice(n, 16, replace=False)
+        gf = torch.zeros(n, device=dev)
+        gg = torch.zeros(n, 3, device=dev)
+        ga = torch.zeros(n, device=dev)
+        vf, vg, va = rng.normal(size=16), rng.normal(size=(16, 3)), rng.normal(size=16)
+        gf[idx] = _t(vf.astype(np.float32), dev)
+        gg[idx] = _t(vg.astype(np.float32), dev)
+        ga[idx] = _t(va.astype(np.float32), dev)
+        idxs.append((idx, vf, vg, va))
+        gfs.append(gf)
+        ggs.append(gg)
+        gas.append(ga)
+    gps = R.mlp_backward_grouped(nets, xs, gfs, ggs, gas)
+    for S, spec, p, (idx, vf, vg, va), gp in zip(scenes, specs, params, idxs, gps):
+        x = S["case"].xyz.reshape(-1, 3)[idx].astype(np.float64)
+        ref = omlp.backward(p.astype(np.float64), spec, x, vf.astype(np.float32).astype(np.float64),
+                            vg.astype(np.float32).astype(np.float64), va.astype(np.float32).astype(np.float64))
+        e = rel_rms(gp.cpu().numpy(), ref)
+        print(f"net {S['k']}: parameter gradient rms rel {e:.2e}")
+        assert e <= 1e-2, S["k"]
