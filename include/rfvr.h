@@ -187,7 +187,9 @@ int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, in
  * complex z), per-scene scalars (g_amp, g_s) [n_scenes].  Every scene is
  * checked before anything is enqueued (an error names the scene); the scenes
  * then run one after another on stream, reusing the workspace, whose size is
- * the largest single-scene requirement.  Same errors as the single calls.
+ * the largest single-scene requirement.  Same errors as the single calls; a
+ * HIP runtime error (RFVR_E_HIP) in a later scene leaves the earlier scenes'
+ * work enqueued.
  * ------------------------------------------------------------------------ */
 typedef struct rfvr_scene {
     rfvr_aperture ap;
@@ -301,7 +303,9 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
  * for the single calls; g_params packed by rfvr_mlp_param_count of each net.
  * Every net is checked before anything is enqueued; the nets then run one
  * after another on stream, reusing the workspace (the largest single-net
- * requirement).  flags: as rfvr_mlp_backward, applied to every net. */
+ * requirement); as for the batched scenes, only a HIP runtime error can stop
+ * the loop after earlier nets.  flags: as rfvr_mlp_backward, applied to every
+ * net. */
 size_t rfvr_mlp_forward_grouped_ws_bytes(int32_t n_nets, const rfvr_mlp* nets, const int64_t* n);
 int rfvr_mlp_forward_grouped(int32_t n_nets, const rfvr_mlp* nets, const float* xyz, const int64_t* n,
                              float* sdf, float* grad, float* refl, void* ws, size_t ws_bytes, void* stream);

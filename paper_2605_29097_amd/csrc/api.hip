@@ -610,8 +610,10 @@ int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t 
 
 // ---------------------------------------------------------------- several scenes per call
 // Each scene runs through the single-scene entry point, in scene order on the
-// stream, with the packed arrays offset per scene; every scene is checked
-// first, so a failed call enqueues nothing.
+// stream, with the packed arrays offset per scene.  Every scene's descriptors
+// are checked first as the single-scene call checks them, and the arguments
+// shared by all scenes fail on the first scene, so an invalid call enqueues
+// nothing; only a HIP runtime error can stop the loop after earlier scenes.
 static int scene_error(int s, int rc) {
     char msg[480];
     snprintf(msg, sizeof msg, "%s", rfvr_last_error());
@@ -619,13 +621,23 @@ static int scene_error(int s, int rc) {
     return rc;
 }
 
-static int check_scenes(int32_t n, const rfvr_scene* sc, bool fields) {
+// what each single-scene call checks of its descriptors, for every scene
+enum SceneCall { SC_RENDER_FWD, SC_RENDER_BWD, SC_FILTER };
+static int check_scenes(int32_t n, const rfvr_scene* sc, SceneCall call) {
     if (n < 1 || !sc) { set_error("n_scenes must be >= 1 and scenes non-NULL"); return RFVR_E_INVALID; }
     for (int s = 0; s < n; ++s) {
         int rc;
         if ((rc = check_aperture(&sc[s].ap, false)) || (rc = check_samples(&sc[s].sm)) ||
-            (fields && (rc = check_fields(&sc[s].fl))))
+            (call != SC_FILTER && (rc = check_fields(&sc[s].fl))))
             return scene_error(s, rc);
+        if (call == SC_RENDER_BWD && sc[s].sm.point_weight) {
+            set_error("scene %d: point weights are supported by rfvr_render_forward only", s);
+            return RFVR_E_UNSUPPORTED;
+        }
+        if (call == SC_FILTER && (int64_t)sc[s].sm.n_ray * sc[s].sm.n_z > (int64_t)1 << 40) {
+            set_error("scene %d: n_ray * n_z too large", s);
+            return RFVR_E_INVALID;
+        }
     }
     return RFVR_OK;
 }
@@ -645,7 +657,7 @@ size_t rfvr_render_forward_batched_ws_bytes(int32_t n, const rfvr_scene* sc) {
 int rfvr_render_forward_batched(int32_t n, const rfvr_scene* sc, uint32_t flags, float* signal,
                                 float* alpha_out, float* trans_out, void* ws, size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_scenes(n, sc, true)) || (rc = check_flags(flags))) return rc;
+    if ((rc = check_scenes(n, sc, SC_RENDER_FWD)) || (rc = check_flags(flags))) return rc;
     if (!signal) { set_error("signal output is NULL"); return RFVR_E_INVALID; }
     if ((rc = check_ws(ws, ws_bytes, rfvr_render_forward_batched_ws_bytes(n, sc)))) return rc;
     size_t so = 0, po = 0;
@@ -669,7 +681,7 @@ int rfvr_render_backward_batched(int32_t n, const rfvr_scene* sc, uint32_t flags
                                  float* g_sdf, float* g_grad, float* g_refl, float* g_amp, float* g_s,
                                  void* ws, size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_scenes(n, sc, true)) || (rc = check_flags(flags))) return rc;
+    if ((rc = check_scenes(n, sc, SC_RENDER_BWD)) || (rc = check_flags(flags))) return rc;
     if (!g_signal) { set_error("g_signal is NULL"); return RFVR_E_INVALID; }
     if ((rc = check_ws(ws, ws_bytes, rfvr_render_backward_batched_ws_bytes(n, sc)))) return rc;
     size_t so = 0, po = 0;
@@ -695,7 +707,7 @@ int rfvr_mf_forward_batched(int32_t n, const rfvr_scene* sc, uint32_t flags, con
                             float* power, const float* signal2, float* z2, float* power2, void* ws,
                             size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_scenes(n, sc, false))) return rc;
+    if ((rc = check_scenes(n, sc, SC_FILTER))) return rc;
     if (!signal) { set_error("signal is NULL"); return RFVR_E_INVALID; }
     if ((rc = check_ws(ws, ws_bytes, rfvr_mf_forward_batched_ws_bytes(n, sc, signal2 ? 1 : 0)))) return rc;
     size_t so = 0, po = 0;
@@ -721,7 +733,7 @@ int rfvr_mf_backward_batched(int32_t n, const rfvr_scene* sc, const float* z, co
                              const float* g_power, uint32_t flags, float* g_signal, void* ws, size_t ws_bytes,
                              void* stream) {
     int rc;
-    if ((rc = check_scenes(n, sc, false))) return rc;
+    if ((rc = check_scenes(n, sc, SC_FILTER))) return rc;
     if (!z || !power || !g_power || !g_signal) {
         set_error("z, power, g_power and g_signal are required");
         return RFVR_E_INVALID;

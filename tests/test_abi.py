@@ -198,6 +198,15 @@ def test_batched_calls_check_every_scene_before_launch(R):
     assert L.rfvr_mf_backward_batched(3, arr, v, v, v, 0, v, ws, 1 << 40, None) == -1
     assert b"scene 2" in L.rfvr_last_error()
     assert L.rfvr_render_forward_batched(0, arr, 0, v, None, None, ws, 1 << 40, None) == -1
+    # what only the single-scene adjoint rejects is checked for every scene too
+    pw = R.CSamples(2, 3, ctypes.c_void_p(0x2000), None, ctypes.c_void_p(0x5000))
+    arr[2].ap, arr[1].sm = good_ap, pw
+    assert L.rfvr_render_backward_batched(3, arr, 0, v, v, v, v, v, v, ws, 1 << 40, None) == -3
+    assert b"scene 1" in L.rfvr_last_error()
+    arr[1].sm = R.CSamples(1 << 30, 1 << 11, ctypes.c_void_p(0x2000), None, None)
+    assert L.rfvr_mf_forward_batched(3, arr, 0, v, v, v, None, None, None, ws, 1 << 40, None) == -1
+    assert b"scene 1" in L.rfvr_last_error()
+    arr[1].sm = sm
     assert L.rfvr_render_forward_batched_ws_bytes(2, arr) == max(
         L.rfvr_render_forward_ws_bytes(ctypes.byref(arr[0].ap), ctypes.byref(arr[0].sm)),
         L.rfvr_render_forward_ws_bytes(ctypes.byref(arr[1].ap), ctypes.byref(arr[1].sm)))
