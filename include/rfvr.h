@@ -43,6 +43,17 @@ extern "C" {
 #define RFVR_E_UNSUPPORTED -3   /* valid but not implemented (bistatic apertures)   */
 #define RFVR_E_HIP         -4   /* HIP launch / runtime error                       */
 
+/* Size limits of one call: at most RFVR_MAX_POINTS points (samples, query
+ * points, network inputs, elements of the per-point calls; for the per-antenna
+ * sampler antennas x rays x depths), RFVR_MAX_RAYS primary rays and
+ * RFVR_MAX_MEAS measurements, so that every launch stays well inside the 2^32
+ * work-items of a one-dimensional grid (one wave per ray in the per-ray
+ * kernels).  Larger inputs are split by the caller; a call beyond a limit
+ * returns RFVR_E_INVALID and a workspace query returns 0. */
+#define RFVR_MAX_POINTS 2147483647LL  /* 2^31 - 1 */
+#define RFVR_MAX_RAYS   33554432      /* 2^25     */
+#define RFVR_MAX_MEAS   1048576       /* 2^20     */
+
 /* flags */
 #define RFVR_SPEC_CLAMP     0x0u  /* specular factor max(0, w_o . w_r)   (default)  */
 #define RFVR_SPEC_RAW       0x1u  /* w_o . w_r                                       */

@@ -28,7 +28,10 @@ static constexpr int kMaxFreq = 8192;
 
 static int check_aperture(const rfvr_aperture* ap, bool allow_rx) {
     if (!ap) { set_error("aperture descriptor is NULL"); return RFVR_E_INVALID; }
-    if (ap->n_meas < 1) { set_error("n_meas must be >= 1 (got %d)", ap->n_meas); return RFVR_E_INVALID; }
+    if (ap->n_meas < 1 || ap->n_meas > RFVR_MAX_MEAS) {
+        set_error("n_meas must be in [1, RFVR_MAX_MEAS] (got %d)", ap->n_meas);
+        return RFVR_E_INVALID;
+    }
     if (ap->n_freq < 1 || ap->n_freq > kMaxFreq) {
         set_error("n_freq must be in [1, %d] (got %d)", kMaxFreq, ap->n_freq);
         return RFVR_E_INVALID;
@@ -49,6 +52,10 @@ static int check_samples(const rfvr_samples* sm) {
     if (!sm) { set_error("samples descriptor is NULL"); return RFVR_E_INVALID; }
     if (sm->n_ray < 1 || sm->n_z < 1) {
         set_error("n_ray and n_z must be >= 1 (got %d, %d)", sm->n_ray, sm->n_z);
+        return RFVR_E_INVALID;
+    }
+    if (sm->n_ray > RFVR_MAX_RAYS || (int64_t)sm->n_ray * sm->n_z > RFVR_MAX_POINTS) {
+        set_error("n_ray <= RFVR_MAX_RAYS and n_ray * n_z <= RFVR_MAX_POINTS are required");
         return RFVR_E_INVALID;
     }
     if (!sm->xyz) { set_error("samples xyz is NULL"); return RFVR_E_INVALID; }
@@ -196,6 +203,17 @@ size_t rfvr_render_forward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples*
     return ws_render_forward(make_geom(ap, sm->n_ray, sm->n_z));
 }
 
+// element counts of the per-point calls
+static bool count_ok(int64_t n) { return n >= 1 && n <= RFVR_MAX_POINTS; }
+
+static int check_count(const char* what, int64_t n) {
+    if (!count_ok(n)) {
+        set_error("%s must be in [1, RFVR_MAX_POINTS] (got %lld)", what, (long long)n);
+        return RFVR_E_INVALID;
+    }
+    return RFVR_OK;
+}
+
 int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const rfvr_fields* fl,
                         uint32_t flags, float* signal, float* alpha_out, float* trans_out,
                         void* ws, size_t ws_bytes, void* stream) {
@@ -321,7 +339,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
 
 // ---------------------------------------------------------------- matched filter
 size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_signals) {
-    if (check_aperture(ap, false) || n_q < 1) return 0;
+    if (check_aperture(ap, false) || !count_ok(n_q)) return 0;
     return ws_mf_forward(ap, (long)n_q, two_signals);
 }
 
@@ -334,8 +352,8 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
         set_error("only RFVR_PHASE_NAIVE32 and RFVR_TERMS_DIRECT are meaningful here");
         return RFVR_E_INVALID;
     }
-    if (n_q < 1 || !xyz_q || !signal) { set_error("n_q >= 1, xyz_q and signal are required"); return RFVR_E_INVALID; }
-    if (n_q > (int64_t)1 << 40) { set_error("n_q too large"); return RFVR_E_INVALID; }
+    if (!xyz_q || !signal) { set_error("xyz_q and signal are required"); return RFVR_E_INVALID; }
+    if ((rc = check_count("n_q", n_q))) return rc;
     const int two = signal2 ? 1 : 0;
     if ((rc = check_ws(ws, ws_bytes, ws_mf_forward(ap, (long)n_q, two)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -379,7 +397,7 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
 }
 
 size_t rfvr_mf_backward_ws_bytes(const rfvr_aperture* ap, int64_t n_q) {
-    if (check_aperture(ap, false) || n_q < 1) return 0;
+    if (check_aperture(ap, false) || !count_ok(n_q)) return 0;
     return ws_mf_backward(ap, (long)n_q);
 }
 
@@ -388,10 +406,11 @@ int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, c
                      void* ws, size_t ws_bytes, void* stream) {
     int rc;
     if ((rc = check_aperture(ap, false)) || (rc = check_flags(flags))) return rc;
-    if (n_q < 1 || !xyz_q || !z || !power || !g_power || !g_signal) {
-        set_error("n_q >= 1 and xyz_q, z, power, g_power, g_signal are required");
+    if (!xyz_q || !z || !power || !g_power || !g_signal) {
+        set_error("xyz_q, z, power, g_power and g_signal are required");
         return RFVR_E_INVALID;
     }
+    if ((rc = check_count("n_q", n_q))) return rc;
     if ((rc = check_ws(ws, ws_bytes, ws_mf_backward(ap, (long)n_q)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     RenderGeom g = make_geom(ap, 1, 1);
@@ -430,7 +449,7 @@ int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, c
 
 // ---------------------------------------------------------------- term evaluation order
 size_t rfvr_term_order_ws_bytes(const rfvr_aperture* ap, int64_t n_pts) {
-    if (check_aperture(ap, false) || n_pts < 1) return 0;
+    if (check_aperture(ap, false) || !count_ok(n_pts)) return 0;
     return align256(sizeof(AntRec) * ap->n_meas) + ws_cheb((long)n_pts, ap->n_meas);
 }
 
@@ -438,7 +457,8 @@ int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, in
                     size_t ws_bytes, void* stream) {
     int rc;
     if ((rc = check_aperture(ap, false))) return rc;
-    if (n_pts < 1 || !xyz || !order) { set_error("n_pts >= 1, xyz and order are required"); return RFVR_E_INVALID; }
+    if (!xyz || !order) { set_error("xyz and order are required"); return RFVR_E_INVALID; }
+    if ((rc = check_count("n_pts", n_pts))) return rc;
     if ((rc = check_ws(ws, ws_bytes, rfvr_term_order_ws_bytes(ap, n_pts)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const RenderGeom g = make_geom(ap, 1, 1);
@@ -454,14 +474,15 @@ int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, in
 
 // ---------------------------------------------------------------- loss
 size_t rfvr_loss_ws_bytes(int64_t n) {
-    if (n < 1) return 0;
+    if (!count_ok(n)) return 0;
     return align256(sizeof(double) * loss_blocks((long)n));
 }
 
 int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* mask, float* loss,
                  float* g_p, void* ws, size_t ws_bytes, void* stream) {
-    if (n < 1 || !p || !p_star || !loss) { set_error("n >= 1, p, p_star and loss are required"); return RFVR_E_INVALID; }
+    if (!p || !p_star || !loss) { set_error("p, p_star and loss are required"); return RFVR_E_INVALID; }
     int rc;
+    if ((rc = check_count("n", n))) return rc;
     if ((rc = check_ws(ws, ws_bytes, rfvr_loss_ws_bytes(n)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int nb = loss_blocks((long)n);
@@ -473,7 +494,10 @@ int rfvr_loss_l2(int64_t n, const float* p, const float* p_star, const float* ma
 
 // ---------------------------------------------------------------- sampling
 static int sample_basis(const rfvr_sample_desc* d, double basis[9]) {
-    if (d->n_ray_x < 1 || d->n_ray_y < 1) { set_error("ray counts must be >= 1"); return RFVR_E_INVALID; }
+    if (d->n_ray_x < 1 || d->n_ray_y < 1 || (int64_t)d->n_ray_x * d->n_ray_y > RFVR_MAX_RAYS) {
+        set_error("ray counts must be >= 1 with n_ray_x * n_ray_y <= RFVR_MAX_RAYS");
+        return RFVR_E_INVALID;
+    }
     if (!(d->half_extent > 0.0f) || !std::isfinite(d->half_extent)) { set_error("half_extent must be finite and > 0"); return RFVR_E_INVALID; }
     if (!std::isfinite(d->plane_offset)) { set_error("plane_offset must be finite"); return RFVR_E_INVALID; }
     double w[3] = {d->primary_dir[0], d->primary_dir[1], d->primary_dir[2]};
@@ -496,7 +520,10 @@ static int sample_basis(const rfvr_sample_desc* d, double basis[9]) {
 int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* ray_origin,
                        void* stream) {
     if (!d || !xyz) { set_error("descriptor and xyz are required"); return RFVR_E_INVALID; }
-    if (d->n_z < 1) { set_error("n_z must be >= 1"); return RFVR_E_INVALID; }
+    if (d->n_z < 1 || (int64_t)d->n_ray_x * d->n_ray_y * d->n_z > RFVR_MAX_POINTS) {
+        set_error("n_z must be >= 1 and rays * n_z <= RFVR_MAX_POINTS");
+        return RFVR_E_INVALID;
+    }
     if (d->mode != RFVR_SAMPLE_GRID && d->mode != RFVR_SAMPLE_STRATIFIED) { set_error("unknown sampling mode %d", d->mode); return RFVR_E_INVALID; }
     double basis[9];
     int rc;
@@ -508,11 +535,18 @@ int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* r
 
 int rfvr_sample_naive(const rfvr_sample_desc* d, const float* tx, int32_t n_ant, float* xyz, float* jac,
                       void* stream) {
-    if (!d || !tx || !xyz || n_ant < 1) { set_error("descriptor, tx, xyz and n_ant >= 1 are required"); return RFVR_E_INVALID; }
+    if (!d || !tx || !xyz || n_ant < 1 || n_ant > RFVR_MAX_MEAS) {
+        set_error("descriptor, tx, xyz and n_ant in [1, RFVR_MAX_MEAS] are required");
+        return RFVR_E_INVALID;
+    }
     if (d->n_z < 1) { set_error("n_z must be >= 1"); return RFVR_E_INVALID; }
     double basis[9];
     int rc;
     if ((rc = sample_basis(d, basis))) return rc;
+    if ((int64_t)n_ant * d->n_ray_x * d->n_ray_y * d->n_z > RFVR_MAX_POINTS) {
+        set_error("n_ant * rays * n_z must not exceed RFVR_MAX_POINTS");
+        return RFVR_E_INVALID;
+    }
     return hip_status(launch_sample_naive(*d, basis, tx, n_ant, xyz, jac, reinterpret_cast<hipStream_t>(stream)),
                       "naive sampling");
 }
@@ -529,6 +563,10 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
     double basis[9];
     int rc;
     if ((rc = sample_basis(d, basis))) return rc;
+    if ((int64_t)d->n_ray_x * d->n_ray_y * (n_imp + n_uni) > RFVR_MAX_POINTS) {
+        set_error("rays * (n_imp + n_uni) must not exceed RFVR_MAX_POINTS");
+        return RFVR_E_INVALID;
+    }
     return hip_status(launch_sample_importance(*d, basis, logits, n_bins, n_imp, n_uni, xyz, u, ray_origin,
                                                reinterpret_cast<hipStream_t>(stream)),
                       "importance sampling");
@@ -537,9 +575,10 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
 int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
                           const float* trans, float lo, float hi, int32_t n_bins, float* targets,
                           void* stream) {
-    if (n_ray < 1 || n_k < 1 || n_k > RFVR_MAX_RAY_SAMPLES || n_bins < 1 || n_bins > 64 || !u || !alpha ||
-        !trans || !targets) {
-        set_error("need n_ray >= 1, 1 <= n_k <= RFVR_MAX_RAY_SAMPLES (1024), 1 <= n_bins <= 64 and all arrays");
+    if (n_ray < 1 || n_ray > RFVR_MAX_RAYS || n_k < 1 || n_k > RFVR_MAX_RAY_SAMPLES || n_bins < 1 || n_bins > 64 ||
+        !u || !alpha || !trans || !targets) {
+        set_error("need 1 <= n_ray <= RFVR_MAX_RAYS, 1 <= n_k <= RFVR_MAX_RAY_SAMPLES (1024), 1 <= n_bins <= 64 "
+                  "and all arrays");
         return RFVR_E_INVALID;
     }
     if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi)) { set_error("need finite lo < hi"); return RFVR_E_INVALID; }
@@ -551,16 +590,17 @@ int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const floa
 size_t rfvr_bce_ws_bytes(int64_t n) { return rfvr_loss_ws_bytes(n); }
 
 size_t rfvr_mask_ws_bytes(int64_t n) {
-    if (n < 1) return 0;
+    if (!count_ok(n)) return 0;
     return align256(sizeof(float) * (loss_blocks((long)n) + 1));
 }
 
 int rfvr_mask_update(int64_t n, const float* power, const float* power_ref, float* history, float tau_hi,
                      float tau_lo, float* mask, void* ws, size_t ws_bytes, void* stream) {
-    if (n < 1 || !power || !power_ref || !history || !mask) {
-        set_error("n >= 1, power, power_ref, history and mask are required");
+    if (!power || !power_ref || !history || !mask) {
+        set_error("power, power_ref, history and mask are required");
         return RFVR_E_INVALID;
     }
+    if (!count_ok(n)) { set_error("n must be in [1, RFVR_MAX_POINTS]"); return RFVR_E_INVALID; }
     if (!std::isfinite(tau_hi) || !std::isfinite(tau_lo) || tau_hi < 0.0f || tau_lo < 0.0f) {
         set_error("tau_hi and tau_lo must be finite and >= 0");
         return RFVR_E_INVALID;
@@ -575,8 +615,9 @@ int rfvr_mask_update(int64_t n, const float* power, const float* power_ref, floa
 
 int rfvr_bce(int64_t n, const float* logits, const float* t, float* loss, float* g_logits,
              void* ws, size_t ws_bytes, void* stream) {
-    if (n < 1 || !logits || !t || !loss) { set_error("n >= 1, logits, t and loss are required"); return RFVR_E_INVALID; }
+    if (!logits || !t || !loss) { set_error("logits, t and loss are required"); return RFVR_E_INVALID; }
     int rc;
+    if ((rc = check_count("n", n))) return rc;
     if ((rc = check_ws(ws, ws_bytes, rfvr_bce_ws_bytes(n)))) return rc;
     const int nb = loss_blocks((long)n);
     return hip_status(launch_bce((long)n, logits, t, loss, g_logits, reinterpret_cast<double*>(ws), nb,
@@ -586,7 +627,8 @@ int rfvr_bce(int64_t n, const float* logits, const float* t, float* loss, float*
 
 // ---------------------------------------------------------------- occupancy
 int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* stream) {
-    if (n < 1 || !sdf || !phi) { set_error("n >= 1, sdf and phi are required"); return RFVR_E_INVALID; }
+    if (!sdf || !phi) { set_error("sdf and phi are required"); return RFVR_E_INVALID; }
+    if (!count_ok(n)) { set_error("n must be in [1, RFVR_MAX_POINTS]"); return RFVR_E_INVALID; }
     if (!std::isfinite(s) || s <= 0.0f) { set_error("s must be finite and > 0"); return RFVR_E_INVALID; }
     return hip_status(launch_occupancy((long)n, s, sdf, phi, reinterpret_cast<hipStream_t>(stream)),
                       "occupancy");
@@ -595,7 +637,10 @@ int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* strea
 // ---------------------------------------------------------------- AdamW
 int rfvr_adamw(int64_t n, float* p, const float* g, float* m, float* v, int64_t t, float lr,
                float b1, float b2, float eps, float wd, void* stream) {
-    if (n < 1 || !p || !g || !m || !v || t < 1) { set_error("n >= 1, t >= 1 and all arrays are required"); return RFVR_E_INVALID; }
+    if (!count_ok(n) || !p || !g || !m || !v || t < 1) {
+        set_error("n in [1, RFVR_MAX_POINTS], t >= 1 and all arrays are required");
+        return RFVR_E_INVALID;
+    }
     if (!std::isfinite(lr) || !std::isfinite(b1) || !std::isfinite(b2) || !std::isfinite(eps) || !std::isfinite(wd) ||
         b1 < 0.0f || b1 >= 1.0f || b2 < 0.0f || b2 >= 1.0f) {
         set_error("invalid AdamW hyper-parameters");
@@ -633,10 +678,6 @@ static int check_scenes(int32_t n, const rfvr_scene* sc, SceneCall call) {
         if (call == SC_RENDER_BWD && sc[s].sm.point_weight) {
             set_error("scene %d: point weights are supported by rfvr_render_forward only", s);
             return RFVR_E_UNSUPPORTED;
-        }
-        if (call == SC_FILTER && (int64_t)sc[s].sm.n_ray * sc[s].sm.n_z > (int64_t)1 << 40) {
-            set_error("scene %d: n_ray * n_z too large", s);
-            return RFVR_E_INVALID;
         }
     }
     return RFVR_OK;
@@ -755,8 +796,8 @@ static int check_nets(int32_t n, const rfvr_mlp* nets, const int64_t* cnt) {
     if (n < 1 || !nets || !cnt) { set_error("n_nets must be >= 1, nets and n non-NULL"); return RFVR_E_INVALID; }
     for (int s = 0; s < n; ++s) {
         if (rfvr_mlp_param_count(&nets[s]) < 0) return scene_error(s, RFVR_E_INVALID);
-        if (cnt[s] < 1 || !nets[s].params) {
-            set_error("net %d: n >= 1 and params are required", s);
+        if (!count_ok(cnt[s]) || !nets[s].params) {
+            set_error("net %d: n in [1, RFVR_MAX_POINTS] and params are required", s);
             return RFVR_E_INVALID;
         }
     }

@@ -1347,7 +1347,10 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
                 void* reserve, size_t reserve_bytes_, void* ws, size_t ws_bytes, hipStream_t st) {
     int rc;
     if ((rc = check_net(net))) return rc;
-    if (n < 1 || !xyz || !net->params) { set_error("n >= 1, xyz and params are required"); return RFVR_E_INVALID; }
+    if (n < 1 || n > RFVR_MAX_POINTS || !xyz || !net->params) {
+        set_error("n in [1, RFVR_MAX_POINTS], xyz and params are required");
+        return RFVR_E_INVALID;
+    }
     const Layout l = layout(net);
     const bool keep = reserve_bytes_ != 0 || reserve != nullptr;
     if ((rc = check_buffers(ws, ws_bytes, fwd_bytes(l, n, keep), reserve, reserve_bytes_,
@@ -1437,7 +1440,10 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                  void* ws, size_t ws_bytes, hipStream_t st) {
     int rc;
     if ((rc = check_net(net))) return rc;
-    if (n < 1 || !xyz || !net->params || !g_params) { set_error("n >= 1, xyz, params and g_params are required"); return RFVR_E_INVALID; }
+    if (n < 1 || n > RFVR_MAX_POINTS || !xyz || !net->params || !g_params) {
+        set_error("n in [1, RFVR_MAX_POINTS], xyz, params and g_params are required");
+        return RFVR_E_INVALID;
+    }
     if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }
     const Layout l = layout(net);
     const bool keep = reserve_bytes_ != 0 || reserve != nullptr;
@@ -1609,12 +1615,12 @@ int64_t rfvr_mlp_param_count(const rfvr_mlp* net) {
 }
 
 size_t rfvr_mlp_forward_ws_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
+    if (check_net(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
     return fwd_bytes(layout(net), (long)n, false);
 }
 
 size_t rfvr_mlp_backward_ws_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
+    if (check_net(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
     return bwd_bytes(layout(net), (long)n, false);
 }
 
@@ -1632,17 +1638,17 @@ int rfvr_mlp_backward(const rfvr_mlp* net, const float* xyz, int64_t n, const fl
 }
 
 size_t rfvr_mlp_reserve_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
+    if (check_net(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
     return reserve_bytes(layout(net), (long)n);
 }
 
 size_t rfvr_mlp_forward_train_ws_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
+    if (check_net(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
     return fwd_bytes(layout(net), (long)n, true);
 }
 
 size_t rfvr_mlp_backward_train_ws_bytes(const rfvr_mlp* net, int64_t n) {
-    if (check_net(net) || n < 1) return 0;
+    if (check_net(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
     return bwd_bytes(layout(net), (long)n, true);
 }
 
@@ -1740,7 +1746,7 @@ int64_t rfvr_proposal_param_count(const rfvr_proposal* net) {
 }
 
 size_t rfvr_proposal_ws_bytes(const rfvr_proposal* net, int64_t n) {
-    if (check_prop(net) || n < 1) return 0;
+    if (check_prop(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
     return pbytes(playout(net), (long)n, true);
 }
 
@@ -1749,7 +1755,10 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
                          size_t ws_bytes, void* stream) {
     int rc;
     if ((rc = check_prop(net))) return rc;
-    if (n < 1 || !xyz || !net->params) { set_error("n >= 1, xyz and params are required"); return RFVR_E_INVALID; }
+    if (n < 1 || n > RFVR_MAX_POINTS || !xyz || !net->params) {
+        set_error("n in [1, RFVR_MAX_POINTS], xyz and params are required");
+        return RFVR_E_INVALID;
+    }
     const bool bwd = g_params != nullptr;
     if (bwd && !g_logits) { set_error("g_logits is required"); return RFVR_E_INVALID; }
     if (flags & ~(uint32_t)RFVR_ACCUMULATE) { set_error("only RFVR_ACCUMULATE is meaningful here"); return RFVR_E_INVALID; }

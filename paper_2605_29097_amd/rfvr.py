@@ -26,6 +26,8 @@ ACCUMULATE = 0x8
 TERMS_DIRECT = 0x10      # per-frequency evaluation of the term sums
 SAMPLE_GRID, SAMPLE_STRATIFIED = 0, 1
 PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
+# size limits of one call (RFVR_MAX_* in rfvr.h)
+MAX_POINTS, MAX_RAYS, MAX_MEAS, MAX_RAY_SAMPLES = (1 << 31) - 1, 1 << 25, 1 << 20, 1024
 ERRORS = {-1: "RFVR_E_INVALID", -2: "RFVR_E_WORKSPACE", -3: "RFVR_E_UNSUPPORTED", -4: "RFVR_E_HIP"}
 
 _c_i32, _c_i64, _c_u32, _c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64

@@ -128,6 +128,38 @@ def test_mf_and_loss_reject_bad_arguments(R):
     assert L.rfvr_loss_l2(10, v, v, None, v, None, None, 0, None) == -2
 
 
+def test_size_limits_are_checked_before_launch(R):
+    """Counts past RFVR_MAX_POINTS / RFVR_MAX_RAYS / RFVR_MAX_MEAS are rejected
+    (and their workspace queries return 0) before anything is enqueued."""
+    L = R.lib()
+    hdr = open(os.path.join(ROOT, "include", "rfvr.h")).read()
+    for name, val in (("MAX_POINTS", R.MAX_POINTS), ("MAX_RAYS", R.MAX_RAYS), ("MAX_MEAS", R.MAX_MEAS),
+                      ("MAX_RAY_SAMPLES", R.MAX_RAY_SAMPLES)):
+        m = re.search(r"#define RFVR_%s\s+(\d+)" % name, hdr)
+        assert m and int(m.group(1)) == val, name
+    v = ctypes.c_void_p(0x1000)
+    ap = _ap(R)
+    big = R.MAX_POINTS + 1
+    assert L.rfvr_mf_forward_ws_bytes(ctypes.byref(ap), big, 0) == 0
+    assert L.rfvr_mf_forward(ctypes.byref(ap), v, big, 0, v, v, v, None, None, None, v, 1 << 40, None) == -1
+    assert L.rfvr_mf_backward(ctypes.byref(ap), v, big, v, v, v, 0, v, v, 1 << 40, None) == -1
+    assert L.rfvr_loss_l2(big, v, v, None, v, None, v, 1 << 40, None) == -1
+    assert L.rfvr_occupancy(big, 64.0, v, v, None) == -1
+    sm = R.CSamples(R.MAX_RAYS + 1, 1, v, None, None)
+    assert L.rfvr_render_forward_ws_bytes(ctypes.byref(ap), ctypes.byref(sm)) == 0
+    sm = R.CSamples(1 << 24, 1 << 8, v, None, None)                   # 2^32 points
+    assert L.rfvr_render_forward_ws_bytes(ctypes.byref(ap), ctypes.byref(sm)) == 0
+    ap.n_meas = R.MAX_MEAS + 1
+    sm = R.CSamples(4, 4, v, None, None)
+    assert L.rfvr_render_forward_ws_bytes(ctypes.byref(ap), ctypes.byref(sm)) == 0
+    d = R.CSampleDesc((ctypes.c_float * 3)(0, 0, 0.3), 0.05, (ctypes.c_float * 3)(0, 0, 1), 1 << 13, 1 << 13, 64,
+                      0, 0, 0)                                         # 2^26 rays
+    assert L.rfvr_sample_points(ctypes.byref(d), v, None, None, None) == -1
+    d.n_ray_x = 1 << 12                                                # 2^25 rays x 64 depths
+    assert L.rfvr_sample_points(ctypes.byref(d), v, None, None, None) == -1
+    assert L.rfvr_proposal_targets(R.MAX_RAYS + 1, 8, v, v, v, 0.2, 0.4, 8, v, None) == -1
+
+
 def test_sampler_and_optimizer_reject_bad_arguments(R):
     L = R.lib()
     d = R.CSampleDesc((ctypes.c_float * 3)(0, 0, 0.3), 0.05, (ctypes.c_float * 3)(0, 0, 0), 4, 4, 4,
