@@ -450,16 +450,26 @@ def _split(t: torch.Tensor, sizes, tail=()):
     return out
 
 
-def render_forward_batched(scenes, flags: int = 0, stream=None):
-    """Signals of several scenes [(Aperture, Samples, Fields)]: list of [n_meas, n_freq, 2]."""
+def render_forward_batched(scenes, flags: int = 0, want_alpha=False, stream=None):
+    """Signals of several scenes [(Aperture, Samples, Fields)]: list of [n_meas, n_freq, 2]
+    (with want_alpha, list of (signal, alpha, trans) with alpha, trans [n_ray, n_z])."""
     dev = scenes[0][1].xyz.device
     arr = _scenes(scenes)
     sizes = [ap.n_meas * ap.n_freq for ap, _, _ in scenes]
+    npts = [sm.xyz.shape[0] * sm.xyz.shape[1] for _, sm, _ in scenes]
     sig = torch.empty(sum(sizes), 2, dtype=torch.float32, device=dev)
+    alpha = trans = None
+    if want_alpha:
+        alpha = torch.empty(sum(npts), dtype=torch.float32, device=dev)
+        trans = torch.empty_like(alpha)
     ws = _ws(lib().rfvr_render_forward_batched_ws_bytes(len(scenes), arr), dev)
-    _check(lib().rfvr_render_forward_batched(len(scenes), arr, flags, _ptr(sig), None, None, _ptr(ws), ws.numel(),
-                                             _stream(stream)), "rfvr_render_forward_batched")
-    return [v.view(ap.n_meas, ap.n_freq, 2) for v, (ap, _, _) in zip(_split(sig, sizes), scenes)]
+    _check(lib().rfvr_render_forward_batched(len(scenes), arr, flags, _ptr(sig), _ptr(alpha), _ptr(trans), _ptr(ws),
+                                             ws.numel(), _stream(stream)), "rfvr_render_forward_batched")
+    sigs = [v.view(ap.n_meas, ap.n_freq, 2) for v, (ap, _, _) in zip(_split(sig, sizes), scenes)]
+    if not want_alpha:
+        return sigs
+    shp = [tuple(sm.xyz.shape[:2]) for _, sm, _ in scenes]
+    return [(s, a.view(h), t.view(h)) for s, a, t, h in zip(sigs, _split(alpha, npts), _split(trans, npts), shp)]
 
 
 def render_backward_batched(scenes, g_signals, flags: int = 0, stream=None):
@@ -485,18 +495,26 @@ def render_backward_batched(scenes, g_signals, flags: int = 0, stream=None):
     return out
 
 
-def mf_forward_batched(scenes, signals, flags: int = 0, stream=None):
-    """Matched filter of each scene's signal at its sample points: list of (z [Q, 2], power [Q])."""
+def mf_forward_batched(scenes, signals, signals2=None, flags: int = 0, stream=None):
+    """Matched filter of each scene's signal at its sample points: list of (z [Q, 2], power [Q]);
+    with signals2 (a second signal per scene), list of (z, power, z2, power2)."""
     dev = scenes[0][1].xyz.device
     arr = _scenes([(ap, sm, None) for ap, sm, *_ in scenes])
     npts = [sm.xyz.shape[0] * sm.xyz.shape[1] for _, sm, *_ in scenes]
     sig = torch.cat([s.reshape(-1, 2) for s in signals]).contiguous()
+    sig2 = None if signals2 is None else torch.cat([s.reshape(-1, 2) for s in signals2]).contiguous()
     z = torch.empty(sum(npts), 2, dtype=torch.float32, device=dev)
     p = torch.empty(sum(npts), dtype=torch.float32, device=dev)
-    ws = _ws(lib().rfvr_mf_forward_batched_ws_bytes(len(scenes), arr, 0), dev)
-    _check(lib().rfvr_mf_forward_batched(len(scenes), arr, flags, _ptr(sig), _ptr(z), _ptr(p), None, None, None,
-                                         _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mf_forward_batched")
-    return list(zip(_split(z, npts), _split(p, npts)))
+    z2 = p2 = None
+    if sig2 is not None:
+        z2 = torch.empty_like(z)
+        p2 = torch.empty_like(p)
+    ws = _ws(lib().rfvr_mf_forward_batched_ws_bytes(len(scenes), arr, 0 if sig2 is None else 1), dev)
+    _check(lib().rfvr_mf_forward_batched(len(scenes), arr, flags, _ptr(sig), _ptr(z), _ptr(p), _ptr(sig2), _ptr(z2),
+                                         _ptr(p2), _ptr(ws), ws.numel(), _stream(stream)), "rfvr_mf_forward_batched")
+    if sig2 is None:
+        return list(zip(_split(z, npts), _split(p, npts)))
+    return list(zip(_split(z, npts), _split(p, npts), _split(z2, npts), _split(p2, npts)))
 
 
 def mf_backward_batched(scenes, zs, powers, g_powers, flags: int = 0, stream=None):

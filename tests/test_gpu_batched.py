@@ -65,6 +65,24 @@ def test_render_and_filter_batched_equal_single_scene_calls(dev):
     assert all(_same(a, b) for a, b in zip(ga_b, ga_1))
 
 
+def test_batched_optional_outputs_equal_single_scene_calls(dev):
+    """The optional outputs: alpha / T of the render, the filter's second signal."""
+    _say("batched render alpha / T, filter with two signals, 3 scenes")
+    R = _R()
+    scenes = _scenes(dev)
+    out_b = R.render_forward_batched(scenes, want_alpha=True)
+    out_1 = [R.render_forward(ap, sm, fl, want_alpha=True) for ap, sm, fl in scenes]
+    for tb, t1 in zip(out_b, out_1):
+        assert all(_same(a, b) for a, b in zip(tb, t1))
+    rng = np.random.default_rng(8)
+    sig1 = [s for s, _, _ in out_1]
+    sig2 = [torch.from_numpy(rng.normal(size=s.shape).astype(np.float32)).to(dev) for s in sig1]
+    zp_b = R.mf_forward_batched(scenes, sig1, sig2)
+    zp_1 = [R.mf_forward(ap, sm.xyz, a, b) for (ap, sm, _), a, b in zip(scenes, sig1, sig2)]
+    for tb, t1 in zip(zp_b, zp_1):
+        assert len(tb) == 4 and all(_same(a, b) for a, b in zip(tb, t1))
+
+
 def test_mlp_grouped_equals_single_network_calls(dev):
     _say("grouped network calls, 2 nets")
     R = _R()
