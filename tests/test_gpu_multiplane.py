@@ -67,12 +67,13 @@ def test_rotated_plane_samples_and_render(dev):
                            plane_offset=pl["offset"])
     assert np.abs(xyz.cpu().numpy() - xr).max() < 4e-8
     assert np.abs(o.cpu().numpy() - orr).max() < 4e-8
-    x32 = xyz.cpu().numpy()
+    # both renders take the oracle sampler's points, rounded to float32
+    x32 = xr.astype(np.float32)
     sdf, grad, refl = scene_fields(SPHERE, x32)
     f0, df = freq_grid(cfg.n_freq)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     ap = R.Aperture(tx=t(pl["tx"]), f0=f0, df=df, n_freq=cfg.n_freq)
-    sig = R.render_forward(ap, R.Samples(xyz=xyz), R.Fields(sdf=t(sdf), grad=t(grad), refl=t(refl), s=cfg.s))
+    sig = R.render_forward(ap, R.Samples(xyz=t(x32)), R.Fields(sdf=t(sdf), grad=t(grad), refl=t(refl), s=cfg.s))
     F = orc.Fields(sdf=sdf.astype(np.float64), grad=grad.astype(np.float64), refl=refl.astype(np.float64),
                    s=cfg.s, amp=1.0)
     ref = orc.render(orc.Aperture(tx=pl["tx"].astype(np.float64), f0=f0, df=df, n_freq=cfg.n_freq),

@@ -38,11 +38,13 @@ def test_naive_sampler_and_render_match_oracle(dev):
     xr, jr = o_naive(tx, C, H, (0, 0, 1), 10, 8, 24)
     assert np.abs(xyz.cpu().numpy() - xr).max() < 4e-8
     assert np.abs(jac.cpu().numpy() - jr).max() < 1e-6 * np.abs(jr).max()
-    x32 = xyz.cpu().numpy()
+    # both renders take the oracle sampler's points and volumes, rounded to float32
+    x32 = xr.astype(np.float32)
+    j32 = jr.astype(np.float32)
     sdf, grad, refl = scene_fields(SPH, x32)
     ap = R.Aperture(tx=_t(tx, dev), f0=f0, df=df, n_freq=20)
-    sig = render_naive(ap, xyz, jac, _t(sdf, dev), _t(grad, dev), _t(refl, dev), s=64.0)
-    j32 = jac.cpu().numpy()
+    sig = render_naive(ap, _t(x32, dev).view(xyz.shape), _t(j32, dev).view(jac.shape), _t(sdf, dev), _t(grad, dev),
+                       _t(refl, dev), s=64.0)
     ref = np.empty((tx.shape[0], 20), np.complex128)
     for i in range(tx.shape[0]):
         F = orc.Fields(sdf=sdf[i].astype(np.float64), grad=grad[i].astype(np.float64),
