@@ -13,7 +13,8 @@ Both sides take the same float32 inputs: the points are the oracle sampler's
 depths rounded to float32 (the GPU sampler is held to those depths on every
 ray), the fields are the analytic scene's at those points.  Sampled outputs:
   * importance depths of every ray of every scene (float32 rounding);
-  * the rendered signal at 3 measurements x 4 frequencies per scene;
+  * the rendered signal at 3 measurements x 4 frequencies per scene (also
+    through the per-frequency kernels for the smallest and largest aperture);
   * the filter output at 32 query points per scene;
   * the filter adjoint at 2 measurements x 4 frequencies per scene;
   * the render adjoint along one surface-crossing ray per scene (per-ray
@@ -171,6 +172,30 @@ def test_render_forward_batched_sampled(dev, scenes):
         e = rel_rms(got, ref)
         print(f"scene {S['k']}: signal rms rel {e:.2e}")
         assert e <= 1e-4, S["k"]
+
+
+def test_per_frequency_path_at_full_size(dev, scenes):
+    """The per-frequency term kernels (RFVR_TERMS_DIRECT) on the smallest and
+    largest aperture: 256 frequencies in four 64-frequency chunks, up to 4096
+    measurements; signal and filter output on the same samples as above."""
+    R = _R()
+    _say("render / filter forward, per-frequency kernels, scenes 0 and 7")
+    sub = [scenes[0], scenes[-1]]
+    sig = R.render_forward_batched([S["gpu"] for S in sub], flags=R.TERMS_DIRECT)
+    rng = np.random.default_rng(25)
+    for S, s in zip(sub, sig):
+        c = S["case"]
+        sel = _meas_sel(S["geo"]["side"])
+        e = rel_rms(as_complex(s)[sel][:, FREQ_SEL], _render_oracle(c, sel, FREQ_SEL))
+        n_meas = c.tx.shape[0]
+        sg = (rng.normal(size=(n_meas, N_FREQ)) + 1j * rng.normal(size=(n_meas, N_FREQ))).astype(np.complex64)
+        ap, sm, _ = S["gpu"]
+        z, p = R.mf_forward(ap, sm.xyz, _t(np.stack([sg.real, sg.imag], -1), dev), flags=R.TERMS_DIRECT)
+        q = rng.choice(NX * NY * (N_IMP + N_UNI), 16, replace=False)
+        zr, _ = orc.mf(_o_ap(c), c.xyz.reshape(-1, 3)[q], sg.astype(np.complex128))
+        ez = rel_rms(as_complex(z)[q], zr)
+        print(f"scene {S['k']}: per-frequency signal rms rel {e:.2e}, filter rms rel {ez:.2e}")
+        assert e <= 1e-4 and ez <= 1e-4, S["k"]
 
 
 def test_mf_forward_batched_sampled(dev, scenes):
