@@ -88,6 +88,8 @@ SAMPLE_CASES = [
     (5, 3, 64, 192, 64, (0.0, 0.0, 1.0)),
     (3, 2, 17, 700, 1, (0.2, 0.1, 1.0)),
     (2, 2, 64, 1000, 24, (0.0, 0.0, 1.0)),        # RFVR_MAX_RAY_SAMPLES exactly
+    (2, 3, 16, 0, 130, (0.0, 0.0, 1.0)),          # uniform slots only, three registers
+    (2, 2, 64, 200, 0, (0.3, 0.0, 1.0)),          # importance slots only, four registers
 ]
 
 
@@ -136,7 +138,7 @@ def test_sample_importance_full_size(dev):
 
 
 @pytest.mark.parametrize("n_ray,n_k,n_bins", [(5, 64, 64), (300, 20, 64), (33, 7, 13), (40, 256, 64),
-                                               (6, 1000, 37), (3, 1024, 64)])
+                                               (6, 1000, 37), (3, 1024, 64), (4, 129, 1)])
 def test_proposal_targets(dev, n_ray, n_k, n_bins):
     _say(f"proposal_targets n_ray={n_ray} n_k={n_k} n_bins={n_bins}")
     R = _R()
