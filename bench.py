@@ -282,6 +282,84 @@ def naive_compare(args, dev):
     print(json.dumps(out))
 
 
+def batched8_study(args, dev):
+    """The eight-scene workload: apertures of 32^2 .. 64^2 antennas at 2 mm
+    (19,292 in all), 256 frequencies 77-81 GHz, 2^22 points per scene (128 x 128
+    lensless rays x 256 depths in a 25 cm cube at the scene's range), one
+    8 x 256 network per scene.  One call of each batched or grouped entry point
+    over all eight scenes, in the order of a training step, timed with HIP
+    events after a warm-up call; terms/s per term pass (sum over scenes of
+    points x measurements x frequencies).  Prints one JSON line."""
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from synth import MLPSpec, freq_grid, mlp_init, planar_aperture
+    from synth.configs import PITCH, batched8_scene, config
+    c = config("batched8")
+    m = c["mlp"]
+    f0, df = freq_grid(c["n_freq"])
+    nx, ny = c["lines"]
+    nz = c["n_imp"] + c["n_uni"]
+    geo = [batched8_scene(k) for k in range(len(c["ap_sides"]))]
+    aps, xyzs = [], []
+    for g in geo:
+        tx = torch.from_numpy(planar_aperture(g["side"], g["side"], PITCH)).to(dev)
+        aps.append(R.Aperture(tx=tx, f0=f0, df=df, n_freq=c["n_freq"]))
+        xyz, _, _ = R.sample_points(g["centre"], g["half"], (0, 0, 1), nx, ny, nz, mode=R.SAMPLE_STRATIFIED,
+                                    seed=g["seed"], device=dev)
+        xyzs.append(xyz)
+    terms = sum(x.shape[0] * x.shape[1] * a.n_meas * a.n_freq for a, x in zip(aps, xyzs))
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        e1.synchronize()
+        return r, e0.elapsed_time(e1) / reps
+
+    out = {"study": "eight_scene_batched", "terms_per_pass": terms, "points": sum(x.numel() // 3 for x in xyzs),
+           "networks": {}}
+    gen = torch.Generator(device=dev).manual_seed(0)
+    for pname, prec in (("bf16x3", R.PREC_BF16X3), ("bf16", R.PREC_BF16)):
+        nets = []
+        for k, g in enumerate(geo):
+            spec = MLPSpec(n_layers=m["n_layers"], width=m["width"], pe_octaves=m["pe_octaves"],
+                           head_width=m["head_width"], head_layers=m["head_layers"], beta=m["beta"],
+                           centre=g["centre"], half_size=g["half"])
+            nets.append(R.MLP(params=torch.from_numpy(mlp_init(spec, k)).to(dev), n_layers=spec.n_layers,
+                              width=spec.width, pe_octaves=spec.pe_octaves, head_width=spec.head_width,
+                              head_layers=spec.head_layers, beta=spec.beta, centre=spec.centre,
+                              half_size=spec.half_size, precision=prec))
+        row = {}
+        fga, row["mlp_forward_grouped_ms"] = timed(lambda: R.mlp_forward_grouped(nets, xyzs))
+        if pname == "bf16x3":
+            scenes = [(a, R.Samples(xyz=x), R.Fields(sdf=f.view(x.shape[:2]), grad=gr.view(x.shape),
+                                                     refl=al.view(x.shape[:2]), s=c["s"]))
+                      for a, x, (f, gr, al) in zip(aps, xyzs, fga)]
+            sig, t_rf = timed(lambda: R.render_forward_batched(scenes))
+            zp, t_mf = timed(lambda: R.mf_forward_batched(scenes, sig))
+            gps = [torch.randn(p.shape, generator=gen, device=dev) / p.numel() for _, p in zp]
+            gsig, t_mb = timed(lambda: R.mf_backward_batched(scenes, [z for z, _ in zp], [p for _, p in zp], gps))
+            gfl, t_rb = timed(lambda: R.render_backward_batched(scenes, gsig))
+            for name, t in (("render_forward", t_rf), ("mf_forward", t_mf), ("mf_backward", t_mb),
+                            ("render_backward", t_rb)):
+                out[f"{name}_ms"] = round(t, 2)
+                out[f"{name}_terms_per_s"] = terms / (t * 1e-3)
+                print(f"[batched8] {name} {t:.1f} ms, {terms / (t * 1e-3):.3e} terms/s", file=sys.stderr,
+                      flush=True)
+        ups = [(d["sdf"].reshape(-1), d["grad"].reshape(-1, 3), d["refl"].reshape(-1)) for d in gfl]
+        _, row["mlp_backward_grouped_ms"] = timed(lambda: R.mlp_backward_grouped(
+            nets, xyzs, [u[0] for u in ups], [u[1] for u in ups], [u[2] for u in ups]))
+        row = {k: round(v, 2) for k, v in row.items()}
+        print(f"[batched8] networks {pname}: {row}", file=sys.stderr, flush=True)
+        out["networks"][pname] = row
+        del nets, fga
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +382,8 @@ def main():
     ap.add_argument("--naive-compare", action="store_true",
                     help="forward time of per-antenna sampling vs lensless sampling")
     ap.add_argument("--naive-apertures", type=int, nargs="+", default=[4, 8, 16])
+    ap.add_argument("--batched8", action="store_true",
+                    help="time the batched and grouped calls on the eight-scene workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
@@ -328,6 +408,9 @@ def main():
         return
     if args.naive_compare:
         naive_compare(args, dev)
+        return
+    if args.batched8:
+        batched8_study(args, dev)
         return
     cfg = StepConfig()
     params, target = make_inputs(cfg, dev)
