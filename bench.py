@@ -360,6 +360,69 @@ def batched8_study(args, dev):
     print(json.dumps(out))
 
 
+def batched8_train(args, dev):
+    """Training steps of the eight-scene workload: per scene a proposal-sampled
+    step (128 x 128 rays, 64 bins, 192 importance + 64 stratified depths, 2^22
+    points; the measured heatmap recomputed at the new points) of its own
+    network (8 x 256, split-BF16 or BF16 operands), the scenes stepped one
+    after another and sharing one network reserve.  The measured signals are
+    seeded random (a timing run).  Times whole eight-scene steps with HIP events
+    after one warm-up step.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from paper_2605_29097_amd.train import ProposalConfig, ProposalTrainer, StepConfig
+    from synth import MLPSpec, mlp_init
+    from synth.configs import batched8_scene, config
+    c = config("batched8")
+    m = c["mlp"]
+    out = {"study": "eight_scene_training_step", "runs": {}}
+    for pname, prec in (("bf16x3", R.PREC_BF16X3), ("bf16", R.PREC_BF16)):
+        trainers, shared = [], None
+        for k in range(len(c["ap_sides"])):
+            g = batched8_scene(k)
+            cfg = StepConfig(ap=(g["side"], g["side"]), n_freq=c["n_freq"], cube_centre=g["centre"],
+                             cube_side=c["cube_side"], lines=c["lines"], n_z=c["n_imp"] + c["n_uni"],
+                             s=c["s"], n_layers=m["n_layers"], width=m["width"], pe_octaves=m["pe_octaves"],
+                             head_width=m["head_width"], head_layers=m["head_layers"], beta=m["beta"],
+                             precision=prec, seed=k)
+            spec = MLPSpec(n_layers=m["n_layers"], width=m["width"], pe_octaves=m["pe_octaves"],
+                           head_width=m["head_width"], head_layers=m["head_layers"], beta=m["beta"],
+                           centre=g["centre"], half_size=g["half"])
+            rng = np.random.default_rng(100 + k)
+            target = torch.from_numpy((rng.normal(size=(cfg.n_meas, c["n_freq"], 2)) * 1e-3).astype(np.float32))
+            tr = ProposalTrainer(cfg, torch.from_numpy(mlp_init(spec, k)), target,
+                                 ProposalConfig(n_imp=c["n_imp"], n_uni=c["n_uni"], seed=k), device=dev)
+            if shared is None:
+                shared = R.mlp_reserve(tr.net, cfg.lines[0] * cfg.lines[1] * cfg.n_z, dev)
+            tr.shared_reserve = shared
+            trainers.append(tr)
+
+        def step():
+            return [tr.step() for tr in trainers]
+
+        step()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps if args.steps < 10 else 3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            losses = step()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+            print(f"[batched8-train] {pname} step {e0.elapsed_time(e1):.1f} ms, losses "
+                  f"{[round(float(x.item()), 6) for x in losses]}", file=sys.stderr, flush=True)
+        terms = 4 * sum(tr.cfg.n_meas * tr.cfg.n_freq * tr.cfg.lines[0] * tr.cfg.lines[1] * tr.cfg.n_z
+                        for tr in trainers)
+        ms = float(np.median(times))
+        out["runs"][pname] = {"ms_per_step": round(ms, 1), "terms_per_step": terms,
+                              "terms_per_s": terms / (ms * 1e-3)}
+        del trainers, shared, tr
+        torch.cuda.empty_cache()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,6 +447,8 @@ def main():
     ap.add_argument("--naive-apertures", type=int, nargs="+", default=[4, 8, 16])
     ap.add_argument("--batched8", action="store_true",
                     help="time the batched and grouped calls on the eight-scene workload")
+    ap.add_argument("--batched8-train", action="store_true",
+                    help="time proposal-sampled training steps of the eight-scene workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
@@ -411,6 +476,9 @@ def main():
         return
     if args.batched8:
         batched8_study(args, dev)
+        return
+    if args.batched8_train:
+        batched8_train(args, dev)
         return
     cfg = StepConfig()
     params, target = make_inputs(cfg, dev)

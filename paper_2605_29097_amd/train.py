@@ -51,6 +51,7 @@ class StepConfig:
     spec_flags: int = R.SPEC_CLAMP
     bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
     learn_s: bool = False                  # train log s with the head's learning rate
+    precision: int = R.PREC_FP32           # network matrix operands (R.PREC_FP32 / BF16 / BF16X3)
     keep_activations: bool = True          # network training pair: the backward reads the
                                            # forward's layer activations from a reserve
     mask_tau: Optional[tuple] = None       # (tau_hi, tau_lo): dynamic loss masking on
@@ -114,13 +115,17 @@ class Trainer:
         self.net = R.MLP(params=params.to(self.dev).contiguous(), n_layers=cfg.n_layers,
                          width=cfg.width, pe_octaves=cfg.pe_octaves, head_width=cfg.head_width,
                          head_layers=cfg.head_layers, beta=cfg.beta,
-                         centre=tuple(cfg.cube_centre), half_size=cfg.cube_side / 2)
+                         centre=tuple(cfg.cube_centre), half_size=cfg.cube_side / 2,
+                         precision=cfg.precision)
         n_par = self.net.param_count()
         assert self.net.params.numel() == n_par
         self.m = torch.zeros(n_par, device=self.dev)
         self.v = torch.zeros(n_par, device=self.dev)
         self.g = torch.zeros(n_par, device=self.dev)
         self._res = None
+        # a reserve shared by trainers that step one after another (each step
+        # fills it in its forward and reads it in its backward); None: own one
+        self.shared_reserve = None
         # the SDF branch (trunk + sdf output) comes first in the flat layout
         w, L, in0 = cfg.width, cfg.n_layers, 3 + 6 * cfg.pe_octaves
         self.n_sdf = w * in0 + w + (L - 1) * (w * w + w) + w + 1
@@ -233,6 +238,8 @@ class Trainer:
         """Reserve of the network's training pair for n points (None when off)."""
         if not self.cfg.keep_activations:
             return None
+        if self.shared_reserve is not None:
+            return self.shared_reserve
         if self._res is None or self._res_n != n:
             self._res, self._res_n = R.mlp_reserve(self.net, n, self.dev), n
         return self._res
