@@ -107,3 +107,35 @@ def test_mlp_grouped_equals_single_network_calls(dev):
     gb = R.mlp_backward_grouped(nets, xyzs, [u[0] for u in up], [u[1] for u in up], [u[2] for u in up])
     g1 = [R.mlp_backward(n, x, *u) for n, x, u in zip(nets, xyzs, up)]
     assert all(_same(a, b) for a, b in zip(gb, g1))
+
+
+def test_trainers_sharing_a_reserve_match_trainers_with_their_own(dev):
+    """Two scenes stepped in turn on one shared network reserve end with the
+    same parameters, bit for bit, as with a reserve each."""
+    _say("two trainers, shared reserve vs own reserves")
+    R = _R()
+    from paper_2605_29097_amd.train import StepConfig, Trainer
+    rng = np.random.default_rng(31)
+    cfgs = [StepConfig(ap=(6, 6), n_freq=16, cube_centre=(0.0, 0.0, 0.30), cube_side=0.10, lines=(8, 8), n_z=16,
+                       n_layers=3, width=64, pe_octaves=2, head_width=64, head_layers=1, lr_sdf=1e-3),
+            StepConfig(ap=(5, 7), n_freq=16, cube_centre=(0.01, 0.0, 0.32), cube_side=0.10, lines=(8, 8), n_z=16,
+                       n_layers=3, width=64, pe_octaves=2, head_width=64, head_layers=1, lr_sdf=1e-3)]
+    targets = [torch.from_numpy((rng.normal(size=(c.n_meas, 16, 2)) * 1e-2).astype(np.float32)) for c in cfgs]
+
+    def make(k):
+        c = cfgs[k]
+        spec = MLPSpec(n_layers=3, width=64, pe_octaves=2, head_width=64, head_layers=1,
+                       centre=c.cube_centre, half_size=c.cube_side / 2)
+        return Trainer(c, torch.from_numpy(mlp_init(spec, 40 + k)), targets[k], device=dev)
+
+    own = [make(0), make(1)]
+    shared = [make(0), make(1)]
+    res = R.mlp_reserve(shared[0].net, cfgs[0].n_pts, dev)
+    for tr in shared:
+        tr.shared_reserve = res
+    for _ in range(3):
+        for a, b in zip(own, shared):
+            la, lb = a.step(), b.step()
+            assert _same(la, lb)
+    for a, b in zip(own, shared):
+        assert _same(a.net.params, b.net.params)
