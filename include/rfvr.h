@@ -379,7 +379,9 @@ typedef struct rfvr_proposal {
 } rfvr_proposal;
 int64_t rfvr_proposal_param_count(const rfvr_proposal* net);
 size_t rfvr_proposal_ws_bytes(const rfvr_proposal* net, int64_t n);
-/* logits [n] at points xyz [n][3]. */
+/* logits [n] at points xyz [n][3].  The proposal calls evaluate all n points
+ * in one pass (two threads per point in its matrix products), so they take at
+ * most RFVR_MAX_POINTS / 2 + 1 = 2^30 points. */
 int rfvr_proposal_forward(const rfvr_proposal* net, const float* xyz, int64_t n, float* logits,
                           void* ws, size_t ws_bytes, void* stream);
 /* g_params (+)= d/dparams sum_q g_logits[q] z_q (activations recomputed). */

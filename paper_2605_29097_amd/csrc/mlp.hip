@@ -1745,8 +1745,11 @@ int64_t rfvr_proposal_param_count(const rfvr_proposal* net) {
     return playout(net).total;
 }
 
+// one pass over all points, two threads per point in its matrix products
+constexpr int64_t kPropMaxPoints = (int64_t)1 << 30;
+
 size_t rfvr_proposal_ws_bytes(const rfvr_proposal* net, int64_t n) {
-    if (check_prop(net) || n < 1 || n > RFVR_MAX_POINTS) return 0;
+    if (check_prop(net) || n < 1 || n > kPropMaxPoints) return 0;
     return pbytes(playout(net), (long)n, true);
 }
 
@@ -1755,8 +1758,8 @@ static int proposal_pass(const rfvr_proposal* net, const float* xyz, int64_t n, 
                          size_t ws_bytes, void* stream) {
     int rc;
     if ((rc = check_prop(net))) return rc;
-    if (n < 1 || n > RFVR_MAX_POINTS || !xyz || !net->params) {
-        set_error("n in [1, RFVR_MAX_POINTS], xyz and params are required");
+    if (n < 1 || n > kPropMaxPoints || !xyz || !net->params) {
+        set_error("n in [1, 2^30], xyz and params are required");
         return RFVR_E_INVALID;
     }
     const bool bwd = g_params != nullptr;
