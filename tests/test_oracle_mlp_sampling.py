@@ -235,3 +235,68 @@ def test_naive_samples_on_antenna_rays_and_volume_jacobian():
     from oracle.sampling import sample_points
     xs, _, _ = sample_points(c, h, (0, 0, 1), 4, 4, 5)
     assert np.abs(xf[0] - xs).max() < 1e-6 and np.abs(jf - 1).max() < 1e-5
+
+
+def test_network_closed_form_with_trunk_biases():
+    """Hand-set two-unit network whose every bias matters: layer 0 reads
+    x_hat_x (plus half of its first sine feature) and 2 x_hat_y, layer 1 mixes
+    the two units, the output layer and the head read known units.  f, grad_x f
+    and a are written out with math.exp / math.log1p from the definitions of
+    softplus_beta, the encoding and the sigmoid (dropped or mis-indexed biases,
+    a transposed matrix or a missing half_size change the values)."""
+    import math
+    spec = MLPSpec(n_layers=2, width=2, pe_octaves=1, head_width=2, head_layers=1, beta=100.0,
+                   centre=(0.01, -0.02, 0.30), half_size=0.1)
+    lay = mlp_layout(spec)
+    p = np.zeros(lay["__total__"][0])
+
+    def put(name, idx, v):
+        off, shp = lay[name]
+        p[off + (idx if isinstance(idx, int) else idx[0] * shp[1] + idx[1])] = v
+
+    put("W0", (0, 0), 1.0)          # x_hat_x
+    put("W0", (0, 3), 0.5)          # sin(pi x_hat_x)
+    put("W0", (1, 1), 2.0)          # x_hat_y
+    put("b0", 0, 0.3)
+    put("b0", 1, -0.1)
+    put("W1", (0, 0), 1.0)
+    put("W1", (0, 1), -0.5)
+    put("W1", (1, 1), 0.25)
+    put("b1", 0, -0.2)
+    put("b1", 1, 0.05)
+    put("w_out", 0, 1.0)
+    put("w_out", 1, 2.0)
+    put("b_out", 0, 0.05)
+    put("Wh0", (0, 0), 1.0)
+    put("Wh0", (1, 1), 1.0)
+    put("bh0", 0, -0.1)
+    put("bh0", 1, 0.2)
+    put("wh_out", 0, 1.0)
+    put("wh_out", 1, -1.0)
+    put("bh_out", 0, 0.3)
+
+    beta = 100.0
+    sp = lambda z: max(z, 0.0) + math.log1p(math.exp(-abs(beta * z))) / beta
+    dsp = lambda z: 1.0 / (1.0 + math.exp(-beta * z))
+    pts = np.array([[0.05, 0.03, 0.31], [-0.02, 0.06, 0.27], [0.03, -0.01, 0.35], [0.0, 0.09, 0.30]])
+    f, g, a = omlp.forward(p, spec, pts)
+    for q, x in enumerate(pts):
+        xh = [(x[0] - 0.01) / 0.1, (x[1] + 0.02) / 0.1]
+        z00 = xh[0] + 0.5 * math.sin(math.pi * xh[0]) + 0.3
+        z01 = 2.0 * xh[1] - 0.1
+        h00, h01 = sp(z00), sp(z01)
+        z10 = h00 - 0.5 * h01 - 0.2
+        z11 = 0.25 * h01 + 0.05
+        h10, h11 = sp(z10), sp(z11)
+        f_h = 0.1 * (h10 + 2.0 * h11 + 0.05)
+        # d/dx: chain through both units; d x_hat / dx = 1 / half_size
+        dz00 = (1.0 + 0.5 * math.pi * math.cos(math.pi * xh[0])) / 0.1
+        dz01 = 2.0 / 0.1
+        dh00, dh01 = dsp(z00) * dz00, dsp(z01) * dz01           # d/dx and d/dy
+        gx = 0.1 * (dsp(z10) * dh00)
+        gy = 0.1 * (dsp(z10) * (-0.5) * dh01 + 2.0 * dsp(z11) * 0.25 * dh01)
+        g0, g1 = max(h10 - 0.1, 0.0), max(h11 + 0.2, 0.0)
+        a_h = 1.0 / (1.0 + math.exp(-(g0 - g1 + 0.3)))
+        assert abs(f[q] - f_h) < 1e-14, (q, f[q], f_h)
+        np.testing.assert_allclose(g[q], [gx, gy, 0.0], rtol=1e-12, atol=1e-15)
+        assert abs(a[q] - a_h) < 1e-14
