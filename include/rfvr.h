@@ -140,7 +140,8 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
                         uint32_t flags, float* signal, float* alpha_out, float* trans_out,
                         void* ws, size_t ws_bytes, void* stream);
 
-/* Adjoint of rfvr_render_forward (App. A.4 signal-tracing backward), with the
+/* Adjoint of rfvr_render_forward (App. A, Differentiable Matched Filter & Signal
+ * Tracing, and Code Implementation, Alg. 2 backward), with the
  * per-term phases and amplitudes recomputed rather than stored:
  *   G_ij = sum_n Re(g_signal[i,n] exp(+j 2 pi f_n 2 r_ij / c)),
  * chained through the amplitude, the transmittance product scan, alpha(Phi),
@@ -156,7 +157,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                          void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Matched filter (filter-based rendering, Eq. mf-sm; App. A.4, Alg. 1)
+ * Matched filter (filter-based rendering, Eq. mf-sm; App. A, Code Implementation, Alg. 1)
  *   z_q = sum_{i,n} signal[i,n] exp(+j 2 pi f_n d_iq / c),  power_q = |z_q|
  * with the monostatic round trip d_iq = 2 |x_q - tx_i|.
  * xyz_q: [n_q][3] query points.  signal2: optional second signal filtered at
@@ -169,7 +170,8 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
                     const float* signal2, float* z2, float* power2,
                     void* ws, size_t ws_bytes, void* stream);
 
-/* Adjoint of rfvr_mf_forward through power = |z| (App. A.4, Alg. 1 backward):
+/* Adjoint of rfvr_mf_forward through power = |z| (App. A, Code Implementation,
+ * Alg. 1 backward):
  *   g_signal[i,n] = sum_q g_power_q (z_q / power_q) exp(-j 2 pi f_n d_iq / c),
  * a point with power_q == 0 contributes nothing.  z: [n_q] complex, power: [n_q],
  * g_power: [n_q] inputs; g_signal: [n_meas][n_freq] complex output. */

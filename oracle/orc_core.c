@@ -146,7 +146,7 @@ void orc_render(int n_meas, const double* tx, const double* rx,
     }
 }
 
-/* Adjoint of signal tracing (App. A.4): G_ij = sum_n Re(g_s[i,n] exp(+j phase)),
+/* Adjoint of signal tracing (App. A, Differentiable Matched Filter & Signal Tracing): G_ij = sum_n Re(g_s[i,n] exp(+j phase)),
  * then the chain rule into the per-point quantities the amplitude depends on.
  * Outputs (per point j, summed over measurements):
  *   g_base  = dL/d(amp*w*refl*alpha),  g_trans = dL/dT_j,  g_nhat = dL/dn_hat_j. */

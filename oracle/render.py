@@ -207,7 +207,8 @@ def mf_adjoint(ap: Aperture, xq, z, P, g_P):
 
     dL/dz = g_P z / P (zero where P == 0); then the adjoint of the linear map
     s -> z, which carries exp(-j phase).  (The printed backward formula of
-    App. A.4 omits the factor z; the factor follows from differentiating |z|.)
+    App. A (Differentiable Matched Filter & Signal Tracing) omits the factor z;
+    the factor follows from differentiating |z|.)
     """
     xq = np.asarray(xq).reshape(-1, 3)
     z = np.asarray(z).ravel()

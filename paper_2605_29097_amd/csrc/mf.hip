@@ -1,4 +1,4 @@
-// Matched filter (Eq. mf-sm; App. A.4 Alg. 1) and the records of its adjoint.
+// Matched filter (Eq. mf-sm; App. A (Code Implementation) Alg. 1) and the records of its adjoint.
 //
 // Forward: one lane per query point; all lanes of a wave walk the same
 // measurements, so the measurement record and the signal row are scalar loads.

@@ -2,7 +2,7 @@
 // (reduction over points) and its adjoint (reduction over frequencies and
 // measurements), and the adjoint of the transmittance scan.
 //
-// Signal tracing, Eq. ref_sim / App. A.4 Alg. 2, rebuilt for gfx950:
+// Signal tracing, Eq. ref_sim / App. A (Code Implementation) Alg. 2, rebuilt for gfx950:
 //  * forward: a lane owns one (measurement, frequency chunk) pair and keeps the
 //    chunk's complex accumulators in VGPRs; all lanes of a work-group walk the
 //    same points, whose records are staged through LDS in double-buffered

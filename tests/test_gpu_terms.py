@@ -104,8 +104,8 @@ def test_term_paths_match_the_oracle_in_every_order_band(dev, z, K):
         sig = as_complex(R.render_forward(ap, sm, fl, flags=flags))
         z_, p_ = R.mf_forward(ap, sm.xyz, st, flags=flags)
         g = as_complex(R.mf_backward(ap, sm.xyz, z_, p_, torch.from_numpy(gP).to(dev), flags=flags))
-        gr = orc.mf_adjoint(c.o_ap(), c.xyz.reshape(-1, 3), as_complex(z_), p_.cpu().numpy().astype(np.float64),
-                            gP.astype(np.float64))
+        # the oracle adjoint at its own z and P (no GPU output as oracle input)
+        gr = orc.mf_adjoint(c.o_ap(), c.xyz.reshape(-1, 3), zr, pr, gP.astype(np.float64))
         adj = R.render_backward(ap, sm, fl, st, flags=flags)
         errs = {"render": rel_rms(sig, ref_sig), "mf z": rel_rms(as_complex(z_), zr),
                 "mf P": rel_rms(p_.cpu().numpy(), pr), "mf adjoint": rel_rms(g, gr)}
@@ -172,7 +172,6 @@ def test_term_order_single_point_and_accumulate(dev):
     gP = torch.ones(1, device=dev)
     g1 = R.mf_backward(ap, sm.xyz, z_, p_, gP)
     g2 = R.mf_backward(ap, sm.xyz, z_, p_, gP, flags=R.ACCUMULATE, out=g1.clone())
-    gr = orc.mf_adjoint(c.o_ap(), xyz.reshape(-1, 3), as_complex(z_), p_.cpu().numpy().astype(np.float64),
-                        np.ones(1))
+    gr = orc.mf_adjoint(c.o_ap(), xyz.reshape(-1, 3), zr, pr, np.ones(1))
     assert rel_rms(as_complex(g1), gr) <= 1e-5
     assert rel_rms(as_complex(g2), 2 * gr) <= 1e-5
