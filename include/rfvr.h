@@ -170,6 +170,26 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
                     const float* signal2, float* z2, float* power2,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation): the matched
+ * filter forward with no workspace argument.  Arguments, outputs, flags and
+ * errors are those of rfvr_mf_forward, whose kernels it runs; its scratch is a
+ * library-owned device array of RFVR_MF_STATIC_SCRATCH_BYTES on each GPU it
+ * runs on, looked up on the first call on that device and held until the
+ * process ends.  It allocates nothing.  A call whose rfvr_mf_forward_ws_bytes()
+ * exceeds RFVR_MF_STATIC_SCRATCH_BYTES returns RFVR_E_INVALID and enqueues
+ * nothing (1024 measurements x 128 frequencies need 1.6 MB with one
+ * signal, 3.1 MB with two).  Every call on one GPU uses that GPU's one array,
+ * which keeps the last call's contents (nothing in it needs clearing between
+ * calls): calls that overlap in time on one GPU, on different streams or
+ * from several host threads, race and give wrong results, so the caller
+ * orders them (one stream, or events).  The work runs on the device that is
+ * current when the call is made; `stream` must belong to it. */
+#define RFVR_MF_STATIC_SCRATCH_BYTES (32u << 20)
+int rfvr_mf_forward_static(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, uint32_t flags,
+                           const float* signal, float* z, float* power, const float* signal2, float* z2,
+                           float* power2, void* stream);
+
 /* Adjoint of rfvr_mf_forward through power = |z| (App. A, Code Implementation,
  * Alg. 1 backward):
  *   g_signal[i,n] = sum_q g_power_q (z_q / power_q) exp(-j 2 pi f_n d_iq / c),

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 
 #include "rfvr_impl.hpp"
 
@@ -186,6 +187,39 @@ static size_t ws_mf_backward(const rfvr_aperture* ap, long n_q) {
 static int loss_blocks(long n) {
     long b = (n + 255) / 256;
     return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+// Scratch of rfvr_mf_forward_static: one library-owned device array per GPU,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host that name is only a stand-in): its device address is
+// looked up once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[RFVR_MF_STATIC_SCRATCH_BYTES];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int static_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index %d beyond the %d devices the static scratch serves", dev, kMaxDevices);
+        return RFVR_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u)) {
+            set_error("static scratch address %p is not 256-byte aligned", p);
+            return RFVR_E_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RFVR_OK;
 }
 
 }  // namespace rfvr
@@ -394,6 +428,25 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
                                         reinterpret_cast<float2*>(z), power,
                                         reinterpret_cast<float2*>(z2), power2, sel, st),
                       "mf forward");
+}
+
+int rfvr_mf_forward_static(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, uint32_t flags,
+                           const float* signal, float* z, float* power, const float* signal2, float* z2,
+                           float* power2, void* stream) {
+    int rc;
+    if ((rc = check_aperture(ap, false))) return rc;
+    if ((rc = check_count("n_q", n_q))) return rc;
+    const size_t need = ws_mf_forward(ap, (long)n_q, signal2 ? 1 : 0);
+    if (need > (size_t)RFVR_MF_STATIC_SCRATCH_BYTES) {
+        set_error("rfvr_mf_forward_static: this call needs %zu bytes of scratch, above the static "
+                  "RFVR_MF_STATIC_SCRATCH_BYTES = %zu (use rfvr_mf_forward with a workspace)",
+                  need, (size_t)RFVR_MF_STATIC_SCRATCH_BYTES);
+        return RFVR_E_INVALID;
+    }
+    void* ws = nullptr;
+    if ((rc = static_scratch(&ws))) return rc;
+    return rfvr_mf_forward(ap, xyz_q, n_q, flags, signal, z, power, signal2, z2, power2, ws,
+                           (size_t)RFVR_MF_STATIC_SCRATCH_BYTES, stream);
 }
 
 size_t rfvr_mf_backward_ws_bytes(const rfvr_aperture* ap, int64_t n_q) {

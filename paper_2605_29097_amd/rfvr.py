@@ -84,6 +84,8 @@ _SIGS = {
     "rfvr_mf_forward": ([_P(CAperture), _vp, _c_i64, _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
                         _c_i32),
     "rfvr_mf_backward_ws_bytes": ([_P(CAperture), _c_i64], _sz),
+    "rfvr_mf_forward_static": ([_P(CAperture), _vp, _c_i64, _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+                               _c_i32),
     "rfvr_mf_backward": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
                          _c_i32),
     "rfvr_loss_ws_bytes": ([_c_i64], _sz),
@@ -309,6 +311,31 @@ def mf_forward(ap: Aperture, xyz_q: torch.Tensor, signal: torch.Tensor, signal2=
 
 
 def mf_backward(ap: Aperture, xyz_q: torch.Tensor, z: torch.Tensor, power: torch.Tensor,
+MF_STATIC_SCRATCH_BYTES = 32 << 20     # RFVR_MF_STATIC_SCRATCH_BYTES
+
+
+def mf_forward_static(ap: Aperture, xyz_q: torch.Tensor, signal: torch.Tensor, signal2=None,
+                      flags: int = 0, out=None, stream=None):
+    """rfvr_mf_forward_static: the filter forward on the library's static
+    scratch.  The library allocates nothing; with ``out`` = (z, power) or
+    (z, power, z2, power2) preallocated by the caller this wrapper allocates
+    nothing either."""
+    dev = xyz_q.device
+    cap = ap.c()
+    nq = xyz_q.numel() // 3
+    if out is None:
+        out = [torch.empty(nq, 2, dtype=torch.float32, device=dev), torch.empty(nq, dtype=torch.float32, device=dev)]
+        if signal2 is not None:
+            out += [torch.empty(nq, 2, dtype=torch.float32, device=dev),
+                    torch.empty(nq, dtype=torch.float32, device=dev)]
+    z, p = out[0], out[1]
+    z2, p2 = (out[2], out[3]) if signal2 is not None else (None, None)
+    _check(lib().rfvr_mf_forward_static(ctypes.byref(cap), _ptr(xyz_q), nq, int(flags), _ptr(signal), _ptr(z),
+                                        _ptr(p), _ptr(signal2), _ptr(z2), _ptr(p2), _stream(stream)),
+           "rfvr_mf_forward_static")
+    return tuple(out)
+
+
                 g_power: torch.Tensor, flags: int = 0, out=None, stream=None):
     """dL/dsignal [n_meas, n_freq, 2]."""
     dev = xyz_q.device

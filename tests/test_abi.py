@@ -246,3 +246,19 @@ def test_batched_calls_check_every_scene_before_launch(R):
     assert L.rfvr_render_forward_batched_ws_bytes(2, arr) == max(
         L.rfvr_render_forward_ws_bytes(ctypes.byref(arr[0].ap), ctypes.byref(arr[0].sm)),
         L.rfvr_render_forward_ws_bytes(ctypes.byref(arr[1].ap), ctypes.byref(arr[1].sm)))
+
+
+def test_static_filter_checks_size_before_any_device_work(R):
+    """rfvr_mf_forward_static refuses arguments and sizes its static scratch
+    cannot hold before touching the device (no GPU here)."""
+    L = R.lib()
+    v = ctypes.c_void_p(0x1000)
+    big = _ap(R, n_meas=16384, n_freq=256)
+    assert L.rfvr_mf_forward_ws_bytes(ctypes.byref(big), 64, 0) > R.MF_STATIC_SCRATCH_BYTES
+    assert L.rfvr_mf_forward_static(ctypes.byref(big), v, 64, 0, v, v, v, None, None, None, None) == -1
+    assert b"RFVR_MF_STATIC_SCRATCH_BYTES" in L.rfvr_last_error()
+    ap = _ap(R)
+    assert L.rfvr_mf_forward_static(ctypes.byref(ap), v, 0, 0, v, v, v, None, None, None, None) == -1
+    assert L.rfvr_mf_forward_static(ctypes.byref(_ap(R, rx=v)), v, 8, 0, v, v, v, None, None, None, None) == -3
+    hdr = open(HEADER).read()
+    assert f"#define RFVR_MF_STATIC_SCRATCH_BYTES (32u << 20)" in hdr and R.MF_STATIC_SCRATCH_BYTES == 32 << 20
