@@ -63,6 +63,9 @@ extern "C" {
 #define RFVR_PHASE_NAIVE32  0x4u  /* radians 2 pi f d / c formed in FP32 (precision study) */
 #define RFVR_ACCUMULATE     0x8u  /* gradient outputs add into existing contents   */
 #define RFVR_TERMS_DIRECT   0x10u /* per-frequency evaluation of the term sums (see below) */
+#define RFVR_WEIGHT_SEGMENT 0x20u /* render: each sample's segment weighted by the exact
+                                     integral of T^2 rho over it, placed at its midpoint
+                                     (see the render section) */
 
 /* Evaluation of the term sums (Eq. ref_sim, Eq. mf-sm and their adjoints).
  * By default the four term entry points (render forward / backward, matched
@@ -132,6 +135,17 @@ typedef struct rfvr_fields {
  *   c_ij   = A' w_r a_j alpha_j T'^2 spec_ij / r_ij^2,  r_ij = |x_j - tx_i|,
  *            spec = 2 (n_hat . w_i)^2 - 1 (monostatic w_o . w_r), see RFVR_SPEC_*
  *   s[i,n] = sum_j c_ij exp(-j 2 pi f_n 2 r_ij / c)
+ * With RFVR_WEIGHT_SEGMENT, sample j instead stands for the segment from it to
+ * the next sample of its ray: the weight alpha_j T'^2 becomes the exact
+ * integral of the round-trip weight T(u)^2 rho(u) over that segment (Eq.
+ * signal_amp_tracing, discretised as NeuS's T alpha is the integral of T rho),
+ *   alpha_j T_j clamp(Tbar_j + phi_tx[i] - phi_ray[r], 0, 1),  Tbar_j = T_j (1 - alpha_j/2)
+ * ((T_j^2 - T_{j+1}^2)/2 without the shift; on a real ray T' rho' du' = T rho du,
+ * so the shift enters once), and the contribution sits at the segment's
+ * midpoint m_j = (x_j + x_{j+1})/2 (the last sample, alpha = 0, at itself):
+ * r_ij, the phase and spec are taken at m_j, n_hat and a at x_j.  The sum
+ * then does not depend on how the samples split a ray, so sparse (importance)
+ * samples estimate the same signal as dense ones.
  * signal: [n_meas][n_freq] complex (output).  alpha_out/trans_out: optional
  * [n_ray*n_z] outputs (NULL to skip).
  * ------------------------------------------------------------------------ */

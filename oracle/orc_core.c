@@ -46,9 +46,13 @@ typedef struct {
 
 static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 
+/* seg = 0: the round trip weighs the sample by T_tx T_rx (T'^2 monostatic).
+ * seg = 1 (monostatic only): the caller passes base = amp w refl alpha T and
+ * T = the segment's mean transmittance; the pair's factor is then the single
+ * shifted value clamp(T + dtx, 0, 1) (see orc_render). */
 static void pair_eval(const double* tx, const double* rx, const double* x,
                       const double* nh, double base, double T, double dtx, double drx,
-                      int spec_mode, pair_t* p)
+                      int spec_mode, int seg, pair_t* p)
 {
     double dt[3] = {x[0] - tx[0], x[1] - tx[1], x[2] - tx[2]};
     double rt = sqrt(dt[0] * dt[0] + dt[1] * dt[1] + dt[2] * dt[2]);
@@ -82,14 +86,16 @@ static void pair_eval(const double* tx, const double* rx, const double* x,
     double mtx = (ttx_raw >= 0.0 && ttx_raw <= 1.0) ? 1.0 : 0.0;
     double mrx = (trx_raw >= 0.0 && trx_raw <= 1.0) ? 1.0 : 0.0;
     double geo = 1.0 / (rt * rr);
+    double tt = seg ? ttx : ttx * trx;                      /* transmittance factor   */
+    double dtt = seg ? mtx : (mtx * trx + ttx * mrx);       /* its derivative in T    */
 
     p->d = rt + rr;
-    p->c = base * spec * ttx * trx * geo;
-    p->dc_dbase = spec * ttx * trx * geo;
-    p->dc_dT = base * spec * geo * (mtx * trx + ttx * mrx);
+    p->c = base * spec * tt * geo;
+    p->dc_dbase = spec * tt * geo;
+    p->dc_dT = base * spec * geo * dtt;
     for (int k = 0; k < 3; ++k) {
         double ds = spec_live ? -2.0 * (nr * wi[k] + ni * wr[k]) : 0.0;
-        p->dc_dn[k] = base * ttx * trx * geo * ds;
+        p->dc_dn[k] = base * tt * geo * ds;
     }
 }
 
@@ -100,7 +106,7 @@ typedef struct {
     int n_ray, n_z; const double* xyz; const double* ray_w;
     const double* nhat; const double* refl; const double* alpha; const double* trans;
     const double* phi_ray; const double* phi_tx; const double* phi_rx;
-    double amp; int spec_mode;
+    double amp; int spec_mode; int seg;
 } scene_t;
 
 static void scene_pair(const scene_t* S, int i, long j, pair_t* p)
@@ -116,20 +122,23 @@ static void scene_pair(const scene_t* S, int i, long j, pair_t* p)
         drx = dtx;
     }
     pair_eval(S->tx + 3 * (long)i, S->rx ? S->rx + 3 * (long)i : NULL, S->xyz + 3 * j,
-              S->nhat + 3 * j, base, S->trans[j], dtx, drx, S->spec_mode, p);
+              S->nhat + 3 * j, base, S->trans[j], dtx, drx, S->spec_mode, S->seg, p);
 }
 
-/* Signal tracing, Eq. ref_sim: s[i,n] = sum_j c_ij exp(-j 2 pi f_n d_ij / c). */
+/* Signal tracing, Eq. ref_sim: s[i,n] = sum_j c_ij exp(-j 2 pi f_n d_ij / c).
+ * The per-point arrays are what the weight needs (render.py prepares them):
+ * seg = 0: alpha_j and T_j at the sample points; seg = 1: alpha_j T_j, the
+ * segment's mean transmittance and the segment midpoints as positions. */
 void orc_render(int n_meas, const double* tx, const double* rx,
                 int n_freq, double f0, double df,
                 int n_ray, int n_z, const double* xyz, const double* ray_w,
                 const double* nhat, const double* refl, const double* alpha,
                 const double* trans, const double* phi_ray, const double* phi_tx,
-                const double* phi_rx, double amp, int spec_mode,
+                const double* phi_rx, double amp, int spec_mode, int seg,
                 double* s_re, double* s_im)
 {
     scene_t S = {n_meas, tx, rx, n_freq, f0, df, n_ray, n_z, xyz, ray_w, nhat, refl,
-                 alpha, trans, phi_ray, phi_tx, phi_rx, amp, spec_mode};
+                 alpha, trans, phi_ray, phi_tx, phi_rx, amp, spec_mode, seg};
     long n_pts = (long)n_ray * n_z;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < n_meas; ++i) {
@@ -155,12 +164,12 @@ void orc_render_adjoint(int n_meas, const double* tx, const double* rx,
                         int n_ray, int n_z, const double* xyz, const double* ray_w,
                         const double* nhat, const double* refl, const double* alpha,
                         const double* trans, const double* phi_ray, const double* phi_tx,
-                        const double* phi_rx, double amp, int spec_mode,
+                        const double* phi_rx, double amp, int spec_mode, int seg,
                         const double* gs_re, const double* gs_im,
                         double* g_base, double* g_trans, double* g_nhat)
 {
     scene_t S = {n_meas, tx, rx, n_freq, f0, df, n_ray, n_z, xyz, ray_w, nhat, refl,
-                 alpha, trans, phi_ray, phi_tx, phi_rx, amp, spec_mode};
+                 alpha, trans, phi_ray, phi_tx, phi_rx, amp, spec_mode, seg};
     long n_pts = (long)n_ray * n_z;
 #pragma omp parallel for schedule(dynamic, 64)
     for (long j = 0; j < n_pts; ++j) {

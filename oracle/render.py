@@ -19,6 +19,16 @@ Definitions followed (GeRaF, arXiv 2605.29097):
   primary ray), 0, 1), origins detached (Eq. lens-less-transmittance);
 * amplitude amp * w * refl * alpha * T_tx * T_rx * (w_o . w_r) / (r_t r_r)
   (Eq. signal_amp_tracing, Eq. reflection_angle);
+* or, with weight="segment" (monostatic): the exact integral of the round-trip
+  weight T(u)^2 rho(u) over the segment [u_k, u_{k+1}] that alpha_k covers.
+  Along the primary ray T rho du = -dT, so the integral is
+  (T_k^2 - T_{k+1}^2) / 2 = alpha_k T_k Tbar_k with the segment's mean
+  transmittance Tbar_k = T_k (1 - alpha_k / 2), whatever the spacing; on a real
+  ray (Eq. lens-less-transmittance, App. B.2) T' rho' du' = T rho du as well,
+  so the integral of T'^2 rho' is alpha_k T_k (Tbar_k + dPhi), clamped to
+  [0, 1] like T'.  The segment's contribution sits at its midpoint
+  (x_k + x_{k+1}) / 2 (the last sample, alpha = 0, at itself), with the
+  sample's normal and reflectiveness;
 * signal tracing Eq. ref_sim and matched filter Eq. mf-sm, with
   f_n = f0 + n df and round-trip delay d/c; P = |z| (magnitude, as printed);
 * loss L = (1/Q) sum_q m_q (P_q - P*_q)^2 (Sec. "Overview", step 5).
@@ -49,11 +59,11 @@ def _lib():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.orc_render.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp,
-                                   ctypes.c_double, ctypes.c_int, dp, dp]
+                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
         lib.orc_render_adjoint.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp,
-                                           dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp, dp,
-                                           dp, dp, dp]
+                                           dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           dp, dp, dp, dp, dp]
         lib.orc_mf.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                ctypes.c_long, dp, dp, dp, dp, dp]
         lib.orc_mf_adjoint.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double,
@@ -139,7 +149,18 @@ def unit_normal(grad):
 # forward
 # --------------------------------------------------------------------------
 
-def _scene_args(ap: Aperture, xyz, fields: Fields, ray_w):
+WEIGHTS = {"sample": 0, "segment": 1}
+
+
+def segment_midpoints(xyz):
+    """(x_k + x_{k+1}) / 2 along each ray; the last sample stays where it is."""
+    xyz = np.asarray(xyz, np.float64)
+    mid = xyz.copy()
+    mid[:, :-1] = 0.5 * (xyz[:, :-1] + xyz[:, 1:])
+    return mid
+
+
+def _scene_args(ap: Aperture, xyz, fields: Fields, ray_w, weight="sample"):
     xyz = np.asarray(xyz)
     n_ray, n_z = xyz.shape[0], xyz.shape[1]
     _, alpha, trans, _ = alpha_trans(fields.sdf, fields.s)
@@ -151,20 +172,28 @@ def _scene_args(ap: Aperture, xyz, fields: Fields, ray_w):
         keep.append(arr)
         return ptr
 
-    args = [ap.n_meas, P(ap.tx), P(ap.rx), ap.n_freq, ap.f0, ap.df, n_ray, n_z, P(xyz),
-            P(ray_w), P(nhat), P(fields.refl), P(alpha), P(trans), P(fields.phi_ray),
+    if weight == "segment":
+        if ap.rx is not None:
+            raise ValueError("the segment weight is defined for monostatic apertures")
+        pos, a_in, t_in = segment_midpoints(xyz), alpha * trans, trans * (1.0 - 0.5 * alpha)
+    else:
+        pos, a_in, t_in = xyz, alpha, trans
+    args = [ap.n_meas, P(ap.tx), P(ap.rx), ap.n_freq, ap.f0, ap.df, n_ray, n_z, P(pos),
+            P(ray_w), P(nhat), P(fields.refl), P(a_in), P(t_in), P(fields.phi_ray),
             P(fields.phi_tx), P(fields.phi_rx), float(fields.amp)]
     return args, keep, alpha, trans
 
 
 def render(ap: Aperture, xyz, fields: Fields, spec: str = "clamp", ray_w=None,
-           return_parts: bool = False):
-    """Rendered signal s [n_meas, n_freq] complex128 (Eq. ref_sim)."""
-    args, keep, alpha, trans = _scene_args(ap, xyz, fields, ray_w)
+           return_parts: bool = False, weight: str = "sample"):
+    """Rendered signal s [n_meas, n_freq] complex128 (Eq. ref_sim); weight
+    "sample" (T^2 alpha at the sample) or "segment" (see the module notes)."""
+    args, keep, alpha, trans = _scene_args(ap, xyz, fields, ray_w, weight)
     s_re = np.zeros((ap.n_meas, ap.n_freq))
     s_im = np.zeros((ap.n_meas, ap.n_freq))
     dp = ctypes.POINTER(ctypes.c_double)
-    _lib().orc_render(*args, SPEC_MODES[spec], s_re.ctypes.data_as(dp), s_im.ctypes.data_as(dp))
+    _lib().orc_render(*args, SPEC_MODES[spec], WEIGHTS[weight], s_re.ctypes.data_as(dp),
+                      s_im.ctypes.data_as(dp))
     s = s_re + 1j * s_im
     if return_parts:
         return s, alpha, trans
@@ -246,9 +275,10 @@ def mf_adjoint_linear(ap: Aperture, xq, gz):
     return gs_re + 1j * gs_im
 
 
-def render_adjoint_parts(ap: Aperture, xyz, fields: Fields, g_s, spec="clamp", ray_w=None):
-    """Per-point partials before the scan: dL/d(base), dL/dT, dL/dn_hat."""
-    args, keep, alpha, trans = _scene_args(ap, xyz, fields, ray_w)
+def render_adjoint_parts(ap: Aperture, xyz, fields: Fields, g_s, spec="clamp", ray_w=None, weight="sample"):
+    """Per-point partials before the scan: dL/d(base), dL/dT, dL/dn_hat, where
+    base and T are the C core's per-point inputs (see _scene_args)."""
+    args, keep, alpha, trans = _scene_args(ap, xyz, fields, ray_w, weight)
     gr, pgr = _d(np.real(g_s))
     gi, pgi = _d(np.imag(g_s))
     xyz = np.asarray(xyz)
@@ -257,26 +287,34 @@ def render_adjoint_parts(ap: Aperture, xyz, fields: Fields, g_s, spec="clamp", r
     g_trans = np.zeros(n_pts)
     g_nhat = np.zeros((n_pts, 3))
     dp = ctypes.POINTER(ctypes.c_double)
-    _lib().orc_render_adjoint(*args, SPEC_MODES[spec], pgr, pgi, g_base.ctypes.data_as(dp),
+    _lib().orc_render_adjoint(*args, SPEC_MODES[spec], WEIGHTS[weight], pgr, pgi, g_base.ctypes.data_as(dp),
                               g_trans.ctypes.data_as(dp), g_nhat.ctypes.data_as(dp))
     shp = xyz.shape[:2]
     return g_base.reshape(shp), g_trans.reshape(shp), g_nhat.reshape(shp + (3,)), alpha, trans
 
 
-def render_adjoint(ap: Aperture, xyz, fields: Fields, g_s, spec="clamp", ray_w=None):
+def render_adjoint(ap: Aperture, xyz, fields: Fields, g_s, spec="clamp", ray_w=None, weight="sample"):
     """Gradients of L (through s) w.r.t. the per-point fields, A' and s.
 
     Returns dict(sdf [n_ray,n_z], grad [n_ray,n_z,3], refl [n_ray,n_z],
     amp (scalar), s (scalar)).  The origin occupancies are detached.
     """
-    g_base, g_T, g_nhat, alpha, trans = render_adjoint_parts(ap, xyz, fields, g_s, spec, ray_w)
+    g_base, g_Tin, g_nhat, alpha, trans = render_adjoint_parts(ap, xyz, fields, g_s, spec, ray_w, weight)
     n_ray, n_z = g_base.shape
     w = np.ones(n_ray) if ray_w is None else np.asarray(ray_w, np.float64)
     refl = np.asarray(fields.refl, np.float64)
     amp = float(fields.amp)
-    g_alpha = g_base * amp * w[:, None] * refl
-    g_refl = g_base * amp * w[:, None] * alpha
-    g_amp = float(np.sum(g_base * w[:, None] * refl * alpha))
+    if weight == "segment":
+        # base = amp w refl alpha T and Tbar = T (1 - alpha/2)
+        g_alpha = g_base * amp * w[:, None] * refl * trans - 0.5 * g_Tin * trans
+        g_T = g_base * amp * w[:, None] * refl * alpha + g_Tin * (1.0 - 0.5 * alpha)
+        ta = alpha * trans
+    else:
+        g_alpha = g_base * amp * w[:, None] * refl
+        g_T = g_Tin
+        ta = alpha
+    g_refl = g_base * amp * w[:, None] * ta
+    g_amp = float(np.sum(g_base * w[:, None] * refl * ta))
 
     # transmittance product scan, reverse: R_k = g_T[k+1] + (1-alpha[k+1]) R_{k+1}
     R = np.zeros((n_ray, n_z))

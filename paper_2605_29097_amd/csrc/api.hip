@@ -73,7 +73,8 @@ static int check_fields(const rfvr_fields* fl) {
 }
 
 static int check_flags(uint32_t flags) {
-    if ((flags & ~(RFVR_SPEC_MASK | RFVR_PHASE_NAIVE32 | RFVR_ACCUMULATE | RFVR_TERMS_DIRECT)) != 0 ||
+    if ((flags & ~(RFVR_SPEC_MASK | RFVR_PHASE_NAIVE32 | RFVR_ACCUMULATE | RFVR_TERMS_DIRECT |
+                   RFVR_WEIGHT_SEGMENT)) != 0 ||
         (flags & RFVR_SPEC_MASK) == 3u) {
         set_error("unknown flag bits 0x%x", flags);
         return RFVR_E_INVALID;
@@ -90,6 +91,7 @@ static RenderGeom make_geom(const rfvr_aperture* ap, int n_ray, int n_z) {
     g.n_pts = (long)n_ray * n_z;
     g.K0 = 2.0 * ap->f0_hz / kSpeedOfLight;
     g.Kd = 2.0 * ap->df_hz / kSpeedOfLight;
+    g.seg = 0;
     return g;
 }
 
@@ -256,7 +258,8 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
         (rc = check_flags(flags)))
         return rc;
     if (!signal) { set_error("signal output is NULL"); return RFVR_E_INVALID; }
-    const RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
+    RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
+    g.seg = (flags & RFVR_WEIGHT_SEGMENT) ? 1 : 0;
     if ((rc = check_ws(ws, ws_bytes, ws_render_forward(g)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
@@ -310,7 +313,8 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
         return rc;
     if (!g_signal) { set_error("g_signal is NULL"); return RFVR_E_INVALID; }
     if (sm->point_weight) { set_error("point weights are supported by rfvr_render_forward only"); return RFVR_E_UNSUPPORTED; }
-    const RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
+    RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
+    g.seg = (flags & RFVR_WEIGHT_SEGMENT) ? 1 : 0;
     if ((rc = check_ws(ws, ws_bytes, ws_render_backward(g)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int acc = (flags & RFVR_ACCUMULATE) ? 1 : 0;

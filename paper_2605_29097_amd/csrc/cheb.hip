@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_cheb_points(
                 spec_factor<SPEC>(nd, spec, live);
             }
             const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
-            cr = P.b * spec * (T * T) * (y * y);
+            cr = P.b * spec * (T * (P.sq != 0.0f ? T : 1.0f)) * (y * y);
             ci = 0.0f;
         } else {
             const QRec& Q = cur;
@@ -595,11 +595,13 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
         }
         const float Tr = P.tp + A.phi;
         const float T = fminf(fmaxf(Tr, 0.0f), 1.0f);
-        const float Tm = T == Tr ? T : 0.0f;                   // T where the clamp is inactive
+        // transmittance factor T^2 (sample weight) or T (segment weight) and
+        // its derivative where the clamp is inactive
+        const float dT = T == Tr ? (P.sq != 0.0f ? T + T : 1.0f) : 0.0f;
         const float gy = G * (y * y);
-        const float gs = gy * spec, T2 = T * T;
+        const float gs = gy * spec, T2 = T * (P.sq != 0.0f ? T : 1.0f);
         gb = __builtin_fmaf(gs, T2, gb);
-        gt = __builtin_fmaf(gs, Tm, gt);                       // times 2 b after the loop
+        gt = __builtin_fmaf(gs, dT, gt);                       // times b after the loop
         if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
             const float cn = gy * T2 * (nd * y) * live;        // times 4 b after the loop
             gn0 = __builtin_fmaf(cn, fdx, gn0);
@@ -609,7 +611,7 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
     }
     if (j >= n_pts) return;
     g_b[j] = gb;
-    g_T[j] = 2.0f * P.b * gt;
+    g_T[j] = P.b * gt;
     const float b4 = 4.0f * P.b;
     g_n[3 * j] = b4 * gn0;
     g_n[3 * j + 1] = b4 * gn1;

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_render_prep(
     int n_ray, int n_z, const float* __restrict__ xyz, const float* __restrict__ ray_w,
     const float* __restrict__ pt_w, const float* __restrict__ sdf, const float* __restrict__ grad, const float* __restrict__ refl,
     const float* __restrict__ phi_ray, int use_phi, float s, float amp_h,
-    const float* __restrict__ amp_ptr, PtRec* __restrict__ rec, float* __restrict__ alpha_out,
+    const float* __restrict__ amp_ptr, int seg, PtRec* __restrict__ rec, float* __restrict__ alpha_out,
     float* __restrict__ trans_out) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -102,12 +102,25 @@ __global__ __launch_bounds__(256) void k_render_prep(
             p.z = (double)xyz[3 * j + 2];
             p.b = amp * w * refl[j] * alpha * (pt_w ? pt_w[j] : 1.0f);
             p.tp = T - pr;
+            p.sq = 1.0f;
+            if (seg) {
+                // the segment to the next sample: its midpoint (exact in FP64
+                // from the FP32 inputs), the exact integral of T^2 rho over it
+                // alpha T (T (1 - alpha/2) + dPhi) split as b and tp
+                if (k + 1 < n_z) {
+                    p.x = 0.5 * (p.x + (double)xyz[3 * j + 3]);
+                    p.y = 0.5 * (p.y + (double)xyz[3 * j + 4]);
+                    p.z = 0.5 * (p.z + (double)xyz[3 * j + 5]);
+                }
+                p.b *= T;
+                p.tp = T * (1.0f - 0.5f * alpha) - pr;
+                p.sq = 0.0f;
+            }
             float gx = grad[3 * j], gy = grad[3 * j + 1], gz = grad[3 * j + 2];
             float inv = 1.0f / fmaxf(sqrtf(gx * gx + gy * gy + gz * gz), 1e-12f);
             p.nx = gx * inv;
             p.ny = gy * inv;
             p.nz = gz * inv;
-            p.pad = 0.0f;
             rec[j] = p;
             if (alpha_out) alpha_out[j] = alpha;
             if (trans_out) trans_out[j] = T;
@@ -123,7 +136,7 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
     const int waves_per_block = 4;
     dim3 grid((g.n_ray + waves_per_block - 1) / waves_per_block);
     hipLaunchKernelGGL(k_render_prep, grid, dim3(256), 0, st, g.n_ray, g.n_z, xyz, ray_w, pt_w, sdf,
-                       grad, refl, phi_ray, use_phi, s, amp, amp_ptr, rec, alpha_out, trans_out);
+                       grad, refl, phi_ray, use_phi, s, amp, amp_ptr, g.seg, rec, alpha_out, trans_out);
     return hipGetLastError();
 }
 
@@ -209,7 +222,7 @@ __global__ __launch_bounds__(256) void k_reduce_points(
                     spec_factor<SPEC>(nd, spec, live);
                 }
                 const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
-                cr = P.b * spec * (T * T) * (g.y * g.y);
+                cr = P.b * spec * (T * (P.sq != 0.0f ? T : 1.0f)) * (g.y * g.y);
                 ci = 0.0f;
             } else {
                 const QRec Q = reinterpret_cast<const QRec*>(sRec[buf])[k];
@@ -454,12 +467,15 @@ __global__ __launch_bounds__(256) void k_render_bwd_points(
             const float Tr = P[u].tp + A.phi;
             const float T = fminf(fmaxf(Tr, 0.0f), 1.0f);
             const float mT = (Tr >= 0.0f && Tr <= 1.0f) ? 1.0f : 0.0f;
+            // transmittance factor T^2 (sample weight) or T (segment weight)
+            const bool sq = P[u].sq != 0.0f;
+            const float Tf = T * (sq ? T : 1.0f);
             const float gy = G * (y * y);
-            gb[u] = __builtin_fmaf(gy * spec, T * T, gb[u]);
-            gt[u] = __builtin_fmaf(gy * P[u].b * spec, 2.0f * T * mT, gt[u]);
+            gb[u] = __builtin_fmaf(gy * spec, Tf, gb[u]);
+            gt[u] = __builtin_fmaf(gy * P[u].b * spec, (sq ? 2.0f * T : 1.0f) * mT, gt[u]);
             if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
                 // d spec / d n_hat = 4 (n.w_i) w_i, w_i = d * y
-                const float cn = gy * P[u].b * (T * T) * (4.0f * nd * y) * live;
+                const float cn = gy * P[u].b * Tf * (4.0f * nd * y) * live;
                 gn0[u] = __builtin_fmaf(cn, fdx, gn0[u]);
                 gn1[u] = __builtin_fmaf(cn, fdy, gn1[u]);
                 gn2[u] = __builtin_fmaf(cn, fdz, gn2[u]);
@@ -521,7 +537,7 @@ __global__ __launch_bounds__(256) void k_scan_adjoint(
     const float* __restrict__ g_b, const float* __restrict__ g_T, const float* __restrict__ g_n,
     float* g_alpha_tmp, float* __restrict__ part_amp, float* __restrict__ part_s,
     float* __restrict__ g_sdf, float* __restrict__ g_grad, float* __restrict__ g_refl,
-    int accumulate) {
+    int accumulate, int seg) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (wave >= n_ray) return;
@@ -535,8 +551,12 @@ __global__ __launch_bounds__(256) void k_scan_adjoint(
         const int k = cc * 64 + lane;
         float A = 0.0f, B = 0.0f;
         if (k + 1 < n_z) {
-            A = 1.0f - alpha[base + k + 1];
-            B = g_T[base + k + 1];
+            const size_t jn = base + k + 1;
+            A = 1.0f - alpha[jn];
+            B = g_T[jn];
+            // segment weight: g_T holds dL/dTbar, Tbar = T (1 - alpha/2), and b
+            // carries T: dL/dT = dL/dTbar (1 - alpha/2) + dL/db A' w a alpha
+            if (seg) B = __builtin_fmaf(g_b[jn] * amp * w * refl[jn], alpha[jn], B * (1.0f - 0.5f * alpha[jn]));
         }
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -550,11 +570,15 @@ __global__ __launch_bounds__(256) void k_scan_adjoint(
         const float R0 = __shfl(R, 0, 64);
         if (k < n_z) {
             const size_t j = base + k;
-            const float gb = g_b[j], al = alpha[j], a = refl[j];
-            g_alpha_tmp[j] = gb * amp * w * a - trans[j] * R;
-            pamp = __builtin_fmaf(gb * w * a, al, pamp);
+            const float gb = g_b[j], al = alpha[j], a = refl[j], Tj = trans[j];
+            // b = A' w a alpha (sample weight) or A' w a alpha T (segment
+            // weight, whose Tbar = T (1 - alpha/2) adds -T/2 dL/dTbar)
+            const float ta = seg ? al * Tj : al;
+            const float direct = seg ? __builtin_fmaf(gb * amp * w * a, Tj, -0.5f * Tj * g_T[j]) : gb * amp * w * a;
+            g_alpha_tmp[j] = direct - Tj * R;
+            pamp = __builtin_fmaf(gb * w * a, ta, pamp);
             if (g_refl) {
-                float v = gb * amp * w * al;
+                float v = gb * amp * w * ta;
                 g_refl[j] = accumulate ? g_refl[j] + v : v;
             }
         }
@@ -634,7 +658,7 @@ hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const fl
     dim3 grid((g.n_ray + 3) / 4);
     hipLaunchKernelGGL(k_scan_adjoint, grid, dim3(256), 0, st, g.n_ray, g.n_z, ray_w, sdf, grad,
                        refl, s, amp, amp_ptr, alpha, trans, g_b, g_T, g_n, g_alpha_tmp, part_amp, part_s,
-                       g_sdf, g_grad, g_refl, accumulate);
+                       g_sdf, g_grad, g_refl, accumulate, g.seg);
     return hipGetLastError();
 }
 

@@ -21,13 +21,20 @@ namespace rfvr {
 constexpr double kSpeedOfLight = 299792458.0;
 constexpr float kAlphaEps = 1e-5f;
 
-// Per-point record consumed by the render kernels (48 bytes).
-//   b  = A' * w_r * a * alpha      (amplitude without the per-pair factors)
-//   tp = T - Phi(primary-ray origin)  (lensless transmittance before the per-
-//        antenna shift; equals T when the correction is off)
+// Per-point record consumed by the render kernels (48 bytes).  With the
+// sample weight (default):
+//   x    = the sample point
+//   b    = A' * w_r * a * alpha      (amplitude without the per-pair factors)
+//   tp   = T - Phi(primary-ray origin)  (lensless transmittance before the per-
+//          antenna shift; equals T when the correction is off)
+//   sq   = 1: the pair's factor is the square of the shifted value T'
+// With the segment weight (RFVR_WEIGHT_SEGMENT):
+//   x    = the midpoint of the sample and the next one on its ray
+//   b    = A' * w_r * a * alpha * T,  tp = T (1 - alpha/2) - Phi(origin)
+//   sq   = 0: the pair's factor is the shifted value itself
 struct alignas(16) PtRec {
     double x, y, z;
-    float b, tp, nx, ny, nz, pad;
+    float b, tp, nx, ny, nz, sq;
 };
 static_assert(sizeof(PtRec) == 48, "PtRec layout");
 
@@ -274,6 +281,7 @@ struct RenderGeom {
     int n_meas, n_freq, n_ray, n_z;
     long n_pts;
     double K0, Kd;        // 2 f0 / c and 2 df / c (revolutions per metre of range)
+    int seg;              // 1: segment weight (RFVR_WEIGHT_SEGMENT), 0: sample weight
 };
 int choose_point_splits(long n_pts, int lanes_total);
 int freq_chunk(int n_freq);

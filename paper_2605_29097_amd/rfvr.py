@@ -24,6 +24,7 @@ SPEC_CLAMP, SPEC_RAW, SPEC_OFF = 0x0, 0x1, 0x2
 PHASE_FP64RR, PHASE_NAIVE32 = 0x0, 0x4
 ACCUMULATE = 0x8
 TERMS_DIRECT = 0x10      # per-frequency evaluation of the term sums
+WEIGHT_SEGMENT = 0x20    # render: exact segment integral of T^2 rho, placed at the segment midpoint
 SAMPLE_GRID, SAMPLE_STRATIFIED = 0, 1
 PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
 # size limits of one call (RFVR_MAX_* in rfvr.h)
@@ -83,9 +84,9 @@ _SIGS = {
     "rfvr_mf_forward_ws_bytes": ([_P(CAperture), _c_i64, _c_i32], _sz),
     "rfvr_mf_forward": ([_P(CAperture), _vp, _c_i64, _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
                         _c_i32),
-    "rfvr_mf_backward_ws_bytes": ([_P(CAperture), _c_i64], _sz),
     "rfvr_mf_forward_static": ([_P(CAperture), _vp, _c_i64, _c_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
                                _c_i32),
+    "rfvr_mf_backward_ws_bytes": ([_P(CAperture), _c_i64], _sz),
     "rfvr_mf_backward": ([_P(CAperture), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp],
                          _c_i32),
     "rfvr_loss_ws_bytes": ([_c_i64], _sz),
@@ -310,7 +311,6 @@ def mf_forward(ap: Aperture, xyz_q: torch.Tensor, signal: torch.Tensor, signal2=
     return (z, p) if signal2 is None else (z, p, z2, p2)
 
 
-def mf_backward(ap: Aperture, xyz_q: torch.Tensor, z: torch.Tensor, power: torch.Tensor,
 MF_STATIC_SCRATCH_BYTES = 32 << 20     # RFVR_MF_STATIC_SCRATCH_BYTES
 
 
@@ -336,6 +336,7 @@ def mf_forward_static(ap: Aperture, xyz_q: torch.Tensor, signal: torch.Tensor, s
     return tuple(out)
 
 
+def mf_backward(ap: Aperture, xyz_q: torch.Tensor, z: torch.Tensor, power: torch.Tensor,
                 g_power: torch.Tensor, flags: int = 0, out=None, stream=None):
     """dL/dsignal [n_meas, n_freq, 2]."""
     dev = xyz_q.device

@@ -608,3 +608,147 @@ def test_lensless_transmittance_against_real_rays():
     print(f"\n[report] shift |dPhi| mean {np.abs(shift).mean():.3f} max {np.abs(shift).max():.3f}; "
           f"lensless - real T: rms {np.sqrt(np.mean(err ** 2)):.3e}, max {np.abs(err).max():.3e}; "
           f"without the shift: rms {np.sqrt(np.mean((res[:, 0] - shift - res[:, 1]) ** 2)):.3e}")
+
+
+# ---------------------------------------------------------------- segment weight
+
+@pytest.mark.parametrize("n_z", [3, 7, 60])
+def test_segment_weight_sum_is_independent_of_the_samples(n_z):
+    """With weight="segment" every segment carries the exact integral of the
+    round-trip weight T^2 rho, (T_k^2 - T_{k+1}^2) / 2, so the weights of a ray
+    add up to (1 - T_end^2) / 2 whatever its samples.  All samples of the ray
+    sit at one point (so every contribution has the same phase, range and
+    specular factor), the SDF falls monotonically from +2 cm to -1.5 cm through
+    randomly spaced levels, and NeuS telescoping gives T_end = (Phi_end + eps) /
+    (Phi_0 + eps): the signal is A' a spec (1 - T_end^2) / 2 e^{-j4 pi f r/c} /
+    r^2 for every sample count."""
+    s, eps = 64.0, 1e-5
+    rng = np.random.default_rng(n_z)
+    levels = np.sort(rng.uniform(-0.015, 0.02, n_z - 2))[::-1]
+    sdf = np.concatenate([[0.02], levels, [-0.015]])[None]
+    x = np.array([0.003, -0.002, 0.29])
+    xyz = np.tile(x, (1, n_z, 1))
+    nrm = np.array([0.1, 0.05, -1.0])
+    grad = np.tile(nrm, (1, n_z, 1))
+    refl = np.full((1, n_z), 0.7)
+    ap = _ap(3, 2, 6)
+    F = orc.Fields(sdf=sdf, grad=grad, refl=refl, s=s, amp=1.4)
+    got = orc.render(ap, xyz, F, spec="raw", weight="segment")
+    Phi = lambda f: 1.0 / (1.0 + np.exp(-s * f))
+    T_end = (Phi(-0.015) + eps) / (Phi(0.02) + eps)
+    fn = ap.f0 + ap.df * np.arange(ap.n_freq)
+    nh = nrm / np.linalg.norm(nrm)
+    for i in range(ap.n_meas):
+        d = x - ap.tx[i]
+        r = np.linalg.norm(d)
+        spec_f = 2.0 * np.dot(nh, d / r) ** 2 - 1.0
+        expect = 1.4 * 0.7 * spec_f * 0.5 * (1.0 - T_end ** 2) * np.exp(-4j * np.pi * fn * r / C0) / r ** 2
+        np.testing.assert_allclose(got[i], expect, rtol=1e-11)
+    # the sample weight instead depends on the spacing (the three sample
+    # counts give different sums), which is what the segment weight removes
+    w_sample = orc.render(ap, xyz, F, spec="raw")[0, 0] / got[0, 0] * 0.5 * (1 - T_end ** 2)
+    assert abs(w_sample - 0.5 * (1 - T_end ** 2)) > 1e-3
+
+
+def test_segment_weight_closed_form_with_midpoints_and_shift():
+    """The two-scatterer ray of the transmittance-shift pin, with the segment
+    weight: each live segment contributes A' a spec alpha T clamp(T (1 -
+    alpha/2) + dPhi, 0, 1) / r^2 at the midpoint of its two samples (range,
+    phase and specular factor taken there, normal and reflectiveness from its
+    first sample), written out by hand; the occupancies make the clamp act at
+    both ends for some measurements."""
+    s, f_mid = 64.0, 0.01
+    xyz, sdf, grad, refl = _two_scatterer_ray(s=s, f_mid=f_mid)
+    tx = planar_aperture(4, 3, 2e-3).astype(np.float64)
+    f0, df = freq_grid(5)
+    phi_ray = np.array([0.90, 0.70, 0.60])
+    d_tx = np.array([-0.30, 0.25, -0.50, -0.45, 0.20, -0.10, -0.65, 0.28, -0.70, -0.40, 0.0, -0.60])
+    phi_tx = phi_ray[1] + d_tx
+    ap = orc.Aperture(tx=tx, f0=f0, df=df, n_freq=5)
+    F = orc.Fields(sdf=sdf, grad=grad, refl=refl, s=s, amp=1.3, phi_ray=phi_ray, phi_tx=phi_tx)
+    got = orc.render(ap, xyz, F, spec="raw", weight="segment")
+    clamp = lambda v: min(1.0, max(0.0, v))
+    fn = f0 + df * np.arange(5)
+    expect = np.zeros((tx.shape[0], 5), complex)
+    seen = set()
+    for k, (alpha, T) in zip((1, 2), _hand_alpha_T(s, f_mid)):
+        m = 0.5 * (xyz[1, k] + xyz[1, k + 1])
+        nrm = grad[1, k] / np.linalg.norm(grad[1, k])
+        Tbar = T * (1.0 - 0.5 * alpha)
+        for i in range(tx.shape[0]):
+            d = m - tx[i]
+            r = np.linalg.norm(d)
+            spec_f = 2.0 * np.dot(nrm, d / r) ** 2 - 1.0
+            sh = Tbar + d_tx[i]
+            seen.add("low" if sh < 0 else ("high" if sh > 1 else "in"))
+            c = 1.3 * refl[1, k] * alpha * T * spec_f * clamp(sh) / r ** 2
+            expect[i] += c * np.exp(-4j * np.pi * fn * r / C0)
+    assert seen == {"low", "high", "in"}
+    np.testing.assert_allclose(got, expect, rtol=1e-10, atol=1e-12 * np.abs(expect).max())
+
+
+def test_segment_weight_gradient_finite_differences():
+    """Adjoint of the segment-weight render (midpoints, shift past both clamps)
+    in sdf, grad, refl, A' and s against FP64 central differences."""
+    xyz, F = _small_scene(seed=8, n_z=6)
+    ap = _ap(3, 2, 4)
+    rng = np.random.default_rng(23)
+    F.phi_ray = rng.uniform(0.35, 0.65, xyz.shape[0])
+    F.phi_tx = np.array([0.05, 0.95, 0.5, 0.2, 0.8, 0.6])
+    gs = rng.normal(size=(ap.n_meas, ap.n_freq)) + 1j * rng.normal(size=(ap.n_meas, ap.n_freq))
+    g = orc.render_adjoint(ap, xyz, F, gs, spec="raw", weight="segment")
+    _, alpha, T, raw = orc.alpha_trans(F.sdf, F.s)
+    shifted = (T * (1 - 0.5 * alpha))[None] + F.phi_tx[:, None, None] - F.phi_ray[None, :, None]
+    assert (shifted < 0).any() and (shifted > 1).any()
+
+    def J(Fx):
+        s = orc.render(ap, xyz, Fx, spec="raw", weight="segment")
+        return float(np.sum(np.real(np.conj(gs) * s)))
+
+    def copy(Fx):
+        return orc.Fields(**{k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in Fx.__dict__.items()})
+
+    def fd(setter, h):
+        Fp, Fm = copy(F), copy(F)
+        setter(Fp, +h)
+        setter(Fm, -h)
+        return (J(Fp) - J(Fm)) / (2 * h)
+
+    checked = 0
+    for r in range(xyz.shape[0]):
+        for k in range(xyz.shape[1] - 1):
+            if abs(raw[r, k]) < 1e-3 or (k > 0 and abs(raw[r, k - 1]) < 1e-3):
+                continue
+            lo = max(k - 1, 0)
+            near = (np.abs(shifted[:, r, lo:]) < 1e-3) | (np.abs(shifted[:, r, lo:] - 1.0) < 1e-3)
+            if near.any():
+                continue
+
+            def set_sdf(Fx, h, r=r, k=k):
+                Fx.sdf[r, k] += h
+
+            num = fd(set_sdf, 1e-7)
+            assert abs(num - g["sdf"][r, k]) <= 1e-5 * max(abs(num), 1e-3 * np.abs(g["sdf"]).max()), (r, k)
+            checked += 1
+    assert checked >= 6
+    for (r, k) in [(0, 1), (2, 3), (4, 2)]:
+        for c in range(3):
+            def set_grad(Fx, h, r=r, k=k, c=c):
+                Fx.grad[r, k, c] += h
+            num = fd(set_grad, 1e-6)
+            assert abs(num - g["grad"][r, k, c]) <= 1e-6 * max(abs(num), 1e-3 * np.abs(g["grad"]).max())
+
+        def set_refl(Fx, h, r=r, k=k):
+            Fx.refl[r, k] += h
+        num = fd(set_refl, 1e-6)
+        assert abs(num - g["refl"][r, k]) <= 1e-6 * max(abs(num), 1e-3 * np.abs(g["refl"]).max())
+
+    def set_amp(Fx, h):
+        Fx.amp += h
+    num = fd(set_amp, 1e-6)
+    assert abs(num - g["amp"]) <= 1e-7 * abs(num)
+
+    def set_s(Fx, h):
+        Fx.s += h
+    num = fd(set_s, 1e-4)
+    assert abs(num - g["s"]) <= 1e-5 * abs(num)
