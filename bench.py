@@ -210,36 +210,193 @@ def probe(tr, which, reps):
     print(json.dumps({"probe": which, "reps": reps}))
 
 
-def proposal_study(args, dev):
-    """Torus-behind-slab scene: full-space training (2^20 grid points) against
-    proposal-sampled training (16 importance + 4 uniform depths per ray, 81,920
-    points) and the untrained control (20 stratified uniform depths), from the
-    same initial network.  Every run is evaluated by the full-space render of its
-    network against the clean target: signal NRMSE and heatmap (filter output)
-    NRMSE on the full-space grid.  E* is the full-space run's reference error after
-    its step budget; steps_to_e_star is the first evaluation at or below it.
-    Prints one JSON line."""
+def grid_points(centre, half, n):
+    """Cell centres of an n^3 grid over the cube, float32 [n^3, 3] (x fastest)."""
+    import numpy as np
+    ax = [c - half + (np.arange(n) + 0.5) * (2 * half / n) for c in centre]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.float32)
+
+
+def surface_points(f, centre, half):
+    """Points of the zero level set of f sampled on the n^3 grid of
+    grid_points (f indexed [z][y][x]): on every grid edge whose end values
+    change sign, the linear interpolation of the crossing -- the vertices
+    marching cubes places on that grid.  float64 [m, 3]."""
+    import numpy as np
+    f = np.asarray(f, np.float64)
+    n = f.shape[0]
+    h = 2 * half / n
+    lo = np.asarray(centre, np.float64) - half + 0.5 * h
+    out = []
+    for ax in range(3):                     # array axis 0 = z, 1 = y, 2 = x
+        a = np.take(f, np.arange(n - 1), axis=ax)
+        b = np.take(f, np.arange(1, n), axis=ax)
+        hit = (a < 0) != (b < 0)
+        idx = np.argwhere(hit)
+        fa, fb = a[hit], b[hit]
+        t = fa / (fa - fb)
+        pts = idx.astype(np.float64)
+        pts[:, ax] += t
+        out.append(lo[None, ::-1] + pts * h)              # (z, y, x) order
+    return np.concatenate(out, 0)[:, ::-1].copy()          # -> (x, y, z)
+
+
+def chamfer(a, b, n_sample=5000, seed=0):
+    """Chamfer distance between point sets (App. C, Training Setup metrics):
+    n_sample seeded samples per side, CD = mean_a min_b |a-b|^2 + mean_b
+    min_a |a-b|^2 (the squared form), and the symmetric mean of the plain
+    nearest distances.  Returns (cd_squared, cd_mean) in m^2 and m."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    a = a[rng.choice(len(a), min(n_sample, len(a)), replace=False)]
+    b = b[rng.choice(len(b), min(n_sample, len(b)), replace=False)]
+    da, _ = cKDTree(b).query(a)
+    db, _ = cKDTree(a).query(b)
+    return float(np.mean(da ** 2) + np.mean(db ** 2)), float(0.5 * (np.mean(da) + np.mean(db)))
+
+
+def network_grid_sdf(net, centre, half, n, dev):
+    """f of the SDF network at the cell centres of the n^3 grid (GPU), numpy [n][n][n]."""
     import numpy as np
     import torch
+    from paper_2605_29097_amd import rfvr as R
+    x = torch.from_numpy(grid_points(centre, half, n)).to(dev)
+    out = []
+    for k in range(0, x.shape[0], 1 << 22):
+        f, _, _ = R.mlp_forward(net, x[k:k + (1 << 22)].contiguous())
+        out.append(f.cpu().numpy())
+    return np.concatenate(out).reshape(n, n, n)
+
+
+def fit_prior(net, scene, centre, half, steps, dev, lr=1e-3, n_pool=1 << 20, batch=1 << 16, seed=0):
+    """Study scaffolding: fit the SDF network to an analytic prior scene by
+    regression of f on its signed distance (loss rfvr_loss_l2 on f, gradient
+    rfvr_mlp_backward, update rfvr_adamw), on a seeded pool of points in the
+    cube.  Returns the final RMS error of f in metres."""
+    import numpy as np
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from synth import scene_fields
+    rng = np.random.default_rng(seed)
+    pts = (np.asarray(centre) + rng.uniform(-half, half, (n_pool, 3))).astype(np.float32)
+    sdf, _, _ = scene_fields(scene, pts)
+    X = torch.from_numpy(pts).to(dev)
+    Y = torch.from_numpy(np.ascontiguousarray(sdf, np.float32)).to(dev)
+    n_par = net.param_count()
+    g = torch.zeros(n_par, device=dev)
+    m = torch.zeros(n_par, device=dev)
+    v = torch.zeros(n_par, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    for t in range(1, steps + 1):
+        idx = torch.randint(0, n_pool, (batch,), device=dev, generator=gen)
+        x, y = X[idx].contiguous(), Y[idx].contiguous()
+        f, _, _ = R.mlp_forward(net, x)
+        loss, g_f = R.loss_l2(f, y)
+        R.mlp_backward(net, x, g_f, None, None, out=g)
+        R.adamw(net.params, g, m, v, t, lr * 0.5 * (1 + np.cos(np.pi * t / steps)))
+    f, _, _ = R.mlp_forward(net, X[: 1 << 18].contiguous())
+    return float(torch.sqrt(torch.mean((f - Y[: 1 << 18]) ** 2)))
+
+
+def proposal_study(args, dev):
+    """Torus-behind-slab scene: full-space training (2^20 grid points) against
+    proposal-sampled training (n_imp importance + n_uni uniform depths per ray)
+    and the untrained control (n_imp + n_uni stratified uniform depths), from
+    the same initial network.  Every run is evaluated by the full-space render
+    of its network (judge_nz depths per ray) against the clean target: signal
+    NRMSE and heatmap (filter output) NRMSE at the judge's points.  E* is the
+    full-space run's error after its step budget; steps_to_e_star is the first
+    evaluation at or below it, and ms_to_e_star adds the proposal's warm-up
+    (proposal-only steps before the SDF network trains).  Prints one JSON line.
+
+    --study-prior fits every run's initial network to a coarse version of the
+    scene (torus and slab displaced and thickened by a few mm) by SDF
+    regression, the same parameters for every run; otherwise all runs start
+    from the geometric (sphere) initialisation."""
+    import numpy as np
+    import torch
+    from paper_2605_29097_amd import rfvr as R
     from paper_2605_29097_amd.train import ProposalConfig, ProposalTrainer, StepConfig, Trainer
-    from synth import MLPSpec, mlp_init
-    cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28), learn_s=args.study_learn_s, s=args.study_s)
+    from synth import MLPSpec, Slab, Torus, Union, mlp_init
+    flags = R.SPEC_CLAMP | (R.WEIGHT_SEGMENT if args.study_weight == "segment" else 0)
+    cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28), learn_s=args.study_learn_s, s=args.study_s,
+                     render_flags=flags, judge_nz=args.study_judge_nz)
     spec = MLPSpec(centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
-    name = "torus_target.npz" if cfg.s == 64.0 else f"torus_target_s{int(cfg.s)}.npz"
-    data = np.load(os.path.join(ROOT, "tests", "golden", name))      # rendered by the oracle at this s
+    if args.study_target:
+        name = args.study_target
+    else:
+        name = "torus_target.npz" if cfg.s == 64.0 else f"torus_target_s{int(cfg.s)}.npz"
+    data = np.load(os.path.join(ROOT, "tests", "golden", name))      # rendered by the oracle
     to_t = lambda a: torch.from_numpy(np.stack([a.real, a.imag], -1).astype(np.float32)).to(dev)
     noisy, clean = to_t(data["noisy"]), to_t(data["clean"])
+    p0 = torch.from_numpy(mlp_init(spec, cfg.seed)).to(dev)
+    prior_rms = None
+    if args.study_prior:
+        prior = Union([Slab(0.203, 0.007, 0.1), Torus((0.003, -0.002, 0.303), 0.043, 0.013, 0.8)])
+        net = R.MLP(params=p0.clone(), centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
+        prior_rms = fit_prior(net, prior, cfg.cube_centre, cfg.cube_side / 2, args.study_prior, dev)
+        p0 = net.params.detach().clone()
+        print(f"[study] prior fit: {args.study_prior} steps, f rms {prior_rms * 1e3:.3f} mm", file=sys.stderr,
+              flush=True)
+    # Chamfer distances on a 256^3 grid (App. C metrics): the true scene's
+    # surface points, each assigned to the primitive it lies on
+    truth = Union([Slab(0.20, 0.005, 0.1), Torus((0.0, 0.0, 0.30), 0.04, 0.01, 0.8)])
+    n_grid = args.study_grid
+
+    def split(pts):
+        d = [np.abs(p.eval(pts)[0]) for p in truth.parts]
+        return {"slab": pts[d[0] <= d[1]], "torus": pts[d[1] < d[0]]}
+
+    gt = None
+    if n_grid:
+        g_pts = grid_points(cfg.cube_centre, cfg.cube_side / 2, n_grid).astype(np.float64)
+        f_gt = np.concatenate([truth.eval(g_pts[k:k + (1 << 22)])[0] for k in range(0, len(g_pts), 1 << 22)])
+        gt = split(surface_points(f_gt.reshape(n_grid, n_grid, n_grid), cfg.cube_centre, cfg.cube_side / 2))
+        del g_pts, f_gt
+
+    def chamfer_of(net):
+        if gt is None:
+            return None
+        pts = surface_points(network_grid_sdf(net, cfg.cube_centre, cfg.cube_side / 2, n_grid, dev),
+                             cfg.cube_centre, cfg.cube_side / 2)
+        rec = split(pts)
+        out = {}
+        for k in ("torus", "slab"):
+            if len(rec[k]) == 0:
+                out[k] = None
+                continue
+            cd2, cd = chamfer(rec[k], gt[k])
+            out[k] = {"cd_sq_mm2": round(cd2 * 1e6, 4), "cd_mean_mm": round(cd * 1e3, 4)}
+        return out
+
+    prior_cd = None
+    pc = dict(n_imp=args.study_imp, n_uni=args.study_uni)
     runs = {
-        "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps),
-        "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(), device=dev),
-                     args.study_prop_steps),
-        "uniform_20": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(train=False), device=dev),
-                       args.study_prop_steps),
+        "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps, 0),
+        "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(**pc), device=dev),
+                     args.study_prop_steps, args.study_prop_warmup),
+        "uniform": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(train=False, **pc), device=dev),
+                    args.study_prop_steps, 0),
     }
     every = args.study_eval_every
     out = {}
-    for name, (make, n_steps) in runs.items():
-        tr = make(torch.from_numpy(mlp_init(spec, cfg.seed)))
+    for name, (make, n_steps, warm) in runs.items():
+        tr = make(p0.clone())
+        warm_ms = 0.0
+        if warm:
+            # proposal-only steps: the proposal learns where the initial
+            # network's blend weights are; their time is charged to the run
+            tr.train_sdf = False
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(warm):
+                tr.step()
+            e1.record()
+            e1.synchronize()
+            warm_ms = e0.elapsed_time(e1)
+            tr.train_sdf = True
         j = tr.evaluate(clean)
         curve = [(0, j["signal"], j["heatmap"])]
         step_ms = []
@@ -256,16 +413,24 @@ def proposal_study(args, dev):
                 print(f"[study] {name} step {k} reference signal {j['signal']:.4f} heatmap {j['heatmap']:.4f} "
                       f"s {tr.s:.1f} ({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
         out[name] = {"ms_per_step": float(np.median(step_ms[2:] if len(step_ms) > 4 else step_ms)),
-                     "steps": n_steps, "final_s": tr.s,
-                     "reference": [[k, round(a, 5), round(b, 5)] for k, a, b in curve]}
+                     "steps": n_steps, "warmup_steps": warm, "warmup_ms": round(warm_ms, 1), "final_s": tr.s,
+                     "reference": [[k, round(a, 5), round(b, 5)] for k, a, b in curve],
+                     "chamfer": chamfer_of(tr.net)}
+        if prior_cd is None:
+            prior_cd = chamfer_of(R.MLP(params=p0.clone(), centre=cfg.cube_centre, half_size=cfg.cube_side / 2))
+        del tr
+        torch.cuda.empty_cache()
     e_star = {"signal": out["full_space"]["reference"][-1][1], "heatmap": out["full_space"]["reference"][-1][2]}
     for name, r in out.items():
         for col, key in ((1, "signal"), (2, "heatmap")):
             hit = next((row[0] for row in r["reference"] if row[col] <= e_star[key]), None)
             r[f"steps_to_e_star_{key}"] = hit
-            r[f"ms_to_e_star_{key}"] = None if hit is None else round(hit * r["ms_per_step"], 1)
+            r[f"ms_to_e_star_{key}"] = None if hit is None else round(hit * r["ms_per_step"] + r["warmup_ms"], 1)
     print(json.dumps({"study": "proposal_vs_full_space", "e_star": e_star, "eval_every": every,
-                      "learn_s": cfg.learn_s, "s0": cfg.s,
+                      "learn_s": cfg.learn_s, "s0": cfg.s, "weight": args.study_weight, "target": name,
+                      "judge_nz": cfg.judge_nz or cfg.n_z, "prior_fit_steps": args.study_prior,
+                      "prior_f_rms_m": prior_rms, "n_imp": args.study_imp, "n_uni": args.study_uni,
+                      "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
                       "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
                                "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
                       "runs": out}))
@@ -473,6 +638,18 @@ def main():
     ap.add_argument("--study-learn-s", action="store_true", help="train log s in every run")
     ap.add_argument("--study-s", type=float, default=64.0,
                     help="initial s (1/m); the target is the oracle render of the scene at this s")
+    ap.add_argument("--study-weight", choices=["sample", "segment"], default="sample",
+                    help="render weight of every run (segment: RFVR_WEIGHT_SEGMENT)")
+    ap.add_argument("--study-target", default=None, help="target file under tests/golden")
+    ap.add_argument("--study-judge-nz", type=int, default=None, help="depths per ray of the judge render")
+    ap.add_argument("--study-prior", type=int, default=0,
+                    help="fit the initial network to a coarse scene for this many regression steps")
+    ap.add_argument("--study-grid", type=int, default=256,
+                    help="grid side of the Chamfer surface extraction (0: no Chamfer)")
+    ap.add_argument("--study-imp", type=int, default=16)
+    ap.add_argument("--study-uni", type=int, default=4)
+    ap.add_argument("--study-prop-warmup", type=int, default=0,
+                    help="proposal-only steps before the proposal run trains the SDF network")
     ap.add_argument("--naive-compare", action="store_true",
                     help="forward time of per-antenna sampling vs lensless sampling")
     ap.add_argument("--naive-apertures", type=int, nargs="+", default=[4, 8, 16])

@@ -442,10 +442,13 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
                            int32_t n_imp, int32_t n_uni, float* xyz, float* u, float* ray_origin,
                            void* stream);
 
-/* Proposal targets: per ray, blend weights w_k = trans_k * alpha_k of the
- * render at depths u [n_ray][n_k] summed into n_bins equal bins of [lo, hi]
- * (W_b), t_b = min(1, W_b / max(max_b W_b, 1e-3)).  targets: [n_ray][n_bins].
- * n_k <= RFVR_MAX_RAY_SAMPLES, n_bins <= 64. */
+/* Proposal targets: per ray, the blend weights w_k = trans_k * alpha_k of the
+ * render at depths u [n_ray][n_k] (ascending): w_k is the opacity of the
+ * segment [u_k, u_{k+1}], spread over the n_bins equal bins of [lo, hi] that
+ * the segment overlaps in proportion to the overlap (the last sample, and a
+ * segment of zero length, add w_k to the bin of u_k), giving W_b;
+ * t_b = min(1, W_b / max(max_b W_b, 1e-3)).  Overlaps and sums in FP64.
+ * targets: [n_ray][n_bins].  n_k <= RFVR_MAX_RAY_SAMPLES, n_bins <= 64. */
 int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
                           const float* trans, float lo, float hi, int32_t n_bins, float* targets,
                           void* stream);

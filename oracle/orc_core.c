@@ -146,6 +146,7 @@ void orc_render(int n_meas, const double* tx, const double* rx,
         for (long j = 0; j < n_pts; ++j) {
             pair_t p;
             scene_pair(&S, i, j, &p);
+            if (p.c == 0.0) continue;       /* its terms are exact zeros */
             for (int n = 0; n < n_freq; ++n) {
                 double ph = TWO_PI * phase_rev(f0, df, n, p.d);
                 s_re[(long)i * n_freq + n] += p.c * cos(ph);

@@ -15,8 +15,13 @@ draws xi from the counter-based SplitMix64 stream of the step with counter
 r * (n_uni + n_imp) + s; slots 0..n_uni-1 are the uniform ones.
 
 Training signal: the render's blend weights w_k = T_k alpha_k at the sampled
-depths, summed per bin (W_b), normalised per ray t_b = min(1, W_b / max(max_b W_b,
-1e-3)), and the mean binary cross-entropy between sigmoid(z_b) and t_b.
+depths.  w_k is the opacity of the segment [u_k, u_{k+1}] that alpha_k covers,
+so it is spread over the bins that segment overlaps, in proportion to the
+overlap (reading: with sparse samples a long segment says only that the
+surface lies somewhere inside it; the last sample, or a segment of zero length,
+goes to the bin of u_k).  The per-bin sums W_b are normalised per ray,
+t_b = min(1, W_b / max(max_b W_b, 1e-3)), and the mean binary cross-entropy
+between sigmoid(z_b) and t_b is the loss.
 
 Network: gamma_4(x_hat) (27 values) -> Linear(64) -> relu -> Linear(64) -> relu
 -> Linear(1); flat layout W0 [64][27], b0 [64], W1 [64][64], b1 [64],
@@ -107,13 +112,30 @@ def importance_depths(logits, lo, hi, n_imp, n_uni, seed, step):
     return np.take_along_axis(u, order, 1), np.take_along_axis(slot, order, 1)
 
 
-def bin_weights(u, w, lo, hi, n_bins):
-    """W[r, b] = sum of blend weights w[r, k] whose depth u[r, k] lies in bin b."""
+def bin_of(u, lo, hi, n_bins):
+    """Index of the equal depth bin of [lo, hi] holding depth u (clamped)."""
     u = np.asarray(u, np.float64)
-    b = np.clip(np.floor((u - lo) / (hi - lo) * n_bins).astype(np.int64), 0, n_bins - 1)
-    W = np.zeros((u.shape[0], n_bins))
-    for r in range(u.shape[0]):
-        np.add.at(W[r], b[r], np.asarray(w, np.float64)[r])
+    return np.clip(np.floor((u - lo) / (hi - lo) * n_bins).astype(np.int64), 0, n_bins - 1)
+
+
+def bin_weights(u, w, lo, hi, n_bins):
+    """W[r, b]: each blend weight w[r, k] spread over the bins that its segment
+    [u[r, k], u[r, k+1]] overlaps, in proportion to the overlap; the last
+    sample and zero-length segments put theirs in the bin of u[r, k]."""
+    u = np.asarray(u, np.float64)
+    w = np.asarray(w, np.float64)
+    n_ray, n_k = u.shape
+    edges = lo + (hi - lo) * np.arange(n_bins + 1) / n_bins
+    W = np.zeros((n_ray, n_bins))
+    for r in range(n_ray):
+        for k in range(n_k):
+            a = u[r, k]
+            e = u[r, k + 1] if k + 1 < n_k else a
+            if e > a:
+                ov = np.clip(np.minimum(e, edges[1:]) - np.maximum(a, edges[:-1]), 0.0, None)
+                W[r] += w[r, k] * ov / (e - a)
+            else:
+                W[r, bin_of(a, lo, hi, n_bins)] += w[r, k]
     return W
 
 

@@ -354,9 +354,12 @@ hipError_t launch_sample_naive(const rfvr_sample_desc& d, const double basis[9],
     return hipGetLastError();
 }
 
-// proposal targets: bin the blend weights T alpha of each ray, normalise by the max
-// per ray, one wave: sample k = s*64 + lane in register s (S >= n_k / 64)
-template <int S>
+// proposal targets: the blend weight T alpha of sample k is the opacity of the
+// segment [u_k, u_{k+1}] it covers, spread over the bins the segment overlaps
+// in proportion to the overlap (the last sample and zero-length segments: the
+// bin of u_k); then normalised by the ray's largest bin.  One wave per ray,
+// lane b owns bin b and walks the ray's segments in order, in FP64 (the
+// operations and their order are those of a double-precision reference).
 __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, const float* __restrict__ u,
                                                           const float* __restrict__ alpha,
                                                           const float* __restrict__ trans, float lo, float hi,
@@ -364,50 +367,38 @@ __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, co
     const long r = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (r >= n_ray) return;
-    // sample k = s*64 + lane sits in register s of its lane
-    float w[S];
-    int bk[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int k = s * 64 + lane;
-        w[s] = 0.0f;
-        bk[s] = -1;
-        if (k < n_k) {
-            const long j = r * n_k + k;
-            w[s] = trans[j] * alpha[j];
-            // bin decision in FP64, evaluated in the same order as a double-precision reference
-            const int b = (int)floor(((double)u[j] - (double)lo) / ((double)hi - (double)lo) * (double)n_bins);
-            bk[s] = b < 0 ? 0 : (b > n_bins - 1 ? n_bins - 1 : b);
+    const double dlo = lo, span = (double)hi - (double)lo;
+    const double e0 = dlo + span * (double)lane / (double)n_bins;
+    const double e1 = dlo + span * (double)(lane + 1) / (double)n_bins;
+    const float* ur = u + r * n_k;
+    const float* tr = trans + r * n_k;
+    const float* ar = alpha + r * n_k;
+    double W = 0.0;
+    for (int k = 0; k < n_k; ++k) {                            // uniform trip count
+        const double a = (double)ur[k];
+        const double e = k + 1 < n_k ? (double)ur[k + 1] : a;
+        const double w = (double)(tr[k] * ar[k]);
+        if (e > a) {
+            const double ov = fmin(e, e1) - fmax(a, e0);
+            if (ov > 0.0) W += w * ov / (e - a);
+        } else {
+            int b = (int)floor((a - dlo) / span * (double)n_bins);
+            b = b < 0 ? 0 : (b > n_bins - 1 ? n_bins - 1 : b);
+            if (b == lane) W += w;
         }
     }
-    // lane b sums the weights of its bin in sample order
-    float W = 0.0f;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        for (int l = 0; l < 64; ++l) {
-            if (s * 64 + l >= n_k) break;                      // uniform
-            const int bb = __shfl(bk[s], l, 64);
-            const float ww = __shfl(w[s], l, 64);
-            if (bb == lane) W += ww;
-        }
-    }
-    float mx = lane < n_bins ? W : 0.0f;
+    const float Wf = (float)W;
+    float mx = lane < n_bins ? Wf : 0.0f;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, 64));
-    if (lane < n_bins) targets[r * n_bins + lane] = fminf(1.0f, W / fmaxf(mx, 1e-3f));
+    if (lane < n_bins) targets[r * n_bins + lane] = fminf(1.0f, Wf / fmaxf(mx, 1e-3f));
 }
 
 hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
                                    float lo, float hi, int n_bins, float* targets, hipStream_t st) {
     const dim3 grid((unsigned)((n_ray + 3) / 4));
-#define RFVR_PT(S_) hipLaunchKernelGGL(k_proposal_targets<S_>, grid, dim3(256), 0, st, n_ray, n_k, u, alpha, \
-                                       trans, lo, hi, n_bins, targets)
-    if (n_k <= 64) RFVR_PT(1);
-    else if (n_k <= 128) RFVR_PT(2);
-    else if (n_k <= 256) RFVR_PT(4);
-    else if (n_k <= 512) RFVR_PT(8);
-    else RFVR_PT(16);                                          // n_k <= RFVR_MAX_RAY_SAMPLES = 1024
-#undef RFVR_PT
+    hipLaunchKernelGGL(k_proposal_targets, grid, dim3(256), 0, st, n_ray, n_k, u, alpha, trans, lo, hi, n_bins,
+                       targets);
     return hipGetLastError();
 }
 

@@ -48,7 +48,8 @@ class StepConfig:
     lr_other: float = 1e-3
     total_steps: int = 50000
     seed: int = 0
-    spec_flags: int = R.SPEC_CLAMP
+    render_flags: int = R.SPEC_CLAMP       # specular mode, optionally | R.WEIGHT_SEGMENT
+    judge_nz: Optional[int] = None         # depths of the full-space judge render (None: n_z)
     bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
     learn_s: bool = False                  # train log s with the head's learning rate
     precision: int = R.PREC_FP32           # network matrix operands (R.PREC_FP32 / BF16 / BF16X3)
@@ -183,19 +184,19 @@ class Trainer:
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
         ap_r, fl_r = self.ap, fl
         if c.bank_patch is None:
-            sig = R.render_forward(self.ap, sm, fl, flags=c.spec_flags)
+            sig = R.render_forward(self.ap, sm, fl, flags=c.render_flags)
         else:
             # Signal Tracing Bank: trace only the current patch's antennas into
             # its rows of the bank; the other rows keep earlier results
             if self.bank is None:
-                self.bank = R.render_forward(self.ap, sm, fl, flags=c.spec_flags)
+                self.bank = R.render_forward(self.ap, sm, fl, flags=c.render_flags)
             k = self.t % self.n_patch
             i0, i1 = k * self.patch_len, (k + 1) * self.patch_len
             ap_r = R.Aperture(tx=self.tx[i0:i1], f0=self.f0, df=self.df, n_freq=c.n_freq)
             n_ray = origin.shape[0]
             fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=self.s, amp=1.0, amp_dev=self.amp,
                             phi_ray=fl.phi_ray, phi_tx=phi[n_ray + i0:n_ray + i1].contiguous())
-            R.render_forward(ap_r, sm, fl_r, flags=c.spec_flags, out=self.bank[i0:i1])
+            R.render_forward(ap_r, sm, fl_r, flags=c.render_flags, out=self.bank[i0:i1])
             sig = self.bank
         mark("render_fwd")
         key = (c.sampling, None if c.sampling == R.SAMPLE_GRID else self.t)
@@ -217,7 +218,7 @@ class Trainer:
         # the filter has no parameters: only the traced rows carry gradient
         g_sig = R.mf_backward(ap_r, xyz, z, p, g_p)
         mark("mf_bwd")
-        gr = R.render_backward(ap_r, sm, fl_r, g_sig, flags=c.spec_flags)
+        gr = R.render_backward(ap_r, sm, fl_r, g_sig, flags=c.render_flags)
         mark("render_bwd")
         R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
                        out=self.g, reserve=res)
@@ -259,10 +260,11 @@ class Trainer:
     # ------------------------------------------------------- reference evaluation
     def reference_signal(self):
         """Full-space render of the current network on the uniform grid of the
-        configured sample cube (lensless primary rays, c.lines x c.n_z)."""
+        configured sample cube (lensless primary rays, c.lines x c.judge_nz
+        depths, c.n_z by default)."""
         c = self.cfg
         xyz, _, origin = R.sample_points(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0],
-                                         c.lines[1], c.n_z, mode=R.SAMPLE_GRID, device=self.dev)
+                                         c.lines[1], c.judge_nz or c.n_z, mode=R.SAMPLE_GRID, device=self.dev)
         f, grad, a = R.mlp_forward(self.net, xyz)
         f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
         phi = R.occupancy(self.s, f_org)
@@ -270,7 +272,7 @@ class Trainer:
                       refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
         self._ref_xyz = xyz
-        return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.spec_flags)
+        return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.render_flags)
 
     def evaluate(self, clean: torch.Tensor) -> dict:
         """Judge errors of the full-space render against a clean target signal:
@@ -332,7 +334,7 @@ class MultiPlaneTrainer(Trainer):
             fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
                           refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
                           phi_ray=phi[:n_ray].contiguous(), phi_tx=phi[n_ray:].contiguous())
-            sig = R.render_forward(pl["ap"], sm, fl, flags=c.spec_flags)
+            sig = R.render_forward(pl["ap"], sm, fl, flags=c.render_flags)
             if pl["p_star"] is None or c.sampling != R.SAMPLE_GRID:
                 z, p, _, p_star = R.mf_forward(pl["ap"], xyz, sig, pl["target"])
                 if c.sampling == R.SAMPLE_GRID:
@@ -342,7 +344,7 @@ class MultiPlaneTrainer(Trainer):
                 p_star = pl["p_star"]
             loss, g_p = R.loss_l2(p, p_star)
             g_sig = R.mf_backward(pl["ap"], xyz, z, p, g_p)
-            gr = R.render_backward(pl["ap"], sm, fl, g_sig, flags=c.spec_flags)
+            gr = R.render_backward(pl["ap"], sm, fl, g_sig, flags=c.render_flags)
             R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
                            flags=R.ACCUMULATE if j > 0 else 0, out=self.g, reserve=res)
             if j == 0:
@@ -450,7 +452,7 @@ class ProposalTrainer(Trainer):
         fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=self.s,
                       amp=1.0, amp_dev=self.amp, phi_ray=phi[:n_ray].contiguous(),
                       phi_tx=phi[n_ray:].contiguous())
-        sig, alpha, trans = R.render_forward(self.ap, sm, fl, flags=c.spec_flags, want_alpha=True)
+        sig, alpha, trans = R.render_forward(self.ap, sm, fl, flags=c.render_flags, want_alpha=True)
         mark("render_fwd")
         self.t += 1
         loss = None
@@ -460,7 +462,7 @@ class ProposalTrainer(Trainer):
             loss, g_p = R.loss_l2(p, p_star)
             g_sig = R.mf_backward(self.ap, xyz, z, p, g_p)
             mark("mf_bwd")
-            gr = R.render_backward(self.ap, sm, fl, g_sig, flags=c.spec_flags)
+            gr = R.render_backward(self.ap, sm, fl, g_sig, flags=c.render_flags)
             mark("render_bwd")
             R.mlp_backward(self.net, xyz, gr["sdf"].view(-1), gr["grad"].view(-1, 3), gr["refl"].view(-1),
                            out=self.g, reserve=res)

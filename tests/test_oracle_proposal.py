@@ -127,20 +127,40 @@ def test_importance_histogram_follows_pdf():
 
 
 def test_bin_weights_and_targets_brute_force():
+    """Spreading a segment's weight over the bins it overlaps, against brute
+    force: every segment cut into 20000 equal pieces, each piece's share put
+    into the bin of its centre (error below one piece per bin edge); the sum
+    over bins keeps each ray's total weight."""
     rng = np.random.default_rng(5)
     n_ray, n_k, n_bins = 7, 30, 10
     lo, hi = 0.1, 0.5
     u = np.sort(rng.uniform(lo, hi, (n_ray, n_k)), 1)
     u[0, 0], u[0, -1] = lo, hi                  # the range's ends land in the end bins
+    u[1, 5] = u[1, 4]                           # a zero-length segment
     w = rng.uniform(0, 0.2, (n_ray, n_k))
     w[3] = 1e-5                                  # tiny weights: the 1e-3 floor holds
     W = op.bin_weights(u, w, lo, hi, n_bins)
     Wb = np.zeros((n_ray, n_bins))
+    pieces = 20000
+    width = (hi - lo) / n_bins
     for r in range(n_ray):
         for k in range(n_k):
-            b = min(int((u[r, k] - lo) // ((hi - lo) / n_bins)), n_bins - 1)
-            Wb[r, b] += w[r, k]
-    np.testing.assert_allclose(W, Wb, rtol=1e-12, atol=1e-15)
+            a = u[r, k]
+            e = u[r, k + 1] if k + 1 < n_k else a
+            if e > a:
+                x = a + (np.arange(pieces) + 0.5) * (e - a) / pieces
+                b = np.minimum(((x - lo) // width).astype(int), n_bins - 1)
+                np.add.at(Wb[r], b, w[r, k] / pieces)
+            else:
+                Wb[r, min(int((a - lo) // width), n_bins - 1)] += w[r, k]
+    np.testing.assert_allclose(W, Wb, rtol=0, atol=2.0 * w.max() / pieces)
+    np.testing.assert_allclose(W.sum(1), w.sum(1), rtol=1e-12)
+    # a segment inside one bin stays there; one across an edge splits by length
+    Wh = op.bin_weights(np.array([[0.12, 0.13, 0.19, 0.24]]), np.array([[0.5, 0.3, 0.2, 0.0]]), lo, hi, n_bins)
+    # bins of 4 cm from 0.10: [0.12, 0.13] in bin 0; [0.13, 0.19] overlaps bins
+    # 0, 1, 2 by 1, 4, 1 cm; [0.19, 0.24] overlaps bins 2, 3 by 3, 2 cm
+    np.testing.assert_allclose(Wh[0, :4], [0.5 + 0.3 / 6, 0.3 * 4 / 6, 0.3 / 6 + 0.2 * 0.6, 0.2 * 0.4],
+                               rtol=1e-12)
     t = op.targets(W)
     np.testing.assert_allclose(t.max(1)[[0, 1, 2, 4, 5, 6]], 1.0)
     np.testing.assert_allclose(t[3], W[3] / 1e-3, rtol=1e-12)
