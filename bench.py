@@ -372,7 +372,7 @@ def proposal_study(args, dev):
         return out
 
     prior_cd = None
-    pc = dict(n_imp=args.study_imp, n_uni=args.study_uni)
+    pc = dict(n_imp=args.study_imp, n_uni=args.study_uni, loss_on_grid=args.study_loss_grid)
     runs = {
         "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps, 0),
         "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(**pc), device=dev),
@@ -430,6 +430,7 @@ def proposal_study(args, dev):
                       "learn_s": cfg.learn_s, "s0": cfg.s, "weight": args.study_weight, "target": name,
                       "judge_nz": cfg.judge_nz or cfg.n_z, "prior_fit_steps": args.study_prior,
                       "prior_f_rms_m": prior_rms, "n_imp": args.study_imp, "n_uni": args.study_uni,
+                      "loss_on_grid": args.study_loss_grid,
                       "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
                       "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
                                "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
@@ -646,6 +647,8 @@ def main():
                     help="fit the initial network to a coarse scene for this many regression steps")
     ap.add_argument("--study-grid", type=int, default=256,
                     help="grid side of the Chamfer surface extraction (0: no Chamfer)")
+    ap.add_argument("--study-loss-grid", action="store_true",
+                    help="sampled runs take the heatmap loss on the full-space grid (render from their samples)")
     ap.add_argument("--study-imp", type=int, default=16)
     ap.add_argument("--study-uni", type=int, default=4)
     ap.add_argument("--study-prop-warmup", type=int, default=0,
@@ -766,6 +769,10 @@ def main():
                                "6-octave encoding + 2x64 head, FP32, box target + 10 dB noise",
                    "terms_per_step": terms_step, "parallelism": "single GPU"},
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        # detached occupancy at the ray feet and antennas on the aperture
+        # plane (Eq. lens-less-transmittance) after the timed steps: the shift
+        # it produces is 1 - min at most
+        "phi_origins_min": float(tr.last["phi_origins"].min()),
         "roofline": roofline,
         "roofline_terms": roofline_terms,
     }

@@ -232,7 +232,7 @@ class Trainer:
         mark("adamw")
         if c.learn_s:
             self.update_s(gr["s"])
-        self.last = dict(signal=sig, loss=loss)
+        self.last = dict(signal=sig, loss=loss, phi_origins=phi)
         return loss
 
     def reserve(self, n: int):
@@ -379,6 +379,8 @@ class ProposalConfig:
     lr: float = 1e-3
     train: bool = True          # False: the untrained control, a uniform pdf (stratified samples only)
     seed: int = 0
+    loss_on_grid: bool = False  # heatmap loss on the full-space grid (its target cached) instead of
+                                # at the drawn samples; the signal is still rendered from the samples
 
 
 class ProposalTrainer(Trainer):
@@ -457,10 +459,21 @@ class ProposalTrainer(Trainer):
         self.t += 1
         loss = None
         if self.train_sdf:
-            z, p, _, p_star = R.mf_forward(self.ap, xyz, sig, self.target)
+            if pc.loss_on_grid:
+                # the filter and the loss at the full-space grid, whose target
+                # heatmap is fixed (computed once): the samples only render
+                if self.p_star is None:
+                    self.grid_xyz = R.sample_points(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0],
+                                                    c.lines[1], c.n_z, mode=R.SAMPLE_GRID, device=self.dev)[0]
+                    _, self.p_star = R.mf_forward(self.ap, self.grid_xyz, self.target)
+                xq, p_star = self.grid_xyz, self.p_star
+                z, p = R.mf_forward(self.ap, xq, sig)
+            else:
+                xq = xyz
+                z, p, _, p_star = R.mf_forward(self.ap, xq, sig, self.target)
             mark("mf_fwd")
             loss, g_p = R.loss_l2(p, p_star)
-            g_sig = R.mf_backward(self.ap, xyz, z, p, g_p)
+            g_sig = R.mf_backward(self.ap, xq, z, p, g_p)
             mark("mf_bwd")
             gr = R.render_backward(self.ap, sm, fl, g_sig, flags=c.render_flags)
             mark("render_bwd")
