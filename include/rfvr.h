@@ -119,6 +119,11 @@ typedef struct rfvr_fields {
     float        amp_tx;   /* learnt global amplitude A'_tx, finite                  */
     const float* amp_ptr;  /* device [1] or NULL; when set, A'_tx is read from device
                               memory at kernel time (no host round trip per step)   */
+    const float* log_s_ptr;/* device [1] or NULL; when set, s = exp(log_s_ptr[0]) is read
+                              at kernel time (the field s is then unused but must still
+                              be finite and > 0) and rfvr_render_backward's g_s output
+                              is dL/d(log s) = s dL/ds: a log-parameterised learnable s
+                              updated on the device (rfvr_adamw) with no host round trip */
 } rfvr_fields;
 
 /* ------------------------------------------------------------------------
@@ -490,6 +495,9 @@ int rfvr_mask_update(int64_t n, const float* power, const float* power_ref, floa
 /* Occupancy at the detached ray / antenna origins (Eq. lens-less-transmittance):
  *   phi[k] = 1 / (1 + exp(-s * sdf[k])),  k < n.  s finite and > 0. */
 int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* stream);
+/* The same with s = exp(log_s[0]) read from device memory at kernel time
+ * (log_s: device [1], as rfvr_fields.log_s_ptr). */
+int rfvr_occupancy_logs(int64_t n, const float* log_s, const float* sdf, float* phi, void* stream);
 
 /* Library information. */
 const char* rfvr_last_error(void);

@@ -274,7 +274,7 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
                          "ant records")))
         return rc;
     if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, sm->point_weight, fl->sdf, fl->grad, fl->refl,
-                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, fl->amp_ptr, rec,
+                                            fl->phi_ray, use_phi, fl->s, fl->log_s_ptr, fl->amp_tx, fl->amp_ptr, rec,
                                             alpha_out, trans_out, st),
                          "render prep")))
         return rc;
@@ -338,7 +338,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                          "ant records")))
         return rc;
     if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, nullptr, fl->sdf, fl->grad, fl->refl,
-                                            fl->phi_ray, use_phi, fl->s, fl->amp_tx, fl->amp_ptr, rec,
+                                            fl->phi_ray, use_phi, fl->s, fl->log_s_ptr, fl->amp_tx, fl->amp_ptr, rec,
                                             alpha, trans, st),
                          "render prep")))
         return rc;
@@ -363,7 +363,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                          "render adjoint term kernel")))
         return rc;
     if ((rc = hip_status(launch_scan_adjoint(g, sm->ray_weight, fl->sdf, fl->grad, fl->refl, fl->s,
-                                             fl->amp_tx, fl->amp_ptr, alpha, trans, gb, gT, gn, galpha,
+                                             fl->log_s_ptr, fl->amp_tx, fl->amp_ptr, alpha, trans, gb, gT, gn, galpha,
                                              pamp, ps,
                                              g_sdf, g_grad, g_refl, acc, st),
                          "scan adjoint")))
@@ -687,7 +687,14 @@ int rfvr_occupancy(int64_t n, float s, const float* sdf, float* phi, void* strea
     if (!sdf || !phi) { set_error("sdf and phi are required"); return RFVR_E_INVALID; }
     if (!count_ok(n)) { set_error("n must be in [1, RFVR_MAX_POINTS]"); return RFVR_E_INVALID; }
     if (!std::isfinite(s) || s <= 0.0f) { set_error("s must be finite and > 0"); return RFVR_E_INVALID; }
-    return hip_status(launch_occupancy((long)n, s, sdf, phi, reinterpret_cast<hipStream_t>(stream)),
+    return hip_status(launch_occupancy((long)n, s, nullptr, sdf, phi, reinterpret_cast<hipStream_t>(stream)),
+                      "occupancy");
+}
+
+int rfvr_occupancy_logs(int64_t n, const float* log_s, const float* sdf, float* phi, void* stream) {
+    if (!sdf || !phi || !log_s) { set_error("log_s, sdf and phi are required"); return RFVR_E_INVALID; }
+    if (!count_ok(n)) { set_error("n must be in [1, RFVR_MAX_POINTS]"); return RFVR_E_INVALID; }
+    return hip_status(launch_occupancy((long)n, 1.0f, log_s, sdf, phi, reinterpret_cast<hipStream_t>(stream)),
                       "occupancy");
 }
 

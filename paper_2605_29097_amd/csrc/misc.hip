@@ -486,13 +486,15 @@ hipError_t launch_mask_update(long n, const float* p, const float* p_ref, float*
 // ---------------------------------------------------------------------------
 // occupancy Phi = sigmoid(s f)
 // ---------------------------------------------------------------------------
-__global__ void k_occupancy(long n, float s, const float* __restrict__ f, float* __restrict__ phi) {
+__global__ void k_occupancy(long n, float s_h, const float* __restrict__ log_s, const float* __restrict__ f,
+                            float* __restrict__ phi) {
+    const float s = log_s ? expf(log_s[0]) : s_h;
     long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) phi[k] = sigmoidf_(s * f[k]);
 }
 
-hipError_t launch_occupancy(long n, float s, const float* f, float* phi, hipStream_t st) {
-    hipLaunchKernelGGL(k_occupancy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, f, phi);
+hipError_t launch_occupancy(long n, float s, const float* log_s, const float* f, float* phi, hipStream_t st) {
+    hipLaunchKernelGGL(k_occupancy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, log_s, f, phi);
     return hipGetLastError();
 }
 

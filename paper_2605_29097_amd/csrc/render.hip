@@ -67,7 +67,7 @@ hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, 
 __global__ __launch_bounds__(256) void k_render_prep(
     int n_ray, int n_z, const float* __restrict__ xyz, const float* __restrict__ ray_w,
     const float* __restrict__ pt_w, const float* __restrict__ sdf, const float* __restrict__ grad, const float* __restrict__ refl,
-    const float* __restrict__ phi_ray, int use_phi, float s, float amp_h,
+    const float* __restrict__ phi_ray, int use_phi, float s_h, const float* __restrict__ log_s, float amp_h,
     const float* __restrict__ amp_ptr, int seg, PtRec* __restrict__ rec, float* __restrict__ alpha_out,
     float* __restrict__ trans_out) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void k_render_prep(
     if (wave >= n_ray) return;                       // uniform per wave
     const int r = wave;
     const float amp = amp_ptr ? amp_ptr[0] : amp_h;
+    const float s = log_s ? expf(log_s[0]) : s_h;
     const float w = ray_w ? ray_w[r] : 1.0f;
     const float pr = use_phi ? phi_ray[r] : 0.0f;
     const size_t base = (size_t)r * n_z;
@@ -130,13 +131,13 @@ __global__ __launch_bounds__(256) void k_render_prep(
 
 hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w,
                               const float* pt_w, const float* sdf, const float* grad, const float* refl,
-                              const float* phi_ray, int use_phi, float s, float amp,
+                              const float* phi_ray, int use_phi, float s, const float* log_s, float amp,
                               const float* amp_ptr, PtRec* rec, float* alpha_out, float* trans_out,
                               hipStream_t st) {
     const int waves_per_block = 4;
     dim3 grid((g.n_ray + waves_per_block - 1) / waves_per_block);
     hipLaunchKernelGGL(k_render_prep, grid, dim3(256), 0, st, g.n_ray, g.n_z, xyz, ray_w, pt_w, sdf,
-                       grad, refl, phi_ray, use_phi, s, amp, amp_ptr, g.seg, rec, alpha_out, trans_out);
+                       grad, refl, phi_ray, use_phi, s, log_s, amp, amp_ptr, g.seg, rec, alpha_out, trans_out);
     return hipGetLastError();
 }
 
@@ -531,8 +532,8 @@ hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, cons
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scan_adjoint(
     int n_ray, int n_z, const float* __restrict__ ray_w, const float* __restrict__ sdf,
-    const float* __restrict__ grad, const float* __restrict__ refl, float s, float amp_h,
-    const float* __restrict__ amp_ptr, const float* __restrict__ alpha,
+    const float* __restrict__ grad, const float* __restrict__ refl, float s_h, const float* __restrict__ log_s,
+    float amp_h, const float* __restrict__ amp_ptr, const float* __restrict__ alpha,
     const float* __restrict__ trans,
     const float* __restrict__ g_b, const float* __restrict__ g_T, const float* __restrict__ g_n,
     float* g_alpha_tmp, float* __restrict__ part_amp, float* __restrict__ part_s,
@@ -543,6 +544,7 @@ __global__ __launch_bounds__(256) void k_scan_adjoint(
     if (wave >= n_ray) return;
     const int r = wave;
     const float amp = amp_ptr ? amp_ptr[0] : amp_h;
+    const float s = log_s ? expf(log_s[0]) : s_h;
     const size_t base = (size_t)r * n_z;
     const float w = ray_w ? ray_w[r] : 1.0f;
     const int nch = (n_z + 63) / 64;
@@ -645,19 +647,19 @@ __global__ __launch_bounds__(256) void k_scan_adjoint(
     }
     if (lane == 0) {
         part_amp[r] = pamp;
-        part_s[r] = ps;
+        part_s[r] = log_s ? ps * s : ps;            // dL/d(log s) = s dL/ds
     }
 }
 
 hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const float* sdf,
-                               const float* grad, const float* refl, float s, float amp,
+                               const float* grad, const float* refl, float s, const float* log_s, float amp,
                                const float* amp_ptr, const float* alpha, const float* trans,
                                const float* g_b, const float* g_T, const float* g_n,
                                float* g_alpha_tmp, float* part_amp, float* part_s, float* g_sdf,
                                float* g_grad, float* g_refl, int accumulate, hipStream_t st) {
     dim3 grid((g.n_ray + 3) / 4);
     hipLaunchKernelGGL(k_scan_adjoint, grid, dim3(256), 0, st, g.n_ray, g.n_z, ray_w, sdf, grad,
-                       refl, s, amp, amp_ptr, alpha, trans, g_b, g_T, g_n, g_alpha_tmp, part_amp, part_s,
+                       refl, s, log_s, amp, amp_ptr, alpha, trans, g_b, g_T, g_n, g_alpha_tmp, part_amp, part_s,
                        g_sdf, g_grad, g_refl, accumulate, g.seg);
     return hipGetLastError();
 }

@@ -290,7 +290,7 @@ hipError_t launch_ant_records(const float* tx, const float* phi_tx, int n_meas, 
                               hipStream_t st);
 hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float* ray_w, const float* pt_w,
                               const float* sdf, const float* grad, const float* refl,
-                              const float* phi_ray, int use_phi, float s, float amp,
+                              const float* phi_ray, int use_phi, float s, const float* log_s, float amp,
                               const float* amp_ptr, PtRec* rec, float* alpha_out, float* trans_out,
                               hipStream_t st);
 // sel: NULL, or the plan of the Chebyshev path (these kernels then return at
@@ -309,7 +309,7 @@ hipError_t launch_render_bwd_points(const RenderGeom& g, const AntRec* ant, cons
                                     const float2* gsig_pad, int np, uint32_t flags, float* g_b,
                                     float* g_T, float* g_n, const ChebPlan* sel, hipStream_t st);
 hipError_t launch_scan_adjoint(const RenderGeom& g, const float* ray_w, const float* sdf,
-                               const float* grad, const float* refl, float s, float amp,
+                               const float* grad, const float* refl, float s, const float* log_s, float amp,
                                const float* amp_ptr, const float* alpha, const float* trans,
                                const float* g_b, const float* g_T, const float* g_n,
                                float* g_alpha_tmp, float* part_amp, float* part_s, float* g_sdf,
@@ -331,7 +331,7 @@ hipError_t launch_loss_partial(long n, const float* p, const float* ps, const fl
 hipError_t launch_loss_final(const double* part, int n_blocks, long n, float* loss, hipStream_t st);
 hipError_t launch_sample_points(const rfvr_sample_desc& d, const double basis[9], float* xyz,
                                 float* u, float* origin, hipStream_t st);
-hipError_t launch_occupancy(long n, float s, const float* f, float* phi, hipStream_t st);
+hipError_t launch_occupancy(long n, float s, const float* log_s, const float* f, float* phi, hipStream_t st);
 hipError_t launch_mask_update(long n, const float* p, const float* p_ref, float* hist, float tau_hi,
                               float tau_lo, float* mask, float* part, int nb, hipStream_t st);
 hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basis[9], const float* logits,

@@ -46,7 +46,7 @@ class CSamples(ctypes.Structure):
 
 class CFields(ctypes.Structure):
     _fields_ = [("sdf", _vp), ("grad", _vp), ("refl", _vp), ("phi_ray", _vp), ("phi_tx", _vp),
-                ("phi_rx", _vp), ("s", _c_f), ("amp_tx", _c_f), ("amp_ptr", _vp)]
+                ("phi_rx", _vp), ("s", _c_f), ("amp_tx", _c_f), ("amp_ptr", _vp), ("log_s_ptr", _vp)]
 
 
 class CSampleDesc(ctypes.Structure):
@@ -105,6 +105,7 @@ _SIGS = {
     "rfvr_mlp_backward_train": ([_P(CMlp), _vp, _c_i64, _vp, _vp, _vp, _c_u32, _vp, _vp, _sz, _vp, _sz,
                                  _vp], _c_i32),
     "rfvr_occupancy": ([_c_i64, _c_f, _vp, _vp, _vp], _c_i32),
+    "rfvr_occupancy_logs": ([_c_i64, _vp, _vp, _vp, _vp], _c_i32),
     "rfvr_proposal_param_count": ([_P(CProposal)], _c_i64),
     "rfvr_proposal_ws_bytes": ([_P(CProposal), _c_i64], _sz),
     "rfvr_proposal_forward": ([_P(CProposal), _vp, _c_i64, _vp, _vp, _sz, _vp], _c_i32),
@@ -237,10 +238,13 @@ class Fields:
     phi_ray: Optional[torch.Tensor] = None
     phi_tx: Optional[torch.Tensor] = None
     amp_dev: Optional[torch.Tensor] = None     # device [1]: overrides amp at kernel time
+    log_s_dev: Optional[torch.Tensor] = None   # device [1]: s = exp(log_s) at kernel time; g_s is then
+                                               # the gradient in log s
 
     def c(self) -> CFields:
         return CFields(_ptr(self.sdf), _ptr(self.grad), _ptr(self.refl), _ptr(self.phi_ray),
-                       _ptr(self.phi_tx), None, float(self.s), float(self.amp), _ptr(self.amp_dev))
+                       _ptr(self.phi_tx), None, float(self.s), float(self.amp), _ptr(self.amp_dev),
+                       _ptr(self.log_s_dev))
 
 
 # ----------------------------------------------------------------------------
@@ -612,11 +616,16 @@ def term_order(ap: Aperture, xyz: torch.Tensor, stream=None) -> int:
     return int(out.item())
 
 
-def occupancy(s: float, sdf: torch.Tensor, stream=None):
-    """Phi = sigmoid(s * sdf) (detached origin occupancies)."""
+def occupancy(s, sdf: torch.Tensor, stream=None):
+    """Phi = sigmoid(s * sdf) (detached origin occupancies); s a float, or a
+    device tensor [1] holding log s (rfvr_occupancy_logs)."""
     phi = torch.empty_like(sdf)
-    _check(lib().rfvr_occupancy(sdf.numel(), float(s), _ptr(sdf.contiguous()), _ptr(phi), _stream(stream)),
-           "rfvr_occupancy")
+    if isinstance(s, torch.Tensor):
+        _check(lib().rfvr_occupancy_logs(sdf.numel(), _ptr(s), _ptr(sdf.contiguous()), _ptr(phi), _stream(stream)),
+               "rfvr_occupancy_logs")
+    else:
+        _check(lib().rfvr_occupancy(sdf.numel(), float(s), _ptr(sdf.contiguous()), _ptr(phi), _stream(stream)),
+               "rfvr_occupancy")
     return phi
 
 

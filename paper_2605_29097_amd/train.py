@@ -137,8 +137,14 @@ class Trainer:
         if self.perm is not None:
             target = target[torch.from_numpy(self.perm).to(self.dev)]
         self.target = target.contiguous()
-        self.s = float(cfg.s)
-        self._s_m = self._s_v = 0.0
+        self.s0 = float(cfg.s)
+        # a learnable s lives on the device as log s: the kernels read it there
+        # and AdamW updates it there, so a step never waits for the host
+        self.log_s = None
+        if cfg.learn_s:
+            self.log_s = torch.tensor([math.log(cfg.s)], device=self.dev)
+            self.log_s_m = torch.zeros(1, device=self.dev)
+            self.log_s_v = torch.zeros(1, device=self.dev)
         self.history = None                    # per-point filter-output history (masking)
         self.t = 0
         self.p_star = None
@@ -176,11 +182,12 @@ class Trainer:
         # detached occupancies at the primary-ray origins and the antennas
         org = torch.cat([origin, self.tx], 0)
         f_org, _, _ = R.mlp_forward(self.net, org)
-        phi = R.occupancy(self.s, f_org)
+        phi = R.occupancy(self.s_arg, f_org)
         mark("mlp_fwd")
         sm = R.Samples(xyz=xyz)
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
-                      refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
+                      refl=a.view(xyz.shape[:2]), s=self.s0, amp=1.0, amp_dev=self.amp,
+                      log_s_dev=self.log_s,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
         ap_r, fl_r = self.ap, fl
         if c.bank_patch is None:
@@ -194,7 +201,8 @@ class Trainer:
             i0, i1 = k * self.patch_len, (k + 1) * self.patch_len
             ap_r = R.Aperture(tx=self.tx[i0:i1], f0=self.f0, df=self.df, n_freq=c.n_freq)
             n_ray = origin.shape[0]
-            fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=self.s, amp=1.0, amp_dev=self.amp,
+            fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=self.s0, amp=1.0, amp_dev=self.amp,
+                            log_s_dev=self.log_s,
                             phi_ray=fl.phi_ray, phi_tx=phi[n_ray + i0:n_ray + i1].contiguous())
             R.render_forward(ap_r, sm, fl_r, flags=c.render_flags, out=self.bank[i0:i1])
             sig = self.bank
@@ -245,17 +253,20 @@ class Trainer:
             self._res, self._res_n = R.mlp_reserve(self.net, n, self.dev), n
         return self._res
 
-    def update_s(self, g_s: torch.Tensor):
-        """Adam step on log s (host scalar: the kernels take s by value; this
-        reads one float back, so it synchronises the stream once per step)."""
-        c = self.cfg
-        g = float(g_s.item()) * self.s                       # d/dlog s
-        b1, b2, eps = 0.9, 0.999, 1e-8
-        self._s_m = b1 * self._s_m + (1 - b1) * g
-        self._s_v = b2 * self._s_v + (1 - b2) * g * g
-        mh = self._s_m / (1 - b1 ** self.t)
-        vh = self._s_v / (1 - b2 ** self.t)
-        self.s = float(math.exp(math.log(self.s) - self.lr(c.lr_other) * mh / (math.sqrt(vh) + eps)))
+    def update_s(self, g_log_s: torch.Tensor):
+        """AdamW step on log s, on the device (the render adjoint returns the
+        gradient in log s when the fields carry log_s_dev)."""
+        R.adamw(self.log_s, g_log_s, self.log_s_m, self.log_s_v, self.t, self.lr(self.cfg.lr_other))
+
+    @property
+    def s_arg(self):
+        """s as the occupancy call takes it: log s on the device, or the fixed value."""
+        return self.log_s if self.log_s is not None else self.s0
+
+    @property
+    def s(self) -> float:
+        """Current s (reads the device value back when s is learnt)."""
+        return float(torch.exp(self.log_s).item()) if self.log_s is not None else self.s0
 
     # ------------------------------------------------------- reference evaluation
     def reference_signal(self):
@@ -267,9 +278,10 @@ class Trainer:
                                          c.lines[1], c.judge_nz or c.n_z, mode=R.SAMPLE_GRID, device=self.dev)
         f, grad, a = R.mlp_forward(self.net, xyz)
         f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
-        phi = R.occupancy(self.s, f_org)
+        phi = R.occupancy(self.s_arg, f_org)
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
-                      refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
+                      refl=a.view(xyz.shape[:2]), s=self.s0, amp=1.0, amp_dev=self.amp,
+                      log_s_dev=self.log_s,
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
         self._ref_xyz = xyz
         return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.render_flags)
@@ -329,10 +341,11 @@ class MultiPlaneTrainer(Trainer):
             res = self.reserve(xyz.shape[0] * xyz.shape[1])
             f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
             f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, pl["tx"]], 0))
-            phi = R.occupancy(self.s, f_org)
+            phi = R.occupancy(self.s_arg, f_org)
             sm = R.Samples(xyz=xyz)
             fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
-                          refl=a.view(xyz.shape[:2]), s=self.s, amp=1.0, amp_dev=self.amp,
+                          refl=a.view(xyz.shape[:2]), s=self.s0, amp=1.0, amp_dev=self.amp,
+                      log_s_dev=self.log_s,
                           phi_ray=phi[:n_ray].contiguous(), phi_tx=phi[n_ray:].contiguous())
             sig = R.render_forward(pl["ap"], sm, fl, flags=c.render_flags)
             if pl["p_star"] is None or c.sampling != R.SAMPLE_GRID:
@@ -448,11 +461,11 @@ class ProposalTrainer(Trainer):
         res = self.reserve(n_ray * K) if self.train_sdf else None
         f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
         f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
-        phi = R.occupancy(self.s, f_org)
+        phi = R.occupancy(self.s_arg, f_org)
         mark("mlp_fwd")
         sm = R.Samples(xyz=xyz)
-        fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=self.s,
-                      amp=1.0, amp_dev=self.amp, phi_ray=phi[:n_ray].contiguous(),
+        fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=self.s0,
+                      amp=1.0, amp_dev=self.amp, log_s_dev=self.log_s, phi_ray=phi[:n_ray].contiguous(),
                       phi_tx=phi[n_ray:].contiguous())
         sig, alpha, trans = R.render_forward(self.ap, sm, fl, flags=c.render_flags, want_alpha=True)
         mark("render_fwd")
