@@ -327,10 +327,10 @@ def proposal_study(args, dev):
                      render_flags=flags, judge_nz=args.study_judge_nz)
     spec = MLPSpec(centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
     if args.study_target:
-        name = args.study_target
+        target_name = args.study_target
     else:
-        name = "torus_target.npz" if cfg.s == 64.0 else f"torus_target_s{int(cfg.s)}.npz"
-    data = np.load(os.path.join(ROOT, "tests", "golden", name))      # rendered by the oracle
+        target_name = "torus_target.npz" if cfg.s == 64.0 else f"torus_target_s{int(cfg.s)}.npz"
+    data = np.load(os.path.join(ROOT, "tests", "golden", target_name))      # rendered by the oracle
     to_t = lambda a: torch.from_numpy(np.stack([a.real, a.imag], -1).astype(np.float32)).to(dev)
     noisy, clean = to_t(data["noisy"]), to_t(data["clean"])
     p0 = torch.from_numpy(mlp_init(spec, cfg.seed)).to(dev)
@@ -374,7 +374,8 @@ def proposal_study(args, dev):
         return out
 
     prior_cd = None
-    pc = dict(n_imp=args.study_imp, n_uni=args.study_uni, loss_on_grid=args.study_loss_grid)
+    pc = dict(n_imp=args.study_imp, n_uni=args.study_uni, loss_on_grid=args.study_loss_grid,
+              dilate=args.study_dilate)
     runs = {
         "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps, 0),
         "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(**pc), device=dev),
@@ -384,6 +385,7 @@ def proposal_study(args, dev):
     }
     every = args.study_eval_every
     out = {}
+    e_star_hm = None                         # the full-space run's final heatmap error (it runs first)
     for name, (make, n_steps, warm) in runs.items():
         tr = make(p0.clone())
         warm_ms = 0.0
@@ -401,6 +403,7 @@ def proposal_study(args, dev):
             tr.train_sdf = True
         j = tr.evaluate(clean)
         curve = [(0, j["signal"], j["heatmap"])]
+        at_e_star = None                     # (step, Chamfer) where the heatmap error first reaches E*
         step_ms = []
         for k in range(1, n_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -412,12 +415,16 @@ def proposal_study(args, dev):
             if k % every == 0 or k == n_steps:
                 j = tr.evaluate(clean)
                 curve.append((k, j["signal"], j["heatmap"]))
+                if e_star_hm is not None and at_e_star is None and j["heatmap"] <= e_star_hm:
+                    at_e_star = {"step": k, "chamfer": chamfer_of(tr.net)}
                 print(f"[study] {name} step {k} reference signal {j['signal']:.4f} heatmap {j['heatmap']:.4f} "
                       f"s {tr.s:.1f} ({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
         out[name] = {"ms_per_step": float(np.median(step_ms[2:] if len(step_ms) > 4 else step_ms)),
                      "steps": n_steps, "warmup_steps": warm, "warmup_ms": round(warm_ms, 1), "final_s": tr.s,
                      "reference": [[k, round(a, 5), round(b, 5)] for k, a, b in curve],
-                     "chamfer": chamfer_of(tr.net)}
+                     "chamfer": chamfer_of(tr.net), "at_e_star_heatmap": at_e_star}
+        if e_star_hm is None:
+            e_star_hm = round(curve[-1][2], 5)
         if prior_cd is None:
             prior_cd = chamfer_of(R.MLP(params=p0.clone(), centre=cfg.cube_centre, half_size=cfg.cube_side / 2))
         del tr
@@ -429,10 +436,10 @@ def proposal_study(args, dev):
             r[f"steps_to_e_star_{key}"] = hit
             r[f"ms_to_e_star_{key}"] = None if hit is None else round(hit * r["ms_per_step"] + r["warmup_ms"], 1)
     print(json.dumps({"study": "proposal_vs_full_space", "e_star": e_star, "eval_every": every,
-                      "learn_s": cfg.learn_s, "s0": cfg.s, "weight": args.study_weight, "target": name,
+                      "learn_s": cfg.learn_s, "s0": cfg.s, "weight": args.study_weight, "target": target_name,
                       "judge_nz": cfg.judge_nz or cfg.n_z, "prior_fit_steps": args.study_prior,
                       "prior_f_rms_m": prior_rms, "n_imp": args.study_imp, "n_uni": args.study_uni,
-                      "loss_on_grid": args.study_loss_grid,
+                      "loss_on_grid": args.study_loss_grid, "target_dilation_bins": args.study_dilate,
                       "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
                       "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
                                "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
@@ -651,6 +658,8 @@ def main():
                     help="grid side of the Chamfer surface extraction (0: no Chamfer)")
     ap.add_argument("--study-loss-grid", action="store_true",
                     help="sampled runs take the heatmap loss on the full-space grid (render from their samples)")
+    ap.add_argument("--study-dilate", type=int, default=0,
+                    help="proposal targets dilated in depth over this many bins")
     ap.add_argument("--study-imp", type=int, default=16)
     ap.add_argument("--study-uni", type=int, default=4)
     ap.add_argument("--study-prop-warmup", type=int, default=0,

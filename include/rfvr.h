@@ -453,10 +453,13 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
  * the segment overlaps in proportion to the overlap (the last sample, and a
  * segment of zero length, add w_k to the bin of u_k), giving W_b;
  * t_b = min(1, W_b / max(max_b W_b, 1e-3)).  Overlaps and sums in FP64.
- * targets: [n_ray][n_bins].  n_k <= RFVR_MAX_RAY_SAMPLES, n_bins <= 64. */
+ * n_dilate >= 1 dilates the targets in depth: bin b takes the largest t over
+ * bins b - n_dilate .. b (so samples continue past a front surface into the
+ * object behind it).  targets: [n_ray][n_bins].  n_k <= RFVR_MAX_RAY_SAMPLES,
+ * n_bins <= 64, 0 <= n_dilate < n_bins. */
 int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
-                          const float* trans, float lo, float hi, int32_t n_bins, float* targets,
-                          void* stream);
+                          const float* trans, float lo, float hi, int32_t n_bins, int32_t n_dilate,
+                          float* targets, void* stream);
 
 /* Mean binary cross-entropy of sigmoid(z) against t and its gradient
  * g = (sigmoid(z) - t) / n.  loss: [1] output. */

@@ -20,8 +20,11 @@ so it is spread over the bins that segment overlaps, in proportion to the
 overlap (reading: with sparse samples a long segment says only that the
 surface lies somewhere inside it; the last sample, or a segment of zero length,
 goes to the bin of u_k).  The per-bin sums W_b are normalised per ray,
-t_b = min(1, W_b / max(max_b W_b, 1e-3)), and the mean binary cross-entropy
-between sigmoid(z_b) and t_b is the loss.
+t_b = min(1, W_b / max(max_b W_b, 1e-3)), optionally dilated in depth (each
+bin takes the largest t of itself and the `dilate` bins in front of it, so that
+samples continue into an object behind its front surface; reading, see the
+design notes), and the mean binary cross-entropy between sigmoid(z_b) and t_b
+is the loss.
 
 Network: gamma_4(x_hat) (27 values) -> Linear(64) -> relu -> Linear(64) -> relu
 -> Linear(1); flat layout W0 [64][27], b0 [64], W1 [64][64], b1 [64],
@@ -139,9 +142,15 @@ def bin_weights(u, w, lo, hi, n_bins):
     return W
 
 
-def targets(W):
+def targets(W, dilate=0):
+    """t_b = min(1, W_b / max(max_b W_b, floor)), then the largest of t over
+    the bin and the `dilate` bins in front of it (depth dilation)."""
     W = np.asarray(W, np.float64)
-    return np.minimum(1.0, W / np.maximum(W.max(1, keepdims=True), TARGET_FLOOR))
+    t = np.minimum(1.0, W / np.maximum(W.max(1, keepdims=True), TARGET_FLOOR))
+    out = t.copy()
+    for d in range(1, dilate + 1):
+        out[:, d:] = np.maximum(out[:, d:], t[:, :-d])
+    return out
 
 
 def bce(logits, t):

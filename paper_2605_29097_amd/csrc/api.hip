@@ -630,16 +630,16 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
 }
 
 int rfvr_proposal_targets(int32_t n_ray, int32_t n_k, const float* u, const float* alpha,
-                          const float* trans, float lo, float hi, int32_t n_bins, float* targets,
-                          void* stream) {
+                          const float* trans, float lo, float hi, int32_t n_bins, int32_t n_dilate,
+                          float* targets, void* stream) {
     if (n_ray < 1 || n_ray > RFVR_MAX_RAYS || n_k < 1 || n_k > RFVR_MAX_RAY_SAMPLES || n_bins < 1 || n_bins > 64 ||
-        !u || !alpha || !trans || !targets) {
-        set_error("need 1 <= n_ray <= RFVR_MAX_RAYS, 1 <= n_k <= RFVR_MAX_RAY_SAMPLES (1024), 1 <= n_bins <= 64 "
-                  "and all arrays");
+        n_dilate < 0 || n_dilate >= n_bins || !u || !alpha || !trans || !targets) {
+        set_error("need 1 <= n_ray <= RFVR_MAX_RAYS, 1 <= n_k <= RFVR_MAX_RAY_SAMPLES (1024), 1 <= n_bins <= 64, "
+                  "0 <= n_dilate < n_bins and all arrays");
         return RFVR_E_INVALID;
     }
     if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi)) { set_error("need finite lo < hi"); return RFVR_E_INVALID; }
-    return hip_status(launch_proposal_targets(n_ray, n_k, u, alpha, trans, lo, hi, n_bins, targets,
+    return hip_status(launch_proposal_targets(n_ray, n_k, u, alpha, trans, lo, hi, n_bins, n_dilate, targets,
                                               reinterpret_cast<hipStream_t>(stream)),
                       "proposal targets");
 }

@@ -363,7 +363,7 @@ hipError_t launch_sample_naive(const rfvr_sample_desc& d, const double basis[9],
 __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, const float* __restrict__ u,
                                                           const float* __restrict__ alpha,
                                                           const float* __restrict__ trans, float lo, float hi,
-                                                          int n_bins, float* __restrict__ targets) {
+                                                          int n_bins, int n_dilate, float* __restrict__ targets) {
     const long r = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (r >= n_ray) return;
@@ -391,14 +391,21 @@ __global__ __launch_bounds__(256) void k_proposal_targets(int n_ray, int n_k, co
     float mx = lane < n_bins ? Wf : 0.0f;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, 64));
-    if (lane < n_bins) targets[r * n_bins + lane] = fminf(1.0f, Wf / fmaxf(mx, 1e-3f));
+    const float t = fminf(1.0f, Wf / fmaxf(mx, 1e-3f));
+    // depth dilation: the largest t of the bin and the n_dilate bins in front
+    float td = t;
+    for (int d = 1; d <= n_dilate; ++d) {                     // uniform trip count
+        const float v = __shfl_up(t, d, 64);
+        if (lane >= d) td = fmaxf(td, v);
+    }
+    if (lane < n_bins) targets[r * n_bins + lane] = td;
 }
 
 hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
-                                   float lo, float hi, int n_bins, float* targets, hipStream_t st) {
+                                   float lo, float hi, int n_bins, int n_dilate, float* targets, hipStream_t st) {
     const dim3 grid((unsigned)((n_ray + 3) / 4));
     hipLaunchKernelGGL(k_proposal_targets, grid, dim3(256), 0, st, n_ray, n_k, u, alpha, trans, lo, hi, n_bins,
-                       targets);
+                       n_dilate, targets);
     return hipGetLastError();
 }
 

@@ -340,7 +340,7 @@ hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basi
 hipError_t launch_sample_naive(const rfvr_sample_desc& d, const double basis[9], const float* tx, int n_ant,
                                float* xyz, float* jac, hipStream_t st);
 hipError_t launch_proposal_targets(int n_ray, int n_k, const float* u, const float* alpha, const float* trans,
-                                   float lo, float hi, int n_bins, float* targets, hipStream_t st);
+                                   float lo, float hi, int n_bins, int n_dilate, float* targets, hipStream_t st);
 hipError_t launch_bce(long n, const float* z, const float* t, float* loss, float* g, double* part, int nb,
                       hipStream_t st);
 hipError_t launch_adamw(long n, float* p, const float* g, float* m, float* v, float lr, float b1,

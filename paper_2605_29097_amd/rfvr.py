@@ -113,7 +113,7 @@ _SIGS = {
     "rfvr_sample_naive": ([_P(CSampleDesc), _vp, _c_i32, _vp, _vp, _vp], _c_i32),
     "rfvr_sample_importance": ([_P(CSampleDesc), _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp, _vp],
                                _c_i32),
-    "rfvr_proposal_targets": ([_c_i32, _c_i32, _vp, _vp, _vp, _c_f, _c_f, _c_i32, _vp, _vp], _c_i32),
+    "rfvr_proposal_targets": ([_c_i32, _c_i32, _vp, _vp, _vp, _c_f, _c_f, _c_i32, _c_i32, _vp, _vp], _c_i32),
     "rfvr_bce_ws_bytes": ([_c_i64], _sz),
     "rfvr_mask_ws_bytes": ([_c_i64], _sz),
     "rfvr_mask_update": ([_c_i64, _vp, _vp, _vp, _c_f, _c_f, _vp, _vp, _sz, _vp], _c_i32),
@@ -711,13 +711,14 @@ def proposal_backward(net: Proposal, xyz: torch.Tensor, g_logits: torch.Tensor, 
 
 
 def proposal_targets(u: torch.Tensor, alpha: torch.Tensor, trans: torch.Tensor, lo: float, hi: float,
-                     n_bins: int, stream=None):
-    """Binned, max-normalised blend weights [n_ray, n_bins] of the render at depths u [n_ray, n_k]."""
+                     n_bins: int, dilate: int = 0, stream=None):
+    """Binned, max-normalised blend weights [n_ray, n_bins] of the render at depths u [n_ray, n_k],
+    dilated in depth over `dilate` bins."""
     n_ray, n_k = u.shape
     t = torch.empty(n_ray, n_bins, dtype=torch.float32, device=u.device)
     _check(lib().rfvr_proposal_targets(n_ray, n_k, _ptr(u.contiguous()), _ptr(alpha.contiguous()),
-                                       _ptr(trans.contiguous()), float(lo), float(hi), int(n_bins), _ptr(t),
-                                       _stream(stream)), "rfvr_proposal_targets")
+                                       _ptr(trans.contiguous()), float(lo), float(hi), int(n_bins), int(dilate),
+                                       _ptr(t), _stream(stream)), "rfvr_proposal_targets")
     return t
 
 

@@ -394,6 +394,7 @@ class ProposalConfig:
     seed: int = 0
     loss_on_grid: bool = False  # heatmap loss on the full-space grid (its target cached) instead of
                                 # at the drawn samples; the signal is still rendered from the samples
+    dilate: int = 0             # targets dilated in depth over this many bins (rfvr_proposal_targets)
 
 
 class ProposalTrainer(Trainer):
@@ -502,7 +503,8 @@ class ProposalTrainer(Trainer):
             if c.learn_s:
                 self.update_s(gr["s"])
         if self.prop is not None:
-            t = R.proposal_targets(u, alpha.view(n_ray, K), trans.view(n_ray, K), self.lo, self.hi, pc.n_bins)
+            t = R.proposal_targets(u, alpha.view(n_ray, K), trans.view(n_ray, K), self.lo, self.hi, pc.n_bins,
+                                   pc.dilate)
             ploss, g_z = R.bce(logits, t)
             R.proposal_backward(self.prop, self.bin_xyz, g_z, out=self.pg)
             R.adamw(self.prop.params, self.pg, self.pm, self.pv, self.t, pc.lr)

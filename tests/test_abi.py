@@ -157,7 +157,9 @@ def test_size_limits_are_checked_before_launch(R):
     assert L.rfvr_sample_points(ctypes.byref(d), v, None, None, None) == -1
     d.n_ray_x = 1 << 12                                                # 2^25 rays x 64 depths
     assert L.rfvr_sample_points(ctypes.byref(d), v, None, None, None) == -1
-    assert L.rfvr_proposal_targets(R.MAX_RAYS + 1, 8, v, v, v, 0.2, 0.4, 8, v, None) == -1
+    assert L.rfvr_proposal_targets(R.MAX_RAYS + 1, 8, v, v, v, 0.2, 0.4, 8, 0, v, None) == -1
+    assert L.rfvr_proposal_targets(4, 8, v, v, v, 0.2, 0.4, 8, 8, v, None) == -1          # dilation >= n_bins
+    assert L.rfvr_proposal_targets(4, 8, v, v, v, 0.2, 0.4, 8, -1, v, None) == -1
     prop = R.CProposal(4, 64, 2, (ctypes.c_float * 3)(0, 0, 0.3), 0.1, v)
     assert L.rfvr_proposal_ws_bytes(ctypes.byref(prop), 1 << 30) > 0
     assert L.rfvr_proposal_ws_bytes(ctypes.byref(prop), (1 << 30) + 1) == 0

@@ -137,10 +137,12 @@ def test_sample_importance_full_size(dev):
     assert err <= 4e-8
 
 
-@pytest.mark.parametrize("n_ray,n_k,n_bins", [(5, 64, 64), (300, 20, 64), (33, 7, 13), (40, 256, 64),
-                                               (6, 1000, 37), (3, 1024, 64), (4, 129, 1)])
-def test_proposal_targets(dev, n_ray, n_k, n_bins):
-    _say(f"proposal_targets n_ray={n_ray} n_k={n_k} n_bins={n_bins}")
+@pytest.mark.parametrize("n_ray,n_k,n_bins,dilate", [(5, 64, 64, 0), (300, 20, 64, 0), (33, 7, 13, 0),
+                                                      (40, 256, 64, 0), (6, 1000, 37, 0), (3, 1024, 64, 0),
+                                                      (4, 129, 1, 0), (300, 20, 64, 2), (33, 7, 13, 12),
+                                                      (40, 256, 64, 63)])
+def test_proposal_targets(dev, n_ray, n_k, n_bins, dilate):
+    _say(f"proposal_targets n_ray={n_ray} n_k={n_k} n_bins={n_bins} dilate={dilate}")
     R = _R()
     rng = np.random.default_rng(n_ray)
     lo, hi = np.float32(0.18), np.float32(0.38)
@@ -154,10 +156,10 @@ def test_proposal_targets(dev, n_ray, n_k, n_bins):
     alpha = rng.uniform(0, 1.0 if n_k <= 64 else 4.0 / n_k, (n_ray, n_k)).astype(np.float32)
     trans = np.cumprod(1 - alpha, 1).astype(np.float32)
     alpha[min(2, n_ray - 1)] = 1e-6                # floor case
-    t = R.proposal_targets(_t(u, dev), _t(alpha, dev), _t(trans, dev), float(lo), float(hi), n_bins)
+    t = R.proposal_targets(_t(u, dev), _t(alpha, dev), _t(trans, dev), float(lo), float(hi), n_bins, dilate)
     w = trans.astype(np.float32) * alpha.astype(np.float32)          # same float32 product
     W = op.bin_weights(u.astype(np.float64), w.astype(np.float64), float(lo), float(hi), n_bins)
-    t_ref = op.targets(W)
+    t_ref = op.targets(W, dilate)
     err = np.abs(t.cpu().numpy() - t_ref).max()
     print(f"max |dt| {err:.2e}")
     assert err <= 1e-5
@@ -188,6 +190,9 @@ def test_proposal_entry_points_reject_bad_arguments(dev):
     u = torch.zeros(2, 1025, device=dev)
     with pytest.raises(R.RfvrError):
         R.proposal_targets(u, u, u, 0.2, 0.4, 64)                             # 1025 samples
+    u = torch.zeros(2, 16, device=dev)
+    with pytest.raises(R.RfvrError):
+        R.proposal_targets(u, u, u, 0.2, 0.4, 64, dilate=64)                  # dilation past the bins
     bad = _net(R, ProposalSpec(layers=5), np.zeros(10, np.float32), dev)
     assert bad.param_count() == -1
     with pytest.raises(R.RfvrError):

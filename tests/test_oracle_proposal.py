@@ -167,6 +167,23 @@ def test_bin_weights_and_targets_brute_force():
     assert np.all((t >= 0) & (t <= 1))
 
 
+def test_target_depth_dilation():
+    """Dilation over d bins: a hand case (a peak spreads to the d bins behind
+    it, never in front, and not past the range's end), d = 0 leaves t alone,
+    and the result is the running maximum over each window of d + 1 bins
+    (brute force over windows)."""
+    W = np.array([[0.0, 1.0, 0.0, 0.0, 0.5, 0.0, 0.0, 0.25]])
+    np.testing.assert_array_equal(op.targets(W, 0), W)
+    np.testing.assert_array_equal(op.targets(W, 2), [[0.0, 1.0, 1.0, 1.0, 0.5, 0.5, 0.5, 0.25]])
+    np.testing.assert_array_equal(op.targets(W, 7), [[0.0] + [1.0] * 7])
+    rng = np.random.default_rng(3)
+    W = rng.uniform(0, 1, (5, 13)) ** 4
+    t0 = op.targets(W)
+    for d in (1, 3, 12):
+        brute = np.array([[t0[r, max(0, b - d): b + 1].max() for b in range(13)] for r in range(5)])
+        np.testing.assert_array_equal(op.targets(W, d), brute)
+
+
 def test_bce_matches_library_and_gradient():
     rng = np.random.default_rng(6)
     z = rng.normal(0, 4, 300)
