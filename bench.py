@@ -11,8 +11,9 @@ The metric counts render terms: one (point, measurement, frequency) triple
 per pass, four passes per step (signal tracing forward and adjoint, matched
 filter forward and adjoint), 2^20 x 1024 x 128 terms each.
 
-Prints one JSON line (rank 0).  Only --gpus 1 is supported: this build runs on
-one GPU; the multi-GPU sharding is described in the design notes.
+Prints one JSON line (rank 0).  Only --gpus 1 is supported: the path runs on
+one GPU (sharding the points across GPUs would all-reduce the signal, its
+gradient and the network gradient each step; that is not built).
 """
 from __future__ import annotations
 

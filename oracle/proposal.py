@@ -22,9 +22,9 @@ surface lies somewhere inside it; the last sample, or a segment of zero length,
 goes to the bin of u_k).  The per-bin sums W_b are normalised per ray,
 t_b = min(1, W_b / max(max_b W_b, 1e-3)), optionally dilated in depth (each
 bin takes the largest t of itself and the `dilate` bins in front of it, so that
-samples continue into an object behind its front surface; reading, see the
-design notes), and the mean binary cross-entropy between sigmoid(z_b) and t_b
-is the loss.
+samples continue into an object behind its front surface; an option of this
+implementation, not in the paper), and the mean binary cross-entropy between
+sigmoid(z_b) and t_b is the loss.
 
 Network: gamma_4(x_hat) (27 values) -> Linear(64) -> relu -> Linear(64) -> relu
 -> Linear(1); flat layout W0 [64][27], b0 [64], W1 [64][64], b1 [64],
