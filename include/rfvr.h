@@ -23,7 +23,8 @@
  *   point atomics: results are bitwise reproducible for fixed shapes.
  * - NaN/Inf inside arrays propagate; only descriptor scalars are checked.
  *
- * Notation: i = measurement (antenna, monostatic), n = frequency with
+ * Notation: i = measurement (a transmitter and its receiver: the same antenna
+ * for a monostatic aperture, rx = NULL), n = frequency with
  * f_n = f0 + n*df, j = sample point laid out [n_ray][n_z] along primary rays
  * (depth u ascending), c = 299792458 m/s.
  */
@@ -88,9 +89,8 @@ extern "C" {
 typedef struct rfvr_aperture {
     int32_t      n_meas;   /* number of (tx, rx) measurements, >= 1             */
     const float* tx;       /* [n_meas][3] transmitter positions, metres         */
-    const float* rx;       /* NULL = monostatic (rx = tx).  Non-NULL (bistatic) is
-                              reserved: every entry point returns
-                              RFVR_E_UNSUPPORTED for it                          */
+    const float* rx;       /* [n_meas][3] receiver positions (bistatic), or NULL
+                              (monostatic, rx = tx); see the render below       */
     double       f0_hz;    /* first sweep frequency                              */
     double       df_hz;    /* frequency step                                     */
     int32_t      n_freq;   /* >= 1                                               */
@@ -114,7 +114,9 @@ typedef struct rfvr_fields {
     const float* refl;     /* [n_ray*n_z] reflectiveness a                           */
     const float* phi_ray;  /* [n_ray] Phi_s(f) at primary-ray origins, detached; or NULL */
     const float* phi_tx;   /* [n_meas] Phi_s(f) at transmitters, detached; or NULL   */
-    const float* phi_rx;   /* reserved for bistatic, must be NULL                    */
+    const float* phi_rx;   /* [n_meas] Phi_s(f) at receivers, detached: with a bistatic
+                              aperture, given exactly when phi_ray and phi_tx are;
+                              NULL for a monostatic one (else RFVR_E_INVALID)     */
     float        s;        /* logistic sharpness (1/m), finite, > 0                  */
     float        amp_tx;   /* learnt global amplitude A'_tx, finite                  */
     const float* amp_ptr;  /* device [1] or NULL; when set, A'_tx is read from device
@@ -140,6 +142,15 @@ typedef struct rfvr_fields {
  *   c_ij   = A' w_r a_j alpha_j T'^2 spec_ij / r_ij^2,  r_ij = |x_j - tx_i|,
  *            spec = 2 (n_hat . w_i)^2 - 1 (monostatic w_o . w_r), see RFVR_SPEC_*
  *   s[i,n] = sum_j c_ij exp(-j 2 pi f_n 2 r_ij / c)
+ * A bistatic aperture (rx != NULL; Eq. signal_amp_tracing with separate
+ * antennas, App. A, Radar Reflections) takes the path tx_i -> x_j -> rx_i:
+ *   c_ij   = A' w_r a_j alpha_j T'tx_ij T'rx_ij spec_ij / (rt_ij rr_ij),
+ *   rt = |x_j - tx_i|, rr = |rx_i - x_j|, w_i = (x_j - tx_i)/rt, w_r = (rx_i - x_j)/rr,
+ *   spec = w_o . w_r = w_i . w_r - 2 (n_hat . w_i)(n_hat . w_r),
+ *   T'tx as T' above, T'rx = clamp(T_k + phi_rx[i] - phi_ray[r], 0, 1),
+ *   s[i,n] = sum_j c_ij exp(-j 2 pi f_n (rt_ij + rr_ij) / c);
+ * with rx = tx it equals the monostatic render.  RFVR_WEIGHT_SEGMENT is defined
+ * for monostatic apertures only (RFVR_E_UNSUPPORTED otherwise).
  * With RFVR_WEIGHT_SEGMENT, sample j instead stands for the segment from it to
  * the next sample of its ray: the weight alpha_j T'^2 becomes the exact
  * integral of the round-trip weight T(u)^2 rho(u) over that segment (Eq.
@@ -162,7 +173,8 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
 /* Adjoint of rfvr_render_forward (App. A, Differentiable Matched Filter & Signal
  * Tracing, and Code Implementation, Alg. 2 backward), with the
  * per-term phases and amplitudes recomputed rather than stored:
- *   G_ij = sum_n Re(g_signal[i,n] exp(+j 2 pi f_n 2 r_ij / c)),
+ *   G_ij = sum_n Re(g_signal[i,n] exp(+j 2 pi f_n 2 r_ij / c))
+ *          (bistatic: path rt_ij + rr_ij instead of 2 r_ij),
  * chained through the amplitude, the transmittance product scan, alpha(Phi),
  * Phi(s f) and n_hat = grad / max(|grad|, 1e-12).  phi_* are detached.
  * Clamps pass gradient on their closed interval.
@@ -178,7 +190,8 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
 /* ------------------------------------------------------------------------
  * Matched filter (filter-based rendering, Eq. mf-sm; App. A, Code Implementation, Alg. 1)
  *   z_q = sum_{i,n} signal[i,n] exp(+j 2 pi f_n d_iq / c),  power_q = |z_q|
- * with the monostatic round trip d_iq = 2 |x_q - tx_i|.
+ * with the round trip d_iq = 2 |x_q - tx_i| (monostatic) or
+ * |x_q - tx_i| + |rx_i - x_q| (bistatic).
  * xyz_q: [n_q][3] query points.  signal2: optional second signal filtered at
  * the same points (e.g. the measured one), with outputs z2/power2.
  * Any of z, power, z2, power2 may be NULL.  flags: 0 or RFVR_PHASE_NAIVE32.

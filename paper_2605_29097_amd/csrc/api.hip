@@ -27,7 +27,7 @@ int hip_status(hipError_t e, const char* what) {
 
 static constexpr int kMaxFreq = 8192;
 
-static int check_aperture(const rfvr_aperture* ap, bool allow_rx) {
+static int check_aperture(const rfvr_aperture* ap) {
     if (!ap) { set_error("aperture descriptor is NULL"); return RFVR_E_INVALID; }
     if (ap->n_meas < 1 || ap->n_meas > RFVR_MAX_MEAS) {
         set_error("n_meas must be in [1, RFVR_MAX_MEAS] (got %d)", ap->n_meas);
@@ -41,10 +41,6 @@ static int check_aperture(const rfvr_aperture* ap, bool allow_rx) {
     if (!std::isfinite(ap->f0_hz) || !std::isfinite(ap->df_hz) || ap->f0_hz <= 0.0 || ap->df_hz < 0.0) {
         set_error("f0_hz must be finite and > 0, df_hz finite and >= 0");
         return RFVR_E_INVALID;
-    }
-    if (ap->rx && !allow_rx) {
-        set_error("bistatic apertures (rx != NULL) are not implemented on the GPU");
-        return RFVR_E_UNSUPPORTED;
     }
     return RFVR_OK;
 }
@@ -63,12 +59,18 @@ static int check_samples(const rfvr_samples* sm) {
     return RFVR_OK;
 }
 
-static int check_fields(const rfvr_fields* fl) {
+// the shift of the transmittance needs Phi at the ray origins and at every
+// antenna: with a bistatic aperture phi_rx comes with phi_ray and phi_tx
+static int check_fields(const rfvr_fields* fl, const rfvr_aperture* ap) {
     if (!fl) { set_error("fields descriptor is NULL"); return RFVR_E_INVALID; }
     if (!fl->sdf || !fl->grad || !fl->refl) { set_error("fields sdf/grad/refl must not be NULL"); return RFVR_E_INVALID; }
     if (!std::isfinite(fl->s) || fl->s <= 0.0f) { set_error("fields s must be finite and > 0"); return RFVR_E_INVALID; }
     if (!std::isfinite(fl->amp_tx)) { set_error("fields amp_tx must be finite"); return RFVR_E_INVALID; }
-    if (fl->phi_rx) { set_error("phi_rx is reserved for bistatic apertures and must be NULL"); return RFVR_E_UNSUPPORTED; }
+    if (!ap->rx && fl->phi_rx) { set_error("phi_rx is for bistatic apertures only (rx is NULL)"); return RFVR_E_INVALID; }
+    if (ap->rx && (fl->phi_ray && fl->phi_tx) != (fl->phi_rx != nullptr)) {
+        set_error("a bistatic aperture takes phi_ray, phi_tx and phi_rx together, or none of them");
+        return RFVR_E_INVALID;
+    }
     return RFVR_OK;
 }
 
@@ -92,10 +94,38 @@ static RenderGeom make_geom(const rfvr_aperture* ap, int n_ray, int n_z) {
     g.K0 = 2.0 * ap->f0_hz / kSpeedOfLight;
     g.Kd = 2.0 * ap->df_hz / kSpeedOfLight;
     g.seg = 0;
+    g.bi = ap->rx ? 1 : 0;
+    g.rxa = nullptr;
     return g;
 }
 
 static int padded_freq(int n_freq) { return (n_freq + 31) / 32 * 32; }
+
+// the segment weight integrates T'^2 rho of one antenna's shift over a segment;
+// the bistatic round trip (T_tx T_rx) has the sample weight only
+static int check_bistatic_weight(const RenderGeom& g) {
+    if (g.bi && g.seg) {
+        set_error("RFVR_WEIGHT_SEGMENT is not defined for bistatic apertures (rx != NULL)");
+        return RFVR_E_UNSUPPORTED;
+    }
+    return RFVR_OK;
+}
+
+// transmitter records, and receiver records of a bistatic aperture (g.rxa set
+// to them); fl: the fields whose phi_tx / phi_rx shift the transmittance, or
+// NULL when the shift is off
+static int build_ant_records(const rfvr_aperture* ap, const rfvr_fields* fl, AntRec* ant, AntRec* rxa,
+                             RenderGeom& g, hipStream_t st) {
+    int rc;
+    if ((rc = hip_status(launch_ant_records(ap->tx, fl ? fl->phi_tx : nullptr, ap->n_meas, ant, st),
+                         "transmitter records")))
+        return rc;
+    if (rxa && (rc = hip_status(launch_ant_records(ap->rx, fl ? fl->phi_rx : nullptr, ap->n_meas, rxa, st),
+                                "receiver records")))
+        return rc;
+    g.rxa = rxa;
+    return RFVR_OK;
+}
 
 static int render_splits(const RenderGeom& g) {
     const int F = freq_chunk(g.n_freq);
@@ -148,16 +178,19 @@ static size_t partial_count(long n_pts, int n_meas, int n_freq, int ns_direct) {
 }
 
 // ---------------------------------------------------------------- workspace layouts
+// antenna records: transmitters, and receivers of a bistatic aperture
+static size_t ant_bytes(int n_meas, bool bi) { return (bi ? 2 : 1) * align256(sizeof(AntRec) * n_meas); }
+
 static size_t ws_render_forward(const RenderGeom& g) {
     const int ns = render_splits(g);
-    return align256(sizeof(AntRec) * g.n_meas) + align256(sizeof(PtRec) * g.n_pts) +
+    return ant_bytes(g.n_meas, g.bi) + align256(sizeof(PtRec) * g.n_pts) +
            align256(sizeof(float2) * partial_count(g.n_pts, g.n_meas, g.n_freq, ns)) +
            align256(sizeof(float2) * (size_t)g.n_meas * kChebMaxOrder) + ws_cheb(g.n_pts, g.n_meas);
 }
 
 static size_t ws_render_backward(const RenderGeom& g) {
     const size_t np = padded_freq(g.n_freq);
-    return align256(sizeof(AntRec) * g.n_meas) + align256(sizeof(PtRec) * g.n_pts) +
+    return ant_bytes(g.n_meas, g.bi) + align256(sizeof(PtRec) * g.n_pts) +
            4 * align256(sizeof(float) * g.n_pts) +               // alpha, trans, g_b, g_T
            align256(sizeof(float) * 3 * g.n_pts) +               // g_n
            align256(sizeof(float) * g.n_pts) +                   // g_alpha
@@ -168,7 +201,7 @@ static size_t ws_render_backward(const RenderGeom& g) {
 
 static size_t ws_mf_forward(const rfvr_aperture* ap, long n_q, int two) {
     const size_t np = padded_freq(ap->n_freq);
-    return align256(sizeof(AntRec) * ap->n_meas) +
+    return ant_bytes(ap->n_meas, ap->rx != nullptr) +
            (two ? 2 : 1) * (align256(sizeof(float2) * ap->n_meas * np) +
                             align256(sizeof(float2) * (size_t)ap->n_meas * kChebMaxOrder)) +
            ws_cheb(n_q, ap->n_meas);
@@ -181,7 +214,7 @@ static int mf_splits(const rfvr_aperture* ap, long n_q) {
 
 static size_t ws_mf_backward(const rfvr_aperture* ap, long n_q) {
     const int ns = mf_splits(ap, n_q);
-    return align256(sizeof(AntRec) * ap->n_meas) + align256(sizeof(QRec) * n_q) +
+    return ant_bytes(ap->n_meas, ap->rx != nullptr) + align256(sizeof(QRec) * n_q) +
            align256(sizeof(float2) * partial_count(n_q, ap->n_meas, ap->n_freq, ns)) +
            align256(sizeof(float2) * (size_t)ap->n_meas * kChebMaxOrder) + ws_cheb(n_q, ap->n_meas);
 }
@@ -235,7 +268,7 @@ int rfvr_version(void) { return 100; }
 
 // ---------------------------------------------------------------- render
 size_t rfvr_render_forward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples* sm) {
-    if (check_aperture(ap, false) || check_samples(sm)) return 0;
+    if (check_aperture(ap) || check_samples(sm)) return 0;
     return ws_render_forward(make_geom(ap, sm->n_ray, sm->n_z));
 }
 
@@ -254,25 +287,25 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
                         uint32_t flags, float* signal, float* alpha_out, float* trans_out,
                         void* ws, size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_aperture(ap, false)) || (rc = check_samples(sm)) || (rc = check_fields(fl)) ||
+    if ((rc = check_aperture(ap)) || (rc = check_samples(sm)) || (rc = check_fields(fl, ap)) ||
         (rc = check_flags(flags)))
         return rc;
     if (!signal) { set_error("signal output is NULL"); return RFVR_E_INVALID; }
     RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
     g.seg = (flags & RFVR_WEIGHT_SEGMENT) ? 1 : 0;
+    if ((rc = check_bistatic_weight(g))) return rc;
     if ((rc = check_ws(ws, ws_bytes, ws_render_forward(g)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     AntRec* ant = cur.take<AntRec>(g.n_meas);
+    AntRec* rxa = g.bi ? cur.take<AntRec>(g.n_meas) : nullptr;
     PtRec* rec = cur.take<PtRec>(g.n_pts);
     const int ns = render_splits(g);
     float2* partial = cur.take<float2>(partial_count(g.n_pts, g.n_meas, g.n_freq, ns));
     float2* M = cur.take<float2>((size_t)g.n_meas * kChebMaxOrder);
     const ChebWs cw = take_cheb(cur, g.n_pts, g.n_meas);
     const int use_phi = (fl->phi_ray && fl->phi_tx) ? 1 : 0;
-    if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
-                         "ant records")))
-        return rc;
+    if ((rc = build_ant_records(ap, use_phi ? fl : nullptr, ant, rxa, g, st))) return rc;
     if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, sm->point_weight, fl->sdf, fl->grad, fl->refl,
                                             fl->phi_ray, use_phi, fl->s, fl->log_s_ptr, fl->amp_tx, fl->amp_ptr, rec,
                                             alpha_out, trans_out, st),
@@ -280,7 +313,7 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
         return rc;
     const ChebPlan* sel = nullptr;
     if (use_cheb(flags)) {
-        if ((rc = hip_status(launch_cheb_plan(sm->xyz, g.n_pts, ant, g.n_meas, g.Kd, g.n_freq, cw.bbox, cw.meas,
+        if ((rc = hip_status(launch_cheb_plan(sm->xyz, g.n_pts, ant, g.rxa, g.n_meas, g.Kd, g.n_freq, cw.bbox, cw.meas,
                                               cw.plan, st), "term plan")))
             return rc;
         sel = cw.plan;
@@ -299,7 +332,7 @@ int rfvr_render_forward(const rfvr_aperture* ap, const rfvr_samples* sm, const r
 }
 
 size_t rfvr_render_backward_ws_bytes(const rfvr_aperture* ap, const rfvr_samples* sm) {
-    if (check_aperture(ap, false) || check_samples(sm)) return 0;
+    if (check_aperture(ap) || check_samples(sm)) return 0;
     return ws_render_backward(make_geom(ap, sm->n_ray, sm->n_z));
 }
 
@@ -308,19 +341,21 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
                          float* g_refl, float* g_amp, float* g_s, void* ws, size_t ws_bytes,
                          void* stream) {
     int rc;
-    if ((rc = check_aperture(ap, false)) || (rc = check_samples(sm)) || (rc = check_fields(fl)) ||
+    if ((rc = check_aperture(ap)) || (rc = check_samples(sm)) || (rc = check_fields(fl, ap)) ||
         (rc = check_flags(flags)))
         return rc;
     if (!g_signal) { set_error("g_signal is NULL"); return RFVR_E_INVALID; }
     if (sm->point_weight) { set_error("point weights are supported by rfvr_render_forward only"); return RFVR_E_UNSUPPORTED; }
     RenderGeom g = make_geom(ap, sm->n_ray, sm->n_z);
     g.seg = (flags & RFVR_WEIGHT_SEGMENT) ? 1 : 0;
+    if ((rc = check_bistatic_weight(g))) return rc;
     if ((rc = check_ws(ws, ws_bytes, ws_render_backward(g)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int acc = (flags & RFVR_ACCUMULATE) ? 1 : 0;
     const int np = padded_freq(g.n_freq);
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     AntRec* ant = cur.take<AntRec>(g.n_meas);
+    AntRec* rxa = g.bi ? cur.take<AntRec>(g.n_meas) : nullptr;
     PtRec* rec = cur.take<PtRec>(g.n_pts);
     float* alpha = cur.take<float>(g.n_pts);
     float* trans = cur.take<float>(g.n_pts);
@@ -334,9 +369,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
     float2* B = cur.take<float2>((size_t)g.n_meas * kChebMaxOrder);
     const ChebWs cw = take_cheb(cur, g.n_pts, g.n_meas);
     const int use_phi = (fl->phi_ray && fl->phi_tx) ? 1 : 0;
-    if ((rc = hip_status(launch_ant_records(ap->tx, use_phi ? fl->phi_tx : nullptr, g.n_meas, ant, st),
-                         "ant records")))
-        return rc;
+    if ((rc = build_ant_records(ap, use_phi ? fl : nullptr, ant, rxa, g, st))) return rc;
     if ((rc = hip_status(launch_render_prep(g, sm->xyz, sm->ray_weight, nullptr, fl->sdf, fl->grad, fl->refl,
                                             fl->phi_ray, use_phi, fl->s, fl->log_s_ptr, fl->amp_tx, fl->amp_ptr, rec,
                                             alpha, trans, st),
@@ -348,7 +381,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
         return rc;
     const ChebPlan* sel = nullptr;
     if (use_cheb(flags)) {
-        if ((rc = hip_status(launch_cheb_plan(sm->xyz, g.n_pts, ant, g.n_meas, g.Kd, g.n_freq, cw.bbox, cw.meas,
+        if ((rc = hip_status(launch_cheb_plan(sm->xyz, g.n_pts, ant, g.rxa, g.n_meas, g.Kd, g.n_freq, cw.bbox, cw.meas,
                                               cw.plan, st), "term plan")))
             return rc;
         sel = cw.plan;
@@ -377,7 +410,7 @@ int rfvr_render_backward(const rfvr_aperture* ap, const rfvr_samples* sm, const 
 
 // ---------------------------------------------------------------- matched filter
 size_t rfvr_mf_forward_ws_bytes(const rfvr_aperture* ap, int64_t n_q, int two_signals) {
-    if (check_aperture(ap, false) || !count_ok(n_q)) return 0;
+    if (check_aperture(ap) || !count_ok(n_q)) return 0;
     return ws_mf_forward(ap, (long)n_q, two_signals);
 }
 
@@ -385,7 +418,7 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
                     const float* signal, float* z, float* power, const float* signal2, float* z2,
                     float* power2, void* ws, size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_aperture(ap, false))) return rc;
+    if ((rc = check_aperture(ap))) return rc;
     if (flags & ~(uint32_t)(RFVR_PHASE_NAIVE32 | RFVR_TERMS_DIRECT)) {
         set_error("only RFVR_PHASE_NAIVE32 and RFVR_TERMS_DIRECT are meaningful here");
         return RFVR_E_INVALID;
@@ -395,16 +428,17 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
     const int two = signal2 ? 1 : 0;
     if ((rc = check_ws(ws, ws_bytes, ws_mf_forward(ap, (long)n_q, two)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const RenderGeom g = make_geom(ap, 1, 1);
+    RenderGeom g = make_geom(ap, 1, 1);
     const int np = padded_freq(ap->n_freq);
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     AntRec* ant = cur.take<AntRec>(ap->n_meas);
+    AntRec* rxa = g.bi ? cur.take<AntRec>(ap->n_meas) : nullptr;
     float2* sp = cur.take<float2>((size_t)ap->n_meas * np);
     float2* sp2 = two ? cur.take<float2>((size_t)ap->n_meas * np) : nullptr;
     float2* B = cur.take<float2>((size_t)ap->n_meas * kChebMaxOrder);
     float2* B2 = two ? cur.take<float2>((size_t)ap->n_meas * kChebMaxOrder) : nullptr;
     const ChebWs cw = take_cheb(cur, (long)n_q, ap->n_meas);
-    if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
+    if ((rc = build_ant_records(ap, nullptr, ant, rxa, g, st))) return rc;
     if ((rc = hip_status(launch_pad_signal(reinterpret_cast<const float2*>(signal), ap->n_meas,
                                            ap->n_freq, np, sp, st), "pad signal")))
         return rc;
@@ -413,7 +447,7 @@ int rfvr_mf_forward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, ui
         return rc;
     const ChebPlan* sel = nullptr;
     if (use_cheb(flags)) {
-        if ((rc = hip_status(launch_cheb_plan(xyz_q, (long)n_q, ant, ap->n_meas, g.Kd, ap->n_freq, cw.bbox,
+        if ((rc = hip_status(launch_cheb_plan(xyz_q, (long)n_q, ant, g.rxa, ap->n_meas, g.Kd, ap->n_freq, cw.bbox,
                                               cw.meas, cw.plan, st), "term plan")))
             return rc;
         sel = cw.plan;
@@ -438,7 +472,7 @@ int rfvr_mf_forward_static(const rfvr_aperture* ap, const float* xyz_q, int64_t 
                            const float* signal, float* z, float* power, const float* signal2, float* z2,
                            float* power2, void* stream) {
     int rc;
-    if ((rc = check_aperture(ap, false))) return rc;
+    if ((rc = check_aperture(ap))) return rc;
     if ((rc = check_count("n_q", n_q))) return rc;
     const size_t need = ws_mf_forward(ap, (long)n_q, signal2 ? 1 : 0);
     if (need > (size_t)RFVR_MF_STATIC_SCRATCH_BYTES) {
@@ -454,7 +488,7 @@ int rfvr_mf_forward_static(const rfvr_aperture* ap, const float* xyz_q, int64_t 
 }
 
 size_t rfvr_mf_backward_ws_bytes(const rfvr_aperture* ap, int64_t n_q) {
-    if (check_aperture(ap, false) || !count_ok(n_q)) return 0;
+    if (check_aperture(ap) || !count_ok(n_q)) return 0;
     return ws_mf_backward(ap, (long)n_q);
 }
 
@@ -462,7 +496,7 @@ int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, c
                      const float* power, const float* g_power, uint32_t flags, float* g_signal,
                      void* ws, size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_aperture(ap, false)) || (rc = check_flags(flags))) return rc;
+    if ((rc = check_aperture(ap)) || (rc = check_flags(flags))) return rc;
     if (!xyz_q || !z || !power || !g_power || !g_signal) {
         set_error("xyz_q, z, power, g_power and g_signal are required");
         return RFVR_E_INVALID;
@@ -475,18 +509,19 @@ int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, c
     const int ns = mf_splits(ap, (long)n_q);
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     AntRec* ant = cur.take<AntRec>(ap->n_meas);
+    AntRec* rxa = g.bi ? cur.take<AntRec>(ap->n_meas) : nullptr;
     QRec* rec = cur.take<QRec>((size_t)n_q);
     float2* partial = cur.take<float2>(partial_count((long)n_q, ap->n_meas, ap->n_freq, ns));
     float2* M = cur.take<float2>((size_t)ap->n_meas * kChebMaxOrder);
     const ChebWs cw = take_cheb(cur, (long)n_q, ap->n_meas);
     const int acc = (flags & RFVR_ACCUMULATE) ? 1 : 0;
-    if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
+    if ((rc = build_ant_records(ap, nullptr, ant, rxa, g, st))) return rc;
     if ((rc = hip_status(launch_mf_bwd_records(xyz_q, (long)n_q, reinterpret_cast<const float2*>(z),
                                                power, g_power, rec, st), "mf adjoint records")))
         return rc;
     const ChebPlan* sel = nullptr;
     if (use_cheb(flags)) {
-        if ((rc = hip_status(launch_cheb_plan(xyz_q, (long)n_q, ant, ap->n_meas, g.Kd, ap->n_freq, cw.bbox,
+        if ((rc = hip_status(launch_cheb_plan(xyz_q, (long)n_q, ant, g.rxa, ap->n_meas, g.Kd, ap->n_freq, cw.bbox,
                                               cw.meas, cw.plan, st), "term plan")))
             return rc;
         sel = cw.plan;
@@ -506,24 +541,25 @@ int rfvr_mf_backward(const rfvr_aperture* ap, const float* xyz_q, int64_t n_q, c
 
 // ---------------------------------------------------------------- term evaluation order
 size_t rfvr_term_order_ws_bytes(const rfvr_aperture* ap, int64_t n_pts) {
-    if (check_aperture(ap, false) || !count_ok(n_pts)) return 0;
-    return align256(sizeof(AntRec) * ap->n_meas) + ws_cheb((long)n_pts, ap->n_meas);
+    if (check_aperture(ap) || !count_ok(n_pts)) return 0;
+    return ant_bytes(ap->n_meas, ap->rx != nullptr) + ws_cheb((long)n_pts, ap->n_meas);
 }
 
 int rfvr_term_order(const rfvr_aperture* ap, const float* xyz, int64_t n_pts, int32_t* order, void* ws,
                     size_t ws_bytes, void* stream) {
     int rc;
-    if ((rc = check_aperture(ap, false))) return rc;
+    if ((rc = check_aperture(ap))) return rc;
     if (!xyz || !order) { set_error("xyz and order are required"); return RFVR_E_INVALID; }
     if ((rc = check_count("n_pts", n_pts))) return rc;
     if ((rc = check_ws(ws, ws_bytes, rfvr_term_order_ws_bytes(ap, n_pts)))) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const RenderGeom g = make_geom(ap, 1, 1);
+    RenderGeom g = make_geom(ap, 1, 1);
     WsCursor cur{reinterpret_cast<char*>(ws), 0};
     AntRec* ant = cur.take<AntRec>(ap->n_meas);
+    AntRec* rxa = g.bi ? cur.take<AntRec>(ap->n_meas) : nullptr;
     const ChebWs cw = take_cheb(cur, (long)n_pts, ap->n_meas);
-    if ((rc = hip_status(launch_ant_records(ap->tx, nullptr, ap->n_meas, ant, st), "ant records"))) return rc;
-    if ((rc = hip_status(launch_cheb_plan(xyz, (long)n_pts, ant, ap->n_meas, g.Kd, ap->n_freq, cw.bbox, cw.meas,
+    if ((rc = build_ant_records(ap, nullptr, ant, rxa, g, st))) return rc;
+    if ((rc = hip_status(launch_cheb_plan(xyz, (long)n_pts, ant, g.rxa, ap->n_meas, g.Kd, ap->n_freq, cw.bbox, cw.meas,
                                           cw.plan, st), "term plan")))
         return rc;
     return hip_status(launch_cheb_order(cw.plan, order, st), "term order");
@@ -736,8 +772,8 @@ static int check_scenes(int32_t n, const rfvr_scene* sc, SceneCall call) {
     if (n < 1 || !sc) { set_error("n_scenes must be >= 1 and scenes non-NULL"); return RFVR_E_INVALID; }
     for (int s = 0; s < n; ++s) {
         int rc;
-        if ((rc = check_aperture(&sc[s].ap, false)) || (rc = check_samples(&sc[s].sm)) ||
-            (call != SC_FILTER && (rc = check_fields(&sc[s].fl))))
+        if ((rc = check_aperture(&sc[s].ap)) || (rc = check_samples(&sc[s].sm)) ||
+            (call != SC_FILTER && (rc = check_fields(&sc[s].fl, &sc[s].ap))))
             return scene_error(s, rc);
         if (call == SC_RENDER_BWD && sc[s].sm.point_weight) {
             set_error("scene %d: point weights are supported by rfvr_render_forward only", s);

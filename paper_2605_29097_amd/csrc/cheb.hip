@@ -9,7 +9,9 @@
 // the centre of the band, Kc = K0 + nc Kd with nc = (n_freq - 1) / 2, and
 // dn = n - nc in [-nc, nc].  Every point of a launch lies in an axis-aligned
 // box, so for measurement i its range r lies in [rc_i - h_i, rc_i + h_i]
-// (distances from the transmitter to the box).  With x = (r - rc) / h in
+// (distances from the transmitter to the box; for a bistatic pair r is the
+// mean of the distances from the transmitter and to the receiver, and the band
+// the mean of their two bands).  With x = (r - rc) / h in
 // [-1, 1] and z_n = 2 pi dn Kd h (of either sign),
 //   exp(s j 2 pi dn Kd r) = exp(s j 2 pi dn Kd rc) exp(s j z_n x)
 // and the Jacobi-Anger expansion
@@ -104,7 +106,8 @@ __device__ double cheb_log_bound(int K, double z) {
 }
 
 __global__ __launch_bounds__(256) void k_cheb_plan(const float* __restrict__ part, int nb,
-                                                   const AntRec* __restrict__ ant, int n_meas, double Kd,
+                                                   const AntRec* __restrict__ ant,
+                                                   const AntRec* __restrict__ rxa, int n_meas, double Kd,
                                                    int n_freq, MeasCheb* __restrict__ meas,
                                                    ChebPlan* __restrict__ plan) {
     __shared__ float sb[6][256];
@@ -138,18 +141,30 @@ __global__ __launch_bounds__(256) void k_cheb_plan(const float* __restrict__ par
     const double bh[3] = {(double)sb[3][0], (double)sb[4][0], (double)sb[5][0]};
     const bool finite = isfinite(bl[0]) && isfinite(bl[1]) && isfinite(bl[2]) && isfinite(bh[0]) &&
                         isfinite(bh[1]) && isfinite(bh[2]);
-    double zl = 0.0;
-    for (int i = t; i < n_meas; i += 256) {
-        const double tx[3] = {ant[i].x, ant[i].y, ant[i].z};
+    // distances from an antenna to the box: nearest face, farthest corner
+    auto band = [&](const AntRec& a, double& lo_, double& hi_) {
+        const double p[3] = {a.x, a.y, a.z};
         double n2 = 0.0, f2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double qn = fmax(fmax(bl[c] - tx[c], tx[c] - bh[c]), 0.0);   // to the nearest face
-            const double qf = fmax(fabs(tx[c] - bl[c]), fabs(tx[c] - bh[c]));  // to the farthest corner
+            const double qn = fmax(fmax(bl[c] - p[c], p[c] - bh[c]), 0.0);
+            const double qf = fmax(fabs(p[c] - bl[c]), fabs(p[c] - bh[c]));
             n2 += qn * qn;
             f2 += qf * qf;
         }
-        const double rlo = sqrt(n2), rhi = sqrt(f2);
+        lo_ = sqrt(n2);
+        hi_ = sqrt(f2);
+    };
+    double zl = 0.0;
+    for (int i = t; i < n_meas; i += 256) {
+        double rlo, rhi;
+        band(ant[i], rlo, rhi);
+        if (rxa) {
+            double lo2, hi2;
+            band(rxa[i], lo2, hi2);
+            rlo = 0.5 * (rlo + lo2);
+            rhi = 0.5 * (rhi + hi2);
+        }
         MeasCheb m;
         m.rc = 0.5 * (rlo + rhi);
         // margin for the rounding of the per-pair FP64 range (relative ~1e-14)
@@ -246,9 +261,9 @@ __device__ __forceinline__ void bessel_j_desc(double z, int nk, Visit visit) {
 // the XCDs as in the per-frequency kernel.
 // partial[split][meas][kChebKMax] (k < K written).
 // ---------------------------------------------------------------------------
-template <int K, int KIND, int SPEC>
+template <int K, int KIND, int SPEC, bool BI>
 __global__ __launch_bounds__(256) void k_cheb_points(
-    int n_meas, const AntRec* __restrict__ ant, const MeasCheb* __restrict__ meas,
+    int n_meas, const AntRec* __restrict__ ant, const AntRec* __restrict__ rxa, const MeasCheb* __restrict__ meas,
     const ChebPlan* __restrict__ plan, double Kc, const void* __restrict__ recs_v, long n_pts,
     long pts_per_split, int n_split, int gx, float2* __restrict__ partial) {
     if (plan->K != K) return;
@@ -261,6 +276,8 @@ __global__ __launch_bounds__(256) void k_cheb_points(
     const bool live_lane = i < n_meas;
     const int ic = live_lane ? i : n_meas - 1;
     const AntRec A = ant[ic];
+    AntRec Rx = A;
+    if constexpr (BI) Rx = rxa[ic];
     const MeasCheb mc = meas[ic];
     float mr[K], mi[K];
 #pragma unroll
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(256) void k_cheb_points(
     for (long j = j0; j < j1; ++j) {
         double r;
         float cr, ci;
-        if constexpr (KIND == 0) {
+        if constexpr (KIND == 0 && !BI) {
             const PtRec& P = cur;
             const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
             float y;
@@ -292,10 +309,36 @@ __global__ __launch_bounds__(256) void k_cheb_points(
             const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
             cr = P.b * spec * (T * (P.sq != 0.0f ? T : 1.0f)) * (y * y);
             ci = 0.0f;
+        } else if constexpr (KIND == 0) {
+            // bistatic (sample weight only): b spec T_tx T_rx / (r_t r_r)
+            const PtRec& P = cur;
+            const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
+            const double ex = P.x - Rx.x, ey = P.y - Rx.y, ez = P.z - Rx.z;
+            float yt, yr;
+            r = 0.5 * (range_f64(dx, dy, dz, yt) + range_f64(ex, ey, ez, yr));
+            float spec, live;
+            if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                spec = 1.0f;
+            } else {
+                const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+                const float fex = (float)ex, fey = (float)ey, fez = (float)ez;
+                const float ni = (P.nx * fdx + P.ny * fdy + P.nz * fdz) * yt;
+                const float nr = -(P.nx * fex + P.ny * fey + P.nz * fez) * yr;
+                const float ir = -(fdx * fex + fdy * fey + fdz * fez) * (yt * yr);
+                spec_factor_bi<SPEC>(ni, nr, ir, spec, live);
+            }
+            const float Tt = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
+            const float Tr = fminf(fmaxf(P.tp + Rx.phi, 0.0f), 1.0f);
+            cr = P.b * spec * (Tt * Tr) * (yt * yr);
+            ci = 0.0f;
         } else {
             const QRec& Q = cur;
             float y;
             r = range_f64(Q.x - A.x, Q.y - A.y, Q.z - A.z, y);
+            if constexpr (BI) {
+                float yr;
+                r = 0.5 * (r + range_f64(Q.x - Rx.x, Q.y - Rx.y, Q.z - Rx.z, yr));
+            }
             cr = Q.hr;
             ci = Q.hi;
         }
@@ -514,10 +557,11 @@ __device__ __forceinline__ void cheb_series2(const float2* __restrict__ Bi, cons
 // matched filter forward: lane = query point, loop over measurements
 // (records, plan and coefficients are wave-uniform loads)
 // ---------------------------------------------------------------------------
-template <int K, bool TWO>
+template <int K, bool TWO, bool BI>
 __global__ __launch_bounds__(256) void k_cheb_mf(const ChebPlan* __restrict__ plan, long n_q,
                                                  const float* __restrict__ xq, int n_meas,
                                                  const AntRec* __restrict__ ant,
+                                                 const AntRec* __restrict__ rxa,
                                                  const MeasCheb* __restrict__ meas,
                                                  const float2* __restrict__ B, const float2* __restrict__ B2,
                                                  double Kc, float2* __restrict__ z, float* __restrict__ power,
@@ -531,7 +575,12 @@ __global__ __launch_bounds__(256) void k_cheb_mf(const ChebPlan* __restrict__ pl
         const AntRec A = ant[i];
         const MeasCheb mc = meas[i];
         float y;
-        const double r = range_f64(px - A.x, py - A.y, pz - A.z, y);
+        double r = range_f64(px - A.x, py - A.y, pz - A.z, y);
+        if constexpr (BI) {
+            const AntRec Rx = rxa[i];
+            float yr;
+            r = 0.5 * (r + range_f64(px - Rx.x, py - Rx.y, pz - Rx.z, yr));
+        }
         const float x = (float)((r - mc.rc) * mc.inv_h);
         const float t0 = frac_rev(r * Kc);
         const float c0 = cos_rev(t0), s0 = sin_rev(t0);       // exp(+j 2 pi Kc r)
@@ -561,10 +610,11 @@ __global__ __launch_bounds__(256) void k_cheb_mf(const ChebPlan* __restrict__ pl
 // G = Re(sum_n g[i][n] exp(+j 2 pi (K0 + n Kd) r)) then the chain rule of the
 // per-frequency kernel
 // ---------------------------------------------------------------------------
-template <int K, int SPEC>
+template <int K, int SPEC, bool BI>
 __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restrict__ plan, long n_pts,
                                                          const PtRec* __restrict__ rec, int n_meas,
                                                          const AntRec* __restrict__ ant,
+                                                         const AntRec* __restrict__ rxa,
                                                          const MeasCheb* __restrict__ meas,
                                                          const float2* __restrict__ B, double Kc,
                                                          float* __restrict__ g_b, float* __restrict__ g_T,
@@ -578,13 +628,51 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
         const MeasCheb mc = meas[i];
         const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
         float y;
-        const double r = range_f64(dx, dy, dz, y);
+        double r = range_f64(dx, dy, dz, y);
+        AntRec Rx = A;
+        double ex = 0.0, ey = 0.0, ez = 0.0;
+        float yr = 0.0f;
+        if constexpr (BI) {
+            Rx = rxa[i];
+            ex = P.x - Rx.x; ey = P.y - Rx.y; ez = P.z - Rx.z;
+            r = 0.5 * (r + range_f64(ex, ey, ez, yr));
+        }
         const float x = (float)((r - mc.rc) * mc.inv_h);
         float sr, si;
         cheb_series<K>(B + (size_t)i * kChebKMax, x, sr, si);
         const float t0 = frac_rev(r * Kc);
         const float c0 = cos_rev(t0), s0 = sin_rev(t0);
         const float G = c0 * sr - s0 * si;                     // Re(exp(+j 2 pi Kc r) S)
+        if constexpr (BI) {
+            // c = b spec T_tx T_rx y_t y_r (sample weight): dc/db, dc/dT
+            // (times b after the loop) and dc/dn_hat (times -2 b after the loop)
+            const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+            const float fex = (float)ex, fey = (float)ey, fez = (float)ez;
+            float spec, live = 0.0f, ni = 0.0f, nr = 0.0f;
+            if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                spec = 1.0f;
+            } else {
+                ni = (P.nx * fdx + P.ny * fdy + P.nz * fdz) * y;
+                nr = -(P.nx * fex + P.ny * fey + P.nz * fez) * yr;
+                const float ir = -(fdx * fex + fdy * fey + fdz * fez) * (y * yr);
+                spec_factor_bi<SPEC>(ni, nr, ir, spec, live);
+            }
+            const float Ut = P.tp + A.phi, Ur = P.tp + Rx.phi;
+            const float Tt = fminf(fmaxf(Ut, 0.0f), 1.0f), Tr = fminf(fmaxf(Ur, 0.0f), 1.0f);
+            const float dT = (Tt == Ut ? Tr : 0.0f) + (Tr == Ur ? Tt : 0.0f);
+            const float gy = G * (y * yr);
+            const float gs = gy * spec, T2 = Tt * Tr;
+            gb = __builtin_fmaf(gs, T2, gb);
+            gt = __builtin_fmaf(gs, dT, gt);
+            if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
+                // nr w_i + ni w_r with w_i = d_t y_t, w_r = -d_r y_r
+                const float ct = gy * T2 * live * (nr * y), cq = -gy * T2 * live * (ni * yr);
+                gn0 = __builtin_fmaf(ct, fdx, __builtin_fmaf(cq, fex, gn0));
+                gn1 = __builtin_fmaf(ct, fdy, __builtin_fmaf(cq, fey, gn1));
+                gn2 = __builtin_fmaf(ct, fdz, __builtin_fmaf(cq, fez, gn2));
+            }
+            continue;
+        }
         const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
         float spec, live = 0.0f, nd = 0.0f;
         if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
@@ -612,7 +700,7 @@ __global__ __launch_bounds__(256) void k_cheb_render_bwd(const ChebPlan* __restr
     if (j >= n_pts) return;
     g_b[j] = gb;
     g_T[j] = P.b * gt;
-    const float b4 = 4.0f * P.b;
+    const float b4 = (BI ? -2.0f : 4.0f) * P.b;
     g_n[3 * j] = b4 * gn0;
     g_n[3 * j + 1] = b4 * gn1;
     g_n[3 * j + 2] = b4 * gn2;
@@ -635,12 +723,13 @@ hipError_t launch_cheb_order(const ChebPlan* plan, int32_t* order, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, int n_meas, double Kd, int n_freq,
-                            float* bbox_part, MeasCheb* meas, ChebPlan* plan, hipStream_t st) {
+hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, const AntRec* rxa, int n_meas,
+                            double Kd, int n_freq, float* bbox_part, MeasCheb* meas, ChebPlan* plan,
+                            hipStream_t st) {
     const int nb = cheb_bbox_blocks(n);
     const long per = (n + nb - 1) / nb;
     hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, st, xyz, n, per, bbox_part);
-    hipLaunchKernelGGL(k_cheb_plan, dim3(1), dim3(256), 0, st, bbox_part, nb, ant, n_meas, Kd, n_freq, meas,
+    hipLaunchKernelGGL(k_cheb_plan, dim3(1), dim3(256), 0, st, bbox_part, nb, ant, rxa, n_meas, Kd, n_freq, meas,
                        plan);
     return hipGetLastError();
 }
@@ -648,7 +737,7 @@ hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, int n_m
 // wavenumber at the centre of the band (revolutions per metre of range)
 static double band_centre(const RenderGeom& g) { return g.K0 + 0.5 * (double)(g.n_freq - 1) * g.Kd; }
 
-template <int KIND, int SPEC>
+template <int KIND, int SPEC, bool BI>
 static void launch_cp_all(const RenderGeom& g, const AntRec* ant, const MeasCheb* meas, const ChebPlan* plan,
                           const void* rec, int n_split, float2* partial, hipStream_t st) {
     const int gx = (g.n_meas + 255) / 256;
@@ -657,8 +746,8 @@ static void launch_cp_all(const RenderGeom& g, const AntRec* ant, const MeasCheb
     const long per = (g.n_pts + n_split - 1) / n_split;
     const double Kc = band_centre(g);
 #define RFVR_CP(KK)                                                                                           \
-    hipLaunchKernelGGL((k_cheb_points<KK, KIND, SPEC>), grid, dim3(256), 0, st, g.n_meas, ant, meas, plan, Kc, \
-                       rec, g.n_pts, per, n_split, gx, partial)
+    hipLaunchKernelGGL((k_cheb_points<KK, KIND, SPEC, BI>), grid, dim3(256), 0, st, g.n_meas, ant, g.rxa, meas, \
+                       plan, Kc, rec, g.n_pts, per, n_split, gx, partial)
     RFVR_CP(24);
     RFVR_CP(28);
     RFVR_CP(32);
@@ -685,13 +774,20 @@ int cheb_point_splits(long n_pts, int n_meas) {
 hipError_t launch_cheb_points(const RenderGeom& g, int kind, uint32_t flags, const AntRec* ant,
                               const MeasCheb* meas, const ChebPlan* plan, const void* rec, int n_split,
                               float2* partial, float2* M, float2* out, int accumulate, hipStream_t st) {
+    const auto all = [&](auto kind_c, auto spec_c) {
+        constexpr int KI = decltype(kind_c)::value, SP = decltype(spec_c)::value;
+        if (g.rxa) launch_cp_all<KI, SP, true>(g, ant, meas, plan, rec, n_split, partial, st);
+        else launch_cp_all<KI, SP, false>(g, ant, meas, plan, rec, n_split, partial, st);
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I0 = std::integral_constant<int, 0>;
     if (kind == 1) {
-        launch_cp_all<1, RFVR_SPEC_OFF>(g, ant, meas, plan, rec, n_split, partial, st);
+        all(I1{}, std::integral_constant<int, RFVR_SPEC_OFF>{});
     } else {
         switch (flags & RFVR_SPEC_MASK) {
-            case RFVR_SPEC_RAW: launch_cp_all<0, RFVR_SPEC_RAW>(g, ant, meas, plan, rec, n_split, partial, st); break;
-            case RFVR_SPEC_OFF: launch_cp_all<0, RFVR_SPEC_OFF>(g, ant, meas, plan, rec, n_split, partial, st); break;
-            default: launch_cp_all<0, RFVR_SPEC_CLAMP>(g, ant, meas, plan, rec, n_split, partial, st); break;
+            case RFVR_SPEC_RAW: all(I0{}, std::integral_constant<int, RFVR_SPEC_RAW>{}); break;
+            case RFVR_SPEC_OFF: all(I0{}, std::integral_constant<int, RFVR_SPEC_OFF>{}); break;
+            default: all(I0{}, std::integral_constant<int, RFVR_SPEC_CLAMP>{}); break;
         }
     }
     const long nm = (long)g.n_meas * kChebKMax;
@@ -710,15 +806,15 @@ hipError_t launch_cheb_coef(const RenderGeom& g, const ChebPlan* plan, const Mea
     return hipGetLastError();
 }
 
-template <bool TWO>
+template <bool TWO, bool BI>
 static void launch_cmf_all(const RenderGeom& g, const ChebPlan* plan, long n_q, const float* xq,
                            const AntRec* ant, const MeasCheb* meas, const float2* B, const float2* B2,
                            float2* z, float* power, float2* z2, float* power2, hipStream_t st) {
     dim3 grid((unsigned)((n_q + 255) / 256));
     const double Kc = band_centre(g);
 #define RFVR_CMF(KK)                                                                                     \
-    hipLaunchKernelGGL((k_cheb_mf<KK, TWO>), grid, dim3(256), 0, st, plan, n_q, xq, g.n_meas, ant, meas, B, \
-                       B2, Kc, z, power, z2, power2)
+    hipLaunchKernelGGL((k_cheb_mf<KK, TWO, BI>), grid, dim3(256), 0, st, plan, n_q, xq, g.n_meas, ant, g.rxa, \
+                       meas, B, B2, Kc, z, power, z2, power2)
     RFVR_CMF(24);
     RFVR_CMF(28);
     RFVR_CMF(32);
@@ -731,20 +827,25 @@ static void launch_cmf_all(const RenderGeom& g, const ChebPlan* plan, long n_q, 
 hipError_t launch_cheb_mf(const RenderGeom& g, const ChebPlan* plan, long n_q, const float* xq,
                           const AntRec* ant, const MeasCheb* meas, const float2* B, const float2* B2,
                           float2* z, float* power, float2* z2, float* power2, hipStream_t st) {
-    if (B2) launch_cmf_all<true>(g, plan, n_q, xq, ant, meas, B, B2, z, power, z2, power2, st);
-    else launch_cmf_all<false>(g, plan, n_q, xq, ant, meas, B, B2, z, power, z2, power2, st);
+    if (B2) {
+        if (g.rxa) launch_cmf_all<true, true>(g, plan, n_q, xq, ant, meas, B, B2, z, power, z2, power2, st);
+        else launch_cmf_all<true, false>(g, plan, n_q, xq, ant, meas, B, B2, z, power, z2, power2, st);
+    } else {
+        if (g.rxa) launch_cmf_all<false, true>(g, plan, n_q, xq, ant, meas, B, B2, z, power, z2, power2, st);
+        else launch_cmf_all<false, false>(g, plan, n_q, xq, ant, meas, B, B2, z, power, z2, power2, st);
+    }
     return hipGetLastError();
 }
 
-template <int SPEC>
+template <int SPEC, bool BI>
 static void launch_crb_all(const RenderGeom& g, const ChebPlan* plan, const AntRec* ant, const MeasCheb* meas,
                            const PtRec* rec, const float2* B, float* g_b, float* g_T, float* g_n,
                            hipStream_t st) {
     dim3 grid((unsigned)((g.n_pts + 255) / 256));
     const double Kc = band_centre(g);
 #define RFVR_CRB(KK)                                                                                        \
-    hipLaunchKernelGGL((k_cheb_render_bwd<KK, SPEC>), grid, dim3(256), 0, st, plan, g.n_pts, rec, g.n_meas, ant, \
-                       meas, B, Kc, g_b, g_T, g_n)
+    hipLaunchKernelGGL((k_cheb_render_bwd<KK, SPEC, BI>), grid, dim3(256), 0, st, plan, g.n_pts, rec, g.n_meas,  \
+                       ant, g.rxa, meas, B, Kc, g_b, g_T, g_n)
     RFVR_CRB(24);
     RFVR_CRB(28);
     RFVR_CRB(32);
@@ -757,10 +858,15 @@ static void launch_crb_all(const RenderGeom& g, const ChebPlan* plan, const AntR
 hipError_t launch_cheb_render_bwd(const RenderGeom& g, uint32_t flags, const ChebPlan* plan, const AntRec* ant,
                                   const MeasCheb* meas, const PtRec* rec, const float2* B, float* g_b,
                                   float* g_T, float* g_n, hipStream_t st) {
+    const auto all = [&](auto spec_c) {
+        constexpr int SP = decltype(spec_c)::value;
+        if (g.rxa) launch_crb_all<SP, true>(g, plan, ant, meas, rec, B, g_b, g_T, g_n, st);
+        else launch_crb_all<SP, false>(g, plan, ant, meas, rec, B, g_b, g_T, g_n, st);
+    };
     switch (flags & RFVR_SPEC_MASK) {
-        case RFVR_SPEC_RAW: launch_crb_all<RFVR_SPEC_RAW>(g, plan, ant, meas, rec, B, g_b, g_T, g_n, st); break;
-        case RFVR_SPEC_OFF: launch_crb_all<RFVR_SPEC_OFF>(g, plan, ant, meas, rec, B, g_b, g_T, g_n, st); break;
-        default: launch_crb_all<RFVR_SPEC_CLAMP>(g, plan, ant, meas, rec, B, g_b, g_T, g_n, st); break;
+        case RFVR_SPEC_RAW: all(std::integral_constant<int, RFVR_SPEC_RAW>{}); break;
+        case RFVR_SPEC_OFF: all(std::integral_constant<int, RFVR_SPEC_OFF>{}); break;
+        default: all(std::integral_constant<int, RFVR_SPEC_CLAMP>{}); break;
     }
     return hipGetLastError();
 }

@@ -19,9 +19,10 @@ namespace rfvr {
 #endif
 constexpr int kHornerPPL = RFVR_HORNER_PPL;   // query points per lane
 
-template <bool TWO, bool NAIVE>
+template <bool TWO, bool NAIVE, bool BI>
 __global__ __launch_bounds__(256) void k_mf_forward(
     long n_q, const float* __restrict__ xq, int n_meas, const AntRec* __restrict__ ant,
+    const AntRec* __restrict__ rxa,
     const float2* __restrict__ sig, const float2* __restrict__ sig2, int np, double K0,
     double Kd, float2* __restrict__ z, float* __restrict__ power, float2* __restrict__ z2,
     float* __restrict__ power2, const ChebPlan* __restrict__ sel) {
@@ -48,7 +49,13 @@ __global__ __launch_bounds__(256) void k_mf_forward(
         float cw[PPL], sw[PPL];
 #pragma unroll
         for (int u = 0; u < PPL; ++u) {
-            geo[u] = pair_geom<NAIVE>(px[u] - A.x, py[u] - A.y, pz[u] - A.z);
+            if constexpr (BI) {
+                const AntRec Rx = rxa[i];
+                geo[u] = bi_geom<NAIVE>(px[u] - A.x, py[u] - A.y, pz[u] - A.z, px[u] - Rx.x, py[u] - Rx.y,
+                                        pz[u] - Rx.z).g;
+            } else {
+                geo[u] = pair_geom<NAIVE>(px[u] - A.x, py[u] - A.y, pz[u] - A.z);
+            }
             step_phasor<NAIVE>(geo[u], Kd, cw[u], sw[u]);       // w = exp(+j 2 pi delta)
         }
         const float2* row = sig + (size_t)i * np;
@@ -131,25 +138,21 @@ hipError_t launch_mf_forward(const RenderGeom& g, const AntRec* ant, const float
                              hipStream_t st) {
     dim3 grid((unsigned)((n_q + 256L * kHornerPPL - 1) / (256L * kHornerPPL)));
     const bool naive = (flags & RFVR_PHASE_NAIVE32) != 0;
+#define RFVR_MFF(TV, NV, BV)                                                                                 \
+    hipLaunchKernelGGL((k_mf_forward<TV, NV, BV>), grid, dim3(256), 0, st, n_q, xyz_q, g.n_meas, ant, g.rxa, \
+                       sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2, power2, sel)
+#define RFVR_MFF_B(TV, NV)            \
+    if (g.rxa) RFVR_MFF(TV, NV, true); \
+    else RFVR_MFF(TV, NV, false)
     if (sig2_pad) {
-        if (naive)
-            hipLaunchKernelGGL((k_mf_forward<true, true>), grid, dim3(256), 0, st, n_q, xyz_q,
-                               g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2, sel);
-        else
-            hipLaunchKernelGGL((k_mf_forward<true, false>), grid, dim3(256), 0, st, n_q, xyz_q,
-                               g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2, sel);
+        if (naive) { RFVR_MFF_B(true, true); }
+        else { RFVR_MFF_B(true, false); }
     } else {
-        if (naive)
-            hipLaunchKernelGGL((k_mf_forward<false, true>), grid, dim3(256), 0, st, n_q, xyz_q,
-                               g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2, sel);
-        else
-            hipLaunchKernelGGL((k_mf_forward<false, false>), grid, dim3(256), 0, st, n_q, xyz_q,
-                               g.n_meas, ant, sig_pad, sig2_pad, np, g.K0, g.Kd, z, power, z2,
-                               power2, sel);
+        if (naive) { RFVR_MFF_B(false, true); }
+        else { RFVR_MFF_B(false, false); }
     }
+#undef RFVR_MFF_B
+#undef RFVR_MFF
     return hipGetLastError();
 }
 

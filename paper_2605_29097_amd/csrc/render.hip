@@ -151,9 +151,10 @@ hipError_t launch_render_prep(const RenderGeom& g, const float* xyz, const float
 // relative error of the 2^20-point signal against the FP64 reference).
 constexpr int kSeed = 32;
 
-template <int F, int KIND, int SPEC, bool NAIVE>
+template <int F, int KIND, int SPEC, bool NAIVE, bool BI>
 __global__ __launch_bounds__(256) void k_reduce_points(
-    int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, double K0, double Kd,
+    int n_meas, int n_freq, int n_chunks, const AntRec* __restrict__ ant, const AntRec* __restrict__ rxa,
+    double K0, double Kd,
     const void* __restrict__ recs_v, long n_pts, long pts_per_split, int n_split, int gx,
     float2* __restrict__ partial, const ChebPlan* __restrict__ sel) {
     if (sel && sel->K != 0) return;              // the Chebyshev path took this launch
@@ -179,6 +180,8 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     const bool live_lane = c < n_chunks;
     if (!live_lane) c = n_chunks - 1;
     const AntRec A = ant[i];
+    AntRec Rx = A;
+    if constexpr (BI) Rx = rxa[i];
     double Kc[NS];                                // phase rate at each sub-chunk centre
 #pragma unroll
     for (int m = 0; m < NS; ++m) Kc[m] = K0 + (double)(c * F + m * S + S / 2) * Kd;
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(256) void k_reduce_points(
         for (int k = 0; k < cnt; ++k) {
             float wr, wi, cr, ci;          // step phasor, complex weight of the pair
             PairGeom g;
-            if constexpr (KIND == 0) {
+            if constexpr (KIND == 0 && !BI) {
                 const PtRec P = reinterpret_cast<const PtRec*>(sRec[buf])[k];
                 const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
                 g = pair_geom<NAIVE>(dx, dy, dz);
@@ -225,10 +228,36 @@ __global__ __launch_bounds__(256) void k_reduce_points(
                 const float T = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
                 cr = P.b * spec * (T * (P.sq != 0.0f ? T : 1.0f)) * (g.y * g.y);
                 ci = 0.0f;
+            } else if constexpr (KIND == 0) {
+                // bistatic (sample weight only): b spec T_tx T_rx / (r_t r_r)
+                const PtRec P = reinterpret_cast<const PtRec*>(sRec[buf])[k];
+                const double dx = P.x - A.x, dy = P.y - A.y, dz = P.z - A.z;
+                const double ex = P.x - Rx.x, ey = P.y - Rx.y, ez = P.z - Rx.z;
+                const BiGeom b = bi_geom<NAIVE>(dx, dy, dz, ex, ey, ez);
+                g = b.g;
+                float spec, live;
+                if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                    spec = 1.0f;
+                } else {
+                    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+                    const float fex = (float)ex, fey = (float)ey, fez = (float)ez;
+                    const float ni = (P.nx * fdx + P.ny * fdy + P.nz * fdz) * b.yt;
+                    const float nr = -(P.nx * fex + P.ny * fey + P.nz * fez) * b.yr;
+                    const float ir = -(fdx * fex + fdy * fey + fdz * fez) * (b.yt * b.yr);
+                    spec_factor_bi<SPEC>(ni, nr, ir, spec, live);
+                }
+                const float Tt = fminf(fmaxf(P.tp + A.phi, 0.0f), 1.0f);
+                const float Tr = fminf(fmaxf(P.tp + Rx.phi, 0.0f), 1.0f);
+                cr = P.b * spec * (Tt * Tr) * (b.yt * b.yr);
+                ci = 0.0f;
             } else {
                 const QRec Q = reinterpret_cast<const QRec*>(sRec[buf])[k];
                 const double dx = Q.x - A.x, dy = Q.y - A.y, dz = Q.z - A.z;
-                g = pair_geom<NAIVE>(dx, dy, dz);
+                if constexpr (BI) {
+                    g = bi_geom<NAIVE>(dx, dy, dz, Q.x - Rx.x, Q.y - Rx.y, Q.z - Rx.z).g;
+                } else {
+                    g = pair_geom<NAIVE>(dx, dy, dz);
+                }
                 cr = Q.hr;
                 ci = Q.hi;
             }
@@ -285,18 +314,25 @@ __global__ __launch_bounds__(256) void k_reduce_points(
     }
 }
 
-template <int F, int KIND, int SPEC, bool NAIVE>
-static hipError_t launch_rp(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
-                            float2* partial, const ChebPlan* sel, hipStream_t st) {
+template <int F, int KIND, int SPEC, bool NAIVE, bool BI>
+static hipError_t launch_rp_bi(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
+                               float2* partial, const ChebPlan* sel, hipStream_t st) {
     const int n_chunks = (g.n_freq + F - 1) / F;
     const long lanes = (long)g.n_meas * n_chunks;
     const int gx = (int)((lanes + 255) / 256);
     const long groups = (n_split + 7) / 8;                // 8 splits per group, one per XCD
     dim3 grid((unsigned)(groups * 8 * gx));
     const long per = (g.n_pts + n_split - 1) / n_split;
-    hipLaunchKernelGGL((k_reduce_points<F, KIND, SPEC, NAIVE>), grid, dim3(256), 0, st, g.n_meas,
-                       g.n_freq, n_chunks, ant, g.K0, g.Kd, rec, g.n_pts, per, n_split, gx, partial, sel);
+    hipLaunchKernelGGL((k_reduce_points<F, KIND, SPEC, NAIVE, BI>), grid, dim3(256), 0, st, g.n_meas,
+                       g.n_freq, n_chunks, ant, g.rxa, g.K0, g.Kd, rec, g.n_pts, per, n_split, gx, partial, sel);
     return hipGetLastError();
+}
+
+template <int F, int KIND, int SPEC, bool NAIVE>
+static hipError_t launch_rp(const RenderGeom& g, const AntRec* ant, const void* rec, int n_split,
+                            float2* partial, const ChebPlan* sel, hipStream_t st) {
+    if (g.rxa) return launch_rp_bi<F, KIND, SPEC, NAIVE, true>(g, ant, rec, n_split, partial, sel, st);
+    return launch_rp_bi<F, KIND, SPEC, NAIVE, false>(g, ant, rec, n_split, partial, sel, st);
 }
 
 template <int KIND, int SPEC, bool NAIVE>
@@ -387,9 +423,10 @@ hipError_t launch_pad_signal(const float2* sig, int n_meas, int n_freq, int np, 
 #endif
 constexpr int kBwdPPL = RFVR_HORNER_PPL;      // points per lane
 
-template <int SPEC, bool NAIVE>
+template <int SPEC, bool NAIVE, bool BI>
 __global__ __launch_bounds__(256) void k_render_bwd_points(
     long n_pts, const PtRec* __restrict__ rec, int n_meas, const AntRec* __restrict__ ant,
+    const AntRec* __restrict__ rxa,
     const float2* __restrict__ gsig, int np, double K0, double Kd, float* __restrict__ g_b,
     float* __restrict__ g_T, float* __restrict__ g_n, const ChebPlan* __restrict__ sel) {
     if (sel && sel->K != 0) return;              // the Chebyshev path took this launch
@@ -408,13 +445,23 @@ __global__ __launch_bounds__(256) void k_render_bwd_points(
     for (int u = 0; u < PPL; ++u) gb[u] = gt[u] = gn0[u] = gn1[u] = gn2[u] = 0.0f;
     for (int i = 0; i < n_meas; ++i) {
         const AntRec A = ant[i];
+        AntRec Rx = A;
+        if constexpr (BI) Rx = rxa[i];
         PairGeom geo[PPL];
-        float cw[PPL], sw[PPL];
-        double dx[PPL], dy[PPL], dz[PPL];
+        float cw[PPL], sw[PPL], yr[PPL];
+        double dx[PPL], dy[PPL], dz[PPL], ex[PPL], ey[PPL], ez[PPL];
 #pragma unroll
         for (int u = 0; u < PPL; ++u) {
             dx[u] = P[u].x - A.x; dy[u] = P[u].y - A.y; dz[u] = P[u].z - A.z;
-            geo[u] = pair_geom<NAIVE>(dx[u], dy[u], dz[u]);
+            if constexpr (BI) {
+                ex[u] = P[u].x - Rx.x; ey[u] = P[u].y - Rx.y; ez[u] = P[u].z - Rx.z;
+                const BiGeom b = bi_geom<NAIVE>(dx[u], dy[u], dz[u], ex[u], ey[u], ez[u]);
+                geo[u] = b.g;
+                geo[u].y = b.yt;                            // y holds 1/r_t here
+                yr[u] = b.yr;
+            } else {
+                geo[u] = pair_geom<NAIVE>(dx[u], dy[u], dz[u]);
+            }
             step_phasor<NAIVE>(geo[u], Kd, cw[u], sw[u]);       // w = exp(+j 2 pi delta)
         }
         const float2* g = gsig + (size_t)i * np;
@@ -457,6 +504,36 @@ __global__ __launch_bounds__(256) void k_render_bwd_points(
             const float G = c0 * Hr - s0 * Hi;       // Re(exp(+j 2 pi theta_mid) H)
             const float y = geo[u].y;
             const float fdx = (float)dx[u], fdy = (float)dy[u], fdz = (float)dz[u];
+            if constexpr (BI) {
+                // c = b spec T_tx T_rx y_t y_r (sample weight)
+                const float fex = (float)ex[u], fey = (float)ey[u], fez = (float)ez[u];
+                float spec, live = 0.0f, ni = 0.0f, nr = 0.0f;
+                if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+                    spec = 1.0f;
+                } else {
+                    ni = (P[u].nx * fdx + P[u].ny * fdy + P[u].nz * fdz) * y;
+                    nr = -(P[u].nx * fex + P[u].ny * fey + P[u].nz * fez) * yr[u];
+                    const float ir = -(fdx * fex + fdy * fey + fdz * fez) * (y * yr[u]);
+                    spec_factor_bi<SPEC>(ni, nr, ir, spec, live);
+                }
+                const float Ut = P[u].tp + A.phi, Ur = P[u].tp + Rx.phi;
+                const float Tt = fminf(fmaxf(Ut, 0.0f), 1.0f), Tr = fminf(fmaxf(Ur, 0.0f), 1.0f);
+                const float mt = (Ut >= 0.0f && Ut <= 1.0f) ? 1.0f : 0.0f;
+                const float mr = (Ur >= 0.0f && Ur <= 1.0f) ? 1.0f : 0.0f;
+                const float T2 = Tt * Tr;
+                const float gy = G * (y * yr[u]);
+                gb[u] = __builtin_fmaf(gy * spec, T2, gb[u]);
+                gt[u] = __builtin_fmaf(gy * P[u].b * spec, __builtin_fmaf(mt, Tr, Tt * mr), gt[u]);
+                if constexpr (SPEC != (int)RFVR_SPEC_OFF) {
+                    // d spec / d n_hat = -2 (nr w_i + ni w_r), w_i = d_t y_t, w_r = -d_r y_r
+                    const float cb = -2.0f * gy * P[u].b * T2 * live;
+                    const float ct = cb * (nr * y), cq = -cb * (ni * yr[u]);
+                    gn0[u] = __builtin_fmaf(ct, fdx, __builtin_fmaf(cq, fex, gn0[u]));
+                    gn1[u] = __builtin_fmaf(ct, fdy, __builtin_fmaf(cq, fey, gn1[u]));
+                    gn2[u] = __builtin_fmaf(ct, fdz, __builtin_fmaf(cq, fez, gn2[u]));
+                }
+                continue;
+            }
             float spec, live = 0.0f;
             float nd = 0.0f;
             if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
@@ -500,12 +577,17 @@ static hipError_t launch_rbp(const RenderGeom& g, const AntRec* ant, const PtRec
                              const float2* gsig, int np, bool naive, float* g_b, float* g_T,
                              float* g_n, const ChebPlan* sel, hipStream_t st) {
     dim3 grid((unsigned)((g.n_pts + 256L * kBwdPPL - 1) / (256L * kBwdPPL)));
-    if (naive)
-        hipLaunchKernelGGL((k_render_bwd_points<SPEC, true>), grid, dim3(256), 0, st, g.n_pts, rec,
-                           g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n, sel);
-    else
-        hipLaunchKernelGGL((k_render_bwd_points<SPEC, false>), grid, dim3(256), 0, st, g.n_pts,
-                           rec, g.n_meas, ant, gsig, np, g.K0, g.Kd, g_b, g_T, g_n, sel);
+#define RFVR_RBP(NV, BV)                                                                                    \
+    hipLaunchKernelGGL((k_render_bwd_points<SPEC, NV, BV>), grid, dim3(256), 0, st, g.n_pts, rec, g.n_meas, \
+                       ant, g.rxa, gsig, np, g.K0, g.Kd, g_b, g_T, g_n, sel)
+    if (naive) {
+        if (g.rxa) RFVR_RBP(true, true);
+        else RFVR_RBP(true, false);
+    } else {
+        if (g.rxa) RFVR_RBP(false, true);
+        else RFVR_RBP(false, false);
+    }
+#undef RFVR_RBP
     return hipGetLastError();
 }
 

@@ -46,7 +46,9 @@ struct alignas(16) QRec {
 static_assert(sizeof(QRec) == 32, "QRec layout");
 
 // Per-measurement record (positions in FP64 so the path length is exact in the
-// inputs; phi = Phi_s at the transmitter, 0 when the correction is off).
+// inputs; phi = Phi_s at the antenna, 0 when the correction is off).  A
+// bistatic launch holds one array for the transmitters and one for the
+// receivers.
 struct alignas(16) AntRec {
     double x, y, z;
     float phi, pad;
@@ -95,23 +97,39 @@ __device__ __forceinline__ float alpha_pair(float a, float b) {
     return fminf(al, 1.0f);
 }
 
-// specular factor of a pair from nd = n_hat . w_i: 2 nd^2 - 1 = w_o . w_r,
-// clamped at 0 (CLAMP), raw (RAW) or 1 (OFF); live = 1 where it is not clamped
+// the specular factor from its raw value w_o . w_r: clamped at 0 (CLAMP), raw
+// (RAW) or 1 (OFF); live = 1 where it is not clamped
 template <int SPEC>
-__device__ __forceinline__ void spec_factor(float nd, float& spec, float& live) {
+__device__ __forceinline__ void spec_clamp(float sr, float& spec, float& live) {
     if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
         spec = 1.0f;
         live = 0.0f;
+    } else if constexpr (SPEC == (int)RFVR_SPEC_RAW) {
+        spec = sr;
+        live = 1.0f;
     } else {
-        float sr = __builtin_fmaf(2.0f * nd, nd, -1.0f);   // 2 (n.w_i)^2 - 1 = w_o . w_r
-        if constexpr (SPEC == (int)RFVR_SPEC_RAW) {
-            spec = sr;
-            live = 1.0f;
-        } else {
-            spec = fmaxf(sr, 0.0f);
-            live = sr >= 0.0f ? 1.0f : 0.0f;
-        }
+        spec = fmaxf(sr, 0.0f);
+        live = sr >= 0.0f ? 1.0f : 0.0f;
     }
+}
+
+// monostatic pair (w_r = -w_i), from nd = n_hat . w_i: w_o . w_r = 2 nd^2 - 1
+template <int SPEC>
+__device__ __forceinline__ void spec_factor(float nd, float& spec, float& live) {
+    if constexpr (SPEC == (int)RFVR_SPEC_OFF) {
+        spec_clamp<SPEC>(0.0f, spec, live);
+    } else {
+        spec_clamp<SPEC>(__builtin_fmaf(2.0f * nd, nd, -1.0f), spec, live);
+    }
+}
+
+// bistatic pair, from ni = n_hat . w_i, nr = n_hat . w_r and ir = w_i . w_r
+// (w_i from the transmitter to the point, w_r from the point to the receiver):
+// w_o = w_i - 2 ni n_hat, so w_o . w_r = ir - 2 ni nr (App. A, Radar
+// Reflections); its gradient in n_hat is -2 (nr w_i + ni w_r)
+template <int SPEC>
+__device__ __forceinline__ void spec_factor_bi(float ni, float nr, float ir, float& spec, float& live) {
+    spec_clamp<SPEC>(__builtin_fmaf(-2.0f * ni, nr, ir), spec, live);
 }
 
 // ---------------------------------------------------------------------------
@@ -130,6 +148,30 @@ struct PairGeom {
     float y;    // ~1/r
     float rf;   // r in FP32 (NAIVE mode)
 };
+
+template <bool NAIVE>
+__device__ __forceinline__ PairGeom pair_geom(double dx, double dy, double dz);
+
+// Bistatic pair: d_t = x - tx, d_r = x - rx.  The phase and the range band run
+// on the mean range r = (r_t + r_r) / 2, whose doubled value is the path
+// length, as 2 |x - tx| is for a monostatic pair; the amplitude takes
+// y_t y_r ~ 1 / (r_t r_r).
+struct BiGeom {
+    PairGeom g;   // g.r (g.rf in NAIVE mode) = (r_t + r_r) / 2; g.y unused
+    float yt, yr; // ~1/r_t, ~1/r_r
+};
+
+template <bool NAIVE>
+__device__ __forceinline__ BiGeom bi_geom(double tx_, double ty_, double tz_, double rx_, double ry_, double rz_) {
+    const PairGeom a = pair_geom<NAIVE>(tx_, ty_, tz_), b = pair_geom<NAIVE>(rx_, ry_, rz_);
+    BiGeom o;
+    o.g.r = 0.5 * (a.r + b.r);
+    o.g.rf = 0.5f * (a.rf + b.rf);
+    o.g.y = 0.0f;
+    o.yt = a.y;
+    o.yr = b.y;
+    return o;
+}
 
 template <bool NAIVE>
 __device__ __forceinline__ PairGeom pair_geom(double dx, double dy, double dz) {
@@ -282,6 +324,8 @@ struct RenderGeom {
     long n_pts;
     double K0, Kd;        // 2 f0 / c and 2 df / c (revolutions per metre of range)
     int seg;              // 1: segment weight (RFVR_WEIGHT_SEGMENT), 0: sample weight
+    int bi;               // 1: bistatic aperture (separate receivers)
+    const AntRec* rxa;    // its receiver records (set once built), or NULL
 };
 int choose_point_splits(long n_pts, int lanes_total);
 int freq_chunk(int n_freq);
@@ -351,8 +395,9 @@ constexpr int kChebMaxOrder = 64;
 int cheb_bbox_blocks(long n);
 int cheb_point_splits(long n_pts, int n_meas);
 hipError_t launch_cheb_order(const ChebPlan* plan, int32_t* order, hipStream_t st);
-hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, int n_meas, double Kd, int n_freq,
-                            float* bbox_part, MeasCheb* meas, ChebPlan* plan, hipStream_t st);
+hipError_t launch_cheb_plan(const float* xyz, long n, const AntRec* ant, const AntRec* rxa, int n_meas,
+                            double Kd, int n_freq, float* bbox_part, MeasCheb* meas, ChebPlan* plan,
+                            hipStream_t st);
 hipError_t launch_cheb_points(const RenderGeom& g, int kind, uint32_t flags, const AntRec* ant,
                               const MeasCheb* meas, const ChebPlan* plan, const void* rec, int n_split,
                               float2* partial, float2* M, float2* out, int accumulate, hipStream_t st);

@@ -207,9 +207,12 @@ class Aperture:
     f0: float
     df: float
     n_freq: int
+    rx: Optional[torch.Tensor] = None   # [n_meas, 3] receivers (bistatic), or None (rx = tx)
 
     def c(self) -> CAperture:
-        return CAperture(self.tx.shape[0], _ptr(self.tx), None, float(self.f0), float(self.df),
+        if self.rx is not None and tuple(self.rx.shape) != tuple(self.tx.shape):
+            raise ValueError(f"rx {tuple(self.rx.shape)} must have the shape of tx {tuple(self.tx.shape)}")
+        return CAperture(self.tx.shape[0], _ptr(self.tx), _ptr(self.rx), float(self.f0), float(self.df),
                          int(self.n_freq))
 
     @property
@@ -240,11 +243,12 @@ class Fields:
     amp_dev: Optional[torch.Tensor] = None     # device [1]: overrides amp at kernel time
     log_s_dev: Optional[torch.Tensor] = None   # device [1]: s = exp(log_s) at kernel time; g_s is then
                                                # the gradient in log s
+    phi_rx: Optional[torch.Tensor] = None      # [n_meas] Phi at the receivers (bistatic apertures)
 
     def c(self) -> CFields:
         return CFields(_ptr(self.sdf), _ptr(self.grad), _ptr(self.refl), _ptr(self.phi_ray),
-                       _ptr(self.phi_tx), None, float(self.s), float(self.amp), _ptr(self.amp_dev),
-                       _ptr(self.log_s_dev))
+                       _ptr(self.phi_tx), _ptr(self.phi_rx), float(self.s), float(self.amp),
+                       _ptr(self.amp_dev), _ptr(self.log_s_dev))
 
 
 # ----------------------------------------------------------------------------

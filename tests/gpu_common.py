@@ -30,8 +30,10 @@ class Case:
     """One render problem: aperture, points, fields (float32 numpy)."""
 
     def __init__(self, tx, f0, df, n_freq, xyz, sdf, grad, refl, s=64.0, amp=1.0,
-                 phi_ray=None, phi_tx=None, ray_w=None):
+                 phi_ray=None, phi_tx=None, ray_w=None, rx=None, phi_rx=None):
         self.tx = np.ascontiguousarray(tx, np.float32)
+        self.rx = None if rx is None else np.ascontiguousarray(rx, np.float32)
+        self.phi_rx = None if phi_rx is None else np.ascontiguousarray(phi_rx, np.float32)
         self.f0, self.df, self.n_freq = f0, df, n_freq
         self.xyz = np.ascontiguousarray(xyz, np.float32)
         self.sdf = np.ascontiguousarray(sdf, np.float32)
@@ -44,25 +46,27 @@ class Case:
 
     # oracle side
     def o_ap(self, sel=None):
-        tx = self.tx if sel is None else self.tx[sel]
-        return orc.Aperture(tx=tx.astype(np.float64), f0=self.f0, df=self.df, n_freq=self.n_freq)
+        pick = lambda a: None if a is None else (a if sel is None else a[sel]).astype(np.float64)
+        return orc.Aperture(tx=pick(self.tx), f0=self.f0, df=self.df, n_freq=self.n_freq, rx=pick(self.rx))
 
     def o_fields(self, rays=None, sel=None):
         r = slice(None) if rays is None else rays
         return orc.Fields(sdf=self.sdf[r], grad=self.grad[r], refl=self.refl[r], s=self.s, amp=self.amp,
                           phi_ray=None if self.phi_ray is None else self.phi_ray[r],
                           phi_tx=None if self.phi_tx is None else
-                          (self.phi_tx if sel is None else self.phi_tx[sel]))
+                          (self.phi_tx if sel is None else self.phi_tx[sel]),
+                          phi_rx=None if self.phi_rx is None else
+                          (self.phi_rx if sel is None else self.phi_rx[sel]))
 
     # GPU side
     def g(self, dev):
         import torch
         from paper_2605_29097_amd import rfvr as R
         t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-        ap = R.Aperture(tx=t(self.tx), f0=self.f0, df=self.df, n_freq=self.n_freq)
+        ap = R.Aperture(tx=t(self.tx), f0=self.f0, df=self.df, n_freq=self.n_freq, rx=t(self.rx))
         sm = R.Samples(xyz=t(self.xyz), ray_weight=t(self.ray_w))
         fl = R.Fields(sdf=t(self.sdf), grad=t(self.grad), refl=t(self.refl), s=self.s, amp=self.amp,
-                      phi_ray=t(self.phi_ray), phi_tx=t(self.phi_tx))
+                      phi_ray=t(self.phi_ray), phi_tx=t(self.phi_tx), phi_rx=t(self.phi_rx))
         return ap, sm, fl
 
 

@@ -83,9 +83,20 @@ def test_render_forward_rejects_bad_arguments(R):
     assert _fwd(R, _ap(R), _sm(R), _fl(R), flags=0x3) == -1
     assert _fwd(R, _ap(R), _sm(R), _fl(R), flags=0x100) == -1
     assert b"flag" in L.rfvr_last_error()
-    # bistatic is reserved
-    assert _fwd(R, _ap(R, rx=ctypes.c_void_p(0x5000)), _sm(R), _fl(R)) == -3
-    assert _fwd(R, _ap(R), _sm(R), _fl(R, phi_rx=ctypes.c_void_p(0x5000))) == -3
+    # bistatic apertures: accepted up to the workspace check (nothing launched)
+    bi = _ap(R, rx=ctypes.c_void_p(0x5000))
+    v = ctypes.c_void_p(0x5000)
+    assert _fwd(R, bi, _sm(R), _fl(R)) == -2
+    assert _fwd(R, bi, _sm(R), _fl(R, phi_ray=v, phi_tx=v, phi_rx=v)) == -2
+    assert (L.rfvr_render_forward_ws_bytes(ctypes.byref(bi), ctypes.byref(_sm(R))) >=
+            L.rfvr_render_forward_ws_bytes(ctypes.byref(_ap(R)), ctypes.byref(_sm(R))) + 4 * 32)
+    # the segment weight is monostatic only
+    assert _fwd(R, bi, _sm(R), _fl(R), flags=R.WEIGHT_SEGMENT) == -3
+    assert b"bistatic" in L.rfvr_last_error()
+    # phi_rx comes with phi_ray and phi_tx on a bistatic aperture, never on a monostatic one
+    assert _fwd(R, bi, _sm(R), _fl(R, phi_ray=v, phi_tx=v)) == -1
+    assert _fwd(R, bi, _sm(R), _fl(R, phi_rx=v)) == -1
+    assert _fwd(R, _ap(R), _sm(R), _fl(R, phi_rx=v)) == -1
 
 
 def test_workspace_is_checked_before_launch(R):
@@ -261,6 +272,8 @@ def test_static_filter_checks_size_before_any_device_work(R):
     assert b"RFVR_MF_STATIC_SCRATCH_BYTES" in L.rfvr_last_error()
     ap = _ap(R)
     assert L.rfvr_mf_forward_static(ctypes.byref(ap), v, 0, 0, v, v, v, None, None, None, None) == -1
-    assert L.rfvr_mf_forward_static(ctypes.byref(_ap(R, rx=v)), v, 8, 0, v, v, v, None, None, None, None) == -3
+    big_bi = _ap(R, n_meas=16384, n_freq=256, rx=v)          # receiver records are part of the size
+    assert L.rfvr_mf_forward_ws_bytes(ctypes.byref(big_bi), 64, 0) > L.rfvr_mf_forward_ws_bytes(ctypes.byref(big), 64, 0)
+    assert L.rfvr_mf_forward_static(ctypes.byref(big_bi), v, 64, 0, v, v, v, None, None, None, None) == -1
     hdr = open(HEADER).read()
     assert f"#define RFVR_MF_STATIC_SCRATCH_BYTES (32u << 20)" in hdr and R.MF_STATIC_SCRATCH_BYTES == 32 << 20

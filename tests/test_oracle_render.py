@@ -478,21 +478,29 @@ def test_transmittance_shift_closed_form_with_clamps(bistatic):
     np.testing.assert_allclose(got, expect, rtol=1e-10, atol=1e-12 * np.abs(expect).max())
 
 
-def test_gradient_through_shift_and_clamps_finite_differences():
+@pytest.mark.parametrize("bistatic", [False, True])
+def test_gradient_through_shift_and_clamps_finite_differences(bistatic):
     """Adjoint of the render with origin occupancies that push the shifted
     transmittance past both clamps for some (measurement, point) pairs: the
     oracle's gradients in sdf, grad, refl and A' against FP64 central
     differences of its own forward, at entries whose perturbation crosses no
-    clamp kink."""
+    clamp kink.  Bistatic: receivers 1-2 cm from their transmitters with their
+    own occupancies (the gradient of w_o . w_r in the normal, -2 (n.w_r w_i +
+    n.w_i w_r), and of T_tx T_rx)."""
     xyz, F = _small_scene(seed=6, n_z=6)
     ap = _ap(3, 2, 4)
     rng = np.random.default_rng(21)
     F.phi_ray = rng.uniform(0.35, 0.65, xyz.shape[0])
     F.phi_tx = np.array([0.05, 0.95, 0.5, 0.2, 0.8, 0.6])
+    shifts = [F.phi_tx]
+    if bistatic:
+        ap = _ap(3, 2, 4, rx=_ap(3, 2, 4).tx + rng.uniform(-0.02, 0.02, (6, 3)))
+        F.phi_rx = np.array([0.7, 0.1, 0.9, 0.45, 0.3, 0.98])
+        shifts.append(F.phi_rx)
     gs = rng.normal(size=(ap.n_meas, ap.n_freq)) + 1j * rng.normal(size=(ap.n_meas, ap.n_freq))
     g = orc.render_adjoint(ap, xyz, F, gs, spec="raw")
     _, alpha, T, raw = orc.alpha_trans(F.sdf, F.s)
-    shifted = T[None] + F.phi_tx[:, None, None] - F.phi_ray[None, :, None]
+    shifted = np.concatenate([T[None] + p[:, None, None] - F.phi_ray[None, :, None] for p in shifts])
     assert (shifted < 0).any() and (shifted > 1).any() and ((shifted > 0) & (shifted < 1)).any()
 
     def J(Fx):
