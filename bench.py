@@ -311,8 +311,10 @@ def proposal_study(args, dev):
     of its network (judge_nz depths per ray) against the clean target: signal
     NRMSE and heatmap (filter output) NRMSE at the judge's points.  E* is the
     full-space run's error after its step budget; steps_to_e_star is the first
-    evaluation at or below it, and ms_to_e_star adds the proposal's warm-up
-    (proposal-only steps before the SDF network trains).  Prints one JSON line.
+    evaluation at or below it, and ms_to_e_star the measured time of the steps
+    up to it plus the proposal's warm-up (proposal-only steps before the SDF
+    network trains).  --study-full-every N makes every N-th step of the
+    proposal run a full-space step (the fallback).  Prints one JSON line.
 
     --study-prior fits every run's initial network to a coarse version of the
     scene (torus and slab displaced and thickened by a few mm) by SDF
@@ -325,7 +327,7 @@ def proposal_study(args, dev):
     from synth import MLPSpec, Slab, Torus, Union, mlp_init
     flags = R.SPEC_CLAMP | (R.WEIGHT_SEGMENT if args.study_weight == "segment" else 0)
     cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28), learn_s=args.study_learn_s, s=args.study_s,
-                     render_flags=flags, judge_nz=args.study_judge_nz)
+                     render_flags=flags, judge_nz=args.study_judge_nz, amp0=args.study_amp0)
     spec = MLPSpec(centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
     if args.study_target:
         target_name = args.study_target
@@ -379,7 +381,8 @@ def proposal_study(args, dev):
               dilate=args.study_dilate)
     runs = {
         "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps, 0),
-        "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(**pc), device=dev),
+        "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(full_every=args.study_full_every, **pc),
+                                               device=dev),
                      args.study_prop_steps, args.study_prop_warmup),
         "uniform": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(train=False, **pc), device=dev),
                     args.study_prop_steps, 0),
@@ -406,6 +409,7 @@ def proposal_study(args, dev):
         curve = [(0, j["signal"], j["heatmap"])]
         at_e_star = None                     # (step, Chamfer) where the heatmap error first reaches E*
         step_ms = []
+        cum_ms = {0: 0.0}                    # measured training time up to each evaluated step
         for k in range(1, n_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -414,6 +418,7 @@ def proposal_study(args, dev):
             e1.synchronize()
             step_ms.append(e0.elapsed_time(e1))
             if k % every == 0 or k == n_steps:
+                cum_ms[k] = float(np.sum(step_ms))
                 j = tr.evaluate(clean)
                 curve.append((k, j["signal"], j["heatmap"]))
                 if e_star_hm is not None and at_e_star is None and j["heatmap"] <= e_star_hm:
@@ -421,6 +426,7 @@ def proposal_study(args, dev):
                 print(f"[study] {name} step {k} reference signal {j['signal']:.4f} heatmap {j['heatmap']:.4f} "
                       f"s {tr.s:.1f} ({np.median(step_ms):.2f} ms/step)", file=sys.stderr, flush=True)
         out[name] = {"ms_per_step": float(np.median(step_ms[2:] if len(step_ms) > 4 else step_ms)),
+                     "ms_per_step_mean": float(np.mean(step_ms)), "cum_ms": cum_ms,
                      "steps": n_steps, "warmup_steps": warm, "warmup_ms": round(warm_ms, 1), "final_s": tr.s,
                      "reference": [[k, round(a, 5), round(b, 5)] for k, a, b in curve],
                      "chamfer": chamfer_of(tr.net), "at_e_star_heatmap": at_e_star}
@@ -435,12 +441,13 @@ def proposal_study(args, dev):
         for col, key in ((1, "signal"), (2, "heatmap")):
             hit = next((row[0] for row in r["reference"] if row[col] <= e_star[key]), None)
             r[f"steps_to_e_star_{key}"] = hit
-            r[f"ms_to_e_star_{key}"] = None if hit is None else round(hit * r["ms_per_step"] + r["warmup_ms"], 1)
+            r[f"ms_to_e_star_{key}"] = None if hit is None else round(r["cum_ms"][hit] + r["warmup_ms"], 1)
     print(json.dumps({"study": "proposal_vs_full_space", "e_star": e_star, "eval_every": every,
                       "learn_s": cfg.learn_s, "s0": cfg.s, "weight": args.study_weight, "target": target_name,
                       "judge_nz": cfg.judge_nz or cfg.n_z, "prior_fit_steps": args.study_prior,
                       "prior_f_rms_m": prior_rms, "n_imp": args.study_imp, "n_uni": args.study_uni,
                       "loss_on_grid": args.study_loss_grid, "target_dilation_bins": args.study_dilate,
+                      "full_every": args.study_full_every, "amp0": args.study_amp0,
                       "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
                       "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
                                "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
@@ -659,6 +666,9 @@ def main():
                     help="grid side of the Chamfer surface extraction (0: no Chamfer)")
     ap.add_argument("--study-loss-grid", action="store_true",
                     help="sampled runs take the heatmap loss on the full-space grid (render from their samples)")
+    ap.add_argument("--study-full-every", type=int, default=0,
+                    help="every this many steps the proposal run takes a full-space step (0: never)")
+    ap.add_argument("--study-amp0", type=float, default=1.0, help="initial amplitude A' of every run")
     ap.add_argument("--study-dilate", type=int, default=0,
                     help="proposal targets dilated in depth over this many bins")
     ap.add_argument("--study-imp", type=int, default=16)

@@ -123,7 +123,8 @@ class Trainer:
         self.m = torch.zeros(n_par, device=self.dev)
         self.v = torch.zeros(n_par, device=self.dev)
         self.g = torch.zeros(n_par, device=self.dev)
-        self._res = None
+        self._res = {}                  # training-pair reserves by point count (at most two kept)
+        self.keep_alpha = False         # keep the full-space render's alpha and T in self.last
         # a reserve shared by trainers that step one after another (each step
         # fills it in its forward and reads it in its backward); None: own one
         self.shared_reserve = None
@@ -191,7 +192,10 @@ class Trainer:
                       phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
         ap_r, fl_r = self.ap, fl
         if c.bank_patch is None:
-            sig = R.render_forward(self.ap, sm, fl, flags=c.render_flags)
+            if self.keep_alpha:
+                sig, alpha_f, trans_f = R.render_forward(self.ap, sm, fl, flags=c.render_flags, want_alpha=True)
+            else:
+                sig = R.render_forward(self.ap, sm, fl, flags=c.render_flags)
         else:
             # Signal Tracing Bank: trace only the current patch's antennas into
             # its rows of the bank; the other rows keep earlier results
@@ -240,7 +244,9 @@ class Trainer:
         mark("adamw")
         if c.learn_s:
             self.update_s(gr["s"])
-        self.last = dict(signal=sig, loss=loss, phi_origins=phi)
+        self.last = dict(signal=sig, loss=loss, phi_origins=phi, u=u)
+        if self.keep_alpha and c.bank_patch is None:
+            self.last.update(alpha=alpha_f, trans=trans_f)
         return loss
 
     def reserve(self, n: int):
@@ -249,9 +255,11 @@ class Trainer:
             return None
         if self.shared_reserve is not None:
             return self.shared_reserve
-        if self._res is None or self._res_n != n:
-            self._res, self._res_n = R.mlp_reserve(self.net, n, self.dev), n
-        return self._res
+        if n not in self._res:
+            if len(self._res) >= 2:
+                self._res.pop(next(iter(self._res)))
+            self._res[n] = R.mlp_reserve(self.net, n, self.dev)
+        return self._res[n]
 
     def update_s(self, g_log_s: torch.Tensor):
         """AdamW step on log s, on the device (the render adjoint returns the
@@ -395,6 +403,8 @@ class ProposalConfig:
     loss_on_grid: bool = False  # heatmap loss on the full-space grid (its target cached) instead of
                                 # at the drawn samples; the signal is still rendered from the samples
     dilate: int = 0             # targets dilated in depth over this many bins (rfvr_proposal_targets)
+    full_every: int = 0         # every this many steps a full-space step (the fallback): it trains the
+                                # network on the full grid and the proposal on the grid's blend weights
 
 
 class ProposalTrainer(Trainer):
@@ -432,6 +442,7 @@ class ProposalTrainer(Trainer):
             self.pm = torch.zeros(npp, device=self.dev)
             self.pv = torch.zeros(npp, device=self.dev)
         self.train_sdf = True
+        self.keep_alpha = pcfg.full_every > 0
 
     def logits(self):
         n_ray = self.cfg.lines[0] * self.cfg.lines[1]
@@ -444,8 +455,28 @@ class ProposalTrainer(Trainer):
         return R.sample_importance(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0], c.lines[1],
                                    logits, pc.n_imp, pc.n_uni, seed=c.seed, step=self.t)
 
+    def full_step(self, timers: Optional[dict] = None):
+        """A full-space step (the fallback): the network trains on the full grid
+        as in Trainer.step, and the proposal on that render's blend weights
+        binned over the grid's depths."""
+        loss = Trainer.step(self, timers)
+        if self.prop is not None:
+            pc = self.pc
+            u = self.last["u"]
+            n_ray, n_z = u.shape
+            logits = self.logits()
+            t = R.proposal_targets(u, self.last["alpha"].view(n_ray, n_z), self.last["trans"].view(n_ray, n_z),
+                                   self.lo, self.hi, pc.n_bins, pc.dilate)
+            ploss, g_z = R.bce(logits, t)
+            R.proposal_backward(self.prop, self.bin_xyz, g_z, out=self.pg)
+            R.adamw(self.prop.params, self.pg, self.pm, self.pv, self.t, pc.lr)
+            self.last_proposal_loss = ploss
+        return loss
+
     def step(self, timers: Optional[dict] = None):
         c, pc = self.cfg, self.pc
+        if pc.full_every and self.train_sdf and self.t % pc.full_every == 0:
+            return self.full_step(timers)
         ev = timers
 
         def mark(name):
