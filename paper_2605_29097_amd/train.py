@@ -56,6 +56,10 @@ class StepConfig:
     keep_activations: bool = True          # network training pair: the backward reads the
                                            # forward's layer activations from a reserve
     mask_tau: Optional[tuple] = None       # (tau_hi, tau_lo): dynamic loss masking on
+    origin_phi: str = "network"            # Phi at the ray origins and antennas: "network" evaluates the
+                                           # SDF network there (Eq. lens-less-transmittance as written);
+                                           # "volume" takes space outside the sample cube as air, so with
+                                           # every origin and antenna outside it the shift is 0
 
     @property
     def n_pts(self) -> int:
@@ -147,12 +151,30 @@ class Trainer:
             self.log_s_m = torch.zeros(1, device=self.dev)
             self.log_s_v = torch.zeros(1, device=self.dev)
         self.history = None                    # per-point filter-output history (masking)
+        # the ray origins lie on the plane through the world origin normal to
+        # the primary direction (z = 0 here), the antennas at tx
+        h = cfg.cube_side / 2
+        outside = lambda p: bool(np.any(np.abs(np.asarray(p, np.float64) - np.asarray(cfg.cube_centre)) > h, axis=-1).all())
+        self.origins_in_air = (cfg.origin_phi == "volume" and abs(cfg.cube_centre[2]) > h and outside(tx))
+        if cfg.origin_phi not in ("network", "volume"):
+            raise ValueError(f"origin_phi must be 'network' or 'volume', not {cfg.origin_phi!r}")
         self.t = 0
         self.p_star = None
         self._xyz_key = None
         self.origin_pts = None
 
     # ------------------------------------------------------------------ helpers
+    def origin_occupancy(self, origin, tx):
+        """Detached Phi at the primary-ray origins and the antennas:
+        (phi_ray, phi_tx, both), or (None, None, None) when they all lie in air
+        (origin_phi = "volume", all outside the sample cube: no shift)."""
+        if self.origins_in_air:
+            return None, None, None
+        f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, tx], 0))
+        phi = R.occupancy(self.s_arg, f_org)
+        n = origin.shape[0]
+        return phi[:n].contiguous(), phi[n:].contiguous(), phi
+
     def samples(self):
         c = self.cfg
         return R.sample_points(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0], c.lines[1],
@@ -181,15 +203,13 @@ class Trainer:
         res = self.reserve(n)
         f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
         # detached occupancies at the primary-ray origins and the antennas
-        org = torch.cat([origin, self.tx], 0)
-        f_org, _, _ = R.mlp_forward(self.net, org)
-        phi = R.occupancy(self.s_arg, f_org)
+        phi_ray, phi_tx, phi = self.origin_occupancy(origin, self.tx)
         mark("mlp_fwd")
         sm = R.Samples(xyz=xyz)
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
                       refl=a.view(xyz.shape[:2]), s=self.s0, amp=1.0, amp_dev=self.amp,
                       log_s_dev=self.log_s,
-                      phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
+                      phi_ray=phi_ray, phi_tx=phi_tx)
         ap_r, fl_r = self.ap, fl
         if c.bank_patch is None:
             if self.keep_alpha:
@@ -207,7 +227,7 @@ class Trainer:
             n_ray = origin.shape[0]
             fl_r = R.Fields(sdf=fl.sdf, grad=fl.grad, refl=fl.refl, s=self.s0, amp=1.0, amp_dev=self.amp,
                             log_s_dev=self.log_s,
-                            phi_ray=fl.phi_ray, phi_tx=phi[n_ray + i0:n_ray + i1].contiguous())
+                            phi_ray=fl.phi_ray, phi_tx=None if phi_tx is None else phi_tx[i0:i1].contiguous())
             R.render_forward(ap_r, sm, fl_r, flags=c.render_flags, out=self.bank[i0:i1])
             sig = self.bank
         mark("render_fwd")
@@ -285,12 +305,10 @@ class Trainer:
         xyz, _, origin = R.sample_points(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0],
                                          c.lines[1], c.judge_nz or c.n_z, mode=R.SAMPLE_GRID, device=self.dev)
         f, grad, a = R.mlp_forward(self.net, xyz)
-        f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
-        phi = R.occupancy(self.s_arg, f_org)
+        phi_ray, phi_tx, _ = self.origin_occupancy(origin, self.tx)
         fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=grad.view(*xyz.shape[:2], 3),
                       refl=a.view(xyz.shape[:2]), s=self.s0, amp=1.0, amp_dev=self.amp,
-                      log_s_dev=self.log_s,
-                      phi_ray=phi[:origin.shape[0]].contiguous(), phi_tx=phi[origin.shape[0]:].contiguous())
+                      log_s_dev=self.log_s, phi_ray=phi_ray, phi_tx=phi_tx)
         self._ref_xyz = xyz
         return R.render_forward(self.ap, R.Samples(xyz=xyz), fl, flags=c.render_flags)
 
@@ -492,13 +510,11 @@ class ProposalTrainer(Trainer):
         mark("propose")
         res = self.reserve(n_ray * K) if self.train_sdf else None
         f, grad, a = R.mlp_forward(self.net, xyz, reserve=res)
-        f_org, _, _ = R.mlp_forward(self.net, torch.cat([origin, self.tx], 0))
-        phi = R.occupancy(self.s_arg, f_org)
+        phi_ray, phi_tx, _ = self.origin_occupancy(origin, self.tx)
         mark("mlp_fwd")
         sm = R.Samples(xyz=xyz)
         fl = R.Fields(sdf=f.view(n_ray, K), grad=grad.view(n_ray, K, 3), refl=a.view(n_ray, K), s=self.s0,
-                      amp=1.0, amp_dev=self.amp, log_s_dev=self.log_s, phi_ray=phi[:n_ray].contiguous(),
-                      phi_tx=phi[n_ray:].contiguous())
+                      amp=1.0, amp_dev=self.amp, log_s_dev=self.log_s, phi_ray=phi_ray, phi_tx=phi_tx)
         sig, alpha, trans = R.render_forward(self.ap, sm, fl, flags=c.render_flags, want_alpha=True)
         mark("render_fwd")
         self.t += 1

@@ -128,3 +128,42 @@ def test_trainer_step_with_soft_origins_matches_oracle(dev):
     assert e_sig <= 1e-4
     assert e_l <= 1e-4
     assert e_g <= 1e-3 and cos > 0.999999
+
+
+def test_origins_in_air_option(dev):
+    """origin_phi = "volume": with every ray origin and antenna outside the
+    sample cube (the 2^20-point workload: aperture plane z = 0, cube 0.20-0.40
+    m) they are taken as air, the step renders without the shift and skips
+    the origin network evaluations; at the initial network, whose origins sit
+    at Phi ~ 1, the step agrees with the default ("network") step.  With the
+    aperture plane inside the cube the network is still evaluated there."""
+    print("[case] origin_phi volume vs network, 2^20-point step", flush=True)
+    from paper_2605_29097_amd import rfvr as R
+    from paper_2605_29097_amd.train import StepConfig, Trainer
+    from synth import MLPSpec
+    R.lib()
+    spec = MLPSpec()
+    params = torch.from_numpy(mlp_init(spec, 0))
+    rng = np.random.default_rng(9)
+    target = torch.from_numpy((rng.normal(size=(1024, 128, 2)) * 1e-2).astype(np.float32))
+    a = Trainer(StepConfig(), params.clone(), target, device=dev)
+    b = Trainer(StepConfig(origin_phi="volume"), params.clone(), target, device=dev)
+    assert b.origins_in_air and not a.origins_in_air
+    a.step()
+    b.step()
+    torch.cuda.synchronize()
+    assert b.last["phi_origins"] is None
+    phi_a = a.last["phi_origins"]
+    e = rel_rms(as_complex(b.last["signal"]), as_complex(a.last["signal"]))
+    print(f"default step: Phi at origins and antennas {phi_a.min().item():.7f}-{phi_a.max().item():.7f}; "
+          f"volume step's signal differs by {e:.2e}")
+    assert phi_a.min().item() > 0.9999
+    assert e <= 1e-5
+    with pytest.raises(ValueError):
+        Trainer(StepConfig(origin_phi="plane"), params.clone(), target, device=dev)
+    import dataclasses
+    _, cfg2, _, p2, t2, _ = _soft_origin_trainer(dev)
+    cfg_in = dataclasses.replace(cfg2, cube_centre=(0.0, 0.0, 0.03), origin_phi="volume")   # z in [-0.01, 0.07]
+    assert not Trainer(cfg_in, torch.from_numpy(p2), torch.from_numpy(t2), device=dev).origins_in_air
+    cfg_out = dataclasses.replace(cfg2, origin_phi="volume")                                # z in [0.005, 0.085]
+    assert Trainer(cfg_out, torch.from_numpy(p2), torch.from_numpy(t2), device=dev).origins_in_air
