@@ -41,7 +41,7 @@ extern "C" {
 #define RFVR_OK             0
 #define RFVR_E_INVALID     -1   /* bad size, NULL required pointer, non-finite scalar */
 #define RFVR_E_WORKSPACE   -2   /* ws NULL or ws_bytes below the query              */
-#define RFVR_E_UNSUPPORTED -3   /* valid but not implemented (bistatic apertures)   */
+#define RFVR_E_UNSUPPORTED -3   /* valid arguments, combination not provided        */
 #define RFVR_E_HIP         -4   /* HIP launch / runtime error                       */
 
 /* Size limits of one call: at most RFVR_MAX_POINTS points (samples, query
