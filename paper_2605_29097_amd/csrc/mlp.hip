@@ -21,6 +21,8 @@
 // the tangent pass's adjoints from S (Zdot_bar = half_size S), so one adjoint
 // GEMM per layer remains.
 // Weight gradients reduce over points in fixed splits (no atomics).
+#include <mutex>
+
 #include "rfvr_impl.hpp"
 
 namespace rfvr {
@@ -1435,6 +1437,46 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
     return RFVR_OK;
 }
 
+// Side stream of the training backward.  A trunk layer's two weight-gradient
+// products read its Zbar and arrays that stay fixed during the sweep (the
+// reserve's H and S, the tangents, the encoding), and write only their own
+// partials and gradient rows; so they run on a second stream beside the chain
+// of adjoint products, ordered by events: they start once Zbar is written, and
+// the adjoint product that next overwrites that Zbar buffer waits for them.
+// One side stream per device, default priority, created on first use and held
+// until the process ends; a backward call holds its mutex while it enqueues,
+// so calls from several host threads on one device take turns.
+struct SideStream {
+    hipStream_t ss = nullptr;
+    hipEvent_t ready[16] = {}, done[16] = {};
+    std::mutex mu;
+};
+std::mutex g_side_mu;
+SideStream* g_side[64] = {};
+
+int side_stream(SideStream** out) {
+    int dev = -1;
+    int rc;
+    if ((rc = hip_status(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+    if (dev < 0 || dev >= 64) { set_error("device index %d beyond 64", dev); return RFVR_E_UNSUPPORTED; }
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    if (!g_side[dev]) {
+        SideStream* s = new SideStream();
+        if ((rc = hip_status(hipStreamCreateWithFlags(&s->ss, hipStreamNonBlocking), "side stream"))) {
+            delete s;
+            return rc;
+        }
+        for (int k = 0; k < 16; ++k) {
+            if ((rc = hip_status(hipEventCreateWithFlags(&s->ready[k], hipEventDisableTiming), "side event")) ||
+                (rc = hip_status(hipEventCreateWithFlags(&s->done[k], hipEventDisableTiming), "side event")))
+                return rc;          // the partly built context is kept out of g_side (leaked, error path)
+        }
+        g_side[dev] = s;
+    }
+    *out = g_side[dev];
+    return RFVR_OK;
+}
+
 int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_sdf, const float* g_grad,
                  const float* g_refl, uint32_t flags, float* g_params, void* reserve, size_t reserve_bytes_,
                  void* ws, size_t ws_bytes, hipStream_t st) {
@@ -1451,6 +1493,15 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                             keep ? reserve_bytes(l, n) : 0)))
         return rc;
     const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
+    // the training pair's weight gradients run on the side stream
+    SideStream* side = nullptr;
+    std::unique_lock<std::mutex> side_lock;
+    if (keep) {
+        if ((rc = side_stream(&side))) return rc;
+        side_lock = std::unique_lock<std::mutex>(side->mu);
+    }
+    const hipStream_t wst = side ? side->ss : st;
+    const Cx cxw{wst, cx.mm}, cx32w{wst, MM_FP32};
     const float* P = net->params;
     float* GP = g_params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
@@ -1570,19 +1621,30 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
             const bool kept = keep && i < l.L - 1;
             const float* Zdb = kept ? reserve_s(reserve, l, n, i) + c0 * l.W : Zdb_c;
             const int fin = i == 0 ? l.in0 : l.W, finp = i == 0 ? l.in0p : l.W;
-            if (i == 0) {
-                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32, bpart);
-                wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
-                              part + (size_t)kWgSplits * l.W * finp, cx32);
-            } else {
-                wgrad<PRO_ID>(Zb, l.W, l.W, H[i - 1], nullptr, l.W, finp, m, beta, part, cx, bpart);
-                wgrad<PRO_ID>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta,
-                              part + (size_t)kWgSplits * l.W * finp, cx);
+            if (side) {
+                // everything up to Zbar_i is enqueued on st
+                if ((rc = hip_status(hipEventRecord(side->ready[i], st), "side event record")) ||
+                    (rc = hip_status(hipStreamWaitEvent(wst, side->ready[i], 0), "side event wait")))
+                    return rc;
             }
-            wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, st, kWgSplits, kept ? half : 1.0f);
-            hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, bpart, kWgSplits, l.W, 1.0f,
+            if (i == 0) {
+                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32w, bpart);
+                wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
+                              part + (size_t)kWgSplits * l.W * finp, cx32w);
+            } else {
+                wgrad<PRO_ID>(Zb, l.W, l.W, H[i - 1], nullptr, l.W, finp, m, beta, part, cxw, bpart);
+                wgrad<PRO_ID>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta,
+                              part + (size_t)kWgSplits * l.W * finp, cxw);
+            }
+            wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, wst, kWgSplits, kept ? half : 1.0f);
+            hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, wst, bpart, kWgSplits, l.W, 1.0f,
                                GP + l.ob[i], acc);
+            if (side && (rc = hip_status(hipEventRecord(side->done[i], wst), "side event record"))) return rc;
             if (i > 0 && keep) {
+                // the buffer this writes held Zbar_{i+1}, read by that layer's weight gradients
+                if (side && i + 1 < l.L && (rc = hip_status(hipStreamWaitEvent(st, side->done[i + 1], 0),
+                                                            "side event wait")))
+                    return rc;
                 // Zbar_{i-1} from Hbar_{i-1} = Zbar_i W_i and Hdotbar_{i-1} = half S_{i-1} / sp'(Z_{i-1})
                 GemmArgs a = ga(Zb, l.W, w.WT[i], l.W, nullptr, Zb_n, l.W, m, l.W, l.W, beta, H[i - 1], l.W);
                 a.C2 = Hd[i - 1];
@@ -1597,6 +1659,9 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                 t = Zdb_c; Zdb_c = Zdb_n; Zdb_n = t;
             }
         }
+        // join: the next pass reuses the encoding, tangents and partials, and the
+        // caller reads the gradient on st
+        if (side && (rc = hip_status(hipStreamWaitEvent(st, side->done[0], 0), "side event wait"))) return rc;
         if ((rc = hip_status(hipGetLastError(), "mlp backward"))) return rc;
     }
     return RFVR_OK;

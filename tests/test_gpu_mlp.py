@@ -187,3 +187,29 @@ def test_mlp_backward_chunked_sparse_upstream(dev):
     e0, e = rel_rms(gp0, ref), rel_rms(gp, ref)
     print(f"plain {e0:.2e}, training pair {e:.2e}")
     assert e0 <= 1e-4 and e <= 1e-4
+
+
+def test_mlp_training_backward_is_bitwise_reproducible(dev):
+    """The training backward runs its weight-gradient products on a second
+    stream beside the adjoint chain: the gradient is the same bit for bit over
+    repeated calls, and equals the plain backward's to rounding (2^20 + 777
+    points, two passes)."""
+    _say("mlp training backward determinism")
+    R = _R()
+    spec = MLPSpec()
+    p = _params(spec, 21)
+    n = PASS + 777
+    x = _pts(n, spec, 22)
+    rng = np.random.default_rng(23)
+    t = lambda a: torch.from_numpy(a.astype(np.float32)).to(dev)
+    gf, gg, gaa = t(rng.normal(size=n)), t(rng.normal(size=(n, 3))), t(rng.normal(size=n))
+    net = _net(R, spec, p, dev)
+    res = R.mlp_reserve(net, n, dev)
+    R.mlp_forward(net, t(x), reserve=res)
+    runs = [R.mlp_backward(net, t(x), gf, gg, gaa, reserve=res) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert all(torch.equal(runs[0], r) for r in runs[1:])
+    gp0 = R.mlp_backward(net, t(x), gf, gg, gaa)
+    e = rel_rms(runs[0].cpu().numpy(), gp0.cpu().numpy())
+    print(f"training vs plain backward {e:.2e}")
+    assert e <= 1e-5
