@@ -1493,10 +1493,12 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                             keep ? reserve_bytes(l, n) : 0)))
         return rc;
     const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
-    // the training pair's weight gradients run on the side stream
+    // the training pair's weight gradients run on the side stream when the
+    // products are bound by the matrix cores (FP32); the BF16 forms are bound by
+    // HBM and gain nothing measurable from it
     SideStream* side = nullptr;
     std::unique_lock<std::mutex> side_lock;
-    if (keep) {
+    if (keep && cx.mm == MM_FP32) {
         if ((rc = side_stream(&side))) return rc;
         side_lock = std::unique_lock<std::mutex>(side->mu);
     }
