@@ -311,7 +311,8 @@ def fit_prior(net, scene, centre, half, steps, dev, lr=1e-3, n_pool=1 << 20, bat
 
 
 def proposal_study(args, dev):
-    """Torus-behind-slab scene: full-space training (2^20 grid points) against
+    """Torus-behind-slab scene (or, with --study-scene box, the 8 x 6 x 4 cm
+    box): full-space training (2^20 grid points) against
     proposal-sampled training (n_imp importance + n_uni uniform depths per ray)
     and the untrained control (n_imp + n_uni stratified uniform depths), from
     the same initial network.  Every run is evaluated by the full-space render
@@ -333,11 +334,27 @@ def proposal_study(args, dev):
     from paper_2605_29097_amd.train import ProposalConfig, ProposalTrainer, StepConfig, Trainer
     from synth import MLPSpec, Slab, Torus, Union, mlp_init
     flags = R.SPEC_CLAMP | (R.WEIGHT_SEGMENT if args.study_weight == "segment" else 0)
-    cfg = StepConfig(cube_centre=(0.0, 0.0, 0.28), learn_s=args.study_learn_s, s=args.study_s,
+    from synth import Box
+    box = args.study_scene == "box"
+    # the scene, the coarse version of it the prior is fitted to, and its parts
+    # for the Chamfer distances
+    if box:
+        centre = (0.0, 0.0, 0.30)
+        truth = Union([Box((0.0, 0.0, 0.30), (0.04, 0.03, 0.02), 0.8)])
+        prior_scene = Union([Box((0.003, -0.002, 0.302), (0.043, 0.032, 0.022), 0.8)])
+        part_names = ("box",)
+    else:
+        centre = (0.0, 0.0, 0.28)
+        truth = Union([Slab(0.20, 0.005, 0.1), Torus((0.0, 0.0, 0.30), 0.04, 0.01, 0.8)])
+        prior_scene = Union([Slab(0.203, 0.007, 0.1), Torus((0.003, -0.002, 0.303), 0.043, 0.013, 0.8)])
+        part_names = ("slab", "torus")
+    cfg = StepConfig(cube_centre=centre, learn_s=args.study_learn_s, s=args.study_s,
                      render_flags=flags, judge_nz=args.study_judge_nz, amp0=args.study_amp0)
     spec = MLPSpec(centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
     if args.study_target:
         target_name = args.study_target
+    elif box:
+        target_name = "box_target.npz"
     else:
         target_name = "torus_target.npz" if cfg.s == 64.0 else f"torus_target_s{int(cfg.s)}.npz"
     data = np.load(os.path.join(ROOT, "tests", "golden", target_name))      # rendered by the oracle
@@ -346,20 +363,19 @@ def proposal_study(args, dev):
     p0 = torch.from_numpy(mlp_init(spec, cfg.seed)).to(dev)
     prior_rms = None
     if args.study_prior:
-        prior = Union([Slab(0.203, 0.007, 0.1), Torus((0.003, -0.002, 0.303), 0.043, 0.013, 0.8)])
         net = R.MLP(params=p0.clone(), centre=cfg.cube_centre, half_size=cfg.cube_side / 2)
-        prior_rms = fit_prior(net, prior, cfg.cube_centre, cfg.cube_side / 2, args.study_prior, dev)
+        prior_rms = fit_prior(net, prior_scene, cfg.cube_centre, cfg.cube_side / 2, args.study_prior, dev)
         p0 = net.params.detach().clone()
         print(f"[study] prior fit: {args.study_prior} steps, f rms {prior_rms * 1e3:.3f} mm", file=sys.stderr,
               flush=True)
     # Chamfer distances on a 256^3 grid (App. C metrics): the true scene's
-    # surface points, each assigned to the primitive it lies on
-    truth = Union([Slab(0.20, 0.005, 0.1), Torus((0.0, 0.0, 0.30), 0.04, 0.01, 0.8)])
+    # surface points, each assigned to the primitive it lies nearest to
     n_grid = args.study_grid
 
     def split(pts):
-        d = [np.abs(p.eval(pts)[0]) for p in truth.parts]
-        return {"slab": pts[d[0] <= d[1]], "torus": pts[d[1] < d[0]]}
+        d = np.stack([np.abs(p.eval(pts)[0]) for p in truth.parts])
+        near = np.argmin(d, 0)
+        return {name: pts[near == k] for k, name in enumerate(part_names)}
 
     gt = None
     if n_grid:
@@ -375,7 +391,7 @@ def proposal_study(args, dev):
                              cfg.cube_centre, cfg.cube_side / 2)
         rec = split(pts)
         out = {}
-        for k in ("torus", "slab"):
+        for k in part_names:
             if len(rec[k]) == 0:
                 out[k] = None
                 continue
@@ -456,8 +472,10 @@ def proposal_study(args, dev):
                       "loss_on_grid": args.study_loss_grid, "target_dilation_bins": args.study_dilate,
                       "full_every": args.study_full_every, "amp0": args.study_amp0,
                       "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
-                      "scene": "torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
-                               "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise",
+                      "scene": ("box 8x6x4 cm (a=0.8) at 0.30 m; 32x32 aperture, 128 freqs, 20 cm cube at 0.30 m; "
+                                "10 dB noise") if box else
+                               ("torus R=4 cm r=1 cm at 0.30 m behind a 1 cm slab (a=0.1) at 0.20 m; "
+                                "32x32 aperture, 128 freqs, 20 cm cube at 0.28 m; 10 dB noise"),
                       "runs": out}))
 
 
@@ -673,6 +691,8 @@ def main():
                     help="grid side of the Chamfer surface extraction (0: no Chamfer)")
     ap.add_argument("--study-loss-grid", action="store_true",
                     help="sampled runs take the heatmap loss on the full-space grid (render from their samples)")
+    ap.add_argument("--study-scene", choices=["torus_slab", "box"], default="torus_slab",
+                    help="torus behind a slab in a cube at 0.28 m, or the 8 x 6 x 4 cm box in a cube at 0.30 m")
     ap.add_argument("--study-full-every", type=int, default=0,
                     help="every this many steps the proposal run takes a full-space step (0: never)")
     ap.add_argument("--study-amp0", type=float, default=1.0, help="initial amplitude A' of every run")
