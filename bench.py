@@ -18,6 +18,7 @@ gradient and the network gradient each step; that is not built).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -521,6 +522,56 @@ def naive_compare(args, dev):
     print(json.dumps(out))
 
 
+def network_precisions(args, dev):
+    """Network call times at the 2^20-point workload (8 x 256 trunk, 2 x 64 head,
+    6 octaves, the bench's points and parameters) for every matrix-operand form:
+    the forward (f, grad_x f, a), the plain backward (recomputes the forward
+    products), and the training pair (forward keeping the reserve, backward
+    reading it), with upstream gradients of the size the render adjoint gives.
+    HIP events around `--steps` calls of each after one warm-up call.  Prints
+    one JSON line."""
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from paper_2605_29097_amd.train import StepConfig, Trainer
+    cfg = StepConfig()
+    params, target = make_inputs(cfg, dev)
+    tr = Trainer(cfg, params, target, device=dev)
+    xyz, _, _ = R.sample_points(cfg.cube_centre, cfg.cube_side / 2, (0.0, 0.0, 1.0), cfg.lines[0], cfg.lines[1],
+                                cfg.n_z, device=dev)
+    x = xyz.view(-1, 3)
+    n = x.shape[0]
+    gen = torch.Generator(device=dev).manual_seed(1)
+    gf = torch.randn(n, device=dev, generator=gen)
+    gg = torch.randn(n, 3, device=dev, generator=gen)
+    gaa = torch.randn(n, device=dev, generator=gen)
+    reps = max(1, min(args.steps, 10))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return round(e0.elapsed_time(e1) / reps, 2)
+
+    out = {"study": "network_precisions", "points": n, "calls": reps, "ms": {}}
+    for pname in ("fp32", "bf16", "bf16x3", "f16"):
+        net = dataclasses.replace(tr.net, precision=getattr(R, "PREC_" + pname.upper()))
+        res = R.mlp_reserve(net, n, dev)
+        row = {"forward": timed(lambda: R.mlp_forward(net, x)),
+               "backward_plain": timed(lambda: R.mlp_backward(net, x, gf, gg, gaa)),
+               "forward_train": timed(lambda: R.mlp_forward(net, x, reserve=res)),
+               "backward_train": timed(lambda: R.mlp_backward(net, x, gf, gg, gaa, reserve=res))}
+        out["ms"][pname] = row
+        print(f"[networks] {pname}: {row}", file=sys.stderr, flush=True)
+        del res
+        torch.cuda.empty_cache()
+    print(json.dumps(out))
+
+
 def batched8_study(args, dev):
     """The eight-scene workload: apertures of 32^2 .. 64^2 antennas at 2 mm
     (19,292 in all), 256 frequencies 77-81 GHz, 2^22 points per scene (128 x 128
@@ -562,7 +613,7 @@ def batched8_study(args, dev):
     out = {"study": "eight_scene_batched", "terms_per_pass": terms, "points": sum(x.numel() // 3 for x in xyzs),
            "networks": {}}
     gen = torch.Generator(device=dev).manual_seed(0)
-    for pname, prec in (("bf16x3", R.PREC_BF16X3), ("bf16", R.PREC_BF16)):
+    for pname, prec in (("bf16x3", R.PREC_BF16X3), ("f16", R.PREC_F16), ("bf16", R.PREC_BF16)):
         nets = []
         for k, g in enumerate(geo):
             spec = MLPSpec(n_layers=m["n_layers"], width=m["width"], pe_octaves=m["pe_octaves"],
@@ -616,7 +667,7 @@ def batched8_train(args, dev):
     c = config("batched8")
     m = c["mlp"]
     out = {"study": "eight_scene_training_step", "runs": {}}
-    for pname, prec in (("bf16x3", R.PREC_BF16X3), ("bf16", R.PREC_BF16)):
+    for pname, prec in (("bf16x3", R.PREC_BF16X3), ("f16", R.PREC_F16), ("bf16", R.PREC_BF16)):
         trainers, shared = [], None
         for k in range(len(c["ap_sides"])):
             g = batched8_scene(k)
@@ -705,6 +756,8 @@ def main():
     ap.add_argument("--naive-compare", action="store_true",
                     help="forward time of per-antenna sampling vs lensless sampling")
     ap.add_argument("--naive-apertures", type=int, nargs="+", default=[4, 8, 16])
+    ap.add_argument("--network-precisions", action="store_true",
+                    help="time the network calls at 2^20 points for every matrix-operand form")
     ap.add_argument("--batched8", action="store_true",
                     help="time the batched and grouped calls on the eight-scene workload")
     ap.add_argument("--batched8-train", action="store_true",
@@ -733,6 +786,9 @@ def main():
         return
     if args.naive_compare:
         naive_compare(args, dev)
+        return
+    if args.network_precisions:
+        network_precisions(args, dev)
         return
     if args.batched8:
         batched8_study(args, dev)

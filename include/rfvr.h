@@ -334,6 +334,16 @@ int rfvr_sample_points(const rfvr_sample_desc* d, float* xyz, float* u, float* r
 #define RFVR_PREC_BF16X3 2       /* BF16 MFMA on split operands, x = big + small with
                                     big = bf16(x), small = bf16(x - big); products
                                     big*big + big*small + small*big, FP32 accumulation */
+#define RFVR_PREC_F16 3          /* FP32 accumulation.  Forward products (trunk layers,
+                                    head, the grad_x f sweep; also where the plain backward
+                                    recomputes them): FP16 MFMA, the weights rounded once,
+                                    the per-point operand split as big + small in FP16,
+                                    products big*w + small*w.  Backward products (tangent,
+                                    adjoints, weight gradients), whose values scale with
+                                    the upstream gradients and exceed FP16's range: BF16
+                                    operands, one product */
+/* In every 16-bit form the layer that reads the positional encoding keeps FP32
+ * operands. */
 typedef struct rfvr_mlp {
     int32_t      n_layers;       /* 1..16 */
     int32_t      width;          /* multiple of 64, <= 512 */

@@ -29,6 +29,7 @@ namespace rfvr {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Eight FP32 operand values (two float4 along k) rounded to BF16 (RNE) for one
 // v_mfma_f32_16x16x32_bf16.  A and B fragments use the same slot <-> k
@@ -38,6 +39,24 @@ __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi) {
     r[0] = (__bf16)lo[0]; r[1] = (__bf16)lo[1]; r[2] = (__bf16)lo[2]; r[3] = (__bf16)lo[3];
     r[4] = (__bf16)hi[0]; r[5] = (__bf16)hi[1]; r[6] = (__bf16)hi[2]; r[7] = (__bf16)hi[3];
     return r;
+}
+
+// the same for one v_mfma_f32_16x16x32_f16 (FP16, RNE)
+__device__ __forceinline__ f16x8 to_f16x8(floatx4 lo, floatx4 hi) {
+    f16x8 r;
+    r[0] = (_Float16)lo[0]; r[1] = (_Float16)lo[1]; r[2] = (_Float16)lo[2]; r[3] = (_Float16)lo[3];
+    r[4] = (_Float16)hi[0]; r[5] = (_Float16)hi[1]; r[6] = (_Float16)hi[2]; r[7] = (_Float16)hi[3];
+    return r;
+}
+
+// x = big + small with big = f16(x), small = f16(x - big): 22 significant bits
+__device__ __forceinline__ void split_f16x8(floatx4 lo, floatx4 hi, f16x8& big, f16x8& small) {
+    big = to_f16x8(lo, hi);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        small[e] = (_Float16)(lo[e] - (float)big[e]);
+        small[4 + e] = (_Float16)(hi[e] - (float)big[4 + e]);
+    }
 }
 
 // x = big + small with big = bf16(x), small = bf16(x - big): 16 significant bits
@@ -50,9 +69,17 @@ __device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big
     }
 }
 
-// operand precision of a network GEMM: FP32 MFMA, BF16 MFMA, or BF16 MFMA on
-// split operands (a b ~ a_big b_big + a_big b_small + a_small b_big)
-enum { MM_FP32 = 0, MM_BF16 = 1, MM_BF16X3 = 3 };
+// operand precision of a network GEMM: FP32 MFMA, BF16 MFMA, BF16 MFMA on split
+// operands (a b ~ a_big b_big + a_big b_small + a_small b_big), or FP16 MFMA
+// with the weights rounded once and the per-point operand split in two
+// (a b ~ a_big b + a_small b, two products).  The per-point operand's rounding
+// differs from point to point, and the opacity of neighbouring samples takes
+// differences of their SDF values, which magnify it; the weights' rounding is
+// a fixed, smooth change of the network.  FP16 serves the forward products only
+// (its 5-bit exponent cannot hold the backward's adjoints, which scale with the
+// upstream gradients); in the dual forward GEMM, MM_F16 means this form for
+// the primal and BF16 for the tangent.
+enum { MM_FP32 = 0, MM_BF16 = 1, MM_F16 = 2, MM_BF16X3 = 3 };
 
 // operand prologues: identity, relu, or SEED: A[p][k] = H -> sp'(Z) colv[k] (the
 // normal sweep's seed from the top layer's activation, formed while the tile is
@@ -226,6 +253,27 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
                 for (int b = 0; b < TM; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[b], af[a], acc[a][b], 0, 0, 0);
+        } else if constexpr (MM == MM_F16) {
+            // one point row's split at a time (fewer live registers)
+            f16x8 bf[TM];
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const int row = wm * (BM / WM) + b * 16 + li;
+                bf[b] = to_f16x8(*reinterpret_cast<const floatx4*>(&B_[off(row, lg)]),
+                                 *reinterpret_cast<const floatx4*>(&B_[off(row, lg + 4)]));
+            }
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                const int row = wp * (BP / WP) + a * 16 + li;
+                f16x8 ab, as;
+                split_f16x8(*reinterpret_cast<const floatx4*>(&A_[off(row, lg)]),
+                            *reinterpret_cast<const floatx4*>(&A_[off(row, lg + 4)]), ab, as);
+#pragma unroll
+                for (int b = 0; b < TM; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bf[b], as, acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bf[b], ab, acc[a][b], 0, 0, 0);
+                }
+            }
         } else if constexpr (MM == MM_BF16X3) {
             bf16x8 ab[TP], as[TP], bb[TM], bs[TM];
 #pragma unroll
@@ -547,6 +595,34 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_gemm_dual(DualArgs
                             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
                             acd[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af2[a][s], bf[b][s], acd[a][b], 0, 0, 0);
                         }
+            }
+        } else if constexpr (MM == MM_F16) {
+            // primal on FP16 operands (split per-point operand), tangent on BF16
+            // (the tangent scales with the upstream gradient): the staged
+            // weights are rounded both ways
+            f16x8 bh[TM];
+            bf16x8 bb[TM];
+#pragma unroll
+            for (int b = 0; b < TM; ++b) {
+                const float* r = &sB[(wm * (BM / 2) + b * 16 + li) * LW + lg * 4];
+                const floatx4 lo = *reinterpret_cast<const floatx4*>(r), hi = *reinterpret_cast<const floatx4*>(r + 16);
+                bh[b] = to_f16x8(lo, hi);
+                bb[b] = to_bf16x8(lo, hi);
+            }
+#pragma unroll
+            for (int a = 0; a < TP; ++a) {
+                const int off = (wp * (BP / WP) + a * 16 + li) * LW + lg * 4;
+                f16x8 ah, al;
+                split_f16x8(*reinterpret_cast<const floatx4*>(&sA[off]),
+                            *reinterpret_cast<const floatx4*>(&sA[off + 16]), ah, al);
+                const bf16x8 ad = to_bf16x8(*reinterpret_cast<const floatx4*>(&sA2[off]),
+                                            *reinterpret_cast<const floatx4*>(&sA2[off + 16]));
+#pragma unroll
+                for (int b = 0; b < TM; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[b], acc[a][b], 0, 0, 0);
+                    acd[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ad, bb[b], acd[a][b], 0, 0, 0);
+                }
             }
         } else {
             bf16x8 bb[TM], bs[TM];
@@ -1091,7 +1167,8 @@ int check_net(const rfvr_mlp* n) {
         set_error("softplus_beta and half_size must be > 0");
         return RFVR_E_INVALID;
     }
-    if (n->precision != RFVR_PREC_FP32 && n->precision != RFVR_PREC_BF16 && n->precision != RFVR_PREC_BF16X3) {
+    if (n->precision != RFVR_PREC_FP32 && n->precision != RFVR_PREC_BF16 && n->precision != RFVR_PREC_BF16X3 &&
+        n->precision != RFVR_PREC_F16) {
         set_error("unknown precision %d", n->precision);
         return RFVR_E_INVALID;
     }
@@ -1180,12 +1257,20 @@ hipError_t prep_weights(const Layout& l, const float* P, const Weights& w, hipSt
     return hipGetLastError();
 }
 
-int mm_of(int precision) {
-    return precision == RFVR_PREC_BF16 ? MM_BF16 : (precision == RFVR_PREC_BF16X3 ? MM_BF16X3 : MM_FP32);
+// operand form of the forward products (layers, head, the grad_x f sweep) and
+// of the backward's products (tangent, adjoints, weight gradients)
+int mm_fwd(int precision) {
+    switch (precision) {
+    case RFVR_PREC_BF16: return MM_BF16;
+    case RFVR_PREC_BF16X3: return MM_BF16X3;
+    case RFVR_PREC_F16: return MM_F16;
+    default: return MM_FP32;
+    }
 }
+int mm_bwd(int precision) { return precision == RFVR_PREC_F16 ? MM_BF16 : mm_fwd(precision); }
 
 // launch context of the network passes: stream and matrix-operand precision
-// (bf: BF16 operands, FP32 accumulation; layers reading the encoding stay FP32)
+// (16-bit operands, FP32 accumulation; layers reading the encoding stay FP32)
 struct Cx {
     hipStream_t st;
     int mm;        // MM_*
@@ -1208,6 +1293,7 @@ template <int PRO, int EPI>
 void gemm(const GemmArgs& a, const Cx& cx) {
     if (cx.mm == MM_BF16) gemm_launch<PRO, EPI, MM_BF16>(a, cx.st);
     else if (cx.mm == MM_BF16X3) gemm_launch<PRO, EPI, MM_BF16X3>(a, cx.st);
+    else if (cx.mm == MM_F16) gemm_launch<PRO, EPI, MM_F16>(a, cx.st);
     else gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
 }
 
@@ -1229,7 +1315,10 @@ void gemm_dual(const DualArgs& a, int mm, hipStream_t st) {
     const dim3 grid((unsigned)(groups * 8 * nmb));
     if (mm == MM_BF16) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16, NW>), grid, dim3(NW * 64), 0, st, a);
     else if (mm == MM_BF16X3) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_BF16X3, NW>), grid, dim3(NW * 64), 0, st, a);
-    else hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_FP32, NW>), grid, dim3(NW * 64), 0, st, a);
+    else if constexpr (EPI2 == EPI2_FWD) {
+        if (mm == MM_F16) hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_F16, NW>), grid, dim3(NW * 64), 0, st, a);
+        else hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_FP32, NW>), grid, dim3(NW * 64), 0, st, a);
+    } else hipLaunchKernelGGL((k_gemm_dual<EPI2, MM_FP32, NW>), grid, dim3(NW * 64), 0, st, a);
 }
 
 DualArgs da(const float* A, const float* A2, long lda, const float* B, long ldb, const float* bias,
@@ -1358,7 +1447,7 @@ int mlp_forward(const rfvr_mlp* net, const float* xyz, long n, float* sdf, float
     if ((rc = check_buffers(ws, ws_bytes, fwd_bytes(l, n, keep), reserve, reserve_bytes_,
                             keep ? reserve_bytes(l, n) : 0)))
         return rc;
-    const Cx cx{st, mm_of(net->precision)};
+    const Cx cx{st, mm_fwd(net->precision)};
     const float* P = net->params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
     const long chunk = n < kChunk ? n : kChunk;
@@ -1492,7 +1581,9 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
     if ((rc = check_buffers(ws, ws_bytes, bwd_bytes(l, n, keep), reserve, reserve_bytes_,
                             keep ? reserve_bytes(l, n) : 0)))
         return rc;
-    const Cx cx{st, mm_of(net->precision)}, cx32{st, MM_FP32};
+    // cxf: the plain backward's recompute of the forward products, in the
+    // forward's operand form; cx: the backward's own products
+    const Cx cx{st, mm_bwd(net->precision)}, cxf{st, mm_fwd(net->precision)}, cx32{st, MM_FP32};
     // the training pair's weight gradients run on the side stream when the
     // products are bound by the matrix cores (FP32); the BF16 forms are bound by
     // HBM and gain nothing measurable from it
@@ -1560,17 +1651,17 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                                    l.W, m, l.W, l.in0p, beta), MM_FP32, st);
             for (int i = 1; i < l.L; ++i)
                 gemm_dual<EPI2_FWD>(da(H[i - 1], Hd[i - 1], l.W, w.Wp[i], l.W, P + l.ob[i], nullptr, nullptr, Z[i],
-                                       H[i], Hd[i], l.W, m, l.W, l.W, beta), cx.mm, st);
+                                       H[i], Hd[i], l.W, m, l.W, l.W, beta), cxf.mm, st);
         }
         float* Ht = H[l.L - 1];
         // head forward (the training backward reads it from the reserve)
         float* Yh[4];
         for (int h = 0; h < l.HL; ++h) Yh[h] = keep ? reserve_y(reserve, l, n, h) + c0 * l.HW : Yw[h];
         if (!keep) {
-            gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cx);
+            gemm<PRO_ID, EPI_BIAS>(ga(Ht, l.W, w.Whp[0], l.W, P + l.obh[0], Yh[0], l.HW, m, l.HW, l.W, beta), cxf);
             for (int h = 1; h < l.HL; ++h)
                 gemm<PRO_RELU, EPI_BIAS>(ga(Yh[h - 1], l.HW, w.Whp[h], l.HW, P + l.obh[h], Yh[h], l.HW, m, l.HW,
-                                           l.HW, beta), cx);
+                                           l.HW, beta), cxf);
         }
         // head output: ybar3, Ybar_{HL-1}
         hipLaunchKernelGGL(k_head_out_bwd, dim3(blocks(m * kRowLanes)), dim3(256), 0, st, m, Yh[l.HL - 1], (long)l.HW,

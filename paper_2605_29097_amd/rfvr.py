@@ -26,7 +26,7 @@ ACCUMULATE = 0x8
 TERMS_DIRECT = 0x10      # per-frequency evaluation of the term sums
 WEIGHT_SEGMENT = 0x20    # render: exact segment integral of T^2 rho, placed at the segment midpoint
 SAMPLE_GRID, SAMPLE_STRATIFIED = 0, 1
-PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_BF16X3, PREC_F16 = 0, 1, 2, 3
 # size limits of one call (RFVR_MAX_* in rfvr.h)
 MAX_POINTS, MAX_RAYS, MAX_MEAS, MAX_RAY_SAMPLES = (1 << 31) - 1, 1 << 25, 1 << 20, 1024
 ERRORS = {-1: "RFVR_E_INVALID", -2: "RFVR_E_WORKSPACE", -3: "RFVR_E_UNSUPPORTED", -4: "RFVR_E_HIP"}

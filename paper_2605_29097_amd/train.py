@@ -52,7 +52,7 @@ class StepConfig:
     judge_nz: Optional[int] = None         # depths of the full-space judge render (None: n_z)
     bank_patch: Optional[tuple] = None     # (px, py) antennas per Signal Tracing Bank patch
     learn_s: bool = False                  # train log s with the head's learning rate
-    precision: int = R.PREC_FP32           # network matrix operands (R.PREC_FP32 / BF16 / BF16X3)
+    precision: int = R.PREC_FP32           # network matrix operands (R.PREC_FP32 / BF16 / BF16X3 / F16)
     keep_activations: bool = True          # network training pair: the backward reads the
                                            # forward's layer activations from a reserve
     mask_tau: Optional[tuple] = None       # (tau_hi, tau_lo): dynamic loss masking on
