@@ -69,6 +69,37 @@ __device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big
     }
 }
 
+// BF16 storage of the single-rounded BF16 backward's arrays (tangents Hdot and
+// adjoints Zbar): every product that reads them rounds them to BF16 (RNE)
+// anyway, so they are stored rounded, as raw 16-bit words in buffers sized for
+// FP32, and widened where they are used (a main loop keeps the raw words of its
+// prefetch and widens them at the LDS store, so the prefetch stays in flight)
+__device__ __forceinline__ uint2 ld_raw_bf16x4(const float* base, long i) {
+    return *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + i);
+}
+__device__ __forceinline__ float4 widen_bf16x4(uint2 r) {
+    return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                       __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+}
+__device__ __forceinline__ float4 ld_bf16x4(const float* base, long i) { return widen_bf16x4(ld_raw_bf16x4(base, i)); }
+__device__ __forceinline__ float ld_bf16(const float* base, long i) {
+    return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(base)[i] << 16);
+}
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ __forceinline__ void st_bf16x4(float* base, long i, floatx4 v) {
+    uint2 r;
+    r.x = bf16_bits(v[0]) | (bf16_bits(v[1]) << 16);
+    r.y = bf16_bits(v[2]) | (bf16_bits(v[3]) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(base) + i) = r;
+}
+__device__ __forceinline__ void st_bf16(float* base, long i, float v) {
+    reinterpret_cast<uint16_t*>(base)[i] = (uint16_t)bf16_bits(v);
+}
+// which operands of a GEMM are held in BF16 storage
+enum { ST_A = 1, ST_B = 2, ST_C2 = 4, ST_Y = 8 };
+
 // operand precision of a network GEMM: FP32 MFMA, BF16 MFMA, BF16 MFMA on split
 // operands (a b ~ a_big b_big + a_big b_small + a_small b_big), or FP16 MFMA
 // with the weights rounded once and the per-point operand split in two
@@ -152,7 +183,7 @@ struct GemmArgs {
     float beta;
 };
 
-template <int PRO, int EPI, int BM, int MM>
+template <int PRO, int EPI, int BM, int MM, int ST = 0>
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     // padded LDS rows (BK + 4 floats): the MFMA fragment reads (16 rows, one
     // float4 column) are free of bank conflicts.  Variants measured slower on
@@ -189,15 +220,21 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < TM; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    float4 ra[NA], rb[NB];
+    float4 ra[(ST & ST_A) ? 1 : NA], rb[NB];
+    uint2 ra16[(ST & ST_A) ? NA : 1];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * 256;
             const int row = e / RPF, c4 = (e % RPF) * 4;
             const long p = p0 + row;
-            ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (p < g.P) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
+            if constexpr ((ST & ST_A) != 0) {
+                ra16[i] = make_uint2(0u, 0u);
+                if (p < g.P) ra16[i] = ld_raw_bf16x4(g.A, p * g.lda + k0 + c4);
+            } else {
+                ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (p < g.P) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + k0 + c4);
+            }
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -213,7 +250,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int e = tid + i * 256;
-            float4 v = ra[i];
+            float4 v;
+            if constexpr ((ST & ST_A) != 0) v = widen_bf16x4(ra16[i]);
+            else v = ra[i];
             if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
@@ -362,8 +401,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                 for (int b = 0; b < TM; ++b) {
                     const int mb = m0 + wm * (BM / WM) + b * 16 + lg * 4;
 #pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        cl[c][b] = *reinterpret_cast<const floatx4*>(src[c] + pr * g.ldc + mb);
+                    for (int c = 0; c < NC; ++c) {
+                        if ((ST & ST_C2) != 0 && c == 1) {
+                            const float4 t = ld_bf16x4(src[c], pr * g.ldc + mb);
+                            cl[c][b] = floatx4{t.x, t.y, t.z, t.w};
+                        } else {
+                            cl[c][b] = *reinterpret_cast<const floatx4*>(src[c] + pr * g.ldc + mb);
+                        }
+                    }
                 }
             }
             float rv = 0.0f;
@@ -375,7 +420,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) cl[c][b][v] = src[c][pr * g.ldc + min(mb + v, g.M - 1)];
+                        for (int v = 0; v < 4; ++v) {
+                            const long ci = pr * g.ldc + min(mb + v, g.M - 1);
+                            cl[c][b][v] = ((ST & ST_C2) != 0 && c == 1) ? ld_bf16(src[c], ci) : src[c][ci];
+                        }
                 }
                 floatx4 y = acc[a][b], y2 = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -403,14 +451,17 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
                     }
                 }
                 constexpr bool TWO = (EPI == EPI_TOPADJ);
+                constexpr bool YB = (ST & ST_Y) != 0;
                 if constexpr (!GUARD) {
-                    *reinterpret_cast<floatx4*>(g.Y + p * g.ldy + mb) = y;
+                    if constexpr (YB) st_bf16x4(g.Y, p * g.ldy + mb, y);
+                    else *reinterpret_cast<floatx4*>(g.Y + p * g.ldy + mb) = y;
                     if constexpr (TWO) *reinterpret_cast<floatx4*>(g.Y2 + p * g.ldy + mb) = y2;
                 } else if (pin) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         if (mb + v >= g.M) continue;
-                        g.Y[p * g.ldy + mb + v] = y[v];
+                        if constexpr (YB) st_bf16(g.Y, p * g.ldy + mb + v, y[v]);
+                        else g.Y[p * g.ldy + mb + v] = y[v];
                         if constexpr (TWO) g.Y2[p * g.ldy + mb + v] = y2[v];
                     }
                 }
@@ -706,7 +757,7 @@ struct WgArgs {
     float beta;
 };
 
-template <int PRO, bool BIAS, int MM>
+template <int PRO, bool BIAS, int MM, int ST = 0>
 __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
     constexpr int BM = 128, BN = 128, BK = 32, LW = 128 + 4;
     __shared__ float sA[BK * LW];
@@ -735,21 +786,31 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
         for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;                         // column sum of A (thread tid < 128 -> column tid)
 
-    float4 ra[4], rb[4];
+    // raw 16-bit words of a BF16-stored operand's prefetch, widened at the LDS store
+    float4 ra[(ST & ST_A) ? 1 : 4], rb[(ST & ST_B) ? 1 : 4];
+    uint2 ra16[(ST & ST_A) ? 4 : 1], rb16[(ST & ST_B) ? 4 : 1];
     auto load = [&](long q0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + i * 256;
             const int row = e >> 5, c4 = (e & 31) * 4;
             const long p = q0 + row;
-            ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            rb[i] = ra[i];
-            if (p < pe) {
-                if (m0 + c4 < g.M) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c4);
-                if (n0 + c4 < g.Kout) {
-                    const long off = p * g.ldb + n0 + c4;
-                    rb[i] = *reinterpret_cast<const float4*>(g.B + off);
+            if constexpr (ST == 0) {
+                ra[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                rb[i] = ra[i];
+                if (p < pe) {
+                    if (m0 + c4 < g.M) ra[i] = *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c4);
+                    if (n0 + c4 < g.Kout) {
+                        const long off = p * g.ldb + n0 + c4;
+                        rb[i] = *reinterpret_cast<const float4*>(g.B + off);
+                    }
                 }
+            } else {
+                const bool la = p < pe && m0 + c4 < g.M, lb = p < pe && n0 + c4 < g.Kout;
+                if constexpr ((ST & ST_A) != 0) ra16[i] = la ? ld_raw_bf16x4(g.A, p * g.lda + m0 + c4) : make_uint2(0u, 0u);
+                else ra[i] = la ? *reinterpret_cast<const float4*>(g.A + p * g.lda + m0 + c4) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if constexpr ((ST & ST_B) != 0) rb16[i] = lb ? ld_raw_bf16x4(g.B, p * g.ldb + n0 + c4) : make_uint2(0u, 0u);
+                else rb[i] = lb ? *reinterpret_cast<const float4*>(g.B + p * g.ldb + n0 + c4) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         }
     };
@@ -760,12 +821,16 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
             const int e = tid + i * 256;
             const int row = e >> 5, c4 = (e & 31) * 4;
             const bool live = q0 + row < pe;
-            float4 v = rb[i];
+            float4 v, u;
+            if constexpr ((ST & ST_B) != 0) v = widen_bf16x4(rb16[i]);
+            else v = rb[i];
+            if constexpr ((ST & ST_A) != 0) u = widen_bf16x4(ra16[i]);
+            else u = ra[i];
             if constexpr (PRO == PRO_RELU) {
                 v.x = fmaxf(v.x, 0.0f); v.y = fmaxf(v.y, 0.0f); v.z = fmaxf(v.z, 0.0f); v.w = fmaxf(v.w, 0.0f);
             }
             if (!live) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            *reinterpret_cast<float4*>(&sA[row * LW + c4]) = ra[i];
+            *reinterpret_cast<float4*>(&sA[row * LW + c4]) = u;
             *reinterpret_cast<float4*>(&sB[row * LW + c4]) = v;
         }
         __syncthreads();
@@ -1276,15 +1341,15 @@ struct Cx {
     int mm;        // MM_*
 };
 
-template <int PRO, int EPI, int MM>
+template <int PRO, int EPI, int MM, int ST = 0>
 void gemm_launch(const GemmArgs& a, hipStream_t st) {
     const long tiles = (a.P + 127) / 128;
     const long groups = (tiles + 7) / 8;                 // 8 point tiles per XCD group
     if (a.M <= 64) {
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64, MM>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 64, MM, ST>), dim3((unsigned)(groups * 8)), dim3(256), 0, st, a);
     } else {
         const long nmb = (a.M + 127) / 128;
-        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128, MM>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
+        hipLaunchKernelGGL((k_gemm_nt<PRO, EPI, 128, MM, ST>), dim3((unsigned)(groups * 8 * nmb)), dim3(256), 0,
                            st, a);
     }
 }
@@ -1298,9 +1363,16 @@ void gemm(const GemmArgs& a, const Cx& cx) {
 }
 
 // FP32 GEMM whatever the context (first layer: its operand is the encoding)
-template <int PRO, int EPI>
+template <int PRO, int EPI, int ST = 0>
 void gemm32(const GemmArgs& a, const Cx& cx) {
-    gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
+    gemm_launch<PRO, EPI, MM_FP32, ST>(a, cx.st);
+}
+
+// BF16 GEMM of the single-rounded BF16 backward with the ST_* operands in BF16
+// storage
+template <int PRO, int EPI, int ST>
+void gemm_b16(const GemmArgs& a, const Cx& cx) {
+    gemm_launch<PRO, EPI, MM_BF16, ST>(a, cx.st);
 }
 
 #ifndef RFVR_DUAL_NW
@@ -1339,7 +1411,8 @@ GemmArgs ga(const float* A, long lda, const float* B, long ldb, const float* bia
     return g;
 }
 
-template <int PRO>
+// ST != 0 (BF16 storage of operands): the FP32 and single-rounded BF16 forms
+template <int PRO, int ST = 0>
 void wgrad(const float* A, long lda, int M, const float* B, const float* B2, long ldb, int Kout,
            long P, float beta, float* part, const Cx& cx, float* bpart = nullptr) {
     hipStream_t st = cx.st;
@@ -1351,7 +1424,15 @@ void wgrad(const float* A, long lda, int M, const float* B, const float* B2, lon
     const long tiles = (long)((M + 127) / 128) * ((Kout + 127) / 128);
     const long groups = (kWgSplits + 7) / 8;
     const dim3 grid((unsigned)(groups * 8 * tiles));
-    if (cx.mm == MM_BF16) {
+    if constexpr (ST != 0) {
+        if (cx.mm == MM_BF16) {
+            if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, MM_BF16, ST>), grid, dim3(256), 0, st, g);
+            else hipLaunchKernelGGL((k_gemm_wg<PRO, false, MM_BF16, ST>), grid, dim3(256), 0, st, g);
+        } else {
+            if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, MM_FP32, ST>), grid, dim3(256), 0, st, g);
+            else hipLaunchKernelGGL((k_gemm_wg<PRO, false, MM_FP32, ST>), grid, dim3(256), 0, st, g);
+        }
+    } else if (cx.mm == MM_BF16) {
         if (bpart) hipLaunchKernelGGL((k_gemm_wg<PRO, true, MM_BF16>), grid, dim3(256), 0, st, g);
         else hipLaunchKernelGGL((k_gemm_wg<PRO, false, MM_BF16>), grid, dim3(256), 0, st, g);
     } else if (cx.mm == MM_BF16X3) {
@@ -1595,6 +1676,10 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
     }
     const hipStream_t wst = side ? side->ss : st;
     const Cx cxw{wst, cx.mm}, cx32w{wst, MM_FP32};
+    // single-rounded BF16 products in the training backward: the tangents Hdot
+    // and the adjoints Zbar are stored in BF16 (every product reading them rounds
+    // them so), which cuts the HBM bytes of these HBM-bound products by ~30 %
+    const bool b16 = keep && cx.mm == MM_BF16;
     const float* P = net->params;
     float* GP = g_params;
     const float beta = net->softplus_beta, half = net->half_size, inv_half = 1.0f / net->half_size;
@@ -1640,11 +1725,14 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
         if (keep) {
             // tangent only: Hdot_i = sp'(Z_i) (Hdot_{i-1} W_i^T), sp'(Z_i) from the
             // reserve's H_i
-            gemm32<PRO_ID, EPI_DSPMUL>(ga(X0d, l.in0p, w.Wp[0], l.in0p, nullptr, Hd[0], l.W, m, l.W, l.in0p,
-                                          beta, H[0], l.W), cx);
-            for (int i = 1; i < l.L; ++i)
-                gemm<PRO_ID, EPI_DSPMUL>(ga(Hd[i - 1], l.W, w.Wp[i], l.W, nullptr, Hd[i], l.W, m, l.W, l.W,
-                                            beta, H[i], l.W), cx);
+            const GemmArgs a0 = ga(X0d, l.in0p, w.Wp[0], l.in0p, nullptr, Hd[0], l.W, m, l.W, l.in0p, beta, H[0], l.W);
+            if (b16) gemm32<PRO_ID, EPI_DSPMUL, ST_Y>(a0, cx);
+            else gemm32<PRO_ID, EPI_DSPMUL>(a0, cx);
+            for (int i = 1; i < l.L; ++i) {
+                const GemmArgs a = ga(Hd[i - 1], l.W, w.Wp[i], l.W, nullptr, Hd[i], l.W, m, l.W, l.W, beta, H[i], l.W);
+                if (b16) gemm_b16<PRO_ID, EPI_DSPMUL, ST_A | ST_Y>(a, cx);
+                else gemm<PRO_ID, EPI_DSPMUL>(a, cx);
+            }
         } else {
             // one dual GEMM per layer: (Z_i, H_i) and Hdot_i share W_i
             gemm_dual<EPI2_FWD>(da(X0, X0d, l.in0p, w.Wp[0], l.in0p, P + l.ob[0], nullptr, nullptr, Z[0], H[0], Hd[0],
@@ -1697,7 +1785,8 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
             a.colv = P + l.o_wout;
             a.scale = half;
             a.cpart = tpart;
-            gemm<PRO_ID, EPI_TOPADJ>(a, cx);
+            if (b16) gemm_b16<PRO_ID, EPI_TOPADJ, ST_C2 | ST_Y>(a, cx);      // Zbar (Y) in BF16, Zdotbar (Y2) in FP32
+            else gemm<PRO_ID, EPI_TOPADJ>(a, cx);
         }
         // sdf output layer: w_out_bar from the partials, b_out_bar = half sum g_f
         hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, st, tpart, (int)top_rows(m), l.W, 1.0f,
@@ -1720,14 +1809,17 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                     (rc = hip_status(hipStreamWaitEvent(wst, side->ready[i], 0), "side event wait")))
                     return rc;
             }
+            float* part2 = part + (size_t)kWgSplits * l.W * finp;
             if (i == 0) {
-                wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32w, bpart);
-                wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta,
-                              part + (size_t)kWgSplits * l.W * finp, cx32w);
+                if (b16) wgrad<PRO_ID, ST_A>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32w, bpart);
+                else wgrad<PRO_ID>(Zb, l.W, l.W, X0, nullptr, l.in0p, finp, m, beta, part, cx32w, bpart);
+                wgrad<PRO_ID>(Zdb, l.W, l.W, X0d, nullptr, l.in0p, finp, m, beta, part2, cx32w);
+            } else if (b16) {
+                wgrad<PRO_ID, ST_A>(Zb, l.W, l.W, H[i - 1], nullptr, l.W, finp, m, beta, part, cxw, bpart);
+                wgrad<PRO_ID, ST_B>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta, part2, cxw);
             } else {
                 wgrad<PRO_ID>(Zb, l.W, l.W, H[i - 1], nullptr, l.W, finp, m, beta, part, cxw, bpart);
-                wgrad<PRO_ID>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta,
-                              part + (size_t)kWgSplits * l.W * finp, cxw);
+                wgrad<PRO_ID>(Zdb, l.W, l.W, Hd[i - 1], nullptr, l.W, finp, m, beta, part2, cxw);
             }
             wg_reduce(part, 2 * kWgSplits, l.W, finp, fin, GP + l.oW[i], acc, wst, kWgSplits, kept ? half : 1.0f);
             hipLaunchKernelGGL(k_colsum_final, dim3(l.W), dim3(256), 0, wst, bpart, kWgSplits, l.W, 1.0f,
@@ -1743,7 +1835,8 @@ int mlp_backward(const rfvr_mlp* net, const float* xyz, long n, const float* g_s
                 a.C2 = Hd[i - 1];
                 a.C3 = reserve_s(reserve, l, n, i - 1) + c0 * l.W;
                 a.scale = half;
-                gemm<PRO_ID, EPI_ADJ1>(a, cx);
+                if (b16) gemm_b16<PRO_ID, EPI_ADJ1, ST_A | ST_C2 | ST_Y>(a, cx);
+                else gemm<PRO_ID, EPI_ADJ1>(a, cx);
                 float* t = Zb_c; Zb_c = Zb_n; Zb_n = t;
             } else if (i > 0) {
                 gemm_dual<EPI2_ADJ>(da(Zb, Zdb, l.W, w.WT[i], l.W, nullptr, Z[i - 1], Hd[i - 1], Zb_n, Zdb_n, nullptr,

@@ -56,3 +56,40 @@ def test_mlp_f16_against_oracle(dev, name, spec, n):
     assert ef <= 1e-2 and eg <= 1e-2 and ea <= 1e-2
     assert np.isfinite(gp_plain).all() and np.isfinite(gp_train).all()
     assert ep <= 3e-2 and et <= 3e-2 and cp >= 0.999 and ct >= 0.999
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_training_backward_bf16_storage(dev, prec):
+    """With single-rounded BF16 backward products (the F16 and BF16 forms) the
+    training backward keeps its tangents and adjoints in BF16 storage; the
+    plain backward keeps them in FP32.  Both round every such operand to BF16
+    before its product, so the two gradients agree to the BF16 rounding of the
+    few FP32 consumers (the tangent's use in the adjoint epilogue, the
+    encoding layer's weight gradient): RMS relative difference <= 2e-2,
+    cosine >= 0.999, on the 8 x 256 network at 2^20 + 777 points (two
+    passes)."""
+    from test_gpu_mlp import PASS
+    print(f"[case] training backward with BF16 storage, {prec}", flush=True)
+    from paper_2605_29097_amd import rfvr as R
+    R.lib()
+    spec = CASES[0][1]
+    n = PASS + 777
+    p = _params(spec, 31)
+    x = _pts(n, spec, 32)
+    rng = np.random.default_rng(33)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    gf, gg, gaa = t(rng.normal(size=n)), t(rng.normal(size=(n, 3))), t(rng.normal(size=n))
+    net = R.MLP(params=t(p), n_layers=spec.n_layers, width=spec.width, pe_octaves=spec.pe_octaves,
+                head_width=spec.head_width, head_layers=spec.head_layers, beta=spec.beta,
+                centre=spec.centre, half_size=spec.half_size, precision=getattr(R, "PREC_" + prec.upper()))
+    res = R.mlp_reserve(net, n, dev)
+    R.mlp_forward(net, t(x), reserve=res)
+    g1 = R.mlp_backward(net, t(x), gf, gg, gaa, reserve=res)
+    g2 = R.mlp_backward(net, t(x), gf, gg, gaa, reserve=res)
+    assert torch.equal(g1, g2)
+    del res
+    g0 = R.mlp_backward(net, t(x), gf, gg, gaa).cpu().numpy().astype(np.float64)
+    g1 = g1.cpu().numpy().astype(np.float64)
+    e, c = rel_rms(g1, g0), _cos(g1, g0)
+    print(f"[f16] {prec}: training backward (BF16 storage) vs plain backward {e:.2e}, cosine {c:.6f}", flush=True)
+    assert np.isfinite(g1).all() and e <= 2e-2 and c >= 0.999
