@@ -713,6 +713,31 @@ def batched8_train(args, dev):
     print(json.dumps(out))
 
 
+def step_16bit(cfg, params, target, args, dev):
+    """The same training step with the network on its FP16 form (FP16 forward
+    products with the per-point operand split, BF16 backward products, FP32
+    accumulation), which holds the rendered signal within 1e-2 of the FP64
+    oracle: a context figure beside the FP32 line, timed the same way."""
+    import torch
+    from paper_2605_29097_amd import rfvr as R
+    from paper_2605_29097_amd.train import Trainer
+    tr = Trainer(dataclasses.replace(cfg, precision=R.PREC_F16), params, target, device=dev)
+    for _ in range(max(1, args.warmup)):
+        tr.step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    print(f"[bench] FP16-network step {ms:.2f} ms", file=sys.stderr, flush=True)
+    return {"precision": "RFVR_PREC_F16: FP16 forward products (per-point operand split in two), BF16 "
+                         "backward products, FP32 accumulation; render FP32",
+            "steps": steps, "ms_per_step": round(ms, 3),
+            "terms_per_s": 4 * cfg.terms_per_pass() / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -881,6 +906,7 @@ def main():
         "roofline": roofline,
         "roofline_terms": roofline_terms,
     }
+    out["step_16bit_network"] = step_16bit(cfg, params, target, args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_both(cfg)
     print(json.dumps(out))
