@@ -58,21 +58,22 @@ def test_mlp_f16_against_oracle(dev, name, spec, n):
     assert ep <= 3e-2 and et <= 3e-2 and cp >= 0.999 and ct >= 0.999
 
 
-@pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_training_backward_bf16_storage(dev, prec):
+@pytest.mark.parametrize("prec,layers", [("f16", 8), ("bf16", 8), ("f16", 1)], ids=["f16", "bf16", "f16-one-layer"])
+def test_training_backward_bf16_storage(dev, prec, layers):
     """With single-rounded BF16 backward products (the F16 and BF16 forms) the
     training backward keeps its tangents and adjoints in BF16 storage; the
     plain backward keeps them in FP32.  Both round every such operand to BF16
     before its product, so the two gradients agree to the BF16 rounding of the
     few FP32 consumers (the tangent's use in the adjoint epilogue, the
     encoding layer's weight gradient): RMS relative difference <= 2e-2,
-    cosine >= 0.999, on the 8 x 256 network at 2^20 + 777 points (two
-    passes)."""
+    cosine >= 0.999, on the 8 x 256 network (and a one-layer trunk, whose top
+    layer reads the encoding) at 2^20 + 777 points (two passes)."""
     from test_gpu_mlp import PASS
-    print(f"[case] training backward with BF16 storage, {prec}", flush=True)
+    print(f"[case] training backward with BF16 storage, {prec}, {layers} layers", flush=True)
+    import dataclasses
     from paper_2605_29097_amd import rfvr as R
     R.lib()
-    spec = CASES[0][1]
+    spec = dataclasses.replace(CASES[0][1], n_layers=layers)
     n = PASS + 777
     p = _params(spec, 31)
     x = _pts(n, spec, 32)
@@ -91,5 +92,6 @@ def test_training_backward_bf16_storage(dev, prec):
     g0 = R.mlp_backward(net, t(x), gf, gg, gaa).cpu().numpy().astype(np.float64)
     g1 = g1.cpu().numpy().astype(np.float64)
     e, c = rel_rms(g1, g0), _cos(g1, g0)
-    print(f"[f16] {prec}: training backward (BF16 storage) vs plain backward {e:.2e}, cosine {c:.6f}", flush=True)
+    print(f"[f16] {prec}, {layers} layers: training backward (BF16 storage) vs plain backward {e:.2e}, "
+          f"cosine {c:.6f}", flush=True)
     assert np.isfinite(g1).all() and e <= 2e-2 and c >= 0.999
