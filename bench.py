@@ -745,6 +745,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="print per-phase times to stderr")
+    ap.add_argument("--no-16bit-step", action="store_true",
+                    help="leave out the context figure of the same step with the FP16 network form")
     ap.add_argument("--kernel-probe", choices=["mlp_bwd", "render_fwd", "mf_fwd", "mf_bwd", "render_bwd"],
                     help="run only one pass of the workload (for hardware-counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -906,7 +908,8 @@ def main():
         "roofline": roofline,
         "roofline_terms": roofline_terms,
     }
-    out["step_16bit_network"] = step_16bit(cfg, params, target, args, dev)
+    if not args.no_16bit_step:
+        out["step_16bit_network"] = step_16bit(cfg, params, target, args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_both(cfg)
     print(json.dumps(out))
