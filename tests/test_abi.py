@@ -277,3 +277,20 @@ def test_static_filter_checks_size_before_any_device_work(R):
     assert L.rfvr_mf_forward_static(ctypes.byref(big_bi), v, 64, 0, v, v, v, None, None, None, None) == -1
     hdr = open(HEADER).read()
     assert f"#define RFVR_MF_STATIC_SCRATCH_BYTES (32u << 20)" in hdr and R.MF_STATIC_SCRATCH_BYTES == 32 << 20
+
+
+def test_mlp_precision_is_checked_before_launch(R):
+    """Every RFVR_PREC_* value is accepted; anything else is rejected with
+    RFVR_E_INVALID before any device work (a too-small workspace then reports
+    -2 for the accepted values, so the precision check ran first)."""
+    L = R.lib()
+    v, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
+    for prec in (R.PREC_FP32, R.PREC_BF16, R.PREC_BF16X3, R.PREC_F16):
+        net = R.MLP(params=None, precision=prec).c()
+        net.params = v
+        assert L.rfvr_mlp_forward(ctypes.byref(net), v, 1000, v, v, v, ws, 1, None) == -2
+    for prec in (-1, 4, 7):
+        net = R.MLP(params=None, precision=prec).c()
+        net.params = v
+        assert L.rfvr_mlp_forward(ctypes.byref(net), v, 1000, v, v, v, ws, 1 << 40, None) == -1
+        assert b"precision" in L.rfvr_last_error()
