@@ -404,7 +404,10 @@ def proposal_study(args, dev):
     pc = dict(n_imp=args.study_imp, n_uni=args.study_uni, loss_on_grid=args.study_loss_grid,
               dilate=args.study_dilate)
     runs = {
-        "full_space": (lambda p: Trainer(cfg, p, noisy, device=dev), args.study_full_steps, 0),
+        "full_space": (lambda p: Trainer(dataclasses.replace(
+            cfg, n_z=args.study_full_nz or cfg.n_z,
+            sampling=R.SAMPLE_STRATIFIED if args.study_full_stratified else cfg.sampling), p, noisy, device=dev),
+            args.study_full_steps, 0),
         "proposal": (lambda p: ProposalTrainer(cfg, p, noisy, ProposalConfig(full_every=args.study_full_every, **pc),
                                                device=dev),
                      args.study_prop_steps, args.study_prop_warmup),
@@ -774,6 +777,10 @@ def main():
     ap.add_argument("--study-full-every", type=int, default=0,
                     help="every this many steps the proposal run takes a full-space step (0: never)")
     ap.add_argument("--study-amp0", type=float, default=1.0, help="initial amplitude A' of every run")
+    ap.add_argument("--study-full-nz", type=int, default=0,
+                    help="depths per ray of the full-space run (0: the workload's 256)")
+    ap.add_argument("--study-full-stratified", action="store_true",
+                    help="the full-space run draws stratified depths each step instead of the fixed grid")
     ap.add_argument("--study-dilate", type=int, default=0,
                     help="proposal targets dilated in depth over this many bins")
     ap.add_argument("--study-imp", type=int, default=16)
