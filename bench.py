@@ -369,6 +369,23 @@ def proposal_study(args, dev):
         p0 = net.params.detach().clone()
         print(f"[study] prior fit: {args.study_prior} steps, f rms {prior_rms * 1e3:.3f} mm", file=sys.stderr,
               flush=True)
+    amp_fit = None
+    if args.study_fit_amp:
+        # the heatmap P = |z| scales with A' (z is linear in it): the least-squares
+        # A' of the starting network's full-space render against the measured
+        # heatmap, A' = <P1, P*> / <P1, P1> with P1 the render at A' = 1
+        t0 = Trainer(dataclasses.replace(cfg, amp0=1.0), p0.clone(), noisy, device=dev)
+        xyz, _, origin = t0.samples()
+        f, g, a = R.mlp_forward(t0.net, xyz)
+        phi_ray, phi_tx, _ = t0.origin_occupancy(origin, t0.tx)
+        fl = R.Fields(sdf=f.view(xyz.shape[:2]), grad=g.view(*xyz.shape[:2], 3), refl=a.view(xyz.shape[:2]),
+                      s=cfg.s, amp=1.0, phi_ray=phi_ray, phi_tx=phi_tx)
+        sig = R.render_forward(t0.ap, R.Samples(xyz=xyz), fl, flags=cfg.render_flags)
+        _, p1, _, p_star = R.mf_forward(t0.ap, xyz, sig, t0.target)
+        amp_fit = float((p1 * p_star).sum() / (p1 * p1).sum())
+        cfg = dataclasses.replace(cfg, amp0=amp_fit)
+        del t0
+        print(f"[study] fitted initial amplitude A' = {amp_fit:.4f}", file=sys.stderr, flush=True)
     # Chamfer distances on a 256^3 grid (App. C metrics): the true scene's
     # surface points, each assigned to the primitive it lies nearest to
     n_grid = args.study_grid
@@ -474,7 +491,9 @@ def proposal_study(args, dev):
                       "judge_nz": cfg.judge_nz or cfg.n_z, "prior_fit_steps": args.study_prior,
                       "prior_f_rms_m": prior_rms, "n_imp": args.study_imp, "n_uni": args.study_uni,
                       "loss_on_grid": args.study_loss_grid, "target_dilation_bins": args.study_dilate,
-                      "full_every": args.study_full_every, "amp0": args.study_amp0,
+                      "full_every": args.study_full_every, "amp0": cfg.amp0, "amp0_fitted": amp_fit,
+                      "full_sampling": "stratified" if args.study_full_stratified else "grid",
+                      "full_nz": args.study_full_nz or cfg.n_z,
                       "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
                       "scene": ("box 8x6x4 cm (a=0.8) at 0.30 m; 32x32 aperture, 128 freqs, 20 cm cube at 0.30 m; "
                                 "10 dB noise") if box else
@@ -777,6 +796,8 @@ def main():
     ap.add_argument("--study-full-every", type=int, default=0,
                     help="every this many steps the proposal run takes a full-space step (0: never)")
     ap.add_argument("--study-amp0", type=float, default=1.0, help="initial amplitude A' of every run")
+    ap.add_argument("--study-fit-amp", action="store_true",
+                    help="every run starts from the least-squares A' of the starting network's heatmap")
     ap.add_argument("--study-full-nz", type=int, default=0,
                     help="depths per ray of the full-space run (0: the workload's 256)")
     ap.add_argument("--study-full-stratified", action="store_true",
