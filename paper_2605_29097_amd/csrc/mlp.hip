@@ -2,9 +2,10 @@
 // "Signal representation"; App. C) on the MI355X matrix cores.
 //
 // Points are the GEMM's long dimension.  Every dense layer runs as an MFMA
-// (v_mfma_f32_16x16x4_f32) GEMM with the elementwise work of its neighbours
-// fused into the operand loads (softplus, its derivative times a tangent or an
-// adjoint, relu) and the bias / relu-mask / accumulate into its epilogue.
+// GEMM (v_mfma_f32_16x16x4_f32, or one of the 16-bit operand forms below) with
+// the elementwise work of its neighbours fused into the operand loads
+// (softplus, its derivative times a tangent or an adjoint, relu) and the bias /
+// relu-mask / accumulate into its epilogue.
 //
 // Forward call: primal layers, then grad_x f by one reverse sweep
 //   G^(8) = w_out, G^(l) = (softplus'(Z^(l)) . G^(l+1)) W_l, grad = J_PE^T G^(0).
@@ -70,10 +71,12 @@ __device__ __forceinline__ void split_bf16x8(floatx4 lo, floatx4 hi, bf16x8& big
 }
 
 // BF16 storage of the single-rounded BF16 backward's arrays (tangents Hdot and
-// adjoints Zbar): every product that reads them rounds them to BF16 (RNE)
+// adjoints Zbar): the BF16 products that read them round them to BF16 (RNE)
 // anyway, so they are stored rounded, as raw 16-bit words in buffers sized for
-// FP32, and widened where they are used (a main loop keeps the raw words of its
-// prefetch and widens them at the LDS store, so the prefetch stays in flight)
+// FP32 (the few FP32 readers, the adjoint epilogue's Hdot and the encoding
+// layer's FP32 weight-gradient product, see the rounded values), and widened
+// where they are used (a main loop keeps the raw words of its prefetch and
+// widens them at the LDS store, so the prefetch stays in flight)
 __device__ __forceinline__ uint2 ld_raw_bf16x4(const float* base, long i) {
     return *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(base) + i);
 }
