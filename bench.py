@@ -771,6 +771,8 @@ def main():
                     help="leave out the context figure of the same step with the FP16 network form")
     ap.add_argument("--kernel-probe", choices=["mlp_bwd", "render_fwd", "mf_fwd", "mf_bwd", "render_bwd"],
                     help="run only one pass of the workload (for hardware-counter runs)")
+    ap.add_argument("--probe-precision", choices=["fp32", "bf16", "bf16x3", "f16"], default="fp32",
+                    help="network operand form of the kernel probe's workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--proposal-study", action="store_true",
@@ -852,6 +854,8 @@ def main():
         batched8_train(args, dev)
         return
     cfg = StepConfig()
+    if args.kernel_probe:
+        cfg = dataclasses.replace(cfg, precision=getattr(R, "PREC_" + args.probe_precision.upper()))
     params, target = make_inputs(cfg, dev)
     tr = Trainer(cfg, params, target, device=dev)
     if args.kernel_probe:
