@@ -1359,10 +1359,15 @@ void gemm_launch(const GemmArgs& a, hipStream_t st) {
 
 template <int PRO, int EPI>
 void gemm(const GemmArgs& a, const Cx& cx) {
+    // the FP16 form exists for the forward products' epilogues only (a
+    // backward context never carries MM_F16: mm_bwd maps it to BF16)
+    constexpr bool FWD_EPI = EPI == EPI_BIAS || EPI == EPI_BIAS_SP || EPI == EPI_DSPMUL;
     if (cx.mm == MM_BF16) gemm_launch<PRO, EPI, MM_BF16>(a, cx.st);
     else if (cx.mm == MM_BF16X3) gemm_launch<PRO, EPI, MM_BF16X3>(a, cx.st);
-    else if (cx.mm == MM_F16) gemm_launch<PRO, EPI, MM_F16>(a, cx.st);
-    else gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
+    else if (cx.mm == MM_F16) {
+        if constexpr (FWD_EPI) gemm_launch<PRO, EPI, MM_F16>(a, cx.st);
+        else gemm_launch<PRO, EPI, MM_BF16>(a, cx.st);
+    } else gemm_launch<PRO, EPI, MM_FP32>(a, cx.st);
 }
 
 // FP32 GEMM whatever the context (first layer: its operand is the encoding)
