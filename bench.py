@@ -831,6 +831,7 @@ def main():
               "(the multi-GPU sharding by points is a design, not a measured path)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2605_29097_amd import rfvr as R
     from paper_2605_29097_amd.train import StepConfig, Trainer
@@ -884,6 +885,8 @@ def main():
     phases = {}
     for a, b in zip(order[:-1], order[1:]):
         phases[b] = sum(ea.elapsed_time(eb) for ea, eb in zip(timers[a], timers[b])) / args.steps
+    # per-step spread from the same events (first to last mark of each step)
+    per_step = np.array([ea.elapsed_time(eb) for ea, eb in zip(timers[order[0]], timers[order[-1]])])
     if args.phases:
         print(json.dumps({"phases_ms": phases}), file=sys.stderr)
 
@@ -928,6 +931,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "step_ms_median_p10_p90": [round(float(np.median(per_step)), 3), round(float(np.percentile(per_step, 10)), 3),
+                                   round(float(np.percentile(per_step, 90)), 3)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
