@@ -761,7 +761,7 @@ struct WgArgs {
 };
 
 template <int PRO, bool BIAS, int MM, int ST = 0>
-__global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
+__global__ __launch_bounds__(256, MM == MM_BF16 ? 3 : 1) void k_gemm_wg(WgArgs g) {
     constexpr int BM = 128, BN = 128, BK = 32, LW = 128 + 4;
     __shared__ float sA[BK * LW];
     __shared__ float sB[BK * LW];
@@ -844,7 +844,39 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
                 for (int r = 0; r < BK; ++r) bsum += sA[r * LW + tid];
             }
         }
-        if constexpr (MM != MM_FP32) {
+        if constexpr (MM == MM_BF16) {
+            // points lg*4 + s and 16 + lg*4 + s (s < 4) fill the 8 k slots of a
+            // lane; the B fragments are converted first and each A fragment
+            // just before its products (scheduling barriers keep the order), so
+            // that three waves fit on a SIMD
+            bf16x8 bf[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                floatx4 b0, b1;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = lg * 4 + s;
+                    b0[s] = sB[r * LW + wn * 64 + b * 16 + li];
+                    b1[s] = sB[(r + 16) * LW + wn * 64 + b * 16 + li];
+                }
+                bf[b] = to_bf16x8(b0, b1);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                __builtin_amdgcn_sched_barrier(0);
+                floatx4 a0, a1;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int r = lg * 4 + s;
+                    a0[s] = sA[r * LW + wp * 64 + a * 16 + li];
+                    a1[s] = sA[(r + 16) * LW + wp * 64 + a * 16 + li];
+                }
+                const bf16x8 af = to_bf16x8(a0, a1);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[b], acc[a][b], 0, 0, 0);
+            }
+        } else if constexpr (MM != MM_FP32) {
             // points lg*4 + s and 16 + lg*4 + s (s < 4) fill the 8 k slots of a lane
             floatx4 a0[4], a1[4], b0[4], b1[4];
 #pragma unroll
@@ -861,18 +893,7 @@ __global__ __launch_bounds__(256) void k_gemm_wg(WgArgs g) {
                     b1[b][s] = sB[(r + 16) * LW + wn * 64 + b * 16 + li];
                 }
             }
-            if constexpr (MM == MM_BF16) {
-                bf16x8 af[4], bf[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) af[a] = to_bf16x8(a0[a], a1[a]);
-#pragma unroll
-                for (int b = 0; b < 4; ++b) bf[b] = to_bf16x8(b0[b], b1[b]);
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
-            } else {
+            {
                 bf16x8 ab[4], as[4], bb[4], bs[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a) split_bf16x8(a0[a], a1[a], ab[a], as[a]);
