@@ -262,9 +262,15 @@ def test_render_backward_batched_sampled_rays(dev, scenes):
             assert e <= 1e-4, (S["k"], key)
 
 
-def test_networks_grouped_sampled(dev, scenes):
+@pytest.mark.parametrize("prec", ["bf16x3", "f16"])
+def test_networks_grouped_sampled(dev, scenes, prec):
+    """Grouped network calls on the eight scenes in the two 16-bit forms that
+    meet the 1e-2 bar: outputs within 1e-2 at 32 points per network; the
+    parameter gradient for upstream gradients on 16 points within 1e-2 (split
+    BF16) or 3e-2 (FP16 form, whose backward products are single-rounded
+    BF16)."""
     R = _R()
-    _say("mlp_forward_grouped / mlp_backward_grouped, 8 networks x 2^22 points, split BF16")
+    _say(f"mlp_forward_grouped / mlp_backward_grouped, 8 networks x 2^22 points, {prec}")
     m = CFG["mlp"]
     nets, specs, params, xs = [], [], [], []
     for S in scenes:
@@ -278,7 +284,7 @@ def test_networks_grouped_sampled(dev, scenes):
         params.append(p)
         nets.append(R.MLP(params=_t(p, dev), n_layers=spec.n_layers, width=spec.width, pe_octaves=spec.pe_octaves,
                           head_width=spec.head_width, head_layers=spec.head_layers, beta=spec.beta,
-                          centre=spec.centre, half_size=spec.half_size, precision=R.PREC_BF16X3))
+                          centre=spec.centre, half_size=spec.half_size, precision=getattr(R, "PREC_" + prec.upper())))
         xs.append(S["gpu"][1].xyz.reshape(-1, 3))
     outs = R.mlp_forward_grouped(nets, xs)
     rng = np.random.default_rng(24)
@@ -314,4 +320,4 @@ def test_networks_grouped_sampled(dev, scenes):
                             vg.astype(np.float32).astype(np.float64), va.astype(np.float32).astype(np.float64))
         e = rel_rms(gp.cpu().numpy(), ref)
         print(f"net {S['k']}: parameter gradient rms rel {e:.2e}")
-        assert e <= 1e-2, S["k"]
+        assert e <= (1e-2 if prec == "bf16x3" else 3e-2), S["k"]
