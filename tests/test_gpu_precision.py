@@ -123,6 +123,61 @@ def test_precision_study(dev, prec, phase):
         assert e_s <= 1e-1 and e_p <= 1e-1 and cos >= 0.99
 
 
+# ---------------------------------------------------------------- seeds 0-4
+
+_SEEDS = {}
+
+
+def _seed_case(seed):
+    """The scaled workload with the network's initialisation, its perturbation
+    and the points' jitter drawn from `seed`; the oracle's signal there."""
+    if seed not in _SEEDS:
+        spec = MLPSpec(centre=(0.0, 0.0, 0.30), half_size=0.10)
+        rng = np.random.default_rng(1000 + seed)
+        p = mlp_init(spec, seed).astype(np.float64)
+        p = (p + 0.3 * rng.normal(size=p.shape) / np.sqrt(spec.width)).astype(np.float32)
+        f0, df = freq_grid(64)
+        tx = planar_aperture(16, 16, 2e-3)
+        xyz, _ = line_points((0.0, 0.0, 0.30), 0.20, 32, 32, 16, jitter_seed=seed)
+        x64 = xyz.astype(np.float64)
+        f, g, a = omlp.forward(p.astype(np.float64), spec, x64.reshape(-1, 3))
+        shp = xyz.shape[:2]
+        F = orc.Fields(sdf=f.reshape(shp), grad=g.reshape(*shp, 3), refl=a.reshape(shp), s=64.0, amp=1.0)
+        sig = orc.render(orc.Aperture(tx=tx.astype(np.float64), f0=f0, df=df, n_freq=64), x64, F)
+        _SEEDS[seed] = (spec, p, f0, df, tx, xyz, sig)
+    return _SEEDS[seed]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "f16"])
+def test_precision_over_seeds(dev, prec):
+    """The rendered signal's error against the FP64 oracle over seeds 0-4 (the
+    network's initialisation and perturbation, the points' jitter), FP64 phase
+    reduction: every seed within the bar of its path (1e-4 FP32, 1e-2 for the
+    16-bit forms); mean and largest error reported."""
+    print(f"[case] precision over seeds 0-4, net={prec}", flush=True)
+    from paper_2605_29097_amd import rfvr as R
+    R.lib()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    errs = []
+    for seed in range(5):
+        spec, p, f0, df, tx, xyz, ref = _seed_case(seed)
+        net = R.MLP(params=t(p), n_layers=spec.n_layers, width=spec.width, pe_octaves=spec.pe_octaves,
+                    head_width=spec.head_width, head_layers=spec.head_layers, centre=spec.centre,
+                    half_size=spec.half_size, precision=getattr(R, "PREC_" + prec.upper()))
+        x = t(xyz)
+        f, g, a = R.mlp_forward(net, x.view(-1, 3))
+        shp = xyz.shape[:2]
+        fl = R.Fields(sdf=f.view(shp), grad=g.view(*shp, 3), refl=a.view(shp), s=64.0, amp=1.0)
+        sig = R.render_forward(R.Aperture(tx=t(tx), f0=f0, df=df, n_freq=64), R.Samples(xyz=x), fl)
+        sg = sig.cpu().numpy().astype(np.float64)
+        errs.append(rel_rms(sg[..., 0] + 1j * sg[..., 1], ref))
+    errs = np.array(errs)
+    print(f"[precision seeds] net={prec:6s} signal rms per seed {', '.join(f'{e:.2e}' for e in errs)} | "
+          f"mean {errs.mean():.2e} max {errs.max():.2e}", flush=True)
+    assert np.isfinite(errs).all()
+    assert errs.max() <= (1e-4 if prec == "fp32" else 1e-2)
+
+
 # ---------------------------------------------------------------- full shape
 
 _FULL = {}
