@@ -31,7 +31,7 @@ def _say(msg):
 
 # ------------------------------------------------------------------ forward
 
-@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
 def test_render_forward_small_sphere(dev, seed):
     _say(f"render_forward small sphere seed={seed}")
     R = _R()
