@@ -419,7 +419,7 @@ def proposal_study(args, dev):
 
     prior_cd = None
     pc = dict(n_imp=args.study_imp, n_uni=args.study_uni, loss_on_grid=args.study_loss_grid,
-              dilate=args.study_dilate)
+              dilate=args.study_dilate, jitter=not args.study_prop_fixed)
     # the sampled runs' learning rates (network, amplitude), scaled
     cfg_s = dataclasses.replace(cfg, lr_sdf=cfg.lr_sdf * args.study_prop_lr_scale,
                                 lr_other=cfg.lr_other * args.study_prop_lr_scale)
@@ -496,7 +496,7 @@ def proposal_study(args, dev):
                       "loss_on_grid": args.study_loss_grid, "target_dilation_bins": args.study_dilate,
                       "full_every": args.study_full_every, "amp0": cfg.amp0, "amp0_fitted": amp_fit,
                       "full_sampling": "stratified" if args.study_full_stratified else "grid",
-                      "prop_lr_scale": args.study_prop_lr_scale,
+                      "prop_lr_scale": args.study_prop_lr_scale, "prop_fixed_levels": args.study_prop_fixed,
                       "full_nz": args.study_full_nz or cfg.n_z,
                       "chamfer_grid": n_grid, "chamfer_initial": prior_cd,
                       "scene": ("box 8x6x4 cm (a=0.8) at 0.30 m; 32x32 aperture, 128 freqs, 20 cm cube at 0.30 m; "
@@ -802,6 +802,8 @@ def main():
     ap.add_argument("--study-full-every", type=int, default=0,
                     help="every this many steps the proposal run takes a full-space step (0: never)")
     ap.add_argument("--study-amp0", type=float, default=1.0, help="initial amplitude A' of every run")
+    ap.add_argument("--study-prop-fixed", action="store_true",
+                    help="the sampled runs put every depth at the middle of its stratum (no per-step draw)")
     ap.add_argument("--study-prop-lr-scale", type=float, default=1.0,
                     help="scale of the sampled runs' learning rates (network and amplitude)")
     ap.add_argument("--study-fit-amp", action="store_true",

@@ -456,11 +456,13 @@ int rfvr_proposal_backward(const rfvr_proposal* net, const float* xyz, int64_t n
 /* Largest number of samples per ray of the proposal calls below. */
 #define RFVR_MAX_RAY_SAMPLES 1024
 
-/* Importance samples along the primary rays of `d` (its n_z and mode are
- * ignored).  logits: [n_ray][n_bins] at the centres of n_bins equal depth bins
- * over [c.w_p - h, c.w_p + h].  pdf_b = (sigmoid(z_b) + 1e-3) / sum; slot s of
- * ray r draws xi = (SplitMix64(key, r*(n_uni+n_imp) + s) >> 40) 2^-24 from the
- * step's stream key (as RFVR_SAMPLE_STRATIFIED); slots s < n_uni are stratified
+/* Importance samples along the primary rays of `d` (its n_z is ignored).
+ * logits: [n_ray][n_bins] at the centres of n_bins equal depth bins over
+ * [c.w_p - h, c.w_p + h].  pdf_b = (sigmoid(z_b) + 1e-3) / sum.  With d->mode
+ * RFVR_SAMPLE_STRATIFIED slot s of ray r draws xi = (SplitMix64(key,
+ * r*(n_uni+n_imp) + s) >> 40) 2^-24 from the step's stream key (as
+ * rfvr_sample_points does); with RFVR_SAMPLE_GRID xi = 1/2 for every slot (the
+ * depths then move only with the logits).  Slots s < n_uni are stratified
  * uniform over the whole range, u = lo + (s + xi)(hi - lo)/n_uni; the others
  * invert the CDF at v = (s - n_uni + xi)/n_imp, linearly inside the bin.
  * Depths are sorted per ray (ties keep slot order).  n_bins <= 64,

@@ -86,8 +86,9 @@ def bin_centres(centre, half_extent, w_p, n_rx, n_ry, n_bins):
     return xyz, origin, lo, hi
 
 
-def importance_depths(logits, lo, hi, n_imp, n_uni, seed, step):
-    """Sorted depths [n_ray, n_uni + n_imp] and their slot of origin."""
+def importance_depths(logits, lo, hi, n_imp, n_uni, seed, step, jitter=True):
+    """Sorted depths [n_ray, n_uni + n_imp] and their slot of origin; without
+    jitter every slot takes xi = 1/2, the middle of its stratum."""
     z = np.asarray(logits, np.float64)
     n_ray, n_bins = z.shape
     sig = 1.0 / (1.0 + np.exp(-z))
@@ -96,7 +97,7 @@ def importance_depths(logits, lo, hi, n_imp, n_uni, seed, step):
     cdf = np.cumsum(p, 1)
     K = n_uni + n_imp
     cnt = (np.arange(n_ray, dtype=np.uint64)[:, None] * np.uint64(K) + np.arange(K, dtype=np.uint64)[None])
-    xi = uniform24(seed, step, cnt)                               # [n_ray, K]
+    xi = uniform24(seed, step, cnt) if jitter else np.full(cnt.shape, 0.5)   # [n_ray, K]
     delta = (hi - lo) / n_bins
     u = np.empty((n_ray, K))
     # uniform slots

@@ -653,6 +653,10 @@ int rfvr_sample_importance(const rfvr_sample_desc* d, const float* logits, int32
         set_error("need 1 <= n_bins <= 64 and 1 <= n_imp + n_uni <= RFVR_MAX_RAY_SAMPLES (1024)");
         return RFVR_E_INVALID;
     }
+    if (d->mode != RFVR_SAMPLE_GRID && d->mode != RFVR_SAMPLE_STRATIFIED) {
+        set_error("mode must be RFVR_SAMPLE_GRID (levels at the middle of their strata) or RFVR_SAMPLE_STRATIFIED");
+        return RFVR_E_INVALID;
+    }
     double basis[9];
     int rc;
     if ((rc = sample_basis(d, basis))) return rc;

@@ -201,8 +201,9 @@ __global__ __launch_bounds__(256) void k_sample_importance(SampleArgs a, const f
         u[s] = hi + 1.0;                                       // slots >= K sort last
         v[s] = 0.0;
         if (j < K) {
+            // mode 0: every slot at the middle of its stratum; else drawn
             const uint64_t v64 = sm64_output(a.key, (uint64_t)(r * K + j));
-            const double xi = (double)(v64 >> 40) * (1.0 / 16777216.0);
+            const double xi = a.mode == 0 ? 0.5 : (double)(v64 >> 40) * (1.0 / 16777216.0);
             if (j < n_uni) u[s] = lo + ((double)j + xi) * (hi - lo) / n_uni;
             else v[s] = ((double)(j - n_uni) + xi) / n_imp;
         }
@@ -273,7 +274,7 @@ hipError_t launch_sample_importance(const rfvr_sample_desc& d, const double basi
     a.n_rx = d.n_ray_x;
     a.n_ry = d.n_ray_y;
     a.n_z = n_imp + n_uni;
-    a.mode = 2;
+    a.mode = d.mode == RFVR_SAMPLE_GRID ? 0 : 2;      // 0: fixed mid-stratum levels, 2: drawn
     auto mix = [](uint64_t z) {
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

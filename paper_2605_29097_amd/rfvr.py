@@ -652,14 +652,15 @@ def sample_naive(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_z, tx: to
 
 
 def sample_importance(centre, half_extent, primary_dir, n_ray_x, n_ray_y, logits: torch.Tensor,
-                      n_imp, n_uni, seed=0, step=0, plane_offset=0.0, stream=None):
+                      n_imp, n_uni, seed=0, step=0, plane_offset=0.0, stream=None, jitter=True):
     """Proposal-guided depths: (xyz [n_ray, K, 3], u [n_ray, K], ray_origin [n_ray, 3]),
-    K = n_uni + n_imp, from bin logits [n_ray, n_bins]."""
+    K = n_uni + n_imp, from bin logits [n_ray, n_bins]; jitter=False puts every
+    slot at the middle of its stratum."""
     n_ray = n_ray_x * n_ray_y
     n_bins = logits.shape[-1]
     assert logits.numel() == n_ray * n_bins
-    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_imp + n_uni, 0, seed, step,
-                     plane_offset)
+    d = _sample_desc(centre, half_extent, primary_dir, n_ray_x, n_ray_y, n_imp + n_uni,
+                     SAMPLE_STRATIFIED if jitter else SAMPLE_GRID, seed, step, plane_offset)
     dev = logits.device
     K = n_imp + n_uni
     xyz = torch.empty(n_ray, K, 3, dtype=torch.float32, device=dev)

@@ -423,6 +423,8 @@ class ProposalConfig:
     dilate: int = 0             # targets dilated in depth over this many bins (rfvr_proposal_targets)
     full_every: int = 0         # every this many steps a full-space step (the fallback): it trains the
                                 # network on the full grid and the proposal on the grid's blend weights
+    jitter: bool = True         # False: every depth at the middle of its stratum (depths then move only
+                                # with the proposal's pdf, not from step to step)
 
 
 class ProposalTrainer(Trainer):
@@ -471,7 +473,7 @@ class ProposalTrainer(Trainer):
     def proposal_samples(self, logits):
         c, pc = self.cfg, self.pc
         return R.sample_importance(c.cube_centre, c.cube_side / 2, (0.0, 0.0, 1.0), c.lines[0], c.lines[1],
-                                   logits, pc.n_imp, pc.n_uni, seed=c.seed, step=self.t)
+                                   logits, pc.n_imp, pc.n_uni, seed=c.seed, step=self.t, jitter=pc.jitter)
 
     def full_step(self, timers: Optional[dict] = None):
         """A full-space step (the fallback): the network trains on the full grid

@@ -186,6 +186,8 @@ def test_sampler_and_optimizer_reject_bad_arguments(R):
     d.primary_dir[2] = 1.0
     d.mode = 7
     assert L.rfvr_sample_points(ctypes.byref(d), v, None, None, None) == -1
+    assert L.rfvr_sample_importance(ctypes.byref(d), v, 16, 4, 4, v, None, None, None) == -1   # mode 7
+    assert b"mode" in L.rfvr_last_error()
     d.mode = 0
     d.half_extent = -1.0
     assert L.rfvr_sample_points(ctypes.byref(d), v, None, None, None) == -1

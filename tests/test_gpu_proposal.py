@@ -93,10 +93,11 @@ SAMPLE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("jitter", [True, False], ids=["drawn", "fixed"])
 @pytest.mark.parametrize("case", SAMPLE_CASES, ids=[f"{c[0]}x{c[1]}-b{c[2]}-i{c[3]}-u{c[4]}" for c in SAMPLE_CASES])
-def test_sample_importance(dev, case):
+def test_sample_importance(dev, case, jitter):
     nx, ny, n_bins, n_imp, n_uni, wdir = case
-    _say(f"sample_importance {case}")
+    _say(f"sample_importance {case} jitter={jitter}")
     R = _R()
     rng = np.random.default_rng(n_bins + n_imp)
     n_ray = nx * ny
@@ -106,14 +107,15 @@ def test_sample_importance(dev, case):
         z[1] = -50.0
         z[1, n_bins // 2] = 50.0                 # one hot bin
     centre, h, seed, step = (0.01, 0.0, 0.28), 0.1, 12345, 6
-    xyz, u, o = R.sample_importance(centre, h, wdir, nx, ny, _t(z, dev), n_imp, n_uni, seed=seed, step=step)
+    xyz, u, o = R.sample_importance(centre, h, wdir, nx, ny, _t(z, dev), n_imp, n_uni, seed=seed, step=step,
+                                    jitter=jitter)
     # oracle: ray origins and range from the grid sampler, depths from the proposal
     _, _, o_ref = o_sample_points(centre, h, wdir, nx, ny, 1)
     w = np.asarray(wdir, np.float64)
     w /= np.linalg.norm(w)
     cw = float(np.dot(np.asarray(centre, np.float64), w))
     lo, hi = cw - h, cw + h
-    u_ref, _ = op.importance_depths(z.astype(np.float64), lo, hi, n_imp, n_uni, seed, step)
+    u_ref, _ = op.importance_depths(z.astype(np.float64), lo, hi, n_imp, n_uni, seed, step, jitter=jitter)
     x_ref = o_ref[:, None, :] + u_ref[..., None] * w
     ug = u.cpu().numpy().astype(np.float64)
     err_u = np.abs(ug - u_ref).max()

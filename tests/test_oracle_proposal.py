@@ -69,6 +69,40 @@ def test_uniform_logits_give_linear_inverse_cdf():
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
 
 
+def test_fixed_levels_are_the_stratum_midpoints():
+    """Without jitter every slot sits at the middle of its stratum: equal logits
+    give importance depths lo + (k + 1/2)(hi - lo)/n_imp and uniform depths
+    lo + (k + 1/2)(hi - lo)/n_uni, the same for every ray and seed; a single hot
+    bin puts the importance levels that fall in its CDF interval at the
+    interval's linear map into the bin."""
+    n_ray, n_bins, n_imp, n_uni = 4, 16, 8, 3
+    lo, hi = 0.2, 0.4
+    u, slot = op.importance_depths(np.zeros((n_ray, n_bins)), lo, hi, n_imp, n_uni, seed=7, step=2, jitter=False)
+    u2, _ = op.importance_depths(np.zeros((n_ray, n_bins)), lo, hi, n_imp, n_uni, seed=99, step=5, jitter=False)
+    np.testing.assert_array_equal(u, u2)
+    got = np.empty_like(u)
+    np.put_along_axis(got, slot, u, 1)
+    want_uni = lo + (np.arange(n_uni) + 0.5) / n_uni * (hi - lo)
+    want_imp = lo + (np.arange(n_imp) + 0.5) / n_imp * (hi - lo)
+    np.testing.assert_allclose(got[:, :n_uni], np.broadcast_to(want_uni, (n_ray, n_uni)), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(got[:, n_uni:], np.broadcast_to(want_imp, (n_ray, n_imp)), rtol=0, atol=1e-14)
+    # one hot bin b: CDF interval [c0, c1) with c0 = b q_floor / Z, width p_hot;
+    # level v in it lands at lo + (b + (v - c0) / p_hot) (hi - lo) / n_bins
+    b = 5
+    z = np.full((1, n_bins), -60.0)
+    z[0, b] = 60.0
+    uh, sh = op.importance_depths(z, lo, hi, n_imp, 0, seed=0, step=0, jitter=False)
+    q = 1.0 / (1.0 + np.exp(-z[0])) + 1e-3
+    pz = q / q.sum()
+    c0, p_hot = pz[:b].sum(), pz[b]
+    v = (np.arange(n_imp) + 0.5) / n_imp
+    inside = (v >= c0) & (v < c0 + p_hot)
+    want = lo + (b + (v[inside] - c0) / p_hot) * (hi - lo) / n_bins
+    gotb = np.empty_like(uh)
+    np.put_along_axis(gotb, sh, uh, 1)
+    np.testing.assert_allclose(gotb[0, inside], want, rtol=0, atol=1e-12)
+
+
 def test_inverse_cdf_matches_piecewise_linear_interpolation():
     """The importance depths equal the piecewise-linear inverse of the binned CDF,
     evaluated with numpy.interp over the bin edges."""
